@@ -1,0 +1,319 @@
+/*
+ * dftpp.h - C ABI of the MI355X DFT++ band-minimization library (libdftpp.so).
+ *
+ * The calls follow the algebraic (DFT++) statement of plane-wave DFT used by
+ * JDFTx (Sec. 2.1 of the JDFTx paper: named operators I, J, O, the coulomb
+ * operator and pointwise products acting on reciprocal- and real-space
+ * fields and on blocks of wavefunctions, composed by the caller).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Units: bohr, hartree.  Cell matrix R has the lattice vectors as
+ *    COLUMNS, stored row-major: R[3*i + j] = component i of vector a_j.
+ *  - Complex numbers are interleaved {re, im} pairs (dpp_c64 = two doubles,
+ *    dpp_c32 = two floats); layout-compatible with torch complex128/64.
+ *  - Wavefunction blocks ("column bundles") are band-major: band b of a block
+ *    C with leading dimension ldC starts at C + b*ldC (complex elements), and
+ *    holds the npw sphere coefficients in canonical order (lexicographic on
+ *    the Miller indices (n0, n1, n2), each ascending).  ldC >= npw.
+ *  - Real-space fields are row-major (S0, S1, S2) boxes, i2 fastest.
+ *  - Pointers named d_* and every array argument of an operator call are
+ *    DEVICE pointers owned by the caller, unless documented as host.
+ *    The library owns only its handles and their internal device tables.
+ *  - Every call is enqueued on the context's HIP stream and returns without
+ *    synchronizing, except where documented (setup calls and the drivers,
+ *    which read scalars back to decide line-search steps).
+ *  - Scratch: calls taking `void* ws` need a caller-allocated device buffer
+ *    of at least the size reported by the matching *_workspace_size call.
+ *  - Errors: every call returns a dpp_status; arguments are validated on the
+ *    host before any launch and a failing call launches nothing.  The text
+ *    of the last error of the calling thread is dpp_last_error().  Failures
+ *    found on the device (non-positive-definite overlap, non-finite values)
+ *    latch into the context status word, read by dpp_ctx_status after the
+ *    caller synchronizes the stream.
+ */
+#ifndef DFTPP_H
+#define DFTPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } dpp_c64;
+typedef struct { float re, im; } dpp_c32;
+
+typedef enum {
+    DPP_OK = 0,
+    DPP_EINVAL = -1,       /* bad argument (checked on the host)            */
+    DPP_ENOMEM = -2,       /* allocation of an internal table failed        */
+    DPP_EDEVICE = -3,      /* HIP runtime error                             */
+    DPP_ENOTPD = -4,       /* overlap Y^dag O Y not positive definite       */
+    DPP_ENOCONV = -5,      /* an iteration did not converge                 */
+    DPP_EUNSUPPORTED = -6  /* size or mode outside what the kernels handle  */
+} dpp_status;
+
+typedef enum {
+    DPP_F64 = 0,   /* everything in FP64                                    */
+    DPP_F32 = 1    /* FFT passes and the potential multiply in FP32;
+                      contractions and reductions keep FP64 accumulation   */
+} dpp_precision;
+
+/* Device status word bits (dpp_ctx_status). */
+#define DPP_STATUS_NOTPD   1
+#define DPP_STATUS_NONFINITE 2
+
+typedef struct dpp_ctx_s *dpp_ctx;
+typedef struct dpp_grid_s *dpp_grid;
+typedef struct dpp_basis_s *dpp_basis;
+typedef struct dpp_ham_s *dpp_ham;
+typedef struct dpp_system_s *dpp_system;
+
+/* Text of the last error reported to the calling thread ("" if none). */
+const char *dpp_last_error(void);
+int dpp_version(void);
+
+/* ---------------------------------------------------------------- setup -- */
+
+/* Kernel classes measured by the context timer (dpp_timer_*). */
+enum {
+    DPP_TK_PLANES_IN = 0,    /* sphere -> x-planes (scatter, z and y transforms)  */
+    DPP_TK_XZ_H = 1,         /* x transform, V_eff multiply, x transform back     */
+    DPP_TK_PLANES_OUT = 2,   /* y and z transforms, sphere gather (+ kinetic)     */
+    DPP_TK_XZ_DENSITY = 3,   /* x transform and |psi|^2 accumulation              */
+    DPP_TK_OVERLAP = 4,      /* A^dag B contraction (MFMA) and its reduction      */
+    DPP_TK_ROTATE = 5,       /* X M contraction (MFMA)                            */
+    DPP_TK_CHOLESKY = 6,
+    DPP_TK_EIGH = 7,
+    DPP_TK_FULLBOX = 8,      /* full-box transforms (Hartree, J, potentials)      */
+    DPP_TK_FIELDS = 9,       /* LDA, grid reductions, density reduction           */
+    DPP_TK_BLOCKOPS = 10,    /* packed-block elementwise, dots, small matrices    */
+    DPP_TK_XZ_IO = 11        /* x transforms of I and I^dag to/from full boxes    */
+};
+/* Enable (on = 1) or disable the per-context kernel timer: each launch of
+ * an instrumented class is bracketed by HIP events on the context stream.
+ * Reading synchronizes the stream and returns, for one class since the last
+ * reset, the summed milliseconds, the launch count and the summed
+ * algorithmic bytes and flops of those launches (the data the operation must
+ * read and write once, and its arithmetic; any output may be NULL). */
+dpp_status dpp_timer_enable(dpp_ctx ctx, int on);
+dpp_status dpp_timer_reset(dpp_ctx ctx);
+dpp_status dpp_timer_read(dpp_ctx ctx, int kind, double *total_ms, int64_t *launches, double *bytes,
+                          double *flops);
+
+/* Context on HIP device `device`; all work goes to `hip_stream` (a
+ * hipStream_t, NULL = the null stream).  Allocates the device status word. */
+dpp_status dpp_ctx_create(int device, void *hip_stream, dpp_ctx *out);
+dpp_status dpp_ctx_destroy(dpp_ctx ctx);
+/* Synchronizes the stream, then reads (and clears if `clear`) the status word. */
+dpp_status dpp_ctx_status(dpp_ctx ctx, int clear, int *out);
+
+/* Periodic cell R (host, 9 doubles, columns = lattice vectors) with FFT box
+ * S (host, 3 ints, each 2/3/5-smooth, 4 <= S_d <= 128).  GridInfo of Sec. 2.1:
+ * builds FFT plans and twiddle tables (FP64 and FP32) on the device. */
+dpp_status dpp_grid_create(dpp_ctx ctx, const double *R, const int *S, dpp_grid *out);
+dpp_status dpp_grid_destroy(dpp_grid grid);
+/* Volume Omega and point count N = S0 S1 S2 (host outputs). */
+dpp_status dpp_grid_info(dpp_grid grid, double *omega, int64_t *N);
+
+/* G-sphere of Bloch vector k (host, reduced coordinates) at cutoff ecut:
+ * every G = B n with |k+G|^2 / 2 <= ecut evaluated in FP64, canonical order.
+ * Built on the device (flag, scan, compact).  Fails with DPP_EINVAL if the
+ * sphere does not fit the box (2 max|n_d| + 1 > S_d).  Synchronizes. */
+dpp_status dpp_basis_create(dpp_grid grid, const double *k_red, double ecut, dpp_basis *out);
+dpp_status dpp_basis_destroy(dpp_basis basis);
+/* npw, and the Miller-index extent n_ext = {n0min, n0max, n1min, n1max,
+ * n2min, n2max} (host outputs). */
+dpp_status dpp_basis_info(dpp_basis basis, int64_t *npw, int32_t *n_ext);
+/* Copy the sphere tables into caller device arrays: d_index[npw] (int32
+ * linear box index (i0*S1 + i1)*S2 + i2, i_d = n_d mod S_d) and
+ * d_kG2[npw] (|k+G|^2).  Either may be NULL. */
+dpp_status dpp_basis_export(dpp_basis basis, int32_t *d_index, double *d_kG2);
+
+/* Workspace for I, Idag and apply_H on nb bands of `basis` at `prec`. */
+dpp_status dpp_workspace_size(dpp_basis basis, int nb, dpp_precision prec, size_t *bytes);
+/* Workspace for the full-box calls on `grid` (J, Jdag, hartree, lda, ...). */
+dpp_status dpp_grid_workspace_size(dpp_grid grid, size_t *bytes);
+
+/* ------------------------------------------------------------ operators -- */
+
+/* I: sphere -> grid (Sec. 2.1).  grid_out[b] = sum_G C_bG exp(+i G.r)
+ * (unnormalized inverse FFT), nb full boxes of N complex values, band-major.
+ * C and grid_out are dpp_c64 (DPP_F64) or dpp_c32 (DPP_F32). */
+dpp_status dpp_I(dpp_basis basis, int nb, const void *C, int64_t ldC, void *grid_out,
+                 dpp_precision prec, void *ws);
+/* I^dag: grid -> sphere, C_out[b] (+)= sum_r grid[b](r) exp(-i G.r).
+ * accumulate = 0 overwrites C_out, 1 adds to it. */
+dpp_status dpp_Idag(dpp_basis basis, int nb, const void *grid, void *C_out, int64_t ldC,
+                    int accumulate, dpp_precision prec, void *ws);
+/* J: full box, real space -> reciprocal space, y = FFT(x) / N, on nf fields
+ * of N dpp_c64 each (J = I^{-1}).  J^dag: y = IFFT(x) (NumPy normalization). */
+dpp_status dpp_J(dpp_grid grid, int nf, const dpp_c64 *x, dpp_c64 *y, void *ws);
+dpp_status dpp_Jdag(dpp_grid grid, int nf, const dpp_c64 *x, dpp_c64 *y, void *ws);
+
+/* Diagonal operators on a block (in and out may alias; FP64 dpp_c64):
+ *   O: out = Omega in           (overlap, Sec. 2.1)
+ *   L: out = -Omega |k+G|^2 in  (Laplacian)
+ *   K: out = in / (1 + |k+G|^2/2)  (preconditioner) */
+dpp_status dpp_O(dpp_basis basis, int nb, const dpp_c64 *in, int64_t ldin, dpp_c64 *out, int64_t ldout);
+dpp_status dpp_L(dpp_basis basis, int nb, const dpp_c64 *in, int64_t ldin, dpp_c64 *out, int64_t ldout);
+dpp_status dpp_K(dpp_basis basis, int nb, const dpp_c64 *in, int64_t ldin, dpp_c64 *out, int64_t ldout);
+
+/* Kohn-Sham operator of one k-point: kinetic -L/2, local potential
+ * (Omega/N) I^dag(V_eff * I C) and the nonlocal Gaussian s-projectors
+ * P_k D P_k^dag, P_k[G,a] = exp(-|k+G|^2 rp^2/2) exp(-i G.tau_a).
+ * tau: host (nat x 3, Cartesian bohr); has_proj: host (nat ints, 0/1). */
+dpp_status dpp_ham_create(dpp_basis basis, int nat, const double *tau, const int *has_proj,
+                          double rp, double D, dpp_ham *out);
+dpp_status dpp_ham_destroy(dpp_ham ham);
+/* V_eff (device, N doubles) used by later apply_H calls; the pointer is kept,
+ * not copied: the caller keeps the array alive and unchanged meanwhile. */
+dpp_status dpp_ham_set_potential(dpp_ham ham, const double *d_Veff);
+/* HC = H C on nb bands (dpp_c64 for both precisions; DPP_F32 runs the FFT
+ * passes in FP32).  C and HC must not alias. */
+dpp_status dpp_apply_H(dpp_ham ham, int nb, const dpp_c64 *C, int64_t ldC, dpp_c64 *HC,
+                       int64_t ldHC, dpp_precision prec, void *ws);
+
+/* --------------------------------------------------------- contractions -- */
+
+/* U = scale * A^dag B (nbA x nbB, row-major dpp_c64, device) over the npw
+ * coefficients of `basis`; scale = Omega gives the overlap A^dag O B.
+ * Deterministic (fixed reduction order). */
+dpp_status dpp_overlap(dpp_basis basis, int nbA, const dpp_c64 *A, int64_t ldA, int nbB,
+                       const dpp_c64 *B, int64_t ldB, double scale, dpp_c64 *U, void *ws);
+/* out = beta * out + X M: X is nbX bands, M is nbX x nbO (row-major, device),
+ * out is nbO bands.  out must not alias X. */
+dpp_status dpp_rotate(dpp_basis basis, int nbX, const dpp_c64 *X, int64_t ldX, int nbO,
+                      const dpp_c64 *M, double beta, dpp_c64 *out, int64_t ldout);
+/* U = R^dag R (Cholesky, R upper triangular with positive real diagonal) of
+ * the Hermitian positive-definite nb x nb matrix U (device, row-major), then
+ * Rinv = R^{-1}.  A pivot R_jj^2 <= 1e-14 max_i U_ii latches
+ * DPP_STATUS_NOTPD and leaves Rinv undefined.  batch matrices back to back. */
+dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const dpp_c64 *U, dpp_c64 *Rinv);
+/* Orthonormalize a block in place: U = Y^dag O Y, Y <- Y R^{-1}; writes
+ * Rinv (device nb x nb) if not NULL.  Workspace: dpp_ortho_workspace_size.
+ * A non-positive-definite U latches DPP_STATUS_NOTPD and leaves Y as NaN. */
+dpp_status dpp_ortho_workspace_size(dpp_basis basis, int nb, size_t *bytes);
+dpp_status dpp_cholesky_orthonormalize(dpp_basis basis, int nb, dpp_c64 *Y, int64_t ldY,
+                                       dpp_c64 *Rinv, void *ws);
+/* Hermitian eigensolver (FP64, cyclic Jacobi): H (device, batch x nb x nb,
+ * row-major) -> eig ascending (device, batch x nb) and vecs (device, row-major,
+ * column j = eigenvector j).  H is not modified. */
+dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dpp_c64 *H, double *eig,
+                             dpp_c64 *vecs, void *ws);
+dpp_status dpp_eigh_workspace_size(int nb, int batch, size_t *bytes);
+
+/* ------------------------------------------------ densities, potentials -- */
+
+/* d_n += wk * sum_b f_b |(I psi_b)(r)|^2 (f: device, nb doubles). */
+dpp_status dpp_density_accumulate(dpp_basis basis, int nb, const dpp_c64 *psi, int64_t ldpsi,
+                                  const double *d_f, double wk, double *d_n, dpp_precision prec,
+                                  void *ws);
+/* Hartree solve (coulomb operator): V_H = Re I[4 pi (J n)/|G|^2], G = 0
+ * dropped; E_H = (Omega/2) sum_{G != 0} 4 pi |J n|^2 / |G|^2 -> *d_EH. */
+dpp_status dpp_hartree(dpp_grid grid, const double *d_n, double *d_VH, double *d_EH, void *ws);
+/* LDA (Slater exchange + Perdew-Zunger 1981 correlation): v_xc per point
+ * and E_xc = (Omega/N) sum n eps_xc -> *d_Exc.  n < 1e-16 gives 0. */
+dpp_status dpp_lda_pz81(dpp_grid grid, const double *d_n, double *d_vxc, double *d_Exc, void *ws);
+/* V_loc(r) = Re I[sum_a v_a(|G|) exp(-i G.tau_a)], v_a(G) = -4 pi Z_a
+ * exp(-G^2 rc_a^2/4) / (Omega G^2), v_a(0) = 0.  Host tau (nat x 3), Z, rc. */
+dpp_status dpp_local_potential(dpp_grid grid, int nat, const double *tau, const double *Z,
+                               const double *rc, double *d_Vloc, void *ws);
+/* Superposition of atomic Gaussians: n0(G) = (1/Omega) sum_a Z_a
+ * exp(-G^2 sigma^2/4) exp(-i G.tau_a), n0(r) = Re I n0. */
+dpp_status dpp_start_density(dpp_grid grid, int nat, const double *tau, const double *Z,
+                             double sigma, double *d_n, void *ws);
+/* Deterministic sum_j a_j b_j * scale over N grid points -> *d_out (device). */
+dpp_status dpp_grid_dot(dpp_grid grid, const double *d_a, const double *d_b, double scale,
+                        double *d_out, void *ws);
+
+/* --------------------------------------------------------------- drivers -- */
+
+/* One periodic system: a cell, its k-points (Gamma-centred folding or any
+ * list) and the pseudopotential model of its atoms.  All arrays are host
+ * arrays read during the call.  The system owns its bases, Hamiltonians and
+ * every driver buffer (allocated here, never on later calls); wavefunction
+ * blocks Y stay caller-owned and use the packed layout of dpp_system_layout:
+ * the block of k-point k starts at element offsets[k] and holds nb bands of
+ * npw[k] coefficients each (ld = npw[k]). */
+typedef struct {
+    const double *R;        /* 9, columns = lattice vectors                */
+    const int *S;           /* 3, FFT box                                  */
+    double ecut;            /* hartree                                     */
+    int nk;
+    const double *kpts;     /* nk x 3 reduced                              */
+    const double *wk;       /* nk weights (sum 1)                          */
+    int nb;                 /* bands per k-point (<= 128)                  */
+    double n_electrons;
+    int nat;
+    const double *tau;      /* nat x 3 Cartesian                           */
+    const double *Z;        /* nat valence charges                         */
+    const double *rc;       /* nat erf radii of the local potential        */
+    const int *has_proj;    /* nat flags: atom carries the s-projector     */
+    double rp, D;           /* projector width and coupling                */
+    int prec;               /* dpp_precision of the FFT passes             */
+} dpp_system_desc;
+
+typedef struct {
+    double E_el, E_kin, E_nl, E_loc, E_H, E_xc;
+} dpp_energy;
+
+typedef struct {
+    int nat;
+    const double *tau;      /* superposition start density: atoms          */
+    const double *Z;
+    double sigma;           /* Gaussian width                              */
+    const double *d_n_start;/* device start density (overrides the atoms)  */
+    int n_inner;            /* band-CG steps per SCF iteration (0 -> 3)    */
+} dpp_scf_desc;
+
+enum { DPP_FIELD_VLOC = 0, DPP_FIELD_VEFF = 1, DPP_FIELD_N = 2, DPP_FIELD_NIN = 3, DPP_FIELD_NOUT = 4 };
+
+/* Synchronizes.  Builds bases, projectors and V_loc on the device. */
+dpp_status dpp_system_create(dpp_ctx ctx, const dpp_system_desc *desc, dpp_system *out);
+dpp_status dpp_system_destroy(dpp_system sys);
+/* offsets[nk+1] and npw[nk] of the packed wavefunction layout (host). */
+dpp_status dpp_system_layout(dpp_system sys, int64_t *offsets, int64_t *npw);
+/* Device pointer of an internal real-space field (DPP_FIELD_*), N doubles. */
+dpp_status dpp_system_field(dpp_system sys, int which, double **d_ptr);
+
+/* Variational minimization of E_el (Sec. 2.2) over the first nocc bands of
+ * every k-point with filling f, CG with one step length for all k.  init
+ * orthonormalizes those bands of Y once and evaluates E and its gradient;
+ * each step is one CG iteration (stationary = 1 once no step lowers E).
+ * Synchronizes (line-search decisions read energies back). */
+dpp_status dpp_cg_V_init(dpp_system sys, dpp_c64 *Y, int nocc, double f, dpp_energy *E);
+dpp_status dpp_cg_V_step(dpp_system sys, dpp_c64 *Y, dpp_energy *E, int *stationary);
+/* Band-energy minimization at fixed V_eff (device, N doubles), all nb bands,
+ * an independent line search per k-point.  Eb: host nk band energies
+ * Tr(U^{-1} Y^dag H Y) after the call.  Synchronizes. */
+dpp_status dpp_cg_B_init(dpp_system sys, dpp_c64 *Y, const double *d_Veff, double *Eb);
+dpp_status dpp_cg_B_step(dpp_system sys, dpp_c64 *Y, double *Eb);
+/* After band CG: subspace diagonalization Y <- psi V with eigenvalues
+ * eig (host, nk x nb, ascending per k).  Synchronizes. */
+dpp_status dpp_band_eigenvalues(dpp_system sys, dpp_c64 *Y, double *eig);
+
+/* SCF (Sec. 2.1 Pulay mixing; Sec. 2.2): start density from desc.
+ * One iteration: V_eff[n_in], n_inner band-CG steps per k, subspace
+ * diagonalization, aufbau fillings (a degenerate set within 1e-6 Ha at the
+ * Fermi level shares electrons equally), n_out, E_el[psi, n_out], Pulay
+ * mixing of n_in (history 8, alpha 0.5, first iteration linear).
+ * E and eig (host nk x nb, may be NULL) describe this iteration's output.
+ * Synchronizes. */
+dpp_status dpp_scf_init(dpp_system sys, const dpp_scf_desc *desc);
+dpp_status dpp_scf_iteration(dpp_system sys, dpp_c64 *Y, dpp_energy *E, double *eig);
+/* Number of (band, k-point) H applications performed by the system's
+ * drivers since creation (host output). */
+dpp_status dpp_system_counters(dpp_system sys, int64_t *hc_bandk);
+/* HY = H Y on all nb bands of every k-point (packed layout, at the
+ * potential last set: V_eff of the last SCF iteration or dpp_cg_B_init). */
+dpp_status dpp_system_apply_H(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY);
+/* Fillings of the last SCF iteration (host, nk x nb). */
+dpp_status dpp_system_fillings(dpp_system sys, double *f);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFTPP_H */

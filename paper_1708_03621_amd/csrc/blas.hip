@@ -1,0 +1,615 @@
+// Contractions on wavefunction blocks (FP64 MFMA), Cholesky factorization and
+// triangular inverse, Hermitian Jacobi eigensolver, and the full H apply.
+//
+// Complex products are built from real 16x16x4 FP64 MFMAs (v_mfma_f64_16x16x4f64):
+//   A^dag B :  Re = Ar.Br + Ai.Bi,  Im = Ar.Bi - Ai.Br
+//   X M     :  Re = Mr.Xr - Mi.Xi,  Im = Mi.Xr + Mr.Xi
+// MFMA operand layout (one wave, lane l): A[i][k] from lane (i + 16 k),
+// B[k][j] from lane (j + 16 k); result element v of lane l is
+// D[4 v + l / 16][l % 16] (checked on gfx950 with one-hot lane sums).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace dpp {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ----------------------------------------------------------- A^dag B -------
+// One wave accumulates one 16x16 tile of U over a K range; a workgroup of
+// OV_WAVES waves covers consecutive K sub-ranges of the same tile and sums
+// them in LDS in fixed order; the partial of each workgroup (chunk) is
+// written out and reduced by k_overlap_reduce in fixed order.
+constexpr int OV_WAVES = 4;
+constexpr int OV_CHUNK = 512;  // K (sphere points) per workgroup
+
+__global__ void __launch_bounds__(64 * OV_WAVES)
+k_overlap_mfma(int npw, int nbA, const double2* __restrict__ A, int64_t ldA, int nbB,
+               const double2* __restrict__ B, int64_t ldB, int tilesB, double2* __restrict__ part) {
+    __shared__ double red[OV_WAVES][2][4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int chunk = blockIdx.x;
+    const int tile = blockIdx.y;
+    const int ti = tile / tilesB, tj = tile - ti * tilesB;
+    const int r = lane & 15, ks = lane >> 4;
+    const int ia = ti * 16 + r, jb = tj * 16 + r;
+    const bool va = ia < nbA, vb = jb < nbB;
+    const double2* Ap = A + (int64_t)(va ? ia : 0) * ldA;
+    const double2* Bp = B + (int64_t)(vb ? jb : 0) * ldB;
+    d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    const int g0 = chunk * OV_CHUNK;
+    const int sub = OV_CHUNK / OV_WAVES;
+    const int ga = g0 + w * sub, ge = min(npw, ga + sub);
+    for (int g = ga; g < ge; g += 16) {
+        // lane covers points g + 4 ks + s, s = 0..3
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int q = g + 4 * ks + s;
+            double2 a = double2{0, 0}, b = double2{0, 0};
+            if (q < ge) {
+                if (va) a = Ap[q];
+                if (vb) b = Bp[q];
+            }
+            cre = mfma(a.x, b.x, cre);
+            cre = mfma(a.y, b.y, cre);
+            cim = mfma(a.x, b.y, cim);
+            cim = mfma(-a.y, b.x, cim);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        red[w][0][v][lane] = cre[v];
+        red[w][1][v][lane] = cim[v];
+    }
+    __syncthreads();
+    if (w == 0) {
+        double2* dst = part + ((int64_t)chunk * gridDim.y + tile) * 256;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double sr = 0, si = 0;
+            for (int u = 0; u < OV_WAVES; ++u) {
+                sr += red[u][0][v][lane];
+                si += red[u][1][v][lane];
+            }
+            const int i = 4 * v + (lane >> 4), j = lane & 15;
+            dst[i * 16 + j] = double2{sr, si};
+        }
+    }
+}
+
+__global__ void k_overlap_reduce(const double2* __restrict__ part, int nchunk, int ntiles, int tilesB,
+                                 int nbA, int nbB, double scale, double2* __restrict__ U) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ntiles * 256) return;
+    const int tile = e >> 8, ij = e & 255;
+    const int ti = tile / tilesB, tj = tile - ti * tilesB;
+    const int i = ti * 16 + (ij >> 4), j = tj * 16 + (ij & 15);
+    if (i >= nbA || j >= nbB) return;
+    double sr = 0, si = 0;
+    for (int c = 0; c < nchunk; ++c) {
+        const double2 v = part[((int64_t)c * ntiles + tile) * 256 + ij];
+        sr += v.x;
+        si += v.y;
+    }
+    U[(int64_t)i * nbB + j] = double2{scale * sr, scale * si};
+}
+
+size_t overlap_ws_bytes(int npw, int nbA, int nbB) {
+    const int nchunk = std::max(1, (npw + OV_CHUNK - 1) / OV_CHUNK);
+    const int ntiles = ((nbA + 15) / 16) * ((nbB + 15) / 16);
+    return (size_t)nchunk * ntiles * 256 * sizeof(double2) + 256;
+}
+
+dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
+                       const double2* B, int64_t ldB, double scale, double2* U, void* ws,
+                       size_t ws_bytes) {
+    const int nchunk = std::max(1, (npw + OV_CHUNK - 1) / OV_CHUNK);
+    const int tilesA = (nbA + 15) / 16, tilesB = (nbB + 15) / 16;
+    const int ntiles = tilesA * tilesB;
+    if (overlap_ws_bytes(npw, nbA, nbB) > ws_bytes)
+        return set_error(DPP_EINVAL, "overlap: workspace too small");
+    if (ntiles > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: too many bands");
+    double2* part = reinterpret_cast<double2*>(ws);
+    {
+    TimerScope ts_(ctx, DPP_TK_OVERLAP, 16.0 * npw * (nbA + nbB), 8.0 * npw * nbA * (double)nbB);
+    hipLaunchKernelGGL(k_overlap_mfma, dim3(nchunk, ntiles), dim3(64 * OV_WAVES), 0, ctx->stream, npw, nbA, A,
+                       ldA, nbB, B, ldB, tilesB, part);
+    DPP_LAUNCHED();
+    }
+    TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
+    hipLaunchKernelGGL(k_overlap_reduce, dim3((ntiles * 256 + 255) / 256), dim3(256), 0, ctx->stream, part,
+                       nchunk, ntiles, tilesB, nbA, nbB, scale, U);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+// ---------------------------------------------------------------- X M ------
+// One wave owns 16 consecutive sphere points and up to RT_JT x 16 output
+// bands; X is read once per wave.
+constexpr int RT_WAVES = 4;
+constexpr int RT_JT = 8;
+
+__global__ void __launch_bounds__(64 * RT_WAVES)
+k_rotate_mfma(int npw, int nbX, const double2* __restrict__ X, int64_t ldX, int nbO,
+              const double2* __restrict__ M, double beta, double2* __restrict__ out, int64_t ldout,
+              int jt0) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gt = blockIdx.x * RT_WAVES + w;
+    const int G0 = gt * 16;
+    if (G0 >= npw) return;
+    const int c = lane & 15, ks = lane >> 4;
+    const int q = G0 + c;
+    const bool vq = q < npw;
+    const int njt = min(RT_JT, (nbO + 15) / 16 - jt0);
+    d4 dre[RT_JT], dim[RT_JT];
+#pragma unroll
+    for (int t = 0; t < RT_JT; ++t) {
+        dre[t] = d4{0, 0, 0, 0};
+        dim[t] = d4{0, 0, 0, 0};
+    }
+    for (int i0 = 0; i0 < nbX; i0 += 4) {
+        const int i = i0 + ks;
+        double2 x = double2{0, 0};
+        if (i < nbX && vq) x = X[(int64_t)i * ldX + q];
+#pragma unroll
+        for (int t = 0; t < RT_JT; ++t) {
+            if (t < njt) {
+                const int j = (jt0 + t) * 16 + c;
+                double2 m = double2{0, 0};
+                if (i < nbX && j < nbO) m = M[(int64_t)i * nbO + j];
+                dre[t] = mfma(m.x, x.x, dre[t]);
+                dre[t] = mfma(-m.y, x.y, dre[t]);
+                dim[t] = mfma(m.y, x.x, dim[t]);
+                dim[t] = mfma(m.x, x.y, dim[t]);
+            }
+        }
+    }
+    if (!vq) return;
+#pragma unroll
+    for (int t = 0; t < RT_JT; ++t) {
+        if (t < njt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = (jt0 + t) * 16 + 4 * v + ks;
+                if (j < nbO) {
+                    double2* o = out + (int64_t)j * ldout + q;
+                    double2 r = double2{dre[t][v], dim[t][v]};
+                    if (beta != 0.0) {
+                        const double2 p = *o;
+                        r.x += beta * p.x;
+                        r.y += beta * p.y;
+                    }
+                    *o = r;
+                }
+            }
+        }
+    }
+}
+
+dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
+                      const double2* M, double beta, double2* out, int64_t ldout) {
+    const int ntile = (npw + 15) / 16;
+    const int nblk = (ntile + RT_WAVES - 1) / RT_WAVES;
+    const int jtiles = (nbO + 15) / 16;
+    TimerScope ts_(ctx, DPP_TK_ROTATE, 16.0 * npw * (nbX + nbO * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * nbX * nbO,
+                   8.0 * npw * nbX * (double)nbO);
+    for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT) {
+        hipLaunchKernelGGL(k_rotate_mfma, dim3(nblk), dim3(64 * RT_WAVES), 0, ctx->stream, npw, nbX, X, ldX, nbO,
+                           M, beta, out, ldout, jt0);
+        DPP_LAUNCHED();
+    }
+    return DPP_OK;
+}
+
+// ------------------------------------------------------------ Cholesky -----
+// One workgroup per matrix.  Right-looking factorization U = R^dag R on a
+// copy of the upper triangle packed in LDS (n(n+1)/2 entries: 132 KB at
+// n = 128), then R^{-1} by column back substitution.
+constexpr int CH_MAXN = 128;
+constexpr double CH_PIVOT_RTOL = 1e-14;
+
+__device__ __forceinline__ int up_idx(int n, int r, int c) { return r * n - (r * (r - 1)) / 2 + (c - r); }
+
+__global__ void __launch_bounds__(256)
+k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ Rinv,
+                   int* __restrict__ status) {
+    extern __shared__ char smem_raw[];
+    double2* A = reinterpret_cast<double2*>(smem_raw);  // packed upper triangle
+    __shared__ int fail;
+    __shared__ double umax;
+    const int64_t off = (int64_t)blockIdx.x * n * n;
+    const double2* Ug = U + off;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int r = e / n, c = e - r * n;
+        if (c >= r) A[up_idx(n, r, c)] = Ug[e];
+    }
+    if (threadIdx.x == 0) {
+        fail = 0;
+        double m = 0;
+        for (int i = 0; i < n; ++i) m = fmax(m, Ug[(int64_t)i * n + i].x);
+        umax = m;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double d = A[up_idx(n, j, j)].x;
+        if (!(d > CH_PIVOT_RTOL * umax)) {
+            if (threadIdx.x == 0) fail = 1;
+            break;  // uniform: every thread read the same d
+        }
+        const double rjj = sqrt(d);
+        const double inv = 1.0 / rjj;
+        __syncthreads();
+        // row j of R
+        for (int c = j + 1 + threadIdx.x; c < n; c += blockDim.x) {
+            const double2 v = A[up_idx(n, j, c)];
+            A[up_idx(n, j, c)] = double2{v.x * inv, v.y * inv};
+        }
+        if (threadIdx.x == 0) A[up_idx(n, j, j)] = double2{rjj, 0.0};
+        __syncthreads();
+        // trailing update A[r][c] -= conj(R[j][r]) R[j][c], j < r <= c
+        const int m = n - j - 1;
+        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+            const int r = j + 1 + e / m, c = j + 1 + e % m;
+            if (c >= r) {
+                const double2 a = A[up_idx(n, j, r)], b = A[up_idx(n, j, c)];
+                const double re = a.x * b.x + a.y * b.y, im = a.x * b.y - a.y * b.x;  // conj(a) b
+                const int k = up_idx(n, r, c);
+                A[k].x -= re;
+                A[k].y -= im;
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    double2* X = Rinv + off;
+    if (fail) {
+        if (threadIdx.x == 0) atomicOr(status, DPP_STATUS_NOTPD);
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) X[e] = double2{NAN, NAN};
+        return;
+    }
+    // R^{-1}: column c solved by one thread (upper triangular back substitution)
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        for (int r = c + 1; r < n; ++r) X[(int64_t)r * n + c] = double2{0, 0};
+        X[(int64_t)c * n + c] = double2{1.0 / A[up_idx(n, c, c)].x, 0.0};
+        for (int r = c - 1; r >= 0; --r) {
+            double sr = 0, si = 0;
+            for (int k = r + 1; k <= c; ++k) {
+                const double2 a = A[up_idx(n, r, k)];
+                const double2 x = X[(int64_t)k * n + c];
+                sr += a.x * x.x - a.y * x.y;
+                si += a.x * x.y + a.y * x.x;
+            }
+            const double inv = 1.0 / A[up_idx(n, r, r)].x;
+            X[(int64_t)r * n + c] = double2{-sr * inv, -si * inv};
+        }
+    }
+}
+
+// ----------------------------------------------------- Jacobi eigensolver --
+// Parallel cyclic Jacobi on a Hermitian matrix (one workgroup per matrix):
+// each round rotates n/2 disjoint pairs of a round-robin tournament.  For the
+// pair (p,q) with A_pq = |c| e^{i phi}, J = diag-phase * real rotation:
+//   tau = (A_qq - A_pp) / (2|c|), t = sign(tau)/(|tau| + sqrt(1+tau^2)),
+//   cs = 1/sqrt(1+t^2), sn = t cs,
+//   J[p][p] = cs, J[p][q] = sn, J[q][p] = -sn e^{-i phi}, J[q][q] = cs e^{-i phi}
+// and A <- J^dag A J, V <- V J.
+constexpr int EIG_MAXN = 128;
+constexpr int EIG_SWEEPS = 40;
+
+struct Rot {
+    int p, q;
+    double cs, sn, er, ei;  // e^{-i phi} = er + i ei
+};
+
+__global__ void __launch_bounds__(256)
+k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, double2* __restrict__ vecs,
+              double2* __restrict__ scratch) {
+    extern __shared__ char smem_raw[];
+    const int m = n + (n & 1);  // even number of players (a dummy if n odd)
+    const bool in_lds = n <= 64;
+    double2* A;
+    double2* V;
+    if (in_lds) {
+        A = reinterpret_cast<double2*>(smem_raw);
+        V = A + n * n;
+    } else {
+        A = scratch + (int64_t)blockIdx.x * 2 * n * n;
+        V = A + n * n;
+    }
+    __shared__ Rot rot[EIG_MAXN / 2];
+    __shared__ int order[EIG_MAXN + 2];
+    __shared__ double red[256];
+    __shared__ int done;
+    const double2* Hg = H + (int64_t)blockIdx.x * n * n;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        double2 h = Hg[e];
+        const int r = e / n, c = e % n;
+        if (r == c) h.y = 0.0;
+        A[e] = h;
+        V[e] = double2{r == c ? 1.0 : 0.0, 0.0};
+    }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) order[i] = i;
+    __syncthreads();
+    for (int sweep = 0; sweep < EIG_SWEEPS; ++sweep) {
+        // convergence: off-diagonal Frobenius norm vs diagonal scale
+        double off = 0, dia = 0;
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int r = e / n, c = e % n;
+            const double2 a = A[e];
+            if (r != c)
+                off += a.x * a.x + a.y * a.y;
+            else
+                dia += a.x * a.x;
+        }
+        red[threadIdx.x] = off;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        const double offt = red[0];
+        __syncthreads();
+        red[threadIdx.x] = dia;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        const double diat = red[0];
+        if (threadIdx.x == 0) done = (offt <= 1e-30 * fmax(diat, 1e-300)) || offt == 0.0;
+        __syncthreads();
+        if (done) break;
+        for (int round = 0; round < m - 1; ++round) {
+            // pairs (order[2s], order[2s+1])
+            for (int s = threadIdx.x; s < m / 2; s += blockDim.x) {
+                int p = order[s], q = order[m - 1 - s];
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                Rot R;
+                R.p = p;
+                R.q = q;
+                R.cs = 1.0;
+                R.sn = 0.0;
+                R.er = 1.0;
+                R.ei = 0.0;
+                if (q < n) {
+                    const double2 c = A[p * n + q];
+                    const double ac = sqrt(c.x * c.x + c.y * c.y);
+                    const double app = A[p * n + p].x, aqq = A[q * n + q].x;
+                    if (ac > 1e-300 && ac > 1e-18 * sqrt(fabs(app * aqq))) {
+                        const double tau = (aqq - app) / (2.0 * ac);
+                        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        R.cs = 1.0 / sqrt(1.0 + t * t);
+                        R.sn = t * R.cs;
+                        R.er = c.x / ac;
+                        R.ei = -c.y / ac;
+                    }
+                } else {
+                    R.q = -1;
+                }
+                rot[s] = R;
+            }
+            __syncthreads();
+            // columns: A[:, p], A[:, q] <- A[:, [p q]] J ; V likewise
+            for (int e = threadIdx.x; e < (m / 2) * n; e += blockDim.x) {
+                const int s = e / n, r = e % n;
+                const Rot R = rot[s];
+                if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
+                const double2 e2 = double2{R.er, R.ei};
+                for (int which = 0; which < 2; ++which) {
+                    double2* M = which ? V : A;
+                    const double2 ap = M[r * n + R.p], aq = M[r * n + R.q];
+                    // new_p = cs ap - sn e aq ; new_q = sn ap + cs e aq   (e = e^{-i phi})
+                    const double2 eaq = double2{e2.x * aq.x - e2.y * aq.y, e2.x * aq.y + e2.y * aq.x};
+                    M[r * n + R.p] = double2{R.cs * ap.x - R.sn * eaq.x, R.cs * ap.y - R.sn * eaq.y};
+                    M[r * n + R.q] = double2{R.sn * ap.x + R.cs * eaq.x, R.sn * ap.y + R.cs * eaq.y};
+                }
+            }
+            __syncthreads();
+            // rows: A[p, :], A[q, :] <- J^dag A[[p q], :]
+            for (int e = threadIdx.x; e < (m / 2) * n; e += blockDim.x) {
+                const int s = e / n, c = e % n;
+                const Rot R = rot[s];
+                if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
+                const double2 ap = A[R.p * n + c], aq = A[R.q * n + c];
+                // conj(e) aq
+                const double2 eaq = double2{R.er * aq.x + R.ei * aq.y, R.er * aq.y - R.ei * aq.x};
+                A[R.p * n + c] = double2{R.cs * ap.x - R.sn * eaq.x, R.cs * ap.y - R.sn * eaq.y};
+                A[R.q * n + c] = double2{R.sn * ap.x + R.cs * eaq.x, R.sn * ap.y + R.cs * eaq.y};
+            }
+            __syncthreads();
+            // clean the rotated pair exactly and rotate the tournament
+            if (threadIdx.x == 0) {
+                for (int s = 0; s < m / 2; ++s) {
+                    const Rot R = rot[s];
+                    if (R.q < 0) continue;
+                    A[R.p * n + R.q] = double2{0, 0};
+                    A[R.q * n + R.p] = double2{0, 0};
+                    A[R.p * n + R.p].y = 0.0;
+                    A[R.q * n + R.q].y = 0.0;
+                }
+                const int last = order[m - 1];
+                for (int i = m - 1; i > 1; --i) order[i] = order[i - 1];
+                order[1] = last;
+            }
+            __syncthreads();
+        }
+    }
+    // sort eigenvalues ascending (selection, thread 0), then emit
+    __shared__ int perm[EIG_MAXN];
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = 0; i < n; ++i) {
+            int best = i;
+            for (int j = i + 1; j < n; ++j)
+                if (A[perm[j] * n + perm[j]].x < A[perm[best] * n + perm[best]].x) best = j;
+            const int t = perm[i];
+            perm[i] = perm[best];
+            perm[best] = t;
+        }
+    }
+    __syncthreads();
+    double* ev = eig + (int64_t)blockIdx.x * n;
+    double2* vo = vecs + (int64_t)blockIdx.x * n * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = A[perm[i] * n + perm[i]].x;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int r = e / n, c = e % n;
+        vo[e] = V[r * n + perm[c]];
+    }
+}
+
+}  // namespace dpp
+
+using namespace dpp;
+
+// ------------------------------------------------------------- C ABI -------
+
+extern "C" dpp_status dpp_overlap(dpp_basis basis, int nbA, const dpp_c64* A, int64_t ldA, int nbB,
+                                  const dpp_c64* B, int64_t ldB, double scale, dpp_c64* U, void* ws) {
+    clear_error();
+    DPP_REQUIRE(basis && nbA >= 0 && nbB >= 0, "dpp_overlap: bad arguments");
+    DPP_REQUIRE((nbA == 0 || A) && (nbB == 0 || B), "dpp_overlap: null block");
+    DPP_REQUIRE(ldA >= basis->npw && ldB >= basis->npw, "dpp_overlap: leading dimension < npw");
+    if (nbA == 0 || nbB == 0) return DPP_OK;
+    DPP_REQUIRE(U && ws, "dpp_overlap: null output or workspace");
+    return overlap_f64(basis->grid->ctx, (int)basis->npw, nbA, (const double2*)A, ldA, nbB, (const double2*)B,
+                       ldB, scale, (double2*)U, ws, overlap_ws_bytes((int)basis->npw, nbA, nbB));
+}
+
+extern "C" dpp_status dpp_rotate(dpp_basis basis, int nbX, const dpp_c64* X, int64_t ldX, int nbO,
+                                 const dpp_c64* M, double beta, dpp_c64* out, int64_t ldout) {
+    clear_error();
+    DPP_REQUIRE(basis && nbX >= 0 && nbO >= 0, "dpp_rotate: bad arguments");
+    DPP_REQUIRE(ldX >= basis->npw && ldout >= basis->npw, "dpp_rotate: leading dimension < npw");
+    if (nbO == 0) return DPP_OK;
+    DPP_REQUIRE(out && (nbX == 0 || (X && M)), "dpp_rotate: null pointer");
+    DPP_REQUIRE((const void*)X != (const void*)out, "dpp_rotate: out must not alias X");
+    return rotate_f64(basis->grid->ctx, (int)basis->npw, nbX, (const double2*)X, ldX, nbO, (const double2*)M,
+                      beta, (double2*)out, ldout);
+}
+
+extern "C" dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const dpp_c64* U, dpp_c64* Rinv) {
+    clear_error();
+    DPP_REQUIRE(ctx && nb >= 1 && batch >= 0 && U && Rinv, "dpp_cholesky_inverse: bad arguments");
+    DPP_REQUIRE(nb <= CH_MAXN, "dpp_cholesky_inverse: nb > 128");
+    if (batch == 0) return DPP_OK;
+    const size_t lds = (size_t)nb * (nb + 1) / 2 * sizeof(double2);
+    if (lds > 64 * 1024)
+        DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    TimerScope ts_(ctx, DPP_TK_CHOLESKY);
+    hipLaunchKernelGGL(k_cholesky_inverse, dim3(batch), dim3(256), lds, ctx->stream, nb, (const double2*)U,
+                       (double2*)Rinv, ctx->d_status);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_eigh_workspace_size(int nb, int batch, size_t* bytes) {
+    clear_error();
+    DPP_REQUIRE(bytes && nb >= 1 && batch >= 0, "dpp_eigh_workspace_size: bad arguments");
+    *bytes = nb <= 64 ? 256 : (size_t)batch * 2 * nb * nb * sizeof(double2) + 256;
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dpp_c64* H, double* eig,
+                                        dpp_c64* vecs, void* ws) {
+    clear_error();
+    DPP_REQUIRE(ctx && nb >= 1 && batch >= 0, "dpp_subspace_eigh: bad arguments");
+    DPP_REQUIRE(nb <= EIG_MAXN, "dpp_subspace_eigh: nb > 128");
+    if (batch == 0) return DPP_OK;
+    DPP_REQUIRE(H && eig && vecs, "dpp_subspace_eigh: null pointer");
+    DPP_REQUIRE(nb <= 64 || ws, "dpp_subspace_eigh: workspace required for nb > 64");
+    const size_t lds = nb <= 64 ? (size_t)2 * nb * nb * sizeof(double2) : 0;
+    if (lds > 64 * 1024)
+        DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    TimerScope ts_(ctx, DPP_TK_EIGH);
+    hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(256), lds, ctx->stream, nb, (const double2*)H, eig,
+                       (double2*)vecs, (double2*)ws);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+size_t dpp::proj_ws_bytes(const dpp_basis_s* b, int nb) {
+    // Pi (64 projectors max per call chunk is not assumed: use the actual count later)
+    return overlap_ws_bytes((int)b->npw, 128, nb) + (size_t)128 * nb * sizeof(double2) + 512;
+}
+
+extern "C" dpp_status dpp_apply_H(dpp_ham ham, int nb, const dpp_c64* C, int64_t ldC, dpp_c64* HC,
+                                  int64_t ldHC, dpp_precision prec, void* ws) {
+    clear_error();
+    DPP_REQUIRE(ham, "dpp_apply_H: null ham");
+    dpp_basis b = ham->basis;
+    DPP_REQUIRE(nb >= 0 && ldC >= b->npw && ldHC >= b->npw, "dpp_apply_H: bad sizes");
+    if (nb == 0) return DPP_OK;
+    DPP_REQUIRE(C && HC && ws, "dpp_apply_H: null pointer");
+    DPP_REQUIRE((const void*)C != (const void*)HC, "dpp_apply_H: C and HC must not alias");
+    DPP_REQUIRE(ham->d_Veff, "dpp_apply_H: no potential set");
+    DPP_REQUIRE(prec == DPP_F64 || prec == DPP_F32, "dpp_apply_H: bad precision");
+    DPP_REQUIRE(ham->nproj <= 128, "dpp_apply_H: more than 128 projectors");
+    if (prec == DPP_F64)
+        DPP_TRY(run_apply_H_local<double>(ham, nb, (const double2*)C, ldC, (double2*)HC, ldHC, ws));
+    else
+        DPP_TRY(run_apply_H_local<float>(ham, nb, (const double2*)C, ldC, (double2*)HC, ldHC, ws));
+    if (ham->nproj > 0) {
+        const size_t el = prec == DPP_F64 ? 16 : 8;
+        const size_t t = ((plane_buffer_elems(b, nb) * el + 255) / 256) * 256;
+        char* base = reinterpret_cast<char*>(ws) + t;
+        double2* Pi = reinterpret_cast<double2*>(base);
+        char* ovws = base + (((size_t)ham->nproj * nb * sizeof(double2) + 255) / 256) * 256;
+        // Pi' = D P^dag C, then HC += P Pi'
+        DPP_TRY(overlap_f64(b->grid->ctx, (int)b->npw, ham->nproj, ham->d_P, b->npw, nb, (const double2*)C, ldC,
+                            ham->D, Pi, ovws, overlap_ws_bytes((int)b->npw, ham->nproj, nb)));
+        DPP_TRY(rotate_f64(b->grid->ctx, (int)b->npw, ham->nproj, ham->d_P, b->npw, nb, Pi, 1.0, (double2*)HC,
+                           ldHC));
+    }
+    return DPP_OK;
+}
+
+static size_t ortho_ws(const dpp_basis_s* b, int nb) {
+    auto r = [](size_t x) { return ((x + 255) / 256) * 256; };
+    return 2 * r((size_t)nb * nb * 16) + r((size_t)nb * b->npw * 16) + r(overlap_ws_bytes((int)b->npw, nb, nb)) + 256;
+}
+
+extern "C" dpp_status dpp_ortho_workspace_size(dpp_basis basis, int nb, size_t* bytes) {
+    clear_error();
+    DPP_REQUIRE(basis && nb >= 1 && bytes, "dpp_ortho_workspace_size: bad arguments");
+    *bytes = ortho_ws(basis, nb);
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_cholesky_orthonormalize(dpp_basis basis, int nb, dpp_c64* Y, int64_t ldY,
+                                                  dpp_c64* Rinv, void* ws) {
+    clear_error();
+    DPP_REQUIRE(basis && nb >= 1 && Y && ws && ldY >= basis->npw, "dpp_cholesky_orthonormalize: bad arguments");
+    // ws layout: U (nb^2), Rinv (nb^2) if not given, copy of Y (nb x npw), overlap partials
+    char* p = reinterpret_cast<char*>(ws);
+    auto take = [&](size_t bytes) {
+        char* r = p;
+        p += ((bytes + 255) / 256) * 256;
+        return r;
+    };
+    double2* U = reinterpret_cast<double2*>(take((size_t)nb * nb * 16));
+    double2* Ri = Rinv ? (double2*)Rinv : reinterpret_cast<double2*>(take((size_t)nb * nb * 16));
+    double2* Yc = reinterpret_cast<double2*>(take((size_t)nb * basis->npw * 16));
+    void* ovws = take(overlap_ws_bytes((int)basis->npw, nb, nb));
+    dpp_ctx ctx = basis->grid->ctx;
+    DPP_TRY(overlap_f64(ctx, (int)basis->npw, nb, (const double2*)Y, ldY, nb, (const double2*)Y, ldY,
+                        basis->grid->omega, U, ovws, overlap_ws_bytes((int)basis->npw, nb, nb)));
+    DPP_TRY(dpp_cholesky_inverse(ctx, nb, 1, (const dpp_c64*)U, (dpp_c64*)Ri));
+    DPP_HIP(hipMemcpy2DAsync(Yc, basis->npw * 16, Y, ldY * 16, basis->npw * 16, nb, hipMemcpyDeviceToDevice,
+                             ctx->stream));
+    DPP_TRY(rotate_f64(ctx, (int)basis->npw, nb, Yc, basis->npw, nb, Ri, 0.0, (double2*)Y, ldY));
+    return DPP_OK;
+}

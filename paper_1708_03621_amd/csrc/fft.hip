@@ -1,0 +1,830 @@
+// Sphere <-> grid transforms (I, I^dag), the local part of H, full-box
+// transforms (J, J^dag), the Hartree solve and density accumulation.
+//
+// A 3D transform is split into three passes over an intermediate buffer that
+// holds, per band, only the x-planes the G-sphere touches (Miller index n0 in
+// [n0min, n0max]):
+//   pass 1 (plane kernel)  one workgroup per (item, band, plane): scatter the
+//                          plane's sphere points into LDS, transform along z
+//                          (only the rows holding points) and along y, store
+//                          the S1 x S2 plane.
+//   pass 2 (xz kernel)     one workgroup per (item, band, i1): gather the
+//                          pruned rows of the x-z plane, zero the others,
+//                          transform along x, apply the pointwise operation
+//                          (V_eff multiply, |psi|^2, store), transform back,
+//                          store the pruned rows.
+//   pass 3 (plane kernel)  transform y then z (pruned rows) and gather the
+//                          sphere points (plus the kinetic term for H).
+// Full-box fields use the same passes with every plane and row present.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "fft_engine.h"
+#include "internal.h"
+
+namespace dpp {
+
+bool factor_axis(int n, FftAxis* ax) {
+    ax->n = n;
+    ax->nrad = 0;
+    int m = n;
+    while (m % 4 == 0 && ax->nrad < MAX_RADICES) ax->rad[ax->nrad++] = 4, m /= 4;
+    while (m % 2 == 0 && ax->nrad < MAX_RADICES) ax->rad[ax->nrad++] = 2, m /= 2;
+    while (m % 3 == 0 && ax->nrad < MAX_RADICES) ax->rad[ax->nrad++] = 3, m /= 3;
+    while (m % 5 == 0 && ax->nrad < MAX_RADICES) ax->rad[ax->nrad++] = 5, m /= 5;
+    return m == 1;
+}
+
+// Threads per workgroup for a tile of `elems` complex values: each thread
+// holds at most 16 complex values per stage (radix 3 and 5: 15).
+int fft_threads(int elems) {
+    if (elems <= 15 * 256) return 256;
+    if (elems <= 15 * 512) return 512;
+    if (elems <= 8 * 1024) return 1024;
+    return 0;
+}
+
+size_t fft_lds_bytes(int elems, bool fp64) { return (size_t)elems * (fp64 ? 16 : 8); }
+
+dpp_status check_fft_shape(int S0, int S1, int S2, bool fp64) {
+    const int e1 = S1 * S2, e2 = S0 * S2;
+    const int e = std::max(e1, e2);
+    if (fft_threads(e) == 0 || fft_lds_bytes(e, fp64) > 160 * 1024)
+        return set_error(DPP_EUNSUPPORTED, "FFT plane too large for one workgroup's LDS");
+    return DPP_OK;
+}
+
+size_t plane_buffer_elems(const dpp_basis_s* b, int nb) {
+    return (size_t)nb * b->nplanes * b->grid->S[1] * b->grid->S[2];
+}
+
+template <typename T>
+__device__ __forceinline__ const double2* TW64(const FftItem& it, int a) {
+    return it.tw64[a];
+}
+
+template <typename T>
+struct Io;
+template <>
+struct Io<double> {
+    __device__ static double2 from(double2 v) { return v; }
+    __device__ static double2 from(float2 v) { return double2{v.x, v.y}; }
+    __device__ static double2 to_d(double2 v) { return v; }
+};
+template <>
+struct Io<float> {
+    __device__ static float2 from(double2 v) { return float2{(float)v.x, (float)v.y}; }
+    __device__ static float2 from(float2 v) { return v; }
+    __device__ static double2 to_d(float2 v) { return double2{v.x, v.y}; }
+};
+
+template <typename TO>
+struct Out;
+template <>
+struct Out<double2> {
+    __device__ static double2 make(double x, double y) { return double2{x, y}; }
+};
+template <>
+struct Out<float2> {
+    __device__ static float2 make(double x, double y) { return float2{(float)x, (float)y}; }
+};
+template <typename TO, typename C>
+__device__ __forceinline__ TO store_as(C v) {
+    return Out<TO>::make((double)v.x, (double)v.y);
+}
+
+// Kernels take the item either by value (one item per launch) or from a device
+// table indexed by blockIdx.z (batched launches); the choice is compile-time.
+#define DPP_ITEM(items, single) (BATCH ? (items)[blockIdx.z] : (single))
+
+// ------------------------------------------------------------- pass 1 ------
+// Sphere coefficients -> inverse transform along z and y -> plane buffer.
+template <typename T, typename TIO, int NT, bool BATCH = false>
+__global__ void __launch_bounds__(NT)
+k_planes_from_sphere(const FftItem* items, FftItem single, const TIO* __restrict__ C,
+                     typename cx<T>::t* __restrict__ Tb) {
+    using Cx = typename cx<T>::t;
+    const FftItem& it = DPP_ITEM(items, single);
+    const int p = blockIdx.x, b = blockIdx.y;
+    if (p >= it.nplanes || b >= it.nb) return;
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int S1 = it.S1, S2 = it.S2, np = S1 * S2;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = Cx{0, 0};
+    const int4 pl = it.planes[p];
+    __syncthreads();
+    const TIO* src = C + it.c_off + (int64_t)b * it.ld + pl.x;
+    const int* poff = it.poff + pl.x;
+    for (int q = threadIdx.x; q < pl.y; q += blockDim.x) lds[poff[q]] = Io<T>::from(src[q]);
+    __syncthreads();
+    fft_axis<T, false, NT>(lds, it.ax[2], pl.w, AddrRowsWrap{S2, pl.z, S1}, it.tw64[2], it.tw32[2], +1);
+    fft_axis<T, true, NT>(lds, it.ax[1], S2, AddrLinear{1, S2}, it.tw64[1], it.tw32[1], +1);
+    Cx* dst = Tb + it.t_off + ((int64_t)b * it.nplanes + p) * np;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = lds[i];
+}
+
+// Full-box field plane i0 -> 2D transform (sign) -> plane buffer.
+// REAL_IN: input is real (double), else complex (double2).
+template <typename T, bool REAL_IN, int NT>
+__global__ void __launch_bounds__(NT)
+k_planes_from_box(FftItem it, const void* __restrict__ in, int64_t field_stride, int sign,
+                  typename cx<T>::t* __restrict__ Tb) {
+    using Cx = typename cx<T>::t;
+    const int p = blockIdx.x, f = blockIdx.y;
+    if (p >= it.S0) return;
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int S1 = it.S1, S2 = it.S2, np = S1 * S2;
+    const int64_t base = (int64_t)f * field_stride + (int64_t)p * np;
+    if (REAL_IN) {
+        const double* src = reinterpret_cast<const double*>(in) + base;
+        for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = Cx{(T)src[i], (T)0};
+    } else {
+        const double2* src = reinterpret_cast<const double2*>(in) + base;
+        for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = Io<T>::from(src[i]);
+    }
+    __syncthreads();
+    fft_axis<T, false, NT>(lds, it.ax[2], S1, AddrLinear{S2, 1}, it.tw64[2], it.tw32[2], sign);
+    fft_axis<T, true, NT>(lds, it.ax[1], S2, AddrLinear{1, S2}, it.tw64[1], it.tw32[1], sign);
+    Cx* dst = Tb + (int64_t)f * it.S0 * np + (int64_t)p * np;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = lds[i];
+}
+
+// ------------------------------------------------------------- pass 2 ------
+enum XzMode { XZ_H = 0, XZ_TO_BOX = 1, XZ_FROM_BOX = 2 };
+
+__device__ __forceinline__ int wrap(int n, int S) { return n < 0 ? n + S : n; }
+
+// Load the pruned rows of x-z plane (band b, i1) from the plane buffer into
+// LDS rows i0 = (n0min + p) mod S0, zeroing the rows without data.
+template <typename T>
+__device__ __forceinline__ void xz_load_pruned(const FftItem& it, const typename cx<T>::t* Tb,
+                                               int b, int i1, typename cx<T>::t* lds) {
+    using Cx = typename cx<T>::t;
+    const int S0 = it.S0, S1 = it.S1, S2 = it.S2;
+    const int np = S1 * S2;
+    const int nP = it.nplanes;
+    // zero the rows whose Miller index lies outside [n0min, n0min + nplanes)
+    for (int i = threadIdx.x; i < S0 * S2; i += blockDim.x) {
+        const int i0 = i / S2;
+        int d = (i0 - it.n0min) % S0;
+        d += d < 0 ? S0 : 0;
+        if (d >= nP) lds[i] = Cx{0, 0};
+    }
+    const Cx* src = Tb + it.t_off + (int64_t)b * nP * np + (int64_t)i1 * S2;
+    for (int i = threadIdx.x; i < nP * S2; i += blockDim.x) {
+        const int p = i / S2, i2 = i - p * S2;
+        const int i0 = wrap(it.n0min + p, S0);
+        lds[i0 * S2 + i2] = src[(int64_t)p * np + i2];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void xz_store_pruned(const FftItem& it, typename cx<T>::t* Tb, int b,
+                                                int i1, const typename cx<T>::t* lds) {
+    using Cx = typename cx<T>::t;
+    const int S0 = it.S0, S1 = it.S1, S2 = it.S2;
+    const int np = S1 * S2;
+    const int nP = it.nplanes;
+    Cx* dst = Tb + it.t_off + (int64_t)b * nP * np + (int64_t)i1 * S2;
+    for (int i = threadIdx.x; i < nP * S2; i += blockDim.x) {
+        const int p = i / S2, i2 = i - p * S2;
+        const int i0 = wrap(it.n0min + p, S0);
+        dst[(int64_t)p * np + i2] = lds[i0 * S2 + i2];
+    }
+}
+
+template <typename T, int MODE, typename TIO, int NT, bool BATCH = false>
+__global__ void __launch_bounds__(NT)
+k_xz(const FftItem* items, FftItem single, typename cx<T>::t* __restrict__ Tb,
+     const double* __restrict__ V, TIO* __restrict__ box) {
+    using Cx = typename cx<T>::t;
+    const FftItem& it = DPP_ITEM(items, single);
+    const int i1 = blockIdx.x, b = blockIdx.y;
+    if (i1 >= it.S1 || b >= it.nb) return;
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int S0 = it.S0, S1 = it.S1, S2 = it.S2;
+    const int e = S0 * S2;
+    const int64_t N = (int64_t)S0 * S1 * S2;
+    if (MODE == XZ_FROM_BOX) {
+        const TIO* src = box + (int64_t)b * N + (int64_t)i1 * S2;
+        for (int i = threadIdx.x; i < e; i += blockDim.x) {
+            const int i0 = i / S2, i2 = i - i0 * S2;
+            lds[i] = Io<T>::from(src[(int64_t)i0 * S1 * S2 + i2]);
+        }
+        __syncthreads();
+        fft_axis<T, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], -1);
+        xz_store_pruned<T>(it, Tb, b, i1, lds);
+        return;
+    }
+    xz_load_pruned<T>(it, Tb, b, i1, lds);
+    __syncthreads();
+    fft_axis<T, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], +1);
+    if (MODE == XZ_TO_BOX) {
+        TIO* dst = box + (int64_t)b * N + (int64_t)i1 * S2;
+        for (int i = threadIdx.x; i < e; i += blockDim.x) {
+            const int i0 = i / S2, i2 = i - i0 * S2;
+            dst[(int64_t)i0 * S1 * S2 + i2] = store_as<TIO>(lds[i]);
+        }
+        return;
+    }
+    // XZ_H: pointwise (Omega/N) V_eff
+    const double* Vp = V + it.v_off + (int64_t)i1 * S2;
+    const T sc = (T)it.vscale;
+    for (int i = threadIdx.x; i < e; i += blockDim.x) {
+        const int i0 = i / S2, i2 = i - i0 * S2;
+        const T v = (T)Vp[(int64_t)i0 * S1 * S2 + i2] * sc;
+        lds[i] = Cx{lds[i].x * v, lds[i].y * v};
+    }
+    __syncthreads();
+    fft_axis<T, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], -1);
+    xz_store_pruned<T>(it, Tb, b, i1, lds);
+}
+
+// Full-box x pass: plane buffer (all S0 planes) -> transform along x (sign)
+// -> multiply by `scale` -> complex output box.
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
+k_xz_full(FftItem it, const typename cx<T>::t* __restrict__ Tb, int sign, double scale,
+          double2* __restrict__ out, int64_t field_stride) {
+    using Cx = typename cx<T>::t;
+    const int i1 = blockIdx.x, f = blockIdx.y;
+    if (i1 >= it.S1) return;
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int S0 = it.S0, S1 = it.S1, S2 = it.S2;
+    const int e = S0 * S2;
+    const int64_t N = (int64_t)S0 * S1 * S2;
+    const Cx* src = Tb + (int64_t)f * N + (int64_t)i1 * S2;
+    for (int i = threadIdx.x; i < e; i += blockDim.x) {
+        const int i0 = i / S2, i2 = i - i0 * S2;
+        lds[i] = src[(int64_t)i0 * S1 * S2 + i2];
+    }
+    __syncthreads();
+    fft_axis<T, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], sign);
+    double2* dst = out + (int64_t)f * field_stride + (int64_t)i1 * S2;
+    for (int i = threadIdx.x; i < e; i += blockDim.x) {
+        const int i0 = i / S2, i2 = i - i0 * S2;
+        dst[(int64_t)i0 * S1 * S2 + i2] = double2{lds[i].x * scale, lds[i].y * scale};
+    }
+}
+
+// Hartree x pass: forward x transform of the (already y,z transformed) density,
+// multiply by 4 pi / (|G|^2 N^2) (the J normalization 1/N and the I scale N
+// of the way back leave 4 pi / (|G|^2 N)), accumulate the energy partial
+// sum_G 4 pi |n~|^2 / |G|^2 for this i1, transform back along x.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_xz_hartree(FftItem it, double2* __restrict__ Tb, double B00, double B01, double B02, double B10,
+             double B11, double B12, double B20, double B21, double B22,
+             double* __restrict__ epart) {
+    const int i1 = blockIdx.x;
+    if (i1 >= it.S1) return;
+    extern __shared__ char smem_raw[];
+    double2* lds = reinterpret_cast<double2*>(smem_raw);
+    __shared__ double red[NT];
+    const int S0 = it.S0, S1 = it.S1, S2 = it.S2;
+    const int e = S0 * S2;
+    const double N = (double)S0 * S1 * S2;
+    double2* src = Tb + (int64_t)i1 * S2;
+    for (int i = threadIdx.x; i < e; i += blockDim.x) {
+        const int i0 = i / S2, i2 = i - i0 * S2;
+        lds[i] = src[(int64_t)i0 * S1 * S2 + i2];
+    }
+    __syncthreads();
+    fft_axis<double, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], -1);
+    const int n1 = (2 * i1 < S1) ? i1 : i1 - S1;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < e; i += blockDim.x) {
+        const int i0 = i / S2, i2 = i - i0 * S2;
+        const int n0 = (2 * i0 < S0) ? i0 : i0 - S0;
+        const int n2 = (2 * i2 < S2) ? i2 : i2 - S2;
+        const double gx = B00 * n0 + B01 * n1 + B02 * n2;
+        const double gy = B10 * n0 + B11 * n1 + B12 * n2;
+        const double gz = B20 * n0 + B21 * n1 + B22 * n2;
+        const double G2 = gx * gx + gy * gy + gz * gz;
+        double2 v = lds[i];
+        double kern = 0.0;
+        if (G2 > 0.0) kern = 4.0 * M_PI / G2;
+        const double ntr = v.x / N, nti = v.y / N;
+        acc += kern * (ntr * ntr + nti * nti);
+        const double s = kern / N;  // V_H(G) = kern * n~ = kern * X / N; I brings no 1/N
+        lds[i] = double2{v.x * s, v.y * s};
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) epart[i1] = red[0];
+    fft_axis<double, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], +1);
+    for (int i = threadIdx.x; i < e; i += blockDim.x) {
+        const int i0 = i / S2, i2 = i - i0 * S2;
+        src[(int64_t)i0 * S1 * S2 + i2] = lds[i];
+    }
+}
+
+// Density x pass: one workgroup per (item, band chunk, i1) loops over the
+// chunk's bands, transforms each along x and accumulates f_b |psi|^2 in
+// registers; writes the chunk's partial (times w_k) for this i1.
+// accumulators per thread: every x-z tile fits (7680 elements at 512 threads, 8192 at 1024)
+template <int NT>
+struct DensMax {
+    static constexpr int v = NT == 1024 ? 8 : NT == 512 ? 15 : 15;
+};
+constexpr int DENS_CHUNKS = 16;
+template <typename T, int NT, bool BATCH = false>
+__global__ void __launch_bounds__(NT)
+k_xz_density(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb,
+             const double* __restrict__ fill, double wk, int chunk, double* __restrict__ part) {
+    using Cx = typename cx<T>::t;
+    const FftItem& it = DPP_ITEM(items, single);
+    const int i1 = blockIdx.x, c = blockIdx.y;
+    if (i1 >= it.S1) return;
+    const int b0 = c * chunk;
+    if (b0 >= it.nb) return;
+    const int b1 = min(it.nb, b0 + chunk);
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int S0 = it.S0, S1 = it.S1, S2 = it.S2;
+    const int e = S0 * S2;
+    constexpr int DM = DensMax<NT>::v;
+    double acc[DM];
+#pragma unroll
+    for (int u = 0; u < DM; ++u) acc[u] = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const double fb = fill[b];
+        if (fb == 0.0) continue;  // uniform across the workgroup
+        xz_load_pruned<T>(it, Tb, b, i1, lds);
+        __syncthreads();
+        fft_axis<T, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], +1);
+#pragma unroll
+        for (int u = 0; u < DM; ++u) {
+            const int i = threadIdx.x + u * NT;
+            if (i < e) {
+                const double x = (double)lds[i].x, y = (double)lds[i].y;
+                acc[u] += fb * (x * x + y * y);
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t N = (int64_t)S0 * S1 * S2;
+    double* dst = part + (int64_t)c * N + (int64_t)i1 * S2;
+#pragma unroll
+    for (int u = 0; u < DM; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < e) {
+            const int i0 = i / S2, i2 = i - i0 * S2;
+            dst[(int64_t)i0 * S1 * S2 + i2] = wk * acc[u];
+        }
+    }
+}
+
+// Sum the band-chunk partial densities in fixed order and add to n.
+__global__ void k_density_reduce(const double* __restrict__ part, int nchunk, int64_t N,
+                                 double* __restrict__ n) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * N + j];
+    n[j] += s;
+}
+
+// ------------------------------------------------------------- pass 3 ------
+enum GatherMode { G_SET = 0, G_ADD = 1, G_H = 2 };
+
+template <typename T, int MODE, typename TIO, int NT, bool BATCH = false>
+__global__ void __launch_bounds__(NT)
+k_planes_to_sphere(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb,
+                   const double2* __restrict__ Cin, TIO* __restrict__ out, int64_t ldout_override) {
+    using Cx = typename cx<T>::t;
+    const FftItem& it = DPP_ITEM(items, single);
+    const int p = blockIdx.x, b = blockIdx.y;
+    if (p >= it.nplanes || b >= it.nb) return;
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int S1 = it.S1, S2 = it.S2, np = S1 * S2;
+    const Cx* src = Tb + it.t_off + ((int64_t)b * it.nplanes + p) * np;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = src[i];
+    __syncthreads();
+    const int4 pl = it.planes[p];
+    fft_axis<T, true, NT>(lds, it.ax[1], S2, AddrLinear{1, S2}, it.tw64[1], it.tw32[1], -1);
+    fft_axis<T, false, NT>(lds, it.ax[2], pl.w, AddrRowsWrap{S2, pl.z, S1}, it.tw64[2], it.tw32[2], -1);
+    const int64_t ld = ldout_override > 0 ? ldout_override : it.ld;
+    TIO* dst = out + it.c_off + (int64_t)b * ld + pl.x;
+    const int* poff = it.poff + pl.x;
+    if (MODE == G_H) {
+        const double2* cin = Cin + it.c_off + (int64_t)b * it.ld + pl.x;
+        const double* kG2 = it.kG2 + pl.x;
+        const double hk = 0.5 * it.omega;
+        for (int q = threadIdx.x; q < pl.y; q += blockDim.x) {
+            const double2 c = cin[q];
+            const double2 v = Io<T>::to_d(lds[poff[q]]);
+            const double t = hk * kG2[q];
+            dst[q] = store_as<TIO>(double2{t * c.x + v.x, t * c.y + v.y});
+        }
+    } else if (MODE == G_ADD) {
+        for (int q = threadIdx.x; q < pl.y; q += blockDim.x) {
+            const double2 v = Io<T>::to_d(lds[poff[q]]);
+            TIO o = dst[q];
+            dst[q] = store_as<TIO>(double2{(double)o.x + v.x, (double)o.y + v.y});
+        }
+    } else {
+        for (int q = threadIdx.x; q < pl.y; q += blockDim.x)
+            dst[q] = store_as<TIO>(Io<T>::to_d(lds[poff[q]]));
+    }
+}
+
+// Plane buffer (full box) -> 2D transform (sign) -> real part (REAL_OUT) or
+// complex output box, times `scale`.
+template <typename T, bool REAL_OUT, int NT>
+__global__ void __launch_bounds__(NT)
+k_planes_to_box(FftItem it, const typename cx<T>::t* __restrict__ Tb, int sign, double scale,
+                void* __restrict__ out, int64_t field_stride) {
+    using Cx = typename cx<T>::t;
+    const int p = blockIdx.x, f = blockIdx.y;
+    if (p >= it.S0) return;
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int S1 = it.S1, S2 = it.S2, np = S1 * S2;
+    const Cx* src = Tb + (int64_t)f * it.S0 * np + (int64_t)p * np;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = src[i];
+    __syncthreads();
+    fft_axis<T, true, NT>(lds, it.ax[1], S2, AddrLinear{1, S2}, it.tw64[1], it.tw32[1], sign);
+    fft_axis<T, false, NT>(lds, it.ax[2], S1, AddrLinear{S2, 1}, it.tw64[2], it.tw32[2], sign);
+    const int64_t base = (int64_t)f * field_stride + (int64_t)p * np;
+    if (REAL_OUT) {
+        double* dst = reinterpret_cast<double*>(out) + base;
+        for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = (double)lds[i].x * scale;
+    } else {
+        double2* dst = reinterpret_cast<double2*>(out) + base;
+        for (int i = threadIdx.x; i < np; i += blockDim.x)
+            dst[i] = double2{(double)lds[i].x * scale, (double)lds[i].y * scale};
+    }
+}
+
+// ----------------------------------------------------------- launchers -----
+namespace {
+
+struct Launch {
+    int threads;
+    size_t lds;
+};
+
+Launch plane_launch(int S1, int S2, bool fp64) {
+    const int e = S1 * S2;
+    return Launch{fft_threads(e), fft_lds_bytes(e, fp64)};
+}
+Launch xz_launch(int S0, int S2, bool fp64) {
+    const int e = S0 * S2;
+    return Launch{fft_threads(e), fft_lds_bytes(e, fp64)};
+}
+
+template <typename K>
+dpp_status set_lds(K kernel, size_t bytes) {
+    if (bytes > 64 * 1024)
+        DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return DPP_OK;
+}
+
+// Run the statement list with NT_ bound to the workgroup size as a constant.
+#define DPP_NT_DISPATCH(nt, ...)                                                         \
+    switch (nt) {                                                                       \
+        case 256: {                                                                     \
+            constexpr int NT_ = 256;                                                    \
+            __VA_ARGS__;                                                                \
+            break;                                                                      \
+        }                                                                               \
+        case 512: {                                                                     \
+            constexpr int NT_ = 512;                                                    \
+            __VA_ARGS__;                                                                \
+            break;                                                                      \
+        }                                                                               \
+        case 1024: {                                                                    \
+            constexpr int NT_ = 1024;                                                   \
+            __VA_ARGS__;                                                                \
+            break;                                                                      \
+        }                                                                               \
+        default:                                                                        \
+            return set_error(DPP_EUNSUPPORTED, "FFT tile too large for one workgroup"); \
+    }
+
+FftItem item_for(const dpp_basis_s* b, int nb, int64_t ld) {
+    FftItem it = b->h_item;
+    it.nb = nb;
+    it.ld = ld;
+    it.c_off = 0;
+    it.t_off = 0;
+    it.v_off = 0;
+    return it;
+}
+
+}  // namespace
+
+// Sphere -> planes (pass 1) for nb bands.
+template <typename T, typename TIO>
+static dpp_status pass1(dpp_ctx_s* cx_, const FftItem& it, const TIO* C, typename cx<T>::t* Tb) {
+    hipStream_t st = cx_->stream;
+    const double pl_ = (double)it.nplanes * it.S1 * it.S2;
+    TimerScope ts_(cx_, DPP_TK_PLANES_IN, (double)it.nb * (sizeof(TIO) * (double)it.npw + sizeof(typename cx<T>::t) * pl_));
+    const bool fp64 = sizeof(T) == 8;
+    Launch L = plane_launch(it.S1, it.S2, fp64);
+    DPP_NT_DISPATCH(L.threads, auto k = k_planes_from_sphere<T, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
+                    hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, C, Tb));
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+template <typename T, int MODE, typename TIO>
+static dpp_status pass2(dpp_ctx_s* cx_, const FftItem& it, typename cx<T>::t* Tb, const double* V,
+                        TIO* box) {
+    hipStream_t st = cx_->stream;
+    const double pl_ = (double)it.nplanes * it.S1 * it.S2, N_ = (double)it.S0 * it.S1 * it.S2;
+    const double cb_ = sizeof(typename cx<T>::t);
+    const double by_ = MODE == XZ_H ? it.nb * 2.0 * cb_ * pl_ + 8.0 * N_ : it.nb * (cb_ * pl_ + sizeof(TIO) * N_);
+    TimerScope ts_(cx_, MODE == XZ_H ? DPP_TK_XZ_H : DPP_TK_XZ_IO, by_);
+    const bool fp64 = sizeof(T) == 8;
+    Launch L = xz_launch(it.S0, it.S2, fp64);
+    DPP_NT_DISPATCH(L.threads, auto k = k_xz<T, MODE, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
+                    hipLaunchKernelGGL(k, dim3(it.S1, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, Tb, V, box));
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+template <typename T, int MODE, typename TIO>
+static dpp_status pass3(dpp_ctx_s* cx_, const FftItem& it, const typename cx<T>::t* Tb,
+                        const double2* Cin, TIO* out) {
+    hipStream_t st = cx_->stream;
+    const double pl_ = (double)it.nplanes * it.S1 * it.S2;
+    TimerScope ts_(cx_, DPP_TK_PLANES_OUT,
+                   (double)it.nb * (sizeof(typename cx<T>::t) * pl_ + sizeof(TIO) * (MODE == G_ADD ? 2.0 : 1.0) * it.npw));
+    const bool fp64 = sizeof(T) == 8;
+    Launch L = plane_launch(it.S1, it.S2, fp64);
+    DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, MODE, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
+                    hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, Tb, Cin,
+                                       out, (int64_t)0));
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+template <typename T>
+dpp_status run_apply_H_local(dpp_ham_s* ham, int nb, const double2* C, int64_t ldC, double2* HC,
+                             int64_t ldHC, void* ws) {
+    dpp_basis_s* b = ham->basis;
+    dpp_ctx_s* cx_ = b->grid->ctx;
+    hipStream_t st = cx_->stream;
+    using Cx = typename cx<T>::t;
+    Cx* Tb = reinterpret_cast<Cx*>(ws);
+    FftItem it = item_for(b, nb, ldC);
+    DPP_TRY((pass1<T, double2>(cx_, it, C, Tb)));
+    DPP_TRY((pass2<T, XZ_H, double2>(cx_, it, Tb, ham->d_Veff, nullptr)));
+    TimerScope ts_(cx_, DPP_TK_PLANES_OUT,
+                   (double)nb * (sizeof(Cx) * (double)it.nplanes * it.S1 * it.S2 + 32.0 * it.npw));
+    FftItem ot = it;
+    // gather writes HC with its own leading dimension; kinetic term reads C with ldC
+    const bool fp64 = sizeof(T) == 8;
+    Launch L = plane_launch(it.S1, it.S2, fp64);
+    DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_>; DPP_TRY(set_lds(k, L.lds));
+                    hipLaunchKernelGGL(k, dim3(ot.nplanes, ot.nb, 1), dim3(NT_), L.lds, st, nullptr, ot, Tb, C, HC,
+                                       ldHC));
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+template dpp_status run_apply_H_local<double>(dpp_ham_s*, int, const double2*, int64_t, double2*,
+                                              int64_t, void*);
+template dpp_status run_apply_H_local<float>(dpp_ham_s*, int, const double2*, int64_t, double2*,
+                                             int64_t, void*);
+
+}  // namespace dpp
+
+using namespace dpp;
+
+// ------------------------------------------------------------- C ABI -------
+
+extern "C" dpp_status dpp_workspace_size(dpp_basis basis, int nb, dpp_precision prec, size_t* bytes) {
+    clear_error();
+    DPP_REQUIRE(basis && bytes, "dpp_workspace_size: null argument");
+    DPP_REQUIRE(nb >= 0, "dpp_workspace_size: nb < 0");
+    DPP_REQUIRE(prec == DPP_F64 || prec == DPP_F32, "dpp_workspace_size: bad precision");
+    const size_t el = prec == DPP_F64 ? 16 : 8;
+    const size_t t = ((plane_buffer_elems(basis, std::max(nb, 1)) * el + 255) / 256) * 256;
+    // after the plane buffer: density partials (up to DENS_CHUNKS boxes) or the
+    // projector scratch (Pi = P^dag C and its reduction partials)
+    const size_t dens = (size_t)std::min(std::max(nb, 1), DENS_CHUNKS) * basis->grid->N * sizeof(double);
+    const size_t proj = proj_ws_bytes(basis, std::max(nb, 1));
+    *bytes = t + std::max(dens, proj) + 256;
+    return DPP_OK;
+}
+
+// Grid workspace: [plane buffer: N complex][partial sums: 64 KB][coefficients: N complex]
+size_t dpp::grid_coef_offset(const dpp_grid_s* g) { return (size_t)g->N * 16 + 64 * 1024; }
+
+extern "C" dpp_status dpp_grid_workspace_size(dpp_grid grid, size_t* bytes) {
+    clear_error();
+    DPP_REQUIRE(grid && bytes, "dpp_grid_workspace_size: null argument");
+    *bytes = grid_coef_offset(grid) + (size_t)grid->N * 16 + 256;
+    return DPP_OK;
+}
+
+dpp_status dpp::full_inverse_real(dpp_grid_s* g, const double2* coef, double* out, void* ws) {
+    hipStream_t st = g->ctx->stream;
+    TimerScope ts_(g->ctx, DPP_TK_FULLBOX);
+    const FftItem& it = g->h_item;
+    double2* Tb = reinterpret_cast<double2*>(ws);
+    Launch Lp = plane_launch(it.S1, it.S2, true);
+    Launch Lx = xz_launch(it.S0, it.S2, true);
+    DPP_NT_DISPATCH(Lx.threads, auto kx = k_xz_full<double, NT_>; DPP_TRY(set_lds(kx, Lx.lds));
+                    hipLaunchKernelGGL(kx, dim3(it.S1, 1, 1), dim3(NT_), Lx.lds, st, it, coef, +1, 1.0, Tb,
+                                       (int64_t)0));
+    DPP_LAUNCHED();
+    DPP_NT_DISPATCH(Lp.threads, auto kq = k_planes_to_box<double, true, NT_>; DPP_TRY(set_lds(kq, Lp.lds));
+                    hipLaunchKernelGGL(kq, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, it, (const double2*)Tb, +1,
+                                       1.0, (void*)out, (int64_t)0));
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+template <typename TIO, typename T>
+static dpp_status do_I(dpp_basis b, int nb, const TIO* C, int64_t ldC, TIO* out, void* ws) {
+    dpp_ctx_s* cx_ = b->grid->ctx;
+    using Cx = typename cx<T>::t;
+    Cx* Tb = reinterpret_cast<Cx*>(ws);
+    FftItem it = item_for(b, nb, ldC);
+    DPP_TRY((pass1<T, TIO>(cx_, it, C, Tb)));
+    DPP_TRY((pass2<T, XZ_TO_BOX, TIO>(cx_, it, Tb, nullptr, out)));
+    return DPP_OK;
+}
+
+template <typename TIO, typename T>
+static dpp_status do_Idag(dpp_basis b, int nb, const TIO* grid, TIO* C, int64_t ldC, int acc,
+                          void* ws) {
+    dpp_ctx_s* cx_ = b->grid->ctx;
+    using Cx = typename cx<T>::t;
+    Cx* Tb = reinterpret_cast<Cx*>(ws);
+    FftItem it = item_for(b, nb, ldC);
+    DPP_TRY((pass2<T, XZ_FROM_BOX, TIO>(cx_, it, Tb, nullptr, const_cast<TIO*>(grid))));
+    if (acc)
+        DPP_TRY((pass3<T, G_ADD, TIO>(cx_, it, Tb, nullptr, C)));
+    else
+        DPP_TRY((pass3<T, G_SET, TIO>(cx_, it, Tb, nullptr, C)));
+    return DPP_OK;
+}
+
+static dpp_status check_block(dpp_basis b, int nb, const void* p, int64_t ld, const char* who) {
+    DPP_REQUIRE(b, std::string(who) + ": null basis");
+    DPP_REQUIRE(nb >= 0, std::string(who) + ": nb < 0");
+    DPP_REQUIRE(nb == 0 || p, std::string(who) + ": null block");
+    DPP_REQUIRE(ld >= b->npw, std::string(who) + ": leading dimension < npw");
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_I(dpp_basis basis, int nb, const void* C, int64_t ldC, void* grid_out,
+                            dpp_precision prec, void* ws) {
+    clear_error();
+    DPP_TRY(check_block(basis, nb, C, ldC, "dpp_I"));
+    DPP_REQUIRE(nb == 0 || (grid_out && ws), "dpp_I: null output or workspace");
+    DPP_REQUIRE(prec == DPP_F64 || prec == DPP_F32, "dpp_I: bad precision");
+    if (nb == 0) return DPP_OK;
+    if (prec == DPP_F64)
+        return do_I<double2, double>(basis, nb, (const double2*)C, ldC, (double2*)grid_out, ws);
+    return do_I<float2, float>(basis, nb, (const float2*)C, ldC, (float2*)grid_out, ws);
+}
+
+extern "C" dpp_status dpp_Idag(dpp_basis basis, int nb, const void* grid, void* C_out, int64_t ldC,
+                               int accumulate, dpp_precision prec, void* ws) {
+    clear_error();
+    DPP_TRY(check_block(basis, nb, C_out, ldC, "dpp_Idag"));
+    DPP_REQUIRE(nb == 0 || (grid && ws), "dpp_Idag: null input or workspace");
+    DPP_REQUIRE(prec == DPP_F64 || prec == DPP_F32, "dpp_Idag: bad precision");
+    if (nb == 0) return DPP_OK;
+    if (prec == DPP_F64)
+        return do_Idag<double2, double>(basis, nb, (const double2*)grid, (double2*)C_out, ldC,
+                                        accumulate, ws);
+    return do_Idag<float2, float>(basis, nb, (const float2*)grid, (float2*)C_out, ldC, accumulate, ws);
+}
+
+// Full-box complex transform: y = scale * FFT_sign(x).
+static dpp_status full_transform(dpp_grid g, int nf, const double2* x, double2* y, int sign,
+                                 double scale, void* ws) {
+    hipStream_t st = g->ctx->stream;
+    TimerScope ts_(g->ctx, DPP_TK_FULLBOX);
+    const FftItem& it = g->h_item;
+    double2* Tb = reinterpret_cast<double2*>(ws);
+    Launch Lp = plane_launch(it.S1, it.S2, true);
+    Launch Lx = xz_launch(it.S0, it.S2, true);
+    for (int f = 0; f < nf; ++f) {
+        DPP_NT_DISPATCH(Lp.threads, auto kp = k_planes_from_box<double, false, NT_>; DPP_TRY(set_lds(kp, Lp.lds));
+                        hipLaunchKernelGGL(kp, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, it,
+                                           (const void*)(x + (int64_t)f * g->N), (int64_t)0, sign, Tb));
+        DPP_LAUNCHED();
+        DPP_NT_DISPATCH(Lx.threads, auto kx = k_xz_full<double, NT_>; DPP_TRY(set_lds(kx, Lx.lds));
+                        hipLaunchKernelGGL(kx, dim3(it.S1, 1, 1), dim3(NT_), Lx.lds, st, it, Tb, sign, scale,
+                                           y + (int64_t)f * g->N, (int64_t)0));
+        DPP_LAUNCHED();
+    }
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_J(dpp_grid grid, int nf, const dpp_c64* x, dpp_c64* y, void* ws) {
+    clear_error();
+    DPP_REQUIRE(grid && nf >= 0, "dpp_J: bad arguments");
+    DPP_REQUIRE(nf == 0 || (x && y && ws), "dpp_J: null pointer");
+    return full_transform(grid, nf, (const double2*)x, (double2*)y, -1, 1.0 / (double)grid->N, ws);
+}
+
+extern "C" dpp_status dpp_Jdag(dpp_grid grid, int nf, const dpp_c64* x, dpp_c64* y, void* ws) {
+    clear_error();
+    DPP_REQUIRE(grid && nf >= 0, "dpp_Jdag: bad arguments");
+    DPP_REQUIRE(nf == 0 || (x && y && ws), "dpp_Jdag: null pointer");
+    return full_transform(grid, nf, (const double2*)x, (double2*)y, +1, 1.0 / (double)grid->N, ws);
+}
+
+// Reduce per-i1 partial sums in fixed order: out = scale * sum.
+__global__ void k_sum_partials(const double* __restrict__ part, int n, double scale,
+                               double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    // fixed assignment: thread t sums t, t+256, ... in order
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = scale * red[0];
+}
+
+extern "C" dpp_status dpp_hartree(dpp_grid grid, const double* d_n, double* d_VH, double* d_EH,
+                                  void* ws) {
+    clear_error();
+    DPP_REQUIRE(grid && d_n && d_VH && d_EH && ws, "dpp_hartree: null argument");
+    hipStream_t st = grid->ctx->stream;
+    TimerScope ts_(grid->ctx, DPP_TK_FULLBOX);
+    const FftItem& it = grid->h_item;
+    double2* Tb = reinterpret_cast<double2*>(ws);
+    double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + (size_t)grid->N * 16);
+    Launch Lp = plane_launch(it.S1, it.S2, true);
+    Launch Lx = xz_launch(it.S0, it.S2, true);
+    DPP_NT_DISPATCH(Lp.threads, auto kp = k_planes_from_box<double, true, NT_>; DPP_TRY(set_lds(kp, Lp.lds));
+                    hipLaunchKernelGGL(kp, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, it, (const void*)d_n,
+                                       (int64_t)0, -1, Tb));
+    DPP_LAUNCHED();
+    const double* B = grid->B;
+    DPP_NT_DISPATCH(Lx.threads, auto kx = k_xz_hartree<NT_>; DPP_TRY(set_lds(kx, Lx.lds));
+                    hipLaunchKernelGGL(kx, dim3(it.S1, 1, 1), dim3(NT_), Lx.lds, st, it, Tb, B[0], B[1], B[2],
+                                       B[3], B[4], B[5], B[6], B[7], B[8], part));
+    DPP_LAUNCHED();
+    DPP_NT_DISPATCH(Lp.threads, auto kq = k_planes_to_box<double, true, NT_>; DPP_TRY(set_lds(kq, Lp.lds));
+                    hipLaunchKernelGGL(kq, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, it, (const double2*)Tb, +1,
+                                       1.0, (void*)d_VH, (int64_t)0));
+    DPP_LAUNCHED();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, part, it.S1, 0.5 * grid->omega, d_EH);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_density_accumulate(dpp_basis basis, int nb, const dpp_c64* psi,
+                                             int64_t ldpsi, const double* d_f, double wk,
+                                             double* d_n, dpp_precision prec, void* ws) {
+    clear_error();
+    DPP_TRY(check_block(basis, nb, psi, ldpsi, "dpp_density_accumulate"));
+    DPP_REQUIRE(nb == 0 || (d_f && d_n && ws), "dpp_density_accumulate: null argument");
+    DPP_REQUIRE(prec == DPP_F64 || prec == DPP_F32, "dpp_density_accumulate: bad precision");
+    if (nb == 0) return DPP_OK;
+    hipStream_t st = basis->grid->ctx->stream;
+    FftItem it = item_for(basis, nb, ldpsi);
+    const int64_t N = basis->grid->N;
+    const int nchunk = std::min(nb, DENS_CHUNKS);
+    const int chunk = (nb + nchunk - 1) / nchunk;
+    const int nch = (nb + chunk - 1) / chunk;
+    const bool fp64 = prec == DPP_F64;
+    // partials live after the plane buffer
+    const size_t tbytes = plane_buffer_elems(basis, nb) * (fp64 ? 16 : 8);
+    double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + ((tbytes + 255) / 256) * 256);
+    Launch Lx = xz_launch(it.S0, it.S2, fp64);
+    dpp_ctx_s* cx_ = basis->grid->ctx;
+    if (fp64) {
+        DPP_TRY((pass1<double, double2>(cx_, it, (const double2*)psi, (double2*)ws)));
+        TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, nb * 16.0 * it.nplanes * it.S1 * it.S2 + nch * 8.0 * N);
+        DPP_NT_DISPATCH(Lx.threads, auto k = k_xz_density<double, NT_>; DPP_TRY(set_lds(k, Lx.lds));
+                        hipLaunchKernelGGL(k, dim3(it.S1, nch, 1), dim3(NT_), Lx.lds, st, nullptr, it,
+                                           (const double2*)ws, d_f, wk, chunk, part));
+    } else {
+        DPP_TRY((pass1<float, double2>(cx_, it, (const double2*)psi, (float2*)ws)));
+        TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, nb * 8.0 * it.nplanes * it.S1 * it.S2 + nch * 8.0 * N);
+        DPP_NT_DISPATCH(Lx.threads, auto k = k_xz_density<float, NT_>; DPP_TRY(set_lds(k, Lx.lds));
+                        hipLaunchKernelGGL(k, dim3(it.S1, nch, 1), dim3(NT_), Lx.lds, st, nullptr, it,
+                                           (const float2*)ws, d_f, wk, chunk, part));
+    }
+    DPP_LAUNCHED();
+    hipLaunchKernelGGL(k_density_reduce, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, part, nch,
+                       N, d_n);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}

@@ -1,0 +1,176 @@
+// Internal declarations of libdftpp (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dftpp.h"
+
+namespace dpp {
+
+// ------------------------------------------------------------ errors -------
+dpp_status set_error(dpp_status st, const std::string& msg);
+void clear_error();
+
+#define DPP_REQUIRE(cond, msg)                                    \
+    do {                                                          \
+        if (!(cond)) return ::dpp::set_error(DPP_EINVAL, (msg));  \
+    } while (0)
+
+#define DPP_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return ::dpp::set_error(DPP_EDEVICE, std::string(#call ": ") +         \
+                                                     hipGetErrorString(e_));       \
+    } while (0)
+
+#define DPP_TRY(call)                        \
+    do {                                     \
+        dpp_status s_ = (call);              \
+        if (s_ != DPP_OK) return s_;         \
+    } while (0)
+
+// Check the launch that was just enqueued.
+#define DPP_LAUNCHED() DPP_HIP(hipGetLastError())
+
+// ------------------------------------------------------------ FFT plan -----
+constexpr int MAX_RADICES = 8;
+
+struct FftAxis {
+    int n;
+    int nrad;
+    int rad[MAX_RADICES];  // radices in {2,3,4,5}, product n
+};
+
+// Per-(basis or full box) descriptor consumed by the FFT pass kernels.  Lives
+// in device memory (one array entry per work item).
+struct FftItem {
+    int S0, S1, S2;
+    int nplanes;       // x-planes carrying data (sphere: 2*n0max+1; full box: S0)
+    int n0min;         // plane p holds Miller index n0 = n0min + p (i0 = n0 mod S0)
+    int npw;
+    int nb;            // bands of this item
+    int full;          // 1: full-box planes (no sphere tables)
+    FftAxis ax[3];
+    const double2* tw64[3];
+    const float2* tw32[3];
+    const int4* planes;   // per plane: {sphere start, count, n1 of first row, nrows}
+    const int* poff;      // per sphere point: i1*S2 + i2
+    const double* kG2;    // per sphere point |k+G|^2
+    int64_t c_off;        // offset (complex elements) of this item's block
+    int64_t ld;           // leading dimension of the block
+    int64_t t_off;        // offset (complex elements) of this item's plane buffer
+    int64_t v_off;        // offset (doubles) of this item's cell field (V_eff, n)
+    double omega;
+    double vscale;        // Omega / N
+};
+
+// ------------------------------------------------------------ handles ------
+}  // namespace dpp
+
+// Per-context kernel timer: when enabled, launches of the instrumented kernel
+// classes are bracketed by HIP events on the context stream; durations are
+// summed when the pool fills or when the totals are read (both synchronize).
+struct KernelTimer {
+    bool on = false;
+    int cap = 0, used = 0;
+    std::vector<hipEvent_t> ev;   // 2 * cap
+    std::vector<int> kind;        // cap
+    double total_ms[32] = {};
+    int64_t count[32] = {};
+    double bytes[32] = {};        // algorithmic bytes of the timed launches
+    double flops[32] = {};        // algorithmic flops of the timed launches
+};
+
+struct dpp_ctx_s {
+    int device;
+    hipStream_t stream;
+    int* d_status;
+    KernelTimer timer;
+};
+
+namespace dpp {
+// Scope that times the launches enqueued during its lifetime as one `kind`.
+// `bytes` / `flops` are the algorithmic HBM bytes and flops of the scope's
+// launches (what the operation must move and compute, not what it does move).
+struct TimerScope {
+    dpp_ctx_s* c;
+    int slot;
+    TimerScope(dpp_ctx_s* ctx, int kind, double bytes = 0.0, double flops = 0.0);
+    ~TimerScope();
+};
+}  // namespace dpp
+
+struct dpp_grid_s {
+    dpp_ctx ctx;
+    double R[9];   // row-major, columns are lattice vectors
+    double B[9];   // reciprocal basis, columns b_i, row-major
+    double omega;
+    int S[3];
+    int64_t N;
+    dpp::FftAxis ax[3];
+    double2* d_tw64[3];
+    float2* d_tw32[3];
+    int4* d_fullplanes;      // plane table for full-box transforms
+    dpp::FftItem* d_item;    // full-box FFT item (nb = 1)
+    dpp::FftItem h_item;
+};
+
+struct dpp_basis_s {
+    dpp_grid grid;
+    double k[3];
+    double ecut;
+    int64_t npw;
+    int next[6];
+    int nplanes, n0min;
+    int32_t* d_index;
+    int32_t* d_poff;
+    int4* d_miller;      // n0, n1, n2, unused
+    double* d_kG2;
+    int4* d_planes;
+    std::vector<int4> h_planes;
+    dpp::FftItem h_item;     // static part (c_off = t_off = v_off = 0, nb = 0)
+};
+
+struct dpp_ham_s {
+    dpp_basis basis;
+    int nproj;
+    double D;
+    double2* d_P;          // nproj x npw, band-major (projector a at d_P + a*npw)
+    const double* d_Veff;
+};
+
+namespace dpp {
+
+// FFT geometry helpers (fft.hip)
+bool factor_axis(int n, FftAxis* ax);
+int fft_threads(int elems);            // 0 if the plane is too large
+size_t fft_lds_bytes(int elems, bool fp64);
+dpp_status check_fft_shape(int S0, int S1, int S2, bool fp64);
+size_t plane_buffer_elems(const dpp_basis_s* b, int nb);   // complex elements of T for nb bands
+
+// Full-box inverse transform of reciprocal coefficients (unnormalized,
+// e^{+iG.r}) keeping the real part; coef may live in the grid workspace at
+// grid_coef_offset (fft.hip).
+dpp_status full_inverse_real(dpp_grid_s* g, const double2* coef, double* out, void* ws);
+size_t grid_coef_offset(const dpp_grid_s* g);
+
+// Launch the local-potential H pipeline etc. (fft.hip)
+template <typename T>
+dpp_status run_apply_H_local(dpp_ham_s* ham, int nb, const double2* C, int64_t ldC, double2* HC,
+                             int64_t ldHC, void* ws);
+
+// blas.hip
+dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
+                       const double2* B, int64_t ldB, double scale, double2* U, void* ws,
+                       size_t ws_bytes);
+size_t overlap_ws_bytes(int npw, int nbA, int nbB);
+size_t proj_ws_bytes(const dpp_basis_s* b, int nb);
+dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
+                      const double2* M, double beta, double2* out, int64_t ldout);
+
+}  // namespace dpp
