@@ -278,6 +278,8 @@ dpp_status dpp_system_destroy(dpp_system sys);
 dpp_status dpp_system_layout(dpp_system sys, int64_t *offsets, int64_t *npw);
 /* Device pointer of an internal real-space field (DPP_FIELD_*), N doubles. */
 dpp_status dpp_system_field(dpp_system sys, int which, double **d_ptr);
+/* Copy that field into a caller device array of N doubles (stream-ordered). */
+dpp_status dpp_system_copy_field(dpp_system sys, int which, double *d_out);
 
 /* Variational minimization of E_el (Sec. 2.2) over the first nocc bands of
  * every k-point with filling f, CG with one step length for all k.  init

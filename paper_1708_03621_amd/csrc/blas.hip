@@ -27,27 +27,27 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // One wave accumulates one 16x16 tile of U over a K range; a workgroup of
 // OV_WAVES waves covers consecutive K sub-ranges of the same tile and sums
 // them in LDS in fixed order; the partial of each workgroup (chunk) is
-// written out and reduced by k_overlap_reduce in fixed order.
-constexpr int OV_WAVES = 4;
-constexpr int OV_CHUNK = 512;  // K (sphere points) per workgroup
+// written out and reduced by k_overlap_reduce in fixed order.  A launch runs
+// one task (kernel argument) or a table of tasks (blockIdx.z).
 
 __global__ void __launch_bounds__(64 * OV_WAVES)
-k_overlap_mfma(int npw, int nbA, const double2* __restrict__ A, int64_t ldA, int nbB,
-               const double2* __restrict__ B, int64_t ldB, int tilesB, double2* __restrict__ part) {
+k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part) {
     __shared__ double red[OV_WAVES][2][4][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const OvTask& T = tasks ? tasks[blockIdx.z] : single;
     const int chunk = blockIdx.x;
     const int tile = blockIdx.y;
-    const int ti = tile / tilesB, tj = tile - ti * tilesB;
+    if (chunk >= T.nchunk || tile >= T.ntiles) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ti = tile / T.tilesB, tj = tile - ti * T.tilesB;
     const int r = lane & 15, ks = lane >> 4;
     const int ia = ti * 16 + r, jb = tj * 16 + r;
-    const bool va = ia < nbA, vb = jb < nbB;
-    const double2* Ap = A + (int64_t)(va ? ia : 0) * ldA;
-    const double2* Bp = B + (int64_t)(vb ? jb : 0) * ldB;
+    const bool va = ia < T.nbA, vb = jb < T.nbB;
+    const double2* Ap = T.A + (int64_t)(va ? ia : 0) * T.ldA;
+    const double2* Bp = T.B + (int64_t)(vb ? jb : 0) * T.ldB;
     d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
     const int g0 = chunk * OV_CHUNK;
     const int sub = OV_CHUNK / OV_WAVES;
-    const int ga = g0 + w * sub, ge = min(npw, ga + sub);
+    const int ga = g0 + w * sub, ge = min(T.npw, ga + sub);
     for (int g = ga; g < ge; g += 16) {
         // lane covers points g + 4 ks + s, s = 0..3
 #pragma unroll
@@ -71,7 +71,7 @@ k_overlap_mfma(int npw, int nbA, const double2* __restrict__ A, int64_t ldA, int
     }
     __syncthreads();
     if (w == 0) {
-        double2* dst = part + ((int64_t)chunk * gridDim.y + tile) * 256;
+        double2* dst = part + T.part_off + ((int64_t)chunk * T.ntiles + tile) * 256;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double sr = 0, si = 0;
@@ -85,21 +85,21 @@ k_overlap_mfma(int npw, int nbA, const double2* __restrict__ A, int64_t ldA, int
     }
 }
 
-__global__ void k_overlap_reduce(const double2* __restrict__ part, int nchunk, int ntiles, int tilesB,
-                                 int nbA, int nbB, double scale, double2* __restrict__ U) {
+__global__ void k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part) {
+    const OvTask& T = tasks ? tasks[blockIdx.y] : single;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ntiles * 256) return;
+    if (e >= T.ntiles * 256) return;
     const int tile = e >> 8, ij = e & 255;
-    const int ti = tile / tilesB, tj = tile - ti * tilesB;
+    const int ti = tile / T.tilesB, tj = tile - ti * T.tilesB;
     const int i = ti * 16 + (ij >> 4), j = tj * 16 + (ij & 15);
-    if (i >= nbA || j >= nbB) return;
+    if (i >= T.nbA || j >= T.nbB) return;
     double sr = 0, si = 0;
-    for (int c = 0; c < nchunk; ++c) {
-        const double2 v = part[((int64_t)c * ntiles + tile) * 256 + ij];
+    for (int c = 0; c < T.nchunk; ++c) {
+        const double2 v = part[T.part_off + ((int64_t)c * T.ntiles + tile) * 256 + ij];
         sr += v.x;
         si += v.y;
     }
-    U[(int64_t)i * nbB + j] = double2{scale * sr, scale * si};
+    T.out[(int64_t)i * T.out_ld + j] = double2{T.scale * sr, T.scale * si};
 }
 
 size_t overlap_ws_bytes(int npw, int nbA, int nbB) {
@@ -108,25 +108,69 @@ size_t overlap_ws_bytes(int npw, int nbA, int nbB) {
     return (size_t)nchunk * ntiles * 256 * sizeof(double2) + 256;
 }
 
+OvTask make_ov_task(int npw, int nbA, const double2* A, int64_t ldA, int nbB, const double2* B, int64_t ldB,
+                    double scale, double2* out, int out_ld) {
+    OvTask t;
+    t.A = A;
+    t.B = B;
+    t.out = out;
+    t.ldA = ldA;
+    t.ldB = ldB;
+    t.npw = npw;
+    t.nbA = nbA;
+    t.nbB = nbB;
+    t.out_ld = out_ld;
+    t.scale = scale;
+    t.nchunk = std::max(1, (npw + OV_CHUNK - 1) / OV_CHUNK);
+    t.tilesB = (nbB + 15) / 16;
+    t.ntiles = ((nbA + 15) / 16) * t.tilesB;
+    t.part_off = 0;
+    return t;
+}
+
 dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
                        const double2* B, int64_t ldB, double scale, double2* U, void* ws,
                        size_t ws_bytes) {
-    const int nchunk = std::max(1, (npw + OV_CHUNK - 1) / OV_CHUNK);
-    const int tilesA = (nbA + 15) / 16, tilesB = (nbB + 15) / 16;
-    const int ntiles = tilesA * tilesB;
+    OvTask t = make_ov_task(npw, nbA, A, ldA, nbB, B, ldB, scale, U, nbB);
     if (overlap_ws_bytes(npw, nbA, nbB) > ws_bytes)
         return set_error(DPP_EINVAL, "overlap: workspace too small");
-    if (ntiles > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: too many bands");
+    if (t.ntiles > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: too many bands");
     double2* part = reinterpret_cast<double2*>(ws);
     {
-    TimerScope ts_(ctx, DPP_TK_OVERLAP, 16.0 * npw * (nbA + nbB), 8.0 * npw * nbA * (double)nbB);
-    hipLaunchKernelGGL(k_overlap_mfma, dim3(nchunk, ntiles), dim3(64 * OV_WAVES), 0, ctx->stream, npw, nbA, A,
-                       ldA, nbB, B, ldB, tilesB, part);
-    DPP_LAUNCHED();
+        TimerScope ts_(ctx, DPP_TK_OVERLAP, 16.0 * npw * (nbA + nbB), 8.0 * npw * nbA * (double)nbB);
+        hipLaunchKernelGGL(k_overlap_mfma, dim3(t.nchunk, t.ntiles, 1), dim3(64 * OV_WAVES), 0, ctx->stream,
+                           (const OvTask*)nullptr, t, part);
+        DPP_LAUNCHED();
     }
     TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
-    hipLaunchKernelGGL(k_overlap_reduce, dim3((ntiles * 256 + 255) / 256), dim3(256), 0, ctx->stream, part,
-                       nchunk, ntiles, tilesB, nbA, nbB, scale, U);
+    hipLaunchKernelGGL(k_overlap_reduce, dim3((t.ntiles * 256 + 255) / 256, 1), dim3(256), 0, ctx->stream,
+                       (const OvTask*)nullptr, t, part);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+// Batched: the caller has set part_off of every task (disjoint partial areas)
+// and copied the table to d_tasks.
+dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part) {
+    if (h.empty()) return DPP_OK;
+    int mc = 1, mt = 1;
+    double by = 0, fl = 0;
+    for (const OvTask& t : h) {
+        mc = std::max(mc, t.nchunk);
+        mt = std::max(mt, t.ntiles);
+        by += 16.0 * t.npw * (t.nbA + t.nbB);
+        fl += 8.0 * t.npw * t.nbA * (double)t.nbB;
+    }
+    if (mt > 65535 || h.size() > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: batch too large");
+    {
+        TimerScope ts_(ctx, DPP_TK_OVERLAP, by, fl);
+        hipLaunchKernelGGL(k_overlap_mfma, dim3(mc, mt, (unsigned)h.size()), dim3(64 * OV_WAVES), 0, ctx->stream,
+                           d_tasks, OvTask{}, part);
+        DPP_LAUNCHED();
+    }
+    TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
+    hipLaunchKernelGGL(k_overlap_reduce, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
+                       ctx->stream, d_tasks, OvTask{}, (const double2*)part);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -134,37 +178,35 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
 // ---------------------------------------------------------------- X M ------
 // One wave owns 16 consecutive sphere points and up to RT_JT x 16 output
 // bands; X is read once per wave.
-constexpr int RT_WAVES = 4;
-constexpr int RT_JT = 8;
 
 __global__ void __launch_bounds__(64 * RT_WAVES)
-k_rotate_mfma(int npw, int nbX, const double2* __restrict__ X, int64_t ldX, int nbO,
-              const double2* __restrict__ M, double beta, double2* __restrict__ out, int64_t ldout,
-              int jt0) {
+k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0) {
+    const RotTask& T = tasks ? tasks[blockIdx.y] : single;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int gt = blockIdx.x * RT_WAVES + w;
     const int G0 = gt * 16;
-    if (G0 >= npw) return;
+    if (G0 >= T.npw) return;
+    const int njt = min(RT_JT, (T.nbO + 15) / 16 - jt0);
+    if (njt <= 0) return;
     const int c = lane & 15, ks = lane >> 4;
     const int q = G0 + c;
-    const bool vq = q < npw;
-    const int njt = min(RT_JT, (nbO + 15) / 16 - jt0);
+    const bool vq = q < T.npw;
     d4 dre[RT_JT], dim[RT_JT];
 #pragma unroll
     for (int t = 0; t < RT_JT; ++t) {
         dre[t] = d4{0, 0, 0, 0};
         dim[t] = d4{0, 0, 0, 0};
     }
-    for (int i0 = 0; i0 < nbX; i0 += 4) {
+    for (int i0 = 0; i0 < T.nbX; i0 += 4) {
         const int i = i0 + ks;
         double2 x = double2{0, 0};
-        if (i < nbX && vq) x = X[(int64_t)i * ldX + q];
+        if (i < T.nbX && vq) x = T.X[(int64_t)i * T.ldX + q];
 #pragma unroll
         for (int t = 0; t < RT_JT; ++t) {
             if (t < njt) {
                 const int j = (jt0 + t) * 16 + c;
                 double2 m = double2{0, 0};
-                if (i < nbX && j < nbO) m = M[(int64_t)i * nbO + j];
+                if (i < T.nbX && j < T.nbO) m = T.M[(int64_t)i * T.M_ld + j];
                 dre[t] = mfma(m.x, x.x, dre[t]);
                 dre[t] = mfma(-m.y, x.y, dre[t]);
                 dim[t] = mfma(m.y, x.x, dim[t]);
@@ -179,13 +221,13 @@ k_rotate_mfma(int npw, int nbX, const double2* __restrict__ X, int64_t ldX, int 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int j = (jt0 + t) * 16 + 4 * v + ks;
-                if (j < nbO) {
-                    double2* o = out + (int64_t)j * ldout + q;
+                if (j < T.nbO) {
+                    double2* o = T.out + (int64_t)j * T.ldout + q;
                     double2 r = double2{dre[t][v], dim[t][v]};
-                    if (beta != 0.0) {
+                    if (T.beta != 0.0) {
                         const double2 p = *o;
-                        r.x += beta * p.x;
-                        r.y += beta * p.y;
+                        r.x += T.beta * p.x;
+                        r.y += T.beta * p.y;
                     }
                     *o = r;
                 }
@@ -194,16 +236,56 @@ k_rotate_mfma(int npw, int nbX, const double2* __restrict__ X, int64_t ldX, int 
     }
 }
 
+RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, const double2* M, int M_ld,
+                      double beta, double2* out, int64_t ldout) {
+    RotTask t;
+    t.X = X;
+    t.M = M;
+    t.out = out;
+    t.ldX = ldX;
+    t.ldout = ldout;
+    t.npw = npw;
+    t.nbX = nbX;
+    t.nbO = nbO;
+    t.M_ld = M_ld;
+    t.beta = beta;
+    return t;
+}
+
+static double rot_bytes(const RotTask& t) {
+    return 16.0 * t.npw * (t.nbX + t.nbO * (t.beta != 0.0 ? 2.0 : 1.0)) + 16.0 * t.nbX * t.nbO;
+}
+
 dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
                       const double2* M, double beta, double2* out, int64_t ldout) {
+    RotTask t = make_rot_task(npw, nbX, X, ldX, nbO, M, nbO, beta, out, ldout);
     const int ntile = (npw + 15) / 16;
     const int nblk = (ntile + RT_WAVES - 1) / RT_WAVES;
     const int jtiles = (nbO + 15) / 16;
-    TimerScope ts_(ctx, DPP_TK_ROTATE, 16.0 * npw * (nbX + nbO * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * nbX * nbO,
-                   8.0 * npw * nbX * (double)nbO);
+    TimerScope ts_(ctx, DPP_TK_ROTATE, rot_bytes(t), 8.0 * npw * nbX * (double)nbO);
     for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT) {
-        hipLaunchKernelGGL(k_rotate_mfma, dim3(nblk), dim3(64 * RT_WAVES), 0, ctx->stream, npw, nbX, X, ldX, nbO,
-                           M, beta, out, ldout, jt0);
+        hipLaunchKernelGGL(k_rotate_mfma, dim3(nblk, 1), dim3(64 * RT_WAVES), 0, ctx->stream, (const RotTask*)nullptr,
+                           t, jt0);
+        DPP_LAUNCHED();
+    }
+    return DPP_OK;
+}
+
+dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks) {
+    if (h.empty()) return DPP_OK;
+    int mp = 1, mj = 1;
+    double by = 0, fl = 0;
+    for (const RotTask& t : h) {
+        mp = std::max(mp, t.npw);
+        mj = std::max(mj, (t.nbO + 15) / 16);
+        by += rot_bytes(t);
+        fl += 8.0 * t.npw * t.nbX * (double)t.nbO;
+    }
+    const int nblk = ((mp + 15) / 16 + RT_WAVES - 1) / RT_WAVES;
+    TimerScope ts_(ctx, DPP_TK_ROTATE, by, fl);
+    for (int jt0 = 0; jt0 < mj; jt0 += RT_JT) {
+        hipLaunchKernelGGL(k_rotate_mfma, dim3(nblk, (unsigned)h.size()), dim3(64 * RT_WAVES), 0, ctx->stream,
+                           d_tasks, RotTask{}, jt0);
         DPP_LAUNCHED();
     }
     return DPP_OK;

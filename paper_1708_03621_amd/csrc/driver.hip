@@ -87,6 +87,21 @@ struct dpp_system_s {
     double* h_ring;
     int ring_slot, ring_slots;
     size_t ring_len;
+    // batched launches: FFT item tables (all nb bands; nocc bands for the
+    // total-energy CG), task tables and the overlap partial buffer
+    FftItem* d_items_nb;
+    FftItem* d_items_occ;
+    std::vector<FftItem> h_items_nb, h_items_occ;
+    int items_occ_nb;
+    char* d_tab;            // device task table region (reused in stream order)
+    size_t tab_bytes;
+    char* h_tab;            // pinned staging ring for task tables
+    int tab_slot, tab_slots;
+    double2* ov_part;
+    size_t ov_part_elems;
+    double* dens_part;
+    int dens_nch;
+    void* Tplanes;          // plane buffer of every k-point
 };
 
 namespace {
@@ -111,30 +126,177 @@ unsigned seg_blocks(const dpp_system_s* s, int nb) {
 hipStream_t stream(const dpp_system_s* s) { return s->ctx->stream; }
 
 // ---------------------------------------------------------- batched ops ---
-dpp_status apply_H_all(dpp_system_s* s, int nb, const double2* X, double2* HX) {
-    s->hc_bandk += (int64_t)nb * s->nk;
-    for (int k = 0; k < s->nk; ++k)
-        DPP_TRY(dpp_apply_H(s->hams[k], nb, (const dpp_c64*)(X + s->off[k]), s->npw[k], (dpp_c64*)(HX + s->off[k]),
-                            s->npw[k], s->prec, s->ws));
+dpp_status upload_table(dpp_system_s* s, const void* src, size_t bytes, void** dev) {
+    if (bytes > s->tab_bytes) return set_error(DPP_EUNSUPPORTED, "task table too large");
+    if (s->tab_slot == s->tab_slots) {
+        DPP_HIP(hipStreamSynchronize(stream(s)));
+        s->tab_slot = 0;
+    }
+    char* slot = s->h_tab + (size_t)s->tab_slot * s->tab_bytes;
+    s->tab_slot++;
+    std::memcpy(slot, src, bytes);
+    DPP_HIP(hipMemcpyAsync(s->d_tab, slot, bytes, hipMemcpyHostToDevice, stream(s)));
+    *dev = s->d_tab;
     return DPP_OK;
+}
+
+struct OvJob {
+    int nbA;
+    const double2* A;   // packed block set
+    int nbB;
+    const double2* B;
+    double scale;
+    double2* out;       // nk matrices at stride nb^2
+};
+
+// Several A^dag B contractions over every k-point in one launch.
+dpp_status overlap_jobs(dpp_system_s* s, const std::vector<OvJob>& jobs) {
+    std::vector<OvTask> t;
+    int64_t poff = 0;
+    for (const OvJob& j : jobs)
+        for (int k = 0; k < s->nk; ++k) {
+            OvTask x = make_ov_task((int)s->npw[k], j.nbA, j.A + s->off[k], s->npw[k], j.nbB, j.B + s->off[k],
+                                    s->npw[k], j.scale, j.out + (int64_t)k * s->nb * s->nb, j.nbB);
+            x.part_off = poff;
+            poff += (int64_t)x.nchunk * x.ntiles * 256;
+            t.push_back(x);
+        }
+    if ((size_t)poff > s->ov_part_elems) return set_error(DPP_EUNSUPPORTED, "overlap partial buffer too small");
+    void* d = nullptr;
+    DPP_TRY(upload_table(s, t.data(), t.size() * sizeof(OvTask), &d));
+    return overlap_tasks(s->ctx, t, (const OvTask*)d, s->ov_part);
 }
 
 // out_k (stride nb^2) = scale A_k^dag B_k
 dpp_status overlap_all(dpp_system_s* s, int nbA, const double2* A, int nbB, const double2* B, double scale,
                        double2* out) {
-    for (int k = 0; k < s->nk; ++k)
-        DPP_TRY(overlap_f64(s->ctx, (int)s->npw[k], nbA, A + s->off[k], s->npw[k], nbB, B + s->off[k], s->npw[k], scale,
-                            out + (int64_t)k * s->nb * s->nb, s->ws, s->ws_bytes));
-    return DPP_OK;
+    return overlap_jobs(s, {OvJob{nbA, A, nbB, B, scale, out}});
+}
+
+struct RotJob {
+    int nbX;
+    const double2* X;
+    int nbO;
+    const double2* M;   // nk matrices at stride nb^2 (row length nbO)
+    double beta;
+    double2* out;
+};
+
+dpp_status rotate_jobs(dpp_system_s* s, const std::vector<RotJob>& jobs) {
+    std::vector<RotTask> t;
+    for (const RotJob& j : jobs)
+        for (int k = 0; k < s->nk; ++k)
+            t.push_back(make_rot_task((int)s->npw[k], j.nbX, j.X + s->off[k], s->npw[k], j.nbO,
+                                      j.M + (int64_t)k * s->nb * s->nb, j.nbO, j.beta, j.out + s->off[k], s->npw[k]));
+    void* d = nullptr;
+    DPP_TRY(upload_table(s, t.data(), t.size() * sizeof(RotTask), &d));
+    return rotate_tasks(s->ctx, t, (const RotTask*)d);
 }
 
 // out_k = beta out_k + X_k M_k
 dpp_status rotate_all(dpp_system_s* s, int nbX, const double2* X, int nbO, const double2* M, double beta,
                       double2* out) {
-    for (int k = 0; k < s->nk; ++k)
-        DPP_TRY(rotate_f64(s->ctx, (int)s->npw[k], nbX, X + s->off[k], s->npw[k], nbO, M + (int64_t)k * s->nb * s->nb,
-                           beta, out + s->off[k], s->npw[k]));
+    return rotate_jobs(s, {RotJob{nbX, X, nbO, M, beta, out}});
+}
+
+// FFT item table for `nbands` bands per k-point (planes of all k back to back).
+dpp_status item_table(dpp_system_s* s, int nbands, std::vector<FftItem>& h, FftItem** d) {
+    h.clear();
+    int64_t toff = 0;
+    for (int k = 0; k < s->nk; ++k) {
+        FftItem it = s->bases[k]->h_item;
+        it.nb = nbands;
+        it.ld = s->npw[k];
+        it.c_off = s->off[k];
+        it.t_off = toff;
+        it.v_off = 0;
+        it.wk = s->wk[k];
+        it.f_off = (int64_t)k * s->nb;
+        toff += (int64_t)nbands * it.nplanes * it.S1 * it.S2;
+        h.push_back(it);
+    }
+    if (*d == nullptr) DPP_TRY(dalloc_t(s, d, (size_t)s->nk));
+    DPP_HIP(hipMemcpy(*d, h.data(), h.size() * sizeof(FftItem), hipMemcpyHostToDevice));
     return DPP_OK;
+}
+
+dpp_status items_for(dpp_system_s* s, int nbands, const FftItem** d, const std::vector<FftItem>** h) {
+    if (nbands == s->nb) {
+        *d = s->d_items_nb;
+        *h = &s->h_items_nb;
+        return DPP_OK;
+    }
+    if (s->items_occ_nb != nbands) {
+        DPP_TRY(item_table(s, nbands, s->h_items_occ, &s->d_items_occ));
+        s->items_occ_nb = nbands;
+    }
+    *d = s->d_items_occ;
+    *h = &s->h_items_occ;
+    return DPP_OK;
+}
+
+// HX = H X for nbands bands of every k-point: batched FFT passes at the
+// potential of the first Hamiltonian (shared by all k of the cell), then the
+// projector terms HX += P (D P^dag X) as two batched contractions.
+dpp_status apply_H_all(dpp_system_s* s, int nbands, const double2* X, double2* HX) {
+    s->hc_bandk += (int64_t)nbands * s->nk;
+    const FftItem* d;
+    const std::vector<FftItem>* h;
+    DPP_TRY(items_for(s, nbands, &d, &h));
+    const double* V = s->hams[0]->d_Veff;
+    if (!V) return set_error(DPP_EINVAL, "apply_H: no potential set");
+    if (s->prec == DPP_F64)
+        DPP_TRY(apply_H_local_batched<double>(s->ctx, d, *h, X, HX, V, s->Tplanes));
+    else
+        DPP_TRY(apply_H_local_batched<float>(s->ctx, d, *h, X, HX, V, s->Tplanes));
+    if (s->nproj > 0) {
+        std::vector<OvTask> t;
+        int64_t poff = 0;
+        for (int k = 0; k < s->nk; ++k) {
+            OvTask x = make_ov_task((int)s->npw[k], s->nproj, s->hams[k]->d_P, s->npw[k], nbands, X + s->off[k],
+                                    s->npw[k], s->D, s->Pi + (int64_t)k * s->pi_stride, nbands);
+            x.part_off = poff;
+            poff += (int64_t)x.nchunk * x.ntiles * 256;
+            t.push_back(x);
+        }
+        void* dt = nullptr;
+        DPP_TRY(upload_table(s, t.data(), t.size() * sizeof(OvTask), &dt));
+        DPP_TRY(overlap_tasks(s->ctx, t, (const OvTask*)dt, s->ov_part));
+        std::vector<RotTask> r;
+        for (int k = 0; k < s->nk; ++k)
+            r.push_back(make_rot_task((int)s->npw[k], s->nproj, s->hams[k]->d_P, s->npw[k], nbands,
+                                      s->Pi + (int64_t)k * s->pi_stride, nbands, 1.0, HX + s->off[k], s->npw[k]));
+        DPP_TRY(upload_table(s, r.data(), r.size() * sizeof(RotTask), &dt));
+        DPP_TRY(rotate_tasks(s->ctx, r, (const RotTask*)dt));
+    }
+    return DPP_OK;
+}
+
+// Pi_k = P_k^dag X_k (nproj x nbands, row length nbands) for every k.
+dpp_status proj_overlaps(dpp_system_s* s, int nbands, const double2* X) {
+    std::vector<OvTask> t;
+    int64_t poff = 0;
+    for (int k = 0; k < s->nk; ++k) {
+        OvTask x = make_ov_task((int)s->npw[k], s->nproj, s->hams[k]->d_P, s->npw[k], nbands, X + s->off[k],
+                                s->npw[k], 1.0, s->Pi + (int64_t)k * s->pi_stride, nbands);
+        x.part_off = poff;
+        poff += (int64_t)x.nchunk * x.ntiles * 256;
+        t.push_back(x);
+    }
+    void* dt = nullptr;
+    DPP_TRY(upload_table(s, t.data(), t.size() * sizeof(OvTask), &dt));
+    return overlap_tasks(s->ctx, t, (const OvTask*)dt, s->ov_part);
+}
+
+// n (+)= sum_k w_k sum_i f_ki |I psi_ki|^2 over nbands bands (fillings at d_f, stride nb).
+dpp_status density_all(dpp_system_s* s, int nbands, const double2* psi, double* n, dpp_precision prec) {
+    const FftItem* d;
+    const std::vector<FftItem>* h;
+    DPP_TRY(items_for(s, nbands, &d, &h));
+    const int nch = std::min(nbands, s->dens_nch);
+    if (prec == DPP_F64)
+        return density_batched<double>(s->ctx, d, *h, psi, s->d_f, n, s->Tplanes, s->dens_part, nch);
+    return density_batched<float>(s->ctx, d, *h, psi, s->d_f, n, s->Tplanes, s->dens_part, nch);
 }
 
 dpp_status axpby_all(dpp_system_s* s, int nb, const double* a, const double2* x, const double* b, const double2* y,
@@ -212,9 +374,8 @@ dpp_status chol_inv_all(dpp_system_s* s, int n, const double2* Um, double2* Ri, 
 dpp_status grad_B(dpp_system_s* s, const double2* Y) {
     const int nb = s->nb, nk = s->nk;
     const double om = s->grid->omega;
-    DPP_TRY(overlap_all(s, nb, Y, nb, Y, om, s->U));
+    DPP_TRY(overlap_jobs(s, {OvJob{nb, Y, nb, Y, om, s->U}, OvJob{nb, Y, nb, s->HY, 1.0, s->H0}}));
     DPP_TRY(chol_inv_all(s, nb, s->U, s->Rinv, nk));
-    DPP_TRY(overlap_all(s, nb, Y, nb, s->HY, 1.0, s->H0));
     // Uinv = Rinv Rinv^dag (M1); Q = Uinv H0 Uinv (M2)
     DPP_TRY(smm(s, nb, 0, 1, 1.0, nullptr, s->Rinv, s->Rinv, 0.0, s->M1, nk));
     DPP_TRY(smm(s, nb, 0, 0, 1.0, nullptr, s->M1, s->H0, 0.0, s->Rt, nk));
@@ -250,10 +411,8 @@ dpp_status line_mats_B(dpp_system_s* s, const double2* Y) {
     const int nb = s->nb;
     const double om = s->grid->omega;
     DPP_TRY(apply_H_all(s, nb, s->Dd, s->HD));
-    DPP_TRY(overlap_all(s, nb, Y, nb, s->Dd, om, s->X));
-    DPP_TRY(overlap_all(s, nb, s->Dd, nb, s->Dd, om, s->Q));
-    DPP_TRY(overlap_all(s, nb, Y, nb, s->HD, 1.0, s->H1));
-    DPP_TRY(overlap_all(s, nb, s->Dd, nb, s->HD, 1.0, s->H2));
+    DPP_TRY(overlap_jobs(s, {OvJob{nb, Y, nb, s->Dd, om, s->X}, OvJob{nb, s->Dd, nb, s->Dd, om, s->Q},
+                             OvJob{nb, Y, nb, s->HD, 1.0, s->H1}, OvJob{nb, s->Dd, nb, s->HD, 1.0, s->H2}}));
     return DPP_OK;
 }
 
@@ -417,9 +576,7 @@ dpp_status energy_V(dpp_system_s* s, const double2* Y, Parts& P) {
     DPP_TRY(chol_inv_all(s, nb, s->U, s->Rinv, nk));
     DPP_TRY(rotate_all(s, nb, Y, nb, s->Rinv, 0.0, s->psi));
     DPP_HIP(hipMemsetAsync(s->n, 0, N * sizeof(double), stream(s)));
-    for (int k = 0; k < nk; ++k)
-        DPP_TRY(dpp_density_accumulate(s->bases[k], nb, (const dpp_c64*)(s->psi + s->off[k]), s->npw[k],
-                                       s->d_f + (int64_t)k * s->nb, s->wk[k], s->n, DPP_F64, s->ws));
+    DPP_TRY(density_all(s, nb, s->psi, s->n, DPP_F64));
     // potentials and density terms
     DPP_TRY(dpp_hartree(s->grid, s->n, s->VH, s->d_E + 2, s->gws));
     DPP_TRY(dpp_lda_pz81(s->grid, s->n, s->vxc, s->d_E + 3, s->gws));
@@ -434,9 +591,7 @@ dpp_status energy_V(dpp_system_s* s, const double2* Y, Parts& P) {
     hipLaunchKernelGGL(k_seg_weighted_total, dim3(1), dim3(1), 0, stream(s), s->d_part, nk, s->d_wk, 0.5 * om, s->d_E);
     DPP_LAUNCHED();
     if (s->nproj > 0) {
-        for (int k = 0; k < nk; ++k)
-            DPP_TRY(overlap_f64(s->ctx, (int)s->npw[k], s->nproj, s->hams[k]->d_P, s->npw[k], nb, s->psi + s->off[k],
-                                s->npw[k], 1.0, s->Pi + (int64_t)k * s->pi_stride, s->ws, s->ws_bytes));
+        DPP_TRY(proj_overlaps(s, nb, s->psi));
         hipLaunchKernelGGL(k_nonlocal_energy, dim3(1), dim3(256), 0, stream(s), nk, s->nproj, nb, s->nb, s->Pi,
                            s->pi_stride, s->d_f, s->d_wk, s->D, s->d_E + 1);
         DPP_LAUNCHED();
@@ -715,6 +870,7 @@ extern "C" dpp_status dpp_system_create(dpp_ctx ctx, const dpp_system_desc* d, d
     s->n_inner_steps = 3;
     s->hc_bandk = 0;
     s->h_ring = nullptr;
+    s->h_tab = nullptr;
     s->grid = nullptr;
     s->vnocc = 0;
     auto fail = [&](dpp_status st) {
@@ -790,6 +946,29 @@ extern "C" dpp_status dpp_system_create(dpp_ctx ctx, const dpp_system_desc* d, d
     if ((st = dalloc(s, &s->gws, gwsb)) != DPP_OK) return fail(st);
     if ((st = dalloc(s, &s->eigws, ewsb)) != DPP_OK) return fail(st);
     if ((st = dalloc_t(s, &s->d_seg, (size_t)nk)) != DPP_OK) return fail(st);
+    // batched-launch resources
+    s->d_items_nb = s->d_items_occ = nullptr;
+    s->items_occ_nb = -1;
+    if ((st = item_table(s, nb, s->h_items_nb, &s->d_items_nb)) != DPP_OK) return fail(st);
+    {
+        const size_t tel = batched_plane_elems(s->h_items_nb);
+        if ((st = dalloc(s, &s->Tplanes, tel * sizeof(double2))) != DPP_OK) return fail(st);
+        int maxc = 1;
+        for (int k = 0; k < nk; ++k) maxc = std::max(maxc, (int)((s->npw[k] + OV_CHUNK - 1) / OV_CHUNK));
+        const int tiles = ((std::max(nb, s->nproj) + 15) / 16) * ((nb + 15) / 16);
+        s->ov_part_elems = (size_t)4 * nk * maxc * tiles * 256;
+        if ((st = dalloc_t(s, &s->ov_part, s->ov_part_elems)) != DPP_OK) return fail(st);
+        s->dens_nch = std::min(nb, 16);
+        if ((st = dalloc_t(s, &s->dens_part, (size_t)nk * s->dens_nch * N)) != DPP_OK) return fail(st);
+        s->tab_bytes = 256 * 1024;
+        s->tab_slots = 16;
+        s->tab_slot = 0;
+        if ((st = dalloc(s, (void**)&s->d_tab, s->tab_bytes)) != DPP_OK) return fail(st);
+        if (hipHostMalloc((void**)&s->h_tab, s->tab_slots * s->tab_bytes, hipHostMallocDefault) != hipSuccess) {
+            s->h_tab = nullptr;
+            return fail(set_error(DPP_ENOMEM, "dpp_system_create: pinned table staging allocation failed"));
+        }
+    }
     s->ring_slots = 64;
     s->ring_len = std::max<size_t>(256, (size_t)nk * nb);
     s->ring_slot = 0;
@@ -817,6 +996,7 @@ extern "C" dpp_status dpp_system_destroy(dpp_system s) {
     if (s->ctx) hipStreamSynchronize(s->ctx->stream);
     for (void* p : s->allocs) hipFree(p);
     if (s->h_ring) hipHostFree(s->h_ring);
+    if (s->h_tab) hipHostFree(s->h_tab);
     for (dpp_ham h : s->hams) dpp_ham_destroy(h);
     for (dpp_basis b : s->bases) dpp_basis_destroy(b);
     if (s->grid) dpp_grid_destroy(s->grid);
@@ -845,6 +1025,15 @@ extern "C" dpp_status dpp_system_field(dpp_system s, int which, double** d_ptr) 
         case DPP_FIELD_NOUT: *d_ptr = s->nout; break;
         default: return set_error(DPP_EINVAL, "dpp_system_field: unknown field");
     }
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_system_copy_field(dpp_system s, int which, double* d_out) {
+    clear_error();
+    double* src = nullptr;
+    DPP_TRY(dpp_system_field(s, which, &src));
+    DPP_REQUIRE(d_out, "dpp_system_copy_field: null output");
+    DPP_HIP(hipMemcpyAsync(d_out, src, s->grid->N * sizeof(double), hipMemcpyDeviceToDevice, stream(s)));
     return DPP_OK;
 }
 
@@ -893,12 +1082,10 @@ extern "C" dpp_status dpp_cg_B_step(dpp_system s, dpp_c64* Y, double* Eb) {
 // H~ V = V eps; Y <- psi V, HY <- (H psi) V.
 static dpp_status subspace_rotate(dpp_system_s* s, double2* Y, double* eig_host) {
     const int nb = s->nb, nk = s->nk;
-    DPP_TRY(rotate_all(s, nb, Y, nb, s->Rinv, 0.0, s->psi));
-    DPP_TRY(rotate_all(s, nb, s->HY, nb, s->Rinv, 0.0, s->T1));
+    DPP_TRY(rotate_jobs(s, {RotJob{nb, Y, nb, s->Rinv, 0.0, s->psi}, RotJob{nb, s->HY, nb, s->Rinv, 0.0, s->T1}}));
     DPP_TRY(overlap_all(s, nb, s->psi, nb, s->T1, 1.0, s->H0));
     DPP_TRY(dpp_subspace_eigh(s->ctx, nb, nk, (const dpp_c64*)s->H0, s->d_eig, (dpp_c64*)s->vecs, s->eigws));
-    DPP_TRY(rotate_all(s, nb, s->psi, nb, s->vecs, 0.0, Y));
-    DPP_TRY(rotate_all(s, nb, s->T1, nb, s->vecs, 0.0, s->HY));
+    DPP_TRY(rotate_jobs(s, {RotJob{nb, s->psi, nb, s->vecs, 0.0, Y}, RotJob{nb, s->T1, nb, s->vecs, 0.0, s->HY}}));
     if (eig_host) {
         DPP_HIP(hipMemcpyAsync(eig_host, s->d_eig, (size_t)nk * nb * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
         DPP_HIP(hipStreamSynchronize(stream(s)));
@@ -951,9 +1138,7 @@ extern "C" dpp_status dpp_scf_iteration(dpp_system s, dpp_c64* Yc, dpp_energy* E
     DPP_TRY(upload(s, s->d_f, s->fill));
     // 5. n_out and E_el[psi, n_out]
     DPP_HIP(hipMemsetAsync(s->nout, 0, N * sizeof(double), stream(s)));
-    for (int k = 0; k < nk; ++k)
-        DPP_TRY(dpp_density_accumulate(s->bases[k], nb, (const dpp_c64*)(Y + s->off[k]), s->npw[k],
-                                       s->d_f + (int64_t)k * nb, s->wk[k], s->nout, s->prec, s->ws));
+    DPP_TRY(density_all(s, nb, Y, s->nout, s->prec));
     const double om = s->grid->omega;
     DPP_TRY(dpp_hartree(s->grid, s->nout, s->VH, s->d_E + 2, s->gws));
     DPP_TRY(dpp_lda_pz81(s->grid, s->nout, s->vxc, s->d_E + 3, s->gws));
@@ -964,9 +1149,7 @@ extern "C" dpp_status dpp_scf_iteration(dpp_system s, dpp_c64* Yc, dpp_energy* E
     hipLaunchKernelGGL(k_seg_weighted_total, dim3(1), dim3(1), 0, stream(s), s->d_part, nk, s->d_wk, 0.5 * om, s->d_E);
     DPP_LAUNCHED();
     if (s->nproj > 0) {
-        for (int k = 0; k < nk; ++k)
-            DPP_TRY(overlap_f64(s->ctx, (int)s->npw[k], s->nproj, s->hams[k]->d_P, s->npw[k], nb, Y + s->off[k],
-                                s->npw[k], 1.0, s->Pi + (int64_t)k * s->pi_stride, s->ws, s->ws_bytes));
+        DPP_TRY(proj_overlaps(s, nb, Y));
         hipLaunchKernelGGL(k_nonlocal_energy, dim3(1), dim3(256), 0, stream(s), nk, s->nproj, nb, s->nb, s->Pi,
                            s->pi_stride, s->d_f, s->d_wk, s->D, s->d_E + 1);
         DPP_LAUNCHED();

@@ -340,7 +340,7 @@ constexpr int DENS_CHUNKS = 16;
 template <typename T, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_xz_density(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb,
-             const double* __restrict__ fill, double wk, int chunk, double* __restrict__ part) {
+             const double* __restrict__ fill, int chunk, double* __restrict__ part) {
     using Cx = typename cx<T>::t;
     const FftItem& it = DPP_ITEM(items, single);
     const int i1 = blockIdx.x, c = blockIdx.y;
@@ -357,7 +357,7 @@ k_xz_density(const FftItem* items, FftItem single, const typename cx<T>::t* __re
 #pragma unroll
     for (int u = 0; u < DM; ++u) acc[u] = 0.0;
     for (int b = b0; b < b1; ++b) {
-        const double fb = fill[b];
+        const double fb = fill[it.f_off + b];
         if (fb == 0.0) continue;  // uniform across the workgroup
         xz_load_pruned<T>(it, Tb, b, i1, lds);
         __syncthreads();
@@ -373,13 +373,13 @@ k_xz_density(const FftItem* items, FftItem single, const typename cx<T>::t* __re
         __syncthreads();
     }
     const int64_t N = (int64_t)S0 * S1 * S2;
-    double* dst = part + (int64_t)c * N + (int64_t)i1 * S2;
+    double* dst = part + ((int64_t)blockIdx.z * gridDim.y + c) * N + (int64_t)i1 * S2;
 #pragma unroll
     for (int u = 0; u < DM; ++u) {
         const int i = threadIdx.x + u * NT;
         if (i < e) {
             const int i0 = i / S2, i2 = i - i0 * S2;
-            dst[(int64_t)i0 * S1 * S2 + i2] = wk * acc[u];
+            dst[(int64_t)i0 * S1 * S2 + i2] = it.wk * acc[u];
         }
     }
 }
@@ -600,6 +600,112 @@ template dpp_status run_apply_H_local<double>(dpp_ham_s*, int, const double2*, i
 template dpp_status run_apply_H_local<float>(dpp_ham_s*, int, const double2*, int64_t, double2*,
                                              int64_t, void*);
 
+
+size_t batched_plane_elems(const std::vector<FftItem>& h) {
+    size_t t = 0;
+    for (const FftItem& it : h) t = std::max(t, (size_t)it.t_off + (size_t)it.nb * it.nplanes * it.S1 * it.S2);
+    return t;
+}
+
+// One launch per pass for every item of the table.  All items of a table
+// share the box S (one cell), so workgroup size and LDS match.
+template <typename T>
+dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,
+                                 const double2* X, double2* HX, const double* V, void* Tbv) {
+    using Cx = typename cx<T>::t;
+    Cx* Tb = reinterpret_cast<Cx*>(Tbv);
+    hipStream_t st = cx_->stream;
+    const bool fp64 = sizeof(T) == 8;
+    int maxP = 0, nbm = 0;
+    double b1 = 0, b2 = 0, b3 = 0;
+    for (const FftItem& it : h) {
+        maxP = std::max(maxP, it.nplanes);
+        nbm = std::max(nbm, it.nb);
+        const double pl = (double)it.nplanes * it.S1 * it.S2;
+        b1 += it.nb * (16.0 * it.npw + sizeof(Cx) * pl);
+        b2 += it.nb * 2.0 * sizeof(Cx) * pl + 8.0 * it.S0 * it.S1 * it.S2;
+        b3 += it.nb * (sizeof(Cx) * pl + 32.0 * it.npw);
+    }
+    const FftItem& i0 = h[0];
+    const unsigned nit = (unsigned)h.size();
+    {
+        Launch L = plane_launch(i0.S1, i0.S2, fp64);
+        TimerScope ts_(cx_, DPP_TK_PLANES_IN, b1);
+        DPP_NT_DISPATCH(L.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>; DPP_TRY(set_lds(k, L.lds));
+                        hipLaunchKernelGGL(k, dim3(maxP, nbm, nit), dim3(NT_), L.lds, st, d_items, i0, X, Tb));
+        DPP_LAUNCHED();
+    }
+    {
+        Launch L = xz_launch(i0.S0, i0.S2, fp64);
+        TimerScope ts_(cx_, DPP_TK_XZ_H, b2);
+        DPP_NT_DISPATCH(L.threads, auto k = k_xz<T, XZ_H, double2, NT_, true>; DPP_TRY(set_lds(k, L.lds));
+                        hipLaunchKernelGGL(k, dim3(i0.S1, nbm, nit), dim3(NT_), L.lds, st, d_items, i0, Tb, V,
+                                           (double2*)nullptr));
+        DPP_LAUNCHED();
+    }
+    {
+        Launch L = plane_launch(i0.S1, i0.S2, fp64);
+        TimerScope ts_(cx_, DPP_TK_PLANES_OUT, b3);
+        DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_, true>;
+                        DPP_TRY(set_lds(k, L.lds));
+                        hipLaunchKernelGGL(k, dim3(maxP, nbm, nit), dim3(NT_), L.lds, st, d_items, i0,
+                                           (const Cx*)Tb, X, HX, (int64_t)0));
+        DPP_LAUNCHED();
+    }
+    return DPP_OK;
+}
+template dpp_status apply_H_local_batched<double>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
+                                                  const double2*, double2*, const double*, void*);
+template dpp_status apply_H_local_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
+                                                 const double2*, double2*, const double*, void*);
+
+// n += sum over items of w_k sum_b f_b |I psi_b|^2; partials: nit * nch boxes.
+template <typename T>
+dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,
+                           const double2* psi, const double* fill, double* n, void* Tbv, double* part, int nch) {
+    using Cx = typename cx<T>::t;
+    Cx* Tb = reinterpret_cast<Cx*>(Tbv);
+    hipStream_t st = cx_->stream;
+    const bool fp64 = sizeof(T) == 8;
+    int maxP = 0, nbm = 0;
+    double b1 = 0, b2 = 0;
+    const FftItem& i0 = h[0];
+    const int64_t N = (int64_t)i0.S0 * i0.S1 * i0.S2;
+    for (const FftItem& it : h) {
+        maxP = std::max(maxP, it.nplanes);
+        nbm = std::max(nbm, it.nb);
+        const double pl = (double)it.nplanes * it.S1 * it.S2;
+        b1 += it.nb * (16.0 * it.npw + sizeof(Cx) * pl);
+        b2 += it.nb * sizeof(Cx) * pl + nch * 8.0 * N;
+    }
+    const unsigned nit = (unsigned)h.size();
+    const int chunk = (nbm + nch - 1) / nch;
+    {
+        Launch L = plane_launch(i0.S1, i0.S2, fp64);
+        TimerScope ts_(cx_, DPP_TK_PLANES_IN, b1);
+        DPP_NT_DISPATCH(L.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>; DPP_TRY(set_lds(k, L.lds));
+                        hipLaunchKernelGGL(k, dim3(maxP, nbm, nit), dim3(NT_), L.lds, st, d_items, i0, psi, Tb));
+        DPP_LAUNCHED();
+    }
+    {
+        Launch L = xz_launch(i0.S0, i0.S2, fp64);
+        TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, b2);
+        DPP_NT_DISPATCH(L.threads, auto k = k_xz_density<T, NT_, true>; DPP_TRY(set_lds(k, L.lds));
+                        hipLaunchKernelGGL(k, dim3(i0.S1, nch, nit), dim3(NT_), L.lds, st, d_items, i0,
+                                           (const Cx*)Tb, fill, chunk, part));
+        DPP_LAUNCHED();
+    }
+    TimerScope ts_(cx_, DPP_TK_FIELDS);
+    hipLaunchKernelGGL(k_density_reduce, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, (const double*)part,
+                       (int)(nit * nch), N, n);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+template dpp_status density_batched<double>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&, const double2*,
+                                            const double*, double*, void*, double*, int);
+template dpp_status density_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&, const double2*,
+                                           const double*, double*, void*, double*, int);
+
 }  // namespace dpp
 
 using namespace dpp;
@@ -799,6 +905,8 @@ extern "C" dpp_status dpp_density_accumulate(dpp_basis basis, int nb, const dpp_
     if (nb == 0) return DPP_OK;
     hipStream_t st = basis->grid->ctx->stream;
     FftItem it = item_for(basis, nb, ldpsi);
+    it.wk = wk;
+    it.f_off = 0;
     const int64_t N = basis->grid->N;
     const int nchunk = std::min(nb, DENS_CHUNKS);
     const int chunk = (nb + nchunk - 1) / nchunk;
@@ -814,13 +922,13 @@ extern "C" dpp_status dpp_density_accumulate(dpp_basis basis, int nb, const dpp_
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, nb * 16.0 * it.nplanes * it.S1 * it.S2 + nch * 8.0 * N);
         DPP_NT_DISPATCH(Lx.threads, auto k = k_xz_density<double, NT_>; DPP_TRY(set_lds(k, Lx.lds));
                         hipLaunchKernelGGL(k, dim3(it.S1, nch, 1), dim3(NT_), Lx.lds, st, nullptr, it,
-                                           (const double2*)ws, d_f, wk, chunk, part));
+                                           (const double2*)ws, d_f, chunk, part));
     } else {
         DPP_TRY((pass1<float, double2>(cx_, it, (const double2*)psi, (float2*)ws)));
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, nb * 8.0 * it.nplanes * it.S1 * it.S2 + nch * 8.0 * N);
         DPP_NT_DISPATCH(Lx.threads, auto k = k_xz_density<float, NT_>; DPP_TRY(set_lds(k, Lx.lds));
                         hipLaunchKernelGGL(k, dim3(it.S1, nch, 1), dim3(NT_), Lx.lds, st, nullptr, it,
-                                           (const float2*)ws, d_f, wk, chunk, part));
+                                           (const float2*)ws, d_f, chunk, part));
     }
     DPP_LAUNCHED();
     hipLaunchKernelGGL(k_density_reduce, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, part, nch,

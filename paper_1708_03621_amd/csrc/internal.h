@@ -67,6 +67,8 @@ struct FftItem {
     int64_t v_off;        // offset (doubles) of this item's cell field (V_eff, n)
     double omega;
     double vscale;        // Omega / N
+    double wk;            // k-point weight (density accumulation)
+    int64_t f_off;        // offset of this item's fillings
 };
 
 // ------------------------------------------------------------ handles ------
@@ -159,12 +161,53 @@ size_t plane_buffer_elems(const dpp_basis_s* b, int nb);   // complex elements o
 dpp_status full_inverse_real(dpp_grid_s* g, const double2* coef, double* out, void* ws);
 size_t grid_coef_offset(const dpp_grid_s* g);
 
+// Batched passes over a table of items (one per k-point or cell/k pair);
+// h_items mirrors the device table d_items.  Tb holds every item's planes.
+template <typename T>
+dpp_status apply_H_local_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
+                                 const double2* X, double2* HX, const double* V, void* Tb);
+template <typename T>
+dpp_status density_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
+                           const double2* psi, const double* fill, double* n, void* Tb, double* part, int nch);
+size_t batched_plane_elems(const std::vector<FftItem>& h_items);
+
 // Launch the local-potential H pipeline etc. (fft.hip)
 template <typename T>
 dpp_status run_apply_H_local(dpp_ham_s* ham, int nb, const double2* C, int64_t ldC, double2* HC,
                              int64_t ldHC, void* ws);
 
 // blas.hip
+constexpr int OV_WAVES = 4;
+constexpr int OV_CHUNK = 256;  // sphere points per overlap workgroup
+constexpr int RT_WAVES = 4;
+constexpr int RT_JT = 8;       // 16-band output tiles held by one rotate wave
+
+// out = scale * A^dag B (nbA x nbB, row-major with row length out_ld)
+struct OvTask {
+    const double2* A;
+    const double2* B;
+    double2* out;
+    int64_t ldA, ldB;
+    int npw, nbA, nbB, out_ld;
+    double scale;
+    int64_t part_off;  // complex elements into the partial buffer
+    int nchunk, tilesB, ntiles, pad;
+};
+// out = beta * out + X M (M: nbX x nbO row-major with row length M_ld)
+struct RotTask {
+    const double2* X;
+    const double2* M;
+    double2* out;
+    int64_t ldX, ldout;
+    int npw, nbX, nbO, M_ld;
+    double beta;
+};
+OvTask make_ov_task(int npw, int nbA, const double2* A, int64_t ldA, int nbB, const double2* B, int64_t ldB,
+                    double scale, double2* out, int out_ld);
+RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, const double2* M, int M_ld,
+                      double beta, double2* out, int64_t ldout);
+dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part);
+dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks);
 dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
                        const double2* B, int64_t ldB, double scale, double2* U, void* ws,
                        size_t ws_bytes);

@@ -104,6 +104,7 @@ SIGNATURES = {
     "dpp_system_destroy": [_vp],
     "dpp_system_layout": [_vp, _i64p, _i64p],
     "dpp_system_field": [_vp, _i, C.POINTER(_vp)],
+    "dpp_system_copy_field": [_vp, _i, _vp],
     "dpp_cg_V_init": [_vp, _vp, _i, _d, C.POINTER(dpp_energy)],
     "dpp_cg_V_step": [_vp, _vp, C.POINTER(dpp_energy), _ip],
     "dpp_cg_B_init": [_vp, _vp, _vp, _dp],
@@ -395,6 +396,10 @@ def dpp_system_field(sys_, which):
     p = _vp()
     _call("dpp_system_field", sys_, int(which), C.byref(p))
     return p.value
+
+
+def dpp_system_copy_field(sys_, which, d_out):
+    _call("dpp_system_copy_field", sys_, int(which), _ptr(d_out))
 
 
 def dpp_cg_V_init(sys_, Y, nocc, f):

@@ -43,6 +43,12 @@ class Device:
         self.sync()
         return t.cpu().numpy()
 
+    def field(self, sys_, which, S):
+        """Copy of a system's internal real-space field to host."""
+        t = self.torch.empty(tuple(S), dtype=self.torch.float64, device=self.dev)
+        self.D.dpp_system_copy_field(sys_, which, t)
+        return self.host(t)
+
     def grid(self, R, S):
         return self.D.dpp_grid_create(self.ctx, R, S)
 

@@ -121,3 +121,30 @@ def test_scf_iterations_match_oracle(dev, name):
     assert np.max(np.abs(np.array(Eg) - np.array(res["energies"]))) / cell.nat < TOL_ATOM
     assert np.max(np.abs(eg[-1] - np.array(res["eigs"]))) < 1e-7
     dev.D.dpp_system_destroy(sysg)
+
+
+def test_scf_mixed_precision_config2(dev):
+    """FP32 FFT passes (potential multiply and density in FP32, FP64 accumulation),
+    FP64 contractions, Cholesky, eigensolver and reductions: energies within
+    1e-6 Ha/atom, eigenvalues within 1e-5 Ha, density within 1e-5 relative L1
+    of the FP64 oracle after the same SCF iterations."""
+    log("scf mixed cfg2")
+    cell = W.config2()
+    s = oe.build_system(cell)
+    sysg, off, npw = make_gpu_system(dev, cell, prec=1)
+    Y, blocks = packed_Y(dev, cell, npw)
+    dev.D.dpp_scf_init(sysg, cell.tau, cell.Z, W.START_SIGMA)
+    nk = len(cell.kpts)
+    nit = 4
+    Eg = []
+    for _ in range(nit):
+        E, e = dev.D.dpp_scf_iteration(sysg, Y, nk, cell.nb)
+        Eg.append(E["E_el"])
+    nout = dev.field(sysg, dev.D.DPP_FIELD_NOUT, cell.S)
+    res = oscf.scf(s, [b.T.copy() for b in blocks], oe.start_density(cell, W.START_SIGMA), nit)
+    dE = np.max(np.abs(np.array(Eg) - np.array(res["energies"]))) / cell.nat
+    log(f"mixed dE/atom {dE:.3e}")
+    assert dE < 1e-6
+    assert np.max(np.abs(e - np.array(res["eigs"]))) < 1e-5
+    assert np.sum(np.abs(nout - res["n_out"])) / np.sum(np.abs(res["n_out"])) < 1e-5
+    dev.D.dpp_system_destroy(sysg)
