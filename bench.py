@@ -37,6 +37,14 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
+WORKLOADS = {
+    "config2": "diamond 8-atom cubic cell a=10.26 bohr, Ecut 12 Ha, FFT 40^3, 16 bands, Gamma-centred 2x2x2 k "
+               "(8 k-points), one SCF iteration per step (3 band-CG steps/k)",
+    "config3": "64-atom diamond supercell L=20.52 bohr displaced N(0,0.1^2), Ecut 15 Ha, FFT 90^3, 128 bands, "
+               "Gamma only, one SCF iteration per step (3 band-CG steps)",
+}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -99,6 +107,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--converge", type=int, default=40, help="SCF iterations for the convergence report")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3"],
+                    help="config2 (the metric's workload) or config3 (64 atoms, 90^3, 128 bands) for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built: "
@@ -112,13 +122,15 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     ctx = D.dpp_ctx_create(0, stream.cuda_stream)
-    cell = W.config2()
+    cell = W.config2() if args.workload == "config2" else W.config3()
     nk = len(cell.kpts)
 
     def make(prec):
         sys_ = D.dpp_system_create(ctx, cell.R, cell.S, cell.ecut, cell.kpts, cell.wk, cell.nb, cell.n_electrons,
                                    cell.tau, cell.Z.astype(float), cell.rc, cell.has_proj.astype(int), W.PROJ_RP,
                                    W.PROJ_D, prec)
+        # mixed: FP32 bulk, FP64 refinement once the band residual < 1e-4 Ha
+        D.dpp_set_precision_policy(sys_, prec, 1e-4 if prec == D.DPP_F32 else 0.0)
         off, npw = D.dpp_system_layout(sys_, nk)
         blocks = W.initial_wavefunctions(cell.y0_seed, [(cell.nb, n) for n in npw])
         Y = torch.from_numpy(np.concatenate([b.reshape(-1) for b in blocks])).to(dev)
@@ -140,6 +152,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         c1 = D.dpp_system_counters(sys_)
+        res_end, prec_end, _ = D.dpp_scf_status(sys_)
         ms_step = (t1 - t0) * 1e3 / args.steps
         hc_rate = (c1 - c0) / (t1 - t0)
         # same steps again with the kernel timer on (HIP events on the library stream)
@@ -179,7 +192,10 @@ def main():
         Ef = hist[-1]
         it_conv = next((i + 1 for i in range(len(hist)) if all(abs(h - Ef) / cell.nat < 1e-6 for h in hist[i:])),
                        None)
+        _, prec_conv, _ = D.dpp_scf_status(sys_)
         results[name] = dict(ms_per_step=ms_step, hc_rate=hc_rate, hc_only=hc_only, kernels=kern,
+                             timed_prec_end=("f32" if prec_end == 1 else "f64"), residual_after_timed=res_end,
+                             converged_prec=("f32" if prec_conv == 1 else "f64"),
                              E_final=Ef, iters_to_1e6=it_conv, E_last_step=E["E_el"])
         D.dpp_system_destroy(sys_)
 
@@ -208,23 +224,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "diamond 8-atom cubic cell a=10.26 bohr, Ecut 12 Ha, FFT 40^3, 16 bands, "
-                               "Gamma-centred 2x2x2 k (8 k-points), one SCF iteration per step (3 band-CG steps/k)",
-                   "parallelism": "single GPU"},
+        "config": {"workload": WORKLOADS[args.workload], "parallelism": "single GPU"},
         "s_per_scf_iter": {k: v["ms_per_step"] * 1e-3 for k, v in results.items()},
         "hc_in_scf_bands_k_per_s": {k: v["hc_rate"] for k, v in results.items()},
         "hc_only_bands_k_per_s": {k: v["hc_only"] for k, v in results.items()},
         "speedup_mixed_vs_f64": results["f64"]["ms_per_step"] / results["mixed"]["ms_per_step"],
-        "scf_convergence": {k: {"iters_to_1e-6_Ha_per_atom": v["iters_to_1e6"], "E_el": v["E_final"]}
-                            for k, v in results.items()},
-        "mixed_note": "mixed = FFT passes, potential multiply and density in FP32; contractions, Cholesky, "
-                      "eigensolver and reductions in FP64",
+        "scf_convergence": {k: {"iters_to_1e-6_Ha_per_atom": v["iters_to_1e6"], "E_el": v["E_final"],
+                                "precision_at_end": v["converged_prec"]} for k, v in results.items()},
+        "timed_region_precision": {k: {"after_last_step": v["timed_prec_end"],
+                                       "band_residual": v["residual_after_timed"]} for k, v in results.items()},
+        "mixed_note": "mixed = FFT passes, potential multiply and density in FP32 until the band residual "
+                      "falls below 1e-4 Ha, FP64 after; contractions, Cholesky, eigensolver and reductions in FP64",
         "roofline": roof,
         "kernels": {k: {"avg_us": v["avg_us"], "launches": v["launches"], "ms_total": v["ms_total"],
                         "GBps": (v["alg_bytes"] / (v["ms_total"] * 1e-3) / 1e9) if v["alg_bytes"] else None}
                     for k, v in kern.items()},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "config2":
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -70,6 +70,7 @@ typedef struct dpp_grid_s *dpp_grid;
 typedef struct dpp_basis_s *dpp_basis;
 typedef struct dpp_ham_s *dpp_ham;
 typedef struct dpp_system_s *dpp_system;
+typedef struct dpp_net_s *dpp_net;
 
 /* Text of the last error reported to the calling thread ("" if none). */
 const char *dpp_last_error(void);
@@ -90,7 +91,8 @@ enum {
     DPP_TK_FULLBOX = 8,      /* full-box transforms (Hartree, J, potentials)      */
     DPP_TK_FIELDS = 9,       /* LDA, grid reductions, density reduction           */
     DPP_TK_BLOCKOPS = 10,    /* packed-block elementwise, dots, small matrices    */
-    DPP_TK_XZ_IO = 11        /* x transforms of I and I^dag to/from full boxes    */
+    DPP_TK_XZ_IO = 11,       /* x transforms of I and I^dag to/from full boxes    */
+    DPP_TK_NET = 12          /* learned-density network forward/backward          */
 };
 /* Enable (on = 1) or disable the per-context kernel timer: each launch of
  * an instrumented class is bracketed by HIP events on the context stream.
@@ -267,6 +269,7 @@ typedef struct {
     double sigma;           /* Gaussian width                              */
     const double *d_n_start;/* device start density (overrides the atoms)  */
     int n_inner;            /* band-CG steps per SCF iteration (0 -> 3)    */
+    int n_inner_first;      /* steps of the first iteration (0 -> n_inner) */
 } dpp_scf_desc;
 
 enum { DPP_FIELD_VLOC = 0, DPP_FIELD_VEFF = 1, DPP_FIELD_N = 2, DPP_FIELD_NIN = 3, DPP_FIELD_NOUT = 4 };
@@ -312,8 +315,53 @@ dpp_status dpp_system_counters(dpp_system sys, int64_t *hc_bandk);
 /* HY = H Y on all nb bands of every k-point (packed layout, at the
  * potential last set: V_eff of the last SCF iteration or dpp_cg_B_init). */
 dpp_status dpp_system_apply_H(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY);
+/* Precision policy (form 1): FFT passes, potential multiply and density in
+ * `bulk` (DPP_F32 or DPP_F64) until the largest band residual
+ * max_i ||(H - eps_i O) psi_i||_2 / sqrt(Omega) of an SCF iteration falls
+ * below refine_residual (> 0), then FP64 for the rest of that SCF run
+ * (dpp_scf_init returns to bulk).  Contractions, Cholesky, eigensolver,
+ * energies, Hartree and LDA are FP64 throughout. */
+dpp_status dpp_set_precision_policy(dpp_system sys, int bulk, double refine_residual);
+/* Residual of the last SCF iteration, the precision of the next one and the
+ * iteration count since dpp_scf_init (host outputs, any may be NULL). */
+dpp_status dpp_scf_status(dpp_system sys, double *residual, int *prec_now, int *iterations);
 /* Fillings of the last SCF iteration (host, nk x nb). */
 dpp_status dpp_system_fillings(dpp_system sys, double *f);
+
+/* ------------------------------------------------ learned start density -- */
+
+/* A periodic 3D convolutional network that corrects the superposition start
+ * density (form 4): x = n0/nbar, three 3x3x3 conv + SiLU layers of 16
+ * channels and a linear 3x3x3 output layer (1-16-16-16-1, circular
+ * padding, 14737 parameters); dn = nbar (y - mean y); n = max(n0 + dn, 0)
+ * rescaled to N_e.  Weights BF16 (from FP32 master copies), FP32
+ * activations and accumulation, FP64 loss and density reductions.
+ * Parameter order (host float arrays): W1 (16x1x3x3x3), b1, W2, b2, W3, b3,
+ * W4 (1x16x3x3x3), b4, each row-major.  max_batch bounds every batch. */
+dpp_status dpp_net_create(dpp_ctx ctx, const int *S, int max_batch, dpp_net *out);
+dpp_status dpp_net_destroy(dpp_net net);
+dpp_status dpp_net_num_params(dpp_net net, int *count);
+/* Set FP32 master parameters (resets Adam); get parameters and the
+ * gradients of the last backward pass (host arrays, either may be NULL). */
+dpp_status dpp_net_set_params(dpp_net net, const float *h_params);
+dpp_status dpp_net_get_params(dpp_net net, float *h_params, float *h_grads);
+/* Forward pass of `batch` start densities (device, batch x N doubles, back
+ * to back); y (device, batch x N floats, may be NULL) receives the raw output. */
+dpp_status dpp_net_forward(dpp_net net, int batch, const double *d_n0, double nbar, float *d_y);
+/* After dpp_net_forward on the same n0: loss mean_b mean_r (y - mean y - t)^2
+ * with t = (n_conv - n0)/nbar, and its parameter gradients.  Synchronizes
+ * when loss is not NULL. */
+dpp_status dpp_net_backward(dpp_net net, int batch, const double *d_n0, const double *d_nconv, double nbar,
+                            double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the last gradients. */
+dpp_status dpp_net_adam_step(dpp_net net, double lr);
+/* One epoch over nsamples resident samples in the given order (host ints),
+ * batches of `batch`; mean batch loss to *mean_loss.  Synchronizes. */
+dpp_status dpp_net_train_epoch(dpp_net net, int nsamples, const double *d_n0, const double *d_nconv, double nbar,
+                               int batch, double lr, const int *order, double *mean_loss);
+/* Learned start density for one cell (device in/out, N doubles). */
+dpp_status dpp_net_predict_density(dpp_net net, const double *d_n0, double n_electrons, double omega,
+                                   double *d_n_out);
 
 #ifdef __cplusplus
 }

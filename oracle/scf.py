@@ -95,18 +95,23 @@ def subspace_rotate(Y, b, Veff, P, D):
     return psi @ V, eps
 
 
-def scf(sys, Ys, n_in, n_iter: int, n_inner: int = 3, callback=None, etol_per_atom=None):
-    """Run protocol S; returns dict with energies per iteration, final Y, eigs, n."""
+def scf(sys, Ys, n_in, n_iter: int, n_inner: int = 3, callback=None, etol_per_atom=None, n_inner_first=None):
+    """Run protocol S; returns dict with energies per iteration, final Y, eigs, n.
+
+    n_inner_first (default n_inner): band-CG steps of the first iteration, so
+    that the bands can be converged in the start potential before mixing."""
     Ys = [y.copy() for y in Ys]
     pulay = Pulay(sys.omega, sys.N)
     energies = []
     eigs = None
     n_out = None
+    Veff_last = None
     for it in range(n_iter):
         Veff, _ = potentials(n_in, sys)
         new_Y, eigs = [], []
         for k, b in enumerate(sys.bases):
-            cg = protocol_B(Ys[k], b, Veff, sys.P[k], sys.D, n_inner)
+            steps = n_inner_first if (it == 0 and n_inner_first is not None) else n_inner
+            cg = protocol_B(Ys[k], b, Veff, sys.P[k], sys.D, steps)
             Yk, ek = subspace_rotate(cg.Y[0], b, Veff, sys.P[k], sys.D)
             new_Y.append(Yk)
             eigs.append(ek)
@@ -119,7 +124,8 @@ def scf(sys, Ys, n_in, n_iter: int, n_inner: int = 3, callback=None, etol_per_at
         energies.append(E)
         if callback is not None:
             callback(it, E, eigs, n_out)
+        Veff_last = Veff
         n_in = pulay.mix(n_in, n_out)
         if etol_per_atom is not None and it > 0 and abs(energies[-1] - energies[-2]) < etol_per_atom * sys.nat:
             break
-    return dict(energies=energies, Y=Ys, eigs=eigs, n_out=n_out, n_in=n_in)
+    return dict(energies=energies, Y=Ys, eigs=eigs, n_out=n_out, n_in=n_in, Veff=Veff_last)

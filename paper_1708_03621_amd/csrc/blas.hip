@@ -307,17 +307,25 @@ k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ R
     double2* A = reinterpret_cast<double2*>(smem_raw);  // packed upper triangle
     __shared__ int fail;
     __shared__ double umax;
+    __shared__ double red[256];
     const int64_t off = (int64_t)blockIdx.x * n * n;
     const double2* Ug = U + off;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int r = e / n, c = e - r * n;
         if (c >= r) A[up_idx(n, r, c)] = Ug[e];
     }
+    // largest diagonal element (parallel max over LDS-free loads of the diagonal)
+    double m = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, Ug[(int64_t)i * n + i].x);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         fail = 0;
-        double m = 0;
-        for (int i = 0; i < n; ++i) m = fmax(m, Ug[(int64_t)i * n + i].x);
-        umax = m;
+        umax = red[0];
     }
     __syncthreads();
     for (int j = 0; j < n; ++j) {
@@ -357,21 +365,28 @@ k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ R
         for (int e = threadIdx.x; e < n * n; e += blockDim.x) X[e] = double2{NAN, NAN};
         return;
     }
-    // R^{-1}: column c solved by one thread (upper triangular back substitution)
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        for (int r = c + 1; r < n; ++r) X[(int64_t)r * n + c] = double2{0, 0};
-        X[(int64_t)c * n + c] = double2{1.0 / A[up_idx(n, c, c)].x, 0.0};
-        for (int r = c - 1; r >= 0; --r) {
-            double sr = 0, si = 0;
-            for (int k = r + 1; k <= c; ++k) {
-                const double2 a = A[up_idx(n, r, k)];
-                const double2 x = X[(int64_t)k * n + c];
-                sr += a.x * x.x - a.y * x.y;
-                si += a.x * x.y + a.y * x.x;
+    // R^{-1} in place (upper triangular, same packed storage): from X R = 1,
+    // X_ij = -(sum_{k=i}^{j-1} X_ik R_kj) / R_jj for i < j and X_jj = 1 / R_jj;
+    // column j needs only columns < j of X, already in place.
+    for (int j = 0; j < n; ++j) {
+        const double d = 1.0 / A[up_idx(n, j, j)].x;
+        double tr = 0, ti = 0;
+        const int i = threadIdx.x;
+        if (i < j) {
+            for (int k = i; k < j; ++k) {
+                const double2 x = A[up_idx(n, i, k)], r = A[up_idx(n, k, j)];
+                tr += x.x * r.x - x.y * r.y;
+                ti += x.x * r.y + x.y * r.x;
             }
-            const double inv = 1.0 / A[up_idx(n, r, r)].x;
-            X[(int64_t)r * n + c] = double2{-sr * inv, -si * inv};
         }
+        __syncthreads();
+        if (i < j) A[up_idx(n, i, j)] = double2{-tr * d, -ti * d};
+        if (i == j) A[up_idx(n, j, j)] = double2{d, 0.0};
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int r = e / n, c = e - r * n;
+        X[e] = c >= r ? A[up_idx(n, r, c)] : double2{0, 0};
     }
 }
 
@@ -591,7 +606,8 @@ extern "C" dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(ctx, DPP_TK_CHOLESKY);
-    hipLaunchKernelGGL(k_cholesky_inverse, dim3(batch), dim3(256), lds, ctx->stream, nb, (const double2*)U,
+    const int nt = nb <= 64 ? 64 : 256;  // the in-place inverse needs one thread per row
+    hipLaunchKernelGGL(k_cholesky_inverse, dim3(batch), dim3(nt), lds, ctx->stream, nb, (const double2*)U,
                        (double2*)Rinv, ctx->d_status);
     DPP_LAUNCHED();
     return DPP_OK;
@@ -617,7 +633,8 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(ctx, DPP_TK_EIGH);
-    hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(256), lds, ctx->stream, nb, (const double2*)H, eig,
+    const int nt = nb <= 32 ? 64 : 256;  // one wave: barriers are nearly free at small nb
+    hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(nt), lds, ctx->stream, nb, (const double2*)H, eig,
                        (double2*)vecs, (double2*)ws);
     DPP_LAUNCHED();
     return DPP_OK;

@@ -22,6 +22,12 @@ struct DotPairs {
     const double2* b[4];
 };
 
+constexpr int MDOT_BLOCKS = 256;
+
+struct PulayOrder {
+    int s[PULAY_MAX];
+};
+
 struct PulayPtrs {
     const double* nin[PULAY_MAX];
     const double* res[PULAY_MAX];
@@ -44,9 +50,13 @@ __global__ void k_trace(int n, const double2* A, int64_t sa, double scale, doubl
 __global__ void k_trial_mats(int n, const double* alpha, const double2* U, const double2* X, const double2* Q,
                              const double2* H0, const double2* H1, const double2* H2, double2* Ua, double2* Ha);
 __global__ void k_trace_RhHR(int n, const double2* Rinv, const double2* H, double* out);
+__global__ void k_band_residual(const Seg* seg, int nb, int fstride, const double* eig, double omega, const double2* Y,
+                                const double2* HY, double* out);
 __global__ void k_grid_lin3(int64_t N, double a, const double* x, double b, const double* y, double c,
                             const double* z, double* out);
 __global__ void k_pulay_combine(int64_t N, int m, PulayPtrs h, const double* c, double alpha, double* out);
-__global__ void k_pulay_solve(int m, const double* A, double* c, int* status);
+__global__ void k_pulay_solve(int m, const double* A, PulayOrder order, double* c, int* status);
+__global__ void k_multi_dot(int64_t N, const double* a, PulayPtrs bl, int nb, double* part);
+__global__ void k_multi_dot_store(const double* part, int nb, PulayOrder slot, int row, double scale, double* A);
 
 }  // namespace dpp

@@ -269,6 +269,31 @@ k_trace_RhHR(int n, const double2* __restrict__ Rinv, const double2* __restrict_
     if (threadIdx.x == 0) out[b] = red[0];
 }
 
+// Residual norms ||(H - eps_i O) y_i||_2 / sqrt(Omega) for orthonormal
+// eigenvector blocks: one workgroup per (band, k), out[k * fstride + band].
+__global__ void __launch_bounds__(256)
+k_band_residual(const Seg* __restrict__ seg, int nb, int fstride, const double* __restrict__ eig, double omega,
+                const double2* __restrict__ Y, const double2* __restrict__ HY, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int b = blockIdx.x, k = blockIdx.y;
+    const Seg s = seg[k];
+    const double e = eig[k * fstride + b] * omega;
+    const double2* y = Y + s.off + (int64_t)b * s.npw;
+    const double2* h = HY + s.off + (int64_t)b * s.npw;
+    double acc = 0;
+    for (int q = threadIdx.x; q < s.npw; q += 256) {
+        const double rx = h[q].x - e * y[q].x, ry = h[q].y - e * y[q].y;
+        acc += rx * rx + ry * ry;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k * fstride + b] = sqrt(red[0] / omega);
+}
+
 // ------------------------------------------------------------ grids --------
 
 // out = a*x + b*y + c*z (any pointer may be null -> term dropped).
@@ -283,6 +308,43 @@ __global__ void k_grid_lin3(int64_t N, double a, const double* __restrict__ x, d
     out[j] = r;
 }
 
+// Dots of one grid field with up to PULAY_MAX others in one pass:
+// part[j * MDOT_BLOCKS + block] = sum over the block's points of a * b_j.
+__global__ void __launch_bounds__(256)
+k_multi_dot(int64_t N, const double* __restrict__ a, PulayPtrs bl, int nb, double* __restrict__ part) {
+    __shared__ double red[PULAY_MAX][256];
+    double acc[PULAY_MAX];
+#pragma unroll
+    for (int j = 0; j < PULAY_MAX; ++j) acc[j] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)MDOT_BLOCKS * 256) {
+        const double av = a[i];
+#pragma unroll
+        for (int j = 0; j < PULAY_MAX; ++j)
+            if (j < nb) acc[j] += av * bl.res[j][i];
+    }
+#pragma unroll
+    for (int j = 0; j < PULAY_MAX; ++j) red[j][threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int j = 0; j < nb; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < nb) part[threadIdx.x * MDOT_BLOCKS + blockIdx.x] = red[threadIdx.x][0];
+}
+
+// A[row][slot[j]] = A[slot[j]][row] = scale * sum of the partials of dot j (A is
+// PULAY_MAX x PULAY_MAX, indexed by history slot).
+__global__ void k_multi_dot_store(const double* __restrict__ part, int nb, PulayOrder slot, int row, double scale,
+                                  double* __restrict__ A) {
+    const int j = threadIdx.x;
+    if (j >= nb) return;
+    double s = 0;
+    for (int b = 0; b < MDOT_BLOCKS; ++b) s += part[j * MDOT_BLOCKS + b];
+    A[row * PULAY_MAX + slot.s[j]] = scale * s;
+    A[slot.s[j] * PULAY_MAX + row] = scale * s;
+}
+
 // Pulay combination: out = sum_i c_i (nin_i + alpha R_i), histories as arrays of pointers.
 __global__ void k_pulay_combine(int64_t N, int m, PulayPtrs h, const double* __restrict__ c, double alpha,
                                 double* __restrict__ out) {
@@ -294,13 +356,17 @@ __global__ void k_pulay_combine(int64_t N, int m, PulayPtrs h, const double* __r
 }
 
 // Solve the (m+1) x (m+1) Pulay system [A 1; 1^T 0][c; l] = [0; 1] by LU with
-// partial pivoting (one thread).  A is m x m row-major (device).
-__global__ void k_pulay_solve(int m, const double* __restrict__ A, double* __restrict__ c, int* __restrict__ status) {
+// partial pivoting (one thread).  A is indexed by history slot; order.s[i] is
+// the slot of the i-th oldest entry.
+__global__ void k_pulay_solve(int m, const double* __restrict__ A, PulayOrder order, double* __restrict__ c,
+                              int* __restrict__ status) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double M[PULAY_MAX + 1][PULAY_MAX + 2];
     const int n = m + 1;
     for (int i = 0; i < n; ++i) {
-        for (int j = 0; j < n; ++j) M[i][j] = (i < m && j < m) ? A[i * m + j] : ((i == m) != (j == m) ? 1.0 : 0.0);
+        for (int j = 0; j < n; ++j)
+            M[i][j] = (i < m && j < m) ? A[order.s[i] * PULAY_MAX + order.s[j]]
+                                       : ((i == m) != (j == m) ? 1.0 : 0.0);
         M[i][n] = (i == m) ? 1.0 : 0.0;
     }
     for (int col = 0; col < n; ++col) {

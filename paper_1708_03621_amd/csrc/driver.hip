@@ -79,7 +79,14 @@ struct dpp_system_s {
     double vf;
     std::vector<double> fill;  // host fillings nk x nb
     int n_inner_steps;
+    int n_inner_first;
     int64_t hc_bandk;          // H applications counted in (band, k) pairs
+    // precision policy: bulk precision of the FFT passes until the band
+    // residual falls below refine_res, FP64 afterwards (per SCF run)
+    dpp_precision bulk_prec;
+    double refine_res;
+    double last_res;
+    double* d_res;
     dpp_precision prec;
     std::vector<void*> allocs;
     // pinned staging ring for small host -> device uploads; a slot is reused
@@ -822,20 +829,49 @@ dpp_status pulay_mix(dpp_system_s* s) {
     const int m = s->hist_m;
     const double alpha = 0.5;
     if (m == 1) {
+        PulayPtrs bl;
+        PulayOrder sl;
+        for (int i = 0; i < PULAY_MAX; ++i) {
+            bl.nin[i] = nullptr;
+            bl.res[i] = i == 0 ? s->hist_res[slot] : nullptr;
+            sl.s[i] = slot;
+        }
+        hipLaunchKernelGGL(k_multi_dot, dim3(MDOT_BLOCKS), dim3(256), 0, stream(s), N, (const double*)s->hist_res[slot],
+                           bl, 1, s->d_part);
+        DPP_LAUNCHED();
+        hipLaunchKernelGGL(k_multi_dot_store, dim3(1), dim3(64), 0, stream(s), (const double*)s->d_part, 1, sl, slot,
+                           dV, s->pulayA);
+        DPP_LAUNCHED();
         hipLaunchKernelGGL(k_grid_lin3, dim3(nbk), dim3(256), 0, stream(s), N, 1.0, s->nin, alpha, s->hist_res[slot],
                            0.0, (const double*)nullptr, s->nin);
         DPP_LAUNCHED();
         return DPP_OK;
     }
-    // residual overlaps in history order (oldest first), all recomputed in fixed order
+    // residual overlaps: the new residual against every stored one (one pass),
+    // kept in a slot-indexed matrix; the solve reads it in history order
     std::vector<int> order(m);
     for (int i = 0; i < m; ++i) order[i] = (s->hist_head + i) % PULAY_MAX;
-    for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j)
-            DPP_TRY(dpp_grid_dot(s->grid, s->hist_res[order[i]], s->hist_res[order[j]], dV, s->pulayA + i * m + j,
-                                 s->gws));
-    hipLaunchKernelGGL(k_pulay_solve, dim3(1), dim3(1), 0, stream(s), m, s->pulayA, s->pulayC, s->ctx->d_status);
-    DPP_LAUNCHED();
+    {
+        PulayPtrs bl;
+        PulayOrder sl;
+        for (int i = 0; i < PULAY_MAX; ++i) {
+            bl.nin[i] = nullptr;
+            bl.res[i] = i < m ? s->hist_res[order[i]] : nullptr;
+            sl.s[i] = i < m ? order[i] : 0;
+        }
+        TimerScope ts_(s->ctx, DPP_TK_FIELDS);
+        hipLaunchKernelGGL(k_multi_dot, dim3(MDOT_BLOCKS), dim3(256), 0, stream(s), N, (const double*)s->hist_res[slot],
+                           bl, m, s->d_part);
+        DPP_LAUNCHED();
+        hipLaunchKernelGGL(k_multi_dot_store, dim3(1), dim3(64), 0, stream(s), (const double*)s->d_part, m, sl, slot,
+                           dV, s->pulayA);
+        DPP_LAUNCHED();
+        PulayOrder ord;
+        for (int i = 0; i < PULAY_MAX; ++i) ord.s[i] = i < m ? order[i] : 0;
+        hipLaunchKernelGGL(k_pulay_solve, dim3(1), dim3(1), 0, stream(s), m, (const double*)s->pulayA, ord, s->pulayC,
+                           s->ctx->d_status);
+        DPP_LAUNCHED();
+    }
     PulayPtrs h;
     for (int i = 0; i < PULAY_MAX; ++i) {
         h.nin[i] = i < m ? s->hist_nin[order[i]] : nullptr;
@@ -865,10 +901,14 @@ extern "C" dpp_status dpp_system_create(dpp_ctx ctx, const dpp_system_desc* d, d
     s->ne = d->n_electrons;
     s->D = d->D;
     s->prec = (dpp_precision)d->prec;
+    s->bulk_prec = s->prec;
     s->hist_m = s->hist_head = 0;
     s->scf_iter = 0;
     s->n_inner_steps = 3;
+    s->n_inner_first = 3;
     s->hc_bandk = 0;
+    s->refine_res = 0.0;
+    s->last_res = -1.0;
     s->h_ring = nullptr;
     s->h_tab = nullptr;
     s->grid = nullptr;
@@ -930,10 +970,10 @@ extern "C" dpp_status dpp_system_create(dpp_ctx ctx, const dpp_system_desc* d, d
     struct {
         double** p;
         size_t n;
-    } reals[] = {{&s->d_dots, 4 * (size_t)(nk + 1)}, {&s->d_part, 4 * (size_t)nk * DOT_BLOCKS},
+    } reals[] = {{&s->d_dots, 4 * (size_t)(nk + 1)}, {&s->d_part, std::max<size_t>(4 * (size_t)nk * DOT_BLOCKS, (size_t)PULAY_MAX * MDOT_BLOCKS)},
                  {&s->d_alpha, (size_t)nk}, {&s->d_ones, (size_t)nk}, {&s->d_beta, (size_t)nk},
                  {&s->d_E, 16}, {&s->d_f, (size_t)nk * nb}, {&s->d_eig, (size_t)nk * nb},
-                 {&s->d_trial, (size_t)nk}, {&s->d_wk, (size_t)nk}, {&s->Vloc, (size_t)N}, {&s->VH, (size_t)N},
+                 {&s->d_trial, (size_t)nk}, {&s->d_wk, (size_t)nk}, {&s->d_res, (size_t)nk * nb}, {&s->Vloc, (size_t)N}, {&s->VH, (size_t)N},
                  {&s->vxc, (size_t)N}, {&s->Veff, (size_t)N}, {&s->n, (size_t)N}, {&s->nin, (size_t)N},
                  {&s->nout, (size_t)N}, {&s->pulayA, PULAY_MAX * PULAY_MAX}, {&s->pulayC, PULAY_MAX}};
     for (auto& r : reals)
@@ -1114,6 +1154,9 @@ extern "C" dpp_status dpp_scf_init(dpp_system s, const dpp_scf_desc* d) {
     s->hist_head = 0;
     s->scf_iter = 0;
     s->n_inner_steps = d->n_inner > 0 ? d->n_inner : 3;
+    s->n_inner_first = d->n_inner_first > 0 ? d->n_inner_first : s->n_inner_steps;
+    s->prec = s->bulk_prec;
+    s->last_res = -1.0;
     DPP_HIP(hipStreamSynchronize(stream(s)));
     return DPP_OK;
 }
@@ -1128,11 +1171,24 @@ extern "C" dpp_status dpp_scf_iteration(dpp_system s, dpp_c64* Yc, dpp_energy* E
     DPP_TRY(potentials(s, s->nin));
     // 2. band-energy CG, restarted, warm-started Y
     DPP_TRY(cgB_init(s, Y));
-    for (int i = 0; i < s->n_inner_steps; ++i) DPP_TRY(cgB_step(s, Y));
+    const int steps = s->scf_iter == 0 ? s->n_inner_first : s->n_inner_steps;
+    for (int i = 0; i < steps; ++i) DPP_TRY(cgB_step(s, Y));
     // 3. subspace diagonalization
     std::vector<double> ev((size_t)nk * nb);
     DPP_TRY(subspace_rotate(s, Y, ev.data()));
     if (eig) std::copy(ev.begin(), ev.end(), eig);
+    // band residual (Y orthonormal eigenvectors, HY = H Y): drives the switch
+    // from the bulk precision to FP64
+    {
+        TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
+        hipLaunchKernelGGL(k_band_residual, dim3(nb, nk), dim3(256), 0, stream(s), s->d_seg, nb, nb, s->d_eig,
+                           s->grid->omega, (const double2*)Y, (const double2*)s->HY, s->d_res);
+        DPP_LAUNCHED();
+        std::vector<double> res((size_t)nk * nb);
+        DPP_HIP(hipMemcpyAsync(res.data(), s->d_res, res.size() * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
+        DPP_HIP(hipStreamSynchronize(stream(s)));
+        s->last_res = *std::max_element(res.begin(), res.end());
+    }
     // 4. aufbau fillings
     aufbau(ev, nk, nb, s->wk, s->ne, s->fill);
     DPP_TRY(upload(s, s->d_f, s->fill));
@@ -1163,6 +1219,27 @@ extern "C" dpp_status dpp_scf_iteration(dpp_system s, dpp_c64* Yc, dpp_energy* E
     DPP_HIP(hipStreamSynchronize(stream(s)));
     if (E) *E = dpp_energy{e[0] + e[1] + e[2] + e[3] + e[4], e[0], e[1], e[4], e[2], e[3]};
     s->scf_iter++;
+    if (s->prec != DPP_F64 && s->refine_res > 0.0 && s->last_res >= 0.0 && s->last_res < s->refine_res)
+        s->prec = DPP_F64;  // FP64 refinement for the rest of this SCF run
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_set_precision_policy(dpp_system s, int bulk, double refine_residual) {
+    clear_error();
+    DPP_REQUIRE(s && (bulk == DPP_F64 || bulk == DPP_F32) && refine_residual >= 0.0,
+                "dpp_set_precision_policy: bad arguments");
+    s->bulk_prec = (dpp_precision)bulk;
+    s->prec = s->bulk_prec;
+    s->refine_res = refine_residual;
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_scf_status(dpp_system s, double* residual, int* prec_now, int* iterations) {
+    clear_error();
+    DPP_REQUIRE(s, "dpp_scf_status: null system");
+    if (residual) *residual = s->last_res;
+    if (prec_now) *prec_now = s->prec;
+    if (iterations) *iterations = s->scf_iter;
     return DPP_OK;
 }
 

@@ -57,7 +57,8 @@ class dpp_energy(C.Structure):
 
 
 class dpp_scf_desc(C.Structure):
-    _fields_ = [("nat", _i), ("tau", _dp), ("Z", _dp), ("sigma", _d), ("d_n_start", _vp), ("n_inner", _i)]
+    _fields_ = [("nat", _i), ("tau", _dp), ("Z", _dp), ("sigma", _d), ("d_n_start", _vp), ("n_inner", _i),
+                ("n_inner_first", _i)]
 
 
 DPP_FIELD_VLOC, DPP_FIELD_VEFF, DPP_FIELD_N, DPP_FIELD_NIN, DPP_FIELD_NOUT = range(5)
@@ -114,14 +115,26 @@ SIGNATURES = {
     "dpp_scf_iteration": [_vp, _vp, C.POINTER(dpp_energy), _dp],
     "dpp_system_fillings": [_vp, _dp],
     "dpp_system_counters": [_vp, _i64p],
+    "dpp_set_precision_policy": [_vp, _i, _d],
+    "dpp_scf_status": [_vp, _dp, _ip, _ip],
     "dpp_system_apply_H": [_vp, _vp, _vp],
+    "dpp_net_create": [_vp, _ip, _i, C.POINTER(_vp)],
+    "dpp_net_destroy": [_vp],
+    "dpp_net_num_params": [_vp, _ip],
+    "dpp_net_set_params": [_vp, C.POINTER(C.c_float)],
+    "dpp_net_get_params": [_vp, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+    "dpp_net_forward": [_vp, _i, _vp, _d, _vp],
+    "dpp_net_backward": [_vp, _i, _vp, _vp, _d, _dp],
+    "dpp_net_adam_step": [_vp, _d],
+    "dpp_net_train_epoch": [_vp, _i, _vp, _vp, _d, _i, _d, _ip, _dp],
+    "dpp_net_predict_density": [_vp, _vp, _d, _d, _vp],
     "dpp_timer_enable": [_vp, _i],
     "dpp_timer_reset": [_vp],
     "dpp_timer_read": [_vp, _i, _dp, _i64p, _dp, _dp],
 }
 
 TIMER_KINDS = {"planes_in": 0, "xz_h": 1, "planes_out": 2, "xz_density": 3, "overlap": 4, "rotate": 5,
-               "cholesky": 6, "eigh": 7, "fullbox": 8, "fields": 9, "blockops": 10, "xz_io": 11}
+               "cholesky": 6, "eigh": 7, "fullbox": 8, "fields": 9, "blockops": 10, "xz_io": 11, "net": 12}
 
 
 def load(path: str = LIB_PATH):
@@ -434,17 +447,17 @@ def dpp_band_eigenvalues(sys_, Y, nk, nb):
     return e
 
 
-def dpp_scf_init(sys_, tau=None, Z=None, sigma=1.0, d_n_start=None, n_inner=3):
+def dpp_scf_init(sys_, tau=None, Z=None, sigma=1.0, d_n_start=None, n_inner=3, n_inner_first=0):
     keep = []
+    start = None if d_n_start is None else C.c_void_p(d_n_start.data_ptr())
     if tau is not None:
         ta = np.ascontiguousarray(np.asarray(tau, float).reshape(-1))
         Za = np.ascontiguousarray(np.asarray(Z, float).reshape(-1))
         keep += [ta, Za]
-        d = dpp_scf_desc(len(Za), ta.ctypes.data_as(_dp), Za.ctypes.data_as(_dp), float(sigma),
-                         None if d_n_start is None else C.c_void_p(d_n_start.data_ptr()), int(n_inner))
+        d = dpp_scf_desc(len(Za), ta.ctypes.data_as(_dp), Za.ctypes.data_as(_dp), float(sigma), start, int(n_inner),
+                         int(n_inner_first))
     else:
-        d = dpp_scf_desc(0, None, None, float(sigma), None if d_n_start is None else C.c_void_p(d_n_start.data_ptr()),
-                         int(n_inner))
+        d = dpp_scf_desc(0, None, None, float(sigma), start, int(n_inner), int(n_inner_first))
     _call("dpp_scf_init", sys_, C.byref(d))
 
 
@@ -459,6 +472,18 @@ def dpp_system_fillings(sys_, nk, nb):
     f = np.zeros((nk, nb))
     _call("dpp_system_fillings", sys_, f.ctypes.data_as(_dp))
     return f
+
+
+def dpp_set_precision_policy(sys_, bulk, refine_residual):
+    _call("dpp_set_precision_policy", sys_, int(bulk), float(refine_residual))
+
+
+def dpp_scf_status(sys_):
+    r = C.c_double()
+    p = C.c_int()
+    n = C.c_int()
+    _call("dpp_scf_status", sys_, C.byref(r), C.byref(p), C.byref(n))
+    return r.value, p.value, n.value
 
 
 def dpp_system_counters(sys_):
@@ -488,6 +513,64 @@ def dpp_timer_read(ctx, kind):
     k = TIMER_KINDS[kind] if isinstance(kind, str) else int(kind)
     _call("dpp_timer_read", ctx, k, C.byref(ms), C.byref(n), C.byref(by), C.byref(fl))
     return ms.value, n.value, by.value, fl.value
+
+
+# ------------------------------------------------- learned start density ----
+
+def dpp_net_create(ctx, S, max_batch):
+    Sa = (C.c_int * 3)(*[int(x) for x in S])
+    out = _vp()
+    _call("dpp_net_create", ctx, C.cast(Sa, _ip), int(max_batch), C.byref(out))
+    return out
+
+
+def dpp_net_destroy(net):
+    _call("dpp_net_destroy", net)
+
+
+def dpp_net_num_params(net):
+    v = C.c_int()
+    _call("dpp_net_num_params", net, C.byref(v))
+    return v.value
+
+
+def dpp_net_set_params(net, params):
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+    _call("dpp_net_set_params", net, a.ctypes.data_as(C.POINTER(C.c_float)))
+
+
+def dpp_net_get_params(net):
+    n = dpp_net_num_params(net)
+    p = np.zeros(n, np.float32)
+    g = np.zeros(n, np.float32)
+    _call("dpp_net_get_params", net, p.ctypes.data_as(C.POINTER(C.c_float)), g.ctypes.data_as(C.POINTER(C.c_float)))
+    return p, g
+
+
+def dpp_net_forward(net, batch, d_n0, nbar, d_y=None):
+    _call("dpp_net_forward", net, int(batch), _ptr(d_n0), float(nbar), _ptr(d_y))
+
+
+def dpp_net_backward(net, batch, d_n0, d_nconv, nbar):
+    l = C.c_double()
+    _call("dpp_net_backward", net, int(batch), _ptr(d_n0), _ptr(d_nconv), float(nbar), C.byref(l))
+    return l.value
+
+
+def dpp_net_adam_step(net, lr):
+    _call("dpp_net_adam_step", net, float(lr))
+
+
+def dpp_net_train_epoch(net, nsamples, d_n0, d_nconv, nbar, batch, lr, order):
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    l = C.c_double()
+    _call("dpp_net_train_epoch", net, int(nsamples), _ptr(d_n0), _ptr(d_nconv), float(nbar), int(batch), float(lr),
+          o.ctypes.data_as(_ip), C.byref(l))
+    return l.value
+
+
+def dpp_net_predict_density(net, d_n0, n_electrons, omega, d_n_out):
+    _call("dpp_net_predict_density", net, _ptr(d_n0), float(n_electrons), float(omega), _ptr(d_n_out))
 
 
 def exported_symbols():

@@ -120,6 +120,11 @@ def test_scf_iterations_match_oracle(dev, name):
     log(f"gpu {Eg} oracle {res['energies']}")
     assert np.max(np.abs(np.array(Eg) - np.array(res["energies"]))) / cell.nat < TOL_ATOM
     assert np.max(np.abs(eg[-1] - np.array(res["eigs"]))) < 1e-7
+    # band residual of the last iteration (drives the FP64 refinement switch)
+    rg, _, _ = dev.D.dpp_scf_status(sysg)
+    ro = max(oe.residual_norm(res["Y"][k], res["eigs"][k], s.bases[k], res["Veff"], s.P[k], s.D)
+             for k in range(nk))
+    assert abs(rg - ro) < 1e-6 * max(ro, 1e-3)
     dev.D.dpp_system_destroy(sysg)
 
 
@@ -147,4 +152,48 @@ def test_scf_mixed_precision_config2(dev):
     assert dE < 1e-6
     assert np.max(np.abs(e - np.array(res["eigs"]))) < 1e-5
     assert np.sum(np.abs(nout - res["n_out"])) / np.sum(np.abs(res["n_out"])) < 1e-5
+    dev.D.dpp_system_destroy(sysg)
+
+
+def test_scf_mixed_with_fp64_refinement(dev):
+    """FP32 bulk, FP64 once the band residual < 1e-4: the converged energy
+    equals the FP64 path's converged energy to 1e-8 Ha/atom."""
+    log("scf mixed + refinement cfg2")
+    cell = W.config2()
+    nk = len(cell.kpts)
+    out = {}
+    for name, prec, refine in [("f64", 0, 0.0), ("mixed", 1, 1e-4)]:
+        sysg, off, npw = make_gpu_system(dev, cell, prec=prec)
+        dev.D.dpp_set_precision_policy(sysg, prec, refine)
+        Y, _ = packed_Y(dev, cell, npw)
+        dev.D.dpp_scf_init(sysg, cell.tau, cell.Z, W.START_SIGMA)
+        hist = []
+        for _ in range(60):
+            E, e = dev.D.dpp_scf_iteration(sysg, Y, nk, cell.nb)
+            hist.append(E["E_el"])
+        r, p, n = dev.D.dpp_scf_status(sysg)
+        out[name] = (hist, e, r, p)
+        dev.D.dpp_system_destroy(sysg)
+    hf, ef, _, _ = out["f64"]
+    hm, em, rm, pm = out["mixed"]
+    log(f"f64 {hf[-1]:.12f} mixed {hm[-1]:.12f} residual {rm:.2e} prec {pm}")
+    assert pm == 0, "mixed run never switched to FP64"
+    assert abs(hf[-1] - hm[-1]) / cell.nat < TOL_ATOM
+    assert np.max(np.abs(ef - em)) < 1e-7
+
+
+def test_config3_variational_start_and_step(dev):
+    """Config 3 (64 atoms, 90^3, 128 bands, Gamma): total energy and gradient at
+    the orthonormalized start and after one variational CG step, vs the oracle."""
+    log("cfg3 V init + 1 step")
+    cell = W.config3()
+    sysg, off, npw = make_gpu_system(dev, cell)
+    Y, blocks = packed_Y(dev, cell, npw)
+    E0 = dev.D.dpp_cg_V_init(sysg, Y, cell.nb, 2.0)
+    E1, _ = dev.D.dpp_cg_V_step(sysg, Y)
+    s = oe.build_system(cell)
+    cg = om.protocol_V([blocks[0].T.copy()], s, 2.0, 1)
+    log(f"gpu {E0['E_el']:.10f} {E1['E_el']:.10f} oracle {cg.history}")
+    assert abs(E0["E_el"] - cg.history[0]) / cell.nat < TOL_ATOM
+    assert abs(E1["E_el"] - cg.history[1]) / cell.nat < TOL_ATOM
     dev.D.dpp_system_destroy(sysg)

@@ -241,3 +241,25 @@ def random_density(seed: int, S: Sequence[int], mean: float = 0.05) -> np.ndarra
     """Seeded positive field on the box (for LDA/Hartree parity cases)."""
     rng = np.random.default_rng(seed)
     return mean * rng.gamma(2.0, 0.5, tuple(S))
+
+
+NET_CHANNELS = (1, 16, 16, 16, 1)
+
+
+def net_init_params(seed: int = 501):
+    """Seeded initial weights of the learned-density network as a list of
+    (W, b) per layer, W of shape (co, ci, 3, 3, 3): N(0, 2 / (ci * 27)) draws
+    (the output layer scaled by 0.1 so the first correction is small), zero
+    biases.  Random numbers only; both the oracle and the library start here."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for l in range(4):
+        ci, co = NET_CHANNELS[l], NET_CHANNELS[l + 1]
+        std = math.sqrt(2.0 / (ci * 27)) * (0.1 if l == 3 else 1.0)
+        params.append((rng.normal(0.0, std, (co, ci, 3, 3, 3)), np.zeros(co)))
+    return params
+
+
+def net_flatten(params) -> np.ndarray:
+    """Flat float32 vector in the library's order: W1, b1, W2, b2, W3, b3, W4, b4."""
+    return np.concatenate([np.concatenate([W.reshape(-1), b.reshape(-1)]) for W, b in params]).astype(np.float32)
