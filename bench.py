@@ -42,7 +42,15 @@ WORKLOADS = {
                "(8 k-points), one SCF iteration per step (3 band-CG steps/k)",
     "config3": "64-atom diamond supercell L=20.52 bohr displaced N(0,0.1^2), Ecut 15 Ha, FFT 90^3, 128 bands, "
                "Gamma only, one SCF iteration per step (3 band-CG steps)",
+    "config4": "48 independent cubic cells (edges 8-14 bohr, 2-16 atoms Z in {1,4}, Ecut 10 Ha, FFT 24^3-40^3, "
+               "4-32 bands, 1-8 k-points; 171 cell/k items) batched into single launches, one SCF iteration of "
+               "every cell per step (3 band-CG steps/k)",
 }
+
+
+def cells_for(name):
+    import workloads as W
+    return {"config2": lambda: [W.config2()], "config3": lambda: [W.config3()], "config4": W.config4}[name]()
 
 
 def log(msg):
@@ -107,8 +115,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--converge", type=int, default=40, help="SCF iterations for the convergence report")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3"],
-                    help="config2 (the metric's workload) or config3 (64 atoms, 90^3, 128 bands) for profiling")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4"],
+                    help="config2 (the metric's workload), config3 (64 atoms, 90^3, 128 bands) or config4 "
+                         "(48 cells batched)")
+    ap.add_argument("--eager", action="store_true", help="launch every kernel from the host (no graph replay)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built: "
@@ -122,45 +132,58 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     ctx = D.dpp_ctx_create(0, stream.cuda_stream)
-    cell = W.config2() if args.workload == "config2" else W.config3()
-    nk = len(cell.kpts)
+    cells = cells_for(args.workload)
+    nat = np.array([c.nat for c in cells])
+    scf_cells = [dict(tau=c.tau, Z=c.Z.astype(float), sigma=W.START_SIGMA) for c in cells]
 
     def make(prec):
-        sys_ = D.dpp_system_create(ctx, cell.R, cell.S, cell.ecut, cell.kpts, cell.wk, cell.nb, cell.n_electrons,
-                                   cell.tau, cell.Z.astype(float), cell.rc, cell.has_proj.astype(int), W.PROJ_RP,
-                                   W.PROJ_D, prec)
+        descs = [dict(R=c.R, S=c.S, ecut=c.ecut, kpts=c.kpts, wk=c.wk, nb=c.nb, n_electrons=c.n_electrons, tau=c.tau,
+                      Z=c.Z.astype(float), rc=c.rc, has_proj=c.has_proj.astype(int), rp=W.PROJ_RP, D=W.PROJ_D)
+                 for c in cells]
+        sys_ = D.dpp_batch_create(ctx, descs, prec)
         # mixed: FP32 bulk, FP64 refinement once the band residual < 1e-4 Ha
         D.dpp_set_precision_policy(sys_, prec, 1e-4 if prec == D.DPP_F32 else 0.0)
-        off, npw = D.dpp_system_layout(sys_, nk)
-        blocks = W.initial_wavefunctions(cell.y0_seed, [(cell.nb, n) for n in npw])
+        D.dpp_set_graph_mode(sys_, not args.eager)
+        off, npw = D.dpp_system_layout(sys_)
+        item0, _, _ = D.dpp_system_cells(sys_)
+        blocks = []
+        for ci, c in enumerate(cells):
+            blocks += W.initial_wavefunctions(c.y0_seed, [(c.nb, npw[k]) for k in range(item0[ci], item0[ci + 1])])
         Y = torch.from_numpy(np.concatenate([b.reshape(-1) for b in blocks])).to(dev)
-        return sys_, Y, npw
+        return sys_, Y
+
+    def energies(sys_, Y):
+        E, _ = D.dpp_scf_iteration(sys_, Y)
+        return np.array([e["E_el"] for e in E])
 
     results = {}
     for prec, name in [(D.DPP_F64, "f64"), (D.DPP_F32, "mixed")]:
-        sys_, Y, npw = make(prec)
-        D.dpp_scf_init(sys_, cell.tau, cell.Z.astype(float), W.START_SIGMA)
+        sys_, Y = make(prec)
+        D.dpp_scf_init(sys_, cells=scf_cells)
         log(f"[{name}] warmup {args.warmup}")
         for _ in range(args.warmup):
-            D.dpp_scf_iteration(sys_, Y, nk, cell.nb)
+            energies(sys_, Y)
         torch.cuda.synchronize()
         c0 = D.dpp_system_counters(sys_)
         log(f"[{name}] timed {args.steps} SCF iterations")
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            E, eig = D.dpp_scf_iteration(sys_, Y, nk, cell.nb)
+            E = energies(sys_, Y)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         c1 = D.dpp_system_counters(sys_)
         res_end, prec_end, _ = D.dpp_scf_status(sys_)
         ms_step = (t1 - t0) * 1e3 / args.steps
         hc_rate = (c1 - c0) / (t1 - t0)
-        # same steps again with the kernel timer on (HIP events on the library stream)
+        # same steps again, eager, with the kernel timer on (HIP events on the library stream)
+        D.dpp_set_graph_mode(sys_, False)
         D.dpp_timer_reset(ctx)
         D.dpp_timer_enable(ctx, True)
+        te0 = time.perf_counter()
         for _ in range(args.steps):
-            D.dpp_scf_iteration(sys_, Y, nk, cell.nb)
+            energies(sys_, Y)
         torch.cuda.synchronize()
+        ms_eager_timed = (time.perf_counter() - te0) * 1e3 / args.steps
         kern = {}
         for kname in D.TIMER_KINDS:
             ms, n, by, fl = D.dpp_timer_read(ctx, kname)
@@ -168,35 +191,38 @@ def main():
                 kern[kname] = {"ms_total": ms, "launches": n, "avg_us": 1e3 * ms / n, "alg_bytes": by,
                                "alg_flops": fl}
         D.dpp_timer_enable(ctx, False)
-        # isolated H.C on the whole block (8 k x 16 bands), at the current V_eff
+        D.dpp_set_graph_mode(sys_, not args.eager)
+        # isolated H.C on the whole block (every band of every item), at the current V_eff
         HY = torch.empty_like(Y)
         for _ in range(3):
             D.dpp_system_apply_H(sys_, Y, HY)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        reps = 50
+        reps = 50 if args.workload != "config3" else 10
+        nbk = sum(c.nb * len(c.kpts) for c in cells)
         e0.record(stream)
         for _ in range(reps):
             D.dpp_system_apply_H(sys_, Y, HY)
         e1.record(stream)
         torch.cuda.synchronize()
-        hc_only = reps * nk * cell.nb / (e0.elapsed_time(e1) * 1e-3)
-        # convergence report (untimed): iterations until |E_i - E_final| < 1e-6 Ha/atom
-        D.dpp_scf_init(sys_, cell.tau, cell.Z.astype(float), W.START_SIGMA)
-        Y2 = make(prec)[1] if False else Y
-        hist = []
-        for _ in range(args.converge):
-            E2, _ = D.dpp_scf_iteration(sys_, Y2, nk, cell.nb)
-            hist.append(E2["E_el"])
-        Ef = hist[-1]
-        it_conv = next((i + 1 for i in range(len(hist)) if all(abs(h - Ef) / cell.nat < 1e-6 for h in hist[i:])),
-                       None)
-        _, prec_conv, _ = D.dpp_scf_status(sys_)
+        hc_only = reps * nbk / (e0.elapsed_time(e1) * 1e-3)
+        # convergence report (untimed): iterations until |E_i - E_final| < 1e-6 Ha/atom for every cell
+        it_conv, Ef, prec_conv = None, None, prec_end
+        if args.converge > 0:
+            D.dpp_scf_init(sys_, cells=scf_cells)
+            hist = [energies(sys_, Y) for _ in range(args.converge)]
+            Ef = hist[-1]
+            it_conv = next((i + 1 for i in range(len(hist))
+                            if all(np.all(np.abs(h - Ef) / nat < 1e-6) for h in hist[i:])), None)
+            _, prec_conv, _ = D.dpp_scf_status(sys_)
         results[name] = dict(ms_per_step=ms_step, hc_rate=hc_rate, hc_only=hc_only, kernels=kern,
+                             ms_per_step_eager_timer=ms_eager_timed,
                              timed_prec_end=("f32" if prec_end == 1 else "f64"), residual_after_timed=res_end,
                              converged_prec=("f32" if prec_conv == 1 else "f64"),
-                             E_final=Ef, iters_to_1e6=it_conv, E_last_step=E["E_el"])
+                             E_final=(float(Ef[0]) if Ef is not None and len(Ef) == 1 else
+                                      (None if Ef is None else float(np.sum(Ef)))),
+                             iters_to_1e6=it_conv, E_last_step=float(E[0]) if len(E) == 1 else float(np.sum(E)))
         D.dpp_system_destroy(sys_)
 
     r = results["f64"]
@@ -226,6 +252,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "parallelism": "single GPU"},
         "s_per_scf_iter": {k: v["ms_per_step"] * 1e-3 for k, v in results.items()},
+        "launch_mode": "eager" if args.eager else "graph replay (one captured graph per SCF iteration)",
+        "s_per_scf_iter_eager_with_timer": {k: v["ms_per_step_eager_timer"] * 1e-3 for k, v in results.items()},
         "hc_in_scf_bands_k_per_s": {k: v["hc_rate"] for k, v in results.items()},
         "hc_only_bands_k_per_s": {k: v["hc_only"] for k, v in results.items()},
         "speedup_mixed_vs_f64": results["f64"]["ms_per_step"] / results["mixed"]["ms_per_step"],

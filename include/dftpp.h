@@ -62,8 +62,9 @@ typedef enum {
 } dpp_precision;
 
 /* Device status word bits (dpp_ctx_status). */
-#define DPP_STATUS_NOTPD   1
-#define DPP_STATUS_NONFINITE 2
+#define DPP_STATUS_NOTPD   1     /* an overlap matrix was not positive definite */
+#define DPP_STATUS_NONFINITE 2   /* a Pulay system was singular                 */
+#define DPP_STATUS_NOBANDS 4     /* a cell had too few bands for its electrons  */
 
 typedef struct dpp_ctx_s *dpp_ctx;
 typedef struct dpp_grid_s *dpp_grid;
@@ -92,7 +93,8 @@ enum {
     DPP_TK_FIELDS = 9,       /* LDA, grid reductions, density reduction           */
     DPP_TK_BLOCKOPS = 10,    /* packed-block elementwise, dots, small matrices    */
     DPP_TK_XZ_IO = 11,       /* x transforms of I and I^dag to/from full boxes    */
-    DPP_TK_NET = 12          /* learned-density network forward/backward          */
+    DPP_TK_NET = 12,         /* learned-density network forward/backward          */
+    DPP_TK_LINESEARCH = 13   /* fused band-energy line searches (Cholesky, trace) */
 };
 /* Enable (on = 1) or disable the per-context kernel timer: each launch of
  * an instrumented class is bracketed by HIP events on the context stream.
@@ -233,21 +235,29 @@ dpp_status dpp_grid_dot(dpp_grid grid, const double *d_a, const double *d_b, dou
 
 /* --------------------------------------------------------------- drivers -- */
 
-/* One periodic system: a cell, its k-points (Gamma-centred folding or any
- * list) and the pseudopotential model of its atoms.  All arrays are host
- * arrays read during the call.  The system owns its bases, Hamiltonians and
- * every driver buffer (allocated here, never on later calls); wavefunction
- * blocks Y stay caller-owned and use the packed layout of dpp_system_layout:
- * the block of k-point k starts at element offsets[k] and holds nb bands of
- * npw[k] coefficients each (ld = npw[k]). */
+/* A system is a batch of independent periodic cells (a batch of one is the
+ * plain case), each with its k-points (Gamma-centred folding or any list)
+ * and the pseudopotential model of its atoms.  Work items are the
+ * (cell, k-point) pairs numbered cell-major; every driver pass runs as one
+ * launch over all items or all cells, whatever their boxes, spheres and band
+ * counts (form 2).  All descriptor arrays are host arrays read during the
+ * call.  The system owns its bases, Hamiltonians and every driver buffer
+ * (allocated at creation; later calls allocate only small task tables the
+ * first time an operation runs); wavefunction blocks Y stay caller-owned and
+ * use the packed layout of dpp_system_layout: the block of item k starts at
+ * element offsets[k] and holds that cell's nb bands of npw[k] coefficients
+ * each (ld = npw[k]).  Real-space fields of the cells are concatenated (cell c
+ * at foff[c] of dpp_system_cells, N_c doubles); per-state arrays (fillings,
+ * eigenvalues) are concatenated per item (item k at state0 of its cell plus
+ * the nb of the items before it). */
 typedef struct {
     const double *R;        /* 9, columns = lattice vectors                */
     const int *S;           /* 3, FFT box                                  */
     double ecut;            /* hartree                                     */
-    int nk;
+    int nk;                 /* k-points (<= 64)                            */
     const double *kpts;     /* nk x 3 reduced                              */
     const double *wk;       /* nk weights (sum 1)                          */
-    int nb;                 /* bands per k-point (<= 128)                  */
+    int nb;                 /* bands per k-point (<= 128; nk nb <= 2048)   */
     double n_electrons;
     int nat;
     const double *tau;      /* nat x 3 Cartesian                           */
@@ -255,7 +265,8 @@ typedef struct {
     const double *rc;       /* nat erf radii of the local potential        */
     const int *has_proj;    /* nat flags: atom carries the s-projector     */
     double rp, D;           /* projector width and coupling                */
-    int prec;               /* dpp_precision of the FFT passes             */
+    int prec;               /* dpp_precision of the FFT passes (one value
+                               for every cell of a batch)                  */
 } dpp_system_desc;
 
 typedef struct {
@@ -274,58 +285,77 @@ typedef struct {
 
 enum { DPP_FIELD_VLOC = 0, DPP_FIELD_VEFF = 1, DPP_FIELD_N = 2, DPP_FIELD_NIN = 3, DPP_FIELD_NOUT = 4 };
 
-/* Synchronizes.  Builds bases, projectors and V_loc on the device. */
+/* Synchronizes.  Builds bases, projectors and V_loc of ncells cells on the
+ * device.  dpp_system_create is the batch of one. */
+dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system_desc *descs, dpp_system *out);
 dpp_status dpp_system_create(dpp_ctx ctx, const dpp_system_desc *desc, dpp_system *out);
 dpp_status dpp_system_destroy(dpp_system sys);
-/* offsets[nk+1] and npw[nk] of the packed wavefunction layout (host). */
+/* Cells, items, packed block elements, states and concatenated grid points
+ * (host outputs, any may be NULL). */
+dpp_status dpp_system_dims(dpp_system sys, int *ncells, int *nitems, int64_t *total, int64_t *nstates,
+                           int64_t *ngrid);
+/* offsets[nitems+1] and npw[nitems] of the packed wavefunction layout (host). */
 dpp_status dpp_system_layout(dpp_system sys, int64_t *offsets, int64_t *npw);
-/* Device pointer of an internal real-space field (DPP_FIELD_*), N doubles. */
+/* Per cell (ncells + 1 entries each, the last one the total; any may be
+ * NULL): first item, field offset, first state. */
+dpp_status dpp_system_cells(dpp_system sys, int *item0, int64_t *foff, int64_t *state0);
+/* Device pointer of an internal real-space field (DPP_FIELD_*), ngrid doubles. */
 dpp_status dpp_system_field(dpp_system sys, int which, double **d_ptr);
-/* Copy that field into a caller device array of N doubles (stream-ordered). */
+/* Copy that field into a caller device array of ngrid doubles (stream-ordered). */
 dpp_status dpp_system_copy_field(dpp_system sys, int which, double *d_out);
 
 /* Variational minimization of E_el (Sec. 2.2) over the first nocc bands of
- * every k-point with filling f, CG with one step length for all k.  init
- * orthonormalizes those bands of Y once and evaluates E and its gradient;
- * each step is one CG iteration (stationary = 1 once no step lowers E).
- * Synchronizes (line-search decisions read energies back). */
+ * every k-point with filling f, CG with one step length for all k; systems
+ * of one cell.  init orthonormalizes those bands of Y once and evaluates E
+ * and its gradient; each step is one CG iteration (stationary = 1 once no
+ * step lowers E).  Synchronizes (line-search decisions read energies back). */
 dpp_status dpp_cg_V_init(dpp_system sys, dpp_c64 *Y, int nocc, double f, dpp_energy *E);
 dpp_status dpp_cg_V_step(dpp_system sys, dpp_c64 *Y, dpp_energy *E, int *stationary);
-/* Band-energy minimization at fixed V_eff (device, N doubles), all nb bands,
- * an independent line search per k-point.  Eb: host nk band energies
- * Tr(U^{-1} Y^dag H Y) after the call.  Synchronizes. */
+/* Band-energy minimization at fixed V_eff (device, ngrid doubles), all bands,
+ * an independent line search per item, decided on the device.  Eb (host,
+ * may be NULL): per-item band energies Tr(U^{-1} Y^dag H Y) after the call
+ * (reading them synchronizes). */
 dpp_status dpp_cg_B_init(dpp_system sys, dpp_c64 *Y, const double *d_Veff, double *Eb);
 dpp_status dpp_cg_B_step(dpp_system sys, dpp_c64 *Y, double *Eb);
 /* After band CG: subspace diagonalization Y <- psi V with eigenvalues
- * eig (host, nk x nb, ascending per k).  Synchronizes. */
+ * eig (host, nstates, ascending per item).  Synchronizes. */
 dpp_status dpp_band_eigenvalues(dpp_system sys, dpp_c64 *Y, double *eig);
 
-/* SCF (Sec. 2.1 Pulay mixing; Sec. 2.2): start density from desc.
- * One iteration: V_eff[n_in], n_inner band-CG steps per k, subspace
- * diagonalization, aufbau fillings (a degenerate set within 1e-6 Ha at the
- * Fermi level shares electrons equally), n_out, E_el[psi, n_out], Pulay
- * mixing of n_in (history 8, alpha 0.5, first iteration linear).
- * E and eig (host nk x nb, may be NULL) describe this iteration's output.
- * Synchronizes. */
+/* SCF (Sec. 2.1 Pulay mixing; Sec. 2.2): start densities from desc (one
+ * descriptor per cell; n_inner and n_inner_first are taken from the first).
+ * One iteration of every cell: V_eff[n_in], n_inner band-CG steps per item,
+ * subspace diagonalization, aufbau fillings per cell (a degenerate set
+ * within 1e-6 Ha at the Fermi level shares electrons equally), n_out,
+ * E_el[psi, n_out], Pulay mixing of n_in (history 8, alpha 0.5, first
+ * iteration linear).  The iteration runs in stream order without host round
+ * trips; E (host, ncells) and eig (host, nstates, may be NULL) describe its
+ * output, read back at its end (synchronizes). */
 dpp_status dpp_scf_init(dpp_system sys, const dpp_scf_desc *desc);
 dpp_status dpp_scf_iteration(dpp_system sys, dpp_c64 *Y, dpp_energy *E, double *eig);
-/* Number of (band, k-point) H applications performed by the system's
- * drivers since creation (host output). */
+/* Graph mode (on != 0): after the first SCF iteration of a run, each
+ * iteration is captured once as a HIP graph (per Y pointer, step count and
+ * precision) and replayed.  Results equal those of eager mode. */
+dpp_status dpp_set_graph_mode(dpp_system sys, int on);
+/* Number of (band, item) H applications performed by the system's drivers
+ * since creation (host output). */
 dpp_status dpp_system_counters(dpp_system sys, int64_t *hc_bandk);
-/* HY = H Y on all nb bands of every k-point (packed layout, at the
- * potential last set: V_eff of the last SCF iteration or dpp_cg_B_init). */
+/* HY = H Y on all bands of every item (packed layout, at the potential
+ * last set: V_eff of the last SCF iteration or dpp_cg_B_init). */
 dpp_status dpp_system_apply_H(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY);
 /* Precision policy (form 1): FFT passes, potential multiply and density in
  * `bulk` (DPP_F32 or DPP_F64) until the largest band residual
- * max_i ||(H - eps_i O) psi_i||_2 / sqrt(Omega) of an SCF iteration falls
- * below refine_residual (> 0), then FP64 for the rest of that SCF run
- * (dpp_scf_init returns to bulk).  Contractions, Cholesky, eigensolver,
- * energies, Hartree and LDA are FP64 throughout. */
+ * max_i ||(H - eps_i O) psi_i||_2 / sqrt(Omega) of an SCF iteration (over
+ * all cells) falls below refine_residual (> 0), then FP64 for the rest of
+ * that SCF run (dpp_scf_init returns to bulk).  Contractions, Cholesky,
+ * eigensolver, energies, Hartree and LDA are FP64 throughout. */
 dpp_status dpp_set_precision_policy(dpp_system sys, int bulk, double refine_residual);
-/* Residual of the last SCF iteration, the precision of the next one and the
- * iteration count since dpp_scf_init (host outputs, any may be NULL). */
+/* Residual of the last SCF iteration (max over cells), the precision of the
+ * next one and the iteration count since dpp_scf_init (host outputs, any may
+ * be NULL). */
 dpp_status dpp_scf_status(dpp_system sys, double *residual, int *prec_now, int *iterations);
-/* Fillings of the last SCF iteration (host, nk x nb). */
+/* Largest band residual of each cell in the last SCF iteration (host, ncells). */
+dpp_status dpp_scf_cell_residuals(dpp_system sys, double *res);
+/* Fillings of the last SCF iteration (host, nstates). */
 dpp_status dpp_system_fillings(dpp_system sys, double *f);
 
 /* ------------------------------------------------ learned start density -- */

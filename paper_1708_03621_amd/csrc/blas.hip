@@ -13,6 +13,7 @@
 #include <cmath>
 #include <vector>
 
+#include "blockops.h"
 #include "internal.h"
 
 namespace dpp {
@@ -31,9 +32,11 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // one task (kernel argument) or a table of tasks (blockIdx.z).
 
 __global__ void __launch_bounds__(64 * OV_WAVES)
-k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part) {
+k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part,
+               const int* __restrict__ act) {
     __shared__ double red[OV_WAVES][2][4][64];
     const OvTask& T = tasks ? tasks[blockIdx.z] : single;
+    if (act && !act[T.item]) return;
     const int chunk = blockIdx.x;
     const int tile = blockIdx.y;
     if (chunk >= T.nchunk || tile >= T.ntiles) return;
@@ -85,8 +88,10 @@ k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restr
     }
 }
 
-__global__ void k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part) {
+__global__ void k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part,
+                                 const int* __restrict__ act) {
     const OvTask& T = tasks ? tasks[blockIdx.y] : single;
+    if (act && !act[T.item]) return;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= T.ntiles * 256) return;
     const int tile = e >> 8, ij = e & 255;
@@ -125,6 +130,7 @@ OvTask make_ov_task(int npw, int nbA, const double2* A, int64_t ldA, int nbB, co
     t.tilesB = (nbB + 15) / 16;
     t.ntiles = ((nbA + 15) / 16) * t.tilesB;
     t.part_off = 0;
+    t.item = 0;
     return t;
 }
 
@@ -139,19 +145,20 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
     {
         TimerScope ts_(ctx, DPP_TK_OVERLAP, 16.0 * npw * (nbA + nbB), 8.0 * npw * nbA * (double)nbB);
         hipLaunchKernelGGL(k_overlap_mfma, dim3(t.nchunk, t.ntiles, 1), dim3(64 * OV_WAVES), 0, ctx->stream,
-                           (const OvTask*)nullptr, t, part);
+                           (const OvTask*)nullptr, t, part, (const int*)nullptr);
         DPP_LAUNCHED();
     }
     TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
     hipLaunchKernelGGL(k_overlap_reduce, dim3((t.ntiles * 256 + 255) / 256, 1), dim3(256), 0, ctx->stream,
-                       (const OvTask*)nullptr, t, part);
+                       (const OvTask*)nullptr, t, part, (const int*)nullptr);
     DPP_LAUNCHED();
     return DPP_OK;
 }
 
 // Batched: the caller has set part_off of every task (disjoint partial areas)
 // and copied the table to d_tasks.
-dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part) {
+dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
+                         const int* act) {
     if (h.empty()) return DPP_OK;
     int mc = 1, mt = 1;
     double by = 0, fl = 0;
@@ -165,12 +172,12 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
     {
         TimerScope ts_(ctx, DPP_TK_OVERLAP, by, fl);
         hipLaunchKernelGGL(k_overlap_mfma, dim3(mc, mt, (unsigned)h.size()), dim3(64 * OV_WAVES), 0, ctx->stream,
-                           d_tasks, OvTask{}, part);
+                           d_tasks, OvTask{}, part, act);
         DPP_LAUNCHED();
     }
     TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
     hipLaunchKernelGGL(k_overlap_reduce, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
-                       ctx->stream, d_tasks, OvTask{}, (const double2*)part);
+                       ctx->stream, d_tasks, OvTask{}, (const double2*)part, act);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -180,8 +187,9 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
 // bands; X is read once per wave.
 
 __global__ void __launch_bounds__(64 * RT_WAVES)
-k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0) {
+k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const int* __restrict__ act) {
     const RotTask& T = tasks ? tasks[blockIdx.y] : single;
+    if (act && !act[T.item]) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int gt = blockIdx.x * RT_WAVES + w;
     const int G0 = gt * 16;
@@ -249,6 +257,8 @@ RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, 
     t.nbO = nbO;
     t.M_ld = M_ld;
     t.beta = beta;
+    t.item = 0;
+    t.pad = 0;
     return t;
 }
 
@@ -265,13 +275,13 @@ dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t l
     TimerScope ts_(ctx, DPP_TK_ROTATE, rot_bytes(t), 8.0 * npw * nbX * (double)nbO);
     for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT) {
         hipLaunchKernelGGL(k_rotate_mfma, dim3(nblk, 1), dim3(64 * RT_WAVES), 0, ctx->stream, (const RotTask*)nullptr,
-                           t, jt0);
+                           t, jt0, (const int*)nullptr);
         DPP_LAUNCHED();
     }
     return DPP_OK;
 }
 
-dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks) {
+dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks, const int* act) {
     if (h.empty()) return DPP_OK;
     int mp = 1, mj = 1;
     double by = 0, fl = 0;
@@ -285,7 +295,7 @@ dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTas
     TimerScope ts_(ctx, DPP_TK_ROTATE, by, fl);
     for (int jt0 = 0; jt0 < mj; jt0 += RT_JT) {
         hipLaunchKernelGGL(k_rotate_mfma, dim3(nblk, (unsigned)h.size()), dim3(64 * RT_WAVES), 0, ctx->stream,
-                           d_tasks, RotTask{}, jt0);
+                           d_tasks, RotTask{}, jt0, act);
         DPP_LAUNCHED();
     }
     return DPP_OK;
@@ -300,23 +310,23 @@ constexpr double CH_PIVOT_RTOL = 1e-14;
 
 __device__ __forceinline__ int up_idx(int n, int r, int c) { return r * n - (r * (r - 1)) / 2 + (c - r); }
 
-__global__ void __launch_bounds__(256)
-k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ Rinv,
-                   int* __restrict__ status) {
-    extern __shared__ char smem_raw[];
-    double2* A = reinterpret_cast<double2*>(smem_raw);  // packed upper triangle
+// Factor the Hermitian matrix whose upper triangle load(r, c) (c >= r) gives,
+// into packed LDS A, then overwrite A with R^{-1}.  Returns 1 (uniformly) if a
+// pivot falls below CH_PIVOT_RTOL times the largest diagonal element.  Needs
+// blockDim.x >= n and <= 256.
+template <typename Load>
+__device__ int chol_inverse_packed(int n, Load load, double2* __restrict__ A) {
     __shared__ int fail;
     __shared__ double umax;
     __shared__ double red[256];
-    const int64_t off = (int64_t)blockIdx.x * n * n;
-    const double2* Ug = U + off;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int r = e / n, c = e - r * n;
-        if (c >= r) A[up_idx(n, r, c)] = Ug[e];
+        if (c >= r) A[up_idx(n, r, c)] = load(r, c);
     }
-    // largest diagonal element (parallel max over LDS-free loads of the diagonal)
+    __syncthreads();
+    // largest diagonal element
     double m = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, Ug[(int64_t)i * n + i].x);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, A[up_idx(n, i, i)].x);
     red[threadIdx.x] = m;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
@@ -345,9 +355,9 @@ k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ R
         if (threadIdx.x == 0) A[up_idx(n, j, j)] = double2{rjj, 0.0};
         __syncthreads();
         // trailing update A[r][c] -= conj(R[j][r]) R[j][c], j < r <= c
-        const int m = n - j - 1;
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            const int r = j + 1 + e / m, c = j + 1 + e % m;
+        const int mm = n - j - 1;
+        for (int e = threadIdx.x; e < mm * mm; e += blockDim.x) {
+            const int r = j + 1 + e / mm, c = j + 1 + e % mm;
             if (c >= r) {
                 const double2 a = A[up_idx(n, j, r)], b = A[up_idx(n, j, c)];
                 const double re = a.x * b.x + a.y * b.y, im = a.x * b.y - a.y * b.x;  // conj(a) b
@@ -359,12 +369,8 @@ k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ R
         __syncthreads();
     }
     __syncthreads();
-    double2* X = Rinv + off;
-    if (fail) {
-        if (threadIdx.x == 0) atomicOr(status, DPP_STATUS_NOTPD);
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) X[e] = double2{NAN, NAN};
-        return;
-    }
+    const int failed = fail;
+    if (failed) return 1;
     // R^{-1} in place (upper triangular, same packed storage): from X R = 1,
     // X_ij = -(sum_{k=i}^{j-1} X_ik R_kj) / R_jj for i < j and X_jj = 1 / R_jj;
     // column j needs only columns < j of X, already in place.
@@ -384,9 +390,139 @@ k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ R
         if (i == j) A[up_idx(n, j, j)] = double2{d, 0.0};
         __syncthreads();
     }
+    return 0;
+}
+
+__device__ void chol_store(int n, int failed, const double2* __restrict__ A, double2* __restrict__ X,
+                           int* __restrict__ status) {
+    if (failed) {
+        if (threadIdx.x == 0 && status) atomicOr(status, DPP_STATUS_NOTPD);
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) X[e] = double2{NAN, NAN};
+        return;
+    }
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int r = e / n, c = e - r * n;
         X[e] = c >= r ? A[up_idx(n, r, c)] : double2{0, 0};
+    }
+}
+
+// Matrices at stride n^2 (one workgroup each).
+__global__ void __launch_bounds__(256)
+k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ Rinv,
+                   int* __restrict__ status) {
+    extern __shared__ char smem_raw[];
+    double2* A = reinterpret_cast<double2*>(smem_raw);  // packed upper triangle
+    const int64_t off = (int64_t)blockIdx.x * n * n;
+    const double2* Ug = U + off;
+    const int f = chol_inverse_packed(n, [&](int r, int c) { return Ug[(int64_t)r * n + c]; }, A);
+    chol_store(n, f, A, Rinv + off, status);
+}
+
+// Per work item: the item's n x n matrix at moff (n = nbo if > 0, else the
+// item's band count); items with act[item] == 0 are skipped.
+__global__ void __launch_bounds__(256)
+k_cholesky_seg(const Seg* __restrict__ seg, int nbo, const double2* __restrict__ U, double2* __restrict__ Rinv,
+               int* __restrict__ status, const int* __restrict__ act) {
+    if (act && !act[blockIdx.x]) return;
+    extern __shared__ char smem_raw[];
+    double2* A = reinterpret_cast<double2*>(smem_raw);
+    const Seg sg = seg[blockIdx.x];
+    const int n = nbo > 0 ? nbo : sg.nb;
+    const double2* Ug = U + sg.moff;
+    const int f = chol_inverse_packed(n, [&](int r, int c) { return Ug[(int64_t)r * n + c]; }, A);
+    chol_store(n, f, A, Rinv + sg.moff, status);
+}
+
+// Band-energy line search of every active item, entirely on the device (one
+// workgroup per item).  Along D the trial energy is
+//   E(a) = Tr(U(a)^{-1} H(a)),  U(a) = U + a (X + X^dag) + a^2 Q,
+//   H(a) = H0 + a (H1 + H1^dag) + a^2 H2,
+// evaluated through the Cholesky factor of U(a).  Step rule: trial a_t (the
+// item's last accepted step), fit E0 + d0 a + c a^2 through E(a_t), take
+// a* = -d0 / (2c) if c > 0 else 2 a_t, at most 10 a_t; accept a* if
+// E(a*) <= E0, else a_t if E(a_t) <= E0, else halve a_t (at most MAX_TRIES
+// times).  Writes ok[item] and step[item] (0 when the search failed).
+constexpr int LS_MAX_TRIES = 6;
+
+__device__ double trial_energy(const Seg& sg, double a, const double2* __restrict__ U,
+                               const double2* __restrict__ X, const double2* __restrict__ Q,
+                               const double2* __restrict__ H0, const double2* __restrict__ H1,
+                               const double2* __restrict__ H2, double2* __restrict__ A) {
+    __shared__ double red[256];
+    const int n = sg.nb;
+    const int64_t o = sg.moff;
+    auto loadU = [&](int r, int c) {
+        const double2 x = X[o + r * n + c], xt = X[o + c * n + r];
+        const double2 u = U[o + r * n + c], q = Q[o + r * n + c];
+        return double2{u.x + a * (x.x + xt.x) + a * a * q.x, u.y + a * (x.y - xt.y) + a * a * q.y};
+    };
+    const int failed = chol_inverse_packed(n, loadU, A);
+    if (failed) return NAN;
+    // Re Tr(Rinv^dag H(a) Rinv) = sum_{a <= i} Re conj(Rinv[a][i]) sum_{t <= i} H(a)[a][t] Rinv[t][i]
+    double acc = 0;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int ar = e / n, i = e - ar * n;
+        if (ar > i) continue;
+        double wr = 0, wi = 0;
+        for (int t = 0; t <= i; ++t) {
+            const double2 h = H1[o + ar * n + t], ht = H1[o + t * n + ar];
+            const double2 h0 = H0[o + ar * n + t], h2 = H2[o + ar * n + t];
+            const double hr = h0.x + a * (h.x + ht.x) + a * a * h2.x;
+            const double hi = h0.y + a * (h.y - ht.y) + a * a * h2.y;
+            const double2 r = A[up_idx(n, t, i)];
+            wr += hr * r.x - hi * r.y;
+            wi += hr * r.y + hi * r.x;
+        }
+        const double2 ra = A[up_idx(n, ar, i)];
+        acc += ra.x * wr + ra.y * wi;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double E = red[0];
+    __syncthreads();
+    return E;
+}
+
+__global__ void __launch_bounds__(256)
+k_linesearch_B(const Seg* __restrict__ seg, const double2* __restrict__ U, const double2* __restrict__ X,
+               const double2* __restrict__ Q, const double2* __restrict__ H0, const double2* __restrict__ H1,
+               const double2* __restrict__ H2, const double* __restrict__ E0v, const double* __restrict__ at0,
+               const double* __restrict__ d0v, const int* __restrict__ act, int* __restrict__ ok,
+               double* __restrict__ step) {
+    const int k = blockIdx.x;
+    if (!act[k]) return;
+    extern __shared__ char smem_raw[];
+    double2* A = reinterpret_cast<double2*>(smem_raw);
+    const Seg sg = seg[k];
+    const double E0 = E0v[k], d0 = d0v[k];
+    double at = at0[k];
+    int good = 0;
+    double st = 0.0;
+    for (int t = 0; t < LS_MAX_TRIES; ++t) {
+        const double Et = trial_energy(sg, at, U, X, Q, H0, H1, H2, A);
+        const double c = (Et - E0 - d0 * at) / (at * at);
+        double as = c > 0 ? -d0 / (2.0 * c) : 2.0 * at;
+        as = fmin(as, 10.0 * at);
+        const double Es = trial_energy(sg, as, U, X, Q, H0, H1, H2, A);
+        if (Es <= E0) {
+            good = 1;
+            st = as;
+            break;
+        }
+        if (Et <= E0) {
+            good = 1;
+            st = at;
+            break;
+        }
+        at *= 0.5;
+    }
+    if (threadIdx.x == 0) {
+        ok[k] = good;
+        step[k] = st;
     }
 }
 
@@ -406,26 +542,19 @@ struct Rot {
     double cs, sn, er, ei;  // e^{-i phi} = er + i ei
 };
 
-__global__ void __launch_bounds__(256)
-k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, double2* __restrict__ vecs,
-              double2* __restrict__ scratch) {
-    extern __shared__ char smem_raw[];
+// Eigen-decomposition of the Hermitian n x n matrix Hg: ascending eigenvalues
+// to ev, eigenvectors (columns) to vo.  Works in LDS (lds, 2 n^2 entries) if
+// in_lds, else in scr (2 n^2 entries of global scratch).
+__device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double* __restrict__ ev,
+                                  double2* __restrict__ vo, bool in_lds, double2* __restrict__ lds,
+                                  double2* __restrict__ scr) {
     const int m = n + (n & 1);  // even number of players (a dummy if n odd)
-    const bool in_lds = n <= 64;
-    double2* A;
-    double2* V;
-    if (in_lds) {
-        A = reinterpret_cast<double2*>(smem_raw);
-        V = A + n * n;
-    } else {
-        A = scratch + (int64_t)blockIdx.x * 2 * n * n;
-        V = A + n * n;
-    }
+    double2* A = in_lds ? lds : scr;
+    double2* V = A + n * n;
     __shared__ Rot rot[EIG_MAXN / 2];
     __shared__ int order[EIG_MAXN + 2];
     __shared__ double red[256];
     __shared__ int done;
-    const double2* Hg = H + (int64_t)blockIdx.x * n * n;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         double2 h = Hg[e];
         const int r = e / n, c = e % n;
@@ -557,13 +686,32 @@ k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, do
         }
     }
     __syncthreads();
-    double* ev = eig + (int64_t)blockIdx.x * n;
-    double2* vo = vecs + (int64_t)blockIdx.x * n * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = A[perm[i] * n + perm[i]].x;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int r = e / n, c = e % n;
         vo[e] = V[r * n + perm[c]];
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, double2* __restrict__ vecs,
+              double2* __restrict__ scratch) {
+    extern __shared__ char smem_raw[];
+    const int64_t b = blockIdx.x;
+    jacobi_eigh_block(n, H + b * n * n, eig + b * n, vecs + b * n * n, n <= 64, reinterpret_cast<double2*>(smem_raw),
+                      scratch ? scratch + b * 2 * n * n : nullptr);
+}
+
+// Per work item: matrix at moff, eigenvalues at f_off.  With scratch == NULL
+// every matrix works in LDS (the launch provides 2 n^2 entries for the
+// largest n); otherwise in scratch at 2 moff.
+__global__ void __launch_bounds__(256)
+k_jacobi_eigh_seg(const Seg* __restrict__ seg, const double2* __restrict__ H, double* __restrict__ eig,
+                  double2* __restrict__ vecs, double2* __restrict__ scratch) {
+    extern __shared__ char smem_raw[];
+    const Seg sg = seg[blockIdx.x];
+    jacobi_eigh_block(sg.nb, H + sg.moff, eig + sg.f_off, vecs + sg.moff, scratch == nullptr,
+                      reinterpret_cast<double2*>(smem_raw), scratch ? scratch + 2 * sg.moff : nullptr);
 }
 
 }  // namespace dpp

@@ -10,11 +10,17 @@ namespace dpp {
 constexpr int DOT_BLOCKS = 64;  // fixed partial-sum count per block reduction
 constexpr int PULAY_MAX = 8;
 
+// One work item (a k-point of a cell): where its data sits in the packed
+// block buffers, its small matrices, projector overlaps and fillings.
 struct Seg {
-    int64_t off;          // element offset of block k in the packed buffer
-    int npw;
-    int pad;
+    int64_t off;          // element offset of the item's block in the packed buffer
+    int64_t moff;         // offset of its nb x nb matrices
+    int64_t pioff;        // offset of its nproj x nb projector overlaps
+    int64_t f_off;        // offset of its fillings / eigenvalues (nb entries)
     const double* kG2;
+    double wk;            // k-point weight
+    double omega;         // cell volume
+    int npw, nb, nproj, cell;
 };
 
 struct DotPairs {
@@ -23,40 +29,58 @@ struct DotPairs {
 };
 
 constexpr int MDOT_BLOCKS = 256;
+constexpr int AUFBAU_MAX = 2048;       // states (k-points x bands) of one cell
+constexpr int AUFBAU_MAX_ITEMS = 64;   // k-points of one cell
+constexpr double DEGEN_TOL = 1e-6;     // degenerate-set width of the aufbau fillings (Ha)
 
-struct PulayOrder {
-    int s[PULAY_MAX];
+// Device arrays of the band-CG state, one entry per work item.
+struct CgBState {
+    double *at, *gkg, *beta, *d0, *d0r, *step, *step2, *cK, *cD;
+    int *reset, *stat, *act, *steep, *ok, *ok2, *retry;
 };
 
-struct PulayPtrs {
-    const double* nin[PULAY_MAX];
-    const double* res[PULAY_MAX];
-};
-
-__global__ void k_seg_axpby(const Seg* seg, int nb, const double* a, const double2* x, const double* b,
+// Kernels with `nbo`: band count override (> 0) for every item, else seg.nb.
+__global__ void k_seg_axpby(const Seg* seg, int nbo, const double* a, const double2* x, const double* b,
                             const double2* y, double2* out);
-__global__ void k_seg_precond(const Seg* seg, int nb, double scale, const double2* x, double2* out);
-__global__ void k_seg_dots(const Seg* seg, int nk, int nb, int npair, DotPairs pr, double* part);
-__global__ void k_seg_dots_reduce(const double* part, int nk, int npair, double* out);
-__global__ void k_seg_kinetic(const Seg* seg, int nb, int fstride, const double* f, const double2* psi, double* part);
-__global__ void k_seg_weighted_total(const double* part, int nk, const double* wk, double scale, double* out);
-__global__ void k_nonlocal_energy(int nk, int nproj, int nb, int fstride, const double2* pi, int64_t pi_stride,
-                                  const double* f, const double* wk, double D, double* out);
-__global__ void k_sm_scale(int n, int64_t st, int op, double scale, const double* scale_arr, const double2* A,
+__global__ void k_seg_precond(const Seg* seg, int nbo, double scale, const double2* x, double2* out);
+__global__ void k_seg_dots(const Seg* seg, int nitems, int nbo, int npair, DotPairs pr, double* part);
+__global__ void k_seg_dots_reduce(const double* part, int nitems, int npair, double* out);
+__global__ void k_seg_kinetic(const Seg* seg, int nbo, const double* f, const double2* psi, double* part);
+__global__ void k_cell_weighted_totals(const double* part, const Seg* seg, const CellDesc* cells, int ncells,
+                                       double scale_omega, double* out, int out_stride);
+__global__ void k_nonlocal_energy(const Seg* seg, const CellDesc* cells, int nbo, const double2* pi, const double* f,
+                                  double* out, int out_stride);
+__global__ void k_sm_scale(const Seg* seg, int nbo, int op, double scale, int flags, const double2* A,
                            double2* out);
-__global__ void k_smm(int n, int opA, int opB, double alpha, const double* alpha_arr, const double2* A, int64_t sa,
-                      const double2* B, int64_t sb, double beta, double2* Cm, int64_t sc);
-__global__ void k_trace(int n, const double2* A, int64_t sa, double scale, double* out);
-__global__ void k_trial_mats(int n, const double* alpha, const double2* U, const double2* X, const double2* Q,
-                             const double2* H0, const double2* H1, const double2* H2, double2* Ua, double2* Ha);
-__global__ void k_trace_RhHR(int n, const double2* Rinv, const double2* H, double* out);
-__global__ void k_band_residual(const Seg* seg, int nb, int fstride, const double* eig, double omega, const double2* Y,
-                                const double2* HY, double* out);
+__global__ void k_smm(const Seg* seg, int nbo, int opA, int opB, double alpha, int alpha_omega, const double2* A,
+                      const double2* B, double beta, double2* Cm);
+__global__ void k_trace_RhHR(const Seg* seg, int nbo, const double2* Rinv, const double2* H, double* out);
+__global__ void k_band_residual(const Seg* seg, const double* eig, const double2* Y, const double2* HY, double* out);
 __global__ void k_grid_lin3(int64_t N, double a, const double* x, double b, const double* y, double c,
                             const double* z, double* out);
-__global__ void k_pulay_combine(int64_t N, int m, PulayPtrs h, const double* c, double alpha, double* out);
-__global__ void k_pulay_solve(int m, const double* A, PulayOrder order, double* c, int* status);
-__global__ void k_multi_dot(int64_t N, const double* a, PulayPtrs bl, int nb, double* part);
-__global__ void k_multi_dot_store(const double* part, int nb, PulayOrder slot, int row, double scale, double* A);
+__global__ void k_fill(int64_t n, double v, double* out);
+__global__ void k_copy(int64_t n, const double2* x, double2* out);
+__global__ void k_pulay_reset(int* st);
+__global__ void k_pulay_begin(int* st);
+__global__ void k_pulay_store(int64_t Ntot, const int* st, const double* nin, const double* nout, double* hn,
+                              double* hr);
+__global__ void k_pulay_dots(int64_t Ntot, const int* st, const CellDesc* cells, const double* hr, double* part);
+__global__ void k_pulay_solve_cells(int ncells, const int* st, const CellDesc* cells, const double* part, double* A,
+                                    double* coef, int* status);
+__global__ void k_pulay_combine_cells(int64_t Ntot, const int* st, const CellDesc* cells, const double* coef,
+                                      double alpha, const double* hn, const double* hr, double* nin);
+__global__ void k_cgB_reset(int nit, const Seg* seg, CgBState s);
+__global__ void k_cgB_direction(int nit, const double* dots, CgBState s);
+__global__ void k_cgB_retry(int nit, const double* dots, CgBState s);
+__global__ void k_cgB_finish(int nit, const double* dots, CgBState s);
+__global__ void k_aufbau(const CellDesc* cells, const Seg* seg, const double* eig, double* f, int* status);
+
+// blas.hip: per-item Cholesky inverse, eigensolver and fused line search
+__global__ void k_cholesky_seg(const Seg* seg, int nbo, const double2* U, double2* Rinv, int* status,
+                               const int* act);
+__global__ void k_jacobi_eigh_seg(const Seg* seg, const double2* H, double* eig, double2* vecs, double2* scratch);
+__global__ void k_linesearch_B(const Seg* seg, const double2* U, const double2* X, const double2* Q,
+                               const double2* H0, const double2* H1, const double2* H2, const double* E0v,
+                               const double* at0, const double* d0v, const int* act, int* ok, double* step);
 
 }  // namespace dpp

@@ -12,13 +12,15 @@ namespace dpp {
 
 // ------------------------------------------------------- elementwise -------
 
-// out_k = a_k * x_k + b_k * y_k over every block (alpha arrays per k, device).
-__global__ void k_seg_axpby(const Seg* __restrict__ seg, int nb, const double* __restrict__ a,
+__device__ __forceinline__ int item_nb(const Seg& s, int nbo) { return nbo > 0 ? nbo : s.nb; }
+
+// out_i = a_i * x_i + b_i * y_i over every item's block (a, b per item, device).
+__global__ void k_seg_axpby(const Seg* __restrict__ seg, int nbo, const double* __restrict__ a,
                             const double2* __restrict__ x, const double* __restrict__ b,
                             const double2* __restrict__ y, double2* __restrict__ out) {
     const int k = blockIdx.y;
     const Seg s = seg[k];
-    const int64_t n = (int64_t)nb * s.npw;
+    const int64_t n = (int64_t)item_nb(s, nbo) * s.npw;
     const double ak = a ? a[k] : 0.0, bk = b ? b[k] : 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t o = s.off + e;
@@ -37,12 +39,12 @@ __global__ void k_seg_axpby(const Seg* __restrict__ seg, int nb, const double* _
     }
 }
 
-// out = scale * K x  (K = 1/(1 + |k+G|^2/2)), per block.
-__global__ void k_seg_precond(const Seg* __restrict__ seg, int nb, double scale, const double2* __restrict__ x,
+// out = scale * K x  (K = 1/(1 + |k+G|^2/2)), per item.
+__global__ void k_seg_precond(const Seg* __restrict__ seg, int nbo, double scale, const double2* __restrict__ x,
                               double2* __restrict__ out) {
     const int k = blockIdx.y;
     const Seg s = seg[k];
-    const int64_t n = (int64_t)nb * s.npw;
+    const int64_t n = (int64_t)item_nb(s, nbo) * s.npw;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int q = (int)(e % s.npw);
         const double kk = scale / (1.0 + 0.5 * s.kG2[q]);
@@ -51,22 +53,22 @@ __global__ void k_seg_precond(const Seg* __restrict__ seg, int nb, double scale,
     }
 }
 
-// Per-block dots 2 Re sum conj(A) B for up to 4 pairs: partial sums per
-// (pair, k, block) -> part[(pair * nk + k) * DOT_BLOCKS + blockIdx.x].
+// Per-item dots 2 Re sum conj(A) B for up to 4 pairs: partial sums per
+// (pair, item, block) -> part[(pair * nitems + k) * DOT_BLOCKS + blockIdx.x].
 __global__ void __launch_bounds__(256)
-k_seg_dots(const Seg* __restrict__ seg, int nk, int nb, int npair, DotPairs pr, double* __restrict__ part) {
+k_seg_dots(const Seg* __restrict__ seg, int nitems, int nbo, int npair, DotPairs pr, double* __restrict__ part) {
     __shared__ double red[4][256];
     const int k = blockIdx.y;
     const Seg s = seg[k];
-    const int64_t n = (int64_t)nb * s.npw;
+    const int64_t n = (int64_t)item_nb(s, nbo) * s.npw;
     double acc[4] = {0, 0, 0, 0};
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * 256) {
         const int64_t o = s.off + e;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             if (p < npair) {
-                const double2 a = pr.a[p][o], b = pr.b[p][o];
-                acc[p] += a.x * b.x + a.y * b.y;
+                const double2 av = pr.a[p][o], bv = pr.b[p][o];
+                acc[p] += av.x * bv.x + av.y * bv.y;
             }
         }
     }
@@ -78,44 +80,43 @@ k_seg_dots(const Seg* __restrict__ seg, int nk, int nb, int npair, DotPairs pr, 
             for (int p = 0; p < 4; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < npair) part[((int64_t)threadIdx.x * nk + k) * DOT_BLOCKS + blockIdx.x] = 2.0 * red[threadIdx.x][0];
+    if (threadIdx.x < npair)
+        part[((int64_t)threadIdx.x * nitems + k) * DOT_BLOCKS + blockIdx.x] = 2.0 * red[threadIdx.x][0];
 }
 
-// Sum partials in fixed order: out[pair * (nk + 1) + k] per k, and the total
-// over k at out[pair * (nk + 1) + nk].
-__global__ void k_seg_dots_reduce(const double* __restrict__ part, int nk, int npair, double* __restrict__ out) {
+// Fixed-order sums: out[pair * (nitems + 1) + k] per item and the total over
+// items at out[pair * (nitems + 1) + nitems].
+__global__ void k_seg_dots_reduce(const double* __restrict__ part, int nitems, int npair, double* __restrict__ out) {
     const int p = blockIdx.x;
     if (p >= npair) return;
-    __shared__ double tot[64];
-    for (int k = threadIdx.x; k < nk; k += blockDim.x) {
+    for (int k = threadIdx.x; k < nitems; k += blockDim.x) {
         double s = 0;
-        for (int b = 0; b < DOT_BLOCKS; ++b) s += part[((int64_t)p * nk + k) * DOT_BLOCKS + b];
-        out[p * (nk + 1) + k] = s;
+        for (int b = 0; b < DOT_BLOCKS; ++b) s += part[((int64_t)p * nitems + k) * DOT_BLOCKS + b];
+        out[p * (nitems + 1) + k] = s;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0;
-        for (int k = 0; k < nk; ++k) s += out[p * (nk + 1) + k];
-        out[p * (nk + 1) + nk] = s;
+        for (int k = 0; k < nitems; ++k) s += out[p * (nitems + 1) + k];
+        out[p * (nitems + 1) + nitems] = s;
     }
-    (void)tot;
 }
 
 // Band-weighted kinetic sums: part[k * DOT_BLOCKS + block] of
-// sum_i f[k*nb+i] * sum_G |k+G|^2 |psi_Gi|^2.
+// sum_i f_ki * sum_G |k+G|^2 |psi_Gi|^2.
 __global__ void __launch_bounds__(256)
-k_seg_kinetic(const Seg* __restrict__ seg, int nb, int fstride, const double* __restrict__ f,
-              const double2* __restrict__ psi, double* __restrict__ part) {
+k_seg_kinetic(const Seg* __restrict__ seg, int nbo, const double* __restrict__ f, const double2* __restrict__ psi,
+              double* __restrict__ part) {
     __shared__ double red[256];
     const int k = blockIdx.y;
     const Seg s = seg[k];
-    const int64_t n = (int64_t)nb * s.npw;
+    const int64_t n = (int64_t)item_nb(s, nbo) * s.npw;
     double acc = 0;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * 256) {
         const int b = (int)(e / s.npw);
         const int q = (int)(e - (int64_t)b * s.npw);
         const double2 v = psi[s.off + e];
-        acc += f[k * fstride + b] * s.kG2[q] * (v.x * v.x + v.y * v.y);
+        acc += f[s.f_off + b] * s.kG2[q] * (v.x * v.x + v.y * v.y);
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -126,32 +127,39 @@ k_seg_kinetic(const Seg* __restrict__ seg, int nb, int fstride, const double* __
     if (threadIdx.x == 0) part[k * DOT_BLOCKS + blockIdx.x] = red[0];
 }
 
-// E = sum_k w_k * scale * sum_blocks part[k]  (fixed order), written to *out.
-__global__ void k_seg_weighted_total(const double* __restrict__ part, int nk, const double* __restrict__ wk,
-                                     double scale, double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// out[c * out_stride] = sum over the cell's items of w_k (scale_omega * Omega)
+// * sum_blocks part[k]  (fixed order; one thread per cell).
+__global__ void k_cell_weighted_totals(const double* __restrict__ part, const Seg* __restrict__ seg,
+                                       const CellDesc* __restrict__ cells, int ncells, double scale_omega,
+                                       double* __restrict__ out, int out_stride) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const CellDesc cr = cells[c];
     double tot = 0;
-    for (int k = 0; k < nk; ++k) {
+    for (int k = cr.item0; k < cr.item0 + cr.nitems; ++k) {
         double s = 0;
         for (int b = 0; b < DOT_BLOCKS; ++b) s += part[k * DOT_BLOCKS + b];
-        tot += wk[k] * scale * s;
+        tot += seg[k].wk * scale_omega * seg[k].omega * s;
     }
-    *out = tot;
+    out[c * out_stride] = tot;
 }
 
-// Nonlocal energy from Pi (nproj x nb per k, row-major, at pi + k * pi_stride):
-// sum_k w_k D sum_i f_ki sum_a |Pi_ai|^2 -> *out (one thread, fixed order).
-__global__ void k_nonlocal_energy(int nk, int nproj, int nb, int fstride, const double2* __restrict__ pi,
-                                  int64_t pi_stride, const double* __restrict__ f, const double* __restrict__ wk,
-                                  double D, double* __restrict__ out) {
+// Nonlocal energy per cell: sum_k w_k D sum_i f_ki sum_a |Pi_ai|^2, Pi of item
+// k at pi + pioff (nproj x nb row-major).  One workgroup per cell.
+__global__ void k_nonlocal_energy(const Seg* __restrict__ seg, const CellDesc* __restrict__ cells, int nbo,
+                                  const double2* __restrict__ pi, const double* __restrict__ f,
+                                  double* __restrict__ out, int out_stride) {
     __shared__ double red[256];
+    const CellDesc cr = cells[blockIdx.x];
     double tot = 0;
-    for (int k = 0; k < nk; ++k) {
+    for (int k = cr.item0; k < cr.item0 + cr.nitems; ++k) {
+        const Seg s = seg[k];
+        const int nb = item_nb(s, nbo);
         double acc = 0;
-        for (int e = threadIdx.x; e < nproj * nb; e += blockDim.x) {
+        for (int e = threadIdx.x; e < s.nproj * nb; e += blockDim.x) {
             const int i = e % nb;
-            const double2 v = pi[k * pi_stride + e];
-            acc += f[k * fstride + i] * (v.x * v.x + v.y * v.y);
+            const double2 v = pi[s.pioff + e];
+            acc += f[s.f_off + i] * (v.x * v.x + v.y * v.y);
         }
         red[threadIdx.x] = acc;
         __syncthreads();
@@ -159,25 +167,26 @@ __global__ void k_nonlocal_energy(int nk, int nproj, int nb, int fstride, const 
             if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) tot += wk[k] * D * red[0];
+        if (threadIdx.x == 0) tot += s.wk * cr.D * red[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = tot;
+    if (threadIdx.x == 0) out[blockIdx.x * out_stride] = tot;
 }
 
 // ------------------------------------------------------- small matrices ----
+// Every item's matrices are n x n row-major at moff (n = nbo or seg.nb).
 
-// C_b = alpha * op(A_b) op(B_b) + beta * C_b for n x n complex row-major
-// matrices, op = N or H (conjugate transpose); batch b = blockIdx.x with
-// strides sa, sb, sc (elements).  alpha_arr (per batch, optional) multiplies alpha.
-__global__ void k_smm(int n, int opA, int opB, double alpha, const double* __restrict__ alpha_arr,
-                      const double2* __restrict__ A, int64_t sa, const double2* __restrict__ B, int64_t sb,
-                      double beta, double2* __restrict__ Cm, int64_t sc) {
-    const int b = blockIdx.x;
-    const double2* Ab = A + b * sa;
-    const double2* Bb = B + b * sb;
-    double2* Cb = Cm + b * sc;
-    const double al = alpha * (alpha_arr ? alpha_arr[b] : 1.0);
+// C = alpha op(A) op(B) + beta C, op = N or H (conjugate transpose); batch =
+// item; alpha is multiplied by the item's cell volume if alpha_omega.
+__global__ void k_smm(const Seg* __restrict__ seg, int nbo, int opA, int opB, double alpha0, int alpha_omega,
+                      const double2* __restrict__ A, const double2* __restrict__ B, double beta,
+                      double2* __restrict__ Cm) {
+    const Seg s = seg[blockIdx.x];
+    const int n = item_nb(s, nbo);
+    const double alpha = alpha_omega ? alpha0 * s.omega : alpha0;
+    const double2* Ab = A + s.moff;
+    const double2* Bb = B + s.moff;
+    double2* Cb = Cm + s.moff;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int i = e / n, j = e - i * n;
         double sr = 0, si = 0;
@@ -189,7 +198,7 @@ __global__ void k_smm(int n, int opA, int opB, double alpha, const double* __res
             sr += a.x * bb.x - a.y * bb.y;
             si += a.x * bb.y + a.y * bb.x;
         }
-        double2 r = double2{al * sr, al * si};
+        double2 r = double2{alpha * sr, alpha * si};
         if (beta != 0.0) {
             const double2 c = Cb[e];
             r.x += beta * c.x;
@@ -199,54 +208,28 @@ __global__ void k_smm(int n, int opA, int opB, double alpha, const double* __res
     }
 }
 
-// out_b = scale * (scale_arr ? scale_arr[b] : 1) * op(A_b), op = N or H; n x n at stride st.
-__global__ void k_sm_scale(int n, int64_t st, int op, double scale, const double* __restrict__ scale_arr,
+// out = scale * (w_k if flags & 1) * (Omega if flags & 2) * op(A), op = N or H.
+__global__ void k_sm_scale(const Seg* __restrict__ seg, int nbo, int op, double scale, int flags,
                            const double2* __restrict__ A, double2* __restrict__ out) {
-    const int b = blockIdx.x;
-    const double sc = scale * (scale_arr ? scale_arr[b] : 1.0);
+    const Seg s = seg[blockIdx.x];
+    const int n = item_nb(s, nbo);
+    const double sc = scale * ((flags & 1) ? s.wk : 1.0) * ((flags & 2) ? s.omega : 1.0);
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int i = e / n, j = e - i * n;
-        double2 a = op ? A[b * st + j * n + i] : A[b * st + e];
+        double2 a = op ? A[s.moff + j * n + i] : A[s.moff + e];
         if (op) a.y = -a.y;
-        out[b * st + e] = double2{sc * a.x, sc * a.y};
+        out[s.moff + e] = double2{sc * a.x, sc * a.y};
     }
 }
 
-// out[b] = Re Tr(A_b) * scale.
-__global__ void k_trace(int n, const double2* __restrict__ A, int64_t sa, double scale, double* __restrict__ out) {
-    const int b = blockIdx.x;
-    if (threadIdx.x == 0) {
-        double s = 0;
-        for (int i = 0; i < n; ++i) s += A[b * sa + i * n + i].x;
-        out[b] = scale * s;
-    }
-}
-
-// Trial matrices of a line search along D (batch b over k):
-//   U(a) = U + a (X + X^dag) + a^2 Q,   H(a) = H0 + a (H1 + H1^dag) + a^2 H2
-__global__ void k_trial_mats(int n, const double* __restrict__ alpha, const double2* __restrict__ U,
-                             const double2* __restrict__ X, const double2* __restrict__ Q,
-                             const double2* __restrict__ H0, const double2* __restrict__ H1,
-                             const double2* __restrict__ H2, double2* __restrict__ Ua, double2* __restrict__ Ha) {
-    const int b = blockIdx.x;
-    const double a = alpha[b];
-    const int64_t o = (int64_t)b * n * n;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        const double2 x = X[o + e], xt = X[o + j * n + i];
-        const double2 h = H1[o + e], ht = H1[o + j * n + i];
-        const double2 u = U[o + e], q = Q[o + e], h0 = H0[o + e], h2 = H2[o + e];
-        Ua[o + e] = double2{u.x + a * (x.x + xt.x) + a * a * q.x, u.y + a * (x.y - xt.y) + a * a * q.y};
-        Ha[o + e] = double2{h0.x + a * (h.x + ht.x) + a * a * h2.x, h0.y + a * (h.y - ht.y) + a * a * h2.y};
-    }
-}
-
-// Re Tr(Rinv^dag H Rinv) per batch (= Tr(U^{-1} H) for U = R^dag R).
+// Re Tr(Rinv^dag H Rinv) per item (= Tr(U^{-1} H) for U = R^dag R).
 __global__ void __launch_bounds__(256)
-k_trace_RhHR(int n, const double2* __restrict__ Rinv, const double2* __restrict__ H, double* __restrict__ out) {
+k_trace_RhHR(const Seg* __restrict__ seg, int nbo, const double2* __restrict__ Rinv, const double2* __restrict__ H,
+             double* __restrict__ out) {
     __shared__ double red[256];
-    const int b = blockIdx.x;
-    const int64_t o = (int64_t)b * n * n;
+    const Seg s = seg[blockIdx.x];
+    const int n = item_nb(s, nbo);
+    const int64_t o = s.moff;
     double acc = 0;
     // sum_i sum_a conj(Rinv[a][i]) (H Rinv)[a][i]
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
@@ -266,18 +249,19 @@ k_trace_RhHR(int n, const double2* __restrict__ Rinv, const double2* __restrict_
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[b] = red[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // Residual norms ||(H - eps_i O) y_i||_2 / sqrt(Omega) for orthonormal
-// eigenvector blocks: one workgroup per (band, k), out[k * fstride + band].
+// eigenvector blocks: one workgroup per (band, item), out[f_off + band].
 __global__ void __launch_bounds__(256)
-k_band_residual(const Seg* __restrict__ seg, int nb, int fstride, const double* __restrict__ eig, double omega,
-                const double2* __restrict__ Y, const double2* __restrict__ HY, double* __restrict__ out) {
+k_band_residual(const Seg* __restrict__ seg, const double* __restrict__ eig, const double2* __restrict__ Y,
+                const double2* __restrict__ HY, double* __restrict__ out) {
     __shared__ double red[256];
     const int b = blockIdx.x, k = blockIdx.y;
     const Seg s = seg[k];
-    const double e = eig[k * fstride + b] * omega;
+    if (b >= s.nb) return;
+    const double e = eig[s.f_off + b] * s.omega;
     const double2* y = Y + s.off + (int64_t)b * s.npw;
     const double2* h = HY + s.off + (int64_t)b * s.npw;
     double acc = 0;
@@ -291,7 +275,7 @@ k_band_residual(const Seg* __restrict__ seg, int nb, int fstride, const double* 
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[k * fstride + b] = sqrt(red[0] / omega);
+    if (threadIdx.x == 0) out[s.f_off + b] = sqrt(red[0] / s.omega);
 }
 
 // ------------------------------------------------------------ grids --------
@@ -308,64 +292,110 @@ __global__ void k_grid_lin3(int64_t N, double a, const double* __restrict__ x, d
     out[j] = r;
 }
 
-// Dots of one grid field with up to PULAY_MAX others in one pass:
-// part[j * MDOT_BLOCKS + block] = sum over the block's points of a * b_j.
+__global__ void k_fill(int64_t n, double v, double* __restrict__ out) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        out[j] = v;
+}
+
+__global__ void k_copy(int64_t n, const double2* __restrict__ x, double2* __restrict__ out) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        out[j] = x[j];
+}
+
+// ------------------------------------------------------------- Pulay -------
+// History ring of PULAY_MAX entries shared by every cell, state on the device:
+// st[0] = entries m, st[1] = oldest slot, st[2] = slot of the newest entry.
+// Entry s of a history array lives at s * Ntot (fields of all cells).
+
+__global__ void k_pulay_reset(int* __restrict__ st) {
+    if (threadIdx.x == 0) st[0] = st[1] = st[2] = 0;
+}
+
+__global__ void k_pulay_begin(int* __restrict__ st) {
+    if (threadIdx.x != 0) return;
+    int m = st[0], head = st[1], slot;
+    if (m < PULAY_MAX) {
+        slot = (head + m) % PULAY_MAX;
+        ++m;
+    } else {
+        slot = head;
+        head = (head + 1) % PULAY_MAX;
+    }
+    st[0] = m;
+    st[1] = head;
+    st[2] = slot;
+}
+
+// New entry: n_in and R = n_out - n_in into the slot st[2] (all cells at once).
+__global__ void k_pulay_store(int64_t Ntot, const int* __restrict__ st, const double* __restrict__ nin,
+                              const double* __restrict__ nout, double* __restrict__ hn, double* __restrict__ hr) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Ntot) return;
+    const int64_t o = (int64_t)st[2] * Ntot + j;
+    hn[o] = nin[j];
+    hr[o] = nout[j] - nin[j];
+}
+
+// Per cell (blockIdx.y): partial dots of the new residual with the m stored
+// residuals, history order i (slot (head + i) mod PULAY_MAX):
+// part[(cell * PULAY_MAX + i) * MDOT_BLOCKS + block].
 __global__ void __launch_bounds__(256)
-k_multi_dot(int64_t N, const double* __restrict__ a, PulayPtrs bl, int nb, double* __restrict__ part) {
+k_pulay_dots(int64_t Ntot, const int* __restrict__ st, const CellDesc* __restrict__ cells,
+             const double* __restrict__ hr, double* __restrict__ part) {
     __shared__ double red[PULAY_MAX][256];
+    const CellDesc c = cells[blockIdx.y];
+    const int m = st[0], head = st[1], slot = st[2];
+    const double* a = hr + (int64_t)slot * Ntot + c.foff;
     double acc[PULAY_MAX];
 #pragma unroll
-    for (int j = 0; j < PULAY_MAX; ++j) acc[j] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)MDOT_BLOCKS * 256) {
-        const double av = a[i];
+    for (int i = 0; i < PULAY_MAX; ++i) acc[i] = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < c.N; j += (int64_t)MDOT_BLOCKS * 256) {
+        const double av = a[j];
 #pragma unroll
-        for (int j = 0; j < PULAY_MAX; ++j)
-            if (j < nb) acc[j] += av * bl.res[j][i];
+        for (int i = 0; i < PULAY_MAX; ++i)
+            if (i < m) acc[i] += av * hr[(int64_t)((head + i) % PULAY_MAX) * Ntot + c.foff + j];
     }
 #pragma unroll
-    for (int j = 0; j < PULAY_MAX; ++j) red[j][threadIdx.x] = acc[j];
+    for (int i = 0; i < PULAY_MAX; ++i) red[i][threadIdx.x] = acc[i];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w)
-            for (int j = 0; j < nb; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+            for (int i = 0; i < m; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < nb) part[threadIdx.x * MDOT_BLOCKS + blockIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < m)
+        part[((int64_t)blockIdx.y * PULAY_MAX + threadIdx.x) * MDOT_BLOCKS + blockIdx.x] = red[threadIdx.x][0];
 }
 
-// A[row][slot[j]] = A[slot[j]][row] = scale * sum of the partials of dot j (A is
-// PULAY_MAX x PULAY_MAX, indexed by history slot).
-__global__ void k_multi_dot_store(const double* __restrict__ part, int nb, PulayOrder slot, int row, double scale,
-                                  double* __restrict__ A) {
-    const int j = threadIdx.x;
-    if (j >= nb) return;
-    double s = 0;
-    for (int b = 0; b < MDOT_BLOCKS; ++b) s += part[j * MDOT_BLOCKS + b];
-    A[row * PULAY_MAX + slot.s[j]] = scale * s;
-    A[slot.s[j] * PULAY_MAX + row] = scale * s;
-}
-
-// Pulay combination: out = sum_i c_i (nin_i + alpha R_i), histories as arrays of pointers.
-__global__ void k_pulay_combine(int64_t N, int m, PulayPtrs h, const double* __restrict__ c, double alpha,
-                                double* __restrict__ out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    double r = 0;
-    for (int i = 0; i < m; ++i) r += c[i] * (h.nin[i][j] + alpha * h.res[i][j]);
-    out[j] = r;
-}
-
-// Solve the (m+1) x (m+1) Pulay system [A 1; 1^T 0][c; l] = [0; 1] by LU with
-// partial pivoting (one thread).  A is indexed by history slot; order.s[i] is
-// the slot of the i-th oldest entry.
-__global__ void k_pulay_solve(int m, const double* __restrict__ A, PulayOrder order, double* __restrict__ c,
-                              int* __restrict__ status) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Per cell (one thread): finish the residual overlaps into the cell's
+// slot-indexed matrix A (PULAY_MAX^2 per cell, scaled by Omega / N), then the
+// mixing coefficients in history order: c = (1) for one entry, else the
+// solution of [A 1; 1^T 0][c; l] = [0; 1] (LU with partial pivoting).
+__global__ void k_pulay_solve_cells(int ncells, const int* __restrict__ st, const CellDesc* __restrict__ cells,
+                                    const double* __restrict__ part, double* __restrict__ A,
+                                    double* __restrict__ coef, int* __restrict__ status) {
+    const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cidx >= ncells) return;
+    const int m = st[0], head = st[1], slot = st[2];
+    const double dV = cells[cidx].dV;
+    double* Ac = A + (int64_t)cidx * PULAY_MAX * PULAY_MAX;
+    double* c = coef + (int64_t)cidx * PULAY_MAX;
+    for (int i = 0; i < m; ++i) {
+        double s = 0;
+        for (int b = 0; b < MDOT_BLOCKS; ++b) s += part[((int64_t)cidx * PULAY_MAX + i) * MDOT_BLOCKS + b];
+        const int si = (head + i) % PULAY_MAX;
+        Ac[slot * PULAY_MAX + si] = dV * s;
+        Ac[si * PULAY_MAX + slot] = dV * s;
+    }
+    if (m == 1) {
+        c[0] = 1.0;
+        return;
+    }
     double M[PULAY_MAX + 1][PULAY_MAX + 2];
     const int n = m + 1;
     for (int i = 0; i < n; ++i) {
         for (int j = 0; j < n; ++j)
-            M[i][j] = (i < m && j < m) ? A[order.s[i] * PULAY_MAX + order.s[j]]
+            M[i][j] = (i < m && j < m) ? Ac[((head + i) % PULAY_MAX) * PULAY_MAX + (head + j) % PULAY_MAX]
                                        : ((i == m) != (j == m) ? 1.0 : 0.0);
         M[i][n] = (i == m) ? 1.0 : 0.0;
     }
@@ -396,6 +426,171 @@ __global__ void k_pulay_solve(int m, const double* __restrict__ A, PulayOrder or
         x[i] = s / M[i][i];
     }
     for (int i = 0; i < m; ++i) c[i] = x[i];
+}
+
+// n_in = sum_i c_i (n_in,i + alpha R_i) per cell (blockIdx.y), history order.
+__global__ void k_pulay_combine_cells(int64_t Ntot, const int* __restrict__ st, const CellDesc* __restrict__ cells,
+                                      const double* __restrict__ coef, double alpha, const double* __restrict__ hn,
+                                      const double* __restrict__ hr, double* __restrict__ nin) {
+    const CellDesc c = cells[blockIdx.y];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= c.N) return;
+    const int m = st[0], head = st[1];
+    const double* cc = coef + (int64_t)blockIdx.y * PULAY_MAX;
+    double r = 0;
+    for (int i = 0; i < m; ++i) {
+        const int64_t o = (int64_t)((head + i) % PULAY_MAX) * Ntot + c.foff + j;
+        r += cc[i] * (hn[o] + alpha * hr[o]);
+    }
+    nin[c.foff + j] = r;
+}
+
+// ---------------------------------------------------- band-CG control ------
+// Per-item state of the band-energy CG (protocol B), updated on the device so
+// that a whole SCF iteration runs without host round trips.
+
+__global__ void k_cgB_reset(int nit, const Seg* __restrict__ seg, CgBState s) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nit) return;
+    s.at[k] = 0.3 / seg[k].omega;
+    s.reset[k] = 1;
+    s.stat[k] = 0;
+    s.gkg[k] = 0.0;
+}
+
+// Direction coefficients D = -K g + beta D_prev from the dots
+// (<g,Kg>, <g_prev,Kg>, <g,D_prev>) per item.
+__global__ void k_cgB_direction(int nit, const double* __restrict__ dots, CgBState s) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nit) return;
+    const double gkg = dots[k], gpkg = dots[(nit + 1) + k], gdp = dots[2 * (nit + 1) + k];
+    s.cK[k] = -1.0;
+    if (s.stat[k]) {
+        s.act[k] = 0;
+        s.beta[k] = 0.0;
+        s.d0[k] = 0.0;
+        s.steep[k] = 1;
+        return;
+    }
+    s.act[k] = 1;
+    double b = 0.0;
+    if (!s.reset[k]) b = fmax(0.0, (gkg - gpkg) / s.gkg[k]);
+    double dd = -gkg + b * gdp;
+    if (b != 0.0 && dd >= 0.0) {
+        b = 0.0;
+        dd = -gkg;
+    }
+    s.beta[k] = b;
+    s.d0[k] = dd;
+    s.steep[k] = b == 0.0;
+}
+
+// Items whose CG line search failed (and was not already steepest descent)
+// retry along -K g: D <- cK K g + cD D with cK = -1, cD = 0 for them.
+__global__ void k_cgB_retry(int nit, const double* __restrict__ dots, CgBState s) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nit) return;
+    const int r = s.act[k] && !s.ok[k] && !s.steep[k];
+    s.retry[k] = r;
+    s.cK[k] = r ? -1.0 : 0.0;
+    s.cD[k] = r ? 0.0 : 1.0;
+    s.d0r[k] = r ? -dots[k] : s.d0[k];
+}
+
+// Accept the steps: failed items become stationary (step 0); successful ones
+// record <g,Kg> and the step as the next trial.
+__global__ void k_cgB_finish(int nit, const double* __restrict__ dots, CgBState s) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nit) return;
+    if (!s.act[k]) {
+        s.step[k] = 0.0;
+        return;
+    }
+    int o = s.ok[k];
+    double st = s.step[k];
+    if (s.retry[k]) {
+        o = s.ok2[k];
+        st = s.step2[k];
+    }
+    if (!o) {
+        s.stat[k] = 1;
+        s.reset[k] = 1;
+        st = 0.0;
+    }
+    s.step[k] = st;
+    if (o) {
+        s.gkg[k] = dots[k];
+        s.at[k] = st;
+        s.reset[k] = 0;
+    }
+}
+
+// ------------------------------------------------------------ aufbau -------
+// Fillings of one cell (one workgroup): states (e, k, i) ordered by energy,
+// then k-point, then band; groups of states within DEGEN_TOL of the group's
+// first energy fill together, each state holding 2 w_k electrons; a group that
+// does not fit shares the remaining electrons equally.
+__global__ void __launch_bounds__(256)
+k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const double* __restrict__ eig,
+         double* __restrict__ f, int* __restrict__ status) {
+    __shared__ double e[AUFBAU_MAX];
+    __shared__ short kk[AUFBAU_MAX];
+    __shared__ short ii[AUFBAU_MAX];
+    __shared__ int order[AUFBAU_MAX];
+    __shared__ int base[AUFBAU_MAX_ITEMS + 1];
+    const CellDesc c = cells[blockIdx.x];
+    if (threadIdx.x == 0) {
+        base[0] = 0;
+        for (int k = 0; k < c.nitems; ++k) base[k + 1] = base[k] + seg[c.item0 + k].nb;
+    }
+    __syncthreads();
+    const int ns = base[c.nitems];
+    for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+        int k = 0;
+        while (base[k + 1] <= t) ++k;
+        const int i = t - base[k];
+        const Seg sg = seg[c.item0 + k];
+        e[t] = eig[sg.f_off + i];
+        kk[t] = (short)k;
+        ii[t] = (short)i;
+        f[sg.f_off + i] = 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+        int r = 0;
+        for (int u = 0; u < ns; ++u) {
+            const bool less = e[u] < e[t] || (e[u] == e[t] && (kk[u] < kk[t] || (kk[u] == kk[t] && ii[u] < ii[t])));
+            r += less;
+        }
+        order[r] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double rem = c.ne;
+    int j = 0;
+    while (j < ns && rem > 1e-12) {
+        const double e0 = e[order[j]];
+        const int j0 = j;
+        ++j;
+        while (j < ns && e[order[j]] - e0 < DEGEN_TOL) ++j;
+        double cap = 0;
+        for (int t = j0; t < j; ++t) cap += 2.0 * seg[c.item0 + kk[order[t]]].wk;
+        if (cap <= rem + 1e-12) {
+            for (int t = j0; t < j; ++t) {
+                const int u = order[t];
+                f[seg[c.item0 + kk[u]].f_off + ii[u]] = 2.0;
+            }
+            rem -= cap;
+        } else {
+            const double frac = rem / cap;
+            for (int t = j0; t < j; ++t) {
+                const int u = order[t];
+                f[seg[c.item0 + kk[u]].f_off + ii[u]] = 2.0 * frac;
+            }
+            rem = 0.0;
+        }
+    }
+    if (rem > 1e-9) atomicOr(status, DPP_STATUS_NOBANDS);
 }
 
 }  // namespace dpp

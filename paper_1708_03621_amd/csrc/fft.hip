@@ -104,8 +104,9 @@ __device__ __forceinline__ TO store_as(C v) {
 template <typename T, typename TIO, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_planes_from_sphere(const FftItem* items, FftItem single, const TIO* __restrict__ C,
-                     typename cx<T>::t* __restrict__ Tb) {
+                     typename cx<T>::t* __restrict__ Tb, const int* __restrict__ act) {
     using Cx = typename cx<T>::t;
+    if (BATCH && act && !act[blockIdx.z]) return;
     const FftItem& it = DPP_ITEM(items, single);
     const int p = blockIdx.x, b = blockIdx.y;
     if (p >= it.nplanes || b >= it.nb) return;
@@ -127,17 +128,20 @@ k_planes_from_sphere(const FftItem* items, FftItem single, const TIO* __restrict
 
 // Full-box field plane i0 -> 2D transform (sign) -> plane buffer.
 // REAL_IN: input is real (double), else complex (double2).
-template <typename T, bool REAL_IN, int NT>
+// Batched (one item per cell, blockIdx.z): the field sits at v_off, the
+// planes at t_off.
+template <typename T, bool REAL_IN, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
-k_planes_from_box(FftItem it, const void* __restrict__ in, int64_t field_stride, int sign,
-                  typename cx<T>::t* __restrict__ Tb) {
+k_planes_from_box(const FftItem* items, FftItem single, const void* __restrict__ in, int64_t field_stride,
+                  int sign, typename cx<T>::t* __restrict__ Tb) {
     using Cx = typename cx<T>::t;
+    const FftItem& it = DPP_ITEM(items, single);
     const int p = blockIdx.x, f = blockIdx.y;
     if (p >= it.S0) return;
     extern __shared__ char smem_raw[];
     Cx* lds = reinterpret_cast<Cx*>(smem_raw);
     const int S1 = it.S1, S2 = it.S2, np = S1 * S2;
-    const int64_t base = (int64_t)f * field_stride + (int64_t)p * np;
+    const int64_t base = it.v_off + (int64_t)f * field_stride + (int64_t)p * np;
     if (REAL_IN) {
         const double* src = reinterpret_cast<const double*>(in) + base;
         for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = Cx{(T)src[i], (T)0};
@@ -148,7 +152,7 @@ k_planes_from_box(FftItem it, const void* __restrict__ in, int64_t field_stride,
     __syncthreads();
     fft_axis<T, false, NT>(lds, it.ax[2], S1, AddrLinear{S2, 1}, it.tw64[2], it.tw32[2], sign);
     fft_axis<T, true, NT>(lds, it.ax[1], S2, AddrLinear{1, S2}, it.tw64[1], it.tw32[1], sign);
-    Cx* dst = Tb + (int64_t)f * it.S0 * np + (int64_t)p * np;
+    Cx* dst = Tb + it.t_off + (int64_t)f * it.S0 * np + (int64_t)p * np;
     for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = lds[i];
 }
 
@@ -199,8 +203,9 @@ __device__ __forceinline__ void xz_store_pruned(const FftItem& it, typename cx<T
 template <typename T, int MODE, typename TIO, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_xz(const FftItem* items, FftItem single, typename cx<T>::t* __restrict__ Tb,
-     const double* __restrict__ V, TIO* __restrict__ box) {
+     const double* __restrict__ V, TIO* __restrict__ box, const int* __restrict__ act) {
     using Cx = typename cx<T>::t;
+    if (BATCH && act && !act[blockIdx.z]) return;
     const FftItem& it = DPP_ITEM(items, single);
     const int i1 = blockIdx.x, b = blockIdx.y;
     if (i1 >= it.S1 || b >= it.nb) return;
@@ -276,13 +281,15 @@ k_xz_full(FftItem it, const typename cx<T>::t* __restrict__ Tb, int sign, double
 // multiply by 4 pi / (|G|^2 N^2) (the J normalization 1/N and the I scale N
 // of the way back leave 4 pi / (|G|^2 N)), accumulate the energy partial
 // sum_G 4 pi |n~|^2 / |G|^2 for this i1, transform back along x.
-template <int NT>
+template <int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
-k_xz_hartree(FftItem it, double2* __restrict__ Tb, double B00, double B01, double B02, double B10,
-             double B11, double B12, double B20, double B21, double B22,
-             double* __restrict__ epart) {
+k_xz_hartree(const FftItem* items, FftItem single, double2* __restrict__ Tbase, double* __restrict__ epart) {
+    const FftItem& it = DPP_ITEM(items, single);
     const int i1 = blockIdx.x;
     if (i1 >= it.S1) return;
+    double2* Tb = Tbase + it.t_off;
+    const double B00 = it.B[0], B01 = it.B[1], B02 = it.B[2], B10 = it.B[3], B11 = it.B[4], B12 = it.B[5],
+                 B20 = it.B[6], B21 = it.B[7], B22 = it.B[8];
     extern __shared__ char smem_raw[];
     double2* lds = reinterpret_cast<double2*>(smem_raw);
     __shared__ double red[NT];
@@ -320,7 +327,7 @@ k_xz_hartree(FftItem it, double2* __restrict__ Tb, double B00, double B01, doubl
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) epart[i1] = red[0];
+    if (threadIdx.x == 0) epart[it.p_off + i1] = red[0];
     fft_axis<double, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], +1);
     for (int i = threadIdx.x; i < e; i += blockDim.x) {
         const int i0 = i / S2, i2 = i - i0 * S2;
@@ -330,7 +337,8 @@ k_xz_hartree(FftItem it, double2* __restrict__ Tb, double B00, double B01, doubl
 
 // Density x pass: one workgroup per (item, band chunk, i1) loops over the
 // chunk's bands, transforms each along x and accumulates f_b |psi|^2 in
-// registers; writes the chunk's partial (times w_k) for this i1.
+// registers; writes the chunk's partial (times w_k) for this i1 to box
+// p_off + c N of the partial buffer (the item has dnch chunks of dchunk bands).
 // accumulators per thread: every x-z tile fits (7680 elements at 512 threads, 8192 at 1024)
 template <int NT>
 struct DensMax {
@@ -340,14 +348,13 @@ constexpr int DENS_CHUNKS = 16;
 template <typename T, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_xz_density(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb,
-             const double* __restrict__ fill, int chunk, double* __restrict__ part) {
+             const double* __restrict__ fill, double* __restrict__ part) {
     using Cx = typename cx<T>::t;
     const FftItem& it = DPP_ITEM(items, single);
     const int i1 = blockIdx.x, c = blockIdx.y;
-    if (i1 >= it.S1) return;
-    const int b0 = c * chunk;
-    if (b0 >= it.nb) return;
-    const int b1 = min(it.nb, b0 + chunk);
+    if (i1 >= it.S1 || c >= it.dnch) return;
+    const int b0 = c * it.dchunk;
+    const int b1 = min(it.nb, b0 + it.dchunk);
     extern __shared__ char smem_raw[];
     Cx* lds = reinterpret_cast<Cx*>(smem_raw);
     const int S0 = it.S0, S1 = it.S1, S2 = it.S2;
@@ -373,7 +380,7 @@ k_xz_density(const FftItem* items, FftItem single, const typename cx<T>::t* __re
         __syncthreads();
     }
     const int64_t N = (int64_t)S0 * S1 * S2;
-    double* dst = part + ((int64_t)blockIdx.z * gridDim.y + c) * N + (int64_t)i1 * S2;
+    double* dst = part + it.p_off + (int64_t)c * N + (int64_t)i1 * S2;
 #pragma unroll
     for (int u = 0; u < DM; ++u) {
         const int i = threadIdx.x + u * NT;
@@ -394,14 +401,27 @@ __global__ void k_density_reduce(const double* __restrict__ part, int nchunk, in
     n[j] += s;
 }
 
+// Per cell (blockIdx.y): n[foff + j] = sum of the cell's partial boxes in order.
+__global__ void k_density_reduce_cells(const double* __restrict__ part, const CellDesc* __restrict__ cells,
+                                       double* __restrict__ n) {
+    const CellDesc c = cells[blockIdx.y];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= c.N) return;
+    double s = 0.0;
+    for (int p = 0; p < c.nparts; ++p) s += part[c.pstart + (int64_t)p * c.N + j];
+    n[c.foff + j] = s;
+}
+
 // ------------------------------------------------------------- pass 3 ------
 enum GatherMode { G_SET = 0, G_ADD = 1, G_H = 2 };
 
 template <typename T, int MODE, typename TIO, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_planes_to_sphere(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb,
-                   const double2* __restrict__ Cin, TIO* __restrict__ out, int64_t ldout_override) {
+                   const double2* __restrict__ Cin, TIO* __restrict__ out, int64_t ldout_override,
+                   const int* __restrict__ act) {
     using Cx = typename cx<T>::t;
+    if (BATCH && act && !act[blockIdx.z]) return;
     const FftItem& it = DPP_ITEM(items, single);
     const int p = blockIdx.x, b = blockIdx.y;
     if (p >= it.nplanes || b >= it.nb) return;
@@ -441,22 +461,23 @@ k_planes_to_sphere(const FftItem* items, FftItem single, const typename cx<T>::t
 
 // Plane buffer (full box) -> 2D transform (sign) -> real part (REAL_OUT) or
 // complex output box, times `scale`.
-template <typename T, bool REAL_OUT, int NT>
+template <typename T, bool REAL_OUT, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
-k_planes_to_box(FftItem it, const typename cx<T>::t* __restrict__ Tb, int sign, double scale,
-                void* __restrict__ out, int64_t field_stride) {
+k_planes_to_box(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb, int sign,
+                double scale, void* __restrict__ out, int64_t field_stride) {
     using Cx = typename cx<T>::t;
+    const FftItem& it = DPP_ITEM(items, single);
     const int p = blockIdx.x, f = blockIdx.y;
     if (p >= it.S0) return;
     extern __shared__ char smem_raw[];
     Cx* lds = reinterpret_cast<Cx*>(smem_raw);
     const int S1 = it.S1, S2 = it.S2, np = S1 * S2;
-    const Cx* src = Tb + (int64_t)f * it.S0 * np + (int64_t)p * np;
+    const Cx* src = Tb + it.t_off + (int64_t)f * it.S0 * np + (int64_t)p * np;
     for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = src[i];
     __syncthreads();
     fft_axis<T, true, NT>(lds, it.ax[1], S2, AddrLinear{1, S2}, it.tw64[1], it.tw32[1], sign);
     fft_axis<T, false, NT>(lds, it.ax[2], S1, AddrLinear{S2, 1}, it.tw64[2], it.tw32[2], sign);
-    const int64_t base = (int64_t)f * field_stride + (int64_t)p * np;
+    const int64_t base = it.v_off + (int64_t)f * field_stride + (int64_t)p * np;
     if (REAL_OUT) {
         double* dst = reinterpret_cast<double*>(out) + base;
         for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = (double)lds[i].x * scale;
@@ -535,7 +556,8 @@ static dpp_status pass1(dpp_ctx_s* cx_, const FftItem& it, const TIO* C, typenam
     const bool fp64 = sizeof(T) == 8;
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_from_sphere<T, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
-                    hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, C, Tb));
+                    hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, C, Tb,
+                                       (const int*)nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -551,7 +573,8 @@ static dpp_status pass2(dpp_ctx_s* cx_, const FftItem& it, typename cx<T>::t* Tb
     const bool fp64 = sizeof(T) == 8;
     Launch L = xz_launch(it.S0, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_xz<T, MODE, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
-                    hipLaunchKernelGGL(k, dim3(it.S1, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, Tb, V, box));
+                    hipLaunchKernelGGL(k, dim3(it.S1, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, Tb, V, box,
+                                       (const int*)nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -567,7 +590,7 @@ static dpp_status pass3(dpp_ctx_s* cx_, const FftItem& it, const typename cx<T>:
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, MODE, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, Tb, Cin,
-                                       out, (int64_t)0));
+                                       out, (int64_t)0, (const int*)nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -591,7 +614,7 @@ dpp_status run_apply_H_local(dpp_ham_s* ham, int nb, const double2* C, int64_t l
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(ot.nplanes, ot.nb, 1), dim3(NT_), L.lds, st, nullptr, ot, Tb, C, HC,
-                                       ldHC));
+                                       ldHC, (const int*)nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -607,20 +630,44 @@ size_t batched_plane_elems(const std::vector<FftItem>& h) {
     return t;
 }
 
-// One launch per pass for every item of the table.  All items of a table
-// share the box S (one cell), so workgroup size and LDS match.
+namespace {
+// Largest workgroup and LDS any item of a table needs for a plane pass and
+// for an x-z pass, and the largest grid extents.
+struct BatchShape {
+    Launch plane, xz;
+    int maxP, maxS1, maxS0, nbm;
+};
+
+BatchShape batch_shape(const std::vector<FftItem>& h, bool fp64) {
+    BatchShape b{{0, 0}, {0, 0}, 0, 0, 0, 0};
+    for (const FftItem& it : h) {
+        const Launch p = plane_launch(it.S1, it.S2, fp64), x = xz_launch(it.S0, it.S2, fp64);
+        b.plane.threads = std::max(b.plane.threads, p.threads);
+        b.plane.lds = std::max(b.plane.lds, p.lds);
+        b.xz.threads = std::max(b.xz.threads, x.threads);
+        b.xz.lds = std::max(b.xz.lds, x.lds);
+        b.maxP = std::max(b.maxP, it.nplanes);
+        b.maxS1 = std::max(b.maxS1, it.S1);
+        b.maxS0 = std::max(b.maxS0, it.S0);
+        b.nbm = std::max(b.nbm, it.nb);
+    }
+    return b;
+}
+}  // namespace
+
+// One launch per pass for every item of the table (items may differ in box,
+// sphere and band count).
 template <typename T>
 dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,
-                                 const double2* X, double2* HX, const double* V, void* Tbv) {
+                                 const double2* X, double2* HX, const double* V, void* Tbv, const int* act) {
     using Cx = typename cx<T>::t;
+    if (h.empty()) return DPP_OK;
     Cx* Tb = reinterpret_cast<Cx*>(Tbv);
     hipStream_t st = cx_->stream;
     const bool fp64 = sizeof(T) == 8;
-    int maxP = 0, nbm = 0;
+    const BatchShape bs = batch_shape(h, fp64);
     double b1 = 0, b2 = 0, b3 = 0;
     for (const FftItem& it : h) {
-        maxP = std::max(maxP, it.nplanes);
-        nbm = std::max(nbm, it.nb);
         const double pl = (double)it.nplanes * it.S1 * it.S2;
         b1 += it.nb * (16.0 * it.npw + sizeof(Cx) * pl);
         b2 += it.nb * 2.0 * sizeof(Cx) * pl + 8.0 * it.S0 * it.S1 * it.S2;
@@ -629,82 +676,124 @@ dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const s
     const FftItem& i0 = h[0];
     const unsigned nit = (unsigned)h.size();
     {
-        Launch L = plane_launch(i0.S1, i0.S2, fp64);
         TimerScope ts_(cx_, DPP_TK_PLANES_IN, b1);
-        DPP_NT_DISPATCH(L.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>; DPP_TRY(set_lds(k, L.lds));
-                        hipLaunchKernelGGL(k, dim3(maxP, nbm, nit), dim3(NT_), L.lds, st, d_items, i0, X, Tb));
+        DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>;
+                        DPP_TRY(set_lds(k, bs.plane.lds));
+                        hipLaunchKernelGGL(k, dim3(bs.maxP, bs.nbm, nit), dim3(NT_), bs.plane.lds, st, d_items, i0, X,
+                                           Tb, act));
         DPP_LAUNCHED();
     }
     {
-        Launch L = xz_launch(i0.S0, i0.S2, fp64);
         TimerScope ts_(cx_, DPP_TK_XZ_H, b2);
-        DPP_NT_DISPATCH(L.threads, auto k = k_xz<T, XZ_H, double2, NT_, true>; DPP_TRY(set_lds(k, L.lds));
-                        hipLaunchKernelGGL(k, dim3(i0.S1, nbm, nit), dim3(NT_), L.lds, st, d_items, i0, Tb, V,
-                                           (double2*)nullptr));
+        DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz<T, XZ_H, double2, NT_, true>; DPP_TRY(set_lds(k, bs.xz.lds));
+                        hipLaunchKernelGGL(k, dim3(bs.maxS1, bs.nbm, nit), dim3(NT_), bs.xz.lds, st, d_items, i0, Tb,
+                                           V, (double2*)nullptr, act));
         DPP_LAUNCHED();
     }
     {
-        Launch L = plane_launch(i0.S1, i0.S2, fp64);
         TimerScope ts_(cx_, DPP_TK_PLANES_OUT, b3);
-        DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_, true>;
-                        DPP_TRY(set_lds(k, L.lds));
-                        hipLaunchKernelGGL(k, dim3(maxP, nbm, nit), dim3(NT_), L.lds, st, d_items, i0,
-                                           (const Cx*)Tb, X, HX, (int64_t)0));
+        DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_, true>;
+                        DPP_TRY(set_lds(k, bs.plane.lds));
+                        hipLaunchKernelGGL(k, dim3(bs.maxP, bs.nbm, nit), dim3(NT_), bs.plane.lds, st, d_items, i0,
+                                           (const Cx*)Tb, X, HX, (int64_t)0, act));
         DPP_LAUNCHED();
     }
     return DPP_OK;
 }
 template dpp_status apply_H_local_batched<double>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
-                                                  const double2*, double2*, const double*, void*);
+                                                  const double2*, double2*, const double*, void*, const int*);
 template dpp_status apply_H_local_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
-                                                 const double2*, double2*, const double*, void*);
+                                                 const double2*, double2*, const double*, void*, const int*);
 
-// n += sum over items of w_k sum_b f_b |I psi_b|^2; partials: nit * nch boxes.
 template <typename T>
 dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,
-                           const double2* psi, const double* fill, double* n, void* Tbv, double* part, int nch) {
+                           const double2* psi, const double* fill, void* Tbv, double* part,
+                           const CellDesc* d_cells, int ncells, int64_t maxN, double* n) {
     using Cx = typename cx<T>::t;
+    if (h.empty()) return DPP_OK;
     Cx* Tb = reinterpret_cast<Cx*>(Tbv);
     hipStream_t st = cx_->stream;
     const bool fp64 = sizeof(T) == 8;
-    int maxP = 0, nbm = 0;
+    const BatchShape bs = batch_shape(h, fp64);
     double b1 = 0, b2 = 0;
-    const FftItem& i0 = h[0];
-    const int64_t N = (int64_t)i0.S0 * i0.S1 * i0.S2;
+    int mch = 1;
     for (const FftItem& it : h) {
-        maxP = std::max(maxP, it.nplanes);
-        nbm = std::max(nbm, it.nb);
         const double pl = (double)it.nplanes * it.S1 * it.S2;
         b1 += it.nb * (16.0 * it.npw + sizeof(Cx) * pl);
-        b2 += it.nb * sizeof(Cx) * pl + nch * 8.0 * N;
+        b2 += it.nb * sizeof(Cx) * pl + it.dnch * 8.0 * it.S0 * it.S1 * it.S2;
+        mch = std::max(mch, it.dnch);
     }
+    const FftItem& i0 = h[0];
     const unsigned nit = (unsigned)h.size();
-    const int chunk = (nbm + nch - 1) / nch;
     {
-        Launch L = plane_launch(i0.S1, i0.S2, fp64);
         TimerScope ts_(cx_, DPP_TK_PLANES_IN, b1);
-        DPP_NT_DISPATCH(L.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>; DPP_TRY(set_lds(k, L.lds));
-                        hipLaunchKernelGGL(k, dim3(maxP, nbm, nit), dim3(NT_), L.lds, st, d_items, i0, psi, Tb));
+        DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>;
+                        DPP_TRY(set_lds(k, bs.plane.lds));
+                        hipLaunchKernelGGL(k, dim3(bs.maxP, bs.nbm, nit), dim3(NT_), bs.plane.lds, st, d_items, i0,
+                                           psi, Tb, (const int*)nullptr));
         DPP_LAUNCHED();
     }
     {
-        Launch L = xz_launch(i0.S0, i0.S2, fp64);
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, b2);
-        DPP_NT_DISPATCH(L.threads, auto k = k_xz_density<T, NT_, true>; DPP_TRY(set_lds(k, L.lds));
-                        hipLaunchKernelGGL(k, dim3(i0.S1, nch, nit), dim3(NT_), L.lds, st, d_items, i0,
-                                           (const Cx*)Tb, fill, chunk, part));
+        DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz_density<T, NT_, true>; DPP_TRY(set_lds(k, bs.xz.lds));
+                        hipLaunchKernelGGL(k, dim3(bs.maxS1, mch, nit), dim3(NT_), bs.xz.lds, st, d_items, i0,
+                                           (const Cx*)Tb, fill, part));
         DPP_LAUNCHED();
     }
     TimerScope ts_(cx_, DPP_TK_FIELDS);
-    hipLaunchKernelGGL(k_density_reduce, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, (const double*)part,
-                       (int)(nit * nch), N, n);
+    hipLaunchKernelGGL(k_density_reduce_cells, dim3((unsigned)((maxN + 255) / 256), (unsigned)ncells), dim3(256), 0,
+                       st, (const double*)part, d_cells, n);
     DPP_LAUNCHED();
     return DPP_OK;
 }
 template dpp_status density_batched<double>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&, const double2*,
-                                            const double*, double*, void*, double*, int);
+                                            const double*, void*, double*, const CellDesc*, int, int64_t, double*);
 template dpp_status density_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&, const double2*,
-                                           const double*, double*, void*, double*, int);
+                                           const double*, void*, double*, const CellDesc*, int, int64_t, double*);
+
+// Per cell: E[c * stride] = (Omega / 2) sum of the cell's Hartree row partials.
+__global__ void k_hartree_energy_cells(const double* __restrict__ part, const CellDesc* __restrict__ cells,
+                                       int ncells, double* __restrict__ E, int E_stride) {
+    __shared__ double red[256];
+    const CellDesc c = cells[blockIdx.x];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < c.S1; i += 256) s += part[c.eoff + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) E[(int64_t)blockIdx.x * E_stride] = 0.5 * c.omega * red[0];
+}
+
+dpp_status hartree_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h, const double* n,
+                           double* VH, void* Tbv, double* epart, const CellDesc* d_cells, double* E, int E_stride) {
+    if (h.empty()) return DPP_OK;
+    double2* Tb = reinterpret_cast<double2*>(Tbv);
+    hipStream_t st = cx_->stream;
+    const BatchShape bs = batch_shape(h, true);
+    const unsigned nc = (unsigned)h.size();
+    const FftItem& i0 = h[0];
+    TimerScope ts_(cx_, DPP_TK_FULLBOX);
+    DPP_NT_DISPATCH(bs.plane.threads, auto kp = k_planes_from_box<double, true, NT_, true>;
+                    DPP_TRY(set_lds(kp, bs.plane.lds));
+                    hipLaunchKernelGGL(kp, dim3(bs.maxS0, 1, nc), dim3(NT_), bs.plane.lds, st, d_items, i0,
+                                       (const void*)n, (int64_t)0, -1, Tb));
+    DPP_LAUNCHED();
+    DPP_NT_DISPATCH(bs.xz.threads, auto kx = k_xz_hartree<NT_, true>; DPP_TRY(set_lds(kx, bs.xz.lds));
+                    hipLaunchKernelGGL(kx, dim3(bs.maxS1, 1, nc), dim3(NT_), bs.xz.lds, st, d_items, i0, Tb, epart));
+    DPP_LAUNCHED();
+    DPP_NT_DISPATCH(bs.plane.threads, auto kq = k_planes_to_box<double, true, NT_, true>;
+                    DPP_TRY(set_lds(kq, bs.plane.lds));
+                    hipLaunchKernelGGL(kq, dim3(bs.maxS0, 1, nc), dim3(NT_), bs.plane.lds, st, d_items, i0,
+                                       (const double2*)Tb, +1, 1.0, (void*)VH, (int64_t)0));
+    DPP_LAUNCHED();
+    hipLaunchKernelGGL(k_hartree_energy_cells, dim3(nc), dim3(256), 0, st, (const double*)epart, d_cells, (int)nc, E,
+                       E_stride);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
 
 }  // namespace dpp
 
@@ -749,7 +838,7 @@ dpp_status dpp::full_inverse_real(dpp_grid_s* g, const double2* coef, double* ou
                                        (int64_t)0));
     DPP_LAUNCHED();
     DPP_NT_DISPATCH(Lp.threads, auto kq = k_planes_to_box<double, true, NT_>; DPP_TRY(set_lds(kq, Lp.lds));
-                    hipLaunchKernelGGL(kq, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, it, (const double2*)Tb, +1,
+                    hipLaunchKernelGGL(kq, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, nullptr, it, (const double2*)Tb, +1,
                                        1.0, (void*)out, (int64_t)0));
     DPP_LAUNCHED();
     return DPP_OK;
@@ -825,7 +914,7 @@ static dpp_status full_transform(dpp_grid g, int nf, const double2* x, double2* 
     Launch Lx = xz_launch(it.S0, it.S2, true);
     for (int f = 0; f < nf; ++f) {
         DPP_NT_DISPATCH(Lp.threads, auto kp = k_planes_from_box<double, false, NT_>; DPP_TRY(set_lds(kp, Lp.lds));
-                        hipLaunchKernelGGL(kp, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, it,
+                        hipLaunchKernelGGL(kp, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, nullptr, it,
                                            (const void*)(x + (int64_t)f * g->N), (int64_t)0, sign, Tb));
         DPP_LAUNCHED();
         DPP_NT_DISPATCH(Lx.threads, auto kx = k_xz_full<double, NT_>; DPP_TRY(set_lds(kx, Lx.lds));
@@ -878,16 +967,14 @@ extern "C" dpp_status dpp_hartree(dpp_grid grid, const double* d_n, double* d_VH
     Launch Lp = plane_launch(it.S1, it.S2, true);
     Launch Lx = xz_launch(it.S0, it.S2, true);
     DPP_NT_DISPATCH(Lp.threads, auto kp = k_planes_from_box<double, true, NT_>; DPP_TRY(set_lds(kp, Lp.lds));
-                    hipLaunchKernelGGL(kp, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, it, (const void*)d_n,
+                    hipLaunchKernelGGL(kp, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, nullptr, it, (const void*)d_n,
                                        (int64_t)0, -1, Tb));
     DPP_LAUNCHED();
-    const double* B = grid->B;
     DPP_NT_DISPATCH(Lx.threads, auto kx = k_xz_hartree<NT_>; DPP_TRY(set_lds(kx, Lx.lds));
-                    hipLaunchKernelGGL(kx, dim3(it.S1, 1, 1), dim3(NT_), Lx.lds, st, it, Tb, B[0], B[1], B[2],
-                                       B[3], B[4], B[5], B[6], B[7], B[8], part));
+                    hipLaunchKernelGGL(kx, dim3(it.S1, 1, 1), dim3(NT_), Lx.lds, st, nullptr, it, Tb, part));
     DPP_LAUNCHED();
     DPP_NT_DISPATCH(Lp.threads, auto kq = k_planes_to_box<double, true, NT_>; DPP_TRY(set_lds(kq, Lp.lds));
-                    hipLaunchKernelGGL(kq, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, it, (const double2*)Tb, +1,
+                    hipLaunchKernelGGL(kq, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, nullptr, it, (const double2*)Tb, +1,
                                        1.0, (void*)d_VH, (int64_t)0));
     DPP_LAUNCHED();
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, part, it.S1, 0.5 * grid->omega, d_EH);
@@ -911,6 +998,9 @@ extern "C" dpp_status dpp_density_accumulate(dpp_basis basis, int nb, const dpp_
     const int nchunk = std::min(nb, DENS_CHUNKS);
     const int chunk = (nb + nchunk - 1) / nchunk;
     const int nch = (nb + chunk - 1) / chunk;
+    it.p_off = 0;
+    it.dnch = nch;
+    it.dchunk = chunk;
     const bool fp64 = prec == DPP_F64;
     // partials live after the plane buffer
     const size_t tbytes = plane_buffer_elems(basis, nb) * (fp64 ? 16 : 8);
@@ -922,13 +1012,13 @@ extern "C" dpp_status dpp_density_accumulate(dpp_basis basis, int nb, const dpp_
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, nb * 16.0 * it.nplanes * it.S1 * it.S2 + nch * 8.0 * N);
         DPP_NT_DISPATCH(Lx.threads, auto k = k_xz_density<double, NT_>; DPP_TRY(set_lds(k, Lx.lds));
                         hipLaunchKernelGGL(k, dim3(it.S1, nch, 1), dim3(NT_), Lx.lds, st, nullptr, it,
-                                           (const double2*)ws, d_f, chunk, part));
+                                           (const double2*)ws, d_f, part));
     } else {
         DPP_TRY((pass1<float, double2>(cx_, it, (const double2*)psi, (float2*)ws)));
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, nb * 8.0 * it.nplanes * it.S1 * it.S2 + nch * 8.0 * N);
         DPP_NT_DISPATCH(Lx.threads, auto k = k_xz_density<float, NT_>; DPP_TRY(set_lds(k, Lx.lds));
                         hipLaunchKernelGGL(k, dim3(it.S1, nch, 1), dim3(NT_), Lx.lds, st, nullptr, it,
-                                           (const float2*)ws, d_f, chunk, part));
+                                           (const float2*)ws, d_f, part));
     }
     DPP_LAUNCHED();
     hipLaunchKernelGGL(k_density_reduce, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, part, nch,

@@ -91,6 +91,84 @@ __global__ void k_sum_fixed(const double* __restrict__ part, int n, double scale
     if (threadIdx.x == 0) *out = scale * red[0];
 }
 
+// ---------------------------------------------------------- many cells -----
+// Fields of several cells concatenated (cell c at foff, N points); one row of
+// CELL_RED_BLOCKS workgroups per cell, partial sums reduced per cell in fixed
+// order.
+constexpr int CELL_RED_BLOCKS = 256;
+
+__device__ __forceinline__ double block_sum_256(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_lda_cells(const CellDesc* __restrict__ cells, const double* __restrict__ n, double* __restrict__ vxc,
+            double* __restrict__ part) {
+    __shared__ double red[256];
+    const CellDesc c = cells[blockIdx.y];
+    double acc = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < c.N; j += (int64_t)CELL_RED_BLOCKS * 256) {
+        double e, v;
+        const double nj = n[c.foff + j];
+        lda_point(nj, &e, &v);
+        vxc[c.foff + j] = v;
+        acc += (nj >= N_FLOOR) ? nj * e : 0.0;
+    }
+    const double t = block_sum_256(acc, red);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * CELL_RED_BLOCKS + blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256)
+k_dot_cells(const CellDesc* __restrict__ cells, const double* __restrict__ a, const double* __restrict__ b,
+            double* __restrict__ part) {
+    __shared__ double red[256];
+    const CellDesc c = cells[blockIdx.y];
+    double acc = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < c.N; j += (int64_t)CELL_RED_BLOCKS * 256)
+        acc += a[c.foff + j] * b[c.foff + j];
+    const double t = block_sum_256(acc, red);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * CELL_RED_BLOCKS + blockIdx.x] = t;
+}
+
+// E[c * stride] = (Omega / N)_c * sum of the cell's partials.
+__global__ void __launch_bounds__(256)
+k_sum_cells(const CellDesc* __restrict__ cells, const double* __restrict__ part, double* __restrict__ E,
+            int stride) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < CELL_RED_BLOCKS; i += 256) s += part[(int64_t)blockIdx.x * CELL_RED_BLOCKS + i];
+    const double t = block_sum_256(s, red);
+    if (threadIdx.x == 0) E[(int64_t)blockIdx.x * stride] = cells[blockIdx.x].dV * t;
+}
+
+dpp_status lda_cells(dpp_ctx_s* ctx, const CellDesc* d_cells, int ncells, const double* n, double* vxc,
+                     double* part, double* E, int stride) {
+    TimerScope ts_(ctx, DPP_TK_FIELDS);
+    hipLaunchKernelGGL(k_lda_cells, dim3(CELL_RED_BLOCKS, ncells), dim3(256), 0, ctx->stream, d_cells, n, vxc, part);
+    DPP_LAUNCHED();
+    hipLaunchKernelGGL(k_sum_cells, dim3(ncells), dim3(256), 0, ctx->stream, d_cells, (const double*)part, E, stride);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+dpp_status dot_cells(dpp_ctx_s* ctx, const CellDesc* d_cells, int ncells, const double* a, const double* b,
+                     double* part, double* E, int stride) {
+    TimerScope ts_(ctx, DPP_TK_FIELDS);
+    hipLaunchKernelGGL(k_dot_cells, dim3(CELL_RED_BLOCKS, ncells), dim3(256), 0, ctx->stream, d_cells, a, b, part);
+    DPP_LAUNCHED();
+    hipLaunchKernelGGL(k_sum_cells, dim3(ncells), dim3(256), 0, ctx->stream, d_cells, (const double*)part, E, stride);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
+size_t cell_red_elems(int ncells) { return (size_t)ncells * CELL_RED_BLOCKS; }
+
 // Reciprocal-space field of atom-centred Gaussian-type terms on the full box:
 // mode 0 (local pseudopotential): sum_a -4 pi Z_a exp(-G^2 rc_a^2/4) / (Omega G^2), 0 at G = 0
 // mode 1 (start density):         sum_a Z_a exp(-G^2 sigma^2/4) / Omega

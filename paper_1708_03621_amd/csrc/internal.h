@@ -69,6 +69,24 @@ struct FftItem {
     double vscale;        // Omega / N
     double wk;            // k-point weight (density accumulation)
     int64_t f_off;        // offset of this item's fillings
+    int64_t p_off;        // offset (doubles) of this item's partial sums (density boxes, Hartree rows)
+    int dnch, dchunk;     // density: band chunks of this item and bands per chunk
+    double B[9];          // reciprocal basis, row-major (full-box items: Hartree kernel)
+};
+
+// One cell of a batch: where its fields sit in the concatenated field arrays
+// and which work items (k-points) and partial sums belong to it.
+struct CellDesc {
+    int64_t foff;         // offset (doubles) of the cell's fields
+    int64_t N;            // grid points
+    double omega, dV;     // volume and Omega / N
+    int item0, nitems;    // items (k-points) of the cell
+    int64_t pstart;       // first density partial (doubles) of the cell
+    int nparts;           // density partial boxes of the cell
+    int S1;               // rows of Hartree energy partials
+    int64_t eoff;         // offset of the Hartree energy partials
+    double D;             // projector coupling
+    double ne;            // electrons
 };
 
 // ------------------------------------------------------------ handles ------
@@ -163,13 +181,33 @@ size_t grid_coef_offset(const dpp_grid_s* g);
 
 // Batched passes over a table of items (one per k-point or cell/k pair);
 // h_items mirrors the device table d_items.  Tb holds every item's planes.
+// Items may have different boxes: the launch takes the largest workgroup and
+// LDS size any item needs.  `act` (nullable) masks items: inactive items do
+// nothing.
 template <typename T>
 dpp_status apply_H_local_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
-                                 const double2* X, double2* HX, const double* V, void* Tb);
+                                 const double2* X, double2* HX, const double* V, void* Tb,
+                                 const int* act = nullptr);
+// Band-chunk partial densities of every item (item p_off, dnch, dchunk), then
+// per cell n[foff + j] = sum of the cell's partials (fixed order).
 template <typename T>
 dpp_status density_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
-                           const double2* psi, const double* fill, double* n, void* Tb, double* part, int nch);
+                           const double2* psi, const double* fill, void* Tb, double* part,
+                           const CellDesc* d_cells, int ncells, int64_t maxN, double* n);
 size_t batched_plane_elems(const std::vector<FftItem>& h_items);
+// Hartree potential and energy of every cell: full-box items (one per cell,
+// v_off = field offset, t_off = plane offset, p_off = row-partial offset).
+dpp_status hartree_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
+                           const double* n, double* VH, void* Tb, double* epart, const CellDesc* d_cells,
+                           double* E, int E_stride);
+
+// Cell-batched field reductions (fields.hip): v_xc and E_xc per cell; the
+// grid dot (Omega / N) sum a b per cell.  `part` holds cell_red_elems doubles.
+dpp_status lda_cells(dpp_ctx_s* ctx, const CellDesc* d_cells, int ncells, const double* n, double* vxc,
+                     double* part, double* E, int stride);
+dpp_status dot_cells(dpp_ctx_s* ctx, const CellDesc* d_cells, int ncells, const double* a, const double* b,
+                     double* part, double* E, int stride);
+size_t cell_red_elems(int ncells);
 
 // Launch the local-potential H pipeline etc. (fft.hip)
 template <typename T>
@@ -191,7 +229,8 @@ struct OvTask {
     int npw, nbA, nbB, out_ld;
     double scale;
     int64_t part_off;  // complex elements into the partial buffer
-    int nchunk, tilesB, ntiles, pad;
+    int nchunk, tilesB, ntiles;
+    int item;          // work item (index into an activity mask)
 };
 // out = beta * out + X M (M: nbX x nbO row-major with row length M_ld)
 struct RotTask {
@@ -201,13 +240,19 @@ struct RotTask {
     int64_t ldX, ldout;
     int npw, nbX, nbO, M_ld;
     double beta;
+    int item;          // work item (index into an activity mask)
+    int pad;
 };
 OvTask make_ov_task(int npw, int nbA, const double2* A, int64_t ldA, int nbB, const double2* B, int64_t ldB,
                     double scale, double2* out, int out_ld);
 RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, const double2* M, int M_ld,
                       double beta, double2* out, int64_t ldout);
-dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part);
-dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks);
+// Batched contractions over a device task table; `act` (nullable) masks
+// tasks by their work item: tasks of inactive items do nothing.
+dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
+                         const int* act = nullptr);
+dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks,
+                        const int* act = nullptr);
 dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
                        const double2* B, int64_t ldB, double scale, double2* U, void* ws,
                        size_t ws_bytes);

@@ -20,6 +20,7 @@ DPP_F64 = 0
 DPP_F32 = 1
 DPP_STATUS_NOTPD = 1
 DPP_STATUS_NONFINITE = 2
+DPP_STATUS_NOBANDS = 4
 
 STATUS_NAMES = {0: "DPP_OK", -1: "DPP_EINVAL", -2: "DPP_ENOMEM", -3: "DPP_EDEVICE", -4: "DPP_ENOTPD",
                 -5: "DPP_ENOCONV", -6: "DPP_EUNSUPPORTED"}
@@ -102,6 +103,11 @@ SIGNATURES = {
     "dpp_start_density": [_vp, _i, _dp, _dp, _d, _vp, _vp],
     "dpp_grid_dot": [_vp, _vp, _vp, _d, _vp, _vp],
     "dpp_system_create": [_vp, C.POINTER(dpp_system_desc), C.POINTER(_vp)],
+    "dpp_batch_create": [_vp, _i, C.POINTER(dpp_system_desc), C.POINTER(_vp)],
+    "dpp_system_dims": [_vp, _ip, _ip, _i64p, _i64p, _i64p],
+    "dpp_system_cells": [_vp, _ip, _i64p, _i64p],
+    "dpp_set_graph_mode": [_vp, _i],
+    "dpp_scf_cell_residuals": [_vp, _dp],
     "dpp_system_destroy": [_vp],
     "dpp_system_layout": [_vp, _i64p, _i64p],
     "dpp_system_field": [_vp, _i, C.POINTER(_vp)],
@@ -134,7 +140,8 @@ SIGNATURES = {
 }
 
 TIMER_KINDS = {"planes_in": 0, "xz_h": 1, "planes_out": 2, "xz_density": 3, "overlap": 4, "rotate": 5,
-               "cholesky": 6, "eigh": 7, "fullbox": 8, "fields": 9, "blockops": 10, "xz_io": 11, "net": 12}
+               "cholesky": 6, "eigh": 7, "fullbox": 8, "fields": 9, "blockops": 10, "xz_io": 11, "net": 12,
+               "linesearch": 13}
 
 
 def load(path: str = LIB_PATH):
@@ -369,36 +376,82 @@ def dpp_grid_dot(grid, d_a, d_b, scale, d_out, ws):
 
 # --------------------------------------------------------------- drivers ----
 
+def _system_desc(keep, R, S, ecut, kpts, wk, nb, n_electrons, tau, Z, rc, has_proj, rp, D, prec):
+    def arr(a, dt):
+        keep.append(np.ascontiguousarray(np.asarray(a, dtype=dt).reshape(-1)))
+        return keep[-1]
+
+    Ra = arr(np.asarray(R, float).reshape(3, 3), np.float64)
+    Sa = arr(S, np.int32)
+    ka = arr(kpts, np.float64)
+    wa = arr(wk, np.float64)
+    ta = arr(tau, np.float64)
+    Za = arr(Z, np.float64)
+    ra = arr(rc, np.float64)
+    ha = arr(has_proj, np.int32)
+    return dpp_system_desc(Ra.ctypes.data_as(_dp), Sa.ctypes.data_as(_ip), float(ecut), len(wa), ka.ctypes.data_as(_dp),
+                           wa.ctypes.data_as(_dp), int(nb), float(n_electrons), len(Za), ta.ctypes.data_as(_dp),
+                           Za.ctypes.data_as(_dp), ra.ctypes.data_as(_dp), ha.ctypes.data_as(_ip), float(rp), float(D),
+                           int(prec))
+
+
 def dpp_system_create(ctx, R, S, ecut, kpts, wk, nb, n_electrons, tau, Z, rc, has_proj, rp, D, prec=DPP_F64):
-    """Host arrays are copied into a keep-alive dict for the duration of the call."""
-    keep = {}
-
-    def arr(name, a, dt):
-        keep[name] = np.ascontiguousarray(np.asarray(a, dtype=dt).reshape(-1))
-        return keep[name]
-
-    Ra = arr("R", np.asarray(R, float).reshape(3, 3), np.float64)
-    Sa = arr("S", S, np.int32)
-    ka = arr("k", kpts, np.float64)
-    wa = arr("w", wk, np.float64)
-    ta = arr("tau", tau, np.float64)
-    Za = arr("Z", Z, np.float64)
-    ra = arr("rc", rc, np.float64)
-    ha = arr("hp", has_proj, np.int32)
-    d = dpp_system_desc(Ra.ctypes.data_as(_dp), Sa.ctypes.data_as(_ip), float(ecut), len(wa), ka.ctypes.data_as(_dp),
-                        wa.ctypes.data_as(_dp), int(nb), float(n_electrons), len(Za), ta.ctypes.data_as(_dp),
-                        Za.ctypes.data_as(_dp), ra.ctypes.data_as(_dp), ha.ctypes.data_as(_ip), float(rp), float(D),
-                        int(prec))
+    """Host arrays are kept alive for the duration of the call."""
+    keep = []
+    d = _system_desc(keep, R, S, ecut, kpts, wk, nb, n_electrons, tau, Z, rc, has_proj, rp, D, prec)
     out = _vp()
     _call("dpp_system_create", ctx, C.byref(d), C.byref(out))
     return out
+
+
+def dpp_batch_create(ctx, cells, prec=DPP_F64):
+    """cells: list of dicts with the dpp_system_create arguments R, S, ecut,
+    kpts, wk, nb, n_electrons, tau, Z, rc, has_proj, rp, D."""
+    keep = []
+    arr = (dpp_system_desc * len(cells))()
+    for i, c in enumerate(cells):
+        arr[i] = _system_desc(keep, c["R"], c["S"], c["ecut"], c["kpts"], c["wk"], c["nb"], c["n_electrons"],
+                              c["tau"], c["Z"], c["rc"], c["has_proj"], c["rp"], c["D"], prec)
+    out = _vp()
+    _call("dpp_batch_create", ctx, len(cells), arr, C.byref(out))
+    return out
+
+
+def dpp_system_dims(sys_):
+    nc, ni = C.c_int(), C.c_int()
+    tot, ns, ng = C.c_int64(), C.c_int64(), C.c_int64()
+    _call("dpp_system_dims", sys_, C.byref(nc), C.byref(ni), C.byref(tot), C.byref(ns), C.byref(ng))
+    return nc.value, ni.value, tot.value, ns.value, ng.value
+
+
+def dpp_system_cells(sys_):
+    nc = dpp_system_dims(sys_)[0]
+    item0 = np.zeros(nc + 1, np.int32)
+    foff = np.zeros(nc + 1, np.int64)
+    state0 = np.zeros(nc + 1, np.int64)
+    _call("dpp_system_cells", sys_, item0.ctypes.data_as(_ip), foff.ctypes.data_as(_i64p),
+          state0.ctypes.data_as(_i64p))
+    return item0, foff, state0
+
+
+def dpp_set_graph_mode(sys_, on=True):
+    _call("dpp_set_graph_mode", sys_, 1 if on else 0)
+
+
+def dpp_scf_cell_residuals(sys_):
+    r = np.zeros(dpp_system_dims(sys_)[0])
+    _call("dpp_scf_cell_residuals", sys_, r.ctypes.data_as(_dp))
+    return r
 
 
 def dpp_system_destroy(sys_):
     _call("dpp_system_destroy", sys_)
 
 
-def dpp_system_layout(sys_, nk):
+def dpp_system_layout(sys_, nk=None):
+    """Offsets (nitems + 1) and npw (nitems) of the packed layout."""
+    if nk is None:
+        nk = dpp_system_dims(sys_)[1]
     off = (C.c_int64 * (nk + 1))()
     npw = (C.c_int64 * nk)()
     _call("dpp_system_layout", sys_, C.cast(off, _i64p), C.cast(npw, _i64p))
@@ -447,25 +500,39 @@ def dpp_band_eigenvalues(sys_, Y, nk, nb):
     return e
 
 
-def dpp_scf_init(sys_, tau=None, Z=None, sigma=1.0, d_n_start=None, n_inner=3, n_inner_first=0):
+def dpp_scf_init(sys_, tau=None, Z=None, sigma=1.0, d_n_start=None, n_inner=3, n_inner_first=0, cells=None):
+    """One cell (tau, Z or d_n_start) or, with `cells`, a list of dicts with
+    keys tau, Z, sigma, d_n_start (any may be absent) for every cell."""
     keep = []
-    start = None if d_n_start is None else C.c_void_p(d_n_start.data_ptr())
-    if tau is not None:
-        ta = np.ascontiguousarray(np.asarray(tau, float).reshape(-1))
-        Za = np.ascontiguousarray(np.asarray(Z, float).reshape(-1))
-        keep += [ta, Za]
-        d = dpp_scf_desc(len(Za), ta.ctypes.data_as(_dp), Za.ctypes.data_as(_dp), float(sigma), start, int(n_inner),
-                         int(n_inner_first))
-    else:
-        d = dpp_scf_desc(0, None, None, float(sigma), start, int(n_inner), int(n_inner_first))
-    _call("dpp_scf_init", sys_, C.byref(d))
+
+    def desc(tau_, Z_, sigma_, start_):
+        sp = None if start_ is None else C.c_void_p(start_.data_ptr())
+        if tau_ is not None:
+            ta = np.ascontiguousarray(np.asarray(tau_, float).reshape(-1))
+            Za = np.ascontiguousarray(np.asarray(Z_, float).reshape(-1))
+            keep.extend([ta, Za])
+            return dpp_scf_desc(len(Za), ta.ctypes.data_as(_dp), Za.ctypes.data_as(_dp), float(sigma_), sp,
+                                int(n_inner), int(n_inner_first))
+        return dpp_scf_desc(0, None, None, float(sigma_), sp, int(n_inner), int(n_inner_first))
+
+    if cells is None:
+        cells = [dict(tau=tau, Z=Z, sigma=sigma, d_n_start=d_n_start)]
+    arr = (dpp_scf_desc * len(cells))()
+    for i, c in enumerate(cells):
+        arr[i] = desc(c.get("tau"), c.get("Z"), c.get("sigma", sigma), c.get("d_n_start"))
+    _call("dpp_scf_init", sys_, arr)
 
 
-def dpp_scf_iteration(sys_, Y, nk, nb):
-    E = dpp_energy()
-    e = np.zeros((nk, nb))
-    _call("dpp_scf_iteration", sys_, _ptr(Y), C.byref(E), e.ctypes.data_as(_dp))
-    return E.as_dict(), e
+def dpp_scf_iteration(sys_, Y, nk=None, nb=None):
+    """One cell with nk, nb given: (energy dict, eig (nk, nb)).  Otherwise:
+    (list of energy dicts per cell, eig over all states)."""
+    ncells, _, _, nstates, _ = dpp_system_dims(sys_)
+    E = (dpp_energy * ncells)()
+    e = np.zeros(nstates)
+    _call("dpp_scf_iteration", sys_, _ptr(Y), E, e.ctypes.data_as(_dp))
+    if ncells == 1 and nk is not None and nb is not None:
+        return E[0].as_dict(), e.reshape(nk, nb)
+    return [x.as_dict() for x in E], e
 
 
 def dpp_system_fillings(sys_, nk, nb):

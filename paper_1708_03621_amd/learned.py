@@ -1,14 +1,15 @@
 """Learned initial density for SCF (form 4), driven through the C ABI.
 
 Pipeline:
-  1. training data: for each training geometry, the superposition start
-     density n0 and the converged density n_conv from the library's own SCF;
+  1. training data: the superposition start density n0 and the converged
+     density n_conv of every training geometry, from the library's own SCF
+     (cells run together as batches: one launch per pass for the whole batch);
   2. training: the library's network kernels (forward, backward, Adam) on
      the resident (n0, n_conv) pairs;
-  3. evaluation: on held-out geometries, SCF iterations until the energy
-     stays within 1e-6 Ha/atom of the converged energy, starting from the
-     superposition density and from the learned density; the converged
-     energies of both starts must agree.
+  3. evaluation: on held-out geometries, SCF from the superposition density
+     and from the learned density; per cell the number of iterations after
+     which the energy stays within 1e-6 Ha/atom of the plain start's final
+     energy, and the difference of the two final energies.
 
 Every numerical step runs in libdftpp; this module sequences the calls.
 Usage: python -m paper_1708_03621_amd.learned --train 512 --eval 64
@@ -28,50 +29,66 @@ def _log(msg):
 
 
 class Runner:
-    def __init__(self, D, torch, ctx, n_inner=3, n_inner_first=3):
+    """SCF of a list of cells as one batch system (graph replay after the
+    first iteration)."""
+
+    def __init__(self, D, torch, ctx, n_inner=3, n_inner_first=3, graph=True):
         self.D, self.torch, self.ctx = D, torch, ctx
         self.dev = torch.device("cuda:0")
-        self.n_inner, self.n_inner_first = n_inner, n_inner_first
+        self.n_inner, self.n_inner_first, self.graph = n_inner, n_inner_first, graph
 
-    def system(self, cell):
+    def system(self, cells):
         import workloads as W
         D = self.D
-        s = D.dpp_system_create(self.ctx, cell.R, cell.S, cell.ecut, cell.kpts, cell.wk, cell.nb, cell.n_electrons,
-                                cell.tau, cell.Z.astype(float), cell.rc, cell.has_proj.astype(int), W.PROJ_RP,
-                                W.PROJ_D, D.DPP_F64)
-        off, npw = D.dpp_system_layout(s, len(cell.kpts))
-        blocks = W.initial_wavefunctions(cell.y0_seed, [(cell.nb, n) for n in npw])
+        descs = [dict(R=c.R, S=c.S, ecut=c.ecut, kpts=c.kpts, wk=c.wk, nb=c.nb, n_electrons=c.n_electrons, tau=c.tau,
+                      Z=c.Z.astype(float), rc=c.rc, has_proj=c.has_proj.astype(int), rp=W.PROJ_RP, D=W.PROJ_D)
+                 for c in cells]
+        s = D.dpp_batch_create(self.ctx, descs, D.DPP_F64)
+        D.dpp_set_graph_mode(s, self.graph)
+        off, npw = D.dpp_system_layout(s)
+        item0, foff, _ = D.dpp_system_cells(s)
+        blocks = []
+        for ci, c in enumerate(cells):
+            blocks += W.initial_wavefunctions(c.y0_seed, [(c.nb, npw[k]) for k in range(item0[ci], item0[ci + 1])])
         Y = self.torch.from_numpy(np.concatenate([b.reshape(-1) for b in blocks])).to(self.dev)
-        return s, Y
+        return s, Y, foff
 
-    def start_density(self, cell):
+    def start_densities(self, cells):
+        """Superposition start densities of the cells, (ncells, S0, S1, S2)."""
         import workloads as W
         D = self.D
-        g = D.dpp_grid_create(self.ctx, cell.R, cell.S)
-        ws = self.torch.empty(D.dpp_grid_workspace_size(g), dtype=self.torch.uint8, device=self.dev)
-        n0 = self.torch.empty(tuple(cell.S), dtype=self.torch.float64, device=self.dev)
-        D.dpp_start_density(g, cell.tau, cell.Z.astype(float), W.START_SIGMA, n0, ws)
+        s, _, foff = self.system(cells)
+        D.dpp_scf_init(s, cells=[dict(tau=c.tau, Z=c.Z, sigma=W.START_SIGMA) for c in cells])
+        n0 = self.torch.empty(int(foff[-1]), dtype=self.torch.float64, device=self.dev)
+        D.dpp_system_copy_field(s, D.DPP_FIELD_NIN, n0)
         self.torch.cuda.synchronize()
-        D.dpp_grid_destroy(g)
-        return n0
+        D.dpp_system_destroy(s)
+        return n0.view((len(cells),) + tuple(cells[0].S))
 
-    def scf(self, cell, n_start, max_iter=80, tol_atom=1e-10):
-        """SCF from a device start density; returns energies and the last n_out."""
+    def scf(self, cells, n_start, max_iter=80, tol_atom=1e-10):
+        """SCF of all cells from device start densities (ncells, S...);
+        returns energies (iterations, ncells) and the last n_out per cell.
+        Stops once every cell changed by less than tol_atom per atom in two
+        consecutive iterations."""
         D = self.D
-        s, Y = self.system(cell)
-        D.dpp_scf_init(s, d_n_start=n_start, n_inner=self.n_inner, n_inner_first=self.n_inner_first)
-        nk = len(cell.kpts)
+        s, Y, _ = self.system(cells)
+        D.dpp_scf_init(s, cells=[dict(d_n_start=n_start[i]) for i in range(len(cells))],
+                       n_inner=self.n_inner, n_inner_first=self.n_inner_first)
+        nat = np.array([c.nat for c in cells])
         E = []
         for it in range(max_iter):
-            e, _ = D.dpp_scf_iteration(s, Y, nk, cell.nb)
-            E.append(e["E_el"])
-            if it >= 2 and abs(E[-1] - E[-2]) / cell.nat < tol_atom and abs(E[-2] - E[-3]) / cell.nat < tol_atom:
-                break
-        nout = self.torch.empty(tuple(cell.S), dtype=self.torch.float64, device=self.dev)
+            e, _ = D.dpp_scf_iteration(s, Y)
+            E.append([x["E_el"] for x in e])
+            if it >= 2:
+                a = np.abs(np.array(E[-1]) - np.array(E[-2])) / nat
+                b = np.abs(np.array(E[-2]) - np.array(E[-3])) / nat
+                if np.all(a < tol_atom) and np.all(b < tol_atom):
+                    break
+        nout = self.torch.empty(n_start.shape, dtype=self.torch.float64, device=self.dev)
         D.dpp_system_copy_field(s, D.DPP_FIELD_NOUT, nout)
         self.torch.cuda.synchronize()
         D.dpp_system_destroy(s)
-        return E, nout
+        return np.array(E), nout
 
 
 def iterations_to(E, E_ref, nat, tol=1e-6):
@@ -82,7 +99,8 @@ def iterations_to(E, E_ref, nat, tol=1e-6):
     return None
 
 
-def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, seed=502, log=_log):
+def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, seed=502, max_iter=80,
+        scf_batch=64, log=_log):
     import torch
 
     import workloads as W
@@ -98,16 +116,16 @@ def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, se
     nbar = ne / omega
     t0 = time.time()
     n0s, ncs, scf_iters = [], [], []
-    for i, cell in enumerate(train):
-        n0 = R.start_density(cell)
-        E, nc = R.scf(cell, n0)
+    for i in range(0, len(train), scf_batch):
+        cells = train[i:i + scf_batch]
+        n0 = R.start_densities(cells)
+        E, nc = R.scf(cells, n0, max_iter=max_iter)
         n0s.append(n0)
         ncs.append(nc)
         scf_iters.append(len(E))
-        if (i + 1) % 32 == 0:
-            log(f"training data {i + 1}/{len(train)}")
-    n0_all = torch.stack(n0s).contiguous()
-    nc_all = torch.stack(ncs).contiguous()
+        log(f"training data {i + len(cells)}/{len(train)} ({len(E)} SCF iterations)")
+    n0_all = torch.cat(n0s).contiguous()
+    nc_all = torch.cat(ncs).contiguous()
     t_data = time.time() - t0
     net = D.dpp_net_create(ctx, S, batch)
     D.dpp_net_set_params(net, W.net_flatten(W.net_init_params(501)))
@@ -121,27 +139,33 @@ def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, se
             log(f"epoch {ep + 1}: loss {losses[-1]:.3e}")
     torch.cuda.synchronize()
     t_train = time.time() - t1
-    # held-out evaluation
+    # held-out evaluation: the same cells from both starts
     rows = []
-    for cell in evals:
-        n0 = R.start_density(cell)
-        Ep, nconv = R.scf(cell, n0)
+    t2 = time.time()
+    for i in range(0, len(evals), scf_batch):
+        cells = evals[i:i + scf_batch]
+        n0 = R.start_densities(cells)
         nl = torch.empty_like(n0)
-        D.dpp_net_predict_density(net, n0, ne, omega, nl)
-        El, _ = R.scf(cell, nl)
-        E_ref = Ep[-1]
-        l1 = float(torch.sum(torch.abs(nconv)))
-        rows.append(dict(plain=iterations_to(Ep, E_ref, cell.nat), learned=iterations_to(El, E_ref, cell.nat),
-                         dE_per_atom=abs(El[-1] - Ep[-1]) / cell.nat, E=Ep[-1],
-                         start_err_plain=float(torch.sum(torch.abs(n0 - nconv))) / l1,
-                         start_err_learned=float(torch.sum(torch.abs(nl - nconv))) / l1))
+        for j in range(len(cells)):
+            D.dpp_net_predict_density(net, n0[j], ne, omega, nl[j])
+        Ep, nconv = R.scf(cells, n0, max_iter=max_iter)
+        El, _ = R.scf(cells, nl, max_iter=max_iter)
+        for j, c in enumerate(cells):
+            E_ref = Ep[-1, j]
+            l1 = float(torch.sum(torch.abs(nconv[j])))
+            rows.append(dict(plain=iterations_to(Ep[:, j], E_ref, c.nat),
+                             learned=iterations_to(El[:, j], E_ref, c.nat),
+                             dE_per_atom=abs(El[-1, j] - Ep[-1, j]) / c.nat, E=E_ref,
+                             start_err_plain=float(torch.sum(torch.abs(n0[j] - nconv[j]))) / l1,
+                             start_err_learned=float(torch.sum(torch.abs(nl[j] - nconv[j]))) / l1))
+    t_eval = time.time() - t2
     D.dpp_net_destroy(net)
     ip = [r["plain"] for r in rows if r["plain"]]
     il = [r["learned"] for r in rows if r["learned"]]
-    return dict(n_train=len(train), n_eval=len(evals), epochs=epochs, batch=batch, lr=lr,
-                n_inner=3, n_inner_first=n_inner_first,
-                loss_first=losses[0], loss_last=losses[-1], train_data_s=t_data, train_s=t_train,
-                scf_iters_train_mean=float(np.mean(scf_iters)),
+    return dict(n_train=len(train), n_eval=len(evals), nb=train[0].nb, epochs=epochs, batch=batch, lr=lr,
+                n_inner=3, n_inner_first=n_inner_first, max_iter=max_iter,
+                loss_first=losses[0], loss_last=losses[-1], train_data_s=t_data, train_s=t_train, eval_s=t_eval,
+                scf_iters_train_batches=scf_iters,
                 iters_plain_mean=float(np.mean(ip)) if ip else None,
                 iters_learned_mean=float(np.mean(il)) if il else None,
                 start_err_plain_mean=float(np.mean([r["start_err_plain"] for r in rows])),
@@ -155,9 +179,12 @@ def main():
     ap.add_argument("--eval", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--first", type=int, default=3, help="band-CG steps of the first SCF iteration")
+    ap.add_argument("--max-iter", type=int, default=80)
+    ap.add_argument("--scf-batch", type=int, default=64, help="cells per batched SCF system")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
-    res = run(args.train, args.eval, args.epochs, n_inner_first=args.first)
+    res = run(args.train, args.eval, args.epochs, n_inner_first=args.first, max_iter=args.max_iter,
+              scf_batch=args.scf_batch)
     js = json.dumps(res)
     if args.out:
         with open(args.out, "w") as fh:

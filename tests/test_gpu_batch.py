@@ -1,0 +1,138 @@
+"""GPU parity of many-cell batches (form 2).
+
+One system holds cells with different boxes, sphere sizes, band counts,
+k-point sets and electron counts (odd ones included); every SCF iteration
+runs as single launches over all (cell, k-point) items.  Checks:
+  * each cell's SCF trajectory equals the FP64 oracle's (1e-8 Ha/atom) and
+    the trajectory of the same cell run as a system of its own;
+  * graph replay gives exactly the eager results (same kernels, same order);
+  * the 48-cell batched-throughput workload runs in FP32 bulk precision under
+    graph replay, and sampled cells equal their own single-cell runs.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import energy as oe, scf as oscf
+from tests._gpu import Device, log
+
+pytestmark = pytest.mark.gpu
+TOL_ATOM = 1e-8
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return Device()
+
+
+def _mixed_cells():
+    """Small cells of different shapes: 1 and 4 k-points, 3-5 bands, boxes
+    12^3 to 16x15x18, a non-cubic cell, odd and even electron counts, with and
+    without projectors, plus the two smallest one-k-point config-4 cells."""
+    cells = [
+        W.tiny_cell(nat=2, L=6.0, ecut=3.0, S=(12, 12, 12), nb=3, Z=(1, 1), seed=7),
+        W.tiny_cell(nat=3, L=7.0, ecut=3.5, S=(16, 15, 18), nb=5, Z=(4, 1, 4), fold=(2, 1, 2),
+                    R=np.array([[7.0, 0.5, 0.0], [0.0, 6.6, 0.7], [0.4, 0.0, 7.3]]), seed=31),
+        W.tiny_cell(nat=2, L=6.5, ecut=3.0, S=(15, 15, 15), nb=4, Z=(4, 4), fold=(1, 2, 1), seed=13),
+    ]
+    c4 = [c for c in W.config4() if len(c.kpts) == 1]
+    c4.sort(key=lambda c: (c.S[0], c.nb * c.nat))
+    return cells + c4[:2]
+
+
+def _desc(cell):
+    return dict(R=cell.R, S=cell.S, ecut=cell.ecut, kpts=cell.kpts, wk=cell.wk, nb=cell.nb,
+                n_electrons=cell.n_electrons, tau=cell.tau, Z=cell.Z.astype(float), rc=cell.rc,
+                has_proj=cell.has_proj.astype(int), rp=W.PROJ_RP, D=W.PROJ_D)
+
+
+def _batch(dev, cells, prec=0):
+    D = dev.D
+    s = D.dpp_batch_create(dev.ctx, [_desc(c) for c in cells], prec)
+    off, npw = D.dpp_system_layout(s)
+    item0, foff, state0 = D.dpp_system_cells(s)
+    blocks = []
+    for ci, c in enumerate(cells):
+        ks = range(item0[ci], item0[ci + 1])
+        blocks += W.initial_wavefunctions(c.y0_seed, [(c.nb, npw[k]) for k in ks])
+    Y = dev.tensor(np.concatenate([b.reshape(-1) for b in blocks]))
+    return s, Y, (off, npw, item0, foff, state0)
+
+
+def _run(dev, s, Y, cells, nit, graph=False):
+    D = dev.D
+    D.dpp_set_graph_mode(s, graph)
+    D.dpp_scf_init(s, cells=[dict(tau=c.tau, Z=c.Z, sigma=W.START_SIGMA) for c in cells])
+    E, eig = [], None
+    for _ in range(nit):
+        e, eig = D.dpp_scf_iteration(s, Y)
+        E.append([x["E_el"] for x in e])
+    return np.array(E), eig
+
+
+def test_batch_scf_matches_oracle_and_single_cells(dev):
+    cells = _mixed_cells()
+    nit = 4
+    log("batch: " + ", ".join(f"{c.name} S={c.S} nk={len(c.kpts)} nb={c.nb} ne={c.n_electrons}" for c in cells))
+    s, Y, _ = _batch(dev, cells)
+    Eb, _ = _run(dev, s, Y, cells, nit)
+    dev.D.dpp_system_destroy(s)
+    for ci, c in enumerate(cells):
+        so = oe.build_system(c)
+        Ys = W.initial_wavefunctions(c.y0_seed, [(c.nb, b.npw) for b in so.bases])
+        res = oscf.scf(so, [y.T.copy() for y in Ys], oe.start_density(c, W.START_SIGMA), nit)
+        err = np.max(np.abs(Eb[:, ci] - np.array(res["energies"]))) / c.nat
+        log(f"{c.name}: batch {Eb[-1, ci]:.12f} oracle {res['energies'][-1]:.12f} err/atom {err:.2e}")
+        assert err < TOL_ATOM
+        # the same cell as a system of its own
+        s1, Y1, _ = _batch(dev, [c])
+        E1, _ = _run(dev, s1, Y1, [c], nit)
+        dev.D.dpp_system_destroy(s1)
+        assert np.max(np.abs(E1[:, 0] - Eb[:, ci])) / c.nat < 1e-10
+
+
+def test_graph_replay_equals_eager(dev):
+    cells = _mixed_cells()[:3]
+    out = {}
+    for graph in (False, True):
+        s, Y, _ = _batch(dev, cells)
+        E, eig = _run(dev, s, Y, cells, 6, graph=graph)
+        out[graph] = (E, eig, dev.host(Y))
+        dev.D.dpp_system_destroy(s)
+    log(f"eager {out[False][0][-1]} graph {out[True][0][-1]}")
+    assert np.array_equal(out[False][0], out[True][0])
+    assert np.array_equal(out[False][1], out[True][1])
+    assert np.array_equal(out[False][2], out[True][2])
+
+
+def test_graph_replay_config2_mixed(dev):
+    """Config 2 in FP32 bulk precision: graph replay equals eager execution."""
+    cell = W.config2()
+    out = {}
+    for graph in (False, True):
+        s, Y, _ = _batch(dev, [cell], prec=1)
+        E, eig = _run(dev, s, Y, [cell], 4, graph=graph)
+        out[graph] = (E, eig)
+        dev.D.dpp_system_destroy(s)
+    assert np.array_equal(out[False][0], out[True][0])
+    assert np.array_equal(out[False][1], out[True][1])
+
+
+def test_config4_batch_fp32_graph(dev):
+    """The 48-cell throughput workload: FP32 bulk, graph replay, three SCF
+    iterations; three sampled cells equal their own single-cell runs."""
+    cells = W.config4()
+    s, Y, lay = _batch(dev, cells, prec=1)
+    nc, nitems, total, nstates, ngrid = dev.D.dpp_system_dims(s)
+    log(f"config4: {nc} cells, {nitems} items, {total} coefficients per block, {nstates} states, {ngrid} grid points")
+    E, _ = _run(dev, s, Y, cells, 3, graph=True)
+    res = dev.D.dpp_scf_cell_residuals(s)
+    dev.D.dpp_system_destroy(s)
+    assert np.all(np.isfinite(E)) and np.all(np.isfinite(res))
+    for ci in (0, 17, 47):
+        c = cells[ci]
+        s1, Y1, _ = _batch(dev, [c], prec=1)
+        E1, _ = _run(dev, s1, Y1, [c], 3, graph=True)
+        dev.D.dpp_system_destroy(s1)
+        log(f"cell {ci}: batch {E[-1, ci]:.12f} single {E1[-1, 0]:.12f}")
+        assert np.max(np.abs(E1[:, 0] - E[:, ci])) / c.nat < 1e-9

@@ -24,7 +24,7 @@ Workloads (plane-wave DFT, atomic units: bohr, hartree):
 * ``config4``: 48 independent cubic cells with random edge, atom count,
   species, band count and k folding (batched throughput).
 * ``config5``: config2 cell displaced by N(0, 0.3^2), 512 training and 64
-  held-out geometries (learned initial density).
+  held-out geometries, 20 bands (learned initial density).
 """
 from __future__ import annotations
 
@@ -141,7 +141,7 @@ def config1() -> Cell:
 
 
 def diamond_cell(displace_sigma: float = 0.0, seed: int | None = None, name="config2",
-                 reject_below: float | None = None) -> Cell:
+                 reject_below: float | None = None, nb: int = 16) -> Cell:
     a = 10.26
     R = np.eye(3) * a
     base = (R @ DIAMOND_FRAC.T).T
@@ -154,7 +154,7 @@ def diamond_cell(displace_sigma: float = 0.0, seed: int | None = None, name="con
     else:
         tau = base.copy()
     k, w = gamma_centred_kpoints((2, 2, 2))
-    return Cell(name, R, tau, np.full(8, 4), 12.0, (40, 40, 40), 16, k, w, 201)
+    return Cell(name, R, tau, np.full(8, 4), 12.0, (40, 40, 40), nb, k, w, 201)
 
 
 def config2() -> Cell:
@@ -209,8 +209,14 @@ def config4() -> List[Cell]:
     return cells
 
 
+CONFIG5_NB = 20
+
+
 def config5(split: str = "train", count: int | None = None) -> List[Cell]:
-    """Displaced diamond cells: seeds 5000-5511 (train) or 6000-6063 (held out)."""
+    """Displaced diamond cells: seeds 5000-5511 (train) or 6000-6063 (held out).
+
+    20 bands per k-point (16 occupied + 4 empty): displaced cells can have
+    bands crossing between k-points, and the fillings must be free to follow."""
     if split == "train":
         seeds = range(5000, 5512)
     elif split == "eval":
@@ -218,7 +224,7 @@ def config5(split: str = "train", count: int | None = None) -> List[Cell]:
     else:
         raise ValueError(split)
     seeds = list(seeds)[: count if count is not None else None]
-    return [diamond_cell(0.3, s, name=f"config5_{split}_{s}", reject_below=1.5) for s in seeds]
+    return [diamond_cell(0.3, s, name=f"config5_{split}_{s}", reject_below=1.5, nb=CONFIG5_NB) for s in seeds]
 
 
 def tiny_cell(nat=2, L=6.0, ecut=3.0, S=(12, 12, 12), nb=3, Z=(1, 1), seed=7,
