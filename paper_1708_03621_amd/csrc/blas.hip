@@ -205,20 +205,25 @@ k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const 
         dre[t] = d4{0, 0, 0, 0};
         dim[t] = d4{0, 0, 0, 0};
     }
-    for (int i0 = 0; i0 < T.nbX; i0 += 4) {
-        const int i = i0 + ks;
-        double2 x = double2{0, 0};
-        if (i < T.nbX && vq) x = T.X[(int64_t)i * T.ldX + q];
+    for (int term = 0; term < (T.nbX2 > 0 ? 2 : 1); ++term) {
+        const double2* Xs = term ? T.X2 : T.X;
+        const double2* Ms = term ? T.M2 : T.M;
+        const int nbx = term ? T.nbX2 : T.nbX;
+        for (int i0 = 0; i0 < nbx; i0 += 4) {
+            const int i = i0 + ks;
+            double2 x = double2{0, 0};
+            if (i < nbx && vq) x = Xs[(int64_t)i * T.ldX + q];
 #pragma unroll
-        for (int t = 0; t < RT_JT; ++t) {
-            if (t < njt) {
-                const int j = (jt0 + t) * 16 + c;
-                double2 m = double2{0, 0};
-                if (i < T.nbX && j < T.nbO) m = T.M[(int64_t)i * T.M_ld + j];
-                dre[t] = mfma(m.x, x.x, dre[t]);
-                dre[t] = mfma(-m.y, x.y, dre[t]);
-                dim[t] = mfma(m.y, x.x, dim[t]);
-                dim[t] = mfma(m.x, x.y, dim[t]);
+            for (int t = 0; t < RT_JT; ++t) {
+                if (t < njt) {
+                    const int j = (jt0 + t) * 16 + c;
+                    double2 m = double2{0, 0};
+                    if (i < nbx && j < T.nbO) m = Ms[(int64_t)i * T.M_ld + j];
+                    dre[t] = mfma(m.x, x.x, dre[t]);
+                    dre[t] = mfma(-m.y, x.y, dre[t]);
+                    dim[t] = mfma(m.y, x.x, dim[t]);
+                    dim[t] = mfma(m.x, x.y, dim[t]);
+                }
             }
         }
     }
@@ -258,12 +263,14 @@ RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, 
     t.M_ld = M_ld;
     t.beta = beta;
     t.item = 0;
-    t.pad = 0;
+    t.nbX2 = 0;
+    t.X2 = nullptr;
+    t.M2 = nullptr;
     return t;
 }
 
 static double rot_bytes(const RotTask& t) {
-    return 16.0 * t.npw * (t.nbX + t.nbO * (t.beta != 0.0 ? 2.0 : 1.0)) + 16.0 * t.nbX * t.nbO;
+    return 16.0 * t.npw * (t.nbX + t.nbX2 + t.nbO * (t.beta != 0.0 ? 2.0 : 1.0)) + 16.0 * (t.nbX + t.nbX2) * t.nbO;
 }
 
 dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
@@ -289,7 +296,7 @@ dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTas
         mp = std::max(mp, t.npw);
         mj = std::max(mj, (t.nbO + 15) / 16);
         by += rot_bytes(t);
-        fl += 8.0 * t.npw * t.nbX * (double)t.nbO;
+        fl += 8.0 * t.npw * (t.nbX + t.nbX2) * (double)t.nbO;
     }
     const int nblk = ((mp + 15) / 16 + RT_WAVES - 1) / RT_WAVES;
     TimerScope ts_(ctx, DPP_TK_ROTATE, by, fl);
@@ -299,6 +306,61 @@ dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTas
         DPP_LAUNCHED();
     }
     return DPP_OK;
+}
+
+// ------------------------------------------------- small-matrix products ---
+// Per item n x n (row-major at moff, n = nbo or the item's band count):
+// C = alpha op(A) op(B) + beta C with op = N or H; alpha times the cell volume
+// if alpha_omega.  One wave per 16 x 16 tile of C (blockIdx.x), items on
+// blockIdx.y; complex products from four real FP64 MFMAs per K step.
+__global__ void __launch_bounds__(64)
+k_smm_mfma(const Seg* __restrict__ seg, int nbo, int opA, int opB, double alpha0, int alpha_omega,
+           const double2* __restrict__ A, const double2* __restrict__ B, double beta, double2* __restrict__ Cm) {
+    const Seg sg = seg[blockIdx.y];
+    const int n = nbo > 0 ? nbo : sg.nb;
+    const int tn = (n + 15) / 16;
+    const int tile = blockIdx.x;
+    if (tile >= tn * tn) return;
+    const int ti = tile / tn, tj = tile - ti * tn;
+    const int lane = threadIdx.x;
+    const int r = lane & 15, ks = lane >> 4;
+    const int i = ti * 16 + r, j = tj * 16 + r;
+    const double2* Ab = A + sg.moff;
+    const double2* Bb = B + sg.moff;
+    d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < n; k0 += 4) {
+        const int k = k0 + ks;
+        double2 a = double2{0, 0}, b = double2{0, 0};
+        if (k < n) {
+            if (i < n) {
+                a = opA ? Ab[(int64_t)k * n + i] : Ab[(int64_t)i * n + k];
+                if (opA) a.y = -a.y;
+            }
+            if (j < n) {
+                b = opB ? Bb[(int64_t)j * n + k] : Bb[(int64_t)k * n + j];
+                if (opB) b.y = -b.y;
+            }
+        }
+        cre = mfma(a.x, b.x, cre);
+        cre = mfma(-a.y, b.y, cre);
+        cim = mfma(a.x, b.y, cim);
+        cim = mfma(a.y, b.x, cim);
+    }
+    const double alpha = alpha_omega ? alpha0 * sg.omega : alpha0;
+    double2* Cb = Cm + sg.moff;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int ii = ti * 16 + 4 * v + (lane >> 4), jj = tj * 16 + (lane & 15);
+        if (ii < n && jj < n) {
+            double2 o = double2{alpha * cre[v], alpha * cim[v]};
+            if (beta != 0.0) {
+                const double2 c = Cb[(int64_t)ii * n + jj];
+                o.x += beta * c.x;
+                o.y += beta * c.y;
+            }
+            Cb[(int64_t)ii * n + jj] = o;
+        }
+    }
 }
 
 // ------------------------------------------------------------ Cholesky -----
@@ -444,10 +506,12 @@ k_cholesky_seg(const Seg* __restrict__ seg, int nbo, const double2* __restrict__
 // times).  Writes ok[item] and step[item] (0 when the search failed).
 constexpr int LS_MAX_TRIES = 6;
 
+// Trial energy at step a.  With `Hs` (LDS, n^2 entries) H(a) is staged once
+// per trial; otherwise its entries are formed from global memory in the trace.
 __device__ double trial_energy(const Seg& sg, double a, const double2* __restrict__ U,
                                const double2* __restrict__ X, const double2* __restrict__ Q,
                                const double2* __restrict__ H0, const double2* __restrict__ H1,
-                               const double2* __restrict__ H2, double2* __restrict__ A) {
+                               const double2* __restrict__ H2, double2* __restrict__ A, double2* __restrict__ Hs) {
     __shared__ double red[256];
     const int n = sg.nb;
     const int64_t o = sg.moff;
@@ -456,6 +520,14 @@ __device__ double trial_energy(const Seg& sg, double a, const double2* __restric
         const double2 u = U[o + r * n + c], q = Q[o + r * n + c];
         return double2{u.x + a * (x.x + xt.x) + a * a * q.x, u.y + a * (x.y - xt.y) + a * a * q.y};
     };
+    auto Hat = [&](int r, int c) {
+        const double2 h = H1[o + r * n + c], ht = H1[o + c * n + r];
+        const double2 h0 = H0[o + r * n + c], h2 = H2[o + r * n + c];
+        return double2{h0.x + a * (h.x + ht.x) + a * a * h2.x, h0.y + a * (h.y - ht.y) + a * a * h2.y};
+    };
+    if (Hs)
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) Hs[e] = Hat(e / n, e % n);
+    // (the staging is ordered before its use by the barriers of the factorization)
     const int failed = chol_inverse_packed(n, loadU, A);
     if (failed) return NAN;
     // Re Tr(Rinv^dag H(a) Rinv) = sum_{a <= i} Re conj(Rinv[a][i]) sum_{t <= i} H(a)[a][t] Rinv[t][i]
@@ -465,13 +537,10 @@ __device__ double trial_energy(const Seg& sg, double a, const double2* __restric
         if (ar > i) continue;
         double wr = 0, wi = 0;
         for (int t = 0; t <= i; ++t) {
-            const double2 h = H1[o + ar * n + t], ht = H1[o + t * n + ar];
-            const double2 h0 = H0[o + ar * n + t], h2 = H2[o + ar * n + t];
-            const double hr = h0.x + a * (h.x + ht.x) + a * a * h2.x;
-            const double hi = h0.y + a * (h.y - ht.y) + a * a * h2.y;
+            const double2 h = Hs ? Hs[ar * n + t] : Hat(ar, t);
             const double2 r = A[up_idx(n, t, i)];
-            wr += hr * r.x - hi * r.y;
-            wi += hr * r.y + hi * r.x;
+            wr += h.x * r.x - h.y * r.y;
+            wi += h.x * r.y + h.y * r.x;
         }
         const double2 ra = A[up_idx(n, ar, i)];
         acc += ra.x * wr + ra.y * wi;
@@ -492,22 +561,23 @@ k_linesearch_B(const Seg* __restrict__ seg, const double2* __restrict__ U, const
                const double2* __restrict__ Q, const double2* __restrict__ H0, const double2* __restrict__ H1,
                const double2* __restrict__ H2, const double* __restrict__ E0v, const double* __restrict__ at0,
                const double* __restrict__ d0v, const int* __restrict__ act, int* __restrict__ ok,
-               double* __restrict__ step) {
+               double* __restrict__ step, int stage_h) {
     const int k = blockIdx.x;
     if (!act[k]) return;
     extern __shared__ char smem_raw[];
     double2* A = reinterpret_cast<double2*>(smem_raw);
     const Seg sg = seg[k];
+    double2* Hs = stage_h ? A + sg.nb * (sg.nb + 1) / 2 : nullptr;
     const double E0 = E0v[k], d0 = d0v[k];
     double at = at0[k];
     int good = 0;
     double st = 0.0;
     for (int t = 0; t < LS_MAX_TRIES; ++t) {
-        const double Et = trial_energy(sg, at, U, X, Q, H0, H1, H2, A);
+        const double Et = trial_energy(sg, at, U, X, Q, H0, H1, H2, A, Hs);
         const double c = (Et - E0 - d0 * at) / (at * at);
         double as = c > 0 ? -d0 / (2.0 * c) : 2.0 * at;
         as = fmin(as, 10.0 * at);
-        const double Es = trial_energy(sg, as, U, X, Q, H0, H1, H2, A);
+        const double Es = trial_energy(sg, as, U, X, Q, H0, H1, H2, A, Hs);
         if (Es <= E0) {
             good = 1;
             st = as;
@@ -527,13 +597,19 @@ k_linesearch_B(const Seg* __restrict__ seg, const double2* __restrict__ U, const
 }
 
 // ----------------------------------------------------- Jacobi eigensolver --
-// Parallel cyclic Jacobi on a Hermitian matrix (one workgroup per matrix):
-// each round rotates n/2 disjoint pairs of a round-robin tournament.  For the
-// pair (p,q) with A_pq = |c| e^{i phi}, J = diag-phase * real rotation:
+// Parallel cyclic Jacobi on a Hermitian matrix, one workgroup per matrix.
+// Each round rotates m/2 disjoint index pairs of a round-robin tournament
+// (circle schedule: pair 0 = (m-1, r), pair s = ((r+s) mod (m-1),
+// (r-s) mod (m-1)); m = n rounded up to even, index n a dummy).  For the pair
+// (p,q) with A_pq = |c| e^{i phi}, J = diag-phase * real rotation:
 //   tau = (A_qq - A_pp) / (2|c|), t = sign(tau)/(|tau| + sqrt(1+tau^2)),
 //   cs = 1/sqrt(1+t^2), sn = t cs,
 //   J[p][p] = cs, J[p][q] = sn, J[q][p] = -sn e^{-i phi}, J[q][q] = cs e^{-i phi}
-// and A <- J^dag A J, V <- V J.
+// and A <- J^dag A J, V <- V J.  A is kept as its packed upper triangle in
+// LDS (Hermitian), so a round is one pass over 2x2 blocks (pair s', pair s):
+// B <- J_s'^dag B J_s, each stored element touched once; the diagonal blocks
+// become diagonal exactly.  V (n x n) lives in LDS for n <= 64, else in the
+// caller's global scratch.
 constexpr int EIG_MAXN = 128;
 constexpr int EIG_SWEEPS = 40;
 
@@ -542,51 +618,81 @@ struct Rot {
     double cs, sn, er, ei;  // e^{-i phi} = er + i ei
 };
 
-// Eigen-decomposition of the Hermitian n x n matrix Hg: ascending eigenvalues
-// to ev, eigenvectors (columns) to vo.  Works in LDS (lds, 2 n^2 entries) if
-// in_lds, else in scr (2 n^2 entries of global scratch).
+__device__ __forceinline__ double2 hget(const double2* A, int n, int r, int c) {
+    if (r <= c) return A[up_idx(n, r, c)];
+    const double2 v = A[up_idx(n, c, r)];
+    return double2{v.x, -v.y};
+}
+
+__device__ __forceinline__ void hset(double2* A, int n, int r, int c, double2 v) {
+    if (r <= c)
+        A[up_idx(n, r, c)] = v;
+    else
+        A[up_idx(n, c, r)] = double2{v.x, -v.y};
+}
+
+__device__ __forceinline__ double2 cmulz(double2 a, double2 b) {
+    return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// LDS bytes of one matrix: packed A, plus V when n <= 64.
+__host__ __device__ inline size_t eigh_lds_bytes(int n) {
+    return (size_t)n * (n + 1) / 2 * sizeof(double2) + (n <= 64 ? (size_t)n * n * sizeof(double2) : 0);
+}
+
+// Eigen-decomposition of the Hermitian n x n matrix Hg (row-major): ascending
+// eigenvalues to ev, eigenvectors (columns) to vo.  lds holds eigh_lds_bytes(n);
+// scr (n^2 entries) is used for V when n > 64.
 __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double* __restrict__ ev,
-                                  double2* __restrict__ vo, bool in_lds, double2* __restrict__ lds,
-                                  double2* __restrict__ scr) {
-    const int m = n + (n & 1);  // even number of players (a dummy if n odd)
-    double2* A = in_lds ? lds : scr;
-    double2* V = A + n * n;
+                                  double2* __restrict__ vo, double2* __restrict__ lds, double2* __restrict__ scr) {
+    const int m = n + (n & 1);
+    const int P = m / 2;
+    double2* A = lds;
+    double2* V = n <= 64 ? lds + n * (n + 1) / 2 : scr;
     __shared__ Rot rot[EIG_MAXN / 2];
-    __shared__ int order[EIG_MAXN + 2];
     __shared__ double red[256];
+    __shared__ double dg[EIG_MAXN];
+    __shared__ int perm[EIG_MAXN];
     __shared__ int done;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        double2 h = Hg[e];
-        const int r = e / n, c = e % n;
-        if (r == c) h.y = 0.0;
-        A[e] = h;
+        const int r = e / n, c = e - r * n;
+        if (c >= r) {
+            double2 h = Hg[e];
+            if (r == c) h.y = 0.0;
+            A[up_idx(n, r, c)] = h;
+        }
         V[e] = double2{r == c ? 1.0 : 0.0, 0.0};
     }
-    for (int i = threadIdx.x; i < m; i += blockDim.x) order[i] = i;
     __syncthreads();
+    const int nblk = P * (P + 1) / 2;
     for (int sweep = 0; sweep < EIG_SWEEPS; ++sweep) {
         // convergence: off-diagonal Frobenius norm vs diagonal scale
         double off = 0, dia = 0;
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int r = e / n, c = e % n;
+        for (int e = threadIdx.x; e < n * (n + 1) / 2; e += blockDim.x) {
+            int r = 0, rem = e;
+            while (rem >= n - r) {
+                rem -= n - r;
+                ++r;
+            }
+            const int c = r + rem;
             const double2 a = A[e];
             if (r != c)
-                off += a.x * a.x + a.y * a.y;
+                off += 2.0 * (a.x * a.x + a.y * a.y);
             else
                 dia += a.x * a.x;
         }
         red[threadIdx.x] = off;
         __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
         const double offt = red[0];
         __syncthreads();
         red[threadIdx.x] = dia;
         __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
         const double diat = red[0];
@@ -594,25 +700,25 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
         __syncthreads();
         if (done) break;
         for (int round = 0; round < m - 1; ++round) {
-            // pairs (order[2s], order[2s+1])
-            for (int s = threadIdx.x; s < m / 2; s += blockDim.x) {
-                int p = order[s], q = order[m - 1 - s];
+            for (int s = threadIdx.x; s < P; s += blockDim.x) {
+                int p, q;
+                if (s == 0) {
+                    p = m - 1;
+                    q = round;
+                } else {
+                    p = (round + s) % (m - 1);
+                    q = (round - s + (m - 1)) % (m - 1);
+                }
                 if (p > q) {
                     const int t = p;
                     p = q;
                     q = t;
                 }
-                Rot R;
-                R.p = p;
-                R.q = q;
-                R.cs = 1.0;
-                R.sn = 0.0;
-                R.er = 1.0;
-                R.ei = 0.0;
+                Rot R{p, q, 1.0, 0.0, 1.0, 0.0};
                 if (q < n) {
-                    const double2 c = A[p * n + q];
+                    const double2 c = A[up_idx(n, p, q)];
                     const double ac = sqrt(c.x * c.x + c.y * c.y);
-                    const double app = A[p * n + p].x, aqq = A[q * n + q].x;
+                    const double app = A[up_idx(n, p, p)].x, aqq = A[up_idx(n, q, q)].x;
                     if (ac > 1e-300 && ac > 1e-18 * sqrt(fabs(app * aqq))) {
                         const double tau = (aqq - app) / (2.0 * ac);
                         const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -622,73 +728,91 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
                         R.ei = -c.y / ac;
                     }
                 } else {
-                    R.q = -1;
+                    R.q = -1;  // paired with the dummy: no rotation
                 }
                 rot[s] = R;
             }
             __syncthreads();
-            // columns: A[:, p], A[:, q] <- A[:, [p q]] J ; V likewise
-            for (int e = threadIdx.x; e < (m / 2) * n; e += blockDim.x) {
-                const int s = e / n, r = e % n;
-                const Rot R = rot[s];
+            // A: every 2x2 block (pair s2 rows, pair s1 columns), s2 <= s1
+            for (int bk = threadIdx.x; bk < nblk; bk += blockDim.x) {
+                int s2 = 0, rem = bk;
+                while (rem >= P - s2) {
+                    rem -= P - s2;
+                    ++s2;
+                }
+                const int s1 = s2 + rem;
+                const Rot Rc = rot[s1], Rr = rot[s2];
+                const bool idc = Rc.q < 0 || (Rc.sn == 0.0 && Rc.er == 1.0 && Rc.ei == 0.0);
+                const bool idr = Rr.q < 0 || (Rr.sn == 0.0 && Rr.er == 1.0 && Rr.ei == 0.0);
+                if (idc && idr) continue;
+                const int xr[2] = {Rr.p, Rr.q}, yc[2] = {Rc.p, Rc.q};
+                double2 B[2][2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        B[i][j] = (xr[i] >= 0 && xr[i] < n && yc[j] >= 0 && yc[j] < n) ? hget(A, n, xr[i], yc[j])
+                                                                                      : double2{0, 0};
+                if (!idc) {
+                    // columns: new_p = cs b_p - sn e b_q ; new_q = sn b_p + cs e b_q
+                    const double2 e2 = double2{Rc.er, Rc.ei};
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const double2 bp = B[i][0], ebq = cmulz(e2, B[i][1]);
+                        B[i][0] = double2{Rc.cs * bp.x - Rc.sn * ebq.x, Rc.cs * bp.y - Rc.sn * ebq.y};
+                        B[i][1] = double2{Rc.sn * bp.x + Rc.cs * ebq.x, Rc.sn * bp.y + Rc.cs * ebq.y};
+                    }
+                }
+                if (!idr) {
+                    // rows: new_p = cs b_p - sn conj(e) b_q ; new_q = sn b_p + cs conj(e) b_q
+                    const double2 ce = double2{Rr.er, -Rr.ei};
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const double2 bp = B[0][j], ebq = cmulz(ce, B[1][j]);
+                        B[0][j] = double2{Rr.cs * bp.x - Rr.sn * ebq.x, Rr.cs * bp.y - Rr.sn * ebq.y};
+                        B[1][j] = double2{Rr.sn * bp.x + Rr.cs * ebq.x, Rr.sn * bp.y + Rr.cs * ebq.y};
+                    }
+                }
+                if (s1 == s2) {
+                    // the rotated pair: exactly diagonal, real diagonal
+                    if (Rc.q >= 0) {
+                        hset(A, n, Rc.p, Rc.p, double2{B[0][0].x, 0.0});
+                        hset(A, n, Rc.q, Rc.q, double2{B[1][1].x, 0.0});
+                        hset(A, n, Rc.p, Rc.q, double2{0.0, 0.0});
+                    }
+                    continue;
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        if (xr[i] >= 0 && xr[i] < n && yc[j] >= 0 && yc[j] < n) hset(A, n, xr[i], yc[j], B[i][j]);
+            }
+            // V <- V J (columns p, q of every row)
+            for (int e = threadIdx.x; e < P * n; e += blockDim.x) {
+                const int sidx = e / n, r = e - sidx * n;
+                const Rot R = rot[sidx];
                 if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
                 const double2 e2 = double2{R.er, R.ei};
-                for (int which = 0; which < 2; ++which) {
-                    double2* M = which ? V : A;
-                    const double2 ap = M[r * n + R.p], aq = M[r * n + R.q];
-                    // new_p = cs ap - sn e aq ; new_q = sn ap + cs e aq   (e = e^{-i phi})
-                    const double2 eaq = double2{e2.x * aq.x - e2.y * aq.y, e2.x * aq.y + e2.y * aq.x};
-                    M[r * n + R.p] = double2{R.cs * ap.x - R.sn * eaq.x, R.cs * ap.y - R.sn * eaq.y};
-                    M[r * n + R.q] = double2{R.sn * ap.x + R.cs * eaq.x, R.sn * ap.y + R.cs * eaq.y};
-                }
-            }
-            __syncthreads();
-            // rows: A[p, :], A[q, :] <- J^dag A[[p q], :]
-            for (int e = threadIdx.x; e < (m / 2) * n; e += blockDim.x) {
-                const int s = e / n, c = e % n;
-                const Rot R = rot[s];
-                if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
-                const double2 ap = A[R.p * n + c], aq = A[R.q * n + c];
-                // conj(e) aq
-                const double2 eaq = double2{R.er * aq.x + R.ei * aq.y, R.er * aq.y - R.ei * aq.x};
-                A[R.p * n + c] = double2{R.cs * ap.x - R.sn * eaq.x, R.cs * ap.y - R.sn * eaq.y};
-                A[R.q * n + c] = double2{R.sn * ap.x + R.cs * eaq.x, R.sn * ap.y + R.cs * eaq.y};
-            }
-            __syncthreads();
-            // clean the rotated pair exactly and rotate the tournament
-            if (threadIdx.x == 0) {
-                for (int s = 0; s < m / 2; ++s) {
-                    const Rot R = rot[s];
-                    if (R.q < 0) continue;
-                    A[R.p * n + R.q] = double2{0, 0};
-                    A[R.q * n + R.p] = double2{0, 0};
-                    A[R.p * n + R.p].y = 0.0;
-                    A[R.q * n + R.q].y = 0.0;
-                }
-                const int last = order[m - 1];
-                for (int i = m - 1; i > 1; --i) order[i] = order[i - 1];
-                order[1] = last;
+                const double2 vp = V[r * n + R.p], eq = cmulz(e2, V[r * n + R.q]);
+                V[r * n + R.p] = double2{R.cs * vp.x - R.sn * eq.x, R.cs * vp.y - R.sn * eq.y};
+                V[r * n + R.q] = double2{R.sn * vp.x + R.cs * eq.x, R.sn * vp.y + R.cs * eq.y};
             }
             __syncthreads();
         }
     }
-    // sort eigenvalues ascending (selection, thread 0), then emit
-    __shared__ int perm[EIG_MAXN];
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < n; ++i) perm[i] = i;
-        for (int i = 0; i < n; ++i) {
-            int best = i;
-            for (int j = i + 1; j < n; ++j)
-                if (A[perm[j] * n + perm[j]].x < A[perm[best] * n + perm[best]].x) best = j;
-            const int t = perm[i];
-            perm[i] = perm[best];
-            perm[best] = t;
-        }
+    // ascending order by rank (ties by index), then emit
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dg[i] = A[up_idx(n, i, i)].x;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int r = 0;
+        for (int j = 0; j < n; ++j) r += (dg[j] < dg[i]) || (dg[j] == dg[i] && j < i);
+        perm[r] = i;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = A[perm[i] * n + perm[i]].x;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = dg[perm[i]];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int r = e / n, c = e % n;
+        const int r = e / n, c = e - r * n;
         vo[e] = V[r * n + perm[c]];
     }
 }
@@ -698,20 +822,18 @@ k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, do
               double2* __restrict__ scratch) {
     extern __shared__ char smem_raw[];
     const int64_t b = blockIdx.x;
-    jacobi_eigh_block(n, H + b * n * n, eig + b * n, vecs + b * n * n, n <= 64, reinterpret_cast<double2*>(smem_raw),
-                      scratch ? scratch + b * 2 * n * n : nullptr);
+    jacobi_eigh_block(n, H + b * n * n, eig + b * n, vecs + b * n * n, reinterpret_cast<double2*>(smem_raw),
+                      scratch ? scratch + b * n * n : nullptr);
 }
 
-// Per work item: matrix at moff, eigenvalues at f_off.  With scratch == NULL
-// every matrix works in LDS (the launch provides 2 n^2 entries for the
-// largest n); otherwise in scratch at 2 moff.
+// Per work item: matrix at moff, eigenvalues at f_off, V scratch (n > 64) at moff.
 __global__ void __launch_bounds__(256)
 k_jacobi_eigh_seg(const Seg* __restrict__ seg, const double2* __restrict__ H, double* __restrict__ eig,
                   double2* __restrict__ vecs, double2* __restrict__ scratch) {
     extern __shared__ char smem_raw[];
     const Seg sg = seg[blockIdx.x];
-    jacobi_eigh_block(sg.nb, H + sg.moff, eig + sg.f_off, vecs + sg.moff, scratch == nullptr,
-                      reinterpret_cast<double2*>(smem_raw), scratch ? scratch + 2 * sg.moff : nullptr);
+    jacobi_eigh_block(sg.nb, H + sg.moff, eig + sg.f_off, vecs + sg.moff, reinterpret_cast<double2*>(smem_raw),
+                      scratch ? scratch + sg.moff : nullptr);
 }
 
 }  // namespace dpp
@@ -764,7 +886,7 @@ extern "C" dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const
 extern "C" dpp_status dpp_eigh_workspace_size(int nb, int batch, size_t* bytes) {
     clear_error();
     DPP_REQUIRE(bytes && nb >= 1 && batch >= 0, "dpp_eigh_workspace_size: bad arguments");
-    *bytes = nb <= 64 ? 256 : (size_t)batch * 2 * nb * nb * sizeof(double2) + 256;
+    *bytes = nb <= 64 ? 256 : (size_t)batch * nb * nb * sizeof(double2) + 256;
     return DPP_OK;
 }
 
@@ -776,17 +898,19 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
     if (batch == 0) return DPP_OK;
     DPP_REQUIRE(H && eig && vecs, "dpp_subspace_eigh: null pointer");
     DPP_REQUIRE(nb <= 64 || ws, "dpp_subspace_eigh: workspace required for nb > 64");
-    const size_t lds = nb <= 64 ? (size_t)2 * nb * nb * sizeof(double2) : 0;
+    const size_t lds = eigh_lds(nb);
     if (lds > 64 * 1024)
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(ctx, DPP_TK_EIGH);
     const int nt = nb <= 32 ? 64 : 256;  // one wave: barriers are nearly free at small nb
     hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(nt), lds, ctx->stream, nb, (const double2*)H, eig,
-                       (double2*)vecs, (double2*)ws);
+                       (double2*)vecs, nb <= 64 ? (double2*)nullptr : (double2*)ws);
     DPP_LAUNCHED();
     return DPP_OK;
 }
+
+size_t dpp::eigh_lds(int nmax) { return std::max(eigh_lds_bytes(nmax), eigh_lds_bytes(std::min(nmax, 64))); }
 
 size_t dpp::proj_ws_bytes(const dpp_basis_s* b, int nb) {
     // Pi (64 projectors max per call chunk is not assumed: use the actual count later)

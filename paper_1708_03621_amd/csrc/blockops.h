@@ -52,9 +52,6 @@ __global__ void k_nonlocal_energy(const Seg* seg, const CellDesc* cells, int nbo
                                   double* out, int out_stride);
 __global__ void k_sm_scale(const Seg* seg, int nbo, int op, double scale, int flags, const double2* A,
                            double2* out);
-__global__ void k_smm(const Seg* seg, int nbo, int opA, int opB, double alpha, int alpha_omega, const double2* A,
-                      const double2* B, double beta, double2* Cm);
-__global__ void k_trace_RhHR(const Seg* seg, int nbo, const double2* Rinv, const double2* H, double* out);
 __global__ void k_band_residual(const Seg* seg, const double* eig, const double2* Y, const double2* HY, double* out);
 __global__ void k_grid_lin3(int64_t N, double a, const double* x, double b, const double* y, double c,
                             const double* z, double* out);
@@ -70,17 +67,27 @@ __global__ void k_pulay_solve_cells(int ncells, const int* st, const CellDesc* c
 __global__ void k_pulay_combine_cells(int64_t Ntot, const int* st, const CellDesc* cells, const double* coef,
                                       double alpha, const double* hn, const double* hr, double* nin);
 __global__ void k_cgB_reset(int nit, const Seg* seg, CgBState s);
-__global__ void k_cgB_direction(int nit, const double* dots, CgBState s);
 __global__ void k_cgB_retry(int nit, const double* dots, CgBState s);
 __global__ void k_cgB_finish(int nit, const double* dots, CgBState s);
 __global__ void k_aufbau(const CellDesc* cells, const Seg* seg, const double* eig, double* f, int* status);
 
-// blas.hip: per-item Cholesky inverse, eigensolver and fused line search
+__global__ void k_cg_precond_dots(const Seg* seg, int nitems, const double2* g, const double2* gp,
+                                  const double2* Dp, double2* Kg, double* part);
+__global__ void k_cgB_reduce_direction(int nitems, const double* part, double* dots, CgBState s);
+__global__ void k_cgB_update(const Seg* seg, const double* step, double2* Y, const double2* Dd, double2* HY,
+                             const double2* HD, const double2* g, double2* gp, double2* Dp);
+__global__ void k_trace_diag(const Seg* seg, const double2* M, double* out);
+
+// blas.hip: per-item Cholesky inverse, eigensolver, fused line search and
+// small-matrix products
+__global__ void k_smm_mfma(const Seg* seg, int nbo, int opA, int opB, double alpha0, int alpha_omega,
+                           const double2* A, const double2* B, double beta, double2* Cm);
 __global__ void k_cholesky_seg(const Seg* seg, int nbo, const double2* U, double2* Rinv, int* status,
                                const int* act);
 __global__ void k_jacobi_eigh_seg(const Seg* seg, const double2* H, double* eig, double2* vecs, double2* scratch);
 __global__ void k_linesearch_B(const Seg* seg, const double2* U, const double2* X, const double2* Q,
                                const double2* H0, const double2* H1, const double2* H2, const double* E0v,
-                               const double* at0, const double* d0v, const int* act, int* ok, double* step);
+                               const double* at0, const double* d0v, const int* act, int* ok, double* step,
+                               int stage_h);
 
 }  // namespace dpp

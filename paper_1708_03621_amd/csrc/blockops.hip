@@ -176,38 +176,6 @@ __global__ void k_nonlocal_energy(const Seg* __restrict__ seg, const CellDesc* _
 // ------------------------------------------------------- small matrices ----
 // Every item's matrices are n x n row-major at moff (n = nbo or seg.nb).
 
-// C = alpha op(A) op(B) + beta C, op = N or H (conjugate transpose); batch =
-// item; alpha is multiplied by the item's cell volume if alpha_omega.
-__global__ void k_smm(const Seg* __restrict__ seg, int nbo, int opA, int opB, double alpha0, int alpha_omega,
-                      const double2* __restrict__ A, const double2* __restrict__ B, double beta,
-                      double2* __restrict__ Cm) {
-    const Seg s = seg[blockIdx.x];
-    const int n = item_nb(s, nbo);
-    const double alpha = alpha_omega ? alpha0 * s.omega : alpha0;
-    const double2* Ab = A + s.moff;
-    const double2* Bb = B + s.moff;
-    double2* Cb = Cm + s.moff;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        double sr = 0, si = 0;
-        for (int t = 0; t < n; ++t) {
-            double2 a = opA ? Ab[t * n + i] : Ab[i * n + t];
-            if (opA) a.y = -a.y;
-            double2 bb = opB ? Bb[j * n + t] : Bb[t * n + j];
-            if (opB) bb.y = -bb.y;
-            sr += a.x * bb.x - a.y * bb.y;
-            si += a.x * bb.y + a.y * bb.x;
-        }
-        double2 r = double2{alpha * sr, alpha * si};
-        if (beta != 0.0) {
-            const double2 c = Cb[e];
-            r.x += beta * c.x;
-            r.y += beta * c.y;
-        }
-        Cb[e] = r;
-    }
-}
-
 // out = scale * (w_k if flags & 1) * (Omega if flags & 2) * op(A), op = N or H.
 __global__ void k_sm_scale(const Seg* __restrict__ seg, int nbo, int op, double scale, int flags,
                            const double2* __restrict__ A, double2* __restrict__ out) {
@@ -220,36 +188,6 @@ __global__ void k_sm_scale(const Seg* __restrict__ seg, int nbo, int op, double 
         if (op) a.y = -a.y;
         out[s.moff + e] = double2{sc * a.x, sc * a.y};
     }
-}
-
-// Re Tr(Rinv^dag H Rinv) per item (= Tr(U^{-1} H) for U = R^dag R).
-__global__ void __launch_bounds__(256)
-k_trace_RhHR(const Seg* __restrict__ seg, int nbo, const double2* __restrict__ Rinv, const double2* __restrict__ H,
-             double* __restrict__ out) {
-    __shared__ double red[256];
-    const Seg s = seg[blockIdx.x];
-    const int n = item_nb(s, nbo);
-    const int64_t o = s.moff;
-    double acc = 0;
-    // sum_i sum_a conj(Rinv[a][i]) (H Rinv)[a][i]
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int a = e / n, i = e - a * n;
-        double wr = 0, wi = 0;
-        for (int t = 0; t < n; ++t) {
-            const double2 h = H[o + a * n + t], r = Rinv[o + t * n + i];
-            wr += h.x * r.x - h.y * r.y;
-            wi += h.x * r.y + h.y * r.x;
-        }
-        const double2 ra = Rinv[o + a * n + i];
-        acc += ra.x * wr + ra.y * wi;
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // Residual norms ||(H - eps_i O) y_i||_2 / sqrt(Omega) for orthonormal
@@ -371,21 +309,35 @@ k_pulay_dots(int64_t Ntot, const int* __restrict__ st, const CellDesc* __restric
 // slot-indexed matrix A (PULAY_MAX^2 per cell, scaled by Omega / N), then the
 // mixing coefficients in history order: c = (1) for one entry, else the
 // solution of [A 1; 1^T 0][c; l] = [0; 1] (LU with partial pivoting).
-__global__ void k_pulay_solve_cells(int ncells, const int* __restrict__ st, const CellDesc* __restrict__ cells,
-                                    const double* __restrict__ part, double* __restrict__ A,
-                                    double* __restrict__ coef, int* __restrict__ status) {
-    const int cidx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cidx >= ncells) return;
+__global__ void __launch_bounds__(256)
+k_pulay_solve_cells(int ncells, const int* __restrict__ st, const CellDesc* __restrict__ cells,
+                    const double* __restrict__ part, double* __restrict__ A, double* __restrict__ coef,
+                    int* __restrict__ status) {
+    __shared__ double red[256];
+    __shared__ double ov[PULAY_MAX];
+    const int cidx = blockIdx.x;
     const int m = st[0], head = st[1], slot = st[2];
+    // fixed-order tree sums of the MDOT_BLOCKS partials of each overlap
+    for (int i = 0; i < m; ++i) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < MDOT_BLOCKS; b += 256) v += part[((int64_t)cidx * PULAY_MAX + i) * MDOT_BLOCKS + b];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) ov[i] = red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
     const double dV = cells[cidx].dV;
     double* Ac = A + (int64_t)cidx * PULAY_MAX * PULAY_MAX;
     double* c = coef + (int64_t)cidx * PULAY_MAX;
     for (int i = 0; i < m; ++i) {
-        double s = 0;
-        for (int b = 0; b < MDOT_BLOCKS; ++b) s += part[((int64_t)cidx * PULAY_MAX + i) * MDOT_BLOCKS + b];
         const int si = (head + i) % PULAY_MAX;
-        Ac[slot * PULAY_MAX + si] = dV * s;
-        Ac[si * PULAY_MAX + slot] = dV * s;
+        Ac[slot * PULAY_MAX + si] = dV * ov[i];
+        Ac[si * PULAY_MAX + slot] = dV * ov[i];
     }
     if (m == 1) {
         c[0] = 1.0;
@@ -458,33 +410,6 @@ __global__ void k_cgB_reset(int nit, const Seg* __restrict__ seg, CgBState s) {
     s.gkg[k] = 0.0;
 }
 
-// Direction coefficients D = -K g + beta D_prev from the dots
-// (<g,Kg>, <g_prev,Kg>, <g,D_prev>) per item.
-__global__ void k_cgB_direction(int nit, const double* __restrict__ dots, CgBState s) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nit) return;
-    const double gkg = dots[k], gpkg = dots[(nit + 1) + k], gdp = dots[2 * (nit + 1) + k];
-    s.cK[k] = -1.0;
-    if (s.stat[k]) {
-        s.act[k] = 0;
-        s.beta[k] = 0.0;
-        s.d0[k] = 0.0;
-        s.steep[k] = 1;
-        return;
-    }
-    s.act[k] = 1;
-    double b = 0.0;
-    if (!s.reset[k]) b = fmax(0.0, (gkg - gpkg) / s.gkg[k]);
-    double dd = -gkg + b * gdp;
-    if (b != 0.0 && dd >= 0.0) {
-        b = 0.0;
-        dd = -gkg;
-    }
-    s.beta[k] = b;
-    s.d0[k] = dd;
-    s.steep[k] = b == 0.0;
-}
-
 // Items whose CG line search failed (and was not already steepest descent)
 // retry along -K g: D <- cK K g + cD D with cK = -1, cD = 0 for them.
 __global__ void k_cgB_retry(int nit, const double* __restrict__ dots, CgBState s) {
@@ -525,6 +450,121 @@ __global__ void k_cgB_finish(int nit, const double* __restrict__ dots, CgBState 
     }
 }
 
+// Fused start of a band-CG step: Kg = K g and, per item, partial sums of
+// <g, Kg>, <g_prev, Kg>, <g, D_prev> (2 Re sum conj(a) b) in one pass:
+// part[(pair * nitems + k) * DOT_BLOCKS + block].
+__global__ void __launch_bounds__(256)
+k_cg_precond_dots(const Seg* __restrict__ seg, int nitems, const double2* __restrict__ g,
+                  const double2* __restrict__ gp, const double2* __restrict__ Dp, double2* __restrict__ Kg,
+                  double* __restrict__ part) {
+    __shared__ double red[3][256];
+    const int k = blockIdx.y;
+    const Seg s = seg[k];
+    const int64_t n = (int64_t)s.nb * s.npw;
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * 256) {
+        const int q = (int)(e % s.npw);
+        const int64_t o = s.off + e;
+        const double kk = 1.0 / (1.0 + 0.5 * s.kG2[q]);
+        const double2 gv = g[o], gpv = gp[o], dv = Dp[o];
+        const double2 kg = double2{kk * gv.x, kk * gv.y};
+        Kg[o] = kg;
+        a0 += gv.x * kg.x + gv.y * kg.y;
+        a1 += gpv.x * kg.x + gpv.y * kg.y;
+        a2 += gv.x * dv.x + gv.y * dv.y;
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    red[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int p = 0; p < 3; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[((int64_t)threadIdx.x * nitems + k) * DOT_BLOCKS + blockIdx.x] = 2.0 * red[threadIdx.x][0];
+}
+
+// Per item (one 64-thread workgroup): fixed-order sums of the three dot
+// partials into dots[pair * (nitems + 1) + k], then the direction
+// coefficients of the item (as k_cgB_direction).
+__global__ void __launch_bounds__(64)
+k_cgB_reduce_direction(int nitems, const double* __restrict__ part, double* __restrict__ dots, CgBState s) {
+    __shared__ double red[3][64];
+    const int k = blockIdx.x;
+    for (int p = 0; p < 3; ++p) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < DOT_BLOCKS; b += 64) v += part[((int64_t)p * nitems + k) * DOT_BLOCKS + b];
+        red[p][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int p = 0; p < 3; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double gkg = red[0][0], gpkg = red[1][0], gdp = red[2][0];
+    dots[k] = gkg;
+    dots[(nitems + 1) + k] = gpkg;
+    dots[2 * (nitems + 1) + k] = gdp;
+    s.cK[k] = -1.0;
+    if (s.stat[k]) {
+        s.act[k] = 0;
+        s.beta[k] = 0.0;
+        s.d0[k] = 0.0;
+        s.steep[k] = 1;
+        return;
+    }
+    s.act[k] = 1;
+    double b = 0.0;
+    if (!s.reset[k]) b = fmax(0.0, (gkg - gpkg) / s.gkg[k]);
+    double dd = -gkg + b * gdp;
+    if (b != 0.0 && dd >= 0.0) {
+        b = 0.0;
+        dd = -gkg;
+    }
+    s.beta[k] = b;
+    s.d0[k] = dd;
+    s.steep[k] = b == 0.0;
+}
+
+// End of a band-CG step: Y += step D, HY += step HD, and the history for the
+// next direction (g_prev = g, D_prev = D), in one pass.
+__global__ void k_cgB_update(const Seg* __restrict__ seg, const double* __restrict__ step, double2* __restrict__ Y,
+                             const double2* __restrict__ Dd, double2* __restrict__ HY,
+                             const double2* __restrict__ HD, const double2* __restrict__ g, double2* __restrict__ gp,
+                             double2* __restrict__ Dp) {
+    const int k = blockIdx.y;
+    const Seg s = seg[k];
+    const int64_t n = (int64_t)s.nb * s.npw;
+    const double a = step[k];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = s.off + e;
+        const double2 d = Dd[o], hd = HD[o], y = Y[o], hy = HY[o];
+        Y[o] = double2{y.x + a * d.x, y.y + a * d.y};
+        HY[o] = double2{hy.x + a * hd.x, hy.y + a * hd.y};
+        gp[o] = g[o];
+        Dp[o] = d;
+    }
+}
+
+// Re Tr(M) per item (fixed order), out[item].
+__global__ void __launch_bounds__(64)
+k_trace_diag(const Seg* __restrict__ seg, const double2* __restrict__ M, double* __restrict__ out) {
+    __shared__ double red[64];
+    const Seg s = seg[blockIdx.x];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < s.nb; i += 64) v += M[s.moff + (int64_t)i * s.nb + i].x;
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 // ------------------------------------------------------------ aufbau -------
 // Fillings of one cell (one workgroup): states (e, k, i) ordered by energy,
 // then k-point, then band; groups of states within DEGEN_TOL of the group's
@@ -534,11 +574,18 @@ __global__ void __launch_bounds__(256)
 k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const double* __restrict__ eig,
          double* __restrict__ f, int* __restrict__ status) {
     __shared__ double e[AUFBAU_MAX];
+    __shared__ double fv[AUFBAU_MAX];
     __shared__ short kk[AUFBAU_MAX];
     __shared__ short ii[AUFBAU_MAX];
     __shared__ int order[AUFBAU_MAX];
     __shared__ int base[AUFBAU_MAX_ITEMS + 1];
+    __shared__ double wks[AUFBAU_MAX_ITEMS];
+    __shared__ int64_t foffs[AUFBAU_MAX_ITEMS];
     const CellDesc c = cells[blockIdx.x];
+    for (int k = threadIdx.x; k < c.nitems; k += blockDim.x) {
+        wks[k] = seg[c.item0 + k].wk;
+        foffs[k] = seg[c.item0 + k].f_off;
+    }
     if (threadIdx.x == 0) {
         base[0] = 0;
         for (int k = 0; k < c.nitems; ++k) base[k + 1] = base[k] + seg[c.item0 + k].nb;
@@ -549,11 +596,10 @@ k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const 
         int k = 0;
         while (base[k + 1] <= t) ++k;
         const int i = t - base[k];
-        const Seg sg = seg[c.item0 + k];
-        e[t] = eig[sg.f_off + i];
+        e[t] = eig[foffs[k] + i];
         kk[t] = (short)k;
         ii[t] = (short)i;
-        f[sg.f_off + i] = 0.0;
+        fv[t] = 0.0;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ns; t += blockDim.x) {
@@ -565,32 +611,25 @@ k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const 
         order[r] = t;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double rem = c.ne;
-    int j = 0;
-    while (j < ns && rem > 1e-12) {
-        const double e0 = e[order[j]];
-        const int j0 = j;
-        ++j;
-        while (j < ns && e[order[j]] - e0 < DEGEN_TOL) ++j;
-        double cap = 0;
-        for (int t = j0; t < j; ++t) cap += 2.0 * seg[c.item0 + kk[order[t]]].wk;
-        if (cap <= rem + 1e-12) {
-            for (int t = j0; t < j; ++t) {
-                const int u = order[t];
-                f[seg[c.item0 + kk[u]].f_off + ii[u]] = 2.0;
-            }
-            rem -= cap;
-        } else {
-            const double frac = rem / cap;
-            for (int t = j0; t < j; ++t) {
-                const int u = order[t];
-                f[seg[c.item0 + kk[u]].f_off + ii[u]] = 2.0 * frac;
-            }
-            rem = 0.0;
+    if (threadIdx.x == 0) {
+        double rem = c.ne;
+        int j = 0;
+        while (j < ns && rem > 1e-12) {
+            const double e0 = e[order[j]];
+            const int j0 = j;
+            ++j;
+            while (j < ns && e[order[j]] - e0 < DEGEN_TOL) ++j;
+            double cap = 0;
+            for (int t = j0; t < j; ++t) cap += 2.0 * wks[kk[order[t]]];
+            const bool fits = cap <= rem + 1e-12;
+            const double val = fits ? 2.0 : 2.0 * (rem / cap);
+            for (int t = j0; t < j; ++t) fv[order[t]] = val;
+            rem = fits ? rem - cap : 0.0;
         }
+        if (rem > 1e-9) atomicOr(status, DPP_STATUS_NOBANDS);
     }
-    if (rem > 1e-9) atomicOr(status, DPP_STATUS_NOBANDS);
+    __syncthreads();
+    for (int t = threadIdx.x; t < ns; t += blockDim.x) f[foffs[kk[t]] + ii[t]] = fv[t];
 }
 
 }  // namespace dpp

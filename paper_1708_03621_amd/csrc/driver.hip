@@ -60,6 +60,7 @@ struct ItemTable {
     std::vector<FftItem> h;
     CellDesc* d_cells = nullptr;
     size_t dens_elems = 0;
+    XzPlan xz;   // items grouped by x length for the register x pass
 };
 
 struct ScfGraph {
@@ -118,6 +119,8 @@ struct dpp_system_s {
     dpp_precision prec = DPP_F64, bulk_prec = DPP_F64;
     double refine_res = 0.0, last_res = -1.0;
     std::vector<double> cell_res;
+    // launch choices (set by dpp_system_tune)
+    bool reg_xpass = true;  // register-resident x pass of H where S0 is compiled in
     // graphs
     bool graph_on = false;
     hipStream_t cap_stream = nullptr;
@@ -245,6 +248,15 @@ dpp_status items_for(dpp_system_s* s, int nbo, const ItemTable** out) {
     DPP_TRY(dalloc_t(s, &t.d_cells, cd.size()));
     DPP_HIP(hipMemcpy(t.d_cells, cd.data(), cd.size() * sizeof(CellDesc), hipMemcpyHostToDevice));
     t.dens_elems = (size_t)poff;
+    std::vector<std::vector<int>> members;
+    t.xz = xz_plan_groups(t.h, members);
+    if (t.xz.S0.size() > 1)
+        for (size_t g = 0; g < members.size(); ++g) {
+            int* d = nullptr;
+            DPP_TRY(dalloc_t(s, &d, members[g].size()));
+            DPP_HIP(hipMemcpy(d, members[g].data(), members[g].size() * sizeof(int), hipMemcpyHostToDevice));
+            t.xz.idx[g] = d;
+        }
     auto ins = s->items.emplace(nbo, std::move(t));
     *out = &ins.first->second;
     return DPP_OK;
@@ -284,6 +296,8 @@ struct RotJob {
     const double2* M;   // item matrices at moff (row length = bands)
     double beta;
     double2* out;
+    const double2* X2 = nullptr;  // optional second term out += X2 M2
+    const double2* M2 = nullptr;
 };
 
 dpp_status rotate_jobs(dpp_system_s* s, int nbo, const std::vector<RotJob>& jobs, const int* act = nullptr) {
@@ -294,6 +308,11 @@ dpp_status rotate_jobs(dpp_system_s* s, int nbo, const std::vector<RotJob>& jobs
             RotTask r = make_rot_task((int)s->npw[k], nb, j.X + s->off[k], s->npw[k], nb, j.M + s->moff[k], nb, j.beta,
                                       j.out + s->off[k], s->npw[k]);
             r.item = k;
+            if (j.X2) {
+                r.nbX2 = nb;
+                r.X2 = j.X2 + s->off[k];
+                r.M2 = j.M2 + s->moff[k];
+            }
             t.push_back(r);
         }
     const RotTask* d = nullptr;
@@ -309,10 +328,11 @@ dpp_status apply_H_all(dpp_system_s* s, int nbo, const double2* X, double2* HX, 
         for (int k = 0; k < s->nit; ++k) s->hc_bandk += nb_of(s, nbo, k);
     const ItemTable* it;
     DPP_TRY(items_for(s, nbo, &it));
+    const XzPlan* plan = s->reg_xpass ? &it->xz : nullptr;
     if (s->prec == DPP_F64)
-        DPP_TRY(apply_H_local_batched<double>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act));
+        DPP_TRY(apply_H_local_batched<double>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act, plan));
     else
-        DPP_TRY(apply_H_local_batched<float>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act));
+        DPP_TRY(apply_H_local_batched<float>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act, plan));
     if (s->maxnproj > 0) {
         std::vector<OvTask> t;
         std::vector<RotTask> r;
@@ -421,8 +441,10 @@ dpp_status dots_host(dpp_system_s* s, int nbo, int npair, const double2* const* 
 dpp_status smm(dpp_system_s* s, int nbo, int opA, int opB, double alpha, int alpha_omega, const double2* A,
                const double2* B, double beta, double2* C) {
     TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
-    hipLaunchKernelGGL(k_smm, dim3(s->nit), dim3(256), 0, stream(s), s->d_seg, nbo, opA, opB, alpha, alpha_omega, A, B,
-                       beta, C);
+    const int n = nbo > 0 ? nbo : s->maxnb;
+    const int tn = (n + 15) / 16;
+    hipLaunchKernelGGL(k_smm_mfma, dim3(tn * tn, s->nit), dim3(64), 0, stream(s), s->d_seg, nbo, opA, opB, alpha,
+                       alpha_omega, A, B, beta, C);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -504,7 +526,7 @@ dpp_status pulay_mix(dpp_system_s* s) {
     hipLaunchKernelGGL(k_pulay_dots, dim3(MDOT_BLOCKS, s->ncells), dim3(256), 0, stream(s), s->Ntot,
                        (const int*)s->d_pst, s->d_cells, (const double*)s->hist_r, s->d_part);
     DPP_LAUNCHED();
-    hipLaunchKernelGGL(k_pulay_solve_cells, dim3((s->ncells + 63) / 64), dim3(64), 0, stream(s), s->ncells,
+    hipLaunchKernelGGL(k_pulay_solve_cells, dim3(s->ncells), dim3(256), 0, stream(s), s->ncells,
                        (const int*)s->d_pst, s->d_cells, (const double*)s->d_part, s->pulayA, s->pulayC,
                        s->ctx->d_status);
     DPP_LAUNCHED();
@@ -525,11 +547,11 @@ dpp_status grad_B(dpp_system_s* s, const double2* Y) {
     DPP_TRY(smm(s, 0, 0, 1, 1.0, 0, s->Rinv, s->Rinv, 0.0, s->M1));
     DPP_TRY(smm(s, 0, 0, 0, 1.0, 0, s->M1, s->H0, 0.0, s->Rt));
     DPP_TRY(smm(s, 0, 0, 0, -1.0, 1, s->Rt, s->M1, 0.0, s->M2));
-    DPP_TRY(rotate_jobs(s, 0, {RotJob{s->HY, s->M1, 0.0, s->g}}));
-    DPP_TRY(rotate_jobs(s, 0, {RotJob{Y, s->M2, 1.0, s->g}}));
+    // g = HY Uinv + Y M2 in one pass
+    DPP_TRY(rotate_jobs(s, 0, {RotJob{s->HY, s->M1, 0.0, s->g, Y, s->M2}}));
+    // E0 = Tr(Uinv H0) = Re Tr(Rt)
     TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
-    hipLaunchKernelGGL(k_trace_RhHR, dim3(s->nit), dim3(256), 0, stream(s), s->d_seg, 0, (const double2*)s->Rinv,
-                       (const double2*)s->H0, s->d_bE0);
+    hipLaunchKernelGGL(k_trace_diag, dim3(s->nit), dim3(64), 0, stream(s), s->d_seg, (const double2*)s->Rt, s->d_bE0);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -546,7 +568,8 @@ dpp_status line_mats_B(dpp_system_s* s, const double2* Y, const int* act) {
 
 dpp_status linesearch_B(dpp_system_s* s, const int* act, const double* d0, int* ok, double* step) {
     const int n = s->maxnb;
-    const size_t lds = (size_t)n * (n + 1) / 2 * sizeof(double2);
+    const int stage = n <= 64;  // H(a) staged in LDS beside the packed factor
+    const size_t lds = (size_t)n * (n + 1) / 2 * sizeof(double2) + (stage ? (size_t)n * n * sizeof(double2) : 0);
     if (lds > 64 * 1024)
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_linesearch_B),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -554,7 +577,7 @@ dpp_status linesearch_B(dpp_system_s* s, const int* act, const double* d0, int* 
     hipLaunchKernelGGL(k_linesearch_B, dim3(s->nit), dim3(n <= 64 ? 64 : 256), lds, stream(s), s->d_seg,
                        (const double2*)s->U, (const double2*)s->X, (const double2*)s->Q, (const double2*)s->H0,
                        (const double2*)s->H1, (const double2*)s->H2, (const double*)s->d_bE0,
-                       (const double*)s->cg.at, d0, act, ok, step);
+                       (const double*)s->cg.at, d0, act, ok, step, stage);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -577,12 +600,15 @@ dpp_status cgB_init(dpp_system_s* s, double2* Y) {
 
 dpp_status cgB_step(dpp_system_s* s, double2* Y) {
     const unsigned ib = item_threads_blocks(s);
-    DPP_TRY(precond_all(s, 0, s->g, s->Kg));
-    const double2* pa[3] = {s->g, s->gp, s->g};
-    const double2* pb[3] = {s->Kg, s->Kg, s->Dp};
-    DPP_TRY(dots_dev(s, 0, 3, pa, pb));
-    hipLaunchKernelGGL(k_cgB_direction, dim3(ib), dim3(64), 0, stream(s), s->nit, (const double*)s->d_dots, s->cg);
-    DPP_LAUNCHED();
+    {
+        TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
+        hipLaunchKernelGGL(k_cg_precond_dots, dim3(DOT_BLOCKS, s->nit), dim3(256), 0, stream(s), s->d_seg, s->nit,
+                           (const double2*)s->g, (const double2*)s->gp, (const double2*)s->Dp, s->Kg, s->d_part);
+        DPP_LAUNCHED();
+        hipLaunchKernelGGL(k_cgB_reduce_direction, dim3(s->nit), dim3(64), 0, stream(s), s->nit,
+                           (const double*)s->d_part, s->d_dots, s->cg);
+        DPP_LAUNCHED();
+    }
     DPP_TRY(axpby_all(s, 0, s->cg.cK, s->Kg, s->cg.beta, s->Dp, s->Dd));
     DPP_TRY(line_mats_B(s, Y, nullptr));
     DPP_TRY(linesearch_B(s, s->cg.act, s->cg.d0, s->cg.ok, s->cg.step));
@@ -594,11 +620,14 @@ dpp_status cgB_step(dpp_system_s* s, double2* Y) {
     DPP_TRY(linesearch_B(s, s->cg.retry, s->cg.d0r, s->cg.ok2, s->cg.step2));
     hipLaunchKernelGGL(k_cgB_finish, dim3(ib), dim3(64), 0, stream(s), s->nit, (const double*)s->d_dots, s->cg);
     DPP_LAUNCHED();
-    DPP_TRY(axpby_all(s, 0, s->d_ones, Y, s->cg.step, s->Dd, Y));
-    DPP_TRY(axpby_all(s, 0, s->d_ones, s->HY, s->cg.step, s->HD, s->HY));
-    // history for the next direction
-    DPP_TRY(copy_blocks(s, s->g, s->gp));
-    DPP_TRY(copy_blocks(s, s->Dd, s->Dp));
+    {
+        // Y += step D, HY += step HD; history for the next direction
+        TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
+        hipLaunchKernelGGL(k_cgB_update, dim3(seg_blocks(s, 0), s->nit), dim3(256), 0, stream(s), s->d_seg,
+                           (const double*)s->cg.step, Y, (const double2*)s->Dd, s->HY, (const double2*)s->HD,
+                           (const double2*)s->g, s->gp, s->Dp);
+        DPP_LAUNCHED();
+    }
     DPP_TRY(grad_B(s, Y));
     return DPP_OK;
 }
@@ -610,13 +639,13 @@ dpp_status subspace_rotate(dpp_system_s* s, double2* Y) {
     DPP_TRY(overlap_jobs(s, 0, {OvJob{s->psi, s->T1, 1.0, false, s->H0}}));
     {
         const int n = s->maxnb;
-        const size_t lds = n <= 64 ? (size_t)2 * n * n * sizeof(double2) : 0;
+        const size_t lds = eigh_lds(n);
         if (lds > 64 * 1024)
             DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh_seg),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         TimerScope ts_(s->ctx, DPP_TK_EIGH);
         hipLaunchKernelGGL(k_jacobi_eigh_seg, dim3(s->nit), dim3(n <= 32 ? 64 : 256), lds, stream(s), s->d_seg,
-                           (const double2*)s->H0, s->d_eig, s->vecs, n <= 64 ? (double2*)nullptr : s->eig_scr);
+                           (const double2*)s->H0, s->d_eig, s->vecs, s->eig_scr);
         DPP_LAUNCHED();
     }
     DPP_TRY(rotate_jobs(s, 0, {RotJob{s->psi, s->vecs, 0.0, Y}, RotJob{s->T1, s->vecs, 0.0, s->HY}}));

@@ -22,6 +22,7 @@
 #include <cmath>
 
 #include "fft_engine.h"
+#include "fft_reg.h"
 #include "internal.h"
 
 namespace dpp {
@@ -203,10 +204,12 @@ __device__ __forceinline__ void xz_store_pruned(const FftItem& it, typename cx<T
 template <typename T, int MODE, typename TIO, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_xz(const FftItem* items, FftItem single, typename cx<T>::t* __restrict__ Tb,
-     const double* __restrict__ V, TIO* __restrict__ box, const int* __restrict__ act) {
+     const double* __restrict__ V, TIO* __restrict__ box, const int* __restrict__ act,
+     const int* __restrict__ idx = nullptr) {
     using Cx = typename cx<T>::t;
-    if (BATCH && act && !act[blockIdx.z]) return;
-    const FftItem& it = DPP_ITEM(items, single);
+    const int item = (BATCH && idx) ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (BATCH && act && !act[item]) return;
+    const FftItem& it = BATCH ? items[item] : single;
     const int i1 = blockIdx.x, b = blockIdx.y;
     if (i1 >= it.S1 || b >= it.nb) return;
     extern __shared__ char smem_raw[];
@@ -247,6 +250,85 @@ k_xz(const FftItem* items, FftItem single, typename cx<T>::t* __restrict__ Tb,
     __syncthreads();
     fft_axis<T, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], -1);
     xz_store_pruned<T>(it, Tb, b, i1, lds);
+}
+
+// Register-resident x pass of H: one thread per (item, band, i1, i2) column.
+// Gather the pruned rows into registers (zeros elsewhere), inverse transform
+// along x (decimation in frequency: register p then holds x point
+// digit_rev(p)), multiply by (Omega/N) V_eff there, transform back
+// (decimation in time: natural order again), store the pruned rows.  No LDS,
+// no barriers; every load and store is coalesced across the i2 of a wave.
+template <typename T, int S0>
+__global__ void __launch_bounds__(256)
+k_xz_reg(const FftItem* __restrict__ items, const int* __restrict__ idx, typename cx<T>::t* __restrict__ Tb,
+         const double* __restrict__ V, const int* __restrict__ act) {
+    using Cx = typename cx<T>::t;
+    const int item = idx ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (act && !act[item]) return;
+    const FftItem& it = items[item];
+    const int b = blockIdx.y;
+    if (b >= it.nb) return;
+    const int np = it.S1 * it.S2;
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= np) return;
+    const int nP = it.nplanes;
+    Cx* base = Tb + it.t_off + (int64_t)b * nP * np + col;
+    Cx x[S0];
+#pragma unroll
+    for (int i0 = 0; i0 < S0; ++i0) {
+        int d = (i0 - it.n0min) % S0;
+        d += d < 0 ? S0 : 0;
+        x[i0] = d < nP ? base[(int64_t)d * np] : Cx{0, 0};
+    }
+    const double2* tw64 = it.tw64[0];
+    const float2* tw32 = it.tw32[0];
+    reg_dif<T, S0, +1, 0>(x, tw64, tw32);
+    const double* Vp = V + it.v_off + col;
+    const T sc = (T)it.vscale;
+#pragma unroll
+    for (int p = 0; p < S0; ++p) {
+        const int k = reg_digit_rev(S0, p);
+        const T v = (T)Vp[(int64_t)k * np] * sc;
+        x[p] = Cx{x[p].x * v, x[p].y * v};
+    }
+    reg_dit<T, S0, -1, 0>(x, tw64, tw32);
+#pragma unroll
+    for (int i0 = 0; i0 < S0; ++i0) {
+        int d = (i0 - it.n0min) % S0;
+        d += d < 0 ? S0 : 0;
+        if (d < nP) base[(int64_t)d * np] = x[i0];
+    }
+}
+
+// Register x pass lengths: FP64 up to 45 and FP32 up to 64 points keep every
+// column in registers without scratch spills on gfx950.
+template <typename T, int N>
+static bool xz_reg_one(dim3 grid, hipStream_t st, const FftItem* items, const int* idx, typename cx<T>::t* Tb,
+                       const double* V, const int* act) {
+    if constexpr (sizeof(T) == 8 && N > 45) {
+        return false;
+    } else {
+        hipLaunchKernelGGL((k_xz_reg<T, N>), grid, dim3(256), 0, st, items, idx, Tb, V, act);
+        return true;
+    }
+}
+
+// Launch the register x pass for one S0 group; false if S0 is not compiled in
+// for this precision (the caller then uses the LDS pass).
+template <typename T>
+static bool xz_reg_launch(int S0, dim3 grid, hipStream_t st, const FftItem* items, const int* idx,
+                          typename cx<T>::t* Tb, const double* V, const int* act) {
+    switch (S0) {
+#define DPP_XZ_REG(n) \
+    case n:           \
+        return xz_reg_one<T, n>(grid, st, items, idx, Tb, V, act);
+        DPP_XZ_REG(12) DPP_XZ_REG(15) DPP_XZ_REG(16) DPP_XZ_REG(18) DPP_XZ_REG(20) DPP_XZ_REG(24)
+        DPP_XZ_REG(25) DPP_XZ_REG(27) DPP_XZ_REG(30) DPP_XZ_REG(32) DPP_XZ_REG(36) DPP_XZ_REG(40)
+        DPP_XZ_REG(45) DPP_XZ_REG(48) DPP_XZ_REG(50) DPP_XZ_REG(54) DPP_XZ_REG(60) DPP_XZ_REG(64)
+#undef DPP_XZ_REG
+        default:
+            return false;
+    }
 }
 
 // Full-box x pass: plane buffer (all S0 planes) -> transform along x (sign)
@@ -574,7 +656,7 @@ static dpp_status pass2(dpp_ctx_s* cx_, const FftItem& it, typename cx<T>::t* Tb
     Launch L = xz_launch(it.S0, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_xz<T, MODE, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(it.S1, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, Tb, V, box,
-                                       (const int*)nullptr));
+                                       (const int*)nullptr, (const int*)nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -657,9 +739,33 @@ BatchShape batch_shape(const std::vector<FftItem>& h, bool fp64) {
 
 // One launch per pass for every item of the table (items may differ in box,
 // sphere and band count).
+XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int>>& members) {
+    XzPlan p;
+    members.clear();
+    for (size_t k = 0; k < h.size(); ++k) {
+        const FftItem& it = h[k];
+        size_t g = 0;
+        while (g < p.S0.size() && p.S0[g] != it.S0) ++g;
+        if (g == p.S0.size()) {
+            p.S0.push_back(it.S0);
+            p.count.push_back(0);
+            p.maxS1S2.push_back(0);
+            p.nbm.push_back(0);
+            p.idx.push_back(nullptr);
+            members.emplace_back();
+        }
+        p.count[g]++;
+        p.maxS1S2[g] = std::max(p.maxS1S2[g], it.S1 * it.S2);
+        p.nbm[g] = std::max(p.nbm[g], it.nb);
+        members[g].push_back((int)k);
+    }
+    return p;
+}
+
 template <typename T>
 dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,
-                                 const double2* X, double2* HX, const double* V, void* Tbv, const int* act) {
+                                 const double2* X, double2* HX, const double* V, void* Tbv, const int* act,
+                                 const XzPlan* plan) {
     using Cx = typename cx<T>::t;
     if (h.empty()) return DPP_OK;
     Cx* Tb = reinterpret_cast<Cx*>(Tbv);
@@ -685,10 +791,25 @@ dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const s
     }
     {
         TimerScope ts_(cx_, DPP_TK_XZ_H, b2);
-        DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz<T, XZ_H, double2, NT_, true>; DPP_TRY(set_lds(k, bs.xz.lds));
-                        hipLaunchKernelGGL(k, dim3(bs.maxS1, bs.nbm, nit), dim3(NT_), bs.xz.lds, st, d_items, i0, Tb,
-                                           V, (double2*)nullptr, act));
-        DPP_LAUNCHED();
+        if (plan) {
+            for (size_t g = 0; g < plan->S0.size(); ++g) {
+                const dim3 grid((unsigned)((plan->maxS1S2[g] + 255) / 256), (unsigned)plan->nbm[g],
+                                (unsigned)plan->count[g]);
+                if (!xz_reg_launch<T>(plan->S0[g], grid, st, d_items, plan->idx[g], Tb, V, act)) {
+                    DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz<T, XZ_H, double2, NT_, true>;
+                                    DPP_TRY(set_lds(k, bs.xz.lds));
+                                    hipLaunchKernelGGL(k, dim3(bs.maxS1, plan->nbm[g], plan->count[g]), dim3(NT_),
+                                                       bs.xz.lds, st, d_items, i0, Tb, V, (double2*)nullptr, act,
+                                                       plan->idx[g]));
+                }
+                DPP_LAUNCHED();
+            }
+        } else {
+            DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz<T, XZ_H, double2, NT_, true>; DPP_TRY(set_lds(k, bs.xz.lds));
+                            hipLaunchKernelGGL(k, dim3(bs.maxS1, bs.nbm, nit), dim3(NT_), bs.xz.lds, st, d_items, i0,
+                                               Tb, V, (double2*)nullptr, act, (const int*)nullptr));
+            DPP_LAUNCHED();
+        }
     }
     {
         TimerScope ts_(cx_, DPP_TK_PLANES_OUT, b3);
@@ -701,9 +822,11 @@ dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const s
     return DPP_OK;
 }
 template dpp_status apply_H_local_batched<double>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
-                                                  const double2*, double2*, const double*, void*, const int*);
+                                                  const double2*, double2*, const double*, void*, const int*,
+                                                  const XzPlan*);
 template dpp_status apply_H_local_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
-                                                 const double2*, double2*, const double*, void*, const int*);
+                                                 const double2*, double2*, const double*, void*, const int*,
+                                                 const XzPlan*);
 
 template <typename T>
 dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,

@@ -181,13 +181,23 @@ size_t grid_coef_offset(const dpp_grid_s* g);
 
 // Batched passes over a table of items (one per k-point or cell/k pair);
 // h_items mirrors the device table d_items.  Tb holds every item's planes.
+// Items of a table grouped by x length S0 (the register x pass is compiled
+// per S0): group g holds count[g] items listed in the device array idx[g]
+// (nullptr when the group is the whole table in order).
+struct XzPlan {
+    std::vector<int> S0, count, maxS1S2, nbm;
+    std::vector<const int*> idx;
+};
+XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int>>& members);
+
 // Items may have different boxes: the launch takes the largest workgroup and
 // LDS size any item needs.  `act` (nullable) masks items: inactive items do
-// nothing.
+// nothing.  With `plan`, the x pass runs one register-resident launch per S0
+// group where that length is compiled in.
 template <typename T>
 dpp_status apply_H_local_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
                                  const double2* X, double2* HX, const double* V, void* Tb,
-                                 const int* act = nullptr);
+                                 const int* act = nullptr, const XzPlan* plan = nullptr);
 // Band-chunk partial densities of every item (item p_off, dnch, dchunk), then
 // per cell n[foff + j] = sum of the cell's partials (fixed order).
 template <typename T>
@@ -241,7 +251,9 @@ struct RotTask {
     int npw, nbX, nbO, M_ld;
     double beta;
     int item;          // work item (index into an activity mask)
-    int pad;
+    int nbX2;          // optional second term out += X2 M2 (0: none; same ldX, M_ld)
+    const double2* X2;
+    const double2* M2;
 };
 OvTask make_ov_task(int npw, int nbA, const double2* A, int64_t ldA, int nbB, const double2* B, int64_t ldB,
                     double scale, double2* out, int out_ld);
@@ -257,6 +269,7 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
                        const double2* B, int64_t ldB, double scale, double2* U, void* ws,
                        size_t ws_bytes);
 size_t overlap_ws_bytes(int npw, int nbA, int nbB);
+size_t eigh_lds(int nmax);   // LDS bytes of the eigensolver for matrices up to nmax
 size_t proj_ws_bytes(const dpp_basis_s* b, int nb);
 dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
                       const double2* M, double beta, double2* out, int64_t ldout);
