@@ -257,7 +257,7 @@ typedef struct {
     int nk;                 /* k-points (<= 64)                            */
     const double *kpts;     /* nk x 3 reduced                              */
     const double *wk;       /* nk weights (sum 1)                          */
-    int nb;                 /* bands per k-point (<= 128; nk nb <= 2048)   */
+    int nb;                 /* bands per k-point (<= 128; nk nb <= 1024)   */
     double n_electrons;
     int nat;
     const double *tau;      /* nat x 3 Cartesian                           */

@@ -509,21 +509,20 @@ constexpr int LS_MAX_TRIES = 6;
 // Trial energy at step a.  With `Hs` (LDS, n^2 entries) H(a) is staged once
 // per trial; otherwise its entries are formed from global memory in the trace.
 __device__ double trial_energy(const Seg& sg, double a, const double2* __restrict__ U,
-                               const double2* __restrict__ X, const double2* __restrict__ Q,
-                               const double2* __restrict__ H0, const double2* __restrict__ H1,
+                               const double2* __restrict__ Xs, const double2* __restrict__ Q,
+                               const double2* __restrict__ H0, const double2* __restrict__ Ps,
                                const double2* __restrict__ H2, double2* __restrict__ A, double2* __restrict__ Hs) {
     __shared__ double red[256];
     const int n = sg.nb;
     const int64_t o = sg.moff;
+    // Xs = X + X^dag and Ps = H1 + H1^dag (prepared by the caller)
     auto loadU = [&](int r, int c) {
-        const double2 x = X[o + r * n + c], xt = X[o + c * n + r];
-        const double2 u = U[o + r * n + c], q = Q[o + r * n + c];
-        return double2{u.x + a * (x.x + xt.x) + a * a * q.x, u.y + a * (x.y - xt.y) + a * a * q.y};
+        const double2 x = Xs[o + r * n + c], u = U[o + r * n + c], q = Q[o + r * n + c];
+        return double2{u.x + a * x.x + a * a * q.x, u.y + a * x.y + a * a * q.y};
     };
     auto Hat = [&](int r, int c) {
-        const double2 h = H1[o + r * n + c], ht = H1[o + c * n + r];
-        const double2 h0 = H0[o + r * n + c], h2 = H2[o + r * n + c];
-        return double2{h0.x + a * (h.x + ht.x) + a * a * h2.x, h0.y + a * (h.y - ht.y) + a * a * h2.y};
+        const double2 h = Ps[o + r * n + c], h0 = H0[o + r * n + c], h2 = H2[o + r * n + c];
+        return double2{h0.x + a * h.x + a * a * h2.x, h0.y + a * h.y + a * a * h2.y};
     };
     if (Hs)
         for (int e = threadIdx.x; e < n * n; e += blockDim.x) Hs[e] = Hat(e / n, e % n);
@@ -561,23 +560,36 @@ k_linesearch_B(const Seg* __restrict__ seg, const double2* __restrict__ U, const
                const double2* __restrict__ Q, const double2* __restrict__ H0, const double2* __restrict__ H1,
                const double2* __restrict__ H2, const double* __restrict__ E0v, const double* __restrict__ at0,
                const double* __restrict__ d0v, const int* __restrict__ act, int* __restrict__ ok,
-               double* __restrict__ step, int stage_h) {
+               double* __restrict__ step, int stage_h, double2* __restrict__ Xs, double2* __restrict__ Ps) {
     const int k = blockIdx.x;
     if (!act[k]) return;
     extern __shared__ char smem_raw[];
     double2* A = reinterpret_cast<double2*>(smem_raw);
     const Seg sg = seg[k];
     double2* Hs = stage_h ? A + sg.nb * (sg.nb + 1) / 2 : nullptr;
+    {
+        // symmetric parts of the line matrices, read coalesced by every trial
+        const int n = sg.nb;
+        const int64_t o = sg.moff;
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int r = e / n, c = e - r * n;
+            const double2 x = X[o + e], xt = X[o + c * n + r];
+            const double2 h = H1[o + e], ht = H1[o + c * n + r];
+            Xs[o + e] = double2{x.x + xt.x, x.y - xt.y};
+            Ps[o + e] = double2{h.x + ht.x, h.y - ht.y};
+        }
+        __syncthreads();
+    }
     const double E0 = E0v[k], d0 = d0v[k];
     double at = at0[k];
     int good = 0;
     double st = 0.0;
     for (int t = 0; t < LS_MAX_TRIES; ++t) {
-        const double Et = trial_energy(sg, at, U, X, Q, H0, H1, H2, A, Hs);
+        const double Et = trial_energy(sg, at, U, Xs, Q, H0, Ps, H2, A, Hs);
         const double c = (Et - E0 - d0 * at) / (at * at);
         double as = c > 0 ? -d0 / (2.0 * c) : 2.0 * at;
         as = fmin(as, 10.0 * at);
-        const double Es = trial_energy(sg, as, U, X, Q, H0, H1, H2, A, Hs);
+        const double Es = trial_energy(sg, as, U, Xs, Q, H0, Ps, H2, A, Hs);
         if (Es <= E0) {
             good = 1;
             st = as;
@@ -608,8 +620,9 @@ k_linesearch_B(const Seg* __restrict__ seg, const double2* __restrict__ U, const
 // and A <- J^dag A J, V <- V J.  A is kept as its packed upper triangle in
 // LDS (Hermitian), so a round is one pass over 2x2 blocks (pair s', pair s):
 // B <- J_s'^dag B J_s, each stored element touched once; the diagonal blocks
-// become diagonal exactly.  V (n x n) lives in LDS for n <= 64, else in the
-// caller's global scratch.
+// become diagonal exactly.  V is kept transposed (row p of Vt = column p of
+// V, so a rotation touches two contiguous rows) in LDS for n <= 64, else in
+// the caller's global scratch.
 constexpr int EIG_MAXN = 128;
 constexpr int EIG_SWEEPS = 40;
 
@@ -648,7 +661,7 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
     const int m = n + (n & 1);
     const int P = m / 2;
     double2* A = lds;
-    double2* V = n <= 64 ? lds + n * (n + 1) / 2 : scr;
+    double2* Vt = n <= 64 ? lds + n * (n + 1) / 2 : scr;
     __shared__ Rot rot[EIG_MAXN / 2];
     __shared__ double red[256];
     __shared__ double dg[EIG_MAXN];
@@ -661,21 +674,16 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
             if (r == c) h.y = 0.0;
             A[up_idx(n, r, c)] = h;
         }
-        V[e] = double2{r == c ? 1.0 : 0.0, 0.0};
+        Vt[e] = double2{r == c ? 1.0 : 0.0, 0.0};
     }
     __syncthreads();
-    const int nblk = P * (P + 1) / 2;
     for (int sweep = 0; sweep < EIG_SWEEPS; ++sweep) {
         // convergence: off-diagonal Frobenius norm vs diagonal scale
         double off = 0, dia = 0;
-        for (int e = threadIdx.x; e < n * (n + 1) / 2; e += blockDim.x) {
-            int r = 0, rem = e;
-            while (rem >= n - r) {
-                rem -= n - r;
-                ++r;
-            }
-            const int c = r + rem;
-            const double2 a = A[e];
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int r = e / n, c = e - r * n;
+            if (c < r) continue;
+            const double2 a = A[up_idx(n, r, c)];
             if (r != c)
                 off += 2.0 * (a.x * a.x + a.y * a.y);
             else
@@ -696,9 +704,14 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
             __syncthreads();
         }
         const double diat = red[0];
-        if (threadIdx.x == 0) done = (offt <= 1e-30 * fmax(diat, 1e-300)) || offt == 0.0;
+        // converged once the off-diagonal part is 1e-14 of the Frobenius norm
+        // (the rounding noise of the rotations sits near 1e-16 n^(1/2))
+        const double fro2 = offt + diat;
+        if (threadIdx.x == 0) done = (offt <= 1e-28 * fmax(fro2, 1e-300)) || offt == 0.0;
         __syncthreads();
         if (done) break;
+        // pairs below the rounding level of the matrix are not rotated
+        const double skip = 1e-16 * sqrt(fro2);
         for (int round = 0; round < m - 1; ++round) {
             for (int s = threadIdx.x; s < P; s += blockDim.x) {
                 int p, q;
@@ -719,7 +732,7 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
                     const double2 c = A[up_idx(n, p, q)];
                     const double ac = sqrt(c.x * c.x + c.y * c.y);
                     const double app = A[up_idx(n, p, p)].x, aqq = A[up_idx(n, q, q)].x;
-                    if (ac > 1e-300 && ac > 1e-18 * sqrt(fabs(app * aqq))) {
+                    if (ac > skip && ac > 1e-300) {
                         const double tau = (aqq - app) / (2.0 * ac);
                         const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         R.cs = 1.0 / sqrt(1.0 + t * t);
@@ -734,13 +747,9 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
             }
             __syncthreads();
             // A: every 2x2 block (pair s2 rows, pair s1 columns), s2 <= s1
-            for (int bk = threadIdx.x; bk < nblk; bk += blockDim.x) {
-                int s2 = 0, rem = bk;
-                while (rem >= P - s2) {
-                    rem -= P - s2;
-                    ++s2;
-                }
-                const int s1 = s2 + rem;
+            for (int bk = threadIdx.x; bk < P * P; bk += blockDim.x) {
+                const int s2 = bk / P, s1 = bk - s2 * P;
+                if (s2 > s1) continue;
                 const Rot Rc = rot[s1], Rr = rot[s2];
                 const bool idc = Rc.q < 0 || (Rc.sn == 0.0 && Rc.er == 1.0 && Rc.ei == 0.0);
                 const bool idr = Rr.q < 0 || (Rr.sn == 0.0 && Rr.er == 1.0 && Rr.ei == 0.0);
@@ -788,15 +797,15 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
                     for (int j = 0; j < 2; ++j)
                         if (xr[i] >= 0 && xr[i] < n && yc[j] >= 0 && yc[j] < n) hset(A, n, xr[i], yc[j], B[i][j]);
             }
-            // V <- V J (columns p, q of every row)
+            // V <- V J: columns p, q of V are rows p, q of Vt
             for (int e = threadIdx.x; e < P * n; e += blockDim.x) {
                 const int sidx = e / n, r = e - sidx * n;
                 const Rot R = rot[sidx];
                 if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
                 const double2 e2 = double2{R.er, R.ei};
-                const double2 vp = V[r * n + R.p], eq = cmulz(e2, V[r * n + R.q]);
-                V[r * n + R.p] = double2{R.cs * vp.x - R.sn * eq.x, R.cs * vp.y - R.sn * eq.y};
-                V[r * n + R.q] = double2{R.sn * vp.x + R.cs * eq.x, R.sn * vp.y + R.cs * eq.y};
+                const double2 vp = Vt[R.p * n + r], eq = cmulz(e2, Vt[R.q * n + r]);
+                Vt[R.p * n + r] = double2{R.cs * vp.x - R.sn * eq.x, R.cs * vp.y - R.sn * eq.y};
+                Vt[R.q * n + r] = double2{R.sn * vp.x + R.cs * eq.x, R.sn * vp.y + R.cs * eq.y};
             }
             __syncthreads();
         }
@@ -813,7 +822,7 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
     for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = dg[perm[i]];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int r = e / n, c = e - r * n;
-        vo[e] = V[r * n + perm[c]];
+        vo[e] = Vt[perm[c] * n + r];
     }
 }
 

@@ -29,7 +29,7 @@ struct DotPairs {
 };
 
 constexpr int MDOT_BLOCKS = 256;
-constexpr int AUFBAU_MAX = 2048;       // states (k-points x bands) of one cell
+constexpr int AUFBAU_MAX = 1024;       // states (k-points x bands) of one cell
 constexpr int AUFBAU_MAX_ITEMS = 64;   // k-points of one cell
 constexpr double DEGEN_TOL = 1e-6;     // degenerate-set width of the aufbau fillings (Ha)
 
@@ -88,6 +88,6 @@ __global__ void k_jacobi_eigh_seg(const Seg* seg, const double2* H, double* eig,
 __global__ void k_linesearch_B(const Seg* seg, const double2* U, const double2* X, const double2* Q,
                                const double2* H0, const double2* H1, const double2* H2, const double* E0v,
                                const double* at0, const double* d0v, const int* act, int* ok, double* step,
-                               int stage_h);
+                               int stage_h, double2* Xs, double2* Ps);
 
 }  // namespace dpp

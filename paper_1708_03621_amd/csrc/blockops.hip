@@ -330,6 +330,8 @@ k_pulay_solve_cells(int ncells, const int* __restrict__ st, const CellDesc* __re
         if (threadIdx.x == 0) ov[i] = red[0];
         __syncthreads();
     }
+    __shared__ double M[PULAY_MAX + 1][PULAY_MAX + 2];
+    __shared__ double x[PULAY_MAX + 1];
     if (threadIdx.x != 0) return;
     const double dV = cells[cidx].dV;
     double* Ac = A + (int64_t)cidx * PULAY_MAX * PULAY_MAX;
@@ -343,7 +345,6 @@ k_pulay_solve_cells(int ncells, const int* __restrict__ st, const CellDesc* __re
         c[0] = 1.0;
         return;
     }
-    double M[PULAY_MAX + 1][PULAY_MAX + 2];
     const int n = m + 1;
     for (int i = 0; i < n; ++i) {
         for (int j = 0; j < n; ++j)
@@ -371,7 +372,6 @@ k_pulay_solve_cells(int ncells, const int* __restrict__ st, const CellDesc* __re
             for (int j = col; j <= n; ++j) M[r][j] -= fct * M[col][j];
         }
     }
-    double x[PULAY_MAX + 1];
     for (int i = n - 1; i >= 0; --i) {
         double s = M[i][n];
         for (int j = i + 1; j < n; ++j) s -= M[i][j] * x[j];
@@ -574,7 +574,9 @@ __global__ void __launch_bounds__(256)
 k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const double* __restrict__ eig,
          double* __restrict__ f, int* __restrict__ status) {
     __shared__ double e[AUFBAU_MAX];
-    __shared__ double fv[AUFBAU_MAX];
+    __shared__ double es[AUFBAU_MAX];
+    __shared__ double cs[AUFBAU_MAX];
+    __shared__ double fs[AUFBAU_MAX];
     __shared__ short kk[AUFBAU_MAX];
     __shared__ short ii[AUFBAU_MAX];
     __shared__ int order[AUFBAU_MAX];
@@ -599,7 +601,6 @@ k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const 
         e[t] = eig[foffs[k] + i];
         kk[t] = (short)k;
         ii[t] = (short)i;
-        fv[t] = 0.0;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ns; t += blockDim.x) {
@@ -611,25 +612,36 @@ k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const 
         order[r] = t;
     }
     __syncthreads();
+    // states in sorted order: energy and capacity 2 w_k (reuse kk/ii-free arrays)
+    for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+        const int t = order[j];
+        es[j] = e[t];
+        cs[j] = 2.0 * wks[kk[t]];
+        fs[j] = 0.0;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double rem = c.ne;
         int j = 0;
         while (j < ns && rem > 1e-12) {
-            const double e0 = e[order[j]];
+            const double e0 = es[j];
             const int j0 = j;
             ++j;
-            while (j < ns && e[order[j]] - e0 < DEGEN_TOL) ++j;
+            while (j < ns && es[j] - e0 < DEGEN_TOL) ++j;
             double cap = 0;
-            for (int t = j0; t < j; ++t) cap += 2.0 * wks[kk[order[t]]];
+            for (int t = j0; t < j; ++t) cap += cs[t];
             const bool fits = cap <= rem + 1e-12;
             const double val = fits ? 2.0 : 2.0 * (rem / cap);
-            for (int t = j0; t < j; ++t) fv[order[t]] = val;
+            for (int t = j0; t < j; ++t) fs[t] = val;
             rem = fits ? rem - cap : 0.0;
         }
         if (rem > 1e-9) atomicOr(status, DPP_STATUS_NOBANDS);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < ns; t += blockDim.x) f[foffs[kk[t]] + ii[t]] = fv[t];
+    for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+        const int t = order[j];
+        f[foffs[kk[t]] + ii[t]] = fs[j];
+    }
 }
 
 }  // namespace dpp

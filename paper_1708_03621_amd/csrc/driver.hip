@@ -577,7 +577,7 @@ dpp_status linesearch_B(dpp_system_s* s, const int* act, const double* d0, int* 
     hipLaunchKernelGGL(k_linesearch_B, dim3(s->nit), dim3(n <= 64 ? 64 : 256), lds, stream(s), s->d_seg,
                        (const double2*)s->U, (const double2*)s->X, (const double2*)s->Q, (const double2*)s->H0,
                        (const double2*)s->H1, (const double2*)s->H2, (const double*)s->d_bE0,
-                       (const double*)s->cg.at, d0, act, ok, step, stage);
+                       (const double*)s->cg.at, d0, act, ok, step, stage, s->M1, s->M2);
     DPP_LAUNCHED();
     return DPP_OK;
 }

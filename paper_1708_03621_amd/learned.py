@@ -65,7 +65,7 @@ class Runner:
         D.dpp_system_destroy(s)
         return n0.view((len(cells),) + tuple(cells[0].S))
 
-    def scf(self, cells, n_start, max_iter=80, tol_atom=1e-10):
+    def scf(self, cells, n_start, max_iter=200, tol_atom=1e-10):
         """SCF of all cells from device start densities (ncells, S...);
         returns energies (iterations, ncells) and the last n_out per cell.
         Stops once every cell changed by less than tol_atom per atom in two
@@ -99,7 +99,7 @@ def iterations_to(E, E_ref, nat, tol=1e-6):
     return None
 
 
-def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, seed=502, max_iter=80,
+def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, seed=502, max_iter=200,
         scf_batch=64, log=_log):
     import torch
 
@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--eval", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--first", type=int, default=3, help="band-CG steps of the first SCF iteration")
-    ap.add_argument("--max-iter", type=int, default=80)
+    ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--scf-batch", type=int, default=64, help="cells per batched SCF system")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()

