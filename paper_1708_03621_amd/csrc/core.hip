@@ -347,6 +347,7 @@ static void free_basis(dpp_basis b) {
     if (b->d_miller) hipFree(b->d_miller);
     if (b->d_kG2) hipFree(b->d_kG2);
     if (b->d_planes) hipFree(b->d_planes);
+    if (b->d_rows) hipFree(b->d_rows);
     delete b;
 }
 
@@ -400,6 +401,7 @@ extern "C" dpp_status dpp_basis_create(dpp_grid grid, const double* k_red, doubl
     b->d_miller = nullptr;
     b->d_kG2 = nullptr;
     b->d_planes = nullptr;
+    b->d_rows = nullptr;
     const int S0 = grid->S[0], S1 = grid->S[1], S2 = grid->S[2];
     bool ok = npw > 0 && hipMalloc(&b->d_index, npw * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&b->d_poff, npw * sizeof(int32_t)) == hipSuccess &&
@@ -456,6 +458,24 @@ extern "C" dpp_status dpp_basis_create(dpp_grid grid, const double* k_red, doubl
         return set_error(DPP_ENOMEM, "dpp_basis_create: allocation failed");
     }
     DPP_HIP(hipMemcpy(b->d_planes, b->h_planes.data(), b->nplanes * sizeof(int4), hipMemcpyHostToDevice));
+    // per (plane, natural row i1): first point, count, n2 of the first point
+    // (the points of one (n0, n1) row are contiguous with n2 ascending)
+    {
+        std::vector<int4> rows((size_t)b->nplanes * S1, int4{0, 0, 0, 0});
+        for (int q = 0; q < npw;) {
+            const int p = mil[q].x - b->n0min, n1 = mil[q].y;
+            const int i1 = ((n1 % S1) + S1) % S1;
+            int e = q;
+            while (e < npw && mil[e].x == mil[q].x && mil[e].y == n1) ++e;
+            rows[(size_t)p * S1 + i1] = int4{q, e - q, mil[q].z, 0};
+            q = e;
+        }
+        if (hipMalloc(&b->d_rows, rows.size() * sizeof(int4)) != hipSuccess) {
+            free_basis(b);
+            return set_error(DPP_ENOMEM, "dpp_basis_create: allocation failed");
+        }
+        DPP_HIP(hipMemcpy(b->d_rows, rows.data(), rows.size() * sizeof(int4), hipMemcpyHostToDevice));
+    }
     FftItem& it = b->h_item;
     it = grid->h_item;
     it.nplanes = b->nplanes;
@@ -464,6 +484,7 @@ extern "C" dpp_status dpp_basis_create(dpp_grid grid, const double* k_red, doubl
     it.nb = 0;
     it.full = 0;
     it.planes = b->d_planes;
+    it.rows = b->d_rows;
     it.poff = b->d_poff;
     it.kG2 = b->d_kG2;
     *out = b;

@@ -61,6 +61,7 @@ struct ItemTable {
     CellDesc* d_cells = nullptr;
     size_t dens_elems = 0;
     XzPlan xz;   // items grouped by x length for the register x pass
+    PlanePlan pl; // items grouped by square y-z face for the register plane passes
 };
 
 struct ScfGraph {
@@ -121,6 +122,7 @@ struct dpp_system_s {
     std::vector<double> cell_res;
     // launch choices (set by dpp_system_tune)
     bool reg_xpass = true;  // register-resident x pass of H where S0 is compiled in
+    bool reg_planes = true; // register plane passes (digit-reversed planes) for square y-z faces
     // graphs
     bool graph_on = false;
     hipStream_t cap_stream = nullptr;
@@ -234,6 +236,7 @@ dpp_status items_for(dpp_system_s* s, int nbo, const ItemTable** out) {
             it.dnch = dens_chunks(it.nb, it.S1, s->nit);
             it.dchunk = (it.nb + it.dnch - 1) / it.dnch;
             it.p_off = poff;
+            it.perm = (s->reg_planes && it.S1 == it.S2 && plane_reg_supported(it.S1)) ? 1 : 0;
             poff += (int64_t)it.dnch * ch.N;
             np += it.dnch;
             toff += (int64_t)it.nb * it.nplanes * it.S1 * it.S2;
@@ -256,6 +259,14 @@ dpp_status items_for(dpp_system_s* s, int nbo, const ItemTable** out) {
             DPP_TRY(dalloc_t(s, &d, members[g].size()));
             DPP_HIP(hipMemcpy(d, members[g].data(), members[g].size() * sizeof(int), hipMemcpyHostToDevice));
             t.xz.idx[g] = d;
+        }
+    t.pl = plane_plan_groups(t.h, members);
+    if (t.pl.N.size() > 1)
+        for (size_t g = 0; g < members.size(); ++g) {
+            int* d = nullptr;
+            DPP_TRY(dalloc_t(s, &d, members[g].size()));
+            DPP_HIP(hipMemcpy(d, members[g].data(), members[g].size() * sizeof(int), hipMemcpyHostToDevice));
+            t.pl.idx[g] = d;
         }
     auto ins = s->items.emplace(nbo, std::move(t));
     *out = &ins.first->second;
@@ -330,9 +341,11 @@ dpp_status apply_H_all(dpp_system_s* s, int nbo, const double2* X, double2* HX, 
     DPP_TRY(items_for(s, nbo, &it));
     const XzPlan* plan = s->reg_xpass ? &it->xz : nullptr;
     if (s->prec == DPP_F64)
-        DPP_TRY(apply_H_local_batched<double>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act, plan));
+        DPP_TRY(apply_H_local_batched<double>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act, plan,
+                                              &it->pl));
     else
-        DPP_TRY(apply_H_local_batched<float>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act, plan));
+        DPP_TRY(apply_H_local_batched<float>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act, plan,
+                                             &it->pl));
     if (s->maxnproj > 0) {
         std::vector<OvTask> t;
         std::vector<RotTask> r;
@@ -390,9 +403,9 @@ dpp_status density_all(dpp_system_s* s, int nbo, const double2* psi, double* n, 
     DPP_TRY(items_for(s, nbo, &it));
     if (prec == DPP_F64)
         return density_batched<double>(s->ctx, it->d_items, it->h, psi, s->d_f, s->Tplanes, s->dens_part,
-                                       it->d_cells, s->ncells, s->maxN, n);
+                                       it->d_cells, s->ncells, s->maxN, n, &it->pl);
     return density_batched<float>(s->ctx, it->d_items, it->h, psi, s->d_f, s->Tplanes, s->dens_part, it->d_cells,
-                                  s->ncells, s->maxN, n);
+                                  s->ncells, s->maxN, n, &it->pl);
 }
 
 dpp_status axpby_all(dpp_system_s* s, int nbo, const double* a, const double2* x, const double* b, const double2* y,

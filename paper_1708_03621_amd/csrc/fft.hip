@@ -105,10 +105,12 @@ __device__ __forceinline__ TO store_as(C v) {
 template <typename T, typename TIO, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_planes_from_sphere(const FftItem* items, FftItem single, const TIO* __restrict__ C,
-                     typename cx<T>::t* __restrict__ Tb, const int* __restrict__ act) {
+                     typename cx<T>::t* __restrict__ Tb, const int* __restrict__ act,
+                     const int* __restrict__ idx) {
     using Cx = typename cx<T>::t;
-    if (BATCH && act && !act[blockIdx.z]) return;
-    const FftItem& it = DPP_ITEM(items, single);
+    const int item = (BATCH && idx) ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (BATCH && act && !act[item]) return;
+    const FftItem& it = BATCH ? items[item] : single;
     const int p = blockIdx.x, b = blockIdx.y;
     if (p >= it.nplanes || b >= it.nb) return;
     extern __shared__ char smem_raw[];
@@ -239,17 +241,148 @@ k_xz(const FftItem* items, FftItem single, typename cx<T>::t* __restrict__ Tb,
         }
         return;
     }
-    // XZ_H: pointwise (Omega/N) V_eff
-    const double* Vp = V + it.v_off + (int64_t)i1 * S2;
+    // XZ_H: pointwise (Omega/N) V_eff at the natural (i1, i2) of the row
+    const int n1 = it.perm ? digit_rev_axis(it.ax[1], i1) : i1;
+    const double* Vp = V + it.v_off + (int64_t)n1 * S2;
     const T sc = (T)it.vscale;
     for (int i = threadIdx.x; i < e; i += blockDim.x) {
         const int i0 = i / S2, i2 = i - i0 * S2;
-        const T v = (T)Vp[(int64_t)i0 * S1 * S2 + i2] * sc;
+        const int n2 = it.perm ? digit_rev_axis(it.ax[2], i2) : i2;
+        const T v = (T)Vp[(int64_t)i0 * S1 * S2 + n2] * sc;
         lds[i] = Cx{lds[i].x * v, lds[i].y * v};
     }
     __syncthreads();
     fft_axis<T, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], -1);
     xz_store_pruned<T>(it, Tb, b, i1, lds);
+}
+
+// Register plane passes for square y-z faces (S1 = S2 = N): one wave per
+// (item, band, plane).  Sphere -> planes: lane r < N owns natural row i1 = r,
+// gathers the row's sphere points into registers (each register is one z
+// point), transforms along z (decimation in frequency), and writes the row to
+// LDS; lane c then owns column c (a digit-reversed z point), transforms along
+// y and stores the column, so the plane holds (y, z) in digit-reversed order.
+// Planes -> sphere runs the same steps backwards with decimation in time and
+// gathers the points with the kinetic term.  One LDS exchange per plane.
+template <typename T, int N>
+__global__ void __launch_bounds__(64)
+k_planes_from_sphere_reg(const FftItem* __restrict__ items, const int* __restrict__ idx,
+                         const double2* __restrict__ C, typename cx<T>::t* __restrict__ Tb,
+                         const int* __restrict__ act) {
+    using Cx = typename cx<T>::t;
+    const int item = idx ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (act && !act[item]) return;
+    const FftItem& it = items[item];
+    const int p = blockIdx.x, b = blockIdx.y;
+    if (p >= it.nplanes || b >= it.nb) return;
+    __shared__ Cx lds[N * (N + 1)];
+    const int lane = threadIdx.x;
+    if (lane < N) {
+        const int4 rw = it.rows[p * N + lane];
+        const double2* src = C + it.c_off + (int64_t)b * it.ld + rw.x;
+        Cx x[N];
+#pragma unroll
+        for (int r2 = 0; r2 < N; ++r2) {
+            const int n2 = 2 * r2 < N ? r2 : r2 - N;
+            const int q = n2 - rw.z;
+            x[r2] = (q >= 0 && q < rw.y) ? Io<T>::from(src[q]) : Cx{0, 0};
+        }
+        if (rw.y > 0) reg_dif<T, N, +1, 0>(x, it.tw64[2], it.tw32[2]);
+#pragma unroll
+        for (int c = 0; c < N; ++c) lds[lane * (N + 1) + c] = x[c];
+    }
+    __syncthreads();
+    if (lane < N) {
+        Cx x[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[r] = lds[r * (N + 1) + lane];
+        reg_dif<T, N, +1, 0>(x, it.tw64[1], it.tw32[1]);
+        Cx* dst = Tb + it.t_off + ((int64_t)b * it.nplanes + p) * (N * N) + lane;
+#pragma unroll
+        for (int r = 0; r < N; ++r) dst[r * N] = x[r];
+    }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(64)
+k_planes_to_sphere_reg(const FftItem* __restrict__ items, const int* __restrict__ idx,
+                       const typename cx<T>::t* __restrict__ Tb, const double2* __restrict__ Cin,
+                       double2* __restrict__ out, const int* __restrict__ act) {
+    using Cx = typename cx<T>::t;
+    const int item = idx ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (act && !act[item]) return;
+    const FftItem& it = items[item];
+    const int p = blockIdx.x, b = blockIdx.y;
+    if (p >= it.nplanes || b >= it.nb) return;
+    __shared__ Cx lds[N * (N + 1)];
+    const int lane = threadIdx.x;
+    if (lane < N) {
+        const Cx* src = Tb + it.t_off + ((int64_t)b * it.nplanes + p) * (N * N) + lane;
+        Cx x[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[r] = src[r * N];
+        reg_dit<T, N, -1, 0>(x, it.tw64[1], it.tw32[1]);
+#pragma unroll
+        for (int r = 0; r < N; ++r) lds[r * (N + 1) + lane] = x[r];
+    }
+    __syncthreads();
+    if (lane < N) {
+        const int4 rw = it.rows[p * N + lane];
+        if (rw.y > 0) {
+            Cx x[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) x[c] = lds[lane * (N + 1) + c];
+            reg_dit<T, N, -1, 0>(x, it.tw64[2], it.tw32[2]);
+            const int64_t o = it.c_off + (int64_t)b * it.ld + rw.x;
+            const double* kG2 = it.kG2 + rw.x;
+            const double hk = 0.5 * it.omega;
+#pragma unroll
+            for (int r2 = 0; r2 < N; ++r2) {
+                const int n2 = 2 * r2 < N ? r2 : r2 - N;
+                const int q = n2 - rw.z;
+                if (q >= 0 && q < rw.y) {
+                    const double2 c = Cin[o + q];
+                    const double2 v = Io<T>::to_d(x[r2]);
+                    const double t = hk * kG2[q];
+                    out[o + q] = double2{t * c.x + v.x, t * c.y + v.y};
+                }
+            }
+        }
+    }
+}
+
+// Register plane pass lengths (FP64 registers of a column: 2N).
+constexpr bool plane_reg_len(int n) {
+    return n == 12 || n == 15 || n == 16 || n == 18 || n == 20 || n == 24 || n == 25 || n == 27 || n == 30 ||
+           n == 32 || n == 36 || n == 40 || n == 45;
+}
+
+template <typename T, int N>
+static void planes_reg_launch_one(bool to_sphere, dim3 grid, hipStream_t st, const FftItem* items, const int* idx,
+                                  const double2* X, typename cx<T>::t* Tb, double2* HX, const int* act) {
+    if (to_sphere)
+        hipLaunchKernelGGL((k_planes_to_sphere_reg<T, N>), grid, dim3(64), 0, st, items, idx,
+                           (const typename cx<T>::t*)Tb, X, HX, act);
+    else
+        hipLaunchKernelGGL((k_planes_from_sphere_reg<T, N>), grid, dim3(64), 0, st, items, idx, X, Tb, act);
+}
+
+template <typename T>
+static bool planes_reg_launch(int N, bool to_sphere, dim3 grid, hipStream_t st, const FftItem* items,
+                              const int* idx, const double2* X, typename cx<T>::t* Tb, double2* HX,
+                              const int* act) {
+    switch (N) {
+#define DPP_PL_REG(n)                                                                      \
+    case n:                                                                                \
+        planes_reg_launch_one<T, n>(to_sphere, grid, st, items, idx, X, Tb, HX, act);      \
+        return true;
+        DPP_PL_REG(12) DPP_PL_REG(15) DPP_PL_REG(16) DPP_PL_REG(18) DPP_PL_REG(20) DPP_PL_REG(24)
+        DPP_PL_REG(25) DPP_PL_REG(27) DPP_PL_REG(30) DPP_PL_REG(32) DPP_PL_REG(36) DPP_PL_REG(40)
+        DPP_PL_REG(45)
+#undef DPP_PL_REG
+        default:
+            return false;
+    }
 }
 
 // Register-resident x pass of H: one thread per (item, band, i1, i2) column.
@@ -283,7 +416,13 @@ k_xz_reg(const FftItem* __restrict__ items, const int* __restrict__ idx, typenam
     const double2* tw64 = it.tw64[0];
     const float2* tw32 = it.tw32[0];
     reg_dif<T, S0, +1, 0>(x, tw64, tw32);
-    const double* Vp = V + it.v_off + col;
+    // natural (i1, i2) of this column (planes may be stored digit-reversed)
+    int vcol = col;
+    if (it.perm) {
+        const int p1 = col / it.S2, p2 = col - p1 * it.S2;
+        vcol = digit_rev_axis(it.ax[1], p1) * it.S2 + digit_rev_axis(it.ax[2], p2);
+    }
+    const double* Vp = V + it.v_off + vcol;
     const T sc = (T)it.vscale;
 #pragma unroll
     for (int p = 0; p < S0; ++p) {
@@ -462,13 +601,15 @@ k_xz_density(const FftItem* items, FftItem single, const typename cx<T>::t* __re
         __syncthreads();
     }
     const int64_t N = (int64_t)S0 * S1 * S2;
-    double* dst = part + it.p_off + (int64_t)c * N + (int64_t)i1 * S2;
+    const int n1 = it.perm ? digit_rev_axis(it.ax[1], i1) : i1;
+    double* dst = part + it.p_off + (int64_t)c * N + (int64_t)n1 * S2;
 #pragma unroll
     for (int u = 0; u < DM; ++u) {
         const int i = threadIdx.x + u * NT;
         if (i < e) {
             const int i0 = i / S2, i2 = i - i0 * S2;
-            dst[(int64_t)i0 * S1 * S2 + i2] = it.wk * acc[u];
+            const int n2 = it.perm ? digit_rev_axis(it.ax[2], i2) : i2;
+            dst[(int64_t)i0 * S1 * S2 + n2] = it.wk * acc[u];
         }
     }
 }
@@ -501,10 +642,11 @@ template <typename T, int MODE, typename TIO, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_planes_to_sphere(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb,
                    const double2* __restrict__ Cin, TIO* __restrict__ out, int64_t ldout_override,
-                   const int* __restrict__ act) {
+                   const int* __restrict__ act, const int* __restrict__ idx) {
     using Cx = typename cx<T>::t;
-    if (BATCH && act && !act[blockIdx.z]) return;
-    const FftItem& it = DPP_ITEM(items, single);
+    const int item = (BATCH && idx) ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (BATCH && act && !act[item]) return;
+    const FftItem& it = BATCH ? items[item] : single;
     const int p = blockIdx.x, b = blockIdx.y;
     if (p >= it.nplanes || b >= it.nb) return;
     extern __shared__ char smem_raw[];
@@ -639,7 +781,7 @@ static dpp_status pass1(dpp_ctx_s* cx_, const FftItem& it, const TIO* C, typenam
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_from_sphere<T, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, C, Tb,
-                                       (const int*)nullptr));
+                                       (const int*)nullptr, (const int*)nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -672,7 +814,7 @@ static dpp_status pass3(dpp_ctx_s* cx_, const FftItem& it, const typename cx<T>:
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, MODE, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, Tb, Cin,
-                                       out, (int64_t)0, (const int*)nullptr));
+                                       out, (int64_t)0, (const int*)nullptr, (const int*)nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -696,7 +838,7 @@ dpp_status run_apply_H_local(dpp_ham_s* ham, int nb, const double2* C, int64_t l
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(ot.nplanes, ot.nb, 1), dim3(NT_), L.lds, st, nullptr, ot, Tb, C, HC,
-                                       ldHC, (const int*)nullptr));
+                                       ldHC, (const int*)nullptr, (const int*)nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -737,8 +879,70 @@ BatchShape batch_shape(const std::vector<FftItem>& h, bool fp64) {
 }
 }  // namespace
 
+// Sphere -> planes (to_sphere = false) or planes -> sphere with the kinetic
+// term (to_sphere = true) for every item: one launch per plane group
+// (register passes for digit-reversed items, LDS passes for the rest), or a
+// single LDS launch without a plan.
+template <typename T>
+static dpp_status planes_pass(dpp_ctx_s* cx_, bool to_sphere, const BatchShape& bs, const FftItem* d_items,
+                              const FftItem& i0, unsigned nit, const PlanePlan* pplan, const double2* X,
+                              typename cx<T>::t* Tb, double2* HX, const int* act) {
+    using Cx = typename cx<T>::t;
+    hipStream_t st = cx_->stream;
+    const size_t ng = pplan ? pplan->N.size() : 1;
+    for (size_t g = 0; g < ng; ++g) {
+        const int N = pplan ? pplan->N[g] : 0;
+        const int* idx = pplan ? pplan->idx[g] : nullptr;
+        const dim3 grid(pplan ? pplan->maxP[g] : bs.maxP, pplan ? pplan->nbm[g] : bs.nbm,
+                        pplan ? pplan->count[g] : nit);
+        if (N > 0 && planes_reg_launch<T>(N, to_sphere, grid, st, d_items, idx, X, Tb, HX, act)) {
+            DPP_LAUNCHED();
+            continue;
+        }
+        if (N > 0) return set_error(DPP_EUNSUPPORTED, "plane pass length without a register kernel");
+        if (to_sphere) {
+            DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_, true>;
+                            DPP_TRY(set_lds(k, bs.plane.lds));
+                            hipLaunchKernelGGL(k, grid, dim3(NT_), bs.plane.lds, st, d_items, i0, (const Cx*)Tb, X,
+                                               HX, (int64_t)0, act, idx));
+        } else {
+            DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>;
+                            DPP_TRY(set_lds(k, bs.plane.lds));
+                            hipLaunchKernelGGL(k, grid, dim3(NT_), bs.plane.lds, st, d_items, i0, X, Tb, act, idx));
+        }
+        DPP_LAUNCHED();
+    }
+    return DPP_OK;
+}
+
 // One launch per pass for every item of the table (items may differ in box,
 // sphere and band count).
+bool plane_reg_supported(int n) { return plane_reg_len(n); }
+
+PlanePlan plane_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int>>& members) {
+    PlanePlan p;
+    members.clear();
+    for (size_t k = 0; k < h.size(); ++k) {
+        const FftItem& it = h[k];
+        const int key = it.perm ? it.S1 : 0;
+        size_t g = 0;
+        while (g < p.N.size() && p.N[g] != key) ++g;
+        if (g == p.N.size()) {
+            p.N.push_back(key);
+            p.count.push_back(0);
+            p.maxP.push_back(0);
+            p.nbm.push_back(0);
+            p.idx.push_back(nullptr);
+            members.emplace_back();
+        }
+        p.count[g]++;
+        p.maxP[g] = std::max(p.maxP[g], it.nplanes);
+        p.nbm[g] = std::max(p.nbm[g], it.nb);
+        members[g].push_back((int)k);
+    }
+    return p;
+}
+
 XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int>>& members) {
     XzPlan p;
     members.clear();
@@ -765,7 +969,7 @@ XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int
 template <typename T>
 dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,
                                  const double2* X, double2* HX, const double* V, void* Tbv, const int* act,
-                                 const XzPlan* plan) {
+                                 const XzPlan* plan, const PlanePlan* pplan) {
     using Cx = typename cx<T>::t;
     if (h.empty()) return DPP_OK;
     Cx* Tb = reinterpret_cast<Cx*>(Tbv);
@@ -783,11 +987,7 @@ dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const s
     const unsigned nit = (unsigned)h.size();
     {
         TimerScope ts_(cx_, DPP_TK_PLANES_IN, b1);
-        DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>;
-                        DPP_TRY(set_lds(k, bs.plane.lds));
-                        hipLaunchKernelGGL(k, dim3(bs.maxP, bs.nbm, nit), dim3(NT_), bs.plane.lds, st, d_items, i0, X,
-                                           Tb, act));
-        DPP_LAUNCHED();
+        DPP_TRY(planes_pass<T>(cx_, false, bs, d_items, i0, nit, pplan, X, Tb, nullptr, act));
     }
     {
         TimerScope ts_(cx_, DPP_TK_XZ_H, b2);
@@ -813,25 +1013,21 @@ dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const s
     }
     {
         TimerScope ts_(cx_, DPP_TK_PLANES_OUT, b3);
-        DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_, true>;
-                        DPP_TRY(set_lds(k, bs.plane.lds));
-                        hipLaunchKernelGGL(k, dim3(bs.maxP, bs.nbm, nit), dim3(NT_), bs.plane.lds, st, d_items, i0,
-                                           (const Cx*)Tb, X, HX, (int64_t)0, act));
-        DPP_LAUNCHED();
+        DPP_TRY(planes_pass<T>(cx_, true, bs, d_items, i0, nit, pplan, X, Tb, HX, act));
     }
     return DPP_OK;
 }
 template dpp_status apply_H_local_batched<double>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
                                                   const double2*, double2*, const double*, void*, const int*,
-                                                  const XzPlan*);
+                                                  const XzPlan*, const PlanePlan*);
 template dpp_status apply_H_local_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
                                                  const double2*, double2*, const double*, void*, const int*,
-                                                 const XzPlan*);
+                                                 const XzPlan*, const PlanePlan*);
 
 template <typename T>
 dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,
                            const double2* psi, const double* fill, void* Tbv, double* part,
-                           const CellDesc* d_cells, int ncells, int64_t maxN, double* n) {
+                           const CellDesc* d_cells, int ncells, int64_t maxN, double* n, const PlanePlan* pplan) {
     using Cx = typename cx<T>::t;
     if (h.empty()) return DPP_OK;
     Cx* Tb = reinterpret_cast<Cx*>(Tbv);
@@ -850,11 +1046,7 @@ dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::ve
     const unsigned nit = (unsigned)h.size();
     {
         TimerScope ts_(cx_, DPP_TK_PLANES_IN, b1);
-        DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_from_sphere<T, double2, NT_, true>;
-                        DPP_TRY(set_lds(k, bs.plane.lds));
-                        hipLaunchKernelGGL(k, dim3(bs.maxP, bs.nbm, nit), dim3(NT_), bs.plane.lds, st, d_items, i0,
-                                           psi, Tb, (const int*)nullptr));
-        DPP_LAUNCHED();
+        DPP_TRY(planes_pass<T>(cx_, false, bs, d_items, i0, nit, pplan, psi, Tb, nullptr, nullptr));
     }
     {
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, b2);
@@ -870,9 +1062,11 @@ dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::ve
     return DPP_OK;
 }
 template dpp_status density_batched<double>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&, const double2*,
-                                            const double*, void*, double*, const CellDesc*, int, int64_t, double*);
+                                            const double*, void*, double*, const CellDesc*, int, int64_t, double*,
+                                            const PlanePlan*);
 template dpp_status density_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&, const double2*,
-                                           const double*, void*, double*, const CellDesc*, int, int64_t, double*);
+                                           const double*, void*, double*, const CellDesc*, int, int64_t, double*,
+                                           const PlanePlan*);
 
 // Per cell: E[c * stride] = (Omega / 2) sum of the cell's Hartree row partials.
 __global__ void k_hartree_energy_cells(const double* __restrict__ part, const CellDesc* __restrict__ cells,

@@ -127,4 +127,19 @@ __device__ __forceinline__ void reg_dit(typename cx<T>::t* x, const double2* tw6
     }
 }
 
+// Point held at position p of an axis after decimation in frequency, for a
+// runtime axis plan (same radix order as the compile-time plan).
+__device__ __forceinline__ int digit_rev_axis(const FftAxis& ax, int p) {
+    int blk = ax.n, k = 0, m = 1;
+    for (int s = 0; s < ax.nrad; ++s) {
+        const int R = ax.rad[s];
+        blk /= R;
+        const int d = p / blk;
+        p -= d * blk;
+        k += d * m;
+        m *= R;
+    }
+    return k;
+}
+
 }  // namespace dpp

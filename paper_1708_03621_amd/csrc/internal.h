@@ -59,6 +59,8 @@ struct FftItem {
     const double2* tw64[3];
     const float2* tw32[3];
     const int4* planes;   // per plane: {sphere start, count, n1 of first row, nrows}
+    const int4* rows;     // per (plane, natural i1): {first point, count, n2 of first point, 0}
+    int perm;             // 1: planes stored in digit-reversed (i1, i2) order (register plane passes)
     const int* poff;      // per sphere point: i1*S2 + i2
     const double* kG2;    // per sphere point |k+G|^2
     int64_t c_off;        // offset (complex elements) of this item's block
@@ -152,6 +154,7 @@ struct dpp_basis_s {
     int4* d_miller;      // n0, n1, n2, unused
     double* d_kG2;
     int4* d_planes;
+    int4* d_rows;        // nplanes x S1 (natural i1): {first point, count, n2 of the first point, 0}
     std::vector<int4> h_planes;
     dpp::FftItem h_item;     // static part (c_off = t_off = v_off = 0, nb = 0)
 };
@@ -190,6 +193,16 @@ struct XzPlan {
 };
 XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int>>& members);
 
+// Items grouped for the plane passes: group g with N[g] > 0 holds items with
+// square y-z faces S1 = S2 = N[g] whose planes are stored digit-reversed
+// (perm = 1, register plane passes); N[g] = 0 is the LDS group.
+struct PlanePlan {
+    std::vector<int> N, count, maxP, nbm;
+    std::vector<const int*> idx;
+};
+bool plane_reg_supported(int n);
+PlanePlan plane_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int>>& members);
+
 // Items may have different boxes: the launch takes the largest workgroup and
 // LDS size any item needs.  `act` (nullable) masks items: inactive items do
 // nothing.  With `plan`, the x pass runs one register-resident launch per S0
@@ -197,13 +210,15 @@ XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int
 template <typename T>
 dpp_status apply_H_local_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
                                  const double2* X, double2* HX, const double* V, void* Tb,
-                                 const int* act = nullptr, const XzPlan* plan = nullptr);
+                                 const int* act = nullptr, const XzPlan* plan = nullptr,
+                                 const PlanePlan* pplan = nullptr);
 // Band-chunk partial densities of every item (item p_off, dnch, dchunk), then
 // per cell n[foff + j] = sum of the cell's partials (fixed order).
 template <typename T>
 dpp_status density_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
                            const double2* psi, const double* fill, void* Tb, double* part,
-                           const CellDesc* d_cells, int ncells, int64_t maxN, double* n);
+                           const CellDesc* d_cells, int ncells, int64_t maxN, double* n,
+                           const PlanePlan* pplan = nullptr);
 size_t batched_plane_elems(const std::vector<FftItem>& h_items);
 // Hartree potential and energy of every cell: full-box items (one per cell,
 // v_off = field offset, t_off = plane offset, p_off = row-partial offset).
