@@ -94,7 +94,9 @@ enum {
     DPP_TK_BLOCKOPS = 10,    /* packed-block elementwise, dots, small matrices    */
     DPP_TK_XZ_IO = 11,       /* x transforms of I and I^dag to/from full boxes    */
     DPP_TK_NET = 12,         /* learned-density network forward/backward          */
-    DPP_TK_LINESEARCH = 13   /* fused band-energy line searches (Cholesky, trace) */
+    DPP_TK_LINESEARCH = 13,  /* fused band-energy line searches (Cholesky, trace) */
+    DPP_TK_MASKED = 14       /* passes masked to a subset of items (line-search retries;
+                                no algorithmic bytes: the active set is decided on the device) */
 };
 /* Enable (on = 1) or disable the per-context kernel timer: each launch of
  * an instrumented class is bracketed by HIP events on the context stream.

@@ -24,68 +24,168 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// ----------------------------------------------------------- A^dag B -------
-// One wave accumulates one 16x16 tile of U over a K range; a workgroup of
-// OV_WAVES waves covers consecutive K sub-ranges of the same tile and sums
-// them in LDS in fixed order; the partial of each workgroup (chunk) is
-// written out and reduced by k_overlap_reduce in fixed order.  A launch runs
-// one task (kernel argument) or a table of tasks (blockIdx.z).
+// Load through the global address space (table pointers are otherwise
+// generic, and generic loads also count against the scalar-load counter).
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 gld(const double2* p) {
+    const d2v v = *(const __attribute__((address_space(1))) d2v*)p;
+    return double2{v.x, v.y};
+}
 
+// ----------------------------------------------------------- A^dag B -------
+// One wave accumulates a TA x TB block of 16x16 tiles of U over a K range, so
+// each loaded A and B value serves every tile of the block; a workgroup of
+// OV_WAVES waves covers consecutive K sub-ranges of the same block and sums
+// them in LDS in fixed order; the partial of each workgroup (chunk) is
+// written out per tile and reduced by k_overlap_reduce in fixed order.  A
+// launch runs one task (kernel argument) or a table of tasks (blockIdx.z).
+// Loads take clamped, in-bounds addresses and are unconditional; points past
+// the range get A = 0 when used, so the next step's loads stay in flight
+// during the MFMAs.  Rows past the band counts are computed from finite data
+// and never stored.
+template <int TA, int TB>
+__device__ __forceinline__ void ov_block(const OvTask& T, double2* __restrict__ part,
+                                         double (*red)[2][4][64]) {
+    const int chunk = blockIdx.x;
+    const int tilesA = (T.nbA + 15) / 16;
+    const int sB = (T.tilesB + TB - 1) / TB, sA = (tilesA + TA - 1) / TA;
+    if ((int)blockIdx.y >= sA * sB) return;
+    const int ti0 = ((int)blockIdx.y / sB) * TA, tj0 = ((int)blockIdx.y % sB) * TB;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, ks = lane >> 4;
+    const double2* Ap[TA];
+    const double2* Bp[TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a) Ap[a] = T.A + (int64_t)min((ti0 + a) * 16 + r, T.nbA - 1) * T.ldA;
+#pragma unroll
+    for (int b = 0; b < TB; ++b) Bp[b] = T.B + (int64_t)min((tj0 + b) * 16 + r, T.nbB - 1) * T.ldB;
+    d4 cre[TA][TB], cim[TA][TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+            cre[a][b] = d4{0, 0, 0, 0};
+            cim[a][b] = d4{0, 0, 0, 0};
+        }
+    const int sub = OV_CHUNK / OV_WAVES;
+    const int ga = chunk * OV_CHUNK + w * sub, ge = min(T.npw, ga + sub);
+    const int nst = ge > ga ? (ge - ga + 15) / 16 : 0;
+    // lane covers points g + 4 ks + s, s = 0..3, of the step at g
+    double2 an[TA][4], bn[TB][4];
+    auto load = [&](int g) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int q = min(g + 4 * ks + s, T.npw - 1);
+#pragma unroll
+            for (int a = 0; a < TA; ++a) an[a][s] = gld(Ap[a] + q);
+#pragma unroll
+            for (int b = 0; b < TB; ++b) bn[b][s] = gld(Bp[b] + q);
+        }
+    };
+    if (nst > 0) load(ga);
+    for (int st = 0; st < nst; ++st) {
+        const int g = ga + 16 * st;
+        double2 av[TA][4], bv[TB][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bool in = g + 4 * ks + s < ge;
+#pragma unroll
+            for (int a = 0; a < TA; ++a) av[a][s] = in ? an[a][s] : double2{0, 0};
+#pragma unroll
+            for (int b = 0; b < TB; ++b) bv[b][s] = bn[b][s];
+        }
+        if (st + 1 < nst) load(g + 16);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < TA; ++a)
+#pragma unroll
+                for (int b = 0; b < TB; ++b) {
+                    cre[a][b] = mfma(av[a][s].x, bv[b][s].x, cre[a][b]);
+                    cre[a][b] = mfma(av[a][s].y, bv[b][s].y, cre[a][b]);
+                    cim[a][b] = mfma(av[a][s].x, bv[b][s].y, cim[a][b]);
+                    cim[a][b] = mfma(-av[a][s].y, bv[b][s].x, cim[a][b]);
+                }
+    }
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+            if (ti0 + a >= tilesA || tj0 + b >= T.tilesB) continue;  // uniform over the workgroup
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                red[w][0][v][lane] = cre[a][b][v];
+                red[w][1][v][lane] = cim[a][b][v];
+            }
+            __syncthreads();
+            if (w == 0) {
+                const int tile = (ti0 + a) * T.tilesB + tj0 + b;
+                double2* dst = part + T.part_off + ((int64_t)chunk * T.ntiles + tile) * 256;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double sr = 0, si = 0;
+                    for (int u = 0; u < OV_WAVES; ++u) {
+                        sr += red[u][0][v][lane];
+                        si += red[u][1][v][lane];
+                    }
+                    const int i = 4 * v + (lane >> 4), j = lane & 15;
+                    dst[i * 16 + j] = double2{sr, si};
+                }
+            }
+            __syncthreads();
+        }
+}
+
+
+// Each task takes the widest block shape its own tile counts fill (WIDE);
+// launches whose operands are all at most 16 bands run the 1 x 1 shape only,
+// at its lower register count.
+template <int TA, int TB>
+__host__ __device__ constexpr int ov_blocks(int tA, int tB) {
+    return ((tA + TA - 1) / TA) * ((tB + TB - 1) / TB);
+}
+
+template <bool WIDE>
 __global__ void __launch_bounds__(64 * OV_WAVES)
 k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part,
                const int* __restrict__ act) {
     __shared__ double red[OV_WAVES][2][4][64];
-    const OvTask& T = tasks ? tasks[blockIdx.z] : single;
+    const OvTask T = tasks ? tasks[blockIdx.z] : single;
     if (act && !act[T.item]) return;
-    const int chunk = blockIdx.x;
-    const int tile = blockIdx.y;
-    if (chunk >= T.nchunk || tile >= T.ntiles) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int ti = tile / T.tilesB, tj = tile - ti * T.tilesB;
-    const int r = lane & 15, ks = lane >> 4;
-    const int ia = ti * 16 + r, jb = tj * 16 + r;
-    const bool va = ia < T.nbA, vb = jb < T.nbB;
-    const double2* Ap = T.A + (int64_t)(va ? ia : 0) * T.ldA;
-    const double2* Bp = T.B + (int64_t)(vb ? jb : 0) * T.ldB;
-    d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
-    const int g0 = chunk * OV_CHUNK;
-    const int sub = OV_CHUNK / OV_WAVES;
-    const int ga = g0 + w * sub, ge = min(T.npw, ga + sub);
-    for (int g = ga; g < ge; g += 16) {
-        // lane covers points g + 4 ks + s, s = 0..3
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int q = g + 4 * ks + s;
-            double2 a = double2{0, 0}, b = double2{0, 0};
-            if (q < ge) {
-                if (va) a = Ap[q];
-                if (vb) b = Bp[q];
-            }
-            cre = mfma(a.x, b.x, cre);
-            cre = mfma(a.y, b.y, cre);
-            cim = mfma(a.x, b.y, cim);
-            cim = mfma(-a.y, b.x, cim);
-        }
+    if ((int)blockIdx.x >= T.nchunk) return;
+    if constexpr (WIDE) {
+        const int tA = (T.nbA + 15) / 16, tB = T.tilesB;
+        if (tA >= 2 && tB >= 2)
+            ov_block<2, 2>(T, part, red);
+        else if (tB >= 2)
+            ov_block<1, 2>(T, part, red);
+        else if (tA >= 2)
+            ov_block<2, 1>(T, part, red);
+        else
+            ov_block<1, 1>(T, part, red);
+    } else {
+        ov_block<1, 1>(T, part, red);
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        red[w][0][v][lane] = cre[v];
-        red[w][1][v][lane] = cim[v];
-    }
-    __syncthreads();
-    if (w == 0) {
-        double2* dst = part + T.part_off + ((int64_t)chunk * T.ntiles + tile) * 256;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            double sr = 0, si = 0;
-            for (int u = 0; u < OV_WAVES; ++u) {
-                sr += red[u][0][v][lane];
-                si += red[u][1][v][lane];
-            }
-            const int i = 4 * v + (lane >> 4), j = lane & 15;
-            dst[i * 16 + j] = double2{sr, si};
-        }
-    }
+}
+
+// Blocks of a task in the shape k_overlap_mfma picks for it.
+static int ov_task_blocks(int tA, int tB) {
+    if (tA >= 2 && tB >= 2) return ov_blocks<2, 2>(tA, tB);
+    if (tB >= 2) return ov_blocks<1, 2>(tA, tB);
+    if (tA >= 2) return ov_blocks<2, 1>(tA, tB);
+    return tA * tB;
+}
+
+// nblk: the largest ov_task_blocks over the tasks; wide: some task has more
+// than one tile.
+static void overlap_launch(dpp_ctx ctx, const OvTask* d_tasks, const OvTask& single, unsigned ntasks, int nchunk,
+                           int nblk, bool wide, double2* part, const int* act) {
+    if (wide)
+        hipLaunchKernelGGL(k_overlap_mfma<true>, dim3(nchunk, nblk, ntasks), dim3(64 * OV_WAVES), 0, ctx->stream,
+                           d_tasks, single, part, act);
+    else
+        hipLaunchKernelGGL(k_overlap_mfma<false>, dim3(nchunk, nblk, ntasks), dim3(64 * OV_WAVES), 0, ctx->stream,
+                           d_tasks, single, part, act);
 }
 
 __global__ void k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part,
@@ -144,8 +244,8 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
     double2* part = reinterpret_cast<double2*>(ws);
     {
         TimerScope ts_(ctx, DPP_TK_OVERLAP, 16.0 * npw * (nbA + nbB), 8.0 * npw * nbA * (double)nbB);
-        hipLaunchKernelGGL(k_overlap_mfma, dim3(t.nchunk, t.ntiles, 1), dim3(64 * OV_WAVES), 0, ctx->stream,
-                           (const OvTask*)nullptr, t, part, (const int*)nullptr);
+        overlap_launch(ctx, nullptr, t, 1, t.nchunk, ov_task_blocks((nbA + 15) / 16, t.tilesB), t.ntiles > 1, part,
+                       nullptr);
         DPP_LAUNCHED();
     }
     TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
@@ -160,22 +260,22 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
                          const int* act) {
     if (h.empty()) return DPP_OK;
-    int mc = 1, mt = 1;
+    int mc = 1, mt = 1, mblk = 1;
     double by = 0, fl = 0;
     for (const OvTask& t : h) {
         mc = std::max(mc, t.nchunk);
         mt = std::max(mt, t.ntiles);
+        mblk = std::max(mblk, ov_task_blocks((t.nbA + 15) / 16, t.tilesB));
         by += 16.0 * t.npw * (t.nbA + t.nbB);
         fl += 8.0 * t.npw * t.nbA * (double)t.nbB;
     }
     if (mt > 65535 || h.size() > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: batch too large");
     {
-        TimerScope ts_(ctx, DPP_TK_OVERLAP, by, fl);
-        hipLaunchKernelGGL(k_overlap_mfma, dim3(mc, mt, (unsigned)h.size()), dim3(64 * OV_WAVES), 0, ctx->stream,
-                           d_tasks, OvTask{}, part, act);
+        TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_OVERLAP, act ? 0.0 : by, act ? 0.0 : fl);
+        overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1, part, act);
         DPP_LAUNCHED();
     }
-    TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
+    TimerScope ts2_(ctx, act ? DPP_TK_MASKED : DPP_TK_BLOCKOPS);
     hipLaunchKernelGGL(k_overlap_reduce, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
                        ctx->stream, d_tasks, OvTask{}, (const double2*)part, act);
     DPP_LAUNCHED();
@@ -183,66 +283,93 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
 }
 
 // ---------------------------------------------------------------- X M ------
-// One wave owns 16 consecutive sphere points and up to RT_JT x 16 output
-// bands; X is read once per wave.
-
+// One wave owns PT tiles of 16 consecutive sphere points and up to JT x 16
+// output bands in accumulators; X is read once, each M value once per wave
+// and K step for all PT point tiles.  The loads of the next K step are issued
+// before the MFMAs of the current one.  Wide outputs take (1, 8); narrow ones
+// take PT > 1 when the batch still gives every CU many waves.
+template <int PT, int JT>
 __global__ void __launch_bounds__(64 * RT_WAVES)
 k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const int* __restrict__ act) {
-    const RotTask& T = tasks ? tasks[blockIdx.y] : single;
+    const RotTask T = tasks ? tasks[blockIdx.y] : single;
     if (act && !act[T.item]) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int gt = blockIdx.x * RT_WAVES + w;
-    const int G0 = gt * 16;
-    if (G0 >= T.npw) return;
-    const int njt = min(RT_JT, (T.nbO + 15) / 16 - jt0);
+    const int gt = (blockIdx.x * RT_WAVES + w) * PT;
+    if (gt * 16 >= T.npw) return;
+    const int njt = min(JT, (T.nbO + 15) / 16 - jt0);
     if (njt <= 0) return;
     const int c = lane & 15, ks = lane >> 4;
-    const int q = G0 + c;
-    const bool vq = q < T.npw;
-    d4 dre[RT_JT], dim[RT_JT];
+    d4 dre[PT][JT], dim[PT][JT];
 #pragma unroll
-    for (int t = 0; t < RT_JT; ++t) {
-        dre[t] = d4{0, 0, 0, 0};
-        dim[t] = d4{0, 0, 0, 0};
-    }
-    for (int term = 0; term < (T.nbX2 > 0 ? 2 : 1); ++term) {
-        const double2* Xs = term ? T.X2 : T.X;
-        const double2* Ms = term ? T.M2 : T.M;
-        const int nbx = term ? T.nbX2 : T.nbX;
-        for (int i0 = 0; i0 < nbx; i0 += 4) {
-            const int i = i0 + ks;
-            double2 x = double2{0, 0};
-            if (i < nbx && vq) x = Xs[(int64_t)i * T.ldX + q];
+    for (int u = 0; u < PT; ++u)
 #pragma unroll
-            for (int t = 0; t < RT_JT; ++t) {
-                if (t < njt) {
-                    const int j = (jt0 + t) * 16 + c;
-                    double2 m = double2{0, 0};
-                    if (i < nbx && j < T.nbO) m = Ms[(int64_t)i * T.M_ld + j];
-                    dre[t] = mfma(m.x, x.x, dre[t]);
-                    dre[t] = mfma(-m.y, x.y, dre[t]);
-                    dim[t] = mfma(m.y, x.x, dim[t]);
-                    dim[t] = mfma(m.x, x.y, dim[t]);
+        for (int t = 0; t < JT; ++t) {
+            dre[u][t] = d4{0, 0, 0, 0};
+            dim[u][t] = d4{0, 0, 0, 0};
+        }
+    const int nterm = T.nbX2 > 0 ? 2 : 1;
+    // K steps run over the rows of X then those of X2
+    const int nk1 = (T.nbX + 3) / 4, nk = nk1 + (nterm == 2 ? (T.nbX2 + 3) / 4 : 0);
+    // Loads use clamped, in-bounds addresses and are unconditional.  Rows of
+    // K beyond the band count get M = 0 (applied when the values are used, so
+    // the next step's loads stay in flight); padded points and output bands
+    // are computed from finite data and never stored.
+    double2 xn[PT], mn[JT];
+    auto load = [&](int kstep) {
+        const bool second = kstep >= nk1;
+        const double2* Xs = second ? T.X2 : T.X;
+        const double2* Ms = second ? T.M2 : T.M;
+        const int nbx = second ? T.nbX2 : T.nbX;
+        const int ic = min((second ? kstep - nk1 : kstep) * 4 + ks, nbx - 1);
+#pragma unroll
+        for (int u = 0; u < PT; ++u) xn[u] = gld(Xs + (int64_t)ic * T.ldX + min((gt + u) * 16 + c, T.npw - 1));
+#pragma unroll
+        for (int t = 0; t < JT; ++t)
+            mn[t] = gld(Ms + (int64_t)ic * T.M_ld + min((jt0 + min(t, njt - 1)) * 16 + c, T.nbO - 1));
+    };
+    if (nk > 0) load(0);
+    for (int k = 0; k < nk; ++k) {
+        const bool second = k >= nk1;
+        const bool vi = (second ? k - nk1 : k) * 4 + ks < (second ? T.nbX2 : T.nbX);
+        double2 x[PT], m[JT];
+#pragma unroll
+        for (int u = 0; u < PT; ++u) x[u] = xn[u];
+#pragma unroll
+        for (int t = 0; t < JT; ++t) m[t] = vi ? mn[t] : double2{0, 0};
+        if (k + 1 < nk) load(k + 1);
+#pragma unroll
+        for (int t = 0; t < JT; ++t) {
+            if (t < njt) {
+#pragma unroll
+                for (int u = 0; u < PT; ++u) {
+                    dre[u][t] = mfma(m[t].x, x[u].x, dre[u][t]);
+                    dre[u][t] = mfma(-m[t].y, x[u].y, dre[u][t]);
+                    dim[u][t] = mfma(m[t].y, x[u].x, dim[u][t]);
+                    dim[u][t] = mfma(m[t].x, x[u].y, dim[u][t]);
                 }
             }
         }
     }
-    if (!vq) return;
 #pragma unroll
-    for (int t = 0; t < RT_JT; ++t) {
-        if (t < njt) {
+    for (int u = 0; u < PT; ++u) {
+        const int q = (gt + u) * 16 + c;
+        if (q >= T.npw) continue;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int j = (jt0 + t) * 16 + 4 * v + ks;
-                if (j < T.nbO) {
-                    double2* o = T.out + (int64_t)j * T.ldout + q;
-                    double2 r = double2{dre[t][v], dim[t][v]};
-                    if (T.beta != 0.0) {
-                        const double2 p = *o;
-                        r.x += T.beta * p.x;
-                        r.y += T.beta * p.y;
+        for (int t = 0; t < JT; ++t) {
+            if (t < njt) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = (jt0 + t) * 16 + 4 * v + ks;
+                    if (j < T.nbO) {
+                        double2* o = T.out + (int64_t)j * T.ldout + q;
+                        double2 r = double2{dre[u][t][v], dim[u][t][v]};
+                        if (T.beta != 0.0) {
+                            const double2 p = *o;
+                            r.x += T.beta * p.x;
+                            r.y += T.beta * p.y;
+                        }
+                        *o = r;
                     }
-                    *o = r;
                 }
             }
         }
@@ -273,39 +400,62 @@ static double rot_bytes(const RotTask& t) {
     return 16.0 * t.npw * (t.nbX + t.nbX2 + t.nbO * (t.beta != 0.0 ? 2.0 : 1.0)) + 16.0 * (t.nbX + t.nbX2) * t.nbO;
 }
 
+template <int PT, int JT>
+static void rotate_go(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single, unsigned ntasks, int ntile,
+                      int jt0, const int* act) {
+    const int nblk = (ntile + RT_WAVES * PT - 1) / (RT_WAVES * PT);
+    hipLaunchKernelGGL((k_rotate_mfma<PT, JT>), dim3(nblk, ntasks), dim3(64 * RT_WAVES), 0, ctx->stream, d_tasks,
+                       single, jt0, act);
+}
+
+// Launch the rotate kernel shape for the widest output of a batch; tiles =
+// point tiles summed over the tasks.  Several point tiles per wave only while
+// the launch keeps at least RT_MIN_WAVES waves.
+constexpr int64_t RT_MIN_WAVES = 4096;
+static dpp_status rotate_launch(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single, unsigned ntasks,
+                                int maxnpw, int maxnbO, int64_t tiles, const int* act) {
+    const int ntile = (maxnpw + 15) / 16;
+    const int jtiles = (maxnbO + 15) / 16;
+    if (jtiles == 1) {
+        if (tiles >= 4 * RT_MIN_WAVES)
+            rotate_go<4, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+        else if (tiles >= 2 * RT_MIN_WAVES)
+            rotate_go<2, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+        else
+            rotate_go<1, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+    } else if (jtiles == 2) {
+        if (tiles >= 2 * RT_MIN_WAVES)
+            rotate_go<2, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+        else
+            rotate_go<1, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+    } else {
+        for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT) rotate_go<1, RT_JT>(ctx, d_tasks, single, ntasks, ntile, jt0, act);
+    }
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
 dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
                       const double2* M, double beta, double2* out, int64_t ldout) {
     RotTask t = make_rot_task(npw, nbX, X, ldX, nbO, M, nbO, beta, out, ldout);
-    const int ntile = (npw + 15) / 16;
-    const int nblk = (ntile + RT_WAVES - 1) / RT_WAVES;
-    const int jtiles = (nbO + 15) / 16;
     TimerScope ts_(ctx, DPP_TK_ROTATE, rot_bytes(t), 8.0 * npw * nbX * (double)nbO);
-    for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT) {
-        hipLaunchKernelGGL(k_rotate_mfma, dim3(nblk, 1), dim3(64 * RT_WAVES), 0, ctx->stream, (const RotTask*)nullptr,
-                           t, jt0, (const int*)nullptr);
-        DPP_LAUNCHED();
-    }
-    return DPP_OK;
+    return rotate_launch(ctx, nullptr, t, 1, npw, nbO, (npw + 15) / 16, nullptr);
 }
 
 dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks, const int* act) {
     if (h.empty()) return DPP_OK;
     int mp = 1, mj = 1;
+    int64_t tiles = 0;
     double by = 0, fl = 0;
     for (const RotTask& t : h) {
         mp = std::max(mp, t.npw);
+        tiles += (t.npw + 15) / 16;
         mj = std::max(mj, (t.nbO + 15) / 16);
         by += rot_bytes(t);
         fl += 8.0 * t.npw * (t.nbX + t.nbX2) * (double)t.nbO;
     }
-    const int nblk = ((mp + 15) / 16 + RT_WAVES - 1) / RT_WAVES;
-    TimerScope ts_(ctx, DPP_TK_ROTATE, by, fl);
-    for (int jt0 = 0; jt0 < mj; jt0 += RT_JT) {
-        hipLaunchKernelGGL(k_rotate_mfma, dim3(nblk, (unsigned)h.size()), dim3(64 * RT_WAVES), 0, ctx->stream,
-                           d_tasks, RotTask{}, jt0, act);
-        DPP_LAUNCHED();
-    }
-    return DPP_OK;
+    TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_ROTATE, act ? 0.0 : by, act ? 0.0 : fl);
+    return rotate_launch(ctx, d_tasks, RotTask{}, (unsigned)h.size(), mp, mj * 16, tiles, act);
 }
 
 // ------------------------------------------------- small-matrix products ---

@@ -439,6 +439,95 @@ k_xz_reg(const FftItem* __restrict__ items, const int* __restrict__ idx, typenam
     }
 }
 
+// Value of the other lane of an adjacent pair (lane ^ 1) by a DPP quad
+// permutation [1, 0, 3, 2].
+__device__ __forceinline__ float pair_swap(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The same x pass with each column split over a lane pair (half h holds
+// points j + h S0/2, j < S0/2), for half the registers per thread.  With
+// M = S0/2 and w = exp(+-2 pi i / S0) the forward transform starts with a
+// radix-2 step across the pair: half h forms y_h[j] = (x[j] + (-1)^h
+// x[j+M]) w^{h j}, whose M-point transform gives the points 2k + h; the
+// inverse ends with the matching step, out[j + h M] = z_0[j] + (-1)^h
+// w^{-j} z_1[j].  Everything between stays in the thread's registers.
+template <typename T, int S0>
+__global__ void __launch_bounds__(256)
+k_xz_reg2(const FftItem* __restrict__ items, const int* __restrict__ idx, typename cx<T>::t* __restrict__ Tb,
+          const double* __restrict__ V, const int* __restrict__ act) {
+    using Cx = typename cx<T>::t;
+    constexpr int M = S0 / 2;
+    const int item = idx ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (act && !act[item]) return;
+    const FftItem& it = items[item];
+    const int b = blockIdx.y;
+    if (b >= it.nb) return;
+    const int np = it.S1 * it.S2;
+    const int col = blockIdx.x * 128 + (threadIdx.x >> 1);
+    const int h = threadIdx.x & 1;
+    if (col >= np) return;  // both lanes of a pair leave together
+    const int nP = it.nplanes;
+    Cx* base = Tb + it.t_off + (int64_t)b * nP * np + col;
+    Cx x[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        int d = (j + h * M - it.n0min) % S0;
+        d += d < 0 ? S0 : 0;
+        x[j] = d < nP ? base[(int64_t)d * np] : Cx{0, 0};
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const Cx o = Cx{pair_swap(x[j].x), pair_swap(x[j].y)};
+        if (h == 0) {
+            x[j] = Cx{x[j].x + o.x, x[j].y + o.y};
+        } else {
+            const Cx dlt = Cx{o.x - x[j].x, o.y - x[j].y};
+            x[j] = j == 0 ? dlt : cmul(dlt, reg_twiddle<T, S0>(j, +1));
+        }
+    }
+    reg_dif<T, M, +1, 0>(x, nullptr, nullptr);
+    int vcol = col;
+    if (it.perm) {
+        const int p1 = col / it.S2, p2 = col - p1 * it.S2;
+        vcol = digit_rev_axis(it.ax[1], p1) * it.S2 + digit_rev_axis(it.ax[2], p2);
+    }
+    const double* Vp = V + it.v_off + vcol + (int64_t)h * np;
+    const T sc = (T)it.vscale;
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+        const int k = 2 * reg_digit_rev(M, p);
+        const T v = (T)Vp[(int64_t)k * np] * sc;
+        x[p] = Cx{x[p].x * v, x[p].y * v};
+    }
+    reg_dit<T, M, -1, 0>(x, nullptr, nullptr);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const Cx t = (h == 0 || j == 0) ? x[j] : cmul(x[j], reg_twiddle<T, S0>(j, -1));
+        const Cx o = Cx{pair_swap(t.x), pair_swap(t.y)};
+        x[j] = h == 0 ? Cx{t.x + o.x, t.y + o.y} : Cx{o.x - t.x, o.y - t.y};
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        int d = (j + h * M - it.n0min) % S0;
+        d += d < 0 ? S0 : 0;
+        if (d < nP) base[(int64_t)d * np] = x[j];
+    }
+}
+
+template <typename T, int N>
+static void xz_reg2_one(dim3 grid, hipStream_t st, const FftItem* items, const int* idx, typename cx<T>::t* Tb,
+                        const double* V, const int* act) {
+    grid.x = (grid.x * 256 + 127) / 128;
+    hipLaunchKernelGGL((k_xz_reg2<T, N>), grid, dim3(256), 0, st, items, idx, Tb, V, act);
+}
+
 // Register x pass lengths: FP64 up to 45 and FP32 up to 64 points keep every
 // column in registers without scratch spills on gfx950.
 template <typename T, int N>
@@ -446,6 +535,9 @@ static bool xz_reg_one(dim3 grid, hipStream_t st, const FftItem* items, const in
                        const double* V, const int* act) {
     if constexpr (sizeof(T) == 8 && N > 45) {
         return false;
+    } else if constexpr (N % 2 == 0 && N >= (sizeof(T) == 8 ? 24 : 36)) {
+        xz_reg2_one<T, N>(grid, st, items, idx, Tb, V, act);
+        return true;
     } else {
         hipLaunchKernelGGL((k_xz_reg<T, N>), grid, dim3(256), 0, st, items, idx, Tb, V, act);
         return true;
@@ -985,12 +1077,14 @@ dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const s
     }
     const FftItem& i0 = h[0];
     const unsigned nit = (unsigned)h.size();
+    // passes masked to a subset of items are timed apart, without bytes
+    const bool masked = act != nullptr;
     {
-        TimerScope ts_(cx_, DPP_TK_PLANES_IN, b1);
+        TimerScope ts_(cx_, masked ? DPP_TK_MASKED : DPP_TK_PLANES_IN, masked ? 0.0 : b1);
         DPP_TRY(planes_pass<T>(cx_, false, bs, d_items, i0, nit, pplan, X, Tb, nullptr, act));
     }
     {
-        TimerScope ts_(cx_, DPP_TK_XZ_H, b2);
+        TimerScope ts_(cx_, masked ? DPP_TK_MASKED : DPP_TK_XZ_H, masked ? 0.0 : b2);
         if (plan) {
             for (size_t g = 0; g < plan->S0.size(); ++g) {
                 const dim3 grid((unsigned)((plan->maxS1S2[g] + 255) / 256), (unsigned)plan->nbm[g],
@@ -1012,7 +1106,7 @@ dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const s
         }
     }
     {
-        TimerScope ts_(cx_, DPP_TK_PLANES_OUT, b3);
+        TimerScope ts_(cx_, masked ? DPP_TK_MASKED : DPP_TK_PLANES_OUT, masked ? 0.0 : b3);
         DPP_TRY(planes_pass<T>(cx_, true, bs, d_items, i0, nit, pplan, X, Tb, HX, act));
     }
     return DPP_OK;

@@ -11,8 +11,9 @@
 // reverse order.  With opposite signs, DIT(-) after DIF(+) is N times the
 // identity, so a pointwise operation in the transformed (real-space) domain
 // needs no reordering: register p holds the point digit_rev(p).
-// Twiddles come from the per-axis table w[m] = exp(-2 pi i m / N) (conjugated
-// for sign > 0) at compile-time indices: uniform scalar loads.
+// Twiddles w[m] = exp(-2 pi i m / N) (conjugated for sign > 0) are
+// compile-time constants: an exact rational octant reduction of the angle and
+// Taylor series of sin and cos on [0, pi/4] evaluated in constant expressions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -74,6 +75,72 @@ constexpr int reg_digit_rev(int n, int p) {
     return k;
 }
 
+// sin and cos of x in [0, pi/4] by Taylor series (16 terms: the truncation
+// error is below 1e-30 there).
+constexpr void reg_sincos_small(double x, double& s, double& c) {
+    double ts = x, tc = 1.0;
+    s = x;
+    c = 1.0;
+    for (int k = 1; k < 16; ++k) {
+        ts *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        tc *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        s += ts;
+        c += tc;
+    }
+}
+
+// exp(-2 pi i m / n): the angle 2 pi m / n = (pi / 4) (8m / n) is split into an
+// octant o = floor(8m / n) and a remainder fraction r = (8m mod n) / n, both
+// exact; sin and cos of (pi/4) r (or of (pi/4)(1 - r) in odd octants) then
+// give the value by octant symmetry.
+struct RegCs {
+    double c, s;
+};
+constexpr RegCs reg_cis(int m, int n) {
+    const long q = 8L * (m % n);
+    const int o = (int)(q / n);
+    const long rem = q % n;
+    const double quarter = 0.78539816339744830962;  // pi / 4
+    double sa = 0, ca = 0;
+    if (o % 2 == 0)
+        reg_sincos_small(quarter * ((double)rem / n), sa, ca);
+    else
+        reg_sincos_small(quarter * ((double)(n - rem) / n), sa, ca);
+    // (cos t, sin t) for t = (pi/4)(o + r)
+    double c = 0, s = 0;
+    switch (o) {
+        case 0: c = ca, s = sa; break;            // t = a
+        case 1: c = sa, s = ca; break;            // t = pi/2 - a
+        case 2: c = -sa, s = ca; break;           // t = pi/2 + a
+        case 3: c = -ca, s = sa; break;           // t = pi - a
+        case 4: c = -ca, s = -sa; break;          // t = pi + a
+        case 5: c = -sa, s = -ca; break;          // t = 3pi/2 - a
+        case 6: c = sa, s = -ca; break;           // t = 3pi/2 + a
+        default: c = ca, s = -sa; break;          // t = 2pi - a
+    }
+    return RegCs{c, -s};  // exp(-i t)
+}
+
+template <int N>
+struct RegTw {
+    double re[N], im[N];
+    constexpr RegTw() : re(), im() {
+        for (int m = 0; m < N; ++m) {
+            const RegCs w = reg_cis(m, N);
+            re[m] = w.c;
+            im[m] = w.s;
+        }
+    }
+};
+
+template <typename T, int N>
+__device__ __forceinline__ typename cx<T>::t reg_twiddle(int m, int sign) {
+    constexpr RegTw<N> tw{};
+    using C = typename cx<T>::t;
+    const double re = tw.re[m], im = tw.im[m];
+    return C{(T)re, (T)(sign > 0 ? -im : im)};
+}
+
 template <typename T, int N, int SIGN, int STAGE>
 __device__ __forceinline__ void reg_dif(typename cx<T>::t* x, const double2* tw64, const float2* tw32) {
     using C = typename cx<T>::t;
@@ -92,7 +159,7 @@ __device__ __forceinline__ void reg_dif(typename cx<T>::t* x, const double2* tw6
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int m = ((N / n) * r * j) % N;
-                    x[base + j + r * S] = m == 0 ? v[r] : cmul(v[r], twiddle<T>(tw64, tw32, m, SIGN));
+                    x[base + j + r * S] = m == 0 ? v[r] : cmul(v[r], reg_twiddle<T, N>(m, SIGN));
                 }
             }
         }
@@ -117,7 +184,7 @@ __device__ __forceinline__ void reg_dit(typename cx<T>::t* x, const double2* tw6
                 for (int r = 0; r < R; ++r) {
                     const int m = ((N / n) * r * j) % N;
                     const C a = x[base + j + r * S];
-                    v[r] = m == 0 ? a : cmul(a, twiddle<T>(tw64, tw32, m, SIGN));
+                    v[r] = m == 0 ? a : cmul(a, reg_twiddle<T, N>(m, SIGN));
                 }
                 Dft<T, R>::run(v, SIGN);
 #pragma unroll

@@ -141,7 +141,7 @@ SIGNATURES = {
 
 TIMER_KINDS = {"planes_in": 0, "xz_h": 1, "planes_out": 2, "xz_density": 3, "overlap": 4, "rotate": 5,
                "cholesky": 6, "eigh": 7, "fullbox": 8, "fields": 9, "blockops": 10, "xz_io": 11, "net": 12,
-               "linesearch": 13}
+               "linesearch": 13, "masked": 14}
 
 
 def load(path: str = LIB_PATH):
