@@ -976,6 +976,180 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
     }
 }
 
+// The same Jacobi method for n <= 32 in one wave, built for the latency of
+// a round: A is stored whole in LDS (row stride n + 1), so a 2x2 block is
+// read and written without index folding; rotations take one reciprocal
+// square root of |a_pq|^2 and no division by |a_pq|; the convergence norms
+// are wave reductions; each workgroup barrier spans a single wave.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ void jacobi_eigh_wave(int n, const double2* __restrict__ Hg, double* __restrict__ ev,
+                                 double2* __restrict__ vo) {
+    constexpr int LD = EIGW_MAXN + 1;
+    __shared__ double2 A[EIGW_MAXN * LD];
+    __shared__ double2 Vt[EIGW_MAXN * LD];
+    __shared__ Rot rot[EIGW_MAXN / 2];
+    __shared__ double dg[EIGW_MAXN];
+    __shared__ int perm[EIGW_MAXN];
+    const int lane = threadIdx.x;
+    const int m = n + (n & 1), P = m / 2;
+    for (int e = lane; e < n * n; e += 64) {
+        const int r = e / n, c = e - r * n;
+        double2 h = c >= r ? Hg[r * n + c] : Hg[c * n + r];
+        if (c < r) h.y = -h.y;
+        if (r == c) h.y = 0.0;
+        A[r * LD + c] = h;
+        Vt[r * LD + c] = double2{r == c ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < EIG_SWEEPS; ++sweep) {
+        double off = 0, dia = 0;
+        for (int e = lane; e < n * n; e += 64) {
+            const int r = e / n, c = e - r * n;
+            const double2 a = A[r * LD + c];
+            if (r != c)
+                off += a.x * a.x + a.y * a.y;
+            else
+                dia += a.x * a.x;
+        }
+        off = wave_sum(off);
+        dia = wave_sum(dia);
+        const double fro2 = off + dia;
+        // converged once the off-diagonal part is 1e-14 of the Frobenius norm
+        if (off <= 1e-28 * fmax(fro2, 1e-300) || off == 0.0) break;
+        const double skip2 = 1e-32 * fro2;  // (1e-16 |A|_F)^2: pairs at rounding level are not rotated
+        for (int round = 0; round < m - 1; ++round) {
+            if (lane < P) {
+                int p, q;
+                if (lane == 0) {
+                    p = m - 1;
+                    q = round;
+                } else {
+                    p = round + lane;
+                    p -= p >= m - 1 ? m - 1 : 0;
+                    q = round - lane;
+                    q += q < 0 ? m - 1 : 0;
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                Rot R{p, q, 1.0, 0.0, 1.0, 0.0};
+                if (q < n) {
+                    const double2 c = A[p * LD + q];
+                    const double ac2 = c.x * c.x + c.y * c.y;
+                    if (ac2 > skip2 && ac2 > 1e-300) {
+                        const double ri = rsqrt(ac2);  // 1 / |a_pq|
+                        const double tau = 0.5 * (A[q * LD + q].x - A[p * LD + p].x) * ri;
+                        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        R.cs = rsqrt(1.0 + t * t);
+                        R.sn = t * R.cs;
+                        R.er = c.x * ri;
+                        R.ei = -c.y * ri;
+                    }
+                } else {
+                    R.q = -1;  // paired with the dummy index: no rotation
+                }
+                rot[lane] = R;
+            }
+            __syncthreads();
+            for (int bk = lane; bk < P * P; bk += 64) {
+                const int s2 = bk / P, s1 = bk - s2 * P;
+                if (s2 > s1) continue;
+                const Rot Rc = rot[s1], Rr = rot[s2];
+                const bool idc = Rc.q < 0 || (Rc.sn == 0.0 && Rc.er == 1.0 && Rc.ei == 0.0);
+                const bool idr = Rr.q < 0 || (Rr.sn == 0.0 && Rr.er == 1.0 && Rr.ei == 0.0);
+                if (idc && idr) continue;
+                const int xr[2] = {Rr.p, Rr.q}, yc[2] = {Rc.p, Rc.q};
+                double2 B[2][2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        B[i][j] = (xr[i] >= 0 && yc[j] >= 0) ? A[xr[i] * LD + yc[j]] : double2{0, 0};
+                if (!idc) {
+                    const double2 e2 = double2{Rc.er, Rc.ei};
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const double2 bp = B[i][0], ebq = cmulz(e2, B[i][1]);
+                        B[i][0] = double2{Rc.cs * bp.x - Rc.sn * ebq.x, Rc.cs * bp.y - Rc.sn * ebq.y};
+                        B[i][1] = double2{Rc.sn * bp.x + Rc.cs * ebq.x, Rc.sn * bp.y + Rc.cs * ebq.y};
+                    }
+                }
+                if (!idr) {
+                    const double2 ce = double2{Rr.er, -Rr.ei};
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const double2 bp = B[0][j], ebq = cmulz(ce, B[1][j]);
+                        B[0][j] = double2{Rr.cs * bp.x - Rr.sn * ebq.x, Rr.cs * bp.y - Rr.sn * ebq.y};
+                        B[1][j] = double2{Rr.sn * bp.x + Rr.cs * ebq.x, Rr.sn * bp.y + Rr.cs * ebq.y};
+                    }
+                }
+                if (s1 == s2) {
+                    // the rotated pair becomes diagonal with a real diagonal
+                    const int p = Rc.p, q = Rc.q;
+                    A[p * LD + p] = double2{B[0][0].x, 0.0};
+                    A[q * LD + q] = double2{B[1][1].x, 0.0};
+                    A[p * LD + q] = double2{0.0, 0.0};
+                    A[q * LD + p] = double2{0.0, 0.0};
+                    continue;
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        if (xr[i] >= 0 && yc[j] >= 0) {
+                            A[xr[i] * LD + yc[j]] = B[i][j];
+                            A[yc[j] * LD + xr[i]] = double2{B[i][j].x, -B[i][j].y};
+                        }
+            }
+            // V <- V J: columns p, q of V are rows p, q of Vt
+            for (int e = lane; e < P * n; e += 64) {
+                const int sidx = e / n, r = e - sidx * n;
+                const Rot R = rot[sidx];
+                if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
+                const double2 e2 = double2{R.er, R.ei};
+                const double2 vp = Vt[R.p * LD + r], eq = cmulz(e2, Vt[R.q * LD + r]);
+                Vt[R.p * LD + r] = double2{R.cs * vp.x - R.sn * eq.x, R.cs * vp.y - R.sn * eq.y};
+                Vt[R.q * LD + r] = double2{R.sn * vp.x + R.cs * eq.x, R.sn * vp.y + R.cs * eq.y};
+            }
+            __syncthreads();
+        }
+    }
+    // ascending order by rank (ties by index), then emit
+    for (int i = lane; i < n; i += 64) dg[i] = A[i * LD + i].x;
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) {
+        int r = 0;
+        for (int j = 0; j < n; ++j) r += (dg[j] < dg[i]) || (dg[j] == dg[i] && j < i);
+        perm[r] = i;
+    }
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) ev[i] = dg[perm[i]];
+    for (int e = lane; e < n * n; e += 64) {
+        const int r = e / n, c = e - r * n;
+        vo[e] = Vt[perm[c] * LD + r];
+    }
+}
+
+__global__ void __launch_bounds__(64)
+k_jacobi_eigh_wave(int n, const double2* __restrict__ H, double* __restrict__ eig, double2* __restrict__ vecs) {
+    const int64_t b = blockIdx.x;
+    jacobi_eigh_wave(n, H + b * n * n, eig + b * n, vecs + b * n * n);
+}
+
+__global__ void __launch_bounds__(64)
+k_jacobi_eigh_seg_wave(const Seg* __restrict__ seg, const double2* __restrict__ H, double* __restrict__ eig,
+                       double2* __restrict__ vecs) {
+    const Seg sg = seg[blockIdx.x];
+    jacobi_eigh_wave(sg.nb, H + sg.moff, eig + sg.f_off, vecs + sg.moff);
+}
+
 __global__ void __launch_bounds__(256)
 k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, double2* __restrict__ vecs,
               double2* __restrict__ scratch) {
@@ -1062,9 +1236,12 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(ctx, DPP_TK_EIGH);
-    const int nt = nb <= 32 ? 64 : 256;  // one wave: barriers are nearly free at small nb
-    hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(nt), lds, ctx->stream, nb, (const double2*)H, eig,
-                       (double2*)vecs, nb <= 64 ? (double2*)nullptr : (double2*)ws);
+    if (nb <= EIGW_MAXN)
+        hipLaunchKernelGGL(k_jacobi_eigh_wave, dim3(batch), dim3(64), 0, ctx->stream, nb, (const double2*)H, eig,
+                           (double2*)vecs);
+    else
+        hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(256), lds, ctx->stream, nb, (const double2*)H, eig,
+                           (double2*)vecs, nb <= 64 ? (double2*)nullptr : (double2*)ws);
     DPP_LAUNCHED();
     return DPP_OK;
 }

@@ -240,6 +240,7 @@ extern "C" dpp_status dpp_grid_create(dpp_ctx ctx, const double* R, const int* S
     it.planes = g->d_fullplanes;
     it.omega = g->omega;
     it.vscale = g->omega / (double)g->N;
+    it.vperm = 1;
     for (int i = 0; i < 9; ++i) it.B[i] = g->B[i];
     *out = g;
     return DPP_OK;

@@ -88,6 +88,11 @@ struct dpp_system_s {
     std::vector<CellDesc> h_cells;
     std::vector<FftItem> h_box;
     FftItem* d_box = nullptr;
+    // x pass of H: V_eff copy in plane order, scaled (rebuilt when V_eff changed)
+    std::vector<FftItem> h_vx;
+    FftItem* d_vx = nullptr;
+    double* Vx = nullptr;
+    bool vx_dirty = true;
     // block buffers (total elements each)
     double2 *HY, *Dd, *HD, *g, *g2, *Kg, *gp, *Dp, *psi, *T1, *T2;
     // small matrices (msum elements each) and projector overlaps (pisum)
@@ -237,6 +242,7 @@ dpp_status items_for(dpp_system_s* s, int nbo, const ItemTable** out) {
             it.dchunk = (it.nb + it.dnch - 1) / it.dnch;
             it.p_off = poff;
             it.perm = (s->reg_planes && it.S1 == it.S2 && plane_reg_supported(it.S1)) ? 1 : 0;
+            it.vperm = 0;  // the x pass reads Vx
             poff += (int64_t)it.dnch * ch.N;
             np += it.dnch;
             toff += (int64_t)it.nb * it.nplanes * it.S1 * it.S2;
@@ -340,11 +346,15 @@ dpp_status apply_H_all(dpp_system_s* s, int nbo, const double2* X, double2* HX, 
     const ItemTable* it;
     DPP_TRY(items_for(s, nbo, &it));
     const XzPlan* plan = s->reg_xpass ? &it->xz : nullptr;
+    if (s->vx_dirty) {
+        DPP_TRY(vx_cells(s->ctx, s->d_vx, s->ncells, s->maxN, s->Veff, s->Vx));
+        s->vx_dirty = false;
+    }
     if (s->prec == DPP_F64)
-        DPP_TRY(apply_H_local_batched<double>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act, plan,
+        DPP_TRY(apply_H_local_batched<double>(s->ctx, it->d_items, it->h, X, HX, s->Vx, s->Tplanes, act, plan,
                                               &it->pl));
     else
-        DPP_TRY(apply_H_local_batched<float>(s->ctx, it->d_items, it->h, X, HX, s->Veff, s->Tplanes, act, plan,
+        DPP_TRY(apply_H_local_batched<float>(s->ctx, it->d_items, it->h, X, HX, s->Vx, s->Tplanes, act, plan,
                                              &it->pl));
     if (s->maxnproj > 0) {
         std::vector<OvTask> t;
@@ -500,6 +510,7 @@ dpp_status potentials(dpp_system_s* s, const double* n) {
     hipLaunchKernelGGL(k_grid_lin3, dim3((unsigned)((s->Ntot + 255) / 256)), dim3(256), 0, stream(s), s->Ntot, 1.0,
                        s->Vloc, 1.0, s->VH, 1.0, s->vxc, s->Veff);
     DPP_LAUNCHED();
+    s->vx_dirty = true;
     return DPP_OK;
 }
 
@@ -657,8 +668,12 @@ dpp_status subspace_rotate(dpp_system_s* s, double2* Y) {
             DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh_seg),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         TimerScope ts_(s->ctx, DPP_TK_EIGH);
-        hipLaunchKernelGGL(k_jacobi_eigh_seg, dim3(s->nit), dim3(n <= 32 ? 64 : 256), lds, stream(s), s->d_seg,
-                           (const double2*)s->H0, s->d_eig, s->vecs, s->eig_scr);
+        if (n <= EIGW_MAXN)
+            hipLaunchKernelGGL(k_jacobi_eigh_seg_wave, dim3(s->nit), dim3(64), 0, stream(s), s->d_seg,
+                               (const double2*)s->H0, s->d_eig, s->vecs);
+        else
+            hipLaunchKernelGGL(k_jacobi_eigh_seg, dim3(s->nit), dim3(256), lds, stream(s), s->d_seg,
+                               (const double2*)s->H0, s->d_eig, s->vecs, s->eig_scr);
         DPP_LAUNCHED();
     }
     DPP_TRY(rotate_jobs(s, 0, {RotJob{s->psi, s->vecs, 0.0, Y}, RotJob{s->T1, s->vecs, 0.0, s->HY}}));
@@ -747,6 +762,7 @@ dpp_status energy_V(dpp_system_s* s, const double2* Y, Parts& P) {
         hipLaunchKernelGGL(k_grid_lin3, dim3((unsigned)((s->Ntot + 255) / 256)), dim3(256), 0, stream(s), s->Ntot,
                            1.0, s->Vloc, 1.0, s->VH, 1.0, s->vxc, s->Veff);
         DPP_LAUNCHED();
+        s->vx_dirty = true;
     }
     return read_parts(s, P);
 }
@@ -994,6 +1010,10 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
         bx.t_off = ch.foff;  // complex plane offset: N per cell
         bx.p_off = eoff;
         s->h_box.push_back(bx);
+        FftItem vx = ch.grid->h_item;
+        vx.v_off = ch.foff;
+        vx.perm = (s->reg_planes && vx.S1 == vx.S2 && plane_reg_supported(vx.S1)) ? 1 : 0;
+        s->h_vx.push_back(vx);
         eoff += ch.grid->S[1];
     }
     for (int k = 0; k < nit; ++k) {
@@ -1035,7 +1055,7 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
                  {&s->d_cred, cell_red_elems(ncells)}, {&s->d_epart, (size_t)eoff},
                  {&s->cg.at, nis}, {&s->cg.gkg, nis}, {&s->cg.beta, nis}, {&s->cg.d0, nis}, {&s->cg.d0r, nis},
                  {&s->cg.step, nis}, {&s->cg.step2, nis}, {&s->cg.cK, nis}, {&s->cg.cD, nis},
-                 {&s->Vloc, Nt}, {&s->VH, Nt}, {&s->vxc, Nt}, {&s->Veff, Nt}, {&s->n, Nt}, {&s->nin, Nt},
+                 {&s->Vloc, Nt}, {&s->VH, Nt}, {&s->vxc, Nt}, {&s->Veff, Nt}, {&s->Vx, Nt}, {&s->n, Nt}, {&s->nin, Nt},
                  {&s->nout, Nt}, {&s->hist_n, PULAY_MAX * Nt}, {&s->hist_r, PULAY_MAX * Nt},
                  {&s->pulayA, (size_t)ncells * PULAY_MAX * PULAY_MAX}, {&s->pulayC, (size_t)ncells * PULAY_MAX}};
     for (auto& r : reals)
@@ -1050,6 +1070,7 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
     if ((st = dalloc_t(s, &s->d_seg, nis)) != DPP_OK) return fail(st);
     if ((st = dalloc_t(s, &s->d_cells, (size_t)ncells)) != DPP_OK) return fail(st);
     if ((st = dalloc_t(s, &s->d_box, (size_t)ncells)) != DPP_OK) return fail(st);
+    if ((st = dalloc_t(s, &s->d_vx, (size_t)ncells)) != DPP_OK) return fail(st);
     size_t gwsb = 0;
     for (const CellHost& ch : s->cells) {
         size_t b = 0;
@@ -1092,7 +1113,8 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
     }
     if (hipMemcpy(s->d_seg, s->h_seg.data(), nis * sizeof(Seg), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s->d_cells, s->h_cells.data(), ncells * sizeof(CellDesc), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(s->d_box, s->h_box.data(), ncells * sizeof(FftItem), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(s->d_box, s->h_box.data(), ncells * sizeof(FftItem), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->d_vx, s->h_vx.data(), ncells * sizeof(FftItem), hipMemcpyHostToDevice) != hipSuccess)
         return fail(set_error(DPP_EDEVICE, "dpp_batch_create: upload failed"));
     // clear every buffer once (history buffers are read before written otherwise)
     hipStream_t sst = stream(s);
@@ -1175,7 +1197,10 @@ extern "C" dpp_status dpp_system_field(dpp_system s, int which, double** d_ptr) 
     DPP_REQUIRE(s && d_ptr, "dpp_system_field: null argument");
     switch (which) {
         case DPP_FIELD_VLOC: *d_ptr = s->Vloc; break;
-        case DPP_FIELD_VEFF: *d_ptr = s->Veff; break;
+        case DPP_FIELD_VEFF:
+            *d_ptr = s->Veff;
+            s->vx_dirty = true;  // the caller may write through it
+            break;
         case DPP_FIELD_N: *d_ptr = s->n; break;
         case DPP_FIELD_NIN: *d_ptr = s->nin; break;
         case DPP_FIELD_NOUT: *d_ptr = s->nout; break;
@@ -1230,6 +1255,7 @@ extern "C" dpp_status dpp_cg_B_init(dpp_system s, dpp_c64* Y, const double* d_Ve
     DPP_REQUIRE(s && Y && d_Veff, "dpp_cg_B_init: null argument");
     if (d_Veff != s->Veff)
         DPP_HIP(hipMemcpyAsync(s->Veff, d_Veff, s->Ntot * sizeof(double), hipMemcpyDeviceToDevice, stream(s)));
+    s->vx_dirty = true;
     DPP_TRY(cgB_init(s, (double2*)Y));
     return read_bE0(s, Eb);
 }

@@ -242,12 +242,12 @@ k_xz(const FftItem* items, FftItem single, typename cx<T>::t* __restrict__ Tb,
         return;
     }
     // XZ_H: pointwise (Omega/N) V_eff at the natural (i1, i2) of the row
-    const int n1 = it.perm ? digit_rev_axis(it.ax[1], i1) : i1;
+    const int n1 = it.vperm && it.perm ? digit_rev_axis(it.ax[1], i1) : i1;
     const double* Vp = V + it.v_off + (int64_t)n1 * S2;
-    const T sc = (T)it.vscale;
+    const T sc = (T)(it.vperm ? it.vscale : 1.0);
     for (int i = threadIdx.x; i < e; i += blockDim.x) {
         const int i0 = i / S2, i2 = i - i0 * S2;
-        const int n2 = it.perm ? digit_rev_axis(it.ax[2], i2) : i2;
+        const int n2 = it.vperm && it.perm ? digit_rev_axis(it.ax[2], i2) : i2;
         const T v = (T)Vp[(int64_t)i0 * S1 * S2 + n2] * sc;
         lds[i] = Cx{lds[i].x * v, lds[i].y * v};
     }
@@ -418,12 +418,12 @@ k_xz_reg(const FftItem* __restrict__ items, const int* __restrict__ idx, typenam
     reg_dif<T, S0, +1, 0>(x, tw64, tw32);
     // natural (i1, i2) of this column (planes may be stored digit-reversed)
     int vcol = col;
-    if (it.perm) {
+    if (it.vperm && it.perm) {
         const int p1 = col / it.S2, p2 = col - p1 * it.S2;
         vcol = digit_rev_axis(it.ax[1], p1) * it.S2 + digit_rev_axis(it.ax[2], p2);
     }
     const double* Vp = V + it.v_off + vcol;
-    const T sc = (T)it.vscale;
+    const T sc = (T)(it.vperm ? it.vscale : 1.0);
 #pragma unroll
     for (int p = 0; p < S0; ++p) {
         const int k = reg_digit_rev(S0, p);
@@ -494,12 +494,12 @@ k_xz_reg2(const FftItem* __restrict__ items, const int* __restrict__ idx, typena
     }
     reg_dif<T, M, +1, 0>(x, nullptr, nullptr);
     int vcol = col;
-    if (it.perm) {
+    if (it.vperm && it.perm) {
         const int p1 = col / it.S2, p2 = col - p1 * it.S2;
         vcol = digit_rev_axis(it.ax[1], p1) * it.S2 + digit_rev_axis(it.ax[2], p2);
     }
     const double* Vp = V + it.v_off + vcol + (int64_t)h * np;
-    const T sc = (T)it.vscale;
+    const T sc = (T)(it.vperm ? it.vscale : 1.0);
 #pragma unroll
     for (int p = 0; p < M; ++p) {
         const int k = 2 * reg_digit_rev(M, p);
@@ -1117,6 +1117,32 @@ template dpp_status apply_H_local_batched<double>(dpp_ctx_s*, const FftItem*, co
 template dpp_status apply_H_local_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&,
                                                  const double2*, double2*, const double*, void*, const int*,
                                                  const XzPlan*, const PlanePlan*);
+
+__global__ void __launch_bounds__(256)
+k_vx_cells(const FftItem* __restrict__ items, const double* __restrict__ V, double* __restrict__ Vx) {
+    const FftItem& it = items[blockIdx.y];
+    const int np = it.S1 * it.S2;
+    const int64_t N = (int64_t)it.S0 * np;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
+        const int k = (int)(e / np), col = (int)(e - (int64_t)k * np);
+        int vcol = col;
+        if (it.perm) {
+            const int p1 = col / it.S2, p2 = col - p1 * it.S2;
+            vcol = digit_rev_axis(it.ax[1], p1) * it.S2 + digit_rev_axis(it.ax[2], p2);
+        }
+        Vx[it.v_off + e] = it.vscale * V[it.v_off + (int64_t)k * np + vcol];
+    }
+}
+
+dpp_status vx_cells(dpp_ctx_s* cx_, const FftItem* d_cell_items, int ncells, int64_t maxN, const double* V,
+                    double* Vx) {
+    if (ncells <= 0) return DPP_OK;
+    TimerScope ts_(cx_, DPP_TK_FIELDS);
+    const unsigned nbx = (unsigned)std::min<int64_t>(1024, (maxN + 255) / 256);
+    hipLaunchKernelGGL(k_vx_cells, dim3(nbx, (unsigned)ncells), dim3(256), 0, cx_->stream, d_cell_items, V, Vx);
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
 
 template <typename T>
 dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,

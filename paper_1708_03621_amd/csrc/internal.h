@@ -61,6 +61,8 @@ struct FftItem {
     const int4* planes;   // per plane: {sphere start, count, n1 of first row, nrows}
     const int4* rows;     // per (plane, natural i1): {first point, count, n2 of first point, 0}
     int perm;             // 1: planes stored in digit-reversed (i1, i2) order (register plane passes)
+    int vperm;            // x pass of H: 1 = V is natural (digit-reverse the column, times vscale);
+                          // 0 = V is already in the plane order and scaled
     const int* poff;      // per sphere point: i1*S2 + i2
     const double* kG2;    // per sphere point |k+G|^2
     int64_t c_off;        // offset (complex elements) of this item's block
@@ -220,6 +222,11 @@ dpp_status density_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::ve
                            const CellDesc* d_cells, int ncells, int64_t maxN, double* n,
                            const PlanePlan* pplan = nullptr);
 size_t batched_plane_elems(const std::vector<FftItem>& h_items);
+// Vx = (Omega/N) V in the plane order of each cell's x pass (one item per
+// cell: v_off = field offset, perm, axes); the x pass of H then reads it
+// with unit stride (items with vperm = 0).
+dpp_status vx_cells(dpp_ctx_s* ctx, const FftItem* d_cell_items, int ncells, int64_t maxN, const double* V,
+                    double* Vx);
 // Hartree potential and energy of every cell: full-box items (one per cell,
 // v_off = field offset, t_off = plane offset, p_off = row-partial offset).
 dpp_status hartree_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
