@@ -645,6 +645,143 @@ k_cholesky_seg(const Seg* __restrict__ seg, int nbo, const double2* __restrict__
     chol_store(n, f, A, Rinv + sg.moff, status);
 }
 
+// ------------------------------------------ single-wave Cholesky inverse ---
+// U = R^dag R and X = R^{-1} for n <= NMAX (16 or 32) in one wave.  The
+// factorization holds the upper triangle of U in registers, lane (j, g)
+// owning rows g*RPL .. g*RPL + RPL - 1 of column j; step k reads the pivot
+// from its lane, scales row k, publishes it in LDS (row k of R) and every
+// lane updates its own entries, so a step costs one LDS round trip.  The
+// inverse holds row i of X in lane i and runs the recurrence
+//   X[i][j] R[j][j] = delta_ij - sum_{k<j} X[i][k] R[k][j]
+// over j with R read from LDS.  Returns 1 (uniform) when a pivot falls
+// below CH_PIVOT_RTOL times the largest diagonal element.
+template <int NMAX>
+struct CholWaveLds {
+    double2 R[NMAX][NMAX + 1];  // rows of R (upper triangle; zeros below)
+    double rinv[NMAX];          // 1 / R[k][k]
+    double2 X[NMAX][NMAX + 1];  // R^{-1}, row-major, zeros below the diagonal
+};
+
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int NMAX, typename Load>
+__device__ int chol_inv_wave(int n, Load load, CholWaveLds<NMAX>& L) {
+    constexpr int G = 64 / NMAX, RPL = NMAX / G;
+    const int lane = threadIdx.x;
+    const int j = lane % NMAX, g = lane / NMAX;
+    double2 a[RPL];
+    double dmax = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = g * RPL + r;
+        double2 v = double2{0.0, 0.0};
+        if (i <= j && j < n) v = load(i, j);
+        if (i == j) {
+            v.y = 0.0;
+            dmax = fmax(dmax, v.x);
+        }
+        a[r] = v;
+    }
+    dmax = wave_max(dmax);
+    int failed = 0;
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+        // (no early exit: a fully unrolled loop keeps a[] in registers)
+        if (k >= n || failed) continue;
+        const double d = lane_read(a[k % RPL].x, k + NMAX * (k / RPL));
+        if (!(d > CH_PIVOT_RTOL * dmax)) {
+            failed = 1;
+            continue;
+        }
+        const double rkk = sqrt(d), inv = 1.0 / rkk;
+        if (g == k / RPL) {
+            const double2 v = a[k % RPL];
+            const double2 w = j > k ? double2{v.x * inv, v.y * inv} : (j == k ? double2{rkk, 0.0} : double2{0.0, 0.0});
+            a[k % RPL] = w;
+            L.R[k][j] = w;
+        }
+        if (lane == 0) L.rinv[k] = inv;
+        __syncthreads();
+        const double2 rkj = L.R[k][j];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = g * RPL + r;
+            if (i > k && i <= j) {
+                const double2 rki = L.R[k][i];
+                a[r].x -= rki.x * rkj.x + rki.y * rkj.y;  // conj(R[k][i]) R[k][j]
+                a[r].y -= rki.x * rkj.y - rki.y * rkj.x;
+            }
+        }
+    }
+    if (failed) return 1;
+    double2 x[NMAX];
+#pragma unroll
+    for (int m = 0; m < NMAX; ++m) x[m] = double2{0.0, 0.0};
+    const int i = lane;
+#pragma unroll
+    for (int jj = 0; jj < NMAX; ++jj) {
+        if (jj >= n) continue;
+        double sr = i == jj ? 1.0 : 0.0, si = 0.0;
+#pragma unroll
+        for (int k = 0; k < jj; ++k) {
+            const double2 r = L.R[k][jj];
+            sr -= x[k].x * r.x - x[k].y * r.y;
+            si -= x[k].x * r.y + x[k].y * r.x;
+        }
+        const double ri = L.rinv[jj];
+        x[jj] = double2{sr * ri, si * ri};
+    }
+    if (i < NMAX) {
+#pragma unroll
+        for (int m = 0; m < NMAX; ++m) L.X[i][m] = x[m];
+    }
+    __syncthreads();
+    return 0;
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(64)
+k_cholesky_wave(int n, int64_t stride, const Seg* __restrict__ seg, int nbo, const double2* __restrict__ U,
+                double2* __restrict__ Rinv, int* __restrict__ status, const int* __restrict__ act) {
+    if (act && !act[blockIdx.x]) return;
+    __shared__ CholWaveLds<NMAX> L;
+    int64_t off = (int64_t)blockIdx.x * stride;
+    if (seg) {
+        const Seg sg = seg[blockIdx.x];
+        n = nbo > 0 ? nbo : sg.nb;
+        off = sg.moff;
+    }
+    const double2* Ug = U + off;
+    const int f = chol_inv_wave<NMAX>(n, [&](int r, int c) { return Ug[r * n + c]; }, L);
+    double2* X = Rinv + off;
+    if (f) {
+        if (threadIdx.x == 0 && status) atomicOr(status, DPP_STATUS_NOTPD);
+        for (int e = threadIdx.x; e < n * n; e += 64) X[e] = double2{NAN, NAN};
+        return;
+    }
+    for (int e = threadIdx.x; e < n * n; e += 64) {
+        const int r = e / n, c = e - r * n;
+        X[e] = L.X[r][c];
+    }
+}
+
 // Band-energy line search of every active item, entirely on the device (one
 // workgroup per item).  Along D the trial energy is
 //   E(a) = Tr(U(a)^{-1} H(a)),  U(a) = U + a (X + X^dag) + a^2 Q,
@@ -756,6 +893,132 @@ k_linesearch_B(const Seg* __restrict__ seg, const double2* __restrict__ U, const
         ok[k] = good;
         step[k] = st;
     }
+}
+
+// The line search for n <= NMAX bands in one wave: H(a) staged in LDS, the
+// factor and inverse of U(a) from chol_inv_wave, and
+//   E(a) = Re Tr(X^dag H(a) X) = sum_{a' <= i} Re conj(X[a'][i]) (H(a) X)[a'][i]
+// over (a', i) entries spread across the lanes.
+template <int NMAX>
+__device__ double trial_energy_wave(const Seg& sg, double a, const double2* __restrict__ U,
+                                    const double2* __restrict__ Xs, const double2* __restrict__ Q,
+                                    const double2* __restrict__ H0, const double2* __restrict__ Ps,
+                                    const double2* __restrict__ H2, CholWaveLds<NMAX>& L,
+                                    double2 (*Hs)[NMAX + 1]) {
+    const int n = sg.nb;
+    const int64_t o = sg.moff;
+    for (int e = threadIdx.x; e < n * n; e += 64) {
+        const int r = e / n, c = e - r * n;
+        const double2 h = Ps[o + e], h0 = H0[o + e], h2 = H2[o + e];
+        Hs[r][c] = double2{h0.x + a * h.x + a * a * h2.x, h0.y + a * h.y + a * a * h2.y};
+    }
+    // (the staging is ordered before its use by the barriers of the factorization)
+    const int failed = chol_inv_wave<NMAX>(
+        n,
+        [&](int r, int c) {
+            const double2 x = Xs[o + r * n + c], u = U[o + r * n + c], q = Q[o + r * n + c];
+            return double2{u.x + a * x.x + a * a * q.x, u.y + a * x.y + a * a * q.y};
+        },
+        L);
+    if (failed) return NAN;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += 64) {
+        const int ar = e / n, i = e - ar * n;
+        if (ar > i) continue;
+        double wr = 0.0, wi = 0.0;
+        for (int t = 0; t <= i; ++t) {
+            const double2 h = Hs[ar][t], r = L.X[t][i];
+            wr += h.x * r.x - h.y * r.y;
+            wi += h.x * r.y + h.y * r.x;
+        }
+        const double2 ra = L.X[ar][i];
+        acc += ra.x * wr + ra.y * wi;
+    }
+    acc = wave_sum64(acc);
+    __syncthreads();  // LDS is reused by the next trial
+    return acc;
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(64)
+k_linesearch_wave(const Seg* __restrict__ seg, const double2* __restrict__ U, const double2* __restrict__ X,
+                  const double2* __restrict__ Q, const double2* __restrict__ H0, const double2* __restrict__ H1,
+                  const double2* __restrict__ H2, const double* __restrict__ E0v, const double* __restrict__ at0,
+                  const double* __restrict__ d0v, const int* __restrict__ act, int* __restrict__ ok,
+                  double* __restrict__ step, double2* __restrict__ Xs, double2* __restrict__ Ps) {
+    const int k = blockIdx.x;
+    if (!act[k]) return;
+    __shared__ CholWaveLds<NMAX> L;
+    __shared__ double2 Hs[NMAX][NMAX + 1];
+    const Seg sg = seg[k];
+    {
+        const int n = sg.nb;
+        const int64_t o = sg.moff;
+        for (int e = threadIdx.x; e < n * n; e += 64) {
+            const int r = e / n, c = e - r * n;
+            const double2 x = X[o + e], xt = X[o + c * n + r];
+            const double2 h = H1[o + e], ht = H1[o + c * n + r];
+            Xs[o + e] = double2{x.x + xt.x, x.y - xt.y};
+            Ps[o + e] = double2{h.x + ht.x, h.y - ht.y};
+        }
+        __syncthreads();
+    }
+    const double E0 = E0v[k], d0 = d0v[k];
+    double at = at0[k];
+    int good = 0;
+    double st = 0.0;
+    for (int t = 0; t < LS_MAX_TRIES; ++t) {
+        const double Et = trial_energy_wave<NMAX>(sg, at, U, Xs, Q, H0, Ps, H2, L, Hs);
+        const double c = (Et - E0 - d0 * at) / (at * at);
+        double as = c > 0 ? -d0 / (2.0 * c) : 2.0 * at;
+        as = fmin(as, 10.0 * at);
+        const double Es = trial_energy_wave<NMAX>(sg, as, U, Xs, Q, H0, Ps, H2, L, Hs);
+        if (Es <= E0) {
+            good = 1;
+            st = as;
+            break;
+        }
+        if (Et <= E0) {
+            good = 1;
+            st = at;
+            break;
+        }
+        at *= 0.5;
+    }
+    if (threadIdx.x == 0) {
+        ok[k] = good;
+        step[k] = st;
+    }
+}
+
+// Launch helpers for the single-wave paths (n <= 32); false: use the
+// general kernels.
+bool cholesky_wave_launch(hipStream_t st, unsigned nblk, int n, int64_t stride, const Seg* seg, int nbo,
+                          const double2* U, double2* Rinv, int* status, const int* act) {
+    if (n <= 16)
+        hipLaunchKernelGGL(k_cholesky_wave<16>, dim3(nblk), dim3(64), 0, st, n, stride, seg, nbo, U, Rinv, status,
+                           act);
+    else if (n <= 32)
+        hipLaunchKernelGGL(k_cholesky_wave<32>, dim3(nblk), dim3(64), 0, st, n, stride, seg, nbo, U, Rinv, status,
+                           act);
+    else
+        return false;
+    return true;
+}
+
+bool linesearch_wave_launch(hipStream_t st, unsigned nblk, int n, const Seg* seg, const double2* U,
+                            const double2* X, const double2* Q, const double2* H0, const double2* H1,
+                            const double2* H2, const double* E0v, const double* at0, const double* d0v,
+                            const int* act, int* ok, double* step, double2* Xs, double2* Ps) {
+    if (n <= 16)
+        hipLaunchKernelGGL(k_linesearch_wave<16>, dim3(nblk), dim3(64), 0, st, seg, U, X, Q, H0, H1, H2, E0v, at0,
+                           d0v, act, ok, step, Xs, Ps);
+    else if (n <= 32)
+        hipLaunchKernelGGL(k_linesearch_wave<32>, dim3(nblk), dim3(64), 0, st, seg, U, X, Q, H0, H1, H2, E0v, at0,
+                           d0v, act, ok, step, Xs, Ps);
+    else
+        return false;
+    return true;
 }
 
 // ----------------------------------------------------- Jacobi eigensolver --
@@ -1209,9 +1472,12 @@ extern "C" dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(ctx, DPP_TK_CHOLESKY);
-    const int nt = nb <= 64 ? 64 : 256;  // the in-place inverse needs one thread per row
-    hipLaunchKernelGGL(k_cholesky_inverse, dim3(batch), dim3(nt), lds, ctx->stream, nb, (const double2*)U,
-                       (double2*)Rinv, ctx->d_status);
+    if (!cholesky_wave_launch(ctx->stream, (unsigned)batch, nb, (int64_t)nb * nb, nullptr, 0, (const double2*)U,
+                              (double2*)Rinv, ctx->d_status, nullptr)) {
+        const int nt = nb <= 64 ? 64 : 256;  // the in-place inverse needs one thread per row
+        hipLaunchKernelGGL(k_cholesky_inverse, dim3(batch), dim3(nt), lds, ctx->stream, nb, (const double2*)U,
+                           (double2*)Rinv, ctx->d_status);
+    }
     DPP_LAUNCHED();
     return DPP_OK;
 }

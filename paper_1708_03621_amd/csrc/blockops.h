@@ -86,6 +86,13 @@ __global__ void k_cholesky_seg(const Seg* seg, int nbo, const double2* U, double
                                const int* act);
 __global__ void k_jacobi_eigh_seg(const Seg* seg, const double2* H, double* eig, double2* vecs, double2* scratch);
 constexpr int EIGW_MAXN = 32;  // largest matrix of the single-wave eigensolver
+// Single-wave Cholesky inverse and line search for n <= 32 (false: n larger).
+bool cholesky_wave_launch(hipStream_t st, unsigned nblk, int n, int64_t stride, const Seg* seg, int nbo,
+                          const double2* U, double2* Rinv, int* status, const int* act);
+bool linesearch_wave_launch(hipStream_t st, unsigned nblk, int n, const Seg* seg, const double2* U,
+                            const double2* X, const double2* Q, const double2* H0, const double2* H1,
+                            const double2* H2, const double* E0v, const double* at0, const double* d0v,
+                            const int* act, int* ok, double* step, double2* Xs, double2* Ps);
 __global__ void k_jacobi_eigh_seg_wave(const Seg* seg, const double2* H, double* eig, double2* vecs);
 __global__ void k_linesearch_B(const Seg* seg, const double2* U, const double2* X, const double2* Q,
                                const double2* H0, const double2* H1, const double2* H2, const double* E0v,

@@ -479,8 +479,9 @@ dpp_status chol_all(dpp_system_s* s, int nbo, const double2* Um, double2* Ri) {
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_seg),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(s->ctx, DPP_TK_CHOLESKY);
-    hipLaunchKernelGGL(k_cholesky_seg, dim3(s->nit), dim3(n <= 64 ? 64 : 256), lds, stream(s), s->d_seg, nbo, Um, Ri,
-                       s->ctx->d_status, (const int*)nullptr);
+    if (!cholesky_wave_launch(stream(s), (unsigned)s->nit, n, 0, s->d_seg, nbo, Um, Ri, s->ctx->d_status, nullptr))
+        hipLaunchKernelGGL(k_cholesky_seg, dim3(s->nit), dim3(n <= 64 ? 64 : 256), lds, stream(s), s->d_seg, nbo, Um,
+                           Ri, s->ctx->d_status, (const int*)nullptr);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -598,10 +599,12 @@ dpp_status linesearch_B(dpp_system_s* s, const int* act, const double* d0, int* 
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_linesearch_B),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(s->ctx, DPP_TK_LINESEARCH);
-    hipLaunchKernelGGL(k_linesearch_B, dim3(s->nit), dim3(n <= 64 ? 64 : 256), lds, stream(s), s->d_seg,
-                       (const double2*)s->U, (const double2*)s->X, (const double2*)s->Q, (const double2*)s->H0,
-                       (const double2*)s->H1, (const double2*)s->H2, (const double*)s->d_bE0,
-                       (const double*)s->cg.at, d0, act, ok, step, stage, s->M1, s->M2);
+    if (!linesearch_wave_launch(stream(s), (unsigned)s->nit, n, s->d_seg, s->U, s->X, s->Q, s->H0, s->H1, s->H2,
+                                s->d_bE0, s->cg.at, d0, act, ok, step, s->M1, s->M2))
+        hipLaunchKernelGGL(k_linesearch_B, dim3(s->nit), dim3(n <= 64 ? 64 : 256), lds, stream(s), s->d_seg,
+                           (const double2*)s->U, (const double2*)s->X, (const double2*)s->Q, (const double2*)s->H0,
+                           (const double2*)s->H1, (const double2*)s->H2, (const double*)s->d_bE0,
+                           (const double*)s->cg.at, d0, act, ok, step, stage, s->M1, s->M2);
     DPP_LAUNCHED();
     return DPP_OK;
 }
