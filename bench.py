@@ -136,6 +136,7 @@ def main():
                     help="config2 (the metric's workload), config3 (64 atoms, 90^3, 128 bands) or config4 "
                          "(48 cells batched)")
     ap.add_argument("--eager", action="store_true", help="launch every kernel from the host (no graph replay)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (default launch rules)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built: "
@@ -174,8 +175,17 @@ def main():
         return np.array([e["E_el"] for e in E])
 
     results = {}
+    tuning = {}
     for prec, name in [(D.DPP_F64, "f64"), (D.DPP_F32, "mixed")]:
         sys_, Y = make(prec)
+        if not args.no_tune:
+            # launch autotuner (untimed): x-pass variant per box length and
+            # precision, rotate point tiles, overlap block shape
+            scratch = torch.empty_like(Y)
+            D.dpp_system_tune(sys_, Y, scratch, 5)
+            del scratch
+            tuning[name] = D.dpp_system_tune_report(sys_)
+            log(f"[{name}] tuning: {tuning[name]}")
         D.dpp_scf_init(sys_, cells=scf_cells)
         log(f"[{name}] warmup {args.warmup}")
         for _ in range(args.warmup):
@@ -282,6 +292,7 @@ def main():
                                        "band_residual": v["residual_after_timed"]} for k, v in results.items()},
         "mixed_note": "mixed = FFT passes, potential multiply and density in FP32 until the band residual "
                       "falls below 1e-4 Ha, FP64 after; contractions, Cholesky, eigensolver and reductions in FP64",
+        "tuning": tuning if tuning else None,
         "roofline": roof,
         "kernels": {k: {"avg_us": v["avg_us"], "launches": v["launches"], "ms_total": v["ms_total"],
                         "GBps": (v["alg_bytes"] / (v["ms_total"] * 1e-3) / 1e9) if v["alg_bytes"] else None}

@@ -344,6 +344,24 @@ dpp_status dpp_system_counters(dpp_system sys, int64_t *hc_bandk);
 /* HY = H Y on all bands of every item (packed layout, at the potential
  * last set: V_eff of the last SCF iteration or dpp_cg_B_init). */
 dpp_status dpp_system_apply_H(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY);
+/* Launch autotuner (form 2's tiles, chosen per system by measurement):
+ * times the candidate launch variants on the system's own items and keeps
+ * the fastest.  Choices: per x-pass length S0 and precision, the register
+ * x pass with one thread per column, with a lane pair per column, or the
+ * LDS pass; point tiles per wave of the X M contraction (1, 2 or 4, for up
+ * to 32 bands); the A^dag O B block shape (2x2 tiles per wave or single
+ * tiles).  Y (device, packed layout) is the block the H applications and
+ * contractions run on; HY (device, same size) is overwritten.  Each
+ * candidate runs reps >= 1 times after a warm-up.  Runs eagerly and
+ * synchronizes; the system's internal work blocks are overwritten (a band-CG
+ * run must start again with dpp_cg_B_init or dpp_scf_init) and captured
+ * graphs are dropped.  Results of every variant agree to rounding.  Errors:
+ * DPP_EINVAL for bad arguments or a capturing stream. */
+dpp_status dpp_system_tune(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY, int reps);
+/* Text report of the last dpp_system_tune: the timed candidates (us per
+ * call) and the choices; buf (host, len bytes) receives a NUL-terminated
+ * string, truncated to fit. */
+dpp_status dpp_system_tune_report(dpp_system sys, char *buf, size_t len);
 /* Precision policy (form 1): FFT passes, potential multiply and density in
  * `bulk` (DPP_F32 or DPP_F64) until the largest band residual
  * max_i ||(H - eps_i O) psi_i||_2 / sqrt(Omega) of an SCF iteration (over

@@ -258,21 +258,21 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
 // Batched: the caller has set part_off of every task (disjoint partial areas)
 // and copied the table to d_tasks.
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
-                         const int* act) {
+                         const int* act, int ov_narrow) {
     if (h.empty()) return DPP_OK;
     int mc = 1, mt = 1, mblk = 1;
     double by = 0, fl = 0;
     for (const OvTask& t : h) {
         mc = std::max(mc, t.nchunk);
         mt = std::max(mt, t.ntiles);
-        mblk = std::max(mblk, ov_task_blocks((t.nbA + 15) / 16, t.tilesB));
+        mblk = std::max(mblk, ov_narrow ? t.ntiles : ov_task_blocks((t.nbA + 15) / 16, t.tilesB));
         by += 16.0 * t.npw * (t.nbA + t.nbB);
         fl += 8.0 * t.npw * t.nbA * (double)t.nbB;
     }
     if (mt > 65535 || h.size() > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: batch too large");
     {
         TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_OVERLAP, act ? 0.0 : by, act ? 0.0 : fl);
-        overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1, part, act);
+        overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act);
         DPP_LAUNCHED();
     }
     TimerScope ts2_(ctx, act ? DPP_TK_MASKED : DPP_TK_BLOCKOPS);
@@ -413,18 +413,20 @@ static void rotate_go(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single
 // the launch keeps at least RT_MIN_WAVES waves.
 constexpr int64_t RT_MIN_WAVES = 4096;
 static dpp_status rotate_launch(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single, unsigned ntasks,
-                                int maxnpw, int maxnbO, int64_t tiles, const int* act) {
+                                int maxnpw, int maxnbO, int64_t tiles, const int* act, int rot_pt = 0) {
     const int ntile = (maxnpw + 15) / 16;
     const int jtiles = (maxnbO + 15) / 16;
     if (jtiles == 1) {
-        if (tiles >= 4 * RT_MIN_WAVES)
+        const int pt = rot_pt ? rot_pt : (tiles >= 4 * RT_MIN_WAVES ? 4 : tiles >= 2 * RT_MIN_WAVES ? 2 : 1);
+        if (pt == 4)
             rotate_go<4, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
-        else if (tiles >= 2 * RT_MIN_WAVES)
+        else if (pt == 2)
             rotate_go<2, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
         else
             rotate_go<1, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
     } else if (jtiles == 2) {
-        if (tiles >= 2 * RT_MIN_WAVES)
+        const int pt = rot_pt ? rot_pt : (tiles >= 2 * RT_MIN_WAVES ? 2 : 1);
+        if (pt >= 2)
             rotate_go<2, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act);
         else
             rotate_go<1, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act);
@@ -442,7 +444,8 @@ dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t l
     return rotate_launch(ctx, nullptr, t, 1, npw, nbO, (npw + 15) / 16, nullptr);
 }
 
-dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks, const int* act) {
+dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks, const int* act,
+                        int rot_pt) {
     if (h.empty()) return DPP_OK;
     int mp = 1, mj = 1;
     int64_t tiles = 0;
@@ -455,7 +458,7 @@ dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTas
         fl += 8.0 * t.npw * (t.nbX + t.nbX2) * (double)t.nbO;
     }
     TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_ROTATE, act ? 0.0 : by, act ? 0.0 : fl);
-    return rotate_launch(ctx, d_tasks, RotTask{}, (unsigned)h.size(), mp, mj * 16, tiles, act);
+    return rotate_launch(ctx, d_tasks, RotTask{}, (unsigned)h.size(), mp, mj * 16, tiles, act, rot_pt);
 }
 
 // ------------------------------------------------- small-matrix products ---

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
@@ -125,9 +126,12 @@ struct dpp_system_s {
     dpp_precision prec = DPP_F64, bulk_prec = DPP_F64;
     double refine_res = 0.0, last_res = -1.0;
     std::vector<double> cell_res;
-    // launch choices (set by dpp_system_tune)
+    // launch choices: fixed layout choices, and the ones dpp_system_tune times
     bool reg_xpass = true;  // register-resident x pass of H where S0 is compiled in
     bool reg_planes = true; // register plane passes (digit-reversed planes) for square y-z faces
+    int rot_pt = 0;         // rotate point tiles per wave (0: by launch size)
+    int ov_narrow = 0;      // 1: overlap tasks as single tiles per wave
+    std::string tune_report;
     // graphs
     bool graph_on = false;
     hipStream_t cap_stream = nullptr;
@@ -305,7 +309,7 @@ dpp_status overlap_jobs(dpp_system_s* s, int nbo, const std::vector<OvJob>& jobs
     if ((size_t)poff > s->ov_part_elems) return set_error(DPP_EUNSUPPORTED, "overlap partial buffer too small");
     const OvTask* d = nullptr;
     DPP_TRY(table_t(s, t, &d));
-    return overlap_tasks(s->ctx, t, d, s->ov_part, act);
+    return overlap_tasks(s->ctx, t, d, s->ov_part, act, s->ov_narrow);
 }
 
 struct RotJob {
@@ -334,7 +338,7 @@ dpp_status rotate_jobs(dpp_system_s* s, int nbo, const std::vector<RotJob>& jobs
         }
     const RotTask* d = nullptr;
     DPP_TRY(table_t(s, t, &d));
-    return rotate_tasks(s->ctx, t, d, act);
+    return rotate_tasks(s->ctx, t, d, act, s->rot_pt);
 }
 
 // HX = H X for nbo bands of every item: batched FFT passes at each cell's
@@ -378,10 +382,10 @@ dpp_status apply_H_all(dpp_system_s* s, int nbo, const double2* X, double2* HX, 
         if ((size_t)poff > s->ov_part_elems) return set_error(DPP_EUNSUPPORTED, "overlap partial buffer too small");
         const OvTask* dt = nullptr;
         DPP_TRY(table_t(s, t, &dt));
-        DPP_TRY(overlap_tasks(s->ctx, t, dt, s->ov_part, act));
+        DPP_TRY(overlap_tasks(s->ctx, t, dt, s->ov_part, act, s->ov_narrow));
         const RotTask* dr = nullptr;
         DPP_TRY(table_t(s, r, &dr));
-        DPP_TRY(rotate_tasks(s->ctx, r, dr, act));
+        DPP_TRY(rotate_tasks(s->ctx, r, dr, act, s->rot_pt));
     }
     return DPP_OK;
 }
@@ -404,7 +408,7 @@ dpp_status proj_overlaps(dpp_system_s* s, int nbo, const double2* X) {
     if (t.empty()) return DPP_OK;
     const OvTask* dt = nullptr;
     DPP_TRY(table_t(s, t, &dt));
-    return overlap_tasks(s->ctx, t, dt, s->ov_part);
+    return overlap_tasks(s->ctx, t, dt, s->ov_part, nullptr, s->ov_narrow);
 }
 
 // n = sum_k w_k sum_i f_ki |I psi_ki|^2 per cell over nbo bands (fillings at d_f).
@@ -1390,6 +1394,115 @@ extern "C" dpp_status dpp_system_counters(dpp_system s, int64_t* hc_bandk) {
     clear_error();
     DPP_REQUIRE(s && hc_bandk, "dpp_system_counters: null argument");
     *hc_bandk = s->hc_bandk;
+    return DPP_OK;
+}
+
+// ------------------------------------------------------------ autotuner ---
+// Times each candidate launch variant on the system's own items and keeps
+// the fastest: per x length S0 (and precision) the register x pass with one
+// thread per column, with a lane pair per column, or the LDS pass; the point
+// tiles per rotate wave; the overlap block shape.  Each candidate runs
+// `reps` times (after one warm-up run) between HIP events on the library
+// stream; the first candidate wins ties.
+extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* HYc, int reps) {
+    clear_error();
+    DPP_REQUIRE(s && Yc && HYc && reps >= 1 && (const void*)Yc != (const void*)HYc, "dpp_system_tune: bad arguments");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DPP_HIP(hipStreamIsCapturing(stream(s), &cs));
+    DPP_REQUIRE(cs == hipStreamCaptureStatusNone, "dpp_system_tune: stream is capturing");
+    const double2* Y = (const double2*)Yc;
+    double2* HY = (double2*)HYc;
+    const ItemTable* itc = nullptr;
+    DPP_TRY(items_for(s, 0, &itc));
+    ItemTable* it = const_cast<ItemTable*>(itc);
+    hipEvent_t e0, e1;
+    DPP_HIP(hipEventCreate(&e0));
+    DPP_HIP(hipEventCreate(&e1));
+    const int64_t bandk = s->hc_bandk;
+    dpp_status err = DPP_OK;
+    auto timeit = [&](auto&& fn) -> double {
+        if (err != DPP_OK) return 1e300;
+        if ((err = fn()) != DPP_OK) return 1e300;
+        (void)hipEventRecord(e0, stream(s));
+        for (int r = 0; r < reps && err == DPP_OK; ++r) err = fn();
+        (void)hipEventRecord(e1, stream(s));
+        if (hipEventSynchronize(e1) != hipSuccess) err = set_error(DPP_EDEVICE, "dpp_system_tune: sync failed");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return err == DPP_OK ? 1e3 * ms / reps : 1e300;
+    };
+    static const char* xname[] = {"auto", "reg1", "reg2", "lds"};
+    std::string rep;
+    char buf[256];
+    const dpp_precision keep = s->prec;
+    for (dpp_precision pr : {DPP_F64, DPP_F32}) {
+        s->prec = pr;
+        const bool fp64 = pr == DPP_F64;
+        std::vector<int>& var = fp64 ? it->xz.var64 : it->xz.var32;
+        for (size_t g = 0; g < it->xz.S0.size(); ++g) {
+            double best = 1e300;
+            int bv = XZ_AUTO;
+            snprintf(buf, sizeof buf, "x pass S0=%d %s:", it->xz.S0[g], fp64 ? "f64" : "f32");
+            rep += buf;
+            for (int v : {XZ_REG2, XZ_REG1, XZ_LDS}) {
+                if (!xz_variant_available(it->xz.S0[g], fp64, v)) continue;
+                var[g] = v;
+                const double t = timeit([&] { return apply_H_all(s, 0, Y, HY); });
+                snprintf(buf, sizeof buf, " %s %.1f", xname[v], t);
+                rep += buf;
+                if (t < best) best = t, bv = v;
+            }
+            var[g] = bv;
+            snprintf(buf, sizeof buf, " us per H -> %s; ", xname[bv]);
+            rep += buf;
+        }
+    }
+    s->prec = keep;
+    if (s->maxnb <= 32) {
+        double best = 1e300;
+        int bp = 0;
+        rep += "rotate point tiles:";
+        for (int pt : {1, 2, 4}) {
+            s->rot_pt = pt;
+            const double t = timeit([&] { return rotate_jobs(s, 0, {RotJob{Y, s->Rinv, 0.0, s->psi}}); });
+            snprintf(buf, sizeof buf, " %d %.1f", pt, t);
+            rep += buf;
+            if (t < best) best = t, bp = pt;
+        }
+        s->rot_pt = bp;
+        snprintf(buf, sizeof buf, " us -> %d; ", bp);
+        rep += buf;
+    }
+    {
+        double best = 1e300;
+        int bn = 0;
+        rep += "overlap blocks:";
+        for (int nar : {0, 1}) {
+            s->ov_narrow = nar;
+            const double t = timeit([&] { return overlap_jobs(s, 0, {OvJob{Y, Y, 1.0, true, s->U}}); });
+            snprintf(buf, sizeof buf, " %s %.1f", nar ? "single-tile" : "wide", t);
+            rep += buf;
+            if (t < best) best = t, bn = nar;
+        }
+        s->ov_narrow = bn;
+        snprintf(buf, sizeof buf, " us -> %s", bn ? "single-tile" : "wide");
+        rep += buf;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->hc_bandk = bandk;
+    s->cgB_ready = false;  // the tuning runs overwrote the band-CG work blocks
+    // captured graphs hold the old launch shapes
+    for (ScfGraph& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+    s->tune_report = rep;
+    return err;
+}
+
+extern "C" dpp_status dpp_system_tune_report(dpp_system s, char* buf, size_t len) {
+    clear_error();
+    DPP_REQUIRE(s && buf && len > 0, "dpp_system_tune_report: bad arguments");
+    snprintf(buf, len, "%s", s->tune_report.c_str());
     return DPP_OK;
 }
 

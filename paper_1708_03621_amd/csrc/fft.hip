@@ -530,35 +530,67 @@ static void xz_reg2_one(dim3 grid, hipStream_t st, const FftItem* items, const i
 
 // Register x pass lengths: FP64 up to 45 and FP32 up to 64 points keep every
 // column in registers without scratch spills on gfx950.
+// One thread per column needs FP64 lengths up to 45 (FP32: 64); the lane-pair
+// split takes even lengths.  XZ_AUTO: the split from 24 (FP64, up to 45) or
+// 36 (FP32) points, where one thread per column runs at low occupancy.
+template <typename T, int N>
+constexpr bool xz_has(int v) {
+    const bool reg1 = !(sizeof(T) == 8 && N > 45);
+    const bool reg2 = N % 2 == 0;
+    return v == XZ_REG1 ? reg1 : v == XZ_REG2 ? reg2 : false;
+}
+template <typename T, int N>
+constexpr int xz_auto() {
+    if (N % 2 == 0 && N >= (sizeof(T) == 8 ? 24 : 36) && !(sizeof(T) == 8 && N > 45)) return XZ_REG2;
+    return xz_has<T, N>(XZ_REG1) ? XZ_REG1 : XZ_LDS;
+}
+
 template <typename T, int N>
 static bool xz_reg_one(dim3 grid, hipStream_t st, const FftItem* items, const int* idx, typename cx<T>::t* Tb,
-                       const double* V, const int* act) {
-    if constexpr (sizeof(T) == 8 && N > 45) {
-        return false;
-    } else if constexpr (N % 2 == 0 && N >= (sizeof(T) == 8 ? 24 : 36)) {
-        xz_reg2_one<T, N>(grid, st, items, idx, Tb, V, act);
-        return true;
-    } else {
-        hipLaunchKernelGGL((k_xz_reg<T, N>), grid, dim3(256), 0, st, items, idx, Tb, V, act);
+                       const double* V, const int* act, int variant) {
+    const int v = variant == XZ_AUTO ? xz_auto<T, N>() : variant;
+    if (v == XZ_REG2 && xz_has<T, N>(XZ_REG2)) {
+        if constexpr (N % 2 == 0) xz_reg2_one<T, N>(grid, st, items, idx, Tb, V, act);
         return true;
     }
+    if (v == XZ_REG1 && xz_has<T, N>(XZ_REG1)) {
+        if constexpr (!(sizeof(T) == 8 && N > 45))
+            hipLaunchKernelGGL((k_xz_reg<T, N>), grid, dim3(256), 0, st, items, idx, Tb, V, act);
+        return true;
+    }
+    return false;
 }
 
 // Launch the register x pass for one S0 group; false if S0 is not compiled in
 // for this precision (the caller then uses the LDS pass).
 template <typename T>
 static bool xz_reg_launch(int S0, dim3 grid, hipStream_t st, const FftItem* items, const int* idx,
-                          typename cx<T>::t* Tb, const double* V, const int* act) {
+                          typename cx<T>::t* Tb, const double* V, const int* act, int variant) {
     switch (S0) {
 #define DPP_XZ_REG(n) \
     case n:           \
-        return xz_reg_one<T, n>(grid, st, items, idx, Tb, V, act);
+        return xz_reg_one<T, n>(grid, st, items, idx, Tb, V, act, variant);
         DPP_XZ_REG(12) DPP_XZ_REG(15) DPP_XZ_REG(16) DPP_XZ_REG(18) DPP_XZ_REG(20) DPP_XZ_REG(24)
         DPP_XZ_REG(25) DPP_XZ_REG(27) DPP_XZ_REG(30) DPP_XZ_REG(32) DPP_XZ_REG(36) DPP_XZ_REG(40)
         DPP_XZ_REG(45) DPP_XZ_REG(48) DPP_XZ_REG(50) DPP_XZ_REG(54) DPP_XZ_REG(60) DPP_XZ_REG(64)
 #undef DPP_XZ_REG
         default:
             return false;
+    }
+}
+
+template <typename T>
+static bool xz_available_t(int S0, int v) {
+    switch (S0) {
+#define DPP_XZ_AV(n) \
+    case n:          \
+        return v == XZ_LDS || v == XZ_AUTO || xz_has<T, n>(v);
+        DPP_XZ_AV(12) DPP_XZ_AV(15) DPP_XZ_AV(16) DPP_XZ_AV(18) DPP_XZ_AV(20) DPP_XZ_AV(24)
+        DPP_XZ_AV(25) DPP_XZ_AV(27) DPP_XZ_AV(30) DPP_XZ_AV(32) DPP_XZ_AV(36) DPP_XZ_AV(40)
+        DPP_XZ_AV(45) DPP_XZ_AV(48) DPP_XZ_AV(50) DPP_XZ_AV(54) DPP_XZ_AV(60) DPP_XZ_AV(64)
+#undef DPP_XZ_AV
+        default:
+            return v == XZ_LDS || v == XZ_AUTO;
     }
 }
 
@@ -1035,6 +1067,10 @@ PlanePlan plane_plan_groups(const std::vector<FftItem>& h, std::vector<std::vect
     return p;
 }
 
+bool xz_variant_available(int S0, bool fp64, int v) {
+    return fp64 ? xz_available_t<double>(S0, v) : xz_available_t<float>(S0, v);
+}
+
 XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int>>& members) {
     XzPlan p;
     members.clear();
@@ -1048,6 +1084,8 @@ XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int
             p.maxS1S2.push_back(0);
             p.nbm.push_back(0);
             p.idx.push_back(nullptr);
+            p.var64.push_back(XZ_AUTO);
+            p.var32.push_back(XZ_AUTO);
             members.emplace_back();
         }
         p.count[g]++;
@@ -1089,7 +1127,9 @@ dpp_status apply_H_local_batched(dpp_ctx_s* cx_, const FftItem* d_items, const s
             for (size_t g = 0; g < plan->S0.size(); ++g) {
                 const dim3 grid((unsigned)((plan->maxS1S2[g] + 255) / 256), (unsigned)plan->nbm[g],
                                 (unsigned)plan->count[g]);
-                if (!xz_reg_launch<T>(plan->S0[g], grid, st, d_items, plan->idx[g], Tb, V, act)) {
+                const std::vector<int>& var = fp64 ? plan->var64 : plan->var32;
+                const int v = g < var.size() ? var[g] : XZ_AUTO;
+                if (!xz_reg_launch<T>(plan->S0[g], grid, st, d_items, plan->idx[g], Tb, V, act, v)) {
                     DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz<T, XZ_H, double2, NT_, true>;
                                     DPP_TRY(set_lds(k, bs.xz.lds));
                                     hipLaunchKernelGGL(k, dim3(bs.maxS1, plan->nbm[g], plan->count[g]), dim3(NT_),

@@ -189,10 +189,16 @@ size_t grid_coef_offset(const dpp_grid_s* g);
 // Items of a table grouped by x length S0 (the register x pass is compiled
 // per S0): group g holds count[g] items listed in the device array idx[g]
 // (nullptr when the group is the whole table in order).
+// var64[g] / var32[g]: the x-pass variant of the group in FP64 / FP32
+// (XZ_AUTO, XZ_REG1, XZ_REG2, XZ_LDS), set by the launch tuner.
+enum XzVariant { XZ_AUTO = 0, XZ_REG1 = 1, XZ_REG2 = 2, XZ_LDS = 3 };
 struct XzPlan {
     std::vector<int> S0, count, maxS1S2, nbm;
     std::vector<const int*> idx;
+    std::vector<int> var64, var32;
 };
+// Whether variant v of the x pass exists for length S0 in this precision.
+bool xz_variant_available(int S0, bool fp64, int v);
 XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int>>& members);
 
 // Items grouped for the plane passes: group g with N[g] > 0 holds items with
@@ -283,10 +289,13 @@ RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, 
                       double beta, double2* out, int64_t ldout);
 // Batched contractions over a device task table; `act` (nullable) masks
 // tasks by their work item: tasks of inactive items do nothing.
+// Launch choices (set by the tuner): ov_narrow = 1 runs every overlap task as
+// single 16x16 tiles per wave; rot_pt = 1, 2 or 4 fixes the point tiles per
+// rotate wave for outputs of up to 32 bands (0: by the launch size).
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
-                         const int* act = nullptr);
+                         const int* act = nullptr, int ov_narrow = 0);
 dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks,
-                        const int* act = nullptr);
+                        const int* act = nullptr, int rot_pt = 0);
 dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
                        const double2* B, int64_t ldB, double scale, double2* U, void* ws,
                        size_t ws_bytes);

@@ -124,6 +124,8 @@ SIGNATURES = {
     "dpp_set_precision_policy": [_vp, _i, _d],
     "dpp_scf_status": [_vp, _dp, _ip, _ip],
     "dpp_system_apply_H": [_vp, _vp, _vp],
+    "dpp_system_tune": [_vp, _vp, _vp, _i],
+    "dpp_system_tune_report": [_vp, C.c_char_p, C.c_size_t],
     "dpp_net_create": [_vp, _ip, _i, C.POINTER(_vp)],
     "dpp_net_destroy": [_vp],
     "dpp_net_num_params": [_vp, _ip],
@@ -436,6 +438,16 @@ def dpp_system_cells(sys_):
 
 def dpp_set_graph_mode(sys_, on=True):
     _call("dpp_set_graph_mode", sys_, 1 if on else 0)
+
+
+def dpp_system_tune(sys_, Y, HY, reps=5):
+    _call("dpp_system_tune", sys_, _ptr(Y), _ptr(HY), int(reps))
+
+
+def dpp_system_tune_report(sys_) -> str:
+    buf = C.create_string_buffer(4096)
+    _call("dpp_system_tune_report", sys_, buf, C.c_size_t(4096))
+    return buf.value.decode()
 
 
 def dpp_scf_cell_residuals(sys_):

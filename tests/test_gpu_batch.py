@@ -136,3 +136,38 @@ def test_config4_batch_fp32_graph(dev):
         dev.D.dpp_system_destroy(s1)
         log(f"cell {ci}: batch {E[-1, ci]:.12f} single {E1[-1, 0]:.12f}")
         assert np.max(np.abs(E1[:, 0] - E[:, ci])) / c.nat < 1e-9
+
+
+def test_tuner_keeps_results(dev):
+    """The launch autotuner times the x-pass, rotate and overlap variants on
+    the system's items; H Y and the SCF trajectory after tuning agree with an
+    untuned system to rounding."""
+    D = dev.D
+    cells = _mixed_cells()
+    sa, Ya, _ = _batch(dev, cells)
+    sb, Yb, _ = _batch(dev, cells)
+    Ea, _ = _run(dev, sa, Ya, cells, 1)
+    Eb, _ = _run(dev, sb, Yb, cells, 1)
+    HYa = dev.torch.empty_like(Ya)
+    HYb = dev.torch.empty_like(Yb)
+    D.dpp_system_apply_H(sa, Ya, HYa)
+    D.dpp_system_tune(sb, Yb, HYb, reps=2)
+    rep = D.dpp_system_tune_report(sb)
+    log("tuning: " + rep)
+    assert "x pass" in rep and "overlap blocks" in rep and "->" in rep
+    D.dpp_system_apply_H(sb, Yb, HYb)
+    a, b = dev.host(HYa), dev.host(HYb)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+    # two more SCF iterations on each (tuning dropped the band-CG state only)
+    Ea2, Eb2 = [], []
+    for _ in range(2):
+        ea, _ = D.dpp_scf_iteration(sa, Ya)
+        eb, _ = D.dpp_scf_iteration(sb, Yb)
+        Ea2.append([x["E_el"] for x in ea])
+        Eb2.append([x["E_el"] for x in eb])
+    nat = np.array([c.nat for c in cells])
+    err = np.max(np.abs(np.array(Ea2) - np.array(Eb2)) / nat)
+    log(f"SCF after tuning: max difference {err:.2e} Ha/atom")
+    assert err < 1e-10
+    D.dpp_system_destroy(sa)
+    D.dpp_system_destroy(sb)
