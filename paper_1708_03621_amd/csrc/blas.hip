@@ -533,7 +533,7 @@ template <typename Load>
 __device__ int chol_inverse_packed(int n, Load load, double2* __restrict__ A) {
     __shared__ int fail;
     __shared__ double umax;
-    __shared__ double red[256];
+    __shared__ double red[SM_NT];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int r = e / n, c = e - r * n;
         if (c >= r) A[up_idx(n, r, c)] = load(r, c);
@@ -622,7 +622,7 @@ __device__ void chol_store(int n, int failed, const double2* __restrict__ A, dou
 }
 
 // Matrices at stride n^2 (one workgroup each).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(SM_NT)
 k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ Rinv,
                    int* __restrict__ status) {
     extern __shared__ char smem_raw[];
@@ -635,7 +635,7 @@ k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ R
 
 // Per work item: the item's n x n matrix at moff (n = nbo if > 0, else the
 // item's band count); items with act[item] == 0 are skipped.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(SM_NT)
 k_cholesky_seg(const Seg* __restrict__ seg, int nbo, const double2* __restrict__ U, double2* __restrict__ Rinv,
                int* __restrict__ status, const int* __restrict__ act) {
     if (act && !act[blockIdx.x]) return;
@@ -802,7 +802,7 @@ __device__ double trial_energy(const Seg& sg, double a, const double2* __restric
                                const double2* __restrict__ Xs, const double2* __restrict__ Q,
                                const double2* __restrict__ H0, const double2* __restrict__ Ps,
                                const double2* __restrict__ H2, double2* __restrict__ A, double2* __restrict__ Hs) {
-    __shared__ double red[256];
+    __shared__ double red[SM_NT];
     const int n = sg.nb;
     const int64_t o = sg.moff;
     // Xs = X + X^dag and Ps = H1 + H1^dag (prepared by the caller)
@@ -845,7 +845,7 @@ __device__ double trial_energy(const Seg& sg, double a, const double2* __restric
     return E;
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(SM_NT)
 k_linesearch_B(const Seg* __restrict__ seg, const double2* __restrict__ U, const double2* __restrict__ X,
                const double2* __restrict__ Q, const double2* __restrict__ H0, const double2* __restrict__ H1,
                const double2* __restrict__ H2, const double* __restrict__ E0v, const double* __restrict__ at0,
@@ -1042,6 +1042,9 @@ bool linesearch_wave_launch(hipStream_t st, unsigned nblk, int n, const Seg* seg
 constexpr int EIG_MAXN = 128;
 constexpr int EIG_SWEEPS = 40;
 
+// Squared relative off-diagonal norm at which the sweeps stop.
+__device__ __forceinline__ double eig_stop2(int n) { return fmax(1e-28, 4e-32 * (double)n * (double)n); }
+
 struct Rot {
     int p, q;
     double cs, sn, er, ei;  // e^{-i phi} = er + i ei
@@ -1079,7 +1082,7 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
     double2* A = lds;
     double2* Vt = n <= 64 ? lds + n * (n + 1) / 2 : scr;
     __shared__ Rot rot[EIG_MAXN / 2];
-    __shared__ double red[256];
+    __shared__ double red[SM_NT];
     __shared__ double dg[EIG_MAXN];
     __shared__ int perm[EIG_MAXN];
     __shared__ int done;
@@ -1120,10 +1123,11 @@ __device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double*
             __syncthreads();
         }
         const double diat = red[0];
-        // converged once the off-diagonal part is 1e-14 of the Frobenius norm
-        // (the rounding noise of the rotations sits near 1e-16 n^(1/2))
+        // converged once the off-diagonal part is 1e-14 of the Frobenius norm,
+        // or (large n) once it is within twice the level below which pairs
+        // are skipped: n(n-1) entries of at most 1e-16 |A|_F each
         const double fro2 = offt + diat;
-        if (threadIdx.x == 0) done = (offt <= 1e-28 * fmax(fro2, 1e-300)) || offt == 0.0;
+        if (threadIdx.x == 0) done = (offt <= eig_stop2(n) * fmax(fro2, 1e-300)) || offt == 0.0;
         __syncthreads();
         if (done) break;
         // pairs below the rounding level of the matrix are not rotated
@@ -1286,7 +1290,7 @@ __device__ void jacobi_eigh_wave(int n, const double2* __restrict__ Hg, double* 
         dia = wave_sum(dia);
         const double fro2 = off + dia;
         // converged once the off-diagonal part is 1e-14 of the Frobenius norm
-        if (off <= 1e-28 * fmax(fro2, 1e-300) || off == 0.0) break;
+        if (off <= eig_stop2(n) * fmax(fro2, 1e-300) || off == 0.0) break;
         const double skip2 = 1e-32 * fro2;  // (1e-16 |A|_F)^2: pairs at rounding level are not rotated
         for (int round = 0; round < m - 1; ++round) {
             if (lane < P) {
@@ -1416,7 +1420,7 @@ k_jacobi_eigh_seg_wave(const Seg* __restrict__ seg, const double2* __restrict__ 
     jacobi_eigh_wave(sg.nb, H + sg.moff, eig + sg.f_off, vecs + sg.moff);
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(SM_NT)
 k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, double2* __restrict__ vecs,
               double2* __restrict__ scratch) {
     extern __shared__ char smem_raw[];
@@ -1426,7 +1430,7 @@ k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, do
 }
 
 // Per work item: matrix at moff, eigenvalues at f_off, V scratch (n > 64) at moff.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(SM_NT)
 k_jacobi_eigh_seg(const Seg* __restrict__ seg, const double2* __restrict__ H, double* __restrict__ eig,
                   double2* __restrict__ vecs, double2* __restrict__ scratch) {
     extern __shared__ char smem_raw[];
@@ -1477,7 +1481,7 @@ extern "C" dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const
     TimerScope ts_(ctx, DPP_TK_CHOLESKY);
     if (!cholesky_wave_launch(ctx->stream, (unsigned)batch, nb, (int64_t)nb * nb, nullptr, 0, (const double2*)U,
                               (double2*)Rinv, ctx->d_status, nullptr)) {
-        const int nt = nb <= 64 ? 64 : 256;  // the in-place inverse needs one thread per row
+        const int nt = nb <= 64 ? 64 : SM_NT;  // the in-place inverse needs one thread per row
         hipLaunchKernelGGL(k_cholesky_inverse, dim3(batch), dim3(nt), lds, ctx->stream, nb, (const double2*)U,
                            (double2*)Rinv, ctx->d_status);
     }
@@ -1509,7 +1513,8 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
         hipLaunchKernelGGL(k_jacobi_eigh_wave, dim3(batch), dim3(64), 0, ctx->stream, nb, (const double2*)H, eig,
                            (double2*)vecs);
     else
-        hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(256), lds, ctx->stream, nb, (const double2*)H, eig,
+        hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(nb > 64 ? SM_NT : 256), lds, ctx->stream, nb,
+                           (const double2*)H, eig,
                            (double2*)vecs, nb <= 64 ? (double2*)nullptr : (double2*)ws);
     DPP_LAUNCHED();
     return DPP_OK;

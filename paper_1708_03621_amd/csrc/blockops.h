@@ -86,6 +86,7 @@ __global__ void k_cholesky_seg(const Seg* seg, int nbo, const double2* U, double
                                const int* act);
 __global__ void k_jacobi_eigh_seg(const Seg* seg, const double2* H, double* eig, double2* vecs, double2* scratch);
 constexpr int EIGW_MAXN = 32;  // largest matrix of the single-wave eigensolver
+constexpr int SM_NT = 1024;    // workgroup size of the LDS small-matrix kernels for n > 64
 // Single-wave Cholesky inverse and line search for n <= 32 (false: n larger).
 bool cholesky_wave_launch(hipStream_t st, unsigned nblk, int n, int64_t stride, const Seg* seg, int nbo,
                           const double2* U, double2* Rinv, int* status, const int* act);

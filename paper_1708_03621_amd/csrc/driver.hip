@@ -484,7 +484,7 @@ dpp_status chol_all(dpp_system_s* s, int nbo, const double2* Um, double2* Ri) {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(s->ctx, DPP_TK_CHOLESKY);
     if (!cholesky_wave_launch(stream(s), (unsigned)s->nit, n, 0, s->d_seg, nbo, Um, Ri, s->ctx->d_status, nullptr))
-        hipLaunchKernelGGL(k_cholesky_seg, dim3(s->nit), dim3(n <= 64 ? 64 : 256), lds, stream(s), s->d_seg, nbo, Um,
+        hipLaunchKernelGGL(k_cholesky_seg, dim3(s->nit), dim3(n <= 64 ? 64 : SM_NT), lds, stream(s), s->d_seg, nbo, Um,
                            Ri, s->ctx->d_status, (const int*)nullptr);
     DPP_LAUNCHED();
     return DPP_OK;
@@ -605,7 +605,7 @@ dpp_status linesearch_B(dpp_system_s* s, const int* act, const double* d0, int* 
     TimerScope ts_(s->ctx, DPP_TK_LINESEARCH);
     if (!linesearch_wave_launch(stream(s), (unsigned)s->nit, n, s->d_seg, s->U, s->X, s->Q, s->H0, s->H1, s->H2,
                                 s->d_bE0, s->cg.at, d0, act, ok, step, s->M1, s->M2))
-        hipLaunchKernelGGL(k_linesearch_B, dim3(s->nit), dim3(n <= 64 ? 64 : 256), lds, stream(s), s->d_seg,
+        hipLaunchKernelGGL(k_linesearch_B, dim3(s->nit), dim3(n <= 64 ? 64 : SM_NT), lds, stream(s), s->d_seg,
                            (const double2*)s->U, (const double2*)s->X, (const double2*)s->Q, (const double2*)s->H0,
                            (const double2*)s->H1, (const double2*)s->H2, (const double*)s->d_bE0,
                            (const double*)s->cg.at, d0, act, ok, step, stage, s->M1, s->M2);
@@ -679,7 +679,7 @@ dpp_status subspace_rotate(dpp_system_s* s, double2* Y) {
             hipLaunchKernelGGL(k_jacobi_eigh_seg_wave, dim3(s->nit), dim3(64), 0, stream(s), s->d_seg,
                                (const double2*)s->H0, s->d_eig, s->vecs);
         else
-            hipLaunchKernelGGL(k_jacobi_eigh_seg, dim3(s->nit), dim3(256), lds, stream(s), s->d_seg,
+            hipLaunchKernelGGL(k_jacobi_eigh_seg, dim3(s->nit), dim3(n > 64 ? SM_NT : 256), lds, stream(s), s->d_seg,
                                (const double2*)s->H0, s->d_eig, s->vecs, s->eig_scr);
         DPP_LAUNCHED();
     }
