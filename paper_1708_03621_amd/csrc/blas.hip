@@ -994,6 +994,114 @@ k_linesearch_wave(const Seg* __restrict__ seg, const double2* __restrict__ U, co
     }
 }
 
+// Band-gradient preparation of one item in one wave (n <= NMAX):
+//   R^dag R = U,  Rinv = R^{-1},  M1 = Rinv Rinv^dag = U^{-1},
+//   M2 = -Omega (M1 H0) M1,  E0 = Re Tr(M1 H0),
+// the five small steps of the gradient at the current point in one launch.
+// On a failed factorization Rinv, M1 and M2 are NaN, E0 is NaN and the
+// status word latches DPP_STATUS_NOTPD.
+template <int NMAX>
+__global__ void __launch_bounds__(64)
+k_grad_prep_wave(const Seg* __restrict__ seg, const double2* __restrict__ U, const double2* __restrict__ H0,
+                 double2* __restrict__ Rinv, double2* __restrict__ M1, double2* __restrict__ M2,
+                 double* __restrict__ E0, int* __restrict__ status) {
+    constexpr int PER = (NMAX * NMAX + 63) / 64;
+    __shared__ CholWaveLds<NMAX> L;
+    __shared__ double2 Hs[NMAX][NMAX + 1];
+    const Seg sg = seg[blockIdx.x];
+    const int n = sg.nb;
+    const int64_t o = sg.moff;
+    const int lane = threadIdx.x;
+    for (int e = lane; e < n * n; e += 64) Hs[e / n][e % n] = H0[o + e];
+    // (the staging is ordered before its use by the barriers of the factorization)
+    const int f = chol_inv_wave<NMAX>(n, [&](int r, int c) { return U[o + r * n + c]; }, L);
+    if (f) {
+        if (lane == 0) {
+            if (status) atomicOr(status, DPP_STATUS_NOTPD);
+            E0[blockIdx.x] = NAN;
+        }
+        for (int e = lane; e < n * n; e += 64) {
+            Rinv[o + e] = double2{NAN, NAN};
+            M1[o + e] = double2{NAN, NAN};
+            M2[o + e] = double2{NAN, NAN};
+        }
+        return;
+    }
+    // M1 = X X^dag (X = Rinv upper triangular): entries into L.R (R is dead)
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = lane + 64 * u;
+        if (e < n * n) {
+            const int i = e / n, j = e - (e / n) * n;
+            Rinv[o + e] = L.X[i][j];
+            double sr = 0.0, si = 0.0;
+            for (int k = max(i, j); k < n; ++k) {
+                const double2 a = L.X[i][k], b = L.X[j][k];
+                sr += a.x * b.x + a.y * b.y;  // a conj(b)
+                si += a.y * b.x - a.x * b.y;
+            }
+            L.R[i][j] = double2{sr, si};
+            M1[o + e] = double2{sr, si};
+        }
+    }
+    __syncthreads();
+    // Rt = M1 H0 into L.X (X is dead once every lane passed the barrier)
+    double2 rt[PER];
+    double tr = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = lane + 64 * u;
+        rt[u] = double2{0.0, 0.0};
+        if (e < n * n) {
+            const int i = e / n, j = e - (e / n) * n;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const double2 a = L.R[i][k], b = Hs[k][j];
+                sr += a.x * b.x - a.y * b.y;
+                si += a.x * b.y + a.y * b.x;
+            }
+            rt[u] = double2{sr, si};
+            if (i == j) tr += sr;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = lane + 64 * u;
+        if (e < n * n) L.X[e / n][e % n] = rt[u];
+    }
+    tr = wave_sum64(tr);
+    if (lane == 0) E0[blockIdx.x] = tr;
+    __syncthreads();
+    // M2 = -Omega Rt M1
+    const double sc = -sg.omega;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = lane + 64 * u;
+        if (e < n * n) {
+            const int i = e / n, j = e - (e / n) * n;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const double2 a = L.X[i][k], b = L.R[k][j];
+                sr += a.x * b.x - a.y * b.y;
+                si += a.x * b.y + a.y * b.x;
+            }
+            M2[o + e] = double2{sc * sr, sc * si};
+        }
+    }
+}
+
+bool grad_prep_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, const double2* U,
+                           const double2* H0, double2* Rinv, double2* M1, double2* M2, double* E0, int* status) {
+    if (nmax <= 16)
+        hipLaunchKernelGGL(k_grad_prep_wave<16>, dim3(nblk), dim3(64), 0, st, seg, U, H0, Rinv, M1, M2, E0, status);
+    else if (nmax <= 32)
+        hipLaunchKernelGGL(k_grad_prep_wave<32>, dim3(nblk), dim3(64), 0, st, seg, U, H0, Rinv, M1, M2, E0, status);
+    else
+        return false;
+    return true;
+}
+
 // Launch helpers for the single-wave paths (n <= 32); false: use the
 // general kernels.
 bool cholesky_wave_launch(hipStream_t st, unsigned nblk, int n, int64_t stride, const Seg* seg, int nbo,

@@ -571,17 +571,28 @@ dpp_status pulay_mix(dpp_system_s* s) {
 // g = (HY - O Y U^{-1} H0) U^{-1}, E0_k = Tr(U^{-1} H0) (device); requires HY.
 dpp_status grad_B(dpp_system_s* s, const double2* Y) {
     DPP_TRY(overlap_jobs(s, 0, {OvJob{Y, Y, 1.0, true, s->U}, OvJob{Y, s->HY, 1.0, false, s->H0}}));
-    DPP_TRY(chol_all(s, 0, s->U, s->Rinv));
-    // Uinv = Rinv Rinv^dag (M1); M2 = -Omega Uinv H0 Uinv
-    DPP_TRY(smm(s, 0, 0, 1, 1.0, 0, s->Rinv, s->Rinv, 0.0, s->M1));
-    DPP_TRY(smm(s, 0, 0, 0, 1.0, 0, s->M1, s->H0, 0.0, s->Rt));
-    DPP_TRY(smm(s, 0, 0, 0, -1.0, 1, s->Rt, s->M1, 0.0, s->M2));
+    bool fused = false;
+    {
+        // up to 32 bands: factor, U^{-1}, M2 and E0 in one single-wave launch
+        TimerScope ts_(s->ctx, DPP_TK_CHOLESKY);
+        fused = grad_prep_wave_launch(stream(s), (unsigned)s->nit, s->maxnb, s->d_seg, s->U, s->H0, s->Rinv, s->M1,
+                                      s->M2, s->d_bE0, s->ctx->d_status);
+        if (fused) DPP_LAUNCHED();
+    }
+    if (!fused) {
+        DPP_TRY(chol_all(s, 0, s->U, s->Rinv));
+        // Uinv = Rinv Rinv^dag (M1); M2 = -Omega Uinv H0 Uinv
+        DPP_TRY(smm(s, 0, 0, 1, 1.0, 0, s->Rinv, s->Rinv, 0.0, s->M1));
+        DPP_TRY(smm(s, 0, 0, 0, 1.0, 0, s->M1, s->H0, 0.0, s->Rt));
+        DPP_TRY(smm(s, 0, 0, 0, -1.0, 1, s->Rt, s->M1, 0.0, s->M2));
+        // E0 = Tr(Uinv H0) = Re Tr(Rt)
+        TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
+        hipLaunchKernelGGL(k_trace_diag, dim3(s->nit), dim3(64), 0, stream(s), s->d_seg, (const double2*)s->Rt,
+                           s->d_bE0);
+        DPP_LAUNCHED();
+    }
     // g = HY Uinv + Y M2 in one pass
     DPP_TRY(rotate_jobs(s, 0, {RotJob{s->HY, s->M1, 0.0, s->g, Y, s->M2}}));
-    // E0 = Tr(Uinv H0) = Re Tr(Rt)
-    TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
-    hipLaunchKernelGGL(k_trace_diag, dim3(s->nit), dim3(64), 0, stream(s), s->d_seg, (const double2*)s->Rt, s->d_bE0);
-    DPP_LAUNCHED();
     return DPP_OK;
 }
 
