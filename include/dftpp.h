@@ -358,6 +358,16 @@ dpp_status dpp_system_apply_H(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY);
  * graphs are dropped.  Results of every variant agree to rounding.  Errors:
  * DPP_EINVAL for bad arguments or a capturing stream. */
 dpp_status dpp_system_tune(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY, int reps);
+/* Sets one launch choice by hand (what dpp_system_tune would choose), for
+ * tests and experiments: DPP_CHOICE_OVERLAP (0: 2x2 tile blocks over
+ * 256-point chunks plus a reduction launch, 1: single tiles, 2: one
+ * workgroup per task over all points), DPP_CHOICE_ROTATE_PT (0 = by launch
+ * size, 1, 2 or 4 point tiles per wave), DPP_CHOICE_XPASS (0 auto, 1 one
+ * thread per column, 2 lane pair per column, 3 LDS; for every x length,
+ * lengths without the variant use the LDS pass).  Drops captured graphs.
+ * Errors: DPP_EINVAL for an unknown choice or value. */
+enum { DPP_CHOICE_OVERLAP = 0, DPP_CHOICE_ROTATE_PT = 1, DPP_CHOICE_XPASS = 2 };
+dpp_status dpp_system_set_launch_choice(dpp_system sys, int which, int value);
 /* Text report of the last dpp_system_tune: the timed candidates (us per
  * call) and the choices; buf (host, len bytes) receives a NUL-terminated
  * string, truncated to fit. */

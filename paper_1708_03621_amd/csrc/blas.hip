@@ -43,10 +43,10 @@ __device__ __forceinline__ double2 gld(const double2* p) {
 // the range get A = 0 when used, so the next step's loads stay in flight
 // during the MFMAs.  Rows past the band counts are computed from finite data
 // and never stored.
-template <int TA, int TB>
+template <int TA, int TB, int NW, bool FULL>
 __device__ __forceinline__ void ov_block(const OvTask& T, double2* __restrict__ part,
                                          double (*red)[2][4][64]) {
-    const int chunk = blockIdx.x;
+    const int chunk = FULL ? 0 : (int)blockIdx.x;
     const int tilesA = (T.nbA + 15) / 16;
     const int sB = (T.tilesB + TB - 1) / TB, sA = (tilesA + TA - 1) / TA;
     if ((int)blockIdx.y >= sA * sB) return;
@@ -67,7 +67,8 @@ __device__ __forceinline__ void ov_block(const OvTask& T, double2* __restrict__ 
             cre[a][b] = d4{0, 0, 0, 0};
             cim[a][b] = d4{0, 0, 0, 0};
         }
-    const int sub = OV_CHUNK / OV_WAVES;
+    // chunked: OV_CHUNK points per workgroup; FULL: all points, NW slices
+    const int sub = FULL ? ((T.npw + NW * 16 - 1) / (NW * 16)) * 16 : OV_CHUNK / NW;
     const int ga = chunk * OV_CHUNK + w * sub, ge = min(T.npw, ga + sub);
     const int nst = ge > ga ? (ge - ga + 15) / 16 : 0;
     // lane covers points g + 4 ks + s, s = 0..3, of the step at g
@@ -124,12 +125,19 @@ __device__ __forceinline__ void ov_block(const OvTask& T, double2* __restrict__ 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     double sr = 0, si = 0;
-                    for (int u = 0; u < OV_WAVES; ++u) {
+                    for (int u = 0; u < NW; ++u) {
                         sr += red[u][0][v][lane];
                         si += red[u][1][v][lane];
                     }
                     const int i = 4 * v + (lane >> 4), j = lane & 15;
-                    dst[i * 16 + j] = double2{sr, si};
+                    if (FULL) {
+                        // one workgroup covered every point: the scaled result
+                        const int gi = (ti0 + a) * 16 + i, gj = (tj0 + b) * 16 + j;
+                        if (gi < T.nbA && gj < T.nbB)
+                            T.out[(int64_t)gi * T.out_ld + gj] = double2{T.scale * sr, T.scale * si};
+                    } else {
+                        dst[i * 16 + j] = double2{sr, si};
+                    }
                 }
             }
             __syncthreads();
@@ -145,26 +153,31 @@ __host__ __device__ constexpr int ov_blocks(int tA, int tB) {
     return ((tA + TA - 1) / TA) * ((tB + TB - 1) / TB);
 }
 
-template <bool WIDE>
-__global__ void __launch_bounds__(64 * OV_WAVES)
+// FULL: one workgroup of OVF_WAVES waves per (task, tile block) covers all
+// points and writes the scaled result (no partials, no reduction launch).
+constexpr int OVF_WAVES = 8;
+
+template <bool WIDE, bool FULL>
+__global__ void __launch_bounds__(64 * (FULL ? OVF_WAVES : OV_WAVES))
 k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part,
                const int* __restrict__ act) {
-    __shared__ double red[OV_WAVES][2][4][64];
+    constexpr int NW = FULL ? OVF_WAVES : OV_WAVES;
+    __shared__ double red[NW][2][4][64];
     const OvTask T = tasks ? tasks[blockIdx.z] : single;
     if (act && !act[T.item]) return;
-    if ((int)blockIdx.x >= T.nchunk) return;
+    if (!FULL && (int)blockIdx.x >= T.nchunk) return;
     if constexpr (WIDE) {
         const int tA = (T.nbA + 15) / 16, tB = T.tilesB;
         if (tA >= 2 && tB >= 2)
-            ov_block<2, 2>(T, part, red);
+            ov_block<2, 2, NW, FULL>(T, part, red);
         else if (tB >= 2)
-            ov_block<1, 2>(T, part, red);
+            ov_block<1, 2, NW, FULL>(T, part, red);
         else if (tA >= 2)
-            ov_block<2, 1>(T, part, red);
+            ov_block<2, 1, NW, FULL>(T, part, red);
         else
-            ov_block<1, 1>(T, part, red);
+            ov_block<1, 1, NW, FULL>(T, part, red);
     } else {
-        ov_block<1, 1>(T, part, red);
+        ov_block<1, 1, NW, FULL>(T, part, red);
     }
 }
 
@@ -179,13 +192,22 @@ static int ov_task_blocks(int tA, int tB) {
 // nblk: the largest ov_task_blocks over the tasks; wide: some task has more
 // than one tile.
 static void overlap_launch(dpp_ctx ctx, const OvTask* d_tasks, const OvTask& single, unsigned ntasks, int nchunk,
-                           int nblk, bool wide, double2* part, const int* act) {
+                           int nblk, bool wide, double2* part, const int* act, bool full = false) {
+    if (full) {
+        if (wide)
+            hipLaunchKernelGGL((k_overlap_mfma<true, true>), dim3(1, nblk, ntasks), dim3(64 * OVF_WAVES), 0,
+                               ctx->stream, d_tasks, single, part, act);
+        else
+            hipLaunchKernelGGL((k_overlap_mfma<false, true>), dim3(1, nblk, ntasks), dim3(64 * OVF_WAVES), 0,
+                               ctx->stream, d_tasks, single, part, act);
+        return;
+    }
     if (wide)
-        hipLaunchKernelGGL(k_overlap_mfma<true>, dim3(nchunk, nblk, ntasks), dim3(64 * OV_WAVES), 0, ctx->stream,
-                           d_tasks, single, part, act);
+        hipLaunchKernelGGL((k_overlap_mfma<true, false>), dim3(nchunk, nblk, ntasks), dim3(64 * OV_WAVES), 0,
+                           ctx->stream, d_tasks, single, part, act);
     else
-        hipLaunchKernelGGL(k_overlap_mfma<false>, dim3(nchunk, nblk, ntasks), dim3(64 * OV_WAVES), 0, ctx->stream,
-                           d_tasks, single, part, act);
+        hipLaunchKernelGGL((k_overlap_mfma<false, false>), dim3(nchunk, nblk, ntasks), dim3(64 * OV_WAVES), 0,
+                           ctx->stream, d_tasks, single, part, act);
 }
 
 __global__ void k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part,
@@ -258,7 +280,9 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
 // Batched: the caller has set part_off of every task (disjoint partial areas)
 // and copied the table to d_tasks.
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
-                         const int* act, int ov_narrow) {
+                         const int* act, int ov_mode) {
+    const int ov_narrow = ov_mode == 1;
+    const bool full = ov_mode == 2;
     if (h.empty()) return DPP_OK;
     int mc = 1, mt = 1, mblk = 1;
     double by = 0, fl = 0;
@@ -272,9 +296,10 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
     if (mt > 65535 || h.size() > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: batch too large");
     {
         TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_OVERLAP, act ? 0.0 : by, act ? 0.0 : fl);
-        overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act);
+        overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act, full);
         DPP_LAUNCHED();
     }
+    if (full) return DPP_OK;
     TimerScope ts2_(ctx, act ? DPP_TK_MASKED : DPP_TK_BLOCKOPS);
     hipLaunchKernelGGL(k_overlap_reduce, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
                        ctx->stream, d_tasks, OvTask{}, (const double2*)part, act);

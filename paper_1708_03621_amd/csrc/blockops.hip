@@ -313,71 +313,92 @@ __global__ void __launch_bounds__(256)
 k_pulay_solve_cells(int ncells, const int* __restrict__ st, const CellDesc* __restrict__ cells,
                     const double* __restrict__ part, double* __restrict__ A, double* __restrict__ coef,
                     int* __restrict__ status) {
-    __shared__ double red[256];
     __shared__ double ov[PULAY_MAX];
+    __shared__ double M[PULAY_MAX + 1][PULAY_MAX + 2];
+    __shared__ int piv_s;
     const int cidx = blockIdx.x;
     const int m = st[0], head = st[1], slot = st[2];
-    // fixed-order tree sums of the MDOT_BLOCKS partials of each overlap
-    for (int i = 0; i < m; ++i) {
+    const int tid = threadIdx.x;
+    // overlap i: 32 lanes (one half wave) sum its MDOT_BLOCKS partials in a
+    // fixed order (strided lane sums, then a butterfly within the 32 lanes)
+    {
+        const int g = tid >> 5, l = tid & 31;
         double v = 0.0;
-        for (int b = threadIdx.x; b < MDOT_BLOCKS; b += 256) v += part[((int64_t)cidx * PULAY_MAX + i) * MDOT_BLOCKS + b];
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) ov[i] = red[0];
-        __syncthreads();
+        if (g < m)
+            for (int b = l; b < MDOT_BLOCKS; b += 32) v += part[((int64_t)cidx * PULAY_MAX + g) * MDOT_BLOCKS + b];
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (g < m && l == 0) ov[g] = v;
     }
-    __shared__ double M[PULAY_MAX + 1][PULAY_MAX + 2];
-    __shared__ double x[PULAY_MAX + 1];
-    if (threadIdx.x != 0) return;
+    __syncthreads();
     const double dV = cells[cidx].dV;
     double* Ac = A + (int64_t)cidx * PULAY_MAX * PULAY_MAX;
     double* c = coef + (int64_t)cidx * PULAY_MAX;
-    for (int i = 0; i < m; ++i) {
-        const int si = (head + i) % PULAY_MAX;
-        Ac[slot * PULAY_MAX + si] = dV * ov[i];
-        Ac[si * PULAY_MAX + slot] = dV * ov[i];
+    if (tid < m) {
+        const int si = (head + tid) % PULAY_MAX;
+        Ac[slot * PULAY_MAX + si] = dV * ov[tid];
+        Ac[si * PULAY_MAX + slot] = dV * ov[tid];
     }
     if (m == 1) {
-        c[0] = 1.0;
+        if (tid == 0) c[0] = 1.0;
         return;
     }
+    // bordered system [[A, 1], [1^T, 0]] [c; lambda] = [0; 1], Gaussian
+    // elimination with partial pivoting: one thread per row
     const int n = m + 1;
-    for (int i = 0; i < n; ++i) {
-        for (int j = 0; j < n; ++j)
-            M[i][j] = (i < m && j < m) ? Ac[((head + i) % PULAY_MAX) * PULAY_MAX + (head + j) % PULAY_MAX]
-                                       : ((i == m) != (j == m) ? 1.0 : 0.0);
-        M[i][n] = (i == m) ? 1.0 : 0.0;
+    if (tid < n * (n + 1)) {
+        const int i = tid / (n + 1), j = tid - i * (n + 1);
+        double v;
+        if (j == n)
+            v = (i == m) ? 1.0 : 0.0;
+        else if (i < m && j < m) {
+            // the newest row and column from this launch's overlaps, the rest
+            // from the stored history
+            const int si = (head + i) % PULAY_MAX, sj = (head + j) % PULAY_MAX;
+            v = si == slot ? dV * ov[j] : (sj == slot ? dV * ov[i] : Ac[si * PULAY_MAX + sj]);
+        }
+        else
+            v = ((i == m) != (j == m)) ? 1.0 : 0.0;
+        M[i][j] = v;
     }
+    __syncthreads();
     for (int col = 0; col < n; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < n; ++r)
-            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
-        if (M[piv][col] == 0.0) {
-            atomicOr(status, DPP_STATUS_NONFINITE);
-            for (int i = 0; i < m; ++i) c[i] = (i == m - 1) ? 1.0 : 0.0;
-            return;
+        if (tid == 0) {
+            int piv = col;
+            for (int r = col + 1; r < n; ++r)
+                if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+            piv_s = M[piv][col] == 0.0 ? -1 : piv;
         }
-        if (piv != col)
-            for (int j = 0; j <= n; ++j) {
-                const double t = M[col][j];
-                M[col][j] = M[piv][j];
-                M[piv][j] = t;
+        __syncthreads();
+        const int piv = piv_s;
+        if (piv < 0) {
+            if (tid == 0) {
+                atomicOr(status, DPP_STATUS_NONFINITE);
+                for (int i = 0; i < m; ++i) c[i] = (i == m - 1) ? 1.0 : 0.0;
             }
-        for (int r = col + 1; r < n; ++r) {
-            const double fct = M[r][col] / M[col][col];
-            for (int j = col; j <= n; ++j) M[r][j] -= fct * M[col][j];
+            return;  // uniform
         }
+        if (piv != col && tid <= n) {
+            const double t = M[col][tid];
+            M[col][tid] = M[piv][tid];
+            M[piv][tid] = t;
+        }
+        __syncthreads();
+        if (tid > col && tid < n) {
+            const double fct = M[tid][col] / M[col][col];
+            for (int j = col; j <= n; ++j) M[tid][j] -= fct * M[col][j];
+        }
+        __syncthreads();
     }
-    for (int i = n - 1; i >= 0; --i) {
-        double s = M[i][n];
-        for (int j = i + 1; j < n; ++j) s -= M[i][j] * x[j];
-        x[i] = s / M[i][i];
+    if (tid == 0) {
+        double x[PULAY_MAX + 1];
+        for (int i = n - 1; i >= 0; --i) {
+            double sacc = M[i][n];
+            for (int j = i + 1; j < n; ++j) sacc -= M[i][j] * x[j];
+            x[i] = sacc / M[i][i];
+        }
+        for (int i = 0; i < m; ++i) c[i] = x[i];
     }
-    for (int i = 0; i < m; ++i) c[i] = x[i];
 }
 
 // n_in = sum_i c_i (n_in,i + alpha R_i) per cell (blockIdx.y), history order.

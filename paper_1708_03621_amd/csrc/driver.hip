@@ -130,7 +130,7 @@ struct dpp_system_s {
     bool reg_xpass = true;  // register-resident x pass of H where S0 is compiled in
     bool reg_planes = true; // register plane passes (digit-reversed planes) for square y-z faces
     int rot_pt = 0;         // rotate point tiles per wave (0: by launch size)
-    int ov_narrow = 0;      // 1: overlap tasks as single tiles per wave
+    int ov_mode = 0;        // overlap launch shape (0 chunked 2x2 blocks, 1 chunked single tiles, 2 single pass)
     std::string tune_report;
     // graphs
     bool graph_on = false;
@@ -309,7 +309,7 @@ dpp_status overlap_jobs(dpp_system_s* s, int nbo, const std::vector<OvJob>& jobs
     if ((size_t)poff > s->ov_part_elems) return set_error(DPP_EUNSUPPORTED, "overlap partial buffer too small");
     const OvTask* d = nullptr;
     DPP_TRY(table_t(s, t, &d));
-    return overlap_tasks(s->ctx, t, d, s->ov_part, act, s->ov_narrow);
+    return overlap_tasks(s->ctx, t, d, s->ov_part, act, s->ov_mode);
 }
 
 struct RotJob {
@@ -382,7 +382,7 @@ dpp_status apply_H_all(dpp_system_s* s, int nbo, const double2* X, double2* HX, 
         if ((size_t)poff > s->ov_part_elems) return set_error(DPP_EUNSUPPORTED, "overlap partial buffer too small");
         const OvTask* dt = nullptr;
         DPP_TRY(table_t(s, t, &dt));
-        DPP_TRY(overlap_tasks(s->ctx, t, dt, s->ov_part, act, s->ov_narrow));
+        DPP_TRY(overlap_tasks(s->ctx, t, dt, s->ov_part, act, s->ov_mode));
         const RotTask* dr = nullptr;
         DPP_TRY(table_t(s, r, &dr));
         DPP_TRY(rotate_tasks(s->ctx, r, dr, act, s->rot_pt));
@@ -408,7 +408,7 @@ dpp_status proj_overlaps(dpp_system_s* s, int nbo, const double2* X) {
     if (t.empty()) return DPP_OK;
     const OvTask* dt = nullptr;
     DPP_TRY(table_t(s, t, &dt));
-    return overlap_tasks(s->ctx, t, dt, s->ov_part, nullptr, s->ov_narrow);
+    return overlap_tasks(s->ctx, t, dt, s->ov_part, nullptr, s->ov_mode);
 }
 
 // n = sum_k w_k sum_i f_ki |I psi_ki|^2 per cell over nbo bands (fillings at d_f).
@@ -1485,18 +1485,21 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
         rep += buf;
     }
     {
+        static const char* oname[] = {"wide", "single-tile", "single-pass"};
         double best = 1e300;
         int bn = 0;
         rep += "overlap blocks:";
-        for (int nar : {0, 1}) {
-            s->ov_narrow = nar;
-            const double t = timeit([&] { return overlap_jobs(s, 0, {OvJob{Y, Y, 1.0, true, s->U}}); });
-            snprintf(buf, sizeof buf, " %s %.1f", nar ? "single-tile" : "wide", t);
+        for (int mode : {0, 1, 2}) {
+            s->ov_mode = mode;
+            const double t = timeit([&] {
+                return overlap_jobs(s, 0, {OvJob{Y, Y, 1.0, true, s->U}, OvJob{Y, HY, 1.0, false, s->H0}});
+            });
+            snprintf(buf, sizeof buf, " %s %.1f", oname[mode], t);
             rep += buf;
-            if (t < best) best = t, bn = nar;
+            if (t < best) best = t, bn = mode;
         }
-        s->ov_narrow = bn;
-        snprintf(buf, sizeof buf, " us -> %s", bn ? "single-tile" : "wide");
+        s->ov_mode = bn;
+        snprintf(buf, sizeof buf, " us -> %s", oname[bn]);
         rep += buf;
     }
     (void)hipEventDestroy(e0);
@@ -1508,6 +1511,39 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
     s->graphs.clear();
     s->tune_report = rep;
     return err;
+}
+
+extern "C" dpp_status dpp_system_set_launch_choice(dpp_system s, int which, int value) {
+    clear_error();
+    DPP_REQUIRE(s, "dpp_system_set_launch_choice: null system");
+    switch (which) {
+        case DPP_CHOICE_OVERLAP:
+            DPP_REQUIRE(value >= 0 && value <= 2, "dpp_system_set_launch_choice: overlap mode 0..2");
+            s->ov_mode = value;
+            break;
+        case DPP_CHOICE_ROTATE_PT:
+            DPP_REQUIRE(value == 0 || value == 1 || value == 2 || value == 4,
+                        "dpp_system_set_launch_choice: rotate point tiles 0, 1, 2 or 4");
+            s->rot_pt = value;
+            break;
+        case DPP_CHOICE_XPASS: {
+            DPP_REQUIRE(value >= XZ_AUTO && value <= XZ_LDS, "dpp_system_set_launch_choice: x-pass variant 0..3");
+            const ItemTable* itc = nullptr;
+            DPP_TRY(items_for(s, 0, &itc));
+            ItemTable* it = const_cast<ItemTable*>(itc);
+            for (size_t g = 0; g < it->xz.S0.size(); ++g) {
+                // variants a length does not have fall back to the LDS pass
+                it->xz.var64[g] = xz_variant_available(it->xz.S0[g], true, value) ? value : XZ_LDS;
+                it->xz.var32[g] = xz_variant_available(it->xz.S0[g], false, value) ? value : XZ_LDS;
+            }
+            break;
+        }
+        default:
+            return set_error(DPP_EINVAL, "dpp_system_set_launch_choice: unknown choice");
+    }
+    for (ScfGraph& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+    return DPP_OK;
 }
 
 extern "C" dpp_status dpp_system_tune_report(dpp_system s, char* buf, size_t len) {

@@ -289,11 +289,14 @@ RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, 
                       double beta, double2* out, int64_t ldout);
 // Batched contractions over a device task table; `act` (nullable) masks
 // tasks by their work item: tasks of inactive items do nothing.
-// Launch choices (set by the tuner): ov_narrow = 1 runs every overlap task as
-// single 16x16 tiles per wave; rot_pt = 1, 2 or 4 fixes the point tiles per
-// rotate wave for outputs of up to 32 bands (0: by the launch size).
+// Launch choices (set by the tuner): ov_mode 0 = 2x2 tile blocks per wave over
+// 256-point chunks, then a fixed-order reduction of the chunk partials; 1 =
+// the same with single 16x16 tiles per wave; 2 = one workgroup per (task,
+// tile block) over all points, writing the result directly (one launch).
+// rot_pt = 1, 2 or 4 fixes the point tiles per rotate wave for outputs of up
+// to 32 bands (0: by the launch size).
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
-                         const int* act = nullptr, int ov_narrow = 0);
+                         const int* act = nullptr, int ov_mode = 0);
 dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks,
                         const int* act = nullptr, int rot_pt = 0);
 dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,

@@ -126,6 +126,7 @@ SIGNATURES = {
     "dpp_system_apply_H": [_vp, _vp, _vp],
     "dpp_system_tune": [_vp, _vp, _vp, _i],
     "dpp_system_tune_report": [_vp, C.c_char_p, C.c_size_t],
+    "dpp_system_set_launch_choice": [_vp, _i, _i],
     "dpp_net_create": [_vp, _ip, _i, C.POINTER(_vp)],
     "dpp_net_destroy": [_vp],
     "dpp_net_num_params": [_vp, _ip],
@@ -442,6 +443,13 @@ def dpp_set_graph_mode(sys_, on=True):
 
 def dpp_system_tune(sys_, Y, HY, reps=5):
     _call("dpp_system_tune", sys_, _ptr(Y), _ptr(HY), int(reps))
+
+
+DPP_CHOICE_OVERLAP, DPP_CHOICE_ROTATE_PT, DPP_CHOICE_XPASS = 0, 1, 2
+
+
+def dpp_system_set_launch_choice(sys_, which, value):
+    _call("dpp_system_set_launch_choice", sys_, int(which), int(value))
 
 
 def dpp_system_tune_report(sys_) -> str:

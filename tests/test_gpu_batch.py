@@ -171,3 +171,22 @@ def test_tuner_keeps_results(dev):
     assert err < 1e-10
     D.dpp_system_destroy(sa)
     D.dpp_system_destroy(sb)
+
+
+@pytest.mark.parametrize("which,value", [(0, 1), (0, 2), (1, 2), (1, 4), (2, 1), (2, 2), (2, 3)])
+def test_launch_choices_match_default(dev, which, value):
+    """Every launch variant the tuner can pick gives the default SCF energies
+    to rounding (mixed cells: several boxes, band counts and k-point sets)."""
+    D = dev.D
+    cells = _mixed_cells()
+    sa, Ya, _ = _batch(dev, cells)
+    Ea, _ = _run(dev, sa, Ya, cells, 3)
+    D.dpp_system_destroy(sa)
+    sb, Yb, _ = _batch(dev, cells)
+    D.dpp_system_set_launch_choice(sb, which, value)
+    Eb, _ = _run(dev, sb, Yb, cells, 3)
+    D.dpp_system_destroy(sb)
+    nat = np.array([c.nat for c in cells])
+    err = np.max(np.abs(Ea - Eb) / nat)
+    log(f"choice {which}={value}: max difference {err:.2e} Ha/atom")
+    assert err < 1e-10
