@@ -415,11 +415,12 @@ dpp_status proj_overlaps(dpp_system_s* s, int nbo, const double2* X) {
 dpp_status density_all(dpp_system_s* s, int nbo, const double2* psi, double* n, dpp_precision prec) {
     const ItemTable* it;
     DPP_TRY(items_for(s, nbo, &it));
+    const XzPlan* xp = s->reg_xpass ? &it->xz : nullptr;
     if (prec == DPP_F64)
         return density_batched<double>(s->ctx, it->d_items, it->h, psi, s->d_f, s->Tplanes, s->dens_part,
-                                       it->d_cells, s->ncells, s->maxN, n, &it->pl);
+                                       it->d_cells, s->ncells, s->maxN, n, &it->pl, xp);
     return density_batched<float>(s->ctx, it->d_items, it->h, psi, s->d_f, s->Tplanes, s->dens_part, it->d_cells,
-                                  s->ncells, s->maxN, n, &it->pl);
+                                  s->ncells, s->maxN, n, &it->pl, xp);
 }
 
 dpp_status axpby_all(dpp_system_s* s, int nbo, const double* a, const double2* x, const double* b, const double2* y,

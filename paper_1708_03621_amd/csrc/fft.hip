@@ -693,9 +693,9 @@ constexpr int DENS_CHUNKS = 16;
 template <typename T, int NT, bool BATCH = false>
 __global__ void __launch_bounds__(NT)
 k_xz_density(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb,
-             const double* __restrict__ fill, double* __restrict__ part) {
+             const double* __restrict__ fill, double* __restrict__ part, const int* __restrict__ idx) {
     using Cx = typename cx<T>::t;
-    const FftItem& it = DPP_ITEM(items, single);
+    const FftItem& it = idx ? items[idx[blockIdx.z]] : DPP_ITEM(items, single);
     const int i1 = blockIdx.x, c = blockIdx.y;
     if (i1 >= it.S1 || c >= it.dnch) return;
     const int b0 = c * it.dchunk;
@@ -1184,10 +1184,102 @@ dpp_status vx_cells(dpp_ctx_s* cx_, const FftItem* d_cell_items, int ncells, int
     return DPP_OK;
 }
 
+// Density x pass in registers: a lane pair per (item, band chunk, column)
+// as in k_xz_reg2; over the chunk's bands the column is transformed to real
+// space along x and w f |psi|^2 accumulated in FP64 registers, then written
+// to the chunk's partial box at natural (x, y, z).
+template <typename T, int S0>
+__global__ void __launch_bounds__(256)
+k_xz_dens_reg2(const FftItem* __restrict__ items, const int* __restrict__ idx, const typename cx<T>::t* __restrict__ Tb,
+               const double* __restrict__ fill, double* __restrict__ part) {
+    using Cx = typename cx<T>::t;
+    constexpr int M = S0 / 2;
+    const int item = idx ? idx[blockIdx.z] : (int)blockIdx.z;
+    const FftItem& it = items[item];
+    const int c = blockIdx.y;
+    if (c >= it.dnch) return;
+    const int np = it.S1 * it.S2;
+    const int col = blockIdx.x * 128 + (threadIdx.x >> 1);
+    const int h = threadIdx.x & 1;
+    if (col >= np) return;  // both lanes of a pair leave together
+    const int nP = it.nplanes;
+    const int b0 = c * it.dchunk, b1 = min(it.nb, b0 + it.dchunk);
+    double acc[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) acc[p] = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const double fb = fill[it.f_off + b];
+        if (fb == 0.0) continue;  // uniform across the workgroup
+        const Cx* base = Tb + it.t_off + (int64_t)b * nP * np + col;
+        Cx x[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            int d = (j + h * M - it.n0min) % S0;
+            d += d < 0 ? S0 : 0;
+            x[j] = d < nP ? base[(int64_t)d * np] : Cx{0, 0};
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const Cx o = Cx{pair_swap(x[j].x), pair_swap(x[j].y)};
+            if (h == 0) {
+                x[j] = Cx{x[j].x + o.x, x[j].y + o.y};
+            } else {
+                const Cx dlt = Cx{o.x - x[j].x, o.y - x[j].y};
+                x[j] = j == 0 ? dlt : cmul(dlt, reg_twiddle<T, S0>(j, +1));
+            }
+        }
+        reg_dif<T, M, +1, 0>(x, nullptr, nullptr);
+#pragma unroll
+        for (int p = 0; p < M; ++p) {
+            const double xr = (double)x[p].x, xi = (double)x[p].y;
+            acc[p] += fb * (xr * xr + xi * xi);
+        }
+    }
+    int n1 = col / it.S2, n2 = col - (col / it.S2) * it.S2;
+    if (it.perm) {
+        n1 = digit_rev_axis(it.ax[1], n1);
+        n2 = digit_rev_axis(it.ax[2], n2);
+    }
+    const int64_t N = (int64_t)S0 * np;
+    double* dst = part + it.p_off + (int64_t)c * N + (int64_t)n1 * it.S2 + n2;
+#pragma unroll
+    for (int p = 0; p < M; ++p) dst[(int64_t)(2 * reg_digit_rev(M, p) + h) * np] = it.wk * acc[p];
+}
+
+// Register density pass for one x-length group; false if S0 has none.
+template <typename T>
+static bool dens_reg_launch(int S0, dim3 grid, hipStream_t st, const FftItem* items, const int* idx,
+                            const typename cx<T>::t* Tb, const double* fill, double* part) {
+    grid.x = (grid.x * 256 + 127) / 128;
+    switch (S0) {
+#define DPP_DENS_REG(n)                                                                                      \
+    case n:                                                                                                  \
+        hipLaunchKernelGGL((k_xz_dens_reg2<T, n>), grid, dim3(256), 0, st, items, idx, Tb, fill, part); \
+        return true;
+        DPP_DENS_REG(12) DPP_DENS_REG(16) DPP_DENS_REG(18) DPP_DENS_REG(20) DPP_DENS_REG(24) DPP_DENS_REG(30)
+        DPP_DENS_REG(32) DPP_DENS_REG(36) DPP_DENS_REG(40) DPP_DENS_REG(48) DPP_DENS_REG(50) DPP_DENS_REG(54)
+        DPP_DENS_REG(60) DPP_DENS_REG(64)
+#undef DPP_DENS_REG
+        default:
+            return false;
+    }
+}
+
+static bool dens_reg_available(int S0) {
+    switch (S0) {
+        case 12: case 16: case 18: case 20: case 24: case 30: case 32: case 36: case 40:
+        case 48: case 50: case 54: case 60: case 64:
+            return true;
+        default:
+            return false;
+    }
+}
+
 template <typename T>
 dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h,
                            const double2* psi, const double* fill, void* Tbv, double* part,
-                           const CellDesc* d_cells, int ncells, int64_t maxN, double* n, const PlanePlan* pplan) {
+                           const CellDesc* d_cells, int ncells, int64_t maxN, double* n, const PlanePlan* pplan,
+                           const XzPlan* xplan) {
     using Cx = typename cx<T>::t;
     if (h.empty()) return DPP_OK;
     Cx* Tb = reinterpret_cast<Cx*>(Tbv);
@@ -1210,10 +1302,27 @@ dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::ve
     }
     {
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, b2);
-        DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz_density<T, NT_, true>; DPP_TRY(set_lds(k, bs.xz.lds));
-                        hipLaunchKernelGGL(k, dim3(bs.maxS1, mch, nit), dim3(NT_), bs.xz.lds, st, d_items, i0,
-                                           (const Cx*)Tb, fill, part));
-        DPP_LAUNCHED();
+        // per x-length group: the register pass where the length has one, else
+        // the LDS pass over the group's items; without groups the LDS pass
+        if (xplan) {
+            for (size_t g = 0; g < xplan->S0.size(); ++g) {
+                const dim3 grid((unsigned)((xplan->maxS1S2[g] + 255) / 256), (unsigned)mch,
+                                (unsigned)xplan->count[g]);
+                if (!dens_reg_available(xplan->S0[g]) ||
+                    !dens_reg_launch<T>(xplan->S0[g], grid, st, d_items, xplan->idx[g], (const Cx*)Tb, fill, part)) {
+                    const int* gidx = xplan->idx[g];
+                    DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz_density<T, NT_, true>; DPP_TRY(set_lds(k, bs.xz.lds));
+                                    hipLaunchKernelGGL(k, dim3(bs.maxS1, mch, xplan->count[g]), dim3(NT_), bs.xz.lds,
+                                                       st, d_items, i0, (const Cx*)Tb, fill, part, gidx));
+                }
+                DPP_LAUNCHED();
+            }
+        } else {
+            DPP_NT_DISPATCH(bs.xz.threads, auto k = k_xz_density<T, NT_, true>; DPP_TRY(set_lds(k, bs.xz.lds));
+                            hipLaunchKernelGGL(k, dim3(bs.maxS1, mch, nit), dim3(NT_), bs.xz.lds, st, d_items, i0,
+                                               (const Cx*)Tb, fill, part, (const int*)nullptr));
+            DPP_LAUNCHED();
+        }
     }
     TimerScope ts_(cx_, DPP_TK_FIELDS);
     hipLaunchKernelGGL(k_density_reduce_cells, dim3((unsigned)((maxN + 255) / 256), (unsigned)ncells), dim3(256), 0,
@@ -1223,10 +1332,10 @@ dpp_status density_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::ve
 }
 template dpp_status density_batched<double>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&, const double2*,
                                             const double*, void*, double*, const CellDesc*, int, int64_t, double*,
-                                            const PlanePlan*);
+                                            const PlanePlan*, const XzPlan*);
 template dpp_status density_batched<float>(dpp_ctx_s*, const FftItem*, const std::vector<FftItem>&, const double2*,
                                            const double*, void*, double*, const CellDesc*, int, int64_t, double*,
-                                           const PlanePlan*);
+                                           const PlanePlan*, const XzPlan*);
 
 // Per cell: E[c * stride] = (Omega / 2) sum of the cell's Hartree row partials.
 __global__ void k_hartree_energy_cells(const double* __restrict__ part, const CellDesc* __restrict__ cells,
@@ -1489,13 +1598,13 @@ extern "C" dpp_status dpp_density_accumulate(dpp_basis basis, int nb, const dpp_
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, nb * 16.0 * it.nplanes * it.S1 * it.S2 + nch * 8.0 * N);
         DPP_NT_DISPATCH(Lx.threads, auto k = k_xz_density<double, NT_>; DPP_TRY(set_lds(k, Lx.lds));
                         hipLaunchKernelGGL(k, dim3(it.S1, nch, 1), dim3(NT_), Lx.lds, st, nullptr, it,
-                                           (const double2*)ws, d_f, part));
+                                           (const double2*)ws, d_f, part, (const int*)nullptr));
     } else {
         DPP_TRY((pass1<float, double2>(cx_, it, (const double2*)psi, (float2*)ws)));
         TimerScope ts_(cx_, DPP_TK_XZ_DENSITY, nb * 8.0 * it.nplanes * it.S1 * it.S2 + nch * 8.0 * N);
         DPP_NT_DISPATCH(Lx.threads, auto k = k_xz_density<float, NT_>; DPP_TRY(set_lds(k, Lx.lds));
                         hipLaunchKernelGGL(k, dim3(it.S1, nch, 1), dim3(NT_), Lx.lds, st, nullptr, it,
-                                           (const float2*)ws, d_f, part));
+                                           (const float2*)ws, d_f, part, (const int*)nullptr));
     }
     DPP_LAUNCHED();
     hipLaunchKernelGGL(k_density_reduce, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, part, nch,

@@ -226,7 +226,7 @@ template <typename T>
 dpp_status density_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
                            const double2* psi, const double* fill, void* Tb, double* part,
                            const CellDesc* d_cells, int ncells, int64_t maxN, double* n,
-                           const PlanePlan* pplan = nullptr);
+                           const PlanePlan* pplan = nullptr, const XzPlan* xplan = nullptr);
 size_t batched_plane_elems(const std::vector<FftItem>& h_items);
 // Vx = (Omega/N) V in the plane order of each cell's x pass (one item per
 // cell: v_off = field offset, perm, axes); the x pass of H then reads it
