@@ -346,7 +346,7 @@ dpp_status dpp_system_counters(dpp_system sys, int64_t *hc_bandk);
 dpp_status dpp_system_apply_H(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY);
 /* Launch autotuner (form 2's tiles, chosen per system by measurement):
  * times the candidate launch variants on the system's own items and keeps
- * the fastest.  Choices: per x-pass length S0 and precision, the register
+ * the default rule unless another candidate is at least 3% faster.  Choices: per x-pass length S0 and precision, the register
  * x pass with one thread per column, with a lane pair per column, or the
  * LDS pass; point tiles per wave of the X M contraction (1, 2 or 4, for up
  * to 32 bands); the A^dag O B block shape (2x2 tiles per wave or single

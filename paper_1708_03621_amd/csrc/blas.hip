@@ -1025,21 +1025,48 @@ k_linesearch_wave(const Seg* __restrict__ seg, const double2* __restrict__ U, co
 // the five small steps of the gradient at the current point in one launch.
 // On a failed factorization Rinv, M1 and M2 are NaN, E0 is NaN and the
 // status word latches DPP_STATUS_NOTPD.
+// With `step` the point moved by a = step[item] along the line whose
+// matrices X = Y^dag O D, Q = D^dag O D, H1 = Y^dag H D, H2 = D^dag H D are
+// given: U and H0 are first advanced to U + a (X + X^dag) + a^2 Q and
+// H0 + a (H1 + H1^dag) + a^2 H2 (the overlaps at Y + a D, as the line search
+// models them) and written back.
 template <int NMAX>
 __global__ void __launch_bounds__(64)
-k_grad_prep_wave(const Seg* __restrict__ seg, const double2* __restrict__ U, const double2* __restrict__ H0,
+k_grad_prep_wave(const Seg* __restrict__ seg, double2* __restrict__ U, double2* __restrict__ H0,
                  double2* __restrict__ Rinv, double2* __restrict__ M1, double2* __restrict__ M2,
-                 double* __restrict__ E0, int* __restrict__ status) {
+                 double* __restrict__ E0, int* __restrict__ status, const double* __restrict__ step,
+                 const double2* __restrict__ X, const double2* __restrict__ Q, const double2* __restrict__ H1,
+                 const double2* __restrict__ H2) {
     constexpr int PER = (NMAX * NMAX + 63) / 64;
     __shared__ CholWaveLds<NMAX> L;
     __shared__ double2 Hs[NMAX][NMAX + 1];
+    // U is staged in L.X: the factorization reads its input before it
+    // writes X
+    double2 (*Us)[NMAX + 1] = L.X;
     const Seg sg = seg[blockIdx.x];
     const int n = sg.nb;
     const int64_t o = sg.moff;
     const int lane = threadIdx.x;
-    for (int e = lane; e < n * n; e += 64) Hs[e / n][e % n] = H0[o + e];
-    // (the staging is ordered before its use by the barriers of the factorization)
-    const int f = chol_inv_wave<NMAX>(n, [&](int r, int c) { return U[o + r * n + c]; }, L);
+    const double a = step ? step[blockIdx.x] : 0.0;
+    for (int e = lane; e < n * n; e += 64) {
+        const int r = e / n, c = e - r * n;
+        double2 u = U[o + e], h = H0[o + e];
+        if (step && a != 0.0) {
+            const double2 x = X[o + e], xt = X[o + c * n + r], q = Q[o + e];
+            const double2 p = H1[o + e], pt = H1[o + c * n + r], h2 = H2[o + e];
+            u = double2{u.x + a * (x.x + xt.x) + a * a * q.x, u.y + a * (x.y - xt.y) + a * a * q.y};
+            h = double2{h.x + a * (p.x + pt.x) + a * a * h2.x, h.y + a * (p.y - pt.y) + a * a * h2.y};
+        }
+        Us[r][c] = u;
+        Hs[r][c] = h;
+    }
+    __syncthreads();
+    if (step && a != 0.0)
+        for (int e = lane; e < n * n; e += 64) {
+            U[o + e] = Us[e / n][e % n];
+            H0[o + e] = Hs[e / n][e % n];
+        }
+    const int f = chol_inv_wave<NMAX>(n, [&](int r, int c) { return Us[r][c]; }, L);
     if (f) {
         if (lane == 0) {
             if (status) atomicOr(status, DPP_STATUS_NOTPD);
@@ -1116,12 +1143,15 @@ k_grad_prep_wave(const Seg* __restrict__ seg, const double2* __restrict__ U, con
     }
 }
 
-bool grad_prep_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, const double2* U,
-                           const double2* H0, double2* Rinv, double2* M1, double2* M2, double* E0, int* status) {
+bool grad_prep_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, double2* U, double2* H0,
+                           double2* Rinv, double2* M1, double2* M2, double* E0, int* status, const double* step,
+                           const double2* X, const double2* Q, const double2* H1, const double2* H2) {
     if (nmax <= 16)
-        hipLaunchKernelGGL(k_grad_prep_wave<16>, dim3(nblk), dim3(64), 0, st, seg, U, H0, Rinv, M1, M2, E0, status);
+        hipLaunchKernelGGL(k_grad_prep_wave<16>, dim3(nblk), dim3(64), 0, st, seg, U, H0, Rinv, M1, M2, E0, status,
+                           step, X, Q, H1, H2);
     else if (nmax <= 32)
-        hipLaunchKernelGGL(k_grad_prep_wave<32>, dim3(nblk), dim3(64), 0, st, seg, U, H0, Rinv, M1, M2, E0, status);
+        hipLaunchKernelGGL(k_grad_prep_wave<32>, dim3(nblk), dim3(64), 0, st, seg, U, H0, Rinv, M1, M2, E0, status,
+                           step, X, Q, H1, H2);
     else
         return false;
     return true;

@@ -91,9 +91,11 @@ constexpr int SM_NT = 1024;    // workgroup size of the LDS small-matrix kernels
 bool cholesky_wave_launch(hipStream_t st, unsigned nblk, int n, int64_t stride, const Seg* seg, int nbo,
                           const double2* U, double2* Rinv, int* status, const int* act);
 // Cholesky inverse, U^{-1}, M2 = -Omega U^{-1} H0 U^{-1} and E0 = Re Tr(U^{-1} H0)
-// per item in one launch for up to 32 bands (false: larger).
-bool grad_prep_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, const double2* U,
-                           const double2* H0, double2* Rinv, double2* M1, double2* M2, double* E0, int* status);
+// per item in one launch for up to 32 bands (false: larger); with `step`, U
+// and H0 are first advanced along the line matrices X, Q, H1, H2.
+bool grad_prep_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, double2* U, double2* H0,
+                           double2* Rinv, double2* M1, double2* M2, double* E0, int* status, const double* step,
+                           const double2* X, const double2* Q, const double2* H1, const double2* H2);
 bool linesearch_wave_launch(hipStream_t st, unsigned nblk, int n, const Seg* seg, const double2* U,
                             const double2* X, const double2* Q, const double2* H0, const double2* H1,
                             const double2* H2, const double* E0v, const double* at0, const double* d0v,

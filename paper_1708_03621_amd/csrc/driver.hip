@@ -570,14 +570,20 @@ dpp_status pulay_mix(dpp_system_s* s) {
 // ----------------------------------------------------- band energy (B) ---
 // Gradient state at the current Y: U, Rinv, H0 = Y^dag H Y,
 // g = (HY - O Y U^{-1} H0) U^{-1}, E0_k = Tr(U^{-1} H0) (device); requires HY.
-dpp_status grad_B(dpp_system_s* s, const double2* Y) {
-    DPP_TRY(overlap_jobs(s, 0, {OvJob{Y, Y, 1.0, true, s->U}, OvJob{Y, s->HY, 1.0, false, s->H0}}));
+// after_step: Y and HY were just advanced by the accepted step along the line
+// of X, Q, H1, H2; with up to 32 bands U and H0 then follow from those
+// matrices (the line search's model of them) without new overlaps.
+dpp_status grad_B(dpp_system_s* s, const double2* Y, bool after_step = false) {
+    const bool wave = s->maxnb <= EIGW_MAXN;
+    if (!(wave && after_step))
+        DPP_TRY(overlap_jobs(s, 0, {OvJob{Y, Y, 1.0, true, s->U}, OvJob{Y, s->HY, 1.0, false, s->H0}}));
     bool fused = false;
     {
         // up to 32 bands: factor, U^{-1}, M2 and E0 in one single-wave launch
         TimerScope ts_(s->ctx, DPP_TK_CHOLESKY);
         fused = grad_prep_wave_launch(stream(s), (unsigned)s->nit, s->maxnb, s->d_seg, s->U, s->H0, s->Rinv, s->M1,
-                                      s->M2, s->d_bE0, s->ctx->d_status);
+                                      s->M2, s->d_bE0, s->ctx->d_status, after_step ? s->cg.step : nullptr, s->X,
+                                      s->Q, s->H1, s->H2);
         if (fused) DPP_LAUNCHED();
     }
     if (!fused) {
@@ -671,7 +677,7 @@ dpp_status cgB_step(dpp_system_s* s, double2* Y) {
                            (const double2*)s->g, s->gp, s->Dp);
         DPP_LAUNCHED();
     }
-    DPP_TRY(grad_B(s, Y));
+    DPP_TRY(grad_B(s, Y, true));
     return DPP_OK;
 }
 
@@ -1415,7 +1421,9 @@ extern "C" dpp_status dpp_system_counters(dpp_system s, int64_t* hc_bandk) {
 // thread per column, with a lane pair per column, or the LDS pass; the point
 // tiles per rotate wave; the overlap block shape.  Each candidate runs
 // `reps` times (after one warm-up run) between HIP events on the library
-// stream; the first candidate wins ties.
+// stream.  The default rule is timed first and kept unless another
+// candidate is at least 3% faster (timing noise does not flip choices).
+constexpr double TUNE_MARGIN = 0.97;
 extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* HYc, int reps) {
     clear_error();
     DPP_REQUIRE(s && Yc && HYc && reps >= 1 && (const void*)Yc != (const void*)HYc, "dpp_system_tune: bad arguments");
@@ -1456,13 +1464,14 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
             int bv = XZ_AUTO;
             snprintf(buf, sizeof buf, "x pass S0=%d %s:", it->xz.S0[g], fp64 ? "f64" : "f32");
             rep += buf;
-            for (int v : {XZ_REG2, XZ_REG1, XZ_LDS}) {
+            // the default rule first; another variant must beat it by 3%
+            for (int v : {XZ_AUTO, XZ_REG2, XZ_REG1, XZ_LDS}) {
                 if (!xz_variant_available(it->xz.S0[g], fp64, v)) continue;
                 var[g] = v;
                 const double t = timeit([&] { return apply_H_all(s, 0, Y, HY); });
                 snprintf(buf, sizeof buf, " %s %.1f", xname[v], t);
                 rep += buf;
-                if (t < best) best = t, bv = v;
+                if (v == XZ_AUTO ? t < best : t < TUNE_MARGIN * best) best = t, bv = v;
             }
             var[g] = bv;
             snprintf(buf, sizeof buf, " us per H -> %s; ", xname[bv]);
@@ -1474,15 +1483,15 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
         double best = 1e300;
         int bp = 0;
         rep += "rotate point tiles:";
-        for (int pt : {1, 2, 4}) {
+        for (int pt : {0, 1, 2, 4}) {
             s->rot_pt = pt;
             const double t = timeit([&] { return rotate_jobs(s, 0, {RotJob{Y, s->Rinv, 0.0, s->psi}}); });
-            snprintf(buf, sizeof buf, " %d %.1f", pt, t);
+            snprintf(buf, sizeof buf, " %s %.1f", pt ? std::to_string(pt).c_str() : "auto", t);
             rep += buf;
-            if (t < best) best = t, bp = pt;
+            if (pt == 0 ? t < best : t < TUNE_MARGIN * best) best = t, bp = pt;
         }
         s->rot_pt = bp;
-        snprintf(buf, sizeof buf, " us -> %d; ", bp);
+        snprintf(buf, sizeof buf, " us -> %s; ", bp ? std::to_string(bp).c_str() : "auto");
         rep += buf;
     }
     {
@@ -1497,7 +1506,7 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
             });
             snprintf(buf, sizeof buf, " %s %.1f", oname[mode], t);
             rep += buf;
-            if (t < best) best = t, bn = mode;
+            if (mode == 0 ? t < best : t < TUNE_MARGIN * best) best = t, bn = mode;
         }
         s->ov_mode = bn;
         snprintf(buf, sizeof buf, " us -> %s", oname[bn]);
