@@ -36,12 +36,24 @@ constexpr double DEGEN_TOL = 1e-6;     // degenerate-set width of the aufbau fil
 // Device arrays of the band-CG state, one entry per work item.
 struct CgBState {
     double *at, *gkg, *beta, *d0, *d0r, *step, *step2, *cK, *cD;
+    double* stepf;  // the accepted step of the last CG step (0: none)
     int *reset, *stat, *act, *steep, *ok, *ok2, *retry;
 };
 
 // Kernels with `nbo`: band count override (> 0) for every item, else seg.nb.
 __global__ void k_seg_axpby(const Seg* seg, int nbo, const double* a, const double2* x, const double* b,
                             const double2* y, double2* out);
+// Band-CG control fused with the elementwise pass that consumes it (each
+// workgroup of an item evaluates the item's control in the same fixed order;
+// workgroup 0 writes the state):
+//   direction: reduce <g,Kg>, <g_prev,Kg>, <g,D_prev>, set beta, then D = -Kg + beta D_prev;
+//   retry:     mark failed CG searches, then D = cK Kg + cD D (D = -Kg for them);
+//   finish:    accept the steps (stepf), then Y += a D, HY += a HD, g_prev = g, D_prev = D.
+__global__ void k_cgB_direction(const Seg* seg, int nitems, const double* part, double* dots, CgBState s,
+                                const double2* Kg, const double2* Dp, double2* Dd);
+__global__ void k_cgB_retry_axpby(const Seg* seg, const double* dots, CgBState s, const double2* Kg, double2* Dd);
+__global__ void k_cgB_finish_update(const Seg* seg, const double* dots, CgBState s, double2* Y, const double2* Dd,
+                                    double2* HY, const double2* HD, const double2* g, double2* gp, double2* Dp);
 __global__ void k_seg_precond(const Seg* seg, int nbo, double scale, const double2* x, double2* out);
 __global__ void k_seg_dots(const Seg* seg, int nitems, int nbo, int npair, DotPairs pr, double* part);
 __global__ void k_seg_dots_reduce(const double* part, int nitems, int npair, double* out);
@@ -67,15 +79,10 @@ __global__ void k_pulay_solve_cells(int ncells, const int* st, const CellDesc* c
 __global__ void k_pulay_combine_cells(int64_t Ntot, const int* st, const CellDesc* cells, const double* coef,
                                       double alpha, const double* hn, const double* hr, double* nin);
 __global__ void k_cgB_reset(int nit, const Seg* seg, CgBState s);
-__global__ void k_cgB_retry(int nit, const double* dots, CgBState s);
-__global__ void k_cgB_finish(int nit, const double* dots, CgBState s);
 __global__ void k_aufbau(const CellDesc* cells, const Seg* seg, const double* eig, double* f, int* status);
 
 __global__ void k_cg_precond_dots(const Seg* seg, int nitems, const double2* g, const double2* gp,
                                   const double2* Dp, double2* Kg, double* part);
-__global__ void k_cgB_reduce_direction(int nitems, const double* part, double* dots, CgBState s);
-__global__ void k_cgB_update(const Seg* seg, const double* step, double2* Y, const double2* Dd, double2* HY,
-                             const double2* HD, const double2* g, double2* gp, double2* Dp);
 __global__ void k_trace_diag(const Seg* seg, const double2* M, double* out);
 
 // blas.hip: per-item Cholesky inverse, eigensolver, fused line search and

@@ -431,46 +431,6 @@ __global__ void k_cgB_reset(int nit, const Seg* __restrict__ seg, CgBState s) {
     s.gkg[k] = 0.0;
 }
 
-// Items whose CG line search failed (and was not already steepest descent)
-// retry along -K g: D <- cK K g + cD D with cK = -1, cD = 0 for them.
-__global__ void k_cgB_retry(int nit, const double* __restrict__ dots, CgBState s) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nit) return;
-    const int r = s.act[k] && !s.ok[k] && !s.steep[k];
-    s.retry[k] = r;
-    s.cK[k] = r ? -1.0 : 0.0;
-    s.cD[k] = r ? 0.0 : 1.0;
-    s.d0r[k] = r ? -dots[k] : s.d0[k];
-}
-
-// Accept the steps: failed items become stationary (step 0); successful ones
-// record <g,Kg> and the step as the next trial.
-__global__ void k_cgB_finish(int nit, const double* __restrict__ dots, CgBState s) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nit) return;
-    if (!s.act[k]) {
-        s.step[k] = 0.0;
-        return;
-    }
-    int o = s.ok[k];
-    double st = s.step[k];
-    if (s.retry[k]) {
-        o = s.ok2[k];
-        st = s.step2[k];
-    }
-    if (!o) {
-        s.stat[k] = 1;
-        s.reset[k] = 1;
-        st = 0.0;
-    }
-    s.step[k] = st;
-    if (o) {
-        s.gkg[k] = dots[k];
-        s.at[k] = st;
-        s.reset[k] = 0;
-    }
-}
-
 // Fused start of a band-CG step: Kg = K g and, per item, partial sums of
 // <g, Kg>, <g_prev, Kg>, <g, D_prev> (2 Re sum conj(a) b) in one pass:
 // part[(pair * nitems + k) * DOT_BLOCKS + block].
@@ -509,14 +469,20 @@ k_cg_precond_dots(const Seg* __restrict__ seg, int nitems, const double2* __rest
 // Per item (one 64-thread workgroup): fixed-order sums of the three dot
 // partials into dots[pair * (nitems + 1) + k], then the direction
 // coefficients of the item (as k_cgB_direction).
-__global__ void __launch_bounds__(64)
-k_cgB_reduce_direction(int nitems, const double* __restrict__ part, double* __restrict__ dots, CgBState s) {
+// --- fused control + elementwise passes (see blockops.h) ---
+
+__global__ void __launch_bounds__(256)
+k_cgB_direction(const Seg* __restrict__ seg, int nitems, const double* __restrict__ part, double* __restrict__ dots,
+                CgBState s, const double2* __restrict__ Kg, const double2* __restrict__ Dp, double2* __restrict__ Dd) {
     __shared__ double red[3][64];
-    const int k = blockIdx.x;
-    for (int p = 0; p < 3; ++p) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < DOT_BLOCKS; b += 64) v += part[((int64_t)p * nitems + k) * DOT_BLOCKS + b];
-        red[p][threadIdx.x] = v;
+    __shared__ double coef[2];
+    const int k = blockIdx.y;
+    if (threadIdx.x < 64) {
+        for (int p = 0; p < 3; ++p) {
+            double v = 0.0;
+            for (int b = threadIdx.x; b < DOT_BLOCKS; b += 64) v += part[((int64_t)p * nitems + k) * DOT_BLOCKS + b];
+            red[p][threadIdx.x] = v;
+        }
     }
     __syncthreads();
     for (int w = 32; w > 0; w >>= 1) {
@@ -524,49 +490,109 @@ k_cgB_reduce_direction(int nitems, const double* __restrict__ part, double* __re
             for (int p = 0; p < 3; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    const double gkg = red[0][0], gpkg = red[1][0], gdp = red[2][0];
-    dots[k] = gkg;
-    dots[(nitems + 1) + k] = gpkg;
-    dots[2 * (nitems + 1) + k] = gdp;
-    s.cK[k] = -1.0;
-    if (s.stat[k]) {
-        s.act[k] = 0;
-        s.beta[k] = 0.0;
-        s.d0[k] = 0.0;
-        s.steep[k] = 1;
-        return;
+    if (threadIdx.x == 0) {
+        const double gkg = red[0][0], gpkg = red[1][0], gdp = red[2][0];
+        const bool st = s.stat[k] != 0;
+        double b = 0.0, dd = 0.0;
+        if (!st) {
+            if (!s.reset[k]) b = fmax(0.0, (gkg - gpkg) / s.gkg[k]);
+            dd = -gkg + b * gdp;
+            if (b != 0.0 && dd >= 0.0) {
+                b = 0.0;
+                dd = -gkg;
+            }
+        }
+        coef[0] = -1.0;
+        coef[1] = b;
+        if (blockIdx.x == 0) {
+            dots[k] = gkg;
+            dots[(nitems + 1) + k] = gpkg;
+            dots[2 * (nitems + 1) + k] = gdp;
+            s.cK[k] = -1.0;
+            s.act[k] = st ? 0 : 1;
+            s.beta[k] = b;
+            s.d0[k] = dd;
+            s.steep[k] = st ? 1 : (b == 0.0);
+        }
     }
-    s.act[k] = 1;
-    double b = 0.0;
-    if (!s.reset[k]) b = fmax(0.0, (gkg - gpkg) / s.gkg[k]);
-    double dd = -gkg + b * gdp;
-    if (b != 0.0 && dd >= 0.0) {
-        b = 0.0;
-        dd = -gkg;
+    __syncthreads();
+    const Seg sg = seg[k];
+    const int64_t n = (int64_t)sg.nb * sg.npw;
+    const double ak = coef[0], bk = coef[1];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = sg.off + e;
+        const double2 v = Kg[o], w = Dp[o];
+        double2 r = double2{ak * v.x, ak * v.y};
+        r.x += bk * w.x;
+        r.y += bk * w.y;
+        Dd[o] = r;
     }
-    s.beta[k] = b;
-    s.d0[k] = dd;
-    s.steep[k] = b == 0.0;
 }
 
-// End of a band-CG step: Y += step D, HY += step HD, and the history for the
-// next direction (g_prev = g, D_prev = D), in one pass.
-__global__ void k_cgB_update(const Seg* __restrict__ seg, const double* __restrict__ step, double2* __restrict__ Y,
-                             const double2* __restrict__ Dd, double2* __restrict__ HY,
-                             const double2* __restrict__ HD, const double2* __restrict__ g, double2* __restrict__ gp,
-                             double2* __restrict__ Dp) {
+__global__ void __launch_bounds__(256)
+k_cgB_retry_axpby(const Seg* __restrict__ seg, const double* __restrict__ dots, CgBState s,
+                  const double2* __restrict__ Kg, double2* __restrict__ Dd) {
     const int k = blockIdx.y;
-    const Seg s = seg[k];
-    const int64_t n = (int64_t)s.nb * s.npw;
-    const double a = step[k];
+    const int r = s.act[k] && !s.ok[k] && !s.steep[k];
+    const double ak = r ? -1.0 : 0.0, bk = r ? 0.0 : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.retry[k] = r;
+        s.cK[k] = ak;
+        s.cD[k] = bk;
+        s.d0r[k] = r ? -dots[k] : s.d0[k];
+    }
+    if (!r) return;  // D stays (the unfused form computed 0 Kg + 1 D)
+    const Seg sg = seg[k];
+    const int64_t n = (int64_t)sg.nb * sg.npw;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t o = s.off + e;
-        const double2 d = Dd[o], hd = HD[o], y = Y[o], hy = HY[o];
-        Y[o] = double2{y.x + a * d.x, y.y + a * d.y};
-        HY[o] = double2{hy.x + a * hd.x, hy.y + a * hd.y};
-        gp[o] = g[o];
-        Dp[o] = d;
+        const int64_t o = sg.off + e;
+        const double2 v = Kg[o], w = Dd[o];
+        double2 q = double2{ak * v.x, ak * v.y};
+        q.x += bk * w.x;
+        q.y += bk * w.y;
+        Dd[o] = q;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_cgB_finish_update(const Seg* __restrict__ seg, const double* __restrict__ dots, CgBState s, double2* __restrict__ Y,
+                    const double2* __restrict__ Dd, double2* __restrict__ HY, const double2* __restrict__ HD,
+                    const double2* __restrict__ g, double2* __restrict__ gp, double2* __restrict__ Dp) {
+    const int k = blockIdx.y;
+    // accept the step (inputs act, ok, ok2, retry, step, step2 are not written here)
+    double st = 0.0;
+    int o = 0;
+    if (s.act[k]) {
+        o = s.ok[k];
+        st = s.step[k];
+        if (s.retry[k]) {
+            o = s.ok2[k];
+            st = s.step2[k];
+        }
+        if (!o) st = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.stepf[k] = st;
+        if (s.act[k]) {
+            if (!o) {
+                s.stat[k] = 1;
+                s.reset[k] = 1;
+            } else {
+                s.gkg[k] = dots[k];
+                s.at[k] = st;
+                s.reset[k] = 0;
+            }
+        }
+    }
+    const Seg sg = seg[k];
+    const int64_t n = (int64_t)sg.nb * sg.npw;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = sg.off + e;
+        const double2 d = Dd[q], hd = HD[q], y = Y[q], hy = HY[q];
+        Y[q] = double2{y.x + st * d.x, y.y + st * d.y};
+        HY[q] = double2{hy.x + st * hd.x, hy.y + st * hd.y};
+        gp[q] = g[q];
+        Dp[q] = d;
     }
 }
 
@@ -604,14 +630,18 @@ k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const 
     __shared__ int base[AUFBAU_MAX_ITEMS + 1];
     __shared__ double wks[AUFBAU_MAX_ITEMS];
     __shared__ int64_t foffs[AUFBAU_MAX_ITEMS];
+    __shared__ int nbk[AUFBAU_MAX_ITEMS];
     const CellDesc c = cells[blockIdx.x];
     for (int k = threadIdx.x; k < c.nitems; k += blockDim.x) {
-        wks[k] = seg[c.item0 + k].wk;
-        foffs[k] = seg[c.item0 + k].f_off;
+        const Seg sk = seg[c.item0 + k];
+        wks[k] = sk.wk;
+        foffs[k] = sk.f_off;
+        nbk[k] = sk.nb;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         base[0] = 0;
-        for (int k = 0; k < c.nitems; ++k) base[k + 1] = base[k] + seg[c.item0 + k].nb;
+        for (int k = 0; k < c.nitems; ++k) base[k + 1] = base[k] + nbk[k];
     }
     __syncthreads();
     const int ns = base[c.nitems];
@@ -642,20 +672,45 @@ k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // One pass over the sorted states, eight at a time from LDS into
+        // registers: a group [j0, j) closes at the first state j with
+        // e_j - e_j0 >= DEGEN_TOL; its capacity is summed in state order.
         double rem = c.ne;
-        int j = 0;
-        while (j < ns && rem > 1e-12) {
-            const double e0 = es[j];
-            const int j0 = j;
-            ++j;
-            while (j < ns && es[j] - e0 < DEGEN_TOL) ++j;
-            double cap = 0;
-            for (int t = j0; t < j; ++t) cap += cs[t];
+        bool stop = !(ns > 0 && rem > 1e-12);
+        int j0 = 0;
+        double e0 = ns > 0 ? es[0] : 0.0, cap = 0.0;
+        auto close = [&](int j) {
             const bool fits = cap <= rem + 1e-12;
             const double val = fits ? 2.0 : 2.0 * (rem / cap);
             for (int t = j0; t < j; ++t) fs[t] = val;
             rem = fits ? rem - cap : 0.0;
+        };
+        for (int jb = 0; jb < ns && !stop; jb += 8) {
+            double eb[8], cb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = min(jb + u, ns - 1);
+                eb[u] = es[j];
+                cb[u] = cs[j];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = jb + u;
+                if (stop || j >= ns) continue;
+                if (j > j0 && !(eb[u] - e0 < DEGEN_TOL)) {
+                    close(j);
+                    if (!(rem > 1e-12)) {
+                        stop = true;
+                        continue;
+                    }
+                    j0 = j;
+                    e0 = eb[u];
+                    cap = 0.0;
+                }
+                cap += cb[u];
+            }
         }
+        if (!stop) close(ns);
         if (rem > 1e-9) atomicOr(status, DPP_STATUS_NOBANDS);
     }
     __syncthreads();

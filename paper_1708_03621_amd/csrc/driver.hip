@@ -582,7 +582,7 @@ dpp_status grad_B(dpp_system_s* s, const double2* Y, bool after_step = false) {
         // up to 32 bands: factor, U^{-1}, M2 and E0 in one single-wave launch
         TimerScope ts_(s->ctx, DPP_TK_CHOLESKY);
         fused = grad_prep_wave_launch(stream(s), (unsigned)s->nit, s->maxnb, s->d_seg, s->U, s->H0, s->Rinv, s->M1,
-                                      s->M2, s->d_bE0, s->ctx->d_status, after_step ? s->cg.step : nullptr, s->X,
+                                      s->M2, s->d_bE0, s->ctx->d_status, after_step ? s->cg.stepf : nullptr, s->X,
                                       s->Q, s->H1, s->H2);
         if (fused) DPP_LAUNCHED();
     }
@@ -648,33 +648,34 @@ dpp_status cgB_init(dpp_system_s* s, double2* Y) {
 }
 
 dpp_status cgB_step(dpp_system_s* s, double2* Y) {
-    const unsigned ib = item_threads_blocks(s);
+    const dim3 eg(seg_blocks(s, 0), s->nit);
     {
+        // Kg and the direction dots, then beta and D = -Kg + beta D_prev
         TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
         hipLaunchKernelGGL(k_cg_precond_dots, dim3(DOT_BLOCKS, s->nit), dim3(256), 0, stream(s), s->d_seg, s->nit,
                            (const double2*)s->g, (const double2*)s->gp, (const double2*)s->Dp, s->Kg, s->d_part);
         DPP_LAUNCHED();
-        hipLaunchKernelGGL(k_cgB_reduce_direction, dim3(s->nit), dim3(64), 0, stream(s), s->nit,
-                           (const double*)s->d_part, s->d_dots, s->cg);
+        hipLaunchKernelGGL(k_cgB_direction, eg, dim3(256), 0, stream(s), s->d_seg, s->nit, (const double*)s->d_part,
+                           s->d_dots, s->cg, (const double2*)s->Kg, (const double2*)s->Dp, s->Dd);
         DPP_LAUNCHED();
     }
-    DPP_TRY(axpby_all(s, 0, s->cg.cK, s->Kg, s->cg.beta, s->Dp, s->Dd));
     DPP_TRY(line_mats_B(s, Y, nullptr));
     DPP_TRY(linesearch_B(s, s->cg.act, s->cg.d0, s->cg.ok, s->cg.step));
-    // failed CG directions: one more search along -K g (masked to those items)
-    hipLaunchKernelGGL(k_cgB_retry, dim3(ib), dim3(64), 0, stream(s), s->nit, (const double*)s->d_dots, s->cg);
-    DPP_LAUNCHED();
-    DPP_TRY(axpby_all(s, 0, s->cg.cK, s->Kg, s->cg.cD, s->Dd, s->Dd));
+    {
+        // failed CG directions: one more search along -K g (masked to those items)
+        TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
+        hipLaunchKernelGGL(k_cgB_retry_axpby, eg, dim3(256), 0, stream(s), s->d_seg, (const double*)s->d_dots, s->cg,
+                           (const double2*)s->Kg, s->Dd);
+        DPP_LAUNCHED();
+    }
     DPP_TRY(line_mats_B(s, Y, s->cg.retry));
     DPP_TRY(linesearch_B(s, s->cg.retry, s->cg.d0r, s->cg.ok2, s->cg.step2));
-    hipLaunchKernelGGL(k_cgB_finish, dim3(ib), dim3(64), 0, stream(s), s->nit, (const double*)s->d_dots, s->cg);
-    DPP_LAUNCHED();
     {
-        // Y += step D, HY += step HD; history for the next direction
+        // accept the steps; Y += step D, HY += step HD; history for the next direction
         TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
-        hipLaunchKernelGGL(k_cgB_update, dim3(seg_blocks(s, 0), s->nit), dim3(256), 0, stream(s), s->d_seg,
-                           (const double*)s->cg.step, Y, (const double2*)s->Dd, s->HY, (const double2*)s->HD,
-                           (const double2*)s->g, s->gp, s->Dp);
+        hipLaunchKernelGGL(k_cgB_finish_update, eg, dim3(256), 0, stream(s), s->d_seg, (const double*)s->d_dots,
+                           s->cg, Y, (const double2*)s->Dd, s->HY, (const double2*)s->HD, (const double2*)s->g, s->gp,
+                           s->Dp);
         DPP_LAUNCHED();
     }
     DPP_TRY(grad_B(s, Y, true));
@@ -1079,7 +1080,7 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
                  {&s->d_ones, nis}, {&s->d_alpha, nis}, {&s->d_beta, nis}, {&s->d_bE0, nis},
                  {&s->d_cred, cell_red_elems(ncells)}, {&s->d_epart, (size_t)eoff},
                  {&s->cg.at, nis}, {&s->cg.gkg, nis}, {&s->cg.beta, nis}, {&s->cg.d0, nis}, {&s->cg.d0r, nis},
-                 {&s->cg.step, nis}, {&s->cg.step2, nis}, {&s->cg.cK, nis}, {&s->cg.cD, nis},
+                 {&s->cg.step, nis}, {&s->cg.step2, nis}, {&s->cg.stepf, nis}, {&s->cg.cK, nis}, {&s->cg.cD, nis},
                  {&s->Vloc, Nt}, {&s->VH, Nt}, {&s->vxc, Nt}, {&s->Veff, Nt}, {&s->Vx, Nt}, {&s->n, Nt}, {&s->nin, Nt},
                  {&s->nout, Nt}, {&s->hist_n, PULAY_MAX * Nt}, {&s->hist_r, PULAY_MAX * Nt},
                  {&s->pulayA, (size_t)ncells * PULAY_MAX * PULAY_MAX}, {&s->pulayC, (size_t)ncells * PULAY_MAX}};

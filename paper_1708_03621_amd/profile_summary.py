@@ -41,18 +41,37 @@ def _counters(path):
     return d
 
 
+def _full_launch_avg(trace_csv):
+    """Per kernel: mean duration (us) and count of the launches longer than
+    half the kernel's median, i.e. without the launches masked to a few
+    items (line-search retries), which return almost at once."""
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        d[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = {}
+    for k, v in d.items():
+        med = statistics.median(v)
+        full = [x for x in v if x > 0.5 * med]
+        out[k] = (statistics.mean(full), len(full))
+    return out
+
+
 def stats(args):
     rows = list(csv.DictReader(open(args.csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    trace = os.path.join(os.path.dirname(args.csv), os.path.basename(args.csv).replace("kernel_stats", "kernel_trace"))
+    full = _full_launch_avg(trace) if os.path.exists(trace) else {}
     print(f"# Kernel statistics: {args.title}\n")
     print(f"Command: `{args.command}`\n")
-    print(f"Total kernel time {tot / 1e6:.3f} ms.\n")
-    print("| total ms | calls | avg us | % | kernel |\n|---:|---:|---:|---:|---|")
+    print(f"Total kernel time {tot / 1e6:.3f} ms. \"full\" = launches longer than half the kernel's median "
+          f"(launches masked to a few items return almost at once).\n")
+    print("| total ms | calls | avg us | avg us (full) | full calls | % | kernel |\n|---:|---:|---:|---:|---:|---:|---|")
     for r in rows[: args.top]:
         name = r["Name"].split("(")[0]
+        fa, fc = full.get(r["Name"], (float("nan"), 0))
         print(f"| {float(r['TotalDurationNs']) / 1e6:.3f} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
-              f"{float(r['Percentage']):.1f} | `{name}` |")
+              f"{fa:.2f} | {fc} | {float(r['Percentage']):.1f} | `{name}` |")
 
 
 def traffic(args):
