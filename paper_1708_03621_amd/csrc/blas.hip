@@ -1420,14 +1420,18 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// NMAX (16 or 32) bounds n; the per-round block and V loops have the
+// compile-time trip counts of NMAX, so they unroll into one straight-line
+// sequence whose loads the compiler can interleave.
+template <int NMAX>
 __device__ void jacobi_eigh_wave(int n, const double2* __restrict__ Hg, double* __restrict__ ev,
                                  double2* __restrict__ vo) {
-    constexpr int LD = EIGW_MAXN + 1;
-    __shared__ double2 A[EIGW_MAXN * LD];
-    __shared__ double2 Vt[EIGW_MAXN * LD];
-    __shared__ Rot rot[EIGW_MAXN / 2];
-    __shared__ double dg[EIGW_MAXN];
-    __shared__ int perm[EIGW_MAXN];
+    constexpr int LD = NMAX + 1, PMAX = NMAX / 2;
+    __shared__ double2 A[NMAX * LD];
+    __shared__ double2 Vt[NMAX * LD];
+    __shared__ Rot rot[PMAX];
+    __shared__ double dg[NMAX];
+    __shared__ int perm[NMAX];
     const int lane = threadIdx.x;
     const int m = n + (n & 1), P = m / 2;
     for (int e = lane; e < n * n; e += 64) {
@@ -1491,7 +1495,10 @@ __device__ void jacobi_eigh_wave(int n, const double2* __restrict__ Hg, double* 
                 rot[lane] = R;
             }
             __syncthreads();
-            for (int bk = lane; bk < P * P; bk += 64) {
+#pragma unroll
+            for (int u = 0; u < (PMAX * PMAX + 63) / 64; ++u) {
+                const int bk = lane + 64 * u;
+                if (bk >= P * P) continue;
                 const int s2 = bk / P, s1 = bk - s2 * P;
                 if (s2 > s1) continue;
                 const Rot Rc = rot[s1], Rr = rot[s2];
@@ -1542,7 +1549,10 @@ __device__ void jacobi_eigh_wave(int n, const double2* __restrict__ Hg, double* 
                         }
             }
             // V <- V J: columns p, q of V are rows p, q of Vt
-            for (int e = lane; e < P * n; e += 64) {
+#pragma unroll
+            for (int u = 0; u < (PMAX * NMAX + 63) / 64; ++u) {
+                const int e = lane + 64 * u;
+                if (e >= P * n) continue;
                 const int sidx = e / n, r = e - sidx * n;
                 const Rot R = rot[sidx];
                 if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
@@ -1570,17 +1580,30 @@ __device__ void jacobi_eigh_wave(int n, const double2* __restrict__ Hg, double* 
     }
 }
 
+template <int NMAX>
 __global__ void __launch_bounds__(64)
 k_jacobi_eigh_wave(int n, const double2* __restrict__ H, double* __restrict__ eig, double2* __restrict__ vecs) {
     const int64_t b = blockIdx.x;
-    jacobi_eigh_wave(n, H + b * n * n, eig + b * n, vecs + b * n * n);
+    jacobi_eigh_wave<NMAX>(n, H + b * n * n, eig + b * n, vecs + b * n * n);
 }
 
+template <int NMAX>
 __global__ void __launch_bounds__(64)
 k_jacobi_eigh_seg_wave(const Seg* __restrict__ seg, const double2* __restrict__ H, double* __restrict__ eig,
                        double2* __restrict__ vecs) {
     const Seg sg = seg[blockIdx.x];
-    jacobi_eigh_wave(sg.nb, H + sg.moff, eig + sg.f_off, vecs + sg.moff);
+    jacobi_eigh_wave<NMAX>(sg.nb, H + sg.moff, eig + sg.f_off, vecs + sg.moff);
+}
+
+bool eigh_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, const double2* H, double* eig,
+                      double2* vecs) {
+    if (nmax <= 16)
+        hipLaunchKernelGGL(k_jacobi_eigh_seg_wave<16>, dim3(nblk), dim3(64), 0, st, seg, H, eig, vecs);
+    else if (nmax <= 32)
+        hipLaunchKernelGGL(k_jacobi_eigh_seg_wave<32>, dim3(nblk), dim3(64), 0, st, seg, H, eig, vecs);
+    else
+        return false;
+    return true;
 }
 
 __global__ void __launch_bounds__(SM_NT)
@@ -1672,8 +1695,11 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
         DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(ctx, DPP_TK_EIGH);
-    if (nb <= EIGW_MAXN)
-        hipLaunchKernelGGL(k_jacobi_eigh_wave, dim3(batch), dim3(64), 0, ctx->stream, nb, (const double2*)H, eig,
+    if (nb <= 16)
+        hipLaunchKernelGGL(k_jacobi_eigh_wave<16>, dim3(batch), dim3(64), 0, ctx->stream, nb, (const double2*)H, eig,
+                           (double2*)vecs);
+    else if (nb <= EIGW_MAXN)
+        hipLaunchKernelGGL(k_jacobi_eigh_wave<32>, dim3(batch), dim3(64), 0, ctx->stream, nb, (const double2*)H, eig,
                            (double2*)vecs);
     else
         hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(nb > 64 ? SM_NT : 256), lds, ctx->stream, nb,

@@ -107,7 +107,9 @@ bool linesearch_wave_launch(hipStream_t st, unsigned nblk, int n, const Seg* seg
                             const double2* X, const double2* Q, const double2* H0, const double2* H1,
                             const double2* H2, const double* E0v, const double* at0, const double* d0v,
                             const int* act, int* ok, double* step, double2* Xs, double2* Ps);
-__global__ void k_jacobi_eigh_seg_wave(const Seg* seg, const double2* H, double* eig, double2* vecs);
+// Single-wave eigensolver for up to 32 bands (false: larger).
+bool eigh_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, const double2* H, double* eig,
+                      double2* vecs);
 __global__ void k_linesearch_B(const Seg* seg, const double2* U, const double2* X, const double2* Q,
                                const double2* H0, const double2* H1, const double2* H2, const double* E0v,
                                const double* at0, const double* d0v, const int* act, int* ok, double* step,

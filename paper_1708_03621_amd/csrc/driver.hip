@@ -694,10 +694,7 @@ dpp_status subspace_rotate(dpp_system_s* s, double2* Y) {
             DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh_seg),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         TimerScope ts_(s->ctx, DPP_TK_EIGH);
-        if (n <= EIGW_MAXN)
-            hipLaunchKernelGGL(k_jacobi_eigh_seg_wave, dim3(s->nit), dim3(64), 0, stream(s), s->d_seg,
-                               (const double2*)s->H0, s->d_eig, s->vecs);
-        else
+        if (!eigh_wave_launch(stream(s), (unsigned)s->nit, n, s->d_seg, s->H0, s->d_eig, s->vecs))
             hipLaunchKernelGGL(k_jacobi_eigh_seg, dim3(s->nit), dim3(n > 64 ? SM_NT : 256), lds, stream(s), s->d_seg,
                                (const double2*)s->H0, s->d_eig, s->vecs, s->eig_scr);
         DPP_LAUNCHED();
