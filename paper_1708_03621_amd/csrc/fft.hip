@@ -257,7 +257,8 @@ k_xz(const FftItem* items, FftItem single, typename cx<T>::t* __restrict__ Tb,
 }
 
 // Register plane passes for square y-z faces (S1 = S2 = N): one wave per
-// (item, band, plane).  Sphere -> planes: lane r < N owns natural row i1 = r,
+// (item, band, plane), or per two planes when N <= 32 (lanes 0-31 and 32-63
+// each take one, so fewer lanes idle).  Sphere -> planes: lane r < N owns natural row i1 = r,
 // gathers the row's sphere points into registers (each register is one z
 // point), transforms along z (decimation in frequency), and writes the row to
 // LDS; lane c then owns column c (a digit-reversed z point), transforms along
@@ -273,11 +274,16 @@ k_planes_from_sphere_reg(const FftItem* __restrict__ items, const int* __restric
     const int item = idx ? idx[blockIdx.z] : (int)blockIdx.z;
     if (act && !act[item]) return;
     const FftItem& it = items[item];
-    const int p = blockIdx.x, b = blockIdx.y;
-    if (p >= it.nplanes || b >= it.nb) return;
-    __shared__ Cx lds[N * (N + 1)];
-    const int lane = threadIdx.x;
-    if (lane < N) {
+    // faces of up to 32 points: two planes per wave (lanes 0-31 and 32-63)
+    constexpr int PPW = N <= 32 ? 2 : 1;
+    const int sub = PPW == 2 ? (int)(threadIdx.x >> 5) : 0;
+    const int lane = PPW == 2 ? (int)(threadIdx.x & 31) : (int)threadIdx.x;
+    const int p = blockIdx.x * PPW + sub, b = blockIdx.y;
+    if ((int)blockIdx.x * PPW >= it.nplanes || b >= it.nb) return;  // uniform
+    const bool on = p < it.nplanes && lane < N;
+    __shared__ Cx ldsb[PPW][N * (N + 1)];
+    Cx* lds = ldsb[sub];
+    if (on) {
         const int4 rw = it.rows[p * N + lane];
         const double2* src = C + it.c_off + (int64_t)b * it.ld + rw.x;
         Cx x[N];
@@ -292,7 +298,7 @@ k_planes_from_sphere_reg(const FftItem* __restrict__ items, const int* __restric
         for (int c = 0; c < N; ++c) lds[lane * (N + 1) + c] = x[c];
     }
     __syncthreads();
-    if (lane < N) {
+    if (on) {
         Cx x[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) x[r] = lds[r * (N + 1) + lane];
@@ -312,11 +318,15 @@ k_planes_to_sphere_reg(const FftItem* __restrict__ items, const int* __restrict_
     const int item = idx ? idx[blockIdx.z] : (int)blockIdx.z;
     if (act && !act[item]) return;
     const FftItem& it = items[item];
-    const int p = blockIdx.x, b = blockIdx.y;
-    if (p >= it.nplanes || b >= it.nb) return;
-    __shared__ Cx lds[N * (N + 1)];
-    const int lane = threadIdx.x;
-    if (lane < N) {
+    constexpr int PPW = N <= 32 ? 2 : 1;
+    const int sub = PPW == 2 ? (int)(threadIdx.x >> 5) : 0;
+    const int lane = PPW == 2 ? (int)(threadIdx.x & 31) : (int)threadIdx.x;
+    const int p = blockIdx.x * PPW + sub, b = blockIdx.y;
+    if ((int)blockIdx.x * PPW >= it.nplanes || b >= it.nb) return;  // uniform
+    const bool on = p < it.nplanes && lane < N;
+    __shared__ Cx ldsb[PPW][N * (N + 1)];
+    Cx* lds = ldsb[sub];
+    if (on) {
         const Cx* src = Tb + it.t_off + ((int64_t)b * it.nplanes + p) * (N * N) + lane;
         Cx x[N];
 #pragma unroll
@@ -326,7 +336,7 @@ k_planes_to_sphere_reg(const FftItem* __restrict__ items, const int* __restrict_
         for (int r = 0; r < N; ++r) lds[r * (N + 1) + lane] = x[r];
     }
     __syncthreads();
-    if (lane < N) {
+    if (on) {
         const int4 rw = it.rows[p * N + lane];
         if (rw.y > 0) {
             Cx x[N];
@@ -360,6 +370,8 @@ constexpr bool plane_reg_len(int n) {
 template <typename T, int N>
 static void planes_reg_launch_one(bool to_sphere, dim3 grid, hipStream_t st, const FftItem* items, const int* idx,
                                   const double2* X, typename cx<T>::t* Tb, double2* HX, const int* act) {
+    constexpr int PPW = N <= 32 ? 2 : 1;  // planes per wave (kernels above)
+    grid.x = (grid.x + PPW - 1) / PPW;
     if (to_sphere)
         hipLaunchKernelGGL((k_planes_to_sphere_reg<T, N>), grid, dim3(64), 0, st, items, idx,
                            (const typename cx<T>::t*)Tb, X, HX, act);
