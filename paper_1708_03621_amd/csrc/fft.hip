@@ -339,22 +339,33 @@ k_planes_to_sphere_reg(const FftItem* __restrict__ items, const int* __restrict_
     if (on) {
         const int4 rw = it.rows[p * N + lane];
         if (rw.y > 0) {
-            Cx x[N];
+            Cx* row = lds + lane * (N + 1);
+            {
+                Cx x[N];
 #pragma unroll
-            for (int c = 0; c < N; ++c) x[c] = lds[lane * (N + 1) + c];
-            reg_dit<T, N, -1, 0>(x, it.tw64[2], it.tw32[2]);
+                for (int c = 0; c < N; ++c) x[c] = row[c];
+                reg_dit<T, N, -1, 0>(x, it.tw64[2], it.tw32[2]);
+                // back to the lane's own LDS row, so the gather below holds
+                // only a few points in registers at a time
+#pragma unroll
+                for (int c = 0; c < N; ++c) row[c] = x[c];
+            }
             const int64_t o = it.c_off + (int64_t)b * it.ld + rw.x;
             const double* kG2 = it.kG2 + rw.x;
             const double hk = 0.5 * it.omega;
+            // the row's points are contiguous in the sphere: q = 0 .. rw.y - 1
+            // at z index n2 = rw.z + q
+            for (int q0 = 0; q0 < rw.y; q0 += 8) {
 #pragma unroll
-            for (int r2 = 0; r2 < N; ++r2) {
-                const int n2 = 2 * r2 < N ? r2 : r2 - N;
-                const int q = n2 - rw.z;
-                if (q >= 0 && q < rw.y) {
-                    const double2 c = Cin[o + q];
-                    const double2 v = Io<T>::to_d(x[r2]);
-                    const double t = hk * kG2[q];
-                    out[o + q] = double2{t * c.x + v.x, t * c.y + v.y};
+                for (int u = 0; u < 8; ++u) {
+                    const int q = q0 + u;
+                    if (q < rw.y) {
+                        const int n2 = rw.z + q;
+                        const double2 c = Cin[o + q];
+                        const double2 v = Io<T>::to_d(row[n2 < 0 ? n2 + N : n2]);
+                        const double t = hk * kG2[q];
+                        out[o + q] = double2{t * c.x + v.x, t * c.y + v.y};
+                    }
                 }
             }
         }
