@@ -45,12 +45,12 @@ __device__ __forceinline__ double2 gld(const double2* p) {
 // and never stored.
 template <int TA, int TB, int NW, bool FULL>
 __device__ __forceinline__ void ov_block(const OvTask& T, double2* __restrict__ part,
-                                         double (*red)[2][4][64]) {
-    const int chunk = FULL ? 0 : (int)blockIdx.x;
+                                         double (*red)[2][4][64], int chunk_in, int blk) {
+    const int chunk = FULL ? 0 : chunk_in;
     const int tilesA = (T.nbA + 15) / 16;
     const int sB = (T.tilesB + TB - 1) / TB, sA = (tilesA + TA - 1) / TA;
-    if ((int)blockIdx.y >= sA * sB) return;
-    const int ti0 = ((int)blockIdx.y / sB) * TA, tj0 = ((int)blockIdx.y % sB) * TB;
+    if (blk >= sA * sB) return;
+    const int ti0 = (blk / sB) * TA, tj0 = (blk % sB) * TB;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 15, ks = lane >> 4;
     const double2* Ap[TA];
@@ -160,24 +160,33 @@ constexpr int OVF_WAVES = 8;
 template <bool WIDE, bool FULL>
 __global__ void __launch_bounds__(64 * (FULL ? OVF_WAVES : OV_WAVES))
 k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part,
-               const int* __restrict__ act) {
+               const int* __restrict__ act, const int4* __restrict__ work) {
     constexpr int NW = FULL ? OVF_WAVES : OV_WAVES;
     __shared__ double red[NW][2][4][64];
-    const OvTask T = tasks ? tasks[blockIdx.z] : single;
+    // a work list (task, chunk, block) covers only the workgroups that have
+    // work; without one the grid is (chunk, block, task)
+    int ti, chunk, blk;
+    if (work) {
+        const int4 w = work[blockIdx.x];
+        ti = w.x, chunk = w.y, blk = w.z;
+    } else {
+        ti = (int)blockIdx.z, chunk = (int)blockIdx.x, blk = (int)blockIdx.y;
+    }
+    const OvTask T = tasks ? tasks[ti] : single;
     if (act && !act[T.item]) return;
-    if (!FULL && (int)blockIdx.x >= T.nchunk) return;
+    if (!FULL && chunk >= T.nchunk) return;
     if constexpr (WIDE) {
         const int tA = (T.nbA + 15) / 16, tB = T.tilesB;
         if (tA >= 2 && tB >= 2)
-            ov_block<2, 2, NW, FULL>(T, part, red);
+            ov_block<2, 2, NW, FULL>(T, part, red, chunk, blk);
         else if (tB >= 2)
-            ov_block<1, 2, NW, FULL>(T, part, red);
+            ov_block<1, 2, NW, FULL>(T, part, red, chunk, blk);
         else if (tA >= 2)
-            ov_block<2, 1, NW, FULL>(T, part, red);
+            ov_block<2, 1, NW, FULL>(T, part, red, chunk, blk);
         else
-            ov_block<1, 1, NW, FULL>(T, part, red);
+            ov_block<1, 1, NW, FULL>(T, part, red, chunk, blk);
     } else {
-        ov_block<1, 1, NW, FULL>(T, part, red);
+        ov_block<1, 1, NW, FULL>(T, part, red, chunk, blk);
     }
 }
 
@@ -192,22 +201,35 @@ static int ov_task_blocks(int tA, int tB) {
 // nblk: the largest ov_task_blocks over the tasks; wide: some task has more
 // than one tile.
 static void overlap_launch(dpp_ctx ctx, const OvTask* d_tasks, const OvTask& single, unsigned ntasks, int nchunk,
-                           int nblk, bool wide, double2* part, const int* act, bool full = false) {
+                           int nblk, bool wide, double2* part, const int* act, bool full = false,
+                           const int4* work = nullptr, int nwork = 0) {
+    const dim3 grid = work ? dim3((unsigned)nwork, 1, 1) : dim3(full ? 1 : nchunk, nblk, ntasks);
     if (full) {
         if (wide)
-            hipLaunchKernelGGL((k_overlap_mfma<true, true>), dim3(1, nblk, ntasks), dim3(64 * OVF_WAVES), 0,
-                               ctx->stream, d_tasks, single, part, act);
+            hipLaunchKernelGGL((k_overlap_mfma<true, true>), grid, dim3(64 * OVF_WAVES), 0, ctx->stream, d_tasks,
+                               single, part, act, work);
         else
-            hipLaunchKernelGGL((k_overlap_mfma<false, true>), dim3(1, nblk, ntasks), dim3(64 * OVF_WAVES), 0,
-                               ctx->stream, d_tasks, single, part, act);
+            hipLaunchKernelGGL((k_overlap_mfma<false, true>), grid, dim3(64 * OVF_WAVES), 0, ctx->stream, d_tasks,
+                               single, part, act, work);
         return;
     }
     if (wide)
-        hipLaunchKernelGGL((k_overlap_mfma<true, false>), dim3(nchunk, nblk, ntasks), dim3(64 * OV_WAVES), 0,
-                           ctx->stream, d_tasks, single, part, act);
+        hipLaunchKernelGGL((k_overlap_mfma<true, false>), grid, dim3(64 * OV_WAVES), 0, ctx->stream, d_tasks, single,
+                           part, act, work);
     else
-        hipLaunchKernelGGL((k_overlap_mfma<false, false>), dim3(nchunk, nblk, ntasks), dim3(64 * OV_WAVES), 0,
-                           ctx->stream, d_tasks, single, part, act);
+        hipLaunchKernelGGL((k_overlap_mfma<false, false>), grid, dim3(64 * OV_WAVES), 0, ctx->stream, d_tasks,
+                           single, part, act, work);
+}
+
+void overlap_worklist(const std::vector<OvTask>& h, int ov_mode, std::vector<int4>& w) {
+    w.clear();
+    for (size_t i = 0; i < h.size(); ++i) {
+        const OvTask& t = h[i];
+        const int nch = ov_mode == 2 ? 1 : t.nchunk;
+        const int nb = ov_mode == 1 ? t.ntiles : ov_task_blocks((t.nbA + 15) / 16, t.tilesB);
+        for (int c = 0; c < nch; ++c)
+            for (int b = 0; b < nb; ++b) w.push_back(int4{(int)i, c, b, 0});
+    }
 }
 
 __global__ void k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part,
@@ -280,7 +302,7 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
 // Batched: the caller has set part_off of every task (disjoint partial areas)
 // and copied the table to d_tasks.
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
-                         const int* act, int ov_mode) {
+                         const int* act, int ov_mode, const int4* d_work, int nwork) {
     const int ov_narrow = ov_mode == 1;
     const bool full = ov_mode == 2;
     if (h.empty()) return DPP_OK;
@@ -296,7 +318,8 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
     if (mt > 65535 || h.size() > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: batch too large");
     {
         TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_OVERLAP, act ? 0.0 : by, act ? 0.0 : fl);
-        overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act, full);
+        overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act, full,
+                       d_work, nwork);
         DPP_LAUNCHED();
     }
     if (full) return DPP_OK;

@@ -292,6 +292,16 @@ struct OvJob {
     double2* out;       // item matrices at moff
 };
 
+// Overlap launch over a task table with its work list (only the workgroups
+// that have work are launched).
+dpp_status overlap_run(dpp_system_s* s, const std::vector<OvTask>& t, const OvTask* d, const int* act) {
+    std::vector<int4> w;
+    overlap_worklist(t, s->ov_mode, w);
+    const int4* dw = nullptr;
+    DPP_TRY(table_t(s, w, &dw));
+    return overlap_tasks(s->ctx, t, d, s->ov_part, act, s->ov_mode, dw, (int)w.size());
+}
+
 // Several A^dag B contractions over every item in one launch (nbo bands).
 dpp_status overlap_jobs(dpp_system_s* s, int nbo, const std::vector<OvJob>& jobs, const int* act = nullptr) {
     std::vector<OvTask> t;
@@ -309,7 +319,7 @@ dpp_status overlap_jobs(dpp_system_s* s, int nbo, const std::vector<OvJob>& jobs
     if ((size_t)poff > s->ov_part_elems) return set_error(DPP_EUNSUPPORTED, "overlap partial buffer too small");
     const OvTask* d = nullptr;
     DPP_TRY(table_t(s, t, &d));
-    return overlap_tasks(s->ctx, t, d, s->ov_part, act, s->ov_mode);
+    return overlap_run(s, t, d, act);
 }
 
 struct RotJob {
@@ -382,7 +392,7 @@ dpp_status apply_H_all(dpp_system_s* s, int nbo, const double2* X, double2* HX, 
         if ((size_t)poff > s->ov_part_elems) return set_error(DPP_EUNSUPPORTED, "overlap partial buffer too small");
         const OvTask* dt = nullptr;
         DPP_TRY(table_t(s, t, &dt));
-        DPP_TRY(overlap_tasks(s->ctx, t, dt, s->ov_part, act, s->ov_mode));
+        DPP_TRY(overlap_run(s, t, dt, act));
         const RotTask* dr = nullptr;
         DPP_TRY(table_t(s, r, &dr));
         DPP_TRY(rotate_tasks(s->ctx, r, dr, act, s->rot_pt));
@@ -408,7 +418,7 @@ dpp_status proj_overlaps(dpp_system_s* s, int nbo, const double2* X) {
     if (t.empty()) return DPP_OK;
     const OvTask* dt = nullptr;
     DPP_TRY(table_t(s, t, &dt));
-    return overlap_tasks(s->ctx, t, dt, s->ov_part, nullptr, s->ov_mode);
+    return overlap_run(s, t, dt, nullptr);
 }
 
 // n = sum_k w_k sum_i f_ki |I psi_ki|^2 per cell over nbo bands (fillings at d_f).

@@ -296,7 +296,10 @@ RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, 
 // rot_pt = 1, 2 or 4 fixes the point tiles per rotate wave for outputs of up
 // to 32 bands (0: by the launch size).
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
-                         const int* act = nullptr, int ov_mode = 0);
+                         const int* act = nullptr, int ov_mode = 0, const int4* d_work = nullptr, int nwork = 0);
+// The (task, chunk, block) workgroups with work of a task table in launch
+// mode ov_mode, for the work-list form of the overlap launch.
+void overlap_worklist(const std::vector<OvTask>& h, int ov_mode, std::vector<int4>& w);
 dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks,
                         const int* act = nullptr, int rot_pt = 0);
 dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
