@@ -338,11 +338,14 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
 // take PT > 1 when the batch still gives every CU many waves.
 template <int PT, int JT>
 __global__ void __launch_bounds__(64 * RT_WAVES)
-k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const int* __restrict__ act) {
-    const RotTask T = tasks ? tasks[blockIdx.y] : single;
+k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const int* __restrict__ act,
+              const int2* __restrict__ work) {
+    // a work list (task, block) covers only the workgroups with points
+    const int2 wk = work ? work[blockIdx.x] : int2{(int)blockIdx.y, (int)blockIdx.x};
+    const RotTask T = tasks ? tasks[wk.x] : single;
     if (act && !act[T.item]) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int gt = (blockIdx.x * RT_WAVES + w) * PT;
+    const int gt = (wk.y * RT_WAVES + w) * PT;
     if (gt * 16 >= T.npw) return;
     const int njt = min(JT, (T.nbO + 15) / 16 - jt0);
     if (njt <= 0) return;
@@ -450,39 +453,70 @@ static double rot_bytes(const RotTask& t) {
 
 template <int PT, int JT>
 static void rotate_go(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single, unsigned ntasks, int ntile,
-                      int jt0, const int* act) {
+                      int jt0, const int* act, const int2* work, int nwork) {
     const int nblk = (ntile + RT_WAVES * PT - 1) / (RT_WAVES * PT);
-    hipLaunchKernelGGL((k_rotate_mfma<PT, JT>), dim3(nblk, ntasks), dim3(64 * RT_WAVES), 0, ctx->stream, d_tasks,
-                       single, jt0, act);
+    const dim3 grid = work ? dim3((unsigned)nwork) : dim3(nblk, ntasks);
+    hipLaunchKernelGGL((k_rotate_mfma<PT, JT>), grid, dim3(64 * RT_WAVES), 0, ctx->stream, d_tasks, single, jt0, act,
+                       work);
 }
 
 // Launch the rotate kernel shape for the widest output of a batch; tiles =
 // point tiles summed over the tasks.  Several point tiles per wave only while
 // the launch keeps at least RT_MIN_WAVES waves.
 constexpr int64_t RT_MIN_WAVES = 4096;
+// Point tiles per wave for outputs of jtiles 16-band tiles and `tiles` point
+// tiles in all (rot_pt > 0 fixes it where the shape allows).
+static int rotate_pt_rule(int jtiles, int64_t tiles, int rot_pt) {
+    if (jtiles == 1) return rot_pt ? rot_pt : (tiles >= 4 * RT_MIN_WAVES ? 4 : tiles >= 2 * RT_MIN_WAVES ? 2 : 1);
+    if (jtiles == 2) return (rot_pt ? rot_pt : (tiles >= 2 * RT_MIN_WAVES ? 2 : 1)) >= 2 ? 2 : 1;
+    return 1;
+}
+
 static dpp_status rotate_launch(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single, unsigned ntasks,
-                                int maxnpw, int maxnbO, int64_t tiles, const int* act, int rot_pt = 0) {
+                                int maxnpw, int maxnbO, int64_t tiles, const int* act, int rot_pt = 0,
+                                const int2* work = nullptr, int nwork = 0) {
     const int ntile = (maxnpw + 15) / 16;
     const int jtiles = (maxnbO + 15) / 16;
+    const int pt = rotate_pt_rule(jtiles, tiles, rot_pt);
     if (jtiles == 1) {
-        const int pt = rot_pt ? rot_pt : (tiles >= 4 * RT_MIN_WAVES ? 4 : tiles >= 2 * RT_MIN_WAVES ? 2 : 1);
         if (pt == 4)
-            rotate_go<4, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+            rotate_go<4, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
         else if (pt == 2)
-            rotate_go<2, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+            rotate_go<2, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
         else
-            rotate_go<1, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+            rotate_go<1, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
     } else if (jtiles == 2) {
-        const int pt = rot_pt ? rot_pt : (tiles >= 2 * RT_MIN_WAVES ? 2 : 1);
-        if (pt >= 2)
-            rotate_go<2, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+        if (pt == 2)
+            rotate_go<2, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
         else
-            rotate_go<1, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act);
+            rotate_go<1, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
     } else {
-        for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT) rotate_go<1, RT_JT>(ctx, d_tasks, single, ntasks, ntile, jt0, act);
+        for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT)
+            rotate_go<1, RT_JT>(ctx, d_tasks, single, ntasks, ntile, jt0, act, work, nwork);
     }
     DPP_LAUNCHED();
     return DPP_OK;
+}
+
+static void rotate_shape(const std::vector<RotTask>& h, int& mp, int& mj, int64_t& tiles) {
+    mp = 1, mj = 1, tiles = 0;
+    for (const RotTask& t : h) {
+        mp = std::max(mp, t.npw);
+        mj = std::max(mj, (t.nbO + 15) / 16);
+        tiles += (t.npw + 15) / 16;
+    }
+}
+
+void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2>& w) {
+    int mp, mj;
+    int64_t tiles;
+    rotate_shape(h, mp, mj, tiles);
+    const int pt = rotate_pt_rule(mj, tiles, rot_pt);
+    w.clear();
+    for (size_t i = 0; i < h.size(); ++i) {
+        const int nblk = ((h[i].npw + 15) / 16 + RT_WAVES * pt - 1) / (RT_WAVES * pt);
+        for (int b = 0; b < nblk; ++b) w.push_back(int2{(int)i, b});
+    }
 }
 
 dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
@@ -493,7 +527,7 @@ dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t l
 }
 
 dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks, const int* act,
-                        int rot_pt) {
+                        int rot_pt, const int2* d_work, int nwork) {
     if (h.empty()) return DPP_OK;
     int mp = 1, mj = 1;
     int64_t tiles = 0;
@@ -506,7 +540,7 @@ dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTas
         fl += 8.0 * t.npw * (t.nbX + t.nbX2) * (double)t.nbO;
     }
     TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_ROTATE, act ? 0.0 : by, act ? 0.0 : fl);
-    return rotate_launch(ctx, d_tasks, RotTask{}, (unsigned)h.size(), mp, mj * 16, tiles, act, rot_pt);
+    return rotate_launch(ctx, d_tasks, RotTask{}, (unsigned)h.size(), mp, mj * 16, tiles, act, rot_pt, d_work, nwork);
 }
 
 // ------------------------------------------------- small-matrix products ---

@@ -302,6 +302,14 @@ dpp_status overlap_run(dpp_system_s* s, const std::vector<OvTask>& t, const OvTa
     return overlap_tasks(s->ctx, t, d, s->ov_part, act, s->ov_mode, dw, (int)w.size());
 }
 
+dpp_status rotate_run(dpp_system_s* s, const std::vector<RotTask>& t, const RotTask* d, const int* act) {
+    std::vector<int2> w;
+    rotate_worklist(t, s->rot_pt, w);
+    const int2* dw = nullptr;
+    DPP_TRY(table_t(s, w, &dw));
+    return rotate_tasks(s->ctx, t, d, act, s->rot_pt, dw, (int)w.size());
+}
+
 // Several A^dag B contractions over every item in one launch (nbo bands).
 dpp_status overlap_jobs(dpp_system_s* s, int nbo, const std::vector<OvJob>& jobs, const int* act = nullptr) {
     std::vector<OvTask> t;
@@ -348,7 +356,7 @@ dpp_status rotate_jobs(dpp_system_s* s, int nbo, const std::vector<RotJob>& jobs
         }
     const RotTask* d = nullptr;
     DPP_TRY(table_t(s, t, &d));
-    return rotate_tasks(s->ctx, t, d, act, s->rot_pt);
+    return rotate_run(s, t, d, act);
 }
 
 // HX = H X for nbo bands of every item: batched FFT passes at each cell's
@@ -395,7 +403,7 @@ dpp_status apply_H_all(dpp_system_s* s, int nbo, const double2* X, double2* HX, 
         DPP_TRY(overlap_run(s, t, dt, act));
         const RotTask* dr = nullptr;
         DPP_TRY(table_t(s, r, &dr));
-        DPP_TRY(rotate_tasks(s->ctx, r, dr, act, s->rot_pt));
+        DPP_TRY(rotate_run(s, r, dr, act));
     }
     return DPP_OK;
 }

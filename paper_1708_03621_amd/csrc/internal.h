@@ -301,7 +301,10 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
 // mode ov_mode, for the work-list form of the overlap launch.
 void overlap_worklist(const std::vector<OvTask>& h, int ov_mode, std::vector<int4>& w);
 dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks,
-                        const int* act = nullptr, int rot_pt = 0);
+                        const int* act = nullptr, int rot_pt = 0, const int2* d_work = nullptr, int nwork = 0);
+// The (task, block) workgroups with points of a rotate task table for the
+// launch shape rot_pt picks, for the work-list form of the launch.
+void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2>& w);
 dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
                        const double2* B, int64_t ldB, double scale, double2* U, void* ws,
                        size_t ws_bytes);
