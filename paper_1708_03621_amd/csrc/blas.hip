@@ -1477,20 +1477,51 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Index pair of a slot in a round of the round-robin ordering over m
+// (even) indices: slot 0 pairs m - 1 with the round, slot s pairs round + s
+// with round - s (mod m - 1); returned with p < q.
+__device__ __forceinline__ void jacobi_pair(int round, int slot, int m, int& p, int& q) {
+    int a, b;
+    if (slot == 0) {
+        a = m - 1;
+        b = round;
+    } else {
+        a = round + slot;
+        a -= a >= m - 1 ? m - 1 : 0;
+        b = round - slot;
+        b += b < 0 ? m - 1 : 0;
+    }
+    p = min(a, b);
+    q = max(a, b);
+}
+
+struct RotW {
+    double cs, sn, er, ei;  // e^{-i phi} = er + i ei
+};
+
 // NMAX (16 or 32) bounds n; the per-round block and V loops have the
 // compile-time trip counts of NMAX, so they unroll into one straight-line
-// sequence whose loads the compiler can interleave.
+// sequence whose loads the compiler can interleave.  Every lane takes the
+// indices of its pairs from the round number, so its A and V loads do not
+// wait for the rotations, and the identity rotation (pairs at rounding level,
+// the padding index of odd n) is applied as an exact no-op instead of a
+// branch; A and V are zero outside n x n so that padding stays finite.
 template <int NMAX>
 __device__ void jacobi_eigh_wave(int n, const double2* __restrict__ Hg, double* __restrict__ ev,
                                  double2* __restrict__ vo) {
     constexpr int LD = NMAX + 1, PMAX = NMAX / 2;
     __shared__ double2 A[NMAX * LD];
     __shared__ double2 Vt[NMAX * LD];
-    __shared__ Rot rot[PMAX];
+    __shared__ RotW rot[PMAX];
     __shared__ double dg[NMAX];
     __shared__ int perm[NMAX];
     const int lane = threadIdx.x;
     const int m = n + (n & 1), P = m / 2;
+    for (int e = lane; e < NMAX * LD; e += 64) {
+        A[e] = double2{0.0, 0.0};
+        Vt[e] = double2{0.0, 0.0};
+    }
+    __syncthreads();
     for (int e = lane; e < n * n; e += 64) {
         const int r = e / n, c = e - r * n;
         double2 h = c >= r ? Hg[r * n + c] : Hg[c * n + r];
@@ -1519,104 +1550,85 @@ __device__ void jacobi_eigh_wave(int n, const double2* __restrict__ Hg, double* 
         for (int round = 0; round < m - 1; ++round) {
             if (lane < P) {
                 int p, q;
-                if (lane == 0) {
-                    p = m - 1;
-                    q = round;
-                } else {
-                    p = round + lane;
-                    p -= p >= m - 1 ? m - 1 : 0;
-                    q = round - lane;
-                    q += q < 0 ? m - 1 : 0;
-                }
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                Rot R{p, q, 1.0, 0.0, 1.0, 0.0};
-                if (q < n) {
-                    const double2 c = A[p * LD + q];
-                    const double ac2 = c.x * c.x + c.y * c.y;
-                    if (ac2 > skip2 && ac2 > 1e-300) {
-                        const double ri = rsqrt(ac2);  // 1 / |a_pq|
-                        const double tau = 0.5 * (A[q * LD + q].x - A[p * LD + p].x) * ri;
-                        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        R.cs = rsqrt(1.0 + t * t);
-                        R.sn = t * R.cs;
-                        R.er = c.x * ri;
-                        R.ei = -c.y * ri;
-                    }
-                } else {
-                    R.q = -1;  // paired with the dummy index: no rotation
+                jacobi_pair(round, lane, m, p, q);
+                const double2 c = A[p * LD + q];
+                const double app = A[p * LD + p].x, aqq = A[q * LD + q].x;
+                const double ac2 = c.x * c.x + c.y * c.y;
+                RotW R{1.0, 0.0, 1.0, 0.0};
+                if (q < n && ac2 > skip2 && ac2 > 1e-300) {
+                    const double ri = rsqrt(ac2);  // 1 / |a_pq|
+                    const double tau = 0.5 * (aqq - app) * ri;
+                    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    R.cs = rsqrt(1.0 + t * t);
+                    R.sn = t * R.cs;
+                    R.er = c.x * ri;
+                    R.ei = -c.y * ri;
                 }
                 rot[lane] = R;
             }
             __syncthreads();
+            // A <- J^H A J on the 2 x 2 blocks (row pair s2 <= column pair s1)
 #pragma unroll
             for (int u = 0; u < (PMAX * PMAX + 63) / 64; ++u) {
                 const int bk = lane + 64 * u;
-                if (bk >= P * P) continue;
-                const int s2 = bk / P, s1 = bk - s2 * P;
-                if (s2 > s1) continue;
-                const Rot Rc = rot[s1], Rr = rot[s2];
-                const bool idc = Rc.q < 0 || (Rc.sn == 0.0 && Rc.er == 1.0 && Rc.ei == 0.0);
-                const bool idr = Rr.q < 0 || (Rr.sn == 0.0 && Rr.er == 1.0 && Rr.ei == 0.0);
-                if (idc && idr) continue;
-                const int xr[2] = {Rr.p, Rr.q}, yc[2] = {Rc.p, Rc.q};
+                const int s2 = bk / PMAX, s1 = bk - s2 * PMAX;
+                if (s2 >= P || s1 >= P || s2 > s1) continue;
+                int p2, q2, p1, q1;
+                jacobi_pair(round, s2, m, p2, q2);
+                jacobi_pair(round, s1, m, p1, q1);
                 double2 B[2][2];
+                B[0][0] = A[p2 * LD + p1];
+                B[0][1] = A[p2 * LD + q1];
+                B[1][0] = A[q2 * LD + p1];
+                B[1][1] = A[q2 * LD + q1];
+                const RotW Rc = rot[s1], Rr = rot[s2];
+                // columns: new_p = cs b_p - sn e b_q ; new_q = sn b_p + cs e b_q
+                const double2 e2 = double2{Rc.er, Rc.ei};
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        B[i][j] = (xr[i] >= 0 && yc[j] >= 0) ? A[xr[i] * LD + yc[j]] : double2{0, 0};
-                if (!idc) {
-                    const double2 e2 = double2{Rc.er, Rc.ei};
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        const double2 bp = B[i][0], ebq = cmulz(e2, B[i][1]);
-                        B[i][0] = double2{Rc.cs * bp.x - Rc.sn * ebq.x, Rc.cs * bp.y - Rc.sn * ebq.y};
-                        B[i][1] = double2{Rc.sn * bp.x + Rc.cs * ebq.x, Rc.sn * bp.y + Rc.cs * ebq.y};
-                    }
+                for (int i = 0; i < 2; ++i) {
+                    const double2 bp = B[i][0], ebq = cmulz(e2, B[i][1]);
+                    B[i][0] = double2{Rc.cs * bp.x - Rc.sn * ebq.x, Rc.cs * bp.y - Rc.sn * ebq.y};
+                    B[i][1] = double2{Rc.sn * bp.x + Rc.cs * ebq.x, Rc.sn * bp.y + Rc.cs * ebq.y};
                 }
-                if (!idr) {
-                    const double2 ce = double2{Rr.er, -Rr.ei};
+                // rows: new_p = cs b_p - sn conj(e) b_q ; new_q = sn b_p + cs conj(e) b_q
+                const double2 ce = double2{Rr.er, -Rr.ei};
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const double2 bp = B[0][j], ebq = cmulz(ce, B[1][j]);
-                        B[0][j] = double2{Rr.cs * bp.x - Rr.sn * ebq.x, Rr.cs * bp.y - Rr.sn * ebq.y};
-                        B[1][j] = double2{Rr.sn * bp.x + Rr.cs * ebq.x, Rr.sn * bp.y + Rr.cs * ebq.y};
-                    }
+                for (int j = 0; j < 2; ++j) {
+                    const double2 bp = B[0][j], ebq = cmulz(ce, B[1][j]);
+                    B[0][j] = double2{Rr.cs * bp.x - Rr.sn * ebq.x, Rr.cs * bp.y - Rr.sn * ebq.y};
+                    B[1][j] = double2{Rr.sn * bp.x + Rr.cs * ebq.x, Rr.sn * bp.y + Rr.cs * ebq.y};
                 }
                 if (s1 == s2) {
-                    // the rotated pair becomes diagonal with a real diagonal
-                    const int p = Rc.p, q = Rc.q;
-                    A[p * LD + p] = double2{B[0][0].x, 0.0};
-                    A[q * LD + q] = double2{B[1][1].x, 0.0};
-                    A[p * LD + q] = double2{0.0, 0.0};
-                    A[q * LD + p] = double2{0.0, 0.0};
-                    continue;
+                    // a rotated pair becomes diagonal with a real diagonal
+                    const bool rotd = Rc.sn != 0.0 || Rc.er != 1.0 || Rc.ei != 0.0;
+                    A[p1 * LD + p1] = rotd ? double2{B[0][0].x, 0.0} : B[0][0];
+                    A[q1 * LD + q1] = rotd ? double2{B[1][1].x, 0.0} : B[1][1];
+                    A[p1 * LD + q1] = rotd ? double2{0.0, 0.0} : B[0][1];
+                    A[q1 * LD + p1] = rotd ? double2{0.0, 0.0} : B[1][0];
+                } else {
+                    A[p2 * LD + p1] = B[0][0];
+                    A[p1 * LD + p2] = double2{B[0][0].x, -B[0][0].y};
+                    A[p2 * LD + q1] = B[0][1];
+                    A[q1 * LD + p2] = double2{B[0][1].x, -B[0][1].y};
+                    A[q2 * LD + p1] = B[1][0];
+                    A[p1 * LD + q2] = double2{B[1][0].x, -B[1][0].y};
+                    A[q2 * LD + q1] = B[1][1];
+                    A[q1 * LD + q2] = double2{B[1][1].x, -B[1][1].y};
                 }
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        if (xr[i] >= 0 && yc[j] >= 0) {
-                            A[xr[i] * LD + yc[j]] = B[i][j];
-                            A[yc[j] * LD + xr[i]] = double2{B[i][j].x, -B[i][j].y};
-                        }
             }
             // V <- V J: columns p, q of V are rows p, q of Vt
 #pragma unroll
             for (int u = 0; u < (PMAX * NMAX + 63) / 64; ++u) {
                 const int e = lane + 64 * u;
-                if (e >= P * n) continue;
-                const int sidx = e / n, r = e - sidx * n;
-                const Rot R = rot[sidx];
-                if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
-                const double2 e2 = double2{R.er, R.ei};
-                const double2 vp = Vt[R.p * LD + r], eq = cmulz(e2, Vt[R.q * LD + r]);
-                Vt[R.p * LD + r] = double2{R.cs * vp.x - R.sn * eq.x, R.cs * vp.y - R.sn * eq.y};
-                Vt[R.q * LD + r] = double2{R.sn * vp.x + R.cs * eq.x, R.sn * vp.y + R.cs * eq.y};
+                const int sidx = e / NMAX, r = e - sidx * NMAX;
+                if (sidx >= P || r >= n) continue;
+                int p, q;
+                jacobi_pair(round, sidx, m, p, q);
+                const double2 vp = Vt[p * LD + r], vq = Vt[q * LD + r];
+                const RotW R = rot[sidx];
+                const double2 eq = cmulz(double2{R.er, R.ei}, vq);
+                Vt[p * LD + r] = double2{R.cs * vp.x - R.sn * eq.x, R.cs * vp.y - R.sn * eq.y};
+                Vt[q * LD + r] = double2{R.sn * vp.x + R.cs * eq.x, R.sn * vp.y + R.cs * eq.y};
             }
             __syncthreads();
         }
