@@ -138,6 +138,7 @@ struct dpp_system_s {
     std::vector<ScfGraph> graphs;
     // pinned staging ring for small host -> device uploads (protocol V)
     double* h_ring = nullptr;
+    double* h_rep = nullptr;  // pinned: energies, residuals, eigenvalues of an SCF iteration
     int ring_slot = 0, ring_slots = 64;
     size_t ring_len = 256;
     std::vector<void*> allocs;
@@ -1152,6 +1153,11 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
         s->h_ring = nullptr;
         return fail(set_error(DPP_ENOMEM, "dpp_batch_create: pinned staging allocation failed"));
     }
+    if (hipHostMalloc((void**)&s->h_rep, ((size_t)ncells * E_STRIDE + 2 * (size_t)s->nstates) * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+        s->h_rep = nullptr;
+        return fail(set_error(DPP_ENOMEM, "dpp_batch_create: pinned report allocation failed"));
+    }
     if (hipMemcpy(s->d_seg, s->h_seg.data(), nis * sizeof(Seg), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s->d_cells, s->h_cells.data(), ncells * sizeof(CellDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s->d_box, s->h_box.data(), ncells * sizeof(FftItem), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1191,6 +1197,7 @@ extern "C" dpp_status dpp_system_destroy(dpp_system s) {
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     for (void* p : s->allocs) (void)hipFree(p);
     if (s->h_ring) (void)hipHostFree(s->h_ring);
+    if (s->h_rep) (void)hipHostFree(s->h_rep);
     for (dpp_ham h : s->hams) dpp_ham_destroy(h);
     for (dpp_basis b : s->bases) dpp_basis_destroy(b);
     for (CellHost& c : s->cells)
@@ -1363,12 +1370,18 @@ extern "C" dpp_status dpp_scf_iteration(dpp_system s, dpp_c64* Yc, dpp_energy* E
     } else {
         DPP_TRY(scf_body(s, Y, steps));
     }
-    // report: energies, residuals, eigenvalues
-    std::vector<double> e((size_t)s->ncells * E_STRIDE), res((size_t)s->nstates);
-    DPP_HIP(hipMemcpyAsync(e.data(), s->d_E, e.size() * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
-    DPP_HIP(hipMemcpyAsync(res.data(), s->d_res, res.size() * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
-    if (eig) DPP_HIP(hipMemcpyAsync(eig, s->d_eig, s->nstates * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
+    // report: energies, residuals, eigenvalues (through pinned memory, so the
+    // three copies are queued behind the iteration without host staging)
+    const size_t ne = (size_t)s->ncells * E_STRIDE;
+    const double* e = s->h_rep;
+    const double* res = s->h_rep + ne;
+    DPP_HIP(hipMemcpyAsync(s->h_rep, s->d_E, ne * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
+    DPP_HIP(hipMemcpyAsync(s->h_rep + ne, s->d_res, s->nstates * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
+    if (eig)
+        DPP_HIP(hipMemcpyAsync(s->h_rep + ne + s->nstates, s->d_eig, s->nstates * sizeof(double),
+                               hipMemcpyDeviceToHost, stream(s)));
     DPP_HIP(hipStreamSynchronize(stream(s)));
+    if (eig) std::memcpy(eig, s->h_rep + ne + s->nstates, s->nstates * sizeof(double));
     s->cell_res.assign(s->ncells, 0.0);
     double rmax = 0.0;
     for (int c = 0; c < s->ncells; ++c) {
@@ -1380,7 +1393,7 @@ extern "C" dpp_status dpp_scf_iteration(dpp_system s, dpp_c64* Yc, dpp_energy* E
         s->cell_res[c] = r;
         rmax = std::max(rmax, r);
         if (E) {
-            const double* p = e.data() + (size_t)c * E_STRIDE;
+            const double* p = e + (size_t)c * E_STRIDE;
             E[c] = dpp_energy{p[EK] + p[ENL] + p[EH] + p[EXC] + p[ELOC], p[EK], p[ENL], p[ELOC], p[EH], p[EXC]};
         }
     }
