@@ -596,6 +596,7 @@ static bool xz_reg_launch(int S0, dim3 grid, hipStream_t st, const FftItem* item
         DPP_XZ_REG(12) DPP_XZ_REG(15) DPP_XZ_REG(16) DPP_XZ_REG(18) DPP_XZ_REG(20) DPP_XZ_REG(24)
         DPP_XZ_REG(25) DPP_XZ_REG(27) DPP_XZ_REG(30) DPP_XZ_REG(32) DPP_XZ_REG(36) DPP_XZ_REG(40)
         DPP_XZ_REG(45) DPP_XZ_REG(48) DPP_XZ_REG(50) DPP_XZ_REG(54) DPP_XZ_REG(60) DPP_XZ_REG(64)
+        DPP_XZ_REG(90)
 #undef DPP_XZ_REG
         default:
             return false;
@@ -611,6 +612,7 @@ static bool xz_available_t(int S0, int v) {
         DPP_XZ_AV(12) DPP_XZ_AV(15) DPP_XZ_AV(16) DPP_XZ_AV(18) DPP_XZ_AV(20) DPP_XZ_AV(24)
         DPP_XZ_AV(25) DPP_XZ_AV(27) DPP_XZ_AV(30) DPP_XZ_AV(32) DPP_XZ_AV(36) DPP_XZ_AV(40)
         DPP_XZ_AV(45) DPP_XZ_AV(48) DPP_XZ_AV(50) DPP_XZ_AV(54) DPP_XZ_AV(60) DPP_XZ_AV(64)
+        DPP_XZ_AV(90)
 #undef DPP_XZ_AV
         default:
             return v == XZ_LDS || v == XZ_AUTO;
@@ -1281,7 +1283,7 @@ static bool dens_reg_launch(int S0, dim3 grid, hipStream_t st, const FftItem* it
         return true;
         DPP_DENS_REG(12) DPP_DENS_REG(16) DPP_DENS_REG(18) DPP_DENS_REG(20) DPP_DENS_REG(24) DPP_DENS_REG(30)
         DPP_DENS_REG(32) DPP_DENS_REG(36) DPP_DENS_REG(40) DPP_DENS_REG(48) DPP_DENS_REG(50) DPP_DENS_REG(54)
-        DPP_DENS_REG(60) DPP_DENS_REG(64)
+        DPP_DENS_REG(60) DPP_DENS_REG(64) DPP_DENS_REG(90)
 #undef DPP_DENS_REG
         default:
             return false;
@@ -1291,7 +1293,7 @@ static bool dens_reg_launch(int S0, dim3 grid, hipStream_t st, const FftItem* it
 static bool dens_reg_available(int S0) {
     switch (S0) {
         case 12: case 16: case 18: case 20: case 24: case 30: case 32: case 36: case 40:
-        case 48: case 50: case 54: case 60: case 64:
+        case 48: case 50: case 54: case 60: case 64: case 90:
             return true;
         default:
             return false;

@@ -252,7 +252,7 @@ def test_subspace_eigh(dev, nb):
         assert np.max(np.abs(V[i].conj().T @ V[i] - np.eye(nb))) < 1e-12 * nb
 
 
-@pytest.mark.parametrize("name", ["tiny_proj_k", "cfg2"])
+@pytest.mark.parametrize("name", ["tiny_proj_k", "cfg2", "cfg3"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
 def test_density(dev, name, prec):
     log(f"density {name} prec={prec}")
