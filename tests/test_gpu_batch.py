@@ -192,13 +192,14 @@ def test_launch_choices_match_default(dev, which, value):
     assert err < 1e-10
 
 
+@pytest.mark.parametrize("S0", [40, 90])
 @pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
-def test_x_pass_variants_at_90_points(dev, prec):
-    """At config 3's 90-point x length every x-pass variant the tuner can pick
-    (lane-pair register split, one thread per column where it compiles, LDS)
-    gives the LDS pass's H Y to rounding; the box is 90 x 20 x 18."""
+def test_x_pass_variants(dev, prec, S0):
+    """At config 2's 40-point and config 3's 90-point x lengths every x-pass
+    variant the tuner can pick (one thread per column where it compiles, lane
+    pair, LDS) gives the LDS pass's H Y to rounding; the box is S0 x 20 x 18."""
     D = dev.D
-    cell = W.tiny_cell(nat=2, L=10.0, ecut=4.0, S=(90, 20, 18), nb=4, Z=(4, 4), seed=19)
+    cell = W.tiny_cell(nat=2, L=10.0, ecut=4.0, S=(S0, 20, 18), nb=4, Z=(4, 4), seed=19)
     s, Y, _ = _batch(dev, [cell], prec=prec)
     out = {}
     for v in (3, 0, 1, 2):  # LDS first: the reference
@@ -211,5 +212,5 @@ def test_x_pass_variants_at_90_points(dev, prec):
     tol = 1e-12 if prec == 0 else 1e-5
     for v in (0, 1, 2):
         err = np.max(np.abs(out[v] - ref)) / np.max(np.abs(ref))
-        log(f"x pass variant {v} at S0=90 prec={prec}: max rel difference {err:.2e}")
+        log(f"x pass variant {v} at S0={S0} prec={prec}: max rel difference {err:.2e}")
         assert err < tol
