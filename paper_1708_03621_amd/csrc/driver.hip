@@ -541,9 +541,9 @@ dpp_status potentials(dpp_system_s* s, const double* n) {
 
 // Energy terms of every cell at orthonormal psi (nbo bands, fillings d_f) and
 // density n: d_E[c * E_STRIDE + {EK, ENL, EH, EXC, ELOC}].  Leaves V_H, v_xc.
-dpp_status energies(dpp_system_s* s, int nbo, const double2* psi, const double* n) {
-    DPP_TRY(hartree_batched(s->ctx, s->d_box, s->h_box, n, s->VH, s->Tplanes, s->d_epart, s->d_cells, s->d_E + EH,
-                            E_STRIDE));
+dpp_status energies(dpp_system_s* s, int nbo, const double2* psi, const double* n, bool with_vh = true) {
+    DPP_TRY(hartree_batched(s->ctx, s->d_box, s->h_box, n, with_vh ? s->VH : nullptr, s->Tplanes, s->d_epart,
+                            s->d_cells, s->d_E + EH, E_STRIDE));
     DPP_TRY(lda_cells(s->ctx, s->d_cells, s->ncells, n, s->vxc, s->d_cred, s->d_E + EXC, E_STRIDE));
     DPP_TRY(dot_cells(s->ctx, s->d_cells, s->ncells, s->Vloc, n, s->d_cred, s->d_E + ELOC, E_STRIDE));
     {
@@ -743,7 +743,7 @@ dpp_status scf_body(dpp_system_s* s, double2* Y, int steps) {
     }
     // 5. n_out and E_el[psi, n_out]
     DPP_TRY(density_all(s, 0, Y, s->nout, s->prec));
-    DPP_TRY(energies(s, 0, Y, s->nout));
+    DPP_TRY(energies(s, 0, Y, s->nout, false));  // V_H[n_out] is not needed: the next V_eff is from the mixed n_in
     // 6. Pulay mixing of n_in
     DPP_TRY(pulay_mix(s));
     return DPP_OK;

@@ -650,8 +650,9 @@ k_xz_full(FftItem it, const typename cx<T>::t* __restrict__ Tb, int sign, double
 // Hartree x pass: forward x transform of the (already y,z transformed) density,
 // multiply by 4 pi / (|G|^2 N^2) (the J normalization 1/N and the I scale N
 // of the way back leave 4 pi / (|G|^2 N)), accumulate the energy partial
-// sum_G 4 pi |n~|^2 / |G|^2 for this i1, transform back along x.
-template <int NT, bool BATCH = false>
+// sum_G 4 pi |n~|^2 / |G|^2 for this i1, transform back along x.  Without
+// BACK only the energy partial is formed (the plane buffer is left as read).
+template <int NT, bool BATCH = false, bool BACK = true>
 __global__ void __launch_bounds__(NT)
 k_xz_hartree(const FftItem* items, FftItem single, double2* __restrict__ Tbase, double* __restrict__ epart) {
     const FftItem& it = DPP_ITEM(items, single);
@@ -689,7 +690,7 @@ k_xz_hartree(const FftItem* items, FftItem single, double2* __restrict__ Tbase, 
         const double ntr = v.x / N, nti = v.y / N;
         acc += kern * (ntr * ntr + nti * nti);
         const double s = kern / N;  // V_H(G) = kern * n~ = kern * X / N; I brings no 1/N
-        lds[i] = double2{v.x * s, v.y * s};
+        if (BACK) lds[i] = double2{v.x * s, v.y * s};
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -698,10 +699,12 @@ k_xz_hartree(const FftItem* items, FftItem single, double2* __restrict__ Tbase, 
         __syncthreads();
     }
     if (threadIdx.x == 0) epart[it.p_off + i1] = red[0];
-    fft_axis<double, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], +1);
-    for (int i = threadIdx.x; i < e; i += blockDim.x) {
-        const int i0 = i / S2, i2 = i - i0 * S2;
-        src[(int64_t)i0 * S1 * S2 + i2] = lds[i];
+    if constexpr (BACK) {
+        fft_axis<double, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], +1);
+        for (int i = threadIdx.x; i < e; i += blockDim.x) {
+            const int i0 = i / S2, i2 = i - i0 * S2;
+            src[(int64_t)i0 * S1 * S2 + i2] = lds[i];
+        }
     }
 }
 
@@ -1392,14 +1395,23 @@ dpp_status hartree_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::ve
                     hipLaunchKernelGGL(kp, dim3(bs.maxS0, 1, nc), dim3(NT_), bs.plane.lds, st, d_items, i0,
                                        (const void*)n, (int64_t)0, -1, Tb));
     DPP_LAUNCHED();
-    DPP_NT_DISPATCH(bs.xz.threads, auto kx = k_xz_hartree<NT_, true>; DPP_TRY(set_lds(kx, bs.xz.lds));
-                    hipLaunchKernelGGL(kx, dim3(bs.maxS1, 1, nc), dim3(NT_), bs.xz.lds, st, d_items, i0, Tb, epart));
-    DPP_LAUNCHED();
-    DPP_NT_DISPATCH(bs.plane.threads, auto kq = k_planes_to_box<double, true, NT_, true>;
-                    DPP_TRY(set_lds(kq, bs.plane.lds));
-                    hipLaunchKernelGGL(kq, dim3(bs.maxS0, 1, nc), dim3(NT_), bs.plane.lds, st, d_items, i0,
-                                       (const double2*)Tb, +1, 1.0, (void*)VH, (int64_t)0));
-    DPP_LAUNCHED();
+    if (VH) {
+        DPP_NT_DISPATCH(bs.xz.threads, auto kx = k_xz_hartree<NT_, true>; DPP_TRY(set_lds(kx, bs.xz.lds));
+                        hipLaunchKernelGGL(kx, dim3(bs.maxS1, 1, nc), dim3(NT_), bs.xz.lds, st, d_items, i0, Tb,
+                                           epart));
+        DPP_LAUNCHED();
+        DPP_NT_DISPATCH(bs.plane.threads, auto kq = k_planes_to_box<double, true, NT_, true>;
+                        DPP_TRY(set_lds(kq, bs.plane.lds));
+                        hipLaunchKernelGGL(kq, dim3(bs.maxS0, 1, nc), dim3(NT_), bs.plane.lds, st, d_items, i0,
+                                           (const double2*)Tb, +1, 1.0, (void*)VH, (int64_t)0));
+        DPP_LAUNCHED();
+    } else {
+        // the energy only: no way back to real space
+        DPP_NT_DISPATCH(bs.xz.threads, auto kx = k_xz_hartree<NT_, true, false>; DPP_TRY(set_lds(kx, bs.xz.lds));
+                        hipLaunchKernelGGL(kx, dim3(bs.maxS1, 1, nc), dim3(NT_), bs.xz.lds, st, d_items, i0, Tb,
+                                           epart));
+        DPP_LAUNCHED();
+    }
     hipLaunchKernelGGL(k_hartree_energy_cells, dim3(nc), dim3(256), 0, st, (const double*)epart, d_cells, (int)nc, E,
                        E_stride);
     DPP_LAUNCHED();
