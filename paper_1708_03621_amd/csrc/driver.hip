@@ -42,7 +42,7 @@ using namespace dpp;
 namespace {
 constexpr int MAX_TRIES = 6;
 constexpr int E_STRIDE = 8;  // per-cell energy slots
-enum { EK = 0, ENL = 1, EH = 2, EXC = 3, ELOC = 4, ESCR1 = 5, ESCR2 = 6 };
+enum { EK = 0, ENL = 1, EH = 2, EXC = 3, ELOC = 4 };
 constexpr int DENS_MAX_CHUNKS = 16;
 }  // namespace
 
@@ -528,9 +528,10 @@ dpp_status fill(dpp_system_s* s, double* p, int64_t n, double v) {
 // ----------------------------------------------------- fields and energies --
 // V_eff = V_loc + V_H[n] + v_xc[n] for every cell.
 dpp_status potentials(dpp_system_s* s, const double* n) {
-    DPP_TRY(hartree_batched(s->ctx, s->d_box, s->h_box, n, s->VH, s->Tplanes, s->d_epart, s->d_cells, s->d_E + ESCR1,
+    // the potentials only: the energies are those of the output density
+    DPP_TRY(hartree_batched(s->ctx, s->d_box, s->h_box, n, s->VH, s->Tplanes, s->d_epart, s->d_cells, nullptr,
                             E_STRIDE));
-    DPP_TRY(lda_cells(s->ctx, s->d_cells, s->ncells, n, s->vxc, s->d_cred, s->d_E + ESCR2, E_STRIDE));
+    DPP_TRY(lda_cells(s->ctx, s->d_cells, s->ncells, n, s->vxc, s->d_cred, nullptr, E_STRIDE));
     TimerScope ts_(s->ctx, DPP_TK_FIELDS);
     hipLaunchKernelGGL(k_grid_lin3, dim3((unsigned)((s->Ntot + 255) / 256)), dim3(256), 0, stream(s), s->Ntot, 1.0,
                        s->Vloc, 1.0, s->VH, 1.0, s->vxc, s->Veff);
@@ -540,7 +541,8 @@ dpp_status potentials(dpp_system_s* s, const double* n) {
 }
 
 // Energy terms of every cell at orthonormal psi (nbo bands, fillings d_f) and
-// density n: d_E[c * E_STRIDE + {EK, ENL, EH, EXC, ELOC}].  Leaves V_H, v_xc.
+// density n: d_E[c * E_STRIDE + {EK, ENL, EH, EXC, ELOC}].  Leaves v_xc, and
+// V_H unless with_vh is false.
 dpp_status energies(dpp_system_s* s, int nbo, const double2* psi, const double* n, bool with_vh = true) {
     DPP_TRY(hartree_batched(s->ctx, s->d_box, s->h_box, n, with_vh ? s->VH : nullptr, s->Tplanes, s->d_epart,
                             s->d_cells, s->d_E + EH, E_STRIDE));

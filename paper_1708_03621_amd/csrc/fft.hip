@@ -1384,6 +1384,7 @@ __global__ void k_hartree_energy_cells(const double* __restrict__ part, const Ce
 dpp_status hartree_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::vector<FftItem>& h, const double* n,
                            double* VH, void* Tbv, double* epart, const CellDesc* d_cells, double* E, int E_stride) {
     if (h.empty()) return DPP_OK;
+    if (!VH && !E) return DPP_OK;
     double2* Tb = reinterpret_cast<double2*>(Tbv);
     hipStream_t st = cx_->stream;
     const BatchShape bs = batch_shape(h, true);
@@ -1412,6 +1413,7 @@ dpp_status hartree_batched(dpp_ctx_s* cx_, const FftItem* d_items, const std::ve
                                            epart));
         DPP_LAUNCHED();
     }
+    if (!E) return DPP_OK;  // V_H only
     hipLaunchKernelGGL(k_hartree_energy_cells, dim3(nc), dim3(256), 0, st, (const double*)epart, d_cells, (int)nc, E,
                        E_stride);
     DPP_LAUNCHED();

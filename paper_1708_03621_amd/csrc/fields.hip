@@ -152,6 +152,7 @@ dpp_status lda_cells(dpp_ctx_s* ctx, const CellDesc* d_cells, int ncells, const 
     TimerScope ts_(ctx, DPP_TK_FIELDS);
     hipLaunchKernelGGL(k_lda_cells, dim3(CELL_RED_BLOCKS, ncells), dim3(256), 0, ctx->stream, d_cells, n, vxc, part);
     DPP_LAUNCHED();
+    if (!E) return DPP_OK;  // v_xc only
     hipLaunchKernelGGL(k_sum_cells, dim3(ncells), dim3(256), 0, ctx->stream, d_cells, (const double*)part, E, stride);
     DPP_LAUNCHED();
     return DPP_OK;

@@ -235,7 +235,8 @@ dpp_status vx_cells(dpp_ctx_s* ctx, const FftItem* d_cell_items, int ncells, int
                     double* Vx);
 // Hartree potential and energy of every cell: full-box items (one per cell,
 // v_off = field offset, t_off = plane offset, p_off = row-partial offset).
-// (VH may be NULL: then only the energies E_H are formed.)
+// VH may be NULL (only the energies E_H are formed) or E may be NULL (only
+// V_H).
 dpp_status hartree_batched(dpp_ctx_s* ctx, const FftItem* d_items, const std::vector<FftItem>& h_items,
                            const double* n, double* VH, void* Tb, double* epart, const CellDesc* d_cells,
                            double* E, int E_stride);
