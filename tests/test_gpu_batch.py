@@ -118,6 +118,32 @@ def test_graph_replay_config2_mixed(dev):
     assert np.array_equal(out[False][1], out[True][1])
 
 
+@pytest.mark.parametrize("case", ["full", "partial", "odd"])
+def test_fillings_match_oracle_aufbau(dev, case):
+    """The device aufbau fillings after one SCF iteration equal the oracle's
+    rule applied to the same eigenvalues: every state occupied (2 atoms Z=4,
+    4 bands, 2 k-points), empty bands (Z=1 pair, 3 bands) and an odd electron
+    count (9 electrons, 5 bands)."""
+    D = dev.D
+    cell = {
+        "full": W.tiny_cell(nat=2, L=6.5, ecut=3.0, S=(15, 15, 15), nb=4, Z=(4, 4), fold=(1, 2, 1), seed=13),
+        "partial": W.tiny_cell(nat=2, L=6.0, ecut=3.0, S=(12, 12, 12), nb=3, Z=(1, 1), seed=7),
+        "odd": W.tiny_cell(nat=3, L=7.0, ecut=3.5, S=(16, 15, 18), nb=5, Z=(4, 1, 4), fold=(2, 1, 2), seed=31),
+    }[case]
+    nk = len(cell.kpts)
+    s, Y, _ = _batch(dev, [cell])
+    D.dpp_scf_init(s, cells=[dict(tau=cell.tau, Z=cell.Z, sigma=W.START_SIGMA)])
+    _, eig = D.dpp_scf_iteration(s, Y)
+    f = D.dpp_system_fillings(s, nk, cell.nb)
+    D.dpp_system_destroy(s)
+    eig = np.asarray(eig).reshape(nk, cell.nb)
+    ref = oscf.aufbau_fillings([eig[k] for k in range(nk)], np.asarray(cell.wk), cell.n_electrons)
+    log(f"fillings {case}: {f.ravel()}")
+    assert np.array_equal(f, np.array(ref))
+    if case == "full":
+        assert np.all(f == 2.0)
+
+
 def test_config4_batch_fp32_graph(dev):
     """The 48-cell throughput workload: FP32 bulk, graph replay, three SCF
     iterations; three sampled cells equal their own single-cell runs."""
