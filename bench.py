@@ -48,17 +48,24 @@ WORKLOADS = {
 }
 
 
+def kernel_source_hash(files):
+    """Hash of the kernel sources a counter summary was taken from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_1708_03621_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch of the x pass from the committed counter summary,
-    if it was taken on this workload from the current kernel source."""
-    if kernel != "xz_h" or workload != "config2":
-        return None
-    path = os.path.join(ROOT, "profiles", "xz_h_config2_f64_traffic.md")
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (profiles/<kernel>_<workload>_traffic.md), if
+    the kernel sources hashed there are unchanged since the counters."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     try:
-        from paper_1708_03621_amd.profile_summary import xz_reg_source_hash
-        vals = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line
-                    and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_hash"))
-        if vals.get("kernel_source_hash") != xz_reg_source_hash():
+        vals = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
+        files = vals["kernel_sources"].split()
+        if vals.get("kernel_source_hash") != kernel_source_hash(files):
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):

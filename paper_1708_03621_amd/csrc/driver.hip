@@ -759,6 +759,9 @@ dpp_status capture_scf(dpp_system_s* s, double2* Y, int steps, hipGraphExec_t* e
     s->ctx->stream = s->cap_stream;
     hipGraph_t graph = nullptr;
     dpp_status st = DPP_OK;
+    // recording launches nothing: the H applications are counted when the
+    // graph is launched, not while its body is recorded
+    const int64_t hc_saved = s->hc_bandk;
     if (hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
         st = set_error(DPP_EDEVICE, "graph capture could not start");
     } else {
@@ -768,6 +771,7 @@ dpp_status capture_scf(dpp_system_s* s, double2* Y, int steps, hipGraphExec_t* e
     }
     s->ctx->stream = user;
     s->ctx->timer.on = timer_on;
+    s->hc_bandk = hc_saved;
     if (st != DPP_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return st;
