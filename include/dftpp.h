@@ -204,9 +204,12 @@ dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const dpp_c64 *U
 dpp_status dpp_ortho_workspace_size(dpp_basis basis, int nb, size_t *bytes);
 dpp_status dpp_cholesky_orthonormalize(dpp_basis basis, int nb, dpp_c64 *Y, int64_t ldY,
                                        dpp_c64 *Rinv, void *ws);
-/* Hermitian eigensolver (FP64, cyclic Jacobi): H (device, batch x nb x nb,
- * row-major) -> eig ascending (device, batch x nb) and vecs (device, row-major,
- * column j = eigenvector j).  H is not modified. */
+/* Hermitian eigensolver (FP64): H (device, batch x nb x nb, row-major; its
+ * lower triangle is read for nb > 32) -> eig ascending (device, batch x nb)
+ * and vecs (device, row-major, column j = eigenvector j).  H is not modified.
+ * Up to 32 bands: cyclic Jacobi in one wave.  33..128 bands: Householder
+ * reduction to a real tridiagonal, bisection, inverse iteration and
+ * back-transformation; ws (device) holds dpp_eigh_workspace_size bytes. */
 dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dpp_c64 *H, double *eig,
                              dpp_c64 *vecs, void *ws);
 dpp_status dpp_eigh_workspace_size(int nb, int batch, size_t *bytes);

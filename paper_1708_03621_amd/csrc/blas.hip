@@ -603,7 +603,7 @@ k_smm_mfma(const Seg* __restrict__ seg, int nbo, int opA, int opB, double alpha0
 // copy of the upper triangle packed in LDS (n(n+1)/2 entries: 132 KB at
 // n = 128), then R^{-1} by column back substitution.
 constexpr int CH_MAXN = 128;
-constexpr double CH_PIVOT_RTOL = 1e-14;
+constexpr double CH_PIVOT_RTOL = PIVOT_RTOL;
 
 __device__ __forceinline__ int up_idx(int n, int r, int c) { return r * n - (r * (r - 1)) / 2 + (c - r); }
 
@@ -1729,25 +1729,23 @@ extern "C" dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const
     DPP_REQUIRE(ctx && nb >= 1 && batch >= 0 && U && Rinv, "dpp_cholesky_inverse: bad arguments");
     DPP_REQUIRE(nb <= CH_MAXN, "dpp_cholesky_inverse: nb > 128");
     if (batch == 0) return DPP_OK;
-    const size_t lds = (size_t)nb * (nb + 1) / 2 * sizeof(double2);
-    if (lds > 64 * 1024)
-        DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(ctx, DPP_TK_CHOLESKY);
     if (!cholesky_wave_launch(ctx->stream, (unsigned)batch, nb, (int64_t)nb * nb, nullptr, 0, (const double2*)U,
-                              (double2*)Rinv, ctx->d_status, nullptr)) {
-        const int nt = nb <= 64 ? 64 : SM_NT;  // the in-place inverse needs one thread per row
-        hipLaunchKernelGGL(k_cholesky_inverse, dim3(batch), dim3(nt), lds, ctx->stream, nb, (const double2*)U,
-                           (double2*)Rinv, ctx->d_status);
-    }
+                              (double2*)Rinv, ctx->d_status, nullptr))
+        DPP_HIP(cholesky_tiles_launch(ctx->stream, (unsigned)batch, nb, nullptr, 0, nb, (const double2*)U,
+                                      (double2*)Rinv, ctx->d_status, nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
+}
+
+static size_t eigh_ws_split(int nb, int batch) {
+    return ((eigh_tiles_ws_bytes((int64_t)batch * nb * nb) + 255) / 256) * 256;
 }
 
 extern "C" dpp_status dpp_eigh_workspace_size(int nb, int batch, size_t* bytes) {
     clear_error();
     DPP_REQUIRE(bytes && nb >= 1 && batch >= 0, "dpp_eigh_workspace_size: bad arguments");
-    *bytes = nb <= 64 ? 256 : (size_t)batch * nb * nb * sizeof(double2) + 256;
+    *bytes = nb <= EIGW_MAXN ? 256 : eigh_ws_split(nb, batch) + eigh_perm_bytes(batch);
     return DPP_OK;
 }
 
@@ -1758,11 +1756,7 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
     DPP_REQUIRE(nb <= EIG_MAXN, "dpp_subspace_eigh: nb > 128");
     if (batch == 0) return DPP_OK;
     DPP_REQUIRE(H && eig && vecs, "dpp_subspace_eigh: null pointer");
-    DPP_REQUIRE(nb <= 64 || ws, "dpp_subspace_eigh: workspace required for nb > 64");
-    const size_t lds = eigh_lds(nb);
-    if (lds > 64 * 1024)
-        DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    DPP_REQUIRE(nb <= EIGW_MAXN || ws, "dpp_subspace_eigh: workspace required for nb > 32");
     TimerScope ts_(ctx, DPP_TK_EIGH);
     if (nb <= 16)
         hipLaunchKernelGGL(k_jacobi_eigh_wave<16>, dim3(batch), dim3(64), 0, ctx->stream, nb, (const double2*)H, eig,
@@ -1770,10 +1764,12 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
     else if (nb <= EIGW_MAXN)
         hipLaunchKernelGGL(k_jacobi_eigh_wave<32>, dim3(batch), dim3(64), 0, ctx->stream, nb, (const double2*)H, eig,
                            (double2*)vecs);
-    else
-        hipLaunchKernelGGL(k_jacobi_eigh, dim3(batch), dim3(nb > 64 ? SM_NT : 256), lds, ctx->stream, nb,
-                           (const double2*)H, eig,
-                           (double2*)vecs, nb <= 64 ? (double2*)nullptr : (double2*)ws);
+    else {
+        char* w = reinterpret_cast<char*>(ws);
+        DPP_HIP(eigh_tiles_launch(ctx->stream, (unsigned)batch, nb, nullptr, nb, (const double2*)H, eig,
+                                  (double2*)vecs, reinterpret_cast<double2*>(w),
+                                  reinterpret_cast<int*>(w + eigh_ws_split(nb, batch))));
+    }
     DPP_LAUNCHED();
     return DPP_OK;
 }

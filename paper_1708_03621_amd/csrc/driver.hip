@@ -106,6 +106,7 @@ struct dpp_system_s {
     double *Vloc, *VH, *vxc, *Veff, *n, *nin, *nout;
     double *hist_n, *hist_r, *pulayA, *pulayC;
     int* d_pst;
+    int* d_perm;  // eigensolver output order (EIG_TILE_MAXN per item)
     // workspaces
     void* Tplanes;
     size_t tplane_elems = 0;  // complex FP64 elements
@@ -498,14 +499,10 @@ dpp_status smm(dpp_system_s* s, int nbo, int opA, int opB, double alpha, int alp
 
 dpp_status chol_all(dpp_system_s* s, int nbo, const double2* Um, double2* Ri) {
     const int n = nbo > 0 ? nbo : s->maxnb;
-    const size_t lds = (size_t)n * (n + 1) / 2 * sizeof(double2);
-    if (lds > 64 * 1024)
-        DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_seg),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(s->ctx, DPP_TK_CHOLESKY);
     if (!cholesky_wave_launch(stream(s), (unsigned)s->nit, n, 0, s->d_seg, nbo, Um, Ri, s->ctx->d_status, nullptr))
-        hipLaunchKernelGGL(k_cholesky_seg, dim3(s->nit), dim3(n <= 64 ? 64 : SM_NT), lds, stream(s), s->d_seg, nbo, Um,
-                           Ri, s->ctx->d_status, (const int*)nullptr);
+        DPP_HIP(cholesky_tiles_launch(stream(s), (unsigned)s->nit, n, s->d_seg, nbo, 0, Um, Ri, s->ctx->d_status,
+                                      nullptr));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -595,8 +592,8 @@ dpp_status pulay_mix(dpp_system_s* s) {
 // of X, Q, H1, H2; with up to 32 bands U and H0 then follow from those
 // matrices (the line search's model of them) without new overlaps.
 dpp_status grad_B(dpp_system_s* s, const double2* Y, bool after_step = false) {
-    const bool wave = s->maxnb <= EIGW_MAXN;
-    if (!(wave && after_step))
+    // after a step U and H0 follow from the line matrices (both kernels below)
+    if (!after_step)
         DPP_TRY(overlap_jobs(s, 0, {OvJob{Y, Y, 1.0, true, s->U}, OvJob{Y, s->HY, 1.0, false, s->H0}}));
     bool fused = false;
     {
@@ -606,18 +603,16 @@ dpp_status grad_B(dpp_system_s* s, const double2* Y, bool after_step = false) {
                                       s->M2, s->d_bE0, s->ctx->d_status, after_step ? s->cg.stepf : nullptr, s->X,
                                       s->Q, s->H1, s->H2);
         if (fused) DPP_LAUNCHED();
+        // more bands: factor, U^{-1} and E0 on register tiles, one workgroup per item
+        if (!fused)
+            DPP_HIP(grad_prep_tiles_launch(stream(s), (unsigned)s->nit, s->maxnb, s->d_seg, s->U, s->H0, s->Rinv,
+                                           s->M1, s->d_bE0, s->ctx->d_status, after_step ? s->cg.stepf : nullptr,
+                                           s->X, s->Q, s->H1, s->H2));
     }
     if (!fused) {
-        DPP_TRY(chol_all(s, 0, s->U, s->Rinv));
-        // Uinv = Rinv Rinv^dag (M1); M2 = -Omega Uinv H0 Uinv
-        DPP_TRY(smm(s, 0, 0, 1, 1.0, 0, s->Rinv, s->Rinv, 0.0, s->M1));
+        // M2 = -Omega Uinv H0 Uinv
         DPP_TRY(smm(s, 0, 0, 0, 1.0, 0, s->M1, s->H0, 0.0, s->Rt));
         DPP_TRY(smm(s, 0, 0, 0, -1.0, 1, s->Rt, s->M1, 0.0, s->M2));
-        // E0 = Tr(Uinv H0) = Re Tr(Rt)
-        TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
-        hipLaunchKernelGGL(k_trace_diag, dim3(s->nit), dim3(64), 0, stream(s), s->d_seg, (const double2*)s->Rt,
-                           s->d_bE0);
-        DPP_LAUNCHED();
     }
     // g = HY Uinv + Y M2 in one pass
     DPP_TRY(rotate_jobs(s, 0, {RotJob{s->HY, s->M1, 0.0, s->g, Y, s->M2}}));
@@ -636,18 +631,11 @@ dpp_status line_mats_B(dpp_system_s* s, const double2* Y, const int* act) {
 
 dpp_status linesearch_B(dpp_system_s* s, const int* act, const double* d0, int* ok, double* step) {
     const int n = s->maxnb;
-    const int stage = n <= 64;  // H(a) staged in LDS beside the packed factor
-    const size_t lds = (size_t)n * (n + 1) / 2 * sizeof(double2) + (stage ? (size_t)n * n * sizeof(double2) : 0);
-    if (lds > 64 * 1024)
-        DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_linesearch_B),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     TimerScope ts_(s->ctx, DPP_TK_LINESEARCH);
     if (!linesearch_wave_launch(stream(s), (unsigned)s->nit, n, s->d_seg, s->U, s->X, s->Q, s->H0, s->H1, s->H2,
                                 s->d_bE0, s->cg.at, d0, act, ok, step, s->M1, s->M2))
-        hipLaunchKernelGGL(k_linesearch_B, dim3(s->nit), dim3(n <= 64 ? 64 : SM_NT), lds, stream(s), s->d_seg,
-                           (const double2*)s->U, (const double2*)s->X, (const double2*)s->Q, (const double2*)s->H0,
-                           (const double2*)s->H1, (const double2*)s->H2, (const double*)s->d_bE0,
-                           (const double*)s->cg.at, d0, act, ok, step, stage, s->M1, s->M2);
+        DPP_HIP(linesearch_tiles_launch(stream(s), (unsigned)s->nit, n, s->d_seg, s->U, s->X, s->Q, s->H0, s->H1,
+                                        s->H2, s->d_bE0, s->cg.at, d0, act, ok, step));
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -709,15 +697,10 @@ dpp_status subspace_rotate(dpp_system_s* s, double2* Y) {
     DPP_TRY(rotate_jobs(s, 0, {RotJob{Y, s->Rinv, 0.0, s->psi}, RotJob{s->HY, s->Rinv, 0.0, s->T1}}));
     DPP_TRY(overlap_jobs(s, 0, {OvJob{s->psi, s->T1, 1.0, false, s->H0}}));
     {
-        const int n = s->maxnb;
-        const size_t lds = eigh_lds(n);
-        if (lds > 64 * 1024)
-            DPP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_eigh_seg),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         TimerScope ts_(s->ctx, DPP_TK_EIGH);
-        if (!eigh_wave_launch(stream(s), (unsigned)s->nit, n, s->d_seg, s->H0, s->d_eig, s->vecs))
-            hipLaunchKernelGGL(k_jacobi_eigh_seg, dim3(s->nit), dim3(n > 64 ? SM_NT : 256), lds, stream(s), s->d_seg,
-                               (const double2*)s->H0, s->d_eig, s->vecs, s->eig_scr);
+        if (!eigh_wave_launch(stream(s), (unsigned)s->nit, s->maxnb, s->d_seg, s->H0, s->d_eig, s->vecs))
+            DPP_HIP(eigh_tiles_launch(stream(s), (unsigned)s->nit, s->maxnb, s->d_seg, 0, s->H0, s->d_eig, s->vecs,
+                                      s->eig_scr, s->d_perm));
         DPP_LAUNCHED();
     }
     DPP_TRY(rotate_jobs(s, 0, {RotJob{s->psi, s->vecs, 0.0, Y}, RotJob{s->T1, s->vecs, 0.0, s->HY}}));
@@ -1089,7 +1072,7 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
                   {&s->gp, blk}, {&s->Dp, blk}, {&s->psi, blk}, {&s->T1, blk}, {&s->T2, blk},
                   {&s->U, sm}, {&s->Rinv, sm}, {&s->H0, sm}, {&s->X, sm}, {&s->Q, sm}, {&s->H1, sm},
                   {&s->H2, sm}, {&s->Rt, sm}, {&s->M1, sm}, {&s->M2, sm}, {&s->vecs, sm},
-                  {&s->eig_scr, 2 * sm}, {&s->Pi, (size_t)std::max<int64_t>(s->pisum, 1)}};
+                  {&s->eig_scr, (eigh_tiles_ws_bytes((int64_t)sm) + 15) / 16}, {&s->Pi, (size_t)std::max<int64_t>(s->pisum, 1)}};
     for (auto& b : blocks)
         if ((st = dalloc_t(s, b.p, b.n)) != DPP_OK) return fail(st);
     const size_t nis = (size_t)nit, ns = (size_t)s->nstates, Nt = (size_t)s->Ntot;
@@ -1112,7 +1095,8 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
         int** p;
         size_t n;
     } ints[] = {{&s->cg.reset, nis}, {&s->cg.stat, nis}, {&s->cg.act, nis}, {&s->cg.steep, nis},
-                {&s->cg.ok, nis},    {&s->cg.ok2, nis},  {&s->cg.retry, nis}, {&s->d_pst, 4}};
+                {&s->cg.ok, nis},    {&s->cg.ok2, nis},  {&s->cg.retry, nis}, {&s->d_pst, 4},
+                {&s->d_perm, nis * EIG_TILE_MAXN}};
     for (auto& r : ints)
         if ((st = dalloc_t(s, r.p, r.n)) != DPP_OK) return fail(st);
     if ((st = dalloc_t(s, &s->d_seg, nis)) != DPP_OK) return fail(st);

@@ -1,0 +1,158 @@
+"""GPU parity above 32 bands against the FP64 oracle.
+
+From 33 to 128 bands the library switches from the single-wave small-matrix
+kernels to the register-tile ones (one workgroup per item): Cholesky inverse,
+band-gradient preparation, band-energy line search and the subspace
+eigensolver (Householder tridiagonalization, bisection, inverse iteration).
+These tests run band CG (protocol B) and SCF (protocol S) through them:
+  * protocol B trajectories at 33, 64, 65 and 128 bands;
+  * SCF trajectories at 40 and 65 bands;
+  * a batch that mixes a 16-band cell with a 40-band one (every item then
+    takes the register-tile path);
+  * two SCF iterations of config 3 itself (64 atoms, 90^3, 128 bands) against
+    oracle values stored by tests/golden/make_config3_scf.py.
+Bars: 1e-8 Ha per atom on energies (FP64), 1e-7 Ha on eigenvalues.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import energy as oe, minimize as om, scf as oscf
+from tests._gpu import Device, log
+from tests._systems import make_gpu_system, packed_Y
+
+pytestmark = pytest.mark.gpu
+TOL_ATOM = 1e-8
+TOL_EIG = 1e-7
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config3_scf2.txt")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return Device()
+
+
+def _cell(nb, seed=41):
+    """Config 1's box (L = 10, Ecut 8 Ha: 1045 plane waves at Gamma, 24^3)
+    with a projector atom (Z = 4) and a Z = 1 atom: 5 electrons, the rest of
+    the nb bands empty."""
+    return W.tiny_cell(nat=2, L=10.0, ecut=8.0, S=(24, 24, 24), nb=nb, Z=(4, 1), seed=seed)
+
+
+@pytest.mark.parametrize("nb", [33, 64, 65, 128])
+def test_band_cg_many_bands(dev, nb):
+    log(f"band CG nb={nb}")
+    cell = _cell(nb)
+    s = oe.build_system(cell)
+    Veff = s.Vloc + W.random_potential(3, cell.S, 0.1)
+    sysg, off, npw = make_gpu_system(dev, cell)
+    Y, blocks = packed_Y(dev, cell, npw)
+    Vg = dev.tensor(Veff)
+    steps = 8
+    Eg = [dev.D.dpp_cg_B_init(sysg, Y, Vg, 1)[0]]
+    for _ in range(steps):
+        Eg.append(dev.D.dpp_cg_B_step(sysg, Y, 1)[0])
+    cg = om.protocol_B(blocks[0].T.copy(), s.bases[0], Veff, s.P[0], s.D, steps)
+    h = np.array(cg.history)
+    n = min(len(h), len(Eg))
+    log(f"gpu {Eg[:n]} oracle {list(h[:n])}")
+    assert n == steps + 1
+    assert np.max(np.abs(np.array(Eg[:n]) - h[:n])) / cell.nat < TOL_ATOM
+    # eigenvalues of the block reached (subspace diagonalization)
+    eig = dev.D.dpp_band_eigenvalues(sysg, Y, 1, nb)[0]
+    _, eo = oscf.subspace_rotate(cg.Y[0], s.bases[0], Veff, s.P[0], s.D)
+    assert np.max(np.abs(eig - eo)) < TOL_EIG
+    dev.D.dpp_system_destroy(sysg)
+
+
+@pytest.mark.parametrize("nb", [40, 65])
+def test_scf_many_bands(dev, nb):
+    log(f"scf nb={nb}")
+    cell = _cell(nb, seed=43)
+    s = oe.build_system(cell)
+    sysg, off, npw = make_gpu_system(dev, cell)
+    Y, blocks = packed_Y(dev, cell, npw)
+    dev.D.dpp_scf_init(sysg, cell.tau, cell.Z, W.START_SIGMA)
+    nit = 3
+    Eg = []
+    for _ in range(nit):
+        E, e = dev.D.dpp_scf_iteration(sysg, Y, 1, cell.nb)
+        Eg.append(E["E_el"])
+    res = oscf.scf(s, [b.T.copy() for b in blocks], oe.start_density(cell, W.START_SIGMA), nit)
+    log(f"gpu {Eg} oracle {res['energies']}")
+    assert np.max(np.abs(np.array(Eg) - np.array(res["energies"]))) / cell.nat < TOL_ATOM
+    assert np.max(np.abs(e - np.array(res["eigs"]))) < TOL_EIG
+    dev.D.dpp_system_destroy(sysg)
+
+
+def test_batch_mixing_16_and_40_bands(dev):
+    """A batch whose largest item has 40 bands runs every item (the 16-band
+    cell's four k-points too) through the register-tile kernels."""
+    small = W.tiny_cell(nat=3, L=7.0, ecut=3.5, S=(16, 15, 18), nb=16, Z=(4, 1, 4), fold=(2, 1, 2),
+                        R=np.array([[7.0, 0.5, 0.0], [0.0, 6.6, 0.7], [0.4, 0.0, 7.3]]), seed=31)
+    big = _cell(40, seed=45)
+    cells = [small, big]
+    log("batch 16 + 40 bands")
+    D = dev.D
+    descs = [dict(R=c.R, S=c.S, ecut=c.ecut, kpts=c.kpts, wk=c.wk, nb=c.nb, n_electrons=c.n_electrons, tau=c.tau,
+                  Z=c.Z.astype(float), rc=c.rc, has_proj=c.has_proj.astype(int), rp=W.PROJ_RP, D=W.PROJ_D)
+             for c in cells]
+    sysg = D.dpp_batch_create(dev.ctx, descs, 0)
+    off, npw = D.dpp_system_layout(sysg)
+    item0, _, _ = D.dpp_system_cells(sysg)
+    blocks = []
+    for ci, c in enumerate(cells):
+        blocks.append(W.initial_wavefunctions(c.y0_seed, [(c.nb, npw[k]) for k in range(item0[ci], item0[ci + 1])]))
+    Y = dev.tensor(np.concatenate([b.reshape(-1) for bl in blocks for b in bl]))
+    D.dpp_scf_init(sysg, cells=[dict(tau=c.tau, Z=c.Z, sigma=W.START_SIGMA) for c in cells])
+    nit = 3
+    Eb = []
+    for _ in range(nit):
+        e, _ = D.dpp_scf_iteration(sysg, Y)
+        Eb.append([x["E_el"] for x in e])
+    Eb = np.array(Eb)
+    D.dpp_system_destroy(sysg)
+    for ci, c in enumerate(cells):
+        s = oe.build_system(c)
+        res = oscf.scf(s, [b.T.copy() for b in blocks[ci]], oe.start_density(c, W.START_SIGMA), nit)
+        d = np.max(np.abs(Eb[:, ci] - np.array(res["energies"]))) / c.nat
+        log(f"cell {ci} nb={c.nb}: max dE/atom {d:.2e}")
+        assert d < TOL_ATOM
+
+
+def _golden():
+    E, eig, nsum = {}, {}, None
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        if k == "E_el":
+            E[int(v[0])] = float(v[1])
+        elif k == "eig":
+            eig[int(v[0])] = float(v[1])
+        elif k == "n_out_abs_sum":
+            nsum = float(v[0])
+    return [E[i] for i in sorted(E)], np.array([eig[i] for i in sorted(eig)]), nsum
+
+
+def test_config3_scf_two_iterations(dev):
+    """Config 3 (64 atoms, 23847 plane waves, 90^3, 128 bands): two FP64 SCF
+    iterations from the seeded start against the oracle's."""
+    log("config 3 SCF x2")
+    Eo, eo, nsum = _golden()
+    cell = W.config3()
+    sysg, off, npw = make_gpu_system(dev, cell)
+    Y, _ = packed_Y(dev, cell, npw)
+    dev.D.dpp_scf_init(sysg, cell.tau, cell.Z, W.START_SIGMA)
+    Eg = []
+    for _ in range(len(Eo)):
+        E, e = dev.D.dpp_scf_iteration(sysg, Y, 1, cell.nb)
+        Eg.append(E["E_el"])
+    nout = dev.field(sysg, dev.D.DPP_FIELD_NOUT, cell.S)
+    log(f"gpu {Eg} oracle {Eo}")
+    assert np.max(np.abs(np.array(Eg) - np.array(Eo))) / cell.nat < TOL_ATOM
+    assert np.max(np.abs(e[0] - eo)) < TOL_EIG
+    assert abs(np.sum(np.abs(nout)) - nsum) / nsum < 1e-10
+    dev.D.dpp_system_destroy(sysg)

@@ -190,7 +190,7 @@ def test_rotate(dev, nbX, nbO, beta):
     assert rel_err(dev.host(out), ref) < 1e-12
 
 
-@pytest.mark.parametrize("nb", [1, 4, 16, 33, 128])
+@pytest.mark.parametrize("nb", [1, 4, 16, 33, 64, 65, 100, 128])
 def test_cholesky_orthonormalize(dev, nb):
     log(f"cholesky nb={nb}")
     cell = W.config2() if nb <= 16 else W.config3()
@@ -211,33 +211,44 @@ def test_cholesky_orthonormalize(dev, nb):
     assert np.max(np.abs(psi.conj().T @ (ref.omega * psi) - np.eye(nb))) < 1e-11
 
 
-def test_cholesky_flags_rank_deficient(dev):
-    log("cholesky rank-deficient")
+@pytest.mark.parametrize("nb", [4, 40, 128])
+def test_cholesky_flags_rank_deficient(dev, nb):
+    log(f"cholesky rank-deficient nb={nb}")
     cell = W.config2()
     ref = ob.gsphere(cell.R, cell.S, cell.kpts[0], cell.ecut)
     g = dev.grid(cell.R, cell.S)
     b = dev.basis(g, cell.kpts[0], cell.ecut)
     rng = np.random.default_rng(1)
-    Y = rng.standard_normal((ref.npw, 4)) + 1j * rng.standard_normal((ref.npw, 4))
-    Y[:, 2] = Y[:, 1]
+    Y = rng.standard_normal((ref.npw, nb)) + 1j * rng.standard_normal((ref.npw, nb))
+    Y[:, nb - 2] = Y[:, 1]
     Yg = block_to_gpu(dev, Y)
-    ws = dev.ws(dev.D.dpp_ortho_workspace_size(b, 4))
+    ws = dev.ws(dev.D.dpp_ortho_workspace_size(b, nb))
     dev.D.dpp_ctx_status(dev.ctx, True)
-    dev.D.dpp_cholesky_orthonormalize(b, 4, Yg, ref.npw, None, ws)
+    dev.D.dpp_cholesky_orthonormalize(b, nb, Yg, ref.npw, None, ws)
     assert dev.D.dpp_ctx_status(dev.ctx, True) & dev.D.DPP_STATUS_NOTPD
     assert dev.D.dpp_ctx_status(dev.ctx, True) == 0
 
 
-@pytest.mark.parametrize("nb", [1, 2, 5, 16, 64, 65, 128])
+@pytest.mark.parametrize("nb", [1, 2, 5, 16, 33, 64, 65, 100, 128])
 def test_subspace_eigh(dev, nb):
     log(f"eigh nb={nb}")
     rng = np.random.default_rng(nb)
-    batch = 3
+    batch = 6 if nb >= 33 else 3
     H = rng.standard_normal((batch, nb, nb)) + 1j * rng.standard_normal((batch, nb, nb))
     H = H + np.conj(np.transpose(H, (0, 2, 1)))
     if nb >= 5:
         H[1] = np.diag(np.arange(nb, dtype=float)) + 0j     # already diagonal
         H[2, :2, :2] = np.array([[1.0, 0.0], [0.0, 1.0]])   # a degenerate block
+    if nb >= 33:
+        Q, _ = np.linalg.qr(rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb)))
+        # shells of equal eigenvalues (free-electron-like multiplicities)
+        ev = np.sort(np.repeat(0.1875 * np.arange(nb), 12)[:nb])
+        H[3] = (Q * ev) @ Q.conj().T
+        # a cluster spaced at 1e-9 inside an otherwise spread spectrum
+        ev = np.sort(rng.standard_normal(nb))
+        ev[5:13] = ev[5] + 1e-9 * np.arange(8)
+        H[4] = 1e3 * ((Q * ev) @ Q.conj().T)
+        H[5] = np.eye(nb) + 0j                               # every eigenvalue equal
     eig = dev.empty((batch, nb), dev.torch.float64)
     vec = dev.empty((batch, nb, nb), dev.torch.complex128)
     ws = dev.ws(dev.D.dpp_eigh_workspace_size(nb, batch))
