@@ -599,136 +599,10 @@ k_smm_mfma(const Seg* __restrict__ seg, int nbo, int opA, int opB, double alpha0
 }
 
 // ------------------------------------------------------------ Cholesky -----
-// One workgroup per matrix.  Right-looking factorization U = R^dag R on a
-// copy of the upper triangle packed in LDS (n(n+1)/2 entries: 132 KB at
-// n = 128), then R^{-1} by column back substitution.
+// Up to 32 bands one wave per matrix (below); 33 to 128 bands run on register
+// tiles (dense.hip).
 constexpr int CH_MAXN = 128;
 constexpr double CH_PIVOT_RTOL = PIVOT_RTOL;
-
-__device__ __forceinline__ int up_idx(int n, int r, int c) { return r * n - (r * (r - 1)) / 2 + (c - r); }
-
-// Factor the Hermitian matrix whose upper triangle load(r, c) (c >= r) gives,
-// into packed LDS A, then overwrite A with R^{-1}.  Returns 1 (uniformly) if a
-// pivot falls below CH_PIVOT_RTOL times the largest diagonal element.  Needs
-// blockDim.x >= n and <= 256.
-template <typename Load>
-__device__ int chol_inverse_packed(int n, Load load, double2* __restrict__ A) {
-    __shared__ int fail;
-    __shared__ double umax;
-    __shared__ double red[SM_NT];
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int r = e / n, c = e - r * n;
-        if (c >= r) A[up_idx(n, r, c)] = load(r, c);
-    }
-    __syncthreads();
-    // largest diagonal element
-    double m = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, A[up_idx(n, i, i)].x);
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        fail = 0;
-        umax = red[0];
-    }
-    __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double d = A[up_idx(n, j, j)].x;
-        if (!(d > CH_PIVOT_RTOL * umax)) {
-            if (threadIdx.x == 0) fail = 1;
-            break;  // uniform: every thread read the same d
-        }
-        const double rjj = sqrt(d);
-        const double inv = 1.0 / rjj;
-        __syncthreads();
-        // row j of R
-        for (int c = j + 1 + threadIdx.x; c < n; c += blockDim.x) {
-            const double2 v = A[up_idx(n, j, c)];
-            A[up_idx(n, j, c)] = double2{v.x * inv, v.y * inv};
-        }
-        if (threadIdx.x == 0) A[up_idx(n, j, j)] = double2{rjj, 0.0};
-        __syncthreads();
-        // trailing update A[r][c] -= conj(R[j][r]) R[j][c], j < r <= c
-        const int mm = n - j - 1;
-        for (int e = threadIdx.x; e < mm * mm; e += blockDim.x) {
-            const int r = j + 1 + e / mm, c = j + 1 + e % mm;
-            if (c >= r) {
-                const double2 a = A[up_idx(n, j, r)], b = A[up_idx(n, j, c)];
-                const double re = a.x * b.x + a.y * b.y, im = a.x * b.y - a.y * b.x;  // conj(a) b
-                const int k = up_idx(n, r, c);
-                A[k].x -= re;
-                A[k].y -= im;
-            }
-        }
-        __syncthreads();
-    }
-    __syncthreads();
-    const int failed = fail;
-    if (failed) return 1;
-    // R^{-1} in place (upper triangular, same packed storage): from X R = 1,
-    // X_ij = -(sum_{k=i}^{j-1} X_ik R_kj) / R_jj for i < j and X_jj = 1 / R_jj;
-    // column j needs only columns < j of X, already in place.
-    for (int j = 0; j < n; ++j) {
-        const double d = 1.0 / A[up_idx(n, j, j)].x;
-        double tr = 0, ti = 0;
-        const int i = threadIdx.x;
-        if (i < j) {
-            for (int k = i; k < j; ++k) {
-                const double2 x = A[up_idx(n, i, k)], r = A[up_idx(n, k, j)];
-                tr += x.x * r.x - x.y * r.y;
-                ti += x.x * r.y + x.y * r.x;
-            }
-        }
-        __syncthreads();
-        if (i < j) A[up_idx(n, i, j)] = double2{-tr * d, -ti * d};
-        if (i == j) A[up_idx(n, j, j)] = double2{d, 0.0};
-        __syncthreads();
-    }
-    return 0;
-}
-
-__device__ void chol_store(int n, int failed, const double2* __restrict__ A, double2* __restrict__ X,
-                           int* __restrict__ status) {
-    if (failed) {
-        if (threadIdx.x == 0 && status) atomicOr(status, DPP_STATUS_NOTPD);
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) X[e] = double2{NAN, NAN};
-        return;
-    }
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int r = e / n, c = e - r * n;
-        X[e] = c >= r ? A[up_idx(n, r, c)] : double2{0, 0};
-    }
-}
-
-// Matrices at stride n^2 (one workgroup each).
-__global__ void __launch_bounds__(SM_NT)
-k_cholesky_inverse(int n, const double2* __restrict__ U, double2* __restrict__ Rinv,
-                   int* __restrict__ status) {
-    extern __shared__ char smem_raw[];
-    double2* A = reinterpret_cast<double2*>(smem_raw);  // packed upper triangle
-    const int64_t off = (int64_t)blockIdx.x * n * n;
-    const double2* Ug = U + off;
-    const int f = chol_inverse_packed(n, [&](int r, int c) { return Ug[(int64_t)r * n + c]; }, A);
-    chol_store(n, f, A, Rinv + off, status);
-}
-
-// Per work item: the item's n x n matrix at moff (n = nbo if > 0, else the
-// item's band count); items with act[item] == 0 are skipped.
-__global__ void __launch_bounds__(SM_NT)
-k_cholesky_seg(const Seg* __restrict__ seg, int nbo, const double2* __restrict__ U, double2* __restrict__ Rinv,
-               int* __restrict__ status, const int* __restrict__ act) {
-    if (act && !act[blockIdx.x]) return;
-    extern __shared__ char smem_raw[];
-    double2* A = reinterpret_cast<double2*>(smem_raw);
-    const Seg sg = seg[blockIdx.x];
-    const int n = nbo > 0 ? nbo : sg.nb;
-    const double2* Ug = U + sg.moff;
-    const int f = chol_inverse_packed(n, [&](int r, int c) { return Ug[(int64_t)r * n + c]; }, A);
-    chol_store(n, f, A, Rinv + sg.moff, status);
-}
 
 // ------------------------------------------ single-wave Cholesky inverse ---
 // U = R^dag R and X = R^{-1} for n <= NMAX (16 or 32) in one wave.  The
@@ -868,7 +742,7 @@ k_cholesky_wave(int n, int64_t stride, const Seg* __restrict__ seg, int nbo, con
 }
 
 // Band-energy line search of every active item, entirely on the device (one
-// workgroup per item).  Along D the trial energy is
+// wave per item up to 32 bands; register tiles above).  Along D the trial energy is
 //   E(a) = Tr(U(a)^{-1} H(a)),  U(a) = U + a (X + X^dag) + a^2 Q,
 //   H(a) = H0 + a (H1 + H1^dag) + a^2 H2,
 // evaluated through the Cholesky factor of U(a).  Step rule: trial a_t (the
@@ -877,108 +751,6 @@ k_cholesky_wave(int n, int64_t stride, const Seg* __restrict__ seg, int nbo, con
 // E(a*) <= E0, else a_t if E(a_t) <= E0, else halve a_t (at most MAX_TRIES
 // times).  Writes ok[item] and step[item] (0 when the search failed).
 constexpr int LS_MAX_TRIES = 6;
-
-// Trial energy at step a.  With `Hs` (LDS, n^2 entries) H(a) is staged once
-// per trial; otherwise its entries are formed from global memory in the trace.
-__device__ double trial_energy(const Seg& sg, double a, const double2* __restrict__ U,
-                               const double2* __restrict__ Xs, const double2* __restrict__ Q,
-                               const double2* __restrict__ H0, const double2* __restrict__ Ps,
-                               const double2* __restrict__ H2, double2* __restrict__ A, double2* __restrict__ Hs) {
-    __shared__ double red[SM_NT];
-    const int n = sg.nb;
-    const int64_t o = sg.moff;
-    // Xs = X + X^dag and Ps = H1 + H1^dag (prepared by the caller)
-    auto loadU = [&](int r, int c) {
-        const double2 x = Xs[o + r * n + c], u = U[o + r * n + c], q = Q[o + r * n + c];
-        return double2{u.x + a * x.x + a * a * q.x, u.y + a * x.y + a * a * q.y};
-    };
-    auto Hat = [&](int r, int c) {
-        const double2 h = Ps[o + r * n + c], h0 = H0[o + r * n + c], h2 = H2[o + r * n + c];
-        return double2{h0.x + a * h.x + a * a * h2.x, h0.y + a * h.y + a * a * h2.y};
-    };
-    if (Hs)
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) Hs[e] = Hat(e / n, e % n);
-    // (the staging is ordered before its use by the barriers of the factorization)
-    const int failed = chol_inverse_packed(n, loadU, A);
-    if (failed) return NAN;
-    // Re Tr(Rinv^dag H(a) Rinv) = sum_{a <= i} Re conj(Rinv[a][i]) sum_{t <= i} H(a)[a][t] Rinv[t][i]
-    double acc = 0;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int ar = e / n, i = e - ar * n;
-        if (ar > i) continue;
-        double wr = 0, wi = 0;
-        for (int t = 0; t <= i; ++t) {
-            const double2 h = Hs ? Hs[ar * n + t] : Hat(ar, t);
-            const double2 r = A[up_idx(n, t, i)];
-            wr += h.x * r.x - h.y * r.y;
-            wi += h.x * r.y + h.y * r.x;
-        }
-        const double2 ra = A[up_idx(n, ar, i)];
-        acc += ra.x * wr + ra.y * wi;
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double E = red[0];
-    __syncthreads();
-    return E;
-}
-
-__global__ void __launch_bounds__(SM_NT)
-k_linesearch_B(const Seg* __restrict__ seg, const double2* __restrict__ U, const double2* __restrict__ X,
-               const double2* __restrict__ Q, const double2* __restrict__ H0, const double2* __restrict__ H1,
-               const double2* __restrict__ H2, const double* __restrict__ E0v, const double* __restrict__ at0,
-               const double* __restrict__ d0v, const int* __restrict__ act, int* __restrict__ ok,
-               double* __restrict__ step, int stage_h, double2* __restrict__ Xs, double2* __restrict__ Ps) {
-    const int k = blockIdx.x;
-    if (!act[k]) return;
-    extern __shared__ char smem_raw[];
-    double2* A = reinterpret_cast<double2*>(smem_raw);
-    const Seg sg = seg[k];
-    double2* Hs = stage_h ? A + sg.nb * (sg.nb + 1) / 2 : nullptr;
-    {
-        // symmetric parts of the line matrices, read coalesced by every trial
-        const int n = sg.nb;
-        const int64_t o = sg.moff;
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int r = e / n, c = e - r * n;
-            const double2 x = X[o + e], xt = X[o + c * n + r];
-            const double2 h = H1[o + e], ht = H1[o + c * n + r];
-            Xs[o + e] = double2{x.x + xt.x, x.y - xt.y};
-            Ps[o + e] = double2{h.x + ht.x, h.y - ht.y};
-        }
-        __syncthreads();
-    }
-    const double E0 = E0v[k], d0 = d0v[k];
-    double at = at0[k];
-    int good = 0;
-    double st = 0.0;
-    for (int t = 0; t < LS_MAX_TRIES; ++t) {
-        const double Et = trial_energy(sg, at, U, Xs, Q, H0, Ps, H2, A, Hs);
-        const double c = (Et - E0 - d0 * at) / (at * at);
-        double as = c > 0 ? -d0 / (2.0 * c) : 2.0 * at;
-        as = fmin(as, 10.0 * at);
-        const double Es = trial_energy(sg, as, U, Xs, Q, H0, Ps, H2, A, Hs);
-        if (Es <= E0) {
-            good = 1;
-            st = as;
-            break;
-        }
-        if (Et <= E0) {
-            good = 1;
-            st = at;
-            break;
-        }
-        at *= 0.5;
-    }
-    if (threadIdx.x == 0) {
-        ok[k] = good;
-        step[k] = st;
-    }
-}
 
 // The line search for n <= NMAX bands in one wave: H(a) staged in LDS, the
 // factor and inverse of U(a) from chol_inv_wave, and
@@ -1245,229 +1017,27 @@ bool linesearch_wave_launch(hipStream_t st, unsigned nblk, int n, const Seg* seg
 }
 
 // ----------------------------------------------------- Jacobi eigensolver --
-// Parallel cyclic Jacobi on a Hermitian matrix, one workgroup per matrix.
-// Each round rotates m/2 disjoint index pairs of a round-robin tournament
-// (circle schedule: pair 0 = (m-1, r), pair s = ((r+s) mod (m-1),
+// Parallel cyclic Jacobi on a Hermitian matrix of up to 32 bands, one wave
+// per matrix.  Each round rotates m/2 disjoint index pairs of a round-robin
+// tournament (circle schedule: pair 0 = (m-1, r), pair s = ((r+s) mod (m-1),
 // (r-s) mod (m-1)); m = n rounded up to even, index n a dummy).  For the pair
 // (p,q) with A_pq = |c| e^{i phi}, J = diag-phase * real rotation:
 //   tau = (A_qq - A_pp) / (2|c|), t = sign(tau)/(|tau| + sqrt(1+tau^2)),
 //   cs = 1/sqrt(1+t^2), sn = t cs,
 //   J[p][p] = cs, J[p][q] = sn, J[q][p] = -sn e^{-i phi}, J[q][q] = cs e^{-i phi}
-// and A <- J^dag A J, V <- V J.  A is kept as its packed upper triangle in
-// LDS (Hermitian), so a round is one pass over 2x2 blocks (pair s', pair s):
-// B <- J_s'^dag B J_s, each stored element touched once; the diagonal blocks
-// become diagonal exactly.  V is kept transposed (row p of Vt = column p of
-// V, so a rotation touches two contiguous rows) in LDS for n <= 64, else in
-// the caller's global scratch.
+// and A <- J^dag A J, V <- V J.  33 to 128 bands use the tridiagonal
+// eigensolver on register tiles (dense.hip).
 constexpr int EIG_MAXN = 128;
 constexpr int EIG_SWEEPS = 40;
 
 // Squared relative off-diagonal norm at which the sweeps stop.
 __device__ __forceinline__ double eig_stop2(int n) { return fmax(1e-28, 4e-32 * (double)n * (double)n); }
 
-struct Rot {
-    int p, q;
-    double cs, sn, er, ei;  // e^{-i phi} = er + i ei
-};
-
-__device__ __forceinline__ double2 hget(const double2* A, int n, int r, int c) {
-    if (r <= c) return A[up_idx(n, r, c)];
-    const double2 v = A[up_idx(n, c, r)];
-    return double2{v.x, -v.y};
-}
-
-__device__ __forceinline__ void hset(double2* A, int n, int r, int c, double2 v) {
-    if (r <= c)
-        A[up_idx(n, r, c)] = v;
-    else
-        A[up_idx(n, c, r)] = double2{v.x, -v.y};
-}
-
 __device__ __forceinline__ double2 cmulz(double2 a, double2 b) {
     return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// LDS bytes of one matrix: packed A, plus V when n <= 64.
-__host__ __device__ inline size_t eigh_lds_bytes(int n) {
-    return (size_t)n * (n + 1) / 2 * sizeof(double2) + (n <= 64 ? (size_t)n * n * sizeof(double2) : 0);
-}
-
-// Eigen-decomposition of the Hermitian n x n matrix Hg (row-major): ascending
-// eigenvalues to ev, eigenvectors (columns) to vo.  lds holds eigh_lds_bytes(n);
-// scr (n^2 entries) is used for V when n > 64.
-__device__ void jacobi_eigh_block(int n, const double2* __restrict__ Hg, double* __restrict__ ev,
-                                  double2* __restrict__ vo, double2* __restrict__ lds, double2* __restrict__ scr) {
-    const int m = n + (n & 1);
-    const int P = m / 2;
-    double2* A = lds;
-    double2* Vt = n <= 64 ? lds + n * (n + 1) / 2 : scr;
-    __shared__ Rot rot[EIG_MAXN / 2];
-    __shared__ double red[SM_NT];
-    __shared__ double dg[EIG_MAXN];
-    __shared__ int perm[EIG_MAXN];
-    __shared__ int done;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int r = e / n, c = e - r * n;
-        if (c >= r) {
-            double2 h = Hg[e];
-            if (r == c) h.y = 0.0;
-            A[up_idx(n, r, c)] = h;
-        }
-        Vt[e] = double2{r == c ? 1.0 : 0.0, 0.0};
-    }
-    __syncthreads();
-    for (int sweep = 0; sweep < EIG_SWEEPS; ++sweep) {
-        // convergence: off-diagonal Frobenius norm vs diagonal scale
-        double off = 0, dia = 0;
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int r = e / n, c = e - r * n;
-            if (c < r) continue;
-            const double2 a = A[up_idx(n, r, c)];
-            if (r != c)
-                off += 2.0 * (a.x * a.x + a.y * a.y);
-            else
-                dia += a.x * a.x;
-        }
-        red[threadIdx.x] = off;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        const double offt = red[0];
-        __syncthreads();
-        red[threadIdx.x] = dia;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        const double diat = red[0];
-        // converged once the off-diagonal part is 1e-14 of the Frobenius norm,
-        // or (large n) once it is within twice the level below which pairs
-        // are skipped: n(n-1) entries of at most 1e-16 |A|_F each
-        const double fro2 = offt + diat;
-        if (threadIdx.x == 0) done = (offt <= eig_stop2(n) * fmax(fro2, 1e-300)) || offt == 0.0;
-        __syncthreads();
-        if (done) break;
-        // pairs below the rounding level of the matrix are not rotated
-        const double skip = 1e-16 * sqrt(fro2);
-        for (int round = 0; round < m - 1; ++round) {
-            for (int s = threadIdx.x; s < P; s += blockDim.x) {
-                int p, q;
-                if (s == 0) {
-                    p = m - 1;
-                    q = round;
-                } else {
-                    p = (round + s) % (m - 1);
-                    q = (round - s + (m - 1)) % (m - 1);
-                }
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                Rot R{p, q, 1.0, 0.0, 1.0, 0.0};
-                if (q < n) {
-                    const double2 c = A[up_idx(n, p, q)];
-                    const double ac = sqrt(c.x * c.x + c.y * c.y);
-                    const double app = A[up_idx(n, p, p)].x, aqq = A[up_idx(n, q, q)].x;
-                    if (ac > skip && ac > 1e-300) {
-                        const double tau = (aqq - app) / (2.0 * ac);
-                        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        R.cs = 1.0 / sqrt(1.0 + t * t);
-                        R.sn = t * R.cs;
-                        R.er = c.x / ac;
-                        R.ei = -c.y / ac;
-                    }
-                } else {
-                    R.q = -1;  // paired with the dummy: no rotation
-                }
-                rot[s] = R;
-            }
-            __syncthreads();
-            // A: every 2x2 block (pair s2 rows, pair s1 columns), s2 <= s1
-            for (int bk = threadIdx.x; bk < P * P; bk += blockDim.x) {
-                const int s2 = bk / P, s1 = bk - s2 * P;
-                if (s2 > s1) continue;
-                const Rot Rc = rot[s1], Rr = rot[s2];
-                const bool idc = Rc.q < 0 || (Rc.sn == 0.0 && Rc.er == 1.0 && Rc.ei == 0.0);
-                const bool idr = Rr.q < 0 || (Rr.sn == 0.0 && Rr.er == 1.0 && Rr.ei == 0.0);
-                if (idc && idr) continue;
-                const int xr[2] = {Rr.p, Rr.q}, yc[2] = {Rc.p, Rc.q};
-                double2 B[2][2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        B[i][j] = (xr[i] >= 0 && xr[i] < n && yc[j] >= 0 && yc[j] < n) ? hget(A, n, xr[i], yc[j])
-                                                                                      : double2{0, 0};
-                if (!idc) {
-                    // columns: new_p = cs b_p - sn e b_q ; new_q = sn b_p + cs e b_q
-                    const double2 e2 = double2{Rc.er, Rc.ei};
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        const double2 bp = B[i][0], ebq = cmulz(e2, B[i][1]);
-                        B[i][0] = double2{Rc.cs * bp.x - Rc.sn * ebq.x, Rc.cs * bp.y - Rc.sn * ebq.y};
-                        B[i][1] = double2{Rc.sn * bp.x + Rc.cs * ebq.x, Rc.sn * bp.y + Rc.cs * ebq.y};
-                    }
-                }
-                if (!idr) {
-                    // rows: new_p = cs b_p - sn conj(e) b_q ; new_q = sn b_p + cs conj(e) b_q
-                    const double2 ce = double2{Rr.er, -Rr.ei};
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const double2 bp = B[0][j], ebq = cmulz(ce, B[1][j]);
-                        B[0][j] = double2{Rr.cs * bp.x - Rr.sn * ebq.x, Rr.cs * bp.y - Rr.sn * ebq.y};
-                        B[1][j] = double2{Rr.sn * bp.x + Rr.cs * ebq.x, Rr.sn * bp.y + Rr.cs * ebq.y};
-                    }
-                }
-                if (s1 == s2) {
-                    // the rotated pair: exactly diagonal, real diagonal
-                    if (Rc.q >= 0) {
-                        hset(A, n, Rc.p, Rc.p, double2{B[0][0].x, 0.0});
-                        hset(A, n, Rc.q, Rc.q, double2{B[1][1].x, 0.0});
-                        hset(A, n, Rc.p, Rc.q, double2{0.0, 0.0});
-                    }
-                    continue;
-                }
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        if (xr[i] >= 0 && xr[i] < n && yc[j] >= 0 && yc[j] < n) hset(A, n, xr[i], yc[j], B[i][j]);
-            }
-            // V <- V J: columns p, q of V are rows p, q of Vt
-            for (int e = threadIdx.x; e < P * n; e += blockDim.x) {
-                const int sidx = e / n, r = e - sidx * n;
-                const Rot R = rot[sidx];
-                if (R.q < 0 || (R.sn == 0.0 && R.er == 1.0 && R.ei == 0.0)) continue;
-                const double2 e2 = double2{R.er, R.ei};
-                const double2 vp = Vt[R.p * n + r], eq = cmulz(e2, Vt[R.q * n + r]);
-                Vt[R.p * n + r] = double2{R.cs * vp.x - R.sn * eq.x, R.cs * vp.y - R.sn * eq.y};
-                Vt[R.q * n + r] = double2{R.sn * vp.x + R.cs * eq.x, R.sn * vp.y + R.cs * eq.y};
-            }
-            __syncthreads();
-        }
-    }
-    // ascending order by rank (ties by index), then emit
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dg[i] = A[up_idx(n, i, i)].x;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int r = 0;
-        for (int j = 0; j < n; ++j) r += (dg[j] < dg[i]) || (dg[j] == dg[i] && j < i);
-        perm[r] = i;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = dg[perm[i]];
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int r = e / n, c = e - r * n;
-        vo[e] = Vt[perm[c] * n + r];
-    }
-}
-
-// The same Jacobi method for n <= 32 in one wave, built for the latency of
-// a round: A is stored whole in LDS (row stride n + 1), so a 2x2 block is
+// Built for the latency of a round: A is stored whole in LDS (row stride n + 1), so a 2x2 block is
 // read and written without index folding; rotations take one reciprocal
 // square root of |a_pq|^2 and no division by |a_pq|; the convergence norms
 // are wave reductions; each workgroup barrier spans a single wave.
@@ -1675,25 +1245,6 @@ bool eigh_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, c
     return true;
 }
 
-__global__ void __launch_bounds__(SM_NT)
-k_jacobi_eigh(int n, const double2* __restrict__ H, double* __restrict__ eig, double2* __restrict__ vecs,
-              double2* __restrict__ scratch) {
-    extern __shared__ char smem_raw[];
-    const int64_t b = blockIdx.x;
-    jacobi_eigh_block(n, H + b * n * n, eig + b * n, vecs + b * n * n, reinterpret_cast<double2*>(smem_raw),
-                      scratch ? scratch + b * n * n : nullptr);
-}
-
-// Per work item: matrix at moff, eigenvalues at f_off, V scratch (n > 64) at moff.
-__global__ void __launch_bounds__(SM_NT)
-k_jacobi_eigh_seg(const Seg* __restrict__ seg, const double2* __restrict__ H, double* __restrict__ eig,
-                  double2* __restrict__ vecs, double2* __restrict__ scratch) {
-    extern __shared__ char smem_raw[];
-    const Seg sg = seg[blockIdx.x];
-    jacobi_eigh_block(sg.nb, H + sg.moff, eig + sg.f_off, vecs + sg.moff, reinterpret_cast<double2*>(smem_raw),
-                      scratch ? scratch + sg.moff : nullptr);
-}
-
 }  // namespace dpp
 
 using namespace dpp;
@@ -1774,7 +1325,6 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
     return DPP_OK;
 }
 
-size_t dpp::eigh_lds(int nmax) { return std::max(eigh_lds_bytes(nmax), eigh_lds_bytes(std::min(nmax, 64))); }
 
 size_t dpp::proj_ws_bytes(const dpp_basis_s* b, int nb) {
     // Pi (64 projectors max per call chunk is not assumed: use the actual count later)

@@ -89,15 +89,11 @@ __global__ void k_trace_diag(const Seg* seg, const double2* M, double* out);
 // small-matrix products
 __global__ void k_smm_mfma(const Seg* seg, int nbo, int opA, int opB, double alpha0, int alpha_omega,
                            const double2* A, const double2* B, double beta, double2* Cm);
-__global__ void k_cholesky_seg(const Seg* seg, int nbo, const double2* U, double2* Rinv, int* status,
-                               const int* act);
-__global__ void k_jacobi_eigh_seg(const Seg* seg, const double2* H, double* eig, double2* vecs, double2* scratch);
 constexpr int EIGW_MAXN = 32;  // largest matrix of the single-wave eigensolver
 constexpr int EIG_TILE_MAXN = 128;  // largest matrix of the register-tile kernels (dense.hip)
 // A Cholesky pivot R_jj^2 at or below this fraction of the largest diagonal
 // entry of U counts as "not positive definite".
 constexpr double PIVOT_RTOL = 1e-14;
-constexpr int SM_NT = 1024;    // workgroup size of the LDS small-matrix kernels for n > 64
 // Single-wave Cholesky inverse and line search for n <= 32 (false: n larger).
 bool cholesky_wave_launch(hipStream_t st, unsigned nblk, int n, int64_t stride, const Seg* seg, int nbo,
                           const double2* U, double2* Rinv, int* status, const int* act);
@@ -114,20 +110,16 @@ bool linesearch_wave_launch(hipStream_t st, unsigned nblk, int n, const Seg* seg
 // Single-wave eigensolver for up to 32 bands (false: larger).
 bool eigh_wave_launch(hipStream_t st, unsigned nblk, int nmax, const Seg* seg, const double2* H, double* eig,
                       double2* vecs);
-__global__ void k_linesearch_B(const Seg* seg, const double2* U, const double2* X, const double2* Q,
-                               const double2* H0, const double2* H1, const double2* H2, const double* E0v,
-                               const double* at0, const double* d0v, const int* act, int* ok, double* step,
-                               int stage_h, double2* Xs, double2* Ps);
 
 // dense.hip: register-tile kernels for 33..128 bands (one workgroup per
 // matrix; seg == nullptr: `nmat` matrices of order n0 at stride n0^2).
 hipError_t cholesky_tiles_launch(hipStream_t st, unsigned nmat, int nmax, const Seg* seg, int nbo, int n0,
                                  const double2* U, double2* Rinv, int* status, const int* act);
-// Rinv, M1 = U^{-1} and E0 = Re Tr(U^{-1} H0); with `step`, U and H0 first
-// advanced along the line matrices (as grad_prep_wave_launch).
+// M1 = U^{-1} and E0 = Re Tr(U^{-1} H0) (no R^{-1}); with `step`, U and H0
+// first advanced along the line matrices (as grad_prep_wave_launch).
 hipError_t grad_prep_tiles_launch(hipStream_t st, unsigned nit, int nmax, const Seg* seg, double2* U, double2* H0,
-                                  double2* Rinv, double2* M1, double* E0, int* status, const double* step,
-                                  const double2* X, const double2* Q, const double2* H1, const double2* H2);
+                                  double2* M1, double* E0, int* status, const double* step, const double2* X,
+                                  const double2* Q, const double2* H1, const double2* H2);
 hipError_t linesearch_tiles_launch(hipStream_t st, unsigned nit, int nmax, const Seg* seg, const double2* U,
                                    const double2* X, const double2* Q, const double2* H0, const double2* H1,
                                    const double2* H2, const double* E0v, const double* at0, const double* d0v,

@@ -35,6 +35,26 @@ __device__ __forceinline__ z2 zadd(z2 a, z2 b) { return z2{a.x + b.x, a.y + b.y}
 __device__ __forceinline__ z2 zsub(z2 a, z2 b) { return z2{a.x - b.x, a.y - b.y}; }
 __device__ __forceinline__ z2 zconj(z2 a) { return z2{a.x, -a.y}; }
 __device__ __forceinline__ z2 zscale(z2 a, double s) { return z2{a.x * s, a.y * s}; }
+// Complex multiply-accumulate as four FMAs (acc +- a b, with a or b conjugated):
+// written out, since the compiler does not re-associate acc - (a b) into FMAs.
+__device__ __forceinline__ z2 zfma(z2 a, z2 b, z2 acc) {  // acc + a b
+    return z2{fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y))};
+}
+__device__ __forceinline__ z2 zfms(z2 a, z2 b, z2 acc) {  // acc - a b
+    return z2{fma(-a.x, b.x, fma(a.y, b.y, acc.x)), fma(-a.x, b.y, fma(-a.y, b.x, acc.y))};
+}
+__device__ __forceinline__ z2 zcfma(z2 a, z2 b, z2 acc) {  // acc + conj(a) b
+    return z2{fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y))};
+}
+__device__ __forceinline__ z2 zcfms(z2 a, z2 b, z2 acc) {  // acc - conj(a) b
+    return z2{fma(-a.x, b.x, fma(-a.y, b.y, acc.x)), fma(-a.x, b.y, fma(a.y, b.x, acc.y))};
+}
+__device__ __forceinline__ z2 zfmac(z2 a, z2 b, z2 acc) {  // acc + a conj(b)
+    return z2{fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.y, b.x, fma(-a.x, b.y, acc.y))};
+}
+__device__ __forceinline__ z2 zfmsc(z2 a, z2 b, z2 acc) {  // acc - a conj(b)
+    return z2{fma(-a.x, b.x, fma(-a.y, b.y, acc.x)), fma(-a.y, b.x, fma(a.x, b.y, acc.y))};
+}
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -63,16 +83,32 @@ __device__ __forceinline__ Mat mat_of(const Seg* seg, int nbo, int n0, int b) {
     return Mat{n0, (int64_t)b * n0 * n0, (int64_t)b * n0, 1.0};
 }
 
-// Index of the upper tile (i, j), i <= j, in a packed tile array of T x T tiles.
-__device__ __forceinline__ int utile(int T, int i, int j) { return i * T - (i * (i - 1)) / 2 + (j - i); }
+// v, hidden from the optimizer: addresses derived from it are computed where
+// they are used instead of being hoisted to the kernel start and kept live
+// (16 of them would take the registers the tile itself needs).
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// 1/sqrt(d): the hardware estimate refined by one Newton step.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+    y = y * fma(-0.5 * d * y, y, 1.5);  // one Newton step: relative error ~ eps
+    return y;
+}
+
 
 // ------------------------------------------------ Cholesky and inverse ----
 // LDS of the factorization (aliases the staging area of the products after it).
+// Panels are stored element-major (entry e of tile j at [e][j]): the lanes of
+// a wave hold consecutive tile columns, so a panel read by all of them touches
+// consecutive 16-byte words instead of one LDS bank 32 times.
 template <int TD>
 struct CholPanels {
-    z2 dinv[TD][16];  // inverses of the diagonal tiles of R
-    z2 pr[TD][16];    // row panel
-    z2 pc[TD][16];    // column panel
+    z2 dinv[TD][16];  // inverses of the diagonal tiles of R (read by broadcast)
+    z2 pr[16][TD];    // row panel
+    z2 pc[16][TD];    // column panel
 };
 
 template <int TD>
@@ -132,19 +168,21 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
     for (int K = 0; K < T; ++K) {
         if (bi == K && bj == K) {
             int f = 0;
+            double ri[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 double d = t[r][r].x;
                 if (4 * K + r < n && !(d > thr)) f = 1;
                 if (!(d > 0.0)) d = 1.0;  // keeps the arithmetic finite after a failure
-                const double rr = sqrt(d), inv = 1.0 / rr;
-                t[r][r] = z2{rr, 0.0};
+                const double inv = rsqrt_nr(d);
+                ri[r] = inv;
+                t[r][r] = z2{d * inv, 0.0};
 #pragma unroll
                 for (int c = r + 1; c < 4; ++c) t[r][c] = zscale(t[r][c], inv);
 #pragma unroll
                 for (int s = r + 1; s < 4; ++s)
 #pragma unroll
-                    for (int c = s; c < 4; ++c) t[s][c] = zsub(t[s][c], zcmul(t[r][s], t[r][c]));
+                    for (int c = s; c < 4; ++c) t[s][c] = zcfms(t[r][s], t[r][c], t[s][c]);
 #pragma unroll
                 for (int s = r + 1; s < 4; ++s) t[s][r] = z2{0.0, 0.0};
             }
@@ -153,7 +191,7 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
             z2* xd = P.dinv[K];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const double dj = 1.0 / t[j][j].x;
+                const double dj = ri[j];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     z2 v = z2{0.0, 0.0};
@@ -161,7 +199,7 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
                         v = z2{dj, 0.0};
                     } else if (i < j) {
 #pragma unroll
-                        for (int k = i; k < j; ++k) v = zadd(v, zmul(xd[4 * i + k], t[k][j]));
+                        for (int k = i; k < j; ++k) v = zfma(xd[4 * i + k], t[k][j], v);
                         v = zscale(v, -dj);
                     }
                     xd[4 * i + j] = v;
@@ -180,9 +218,9 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
                 for (int c = 0; c < 4; ++c) {
                     z2 s = z2{0.0, 0.0};
 #pragma unroll
-                    for (int b = 0; b <= a; ++b) s = zadd(s, zcmul(P.dinv[K][4 * b + a], t[b][c]));
+                    for (int b = 0; b <= a; ++b) s = zcfma(P.dinv[K][4 * b + a], t[b][c], s);
                     t[a][c] = s;
-                    P.pr[bj][4 * a + c] = s;
+                    P.pr[4 * a + c][bj] = s;
                 }
         }
         __syncthreads();
@@ -193,12 +231,12 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
             for (int b = 0; b < 4; ++b) {
                 z2 pi[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) pi[a] = P.pr[bi][4 * b + a];
+                for (int a = 0; a < 4; ++a) pi[a] = P.pr[4 * b + a][bi];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const z2 pj = P.pr[bj][4 * b + c];
+                    const z2 pj = P.pr[4 * b + c][bj];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) t[a][c] = zsub(t[a][c], zcmul(pi[a], pj));
+                    for (int a = 0; a < 4; ++a) t[a][c] = zcfms(pi[a], pj, t[a][c]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -216,7 +254,7 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    P.pr[bj][4 * a + c] = t[a][c];
+                    P.pr[4 * a + c][bj] = t[a][c];
                     t[a][c] = z2{0.0, 0.0};
                 }
         }
@@ -235,14 +273,14 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
                     for (int c = 3; c >= 0; --c) {
                         z2 s = z2{0.0, 0.0};
 #pragma unroll
-                        for (int b = 0; b <= c; ++b) s = zadd(s, zmul(t[a][b], P.dinv[K][4 * b + c]));
+                        for (int b = 0; b <= c; ++b) s = zfma(t[a][b], P.dinv[K][4 * b + c], s);
                         t[a][c] = z2{-s.x, -s.y};
                     }
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) P.pc[bi][4 * a + c] = t[a][c];
+                for (int c = 0; c < 4; ++c) P.pc[4 * a + c][bi] = t[a][c];
         }
         __syncthreads();
         if (bi <= K && K < bj && bj < T) {
@@ -250,12 +288,12 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
             for (int b = 0; b < 4; ++b) {
                 z2 xc[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) xc[a] = P.pc[bi][4 * a + b];
+                for (int a = 0; a < 4; ++a) xc[a] = P.pc[4 * a + b][bi];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const z2 rr = P.pr[bj][4 * b + c];
+                    const z2 rr = P.pr[4 * b + c][bj];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) t[a][c] = zadd(t[a][c], zmul(xc[a], rr));
+                    for (int a = 0; a < 4; ++a) t[a][c] = zfma(xc[a], rr, t[a][c]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -263,47 +301,6 @@ __device__ __attribute__((always_inline)) int chol_inv_tiles(int n, z2 (&t)[4][4
         __syncthreads();
     }
     return 0;
-}
-
-// X (upper tiles of t) into the packed LDS tile array; then every thread
-// replaces t by its tile of M1 = X X^dag = U^{-1}: M1_ij = sum_{k >= max(i,j)} X_ik X_jk^dag.
-template <int TD>
-__device__ __attribute__((always_inline)) void inverse_product_tiles(int n, z2 (&t)[4][4], z2* __restrict__ stage) {
-    const int tid = threadIdx.x, bi = tid / TD, bj = tid % TD;
-    const int T = (n + 3) >> 2;
-    if (bi <= bj && bj < T) {
-        z2* p = stage + 16 * utile(T, bi, bj);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) p[4 * a + c] = t[a][c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) t[a][c] = z2{0.0, 0.0};
-    if (bi < T && bj < T) {
-#pragma unroll 1
-        for (int k = max(bi, bj); k < T; ++k) {
-            const z2* A = stage + 16 * utile(T, bi, k);
-            const z2* B = stage + 16 * utile(T, bj, k);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                z2 xa[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) xa[a] = A[4 * a + b];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const z2 xb = B[4 * c + b];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) t[a][c] = zadd(t[a][c], zmulc(xa[a], xb));
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-    }
-    __syncthreads();  // the staging area may be reused
 }
 
 // f(a, c, r, col, in) over the tile's entries, one at a time: the scheduling
@@ -325,7 +322,8 @@ __device__ __forceinline__ void for_tile(int bi, int bj, int n, F f) {
 
 template <int TD>
 __device__ void store_tile(int n, const z2 (&t)[4][4], z2* __restrict__ out) {
-    const int bi = threadIdx.x / TD, bj = threadIdx.x % TD;
+    const int tid = opaque(threadIdx.x);
+    const int bi = tid / TD, bj = tid % TD;
     for_tile(bi, bj, n, [&](int a, int c, int r, int col, bool in) {
         if (in) out[(int64_t)r * n + col] = t[a][c];
     });
@@ -339,6 +337,170 @@ __device__ void store_nan(int n, z2* __restrict__ out) {
     });
 }
 
+// ------------------------------------------- Gauss-Jordan inverse -------
+// U^{-1} of a Hermitian positive-definite matrix in place on the register
+// tiles, by block Gauss-Jordan elimination with the 4 x 4 diagonal blocks as
+// pivots (no pivoting: U is positive definite).  Step K, with P = A_KK:
+//   A_KK <- P^{-1},  A_Kj <- P^{-1} A_Kj,  A_iK <- -A_iK P^{-1},
+//   A_ij <- A_ij - A_iK P^{-1} A_Kj   (i, j != K).
+// One pass of T steps replaces the factorization, the triangular inverse and
+// the product R^{-1} R^{-dag}; each step's serial part is one 4 x 4 inverse.
+// The diagonal blocks' Cholesky pivots are those of U's own factorization, so
+// the positive-definiteness test is the same (R_jj^2 > PIVOT_RTOL max_i U_ii).
+template <int TD>
+struct GJShared {
+    z2 pinv[2][16];   // P^{-1} of the step (double-buffered by step parity)
+    z2 cp[2][16][TD]; // column panel A_iK before the step, element-major
+    z2 rp[16][TD];    // row panel P^{-1} A_Kj, element-major
+};
+
+// In-place P <- P^{-1} for a Hermitian positive-definite 4 x 4 tile (upper
+// triangle read); pivots of rows < nvalid are tested against thr.  The
+// inverse goes to out (16 entries, row-major); p keeps R^{-1}.
+__device__ __forceinline__ int hpd_inv4(z2 (&p)[4][4], double thr, int nvalid, z2* __restrict__ out) {
+    int f = 0;
+    double ri[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double d = p[r][r].x;
+        if (r < nvalid && !(d > thr)) f = 1;
+        if (!(d > 0.0)) d = 1.0;  // keeps the arithmetic finite after a failure
+        const double y = rsqrt_nr(d);
+        ri[r] = y;
+        p[r][r] = z2{d * y, 0.0};
+#pragma unroll
+        for (int c = r + 1; c < 4; ++c) p[r][c] = zscale(p[r][c], y);
+#pragma unroll
+        for (int s = r + 1; s < 4; ++s)
+#pragma unroll
+            for (int c = s; c < 4; ++c) p[s][c] = zcfms(p[r][s], p[r][c], p[s][c]);
+    }
+    // X = R^{-1} in place, column by column (X_ii = 1 / R_ii)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            z2 s = zscale(p[i][j], ri[i]);
+#pragma unroll
+            for (int k = i + 1; k < j; ++k) s = zfma(p[i][k], p[k][j], s);
+            p[i][j] = zscale(s, -ri[j]);
+        }
+        p[j][j] = z2{ri[j], 0.0};
+    }
+    // P^{-1} = X X^dag
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            z2 s = z2{0.0, 0.0};
+#pragma unroll
+            for (int k = (a > b ? a : b); k < 4; ++k) s = zfmac(p[a][k], p[b][k], s);
+            out[4 * a + b] = s;
+        }
+    return f;
+}
+
+// t: this thread's tile of U (every tile of the T x T grid; identity beyond
+// n).  On success t holds its tile of U^{-1}; returns 1 (uniformly) on a
+// failed pivot test.
+template <int TD>
+__device__ __attribute__((always_inline)) int gj_inverse_tiles(int n, z2 (&t)[4][4], GJShared<TD>& G,
+                                                               TileShared<TD>& S) {
+    const int tid = threadIdx.x, bi = tid / TD, bj = tid % TD;
+    const int T = (n + 3) >> 2;
+    const bool in = bi < T && bj < T;
+    double m = 0.0;
+    if (bi == bj && in) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            if (4 * bi + a < n) m = fmax(m, t[a][a].x);
+    }
+    if (tid == 0) S.fail = 0;
+    const double thr = PIVOT_RTOL * block_max<TD>(m, S);
+#pragma unroll 1
+    for (int K = 0; K < T; ++K) {
+        const int b = K & 1;
+        // the pivot block's inverse (its owner), and the column panel
+        if (bi == K && bj == K) {
+            if (hpd_inv4(t, thr, n - 4 * K, G.pinv[b])) S.fail = 1;
+        }
+        if (bj == K && bi != K && bi < T) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) G.cp[b][4 * a + c][bi] = t[a][c];
+        }
+        __syncthreads();
+        if (S.fail) break;  // uniform: read after the barrier
+        // row panel P^{-1} A_Kj (A_KK <- P^{-1})
+        if (bi == K && bj < T) {
+            if (bj == K) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) t[a][c] = G.pinv[b][4 * a + c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    // (re-read per column: 16 entries kept live would not fit beside the tile)
+                    const z2* pv = G.pinv[b] + opaque(0);
+                    z2 o[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        z2 s = z2{0.0, 0.0};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) s = zfma(pv[4 * a + k], t[k][c], s);
+                        o[a] = s;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        t[a][c] = o[a];
+                        G.rp[4 * a + c][bj] = o[a];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // elimination in the other block rows
+        if (bi != K && in) {
+            if (bj != K) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    z2 ci[4];
+                    const int ob = opaque(0);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) ci[a] = G.cp[b][4 * a + k][bi + ob];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const z2 r = G.rp[4 * k + c][bj];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) t[a][c] = zfms(ci[a], r, t[a][c]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const z2* pv = G.pinv[b] + opaque(0);
+                    z2 o[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        z2 s = z2{0.0, 0.0};
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) s = zfma(t[a][k], pv[4 * k + c], s);
+                        o[c] = s;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) t[a][c] = z2{-o[c].x, -o[c].y};
+                }
+            }
+        }
+    }
+    const int failed = S.fail;
+    __syncthreads();
+    return failed;
+}
+
 // ---------------------------------------------------------- kernels ---------
 // Cholesky inverse Rinv = R^{-1} (upper, zero below) of every matrix.
 template <int TD>
@@ -346,8 +508,7 @@ __global__ void __launch_bounds__(TD* TD)
 k_cholesky_tiles(const Seg* __restrict__ seg, int nbo, int n0, const z2* __restrict__ U, z2* __restrict__ Rinv,
                  int* __restrict__ status, const int* __restrict__ act) {
     if (act && !act[blockIdx.x]) return;
-    extern __shared__ char smem_raw[];
-    CholPanels<TD>& P = *reinterpret_cast<CholPanels<TD>*>(smem_raw);
+    __shared__ CholPanels<TD> P;
     __shared__ TileShared<TD> S;
     const Mat M = mat_of(seg, nbo, n0, blockIdx.x);
     const int n = M.n;
@@ -369,18 +530,16 @@ k_cholesky_tiles(const Seg* __restrict__ seg, int nbo, int n0, const z2* __restr
 
 // Band-gradient preparation per item: (with `step`) U and H0 advanced along
 // the line matrices, U <- U + a (X + X^dag) + a^2 Q, H0 <- H0 + a (H1 + H1^dag)
-// + a^2 H2, and written back; then Rinv = R^{-1}, M1 = U^{-1} = Rinv Rinv^dag
-// and E0 = Re Tr(U^{-1} H0).  On a failed factorization Rinv, M1 and E0 are
-// NaN and the status word latches DPP_STATUS_NOTPD.
+// + a^2 H2, and written back; then M1 = U^{-1} and E0 = Re Tr(U^{-1} H0).
+// On a failed pivot test M1 and E0 are NaN and the status word latches
+// DPP_STATUS_NOTPD.
 template <int TD>
 __global__ void __launch_bounds__(TD* TD)
-k_grad_prep_tiles(const Seg* __restrict__ seg, z2* __restrict__ U, z2* __restrict__ H0, z2* __restrict__ Rinv,
-                  z2* __restrict__ M1, double* __restrict__ E0, int* __restrict__ status,
-                  const double* __restrict__ step, const z2* __restrict__ X, const z2* __restrict__ Q,
-                  const z2* __restrict__ H1, const z2* __restrict__ H2) {
-    extern __shared__ char smem_raw[];
-    CholPanels<TD>& P = *reinterpret_cast<CholPanels<TD>*>(smem_raw);
-    z2* stage = reinterpret_cast<z2*>(smem_raw);
+k_grad_prep_tiles(const Seg* __restrict__ seg, z2* __restrict__ U, z2* __restrict__ H0, z2* __restrict__ M1,
+                  double* __restrict__ E0, int* __restrict__ status, const double* __restrict__ step,
+                  const z2* __restrict__ X, const z2* __restrict__ Q, const z2* __restrict__ H1,
+                  const z2* __restrict__ H2) {
+    __shared__ GJShared<TD> G;
     __shared__ TileShared<TD> S;
     const Mat M = mat_of(seg, 0, 0, blockIdx.x);
     const int n = M.n;
@@ -411,20 +570,16 @@ k_grad_prep_tiles(const Seg* __restrict__ seg, z2* __restrict__ U, z2* __restric
         }
         t[a][c] = u;
     });
-    const int f = chol_inv_tiles<TD>(n, t, P, S);
-    if (f) {
+    if (gj_inverse_tiles<TD>(n, t, G, S)) {
         if (threadIdx.x == 0) {
             if (status) atomicOr(status, DPP_STATUS_NOTPD);
             E0[blockIdx.x] = NAN;
         }
-        store_nan<TD>(n, Rinv + o);
         store_nan<TD>(n, M1 + o);
         return;
     }
-    store_tile<TD>(n, t, Rinv + o);
-    inverse_product_tiles<TD>(n, t, stage);
     store_tile<TD>(n, t, M1 + o);
-    // Re Tr(M1 H0) = sum over entries of Re(conj(M1) H0) (M1 Hermitian)
+    // Re Tr(M1 H0) = sum over entries of Re(conj(M1) H0) (both Hermitian)
     double e = 0.0;
     for_tile(bi, bj, n, [&](int a, int c, int r, int col, bool in) {
         if (in) {
@@ -445,17 +600,20 @@ k_grad_prep_tiles(const Seg* __restrict__ seg, z2* __restrict__ U, z2* __restric
 constexpr int LS_TRIES = 6;
 
 template <int TD>
-__device__ __attribute__((always_inline)) double trial_energy_tiles(const Mat& M, double al, const z2* __restrict__ U, const z2* __restrict__ X,
-                                     const z2* __restrict__ Q, const z2* __restrict__ H0,
-                                     const z2* __restrict__ H1, const z2* __restrict__ H2, CholPanels<TD>& P,
-                                     z2* stage, TileShared<TD>& S) {
+__device__ __attribute__((noinline)) double trial_energy_tiles(const Mat& M, double al, const z2* __restrict__ U,
+                                                                    const z2* __restrict__ X,
+                                                                    const z2* __restrict__ Q,
+                                                                    const z2* __restrict__ H0,
+                                                                    const z2* __restrict__ H1,
+                                                                    const z2* __restrict__ H2, GJShared<TD>& G,
+                                                                    TileShared<TD>& S) {
     const int n = M.n;
     const int64_t o = M.moff;
     const int bi = threadIdx.x / TD, bj = threadIdx.x % TD;
     z2 t[4][4];
     for_tile(bi, bj, n, [&](int a, int c, int r, int col, bool in) {
         z2 u = z2{r == col ? 1.0 : 0.0, 0.0};
-        if (in && bi <= bj) {
+        if (in) {
             const int64_t e = o + (int64_t)r * n + col, et = o + (int64_t)col * n + r;
             const z2 x = X[e], xt = X[et], q = Q[e];
             u = U[e];
@@ -463,8 +621,7 @@ __device__ __attribute__((always_inline)) double trial_energy_tiles(const Mat& M
         }
         t[a][c] = u;
     });
-    if (chol_inv_tiles<TD>(n, t, P, S)) return NAN;
-    inverse_product_tiles<TD>(n, t, stage);
+    if (gj_inverse_tiles<TD>(n, t, G, S)) return NAN;
     double e = 0.0;
     for_tile(bi, bj, n, [&](int a, int c, int r, int col, bool in) {
         if (in) {
@@ -487,9 +644,7 @@ k_linesearch_tiles(const Seg* __restrict__ seg, const z2* __restrict__ U, const 
                    double* __restrict__ step) {
     const int k = blockIdx.x;
     if (!act[k]) return;
-    extern __shared__ char smem_raw[];
-    CholPanels<TD>& P = *reinterpret_cast<CholPanels<TD>*>(smem_raw);
-    z2* stage = reinterpret_cast<z2*>(smem_raw);
+    __shared__ GJShared<TD> G;
     __shared__ TileShared<TD> S;
     const Mat M = mat_of(seg, 0, 0, k);
     const double E0 = E0v[k], d0 = d0v[k];
@@ -498,11 +653,11 @@ k_linesearch_tiles(const Seg* __restrict__ seg, const z2* __restrict__ U, const 
     double st = 0.0;
 #pragma unroll 1
     for (int tr = 0; tr < LS_TRIES; ++tr) {
-        const double Et = trial_energy_tiles<TD>(M, at, U, X, Q, H0, H1, H2, P, stage, S);
+        const double Et = trial_energy_tiles<TD>(M, at, U, X, Q, H0, H1, H2, G, S);
         const double c = (Et - E0 - d0 * at) / (at * at);
         double as = c > 0 ? -d0 / (2.0 * c) : 2.0 * at;
         as = fmin(as, 10.0 * at);
-        const double Es = trial_energy_tiles<TD>(M, as, U, X, Q, H0, H1, H2, P, stage, S);
+        const double Es = trial_energy_tiles<TD>(M, as, U, X, Q, H0, H1, H2, G, S);
         if (Es <= E0) {
             good = 1;
             st = as;
@@ -573,15 +728,23 @@ __device__ __forceinline__ z2* eigh_base(z2* ws, const Seg* seg, int n0, int b) 
     return ws + (int64_t)EIGH_WS_PER_N2 * b * n0 * n0;
 }
 
+// Vectors of length n are stored permuted, row r at (r % 4)(TD + 1) + r / 4:
+// the lanes of a wave read entry c of consecutive tiles (rows 4j + c) and
+// consecutive rows from consecutive 16-byte words.  The partial products are
+// [row][tile column] with a padded row.
 template <int TD>
 struct TriShared {
-    z2 xb[2][4 * TD];
-    z2 yb[4 * TD];
-    z2 vb[4 * TD];
-    z2 part[TD][4 * TD];
+    static constexpr int PS = TD + 1;
+    z2 xb[2][4 * PS];
+    z2 yb[4 * PS];
+    z2 vb[4 * PS];
+    z2 part[4 * TD][PS];
     double d[4 * TD], e[4 * TD];
     z2 clast;
 };
+
+template <int TD>
+__device__ __forceinline__ int vperm(int r) { return (r & 3) * (TD + 1) + (r >> 2); }
 
 template <int TD>
 __global__ void __launch_bounds__(TD* TD)
@@ -621,15 +784,18 @@ k_eigh_tridiag(const Seg* __restrict__ seg, int n0, const z2* __restrict__ H, z2
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     if (c == kc) v = t[a][c];
-                if (r > k && r < n) xb[r] = v;
+                if (r > k && r < n) xb[vperm<TD>(r)] = v;
                 if (r == k) L.d[k] = v.x;
             }
         }
         __syncthreads();
         // the reflector (every wave computes it, identically)
-        const z2 al = xb[k + 1];
+        const z2 al = xb[vperm<TD>(k + 1)];
         double xn2 = 0.0;
-        for (int r = k + 2 + lane; r < n; r += 64) xn2 += xb[r].x * xb[r].x + xb[r].y * xb[r].y;
+        for (int r = k + 2 + lane; r < n; r += 64) {
+            const z2 x = xb[vperm<TD>(r)];
+            xn2 += x.x * x.x + x.y * x.y;
+        }
         xn2 = wsum(xn2);
         z2 tau = z2{0.0, 0.0}, sc = z2{0.0, 0.0};
         double beta = al.x;
@@ -641,7 +807,7 @@ k_eigh_tridiag(const Seg* __restrict__ seg, int n0, const z2* __restrict__ H, z2
             sc = z2{zz.x / m2, -zz.y / m2};
         }
         auto vof = [&](int r) -> z2 {
-            return r == k + 1 ? z2{1.0, 0.0} : (r > k + 1 && r < n ? zmul(xb[r], sc) : z2{0.0, 0.0});
+            return r == k + 1 ? z2{1.0, 0.0} : (r > k + 1 && r < n ? zmul(xb[vperm<TD>(r)], sc) : z2{0.0, 0.0});
         };
         if (tid < 64) {
             for (int r = lane; r < n; r += 64) W.refl[(int64_t)k * n + r] = vof(r);
@@ -660,8 +826,8 @@ k_eigh_tridiag(const Seg* __restrict__ seg, int n0, const z2* __restrict__ H, z2
             for (int a = 0; a < 4; ++a) {
                 z2 p = z2{0.0, 0.0};
 #pragma unroll
-                for (int c = 0; c < 4; ++c) p = zadd(p, zmul(t[a][c], vj[c]));
-                L.part[bj][4 * bi + a] = p;
+                for (int c = 0; c < 4; ++c) p = zfma(t[a][c], vj[c], p);
+                L.part[4 * bi + a][bj] = p;
             }
         }
         __syncthreads();
@@ -676,7 +842,7 @@ k_eigh_tridiag(const Seg* __restrict__ seg, int n0, const z2* __restrict__ H, z2
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int b = s + LPR * q;
-                    if (b < T && 4 * b + 3 > k) y = zadd(y, L.part[b][r]);
+                    if (b < T && 4 * b + 3 > k) y = zadd(y, L.part[r][b]);
                 }
             }
 #pragma unroll
@@ -685,15 +851,15 @@ k_eigh_tridiag(const Seg* __restrict__ seg, int n0, const z2* __restrict__ H, z2
                 y.y += __shfl_xor(y.y, o);
             }
             if (s == 0) {
-                L.yb[r] = live ? y : z2{0.0, 0.0};
-                L.vb[r] = vof(r);
+                L.yb[vperm<TD>(r)] = live ? y : z2{0.0, 0.0};
+                L.vb[vperm<TD>(r)] = vof(r);
             }
         }
         __syncthreads();
         // A <- A - v w^dag - w v^dag, w = tau y - (|tau|^2/2)(v^dag y) v
         double sv = 0.0;
         for (int r = k + 1 + lane; r < n; r += 64) {
-            const z2 v = L.vb[r], y = L.yb[r];
+            const z2 v = L.vb[vperm<TD>(r)], y = L.yb[vperm<TD>(r)];
             sv += v.x * y.x + v.y * y.y;
         }
         sv = wsum(sv);
@@ -702,18 +868,18 @@ k_eigh_tridiag(const Seg* __restrict__ seg, int n0, const z2* __restrict__ H, z2
             z2 vc[4], wc[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                vc[c] = L.vb[4 * bj + c];
-                const z2 ty = zmul(tau, L.yb[4 * bj + c]);
+                vc[c] = L.vb[vperm<TD>(4 * bj + c)];
+                const z2 ty = zmul(tau, L.yb[vperm<TD>(4 * bj + c)]);
                 wc[c] = z2{ty.x - coef * vc[c].x, ty.y - coef * vc[c].y};
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-                const z2 vr = L.vb[4 * bi + a];
-                const z2 ty = zmul(tau, L.yb[4 * bi + a]);
+                const z2 vr = L.vb[vperm<TD>(4 * bi + a)];
+                const z2 ty = zmul(tau, L.yb[vperm<TD>(4 * bi + a)]);
                 const z2 wr = z2{ty.x - coef * vr.x, ty.y - coef * vr.y};
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    t[a][c] = zsub(t[a][c], zadd(zmulc(vr, wc[c]), zmulc(wr, vc[c])));
+                    t[a][c] = zfmsc(wr, vc[c], zfmsc(vr, wc[c], t[a][c]));
             }
         }
     }
@@ -982,7 +1148,7 @@ k_eigh_back(const Seg* __restrict__ seg, int n0, z2* __restrict__ ws, const int*
             const int kk = k - kbeg;
             z2 dt = z2{0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) dt = zadd(dt, zcmul(vs[kk][s + 16 * j], w[j]));
+            for (int j = 0; j < RPT; ++j) dt = zcfma(vs[kk][s + 16 * j], w[j], dt);
 #pragma unroll
             for (int o = 8; o > 0; o >>= 1) {
                 dt.x += __shfl_xor(dt.x, o, 16);
@@ -990,7 +1156,7 @@ k_eigh_back(const Seg* __restrict__ seg, int n0, z2* __restrict__ ws, const int*
             }
             const z2 tv = zmul(ts[kk], dt);
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) w[j] = zsub(w[j], zmul(vs[kk][s + 16 * j], tv));
+            for (int j = 0; j < RPT; ++j) w[j] = zfms(vs[kk][s + 16 * j], tv, w[j]);
         }
     }
     if (col < n) {
@@ -1003,19 +1169,6 @@ k_eigh_back(const Seg* __restrict__ seg, int n0, z2* __restrict__ ws, const int*
     }
 }
 
-template <int TD>
-size_t chol_lds(int n) {
-    const int T = (n + 3) / 4;
-    return std::max(sizeof(CholPanels<TD>), (size_t)T * (T + 1) / 2 * 16 * sizeof(z2));
-}
-
-template <typename K>
-hipError_t allow_lds(K kern, size_t bytes) {
-    if (bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
-}
-
 }  // namespace
 
 // ----------------------------------------------------------- launches ------
@@ -1025,33 +1178,22 @@ size_t eigh_perm_bytes(int nmat) { return (size_t)nmat * EIG_TILE_MAXN * sizeof(
 
 hipError_t cholesky_tiles_launch(hipStream_t st, unsigned nmat, int nmax, const Seg* seg, int nbo, int n0,
                                  const double2* U, double2* Rinv, int* status, const int* act) {
-    if (nmax <= 64) {
-        const size_t lds = chol_lds<16>(nmax);
-        hipLaunchKernelGGL(k_cholesky_tiles<16>, dim3(nmat), dim3(256), lds, st, seg, nbo, n0, U, Rinv, status, act);
-    } else {
-        const size_t lds = chol_lds<32>(nmax);
-        hipError_t e = allow_lds(k_cholesky_tiles<32>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_cholesky_tiles<32>, dim3(nmat), dim3(1024), lds, st, seg, nbo, n0, U, Rinv, status,
-                           act);
-    }
+    if (nmax <= 64)
+        hipLaunchKernelGGL(k_cholesky_tiles<16>, dim3(nmat), dim3(256), 0, st, seg, nbo, n0, U, Rinv, status, act);
+    else
+        hipLaunchKernelGGL(k_cholesky_tiles<32>, dim3(nmat), dim3(1024), 0, st, seg, nbo, n0, U, Rinv, status, act);
     return hipGetLastError();
 }
 
 hipError_t grad_prep_tiles_launch(hipStream_t st, unsigned nit, int nmax, const Seg* seg, double2* U, double2* H0,
-                                  double2* Rinv, double2* M1, double* E0, int* status, const double* step,
-                                  const double2* X, const double2* Q, const double2* H1, const double2* H2) {
-    if (nmax <= 64) {
-        const size_t lds = chol_lds<16>(nmax);
-        hipLaunchKernelGGL(k_grad_prep_tiles<16>, dim3(nit), dim3(256), lds, st, seg, U, H0, Rinv, M1, E0, status,
-                           step, X, Q, H1, H2);
-    } else {
-        const size_t lds = chol_lds<32>(nmax);
-        hipError_t e = allow_lds(k_grad_prep_tiles<32>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_grad_prep_tiles<32>, dim3(nit), dim3(1024), lds, st, seg, U, H0, Rinv, M1, E0, status,
-                           step, X, Q, H1, H2);
-    }
+                                  double2* M1, double* E0, int* status, const double* step, const double2* X,
+                                  const double2* Q, const double2* H1, const double2* H2) {
+    if (nmax <= 64)
+        hipLaunchKernelGGL(k_grad_prep_tiles<16>, dim3(nit), dim3(256), 0, st, seg, U, H0, M1, E0, status, step, X, Q,
+                           H1, H2);
+    else
+        hipLaunchKernelGGL(k_grad_prep_tiles<32>, dim3(nit), dim3(1024), 0, st, seg, U, H0, M1, E0, status, step, X,
+                           Q, H1, H2);
     return hipGetLastError();
 }
 
@@ -1059,17 +1201,12 @@ hipError_t linesearch_tiles_launch(hipStream_t st, unsigned nit, int nmax, const
                                    const double2* X, const double2* Q, const double2* H0, const double2* H1,
                                    const double2* H2, const double* E0v, const double* at0, const double* d0v,
                                    const int* act, int* ok, double* step) {
-    if (nmax <= 64) {
-        const size_t lds = chol_lds<16>(nmax);
-        hipLaunchKernelGGL(k_linesearch_tiles<16>, dim3(nit), dim3(256), lds, st, seg, U, X, Q, H0, H1, H2, E0v,
-                           at0, d0v, act, ok, step);
-    } else {
-        const size_t lds = chol_lds<32>(nmax);
-        hipError_t e = allow_lds(k_linesearch_tiles<32>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_linesearch_tiles<32>, dim3(nit), dim3(1024), lds, st, seg, U, X, Q, H0, H1, H2, E0v,
-                           at0, d0v, act, ok, step);
-    }
+    if (nmax <= 64)
+        hipLaunchKernelGGL(k_linesearch_tiles<16>, dim3(nit), dim3(256), 0, st, seg, U, X, Q, H0, H1, H2, E0v, at0,
+                           d0v, act, ok, step);
+    else
+        hipLaunchKernelGGL(k_linesearch_tiles<32>, dim3(nit), dim3(1024), 0, st, seg, U, X, Q, H0, H1, H2, E0v, at0,
+                           d0v, act, ok, step);
     return hipGetLastError();
 }
 

@@ -603,11 +603,12 @@ dpp_status grad_B(dpp_system_s* s, const double2* Y, bool after_step = false) {
                                       s->M2, s->d_bE0, s->ctx->d_status, after_step ? s->cg.stepf : nullptr, s->X,
                                       s->Q, s->H1, s->H2);
         if (fused) DPP_LAUNCHED();
-        // more bands: factor, U^{-1} and E0 on register tiles, one workgroup per item
+        // more bands: U^{-1} and E0 on register tiles, one workgroup per item
+        // (R^{-1} is formed where it is used, in the subspace rotation)
         if (!fused)
-            DPP_HIP(grad_prep_tiles_launch(stream(s), (unsigned)s->nit, s->maxnb, s->d_seg, s->U, s->H0, s->Rinv,
-                                           s->M1, s->d_bE0, s->ctx->d_status, after_step ? s->cg.stepf : nullptr,
-                                           s->X, s->Q, s->H1, s->H2));
+            DPP_HIP(grad_prep_tiles_launch(stream(s), (unsigned)s->nit, s->maxnb, s->d_seg, s->U, s->H0, s->M1,
+                                           s->d_bE0, s->ctx->d_status, after_step ? s->cg.stepf : nullptr, s->X,
+                                           s->Q, s->H1, s->H2));
     }
     if (!fused) {
         // M2 = -Omega Uinv H0 Uinv
@@ -694,6 +695,8 @@ dpp_status cgB_step(dpp_system_s* s, double2* Y) {
 // Subspace rotation at the current band-CG state: psi = Y R^{-1}, H~ = psi^dag H psi,
 // H~ V = V eps; Y <- psi V, HY <- (H psi) V; eigenvalues to d_eig.
 dpp_status subspace_rotate(dpp_system_s* s, double2* Y) {
+    // the single-wave gradient preparation leaves R^{-1}; the tile one does not
+    if (s->maxnb > EIGW_MAXN) DPP_TRY(chol_all(s, 0, s->U, s->Rinv));
     DPP_TRY(rotate_jobs(s, 0, {RotJob{Y, s->Rinv, 0.0, s->psi}, RotJob{s->HY, s->Rinv, 0.0, s->T1}}));
     DPP_TRY(overlap_jobs(s, 0, {OvJob{s->psi, s->T1, 1.0, false, s->H0}}));
     {

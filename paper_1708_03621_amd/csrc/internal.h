@@ -311,7 +311,6 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
                        const double2* B, int64_t ldB, double scale, double2* U, void* ws,
                        size_t ws_bytes);
 size_t overlap_ws_bytes(int npw, int nbA, int nbB);
-size_t eigh_lds(int nmax);   // LDS bytes of the eigensolver for matrices up to nmax
 size_t proj_ws_bytes(const dpp_basis_s* b, int nb);
 dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
                       const double2* M, double beta, double2* out, int64_t ldout);
