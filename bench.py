@@ -1,23 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the DFT++ band-minimization hot path on one MI355X.
 
-Workload: the 8-atom diamond-structure cell (a = 10.26 bohr, Z = 4, erf local
-potential r_c = 0.7, one Gaussian s-projector per atom), Ecut 12 Ha, FFT box
-40^3, 16 bands, Gamma-centred 2x2x2 k folding (8 k-points with G-spheres of
-2103-2176 plane waves).  Seeded synthetic inputs; inputs are resident in HBM
-before the timed region starts.
+Workload (default): the 64-atom diamond supercell (2x2x2 of the a = 10.26
+bohr cell, L = 20.52 bohr, atoms displaced by N(0, 0.1^2), Z = 4, erf local
+potential r_c = 0.7, one Gaussian s-projector per atom), Ecut 15 Ha (23847
+plane waves), FFT box 90^3, 128 bands, Gamma only: the largest single-GPU
+configuration.  Seeded synthetic inputs; inputs are resident in HBM before
+the timed region starts.
 
 One step = one SCF iteration (the whole hot path): V_eff from the input
-density (Hartree solve, LDA), three band-CG steps per k-point (H applied via
+density (Hartree solve, LDA), three band-CG steps (H applied via
 sphere<->grid FFTs with the fused potential multiply, kinetic and projector
-terms; overlaps and Cholesky orthonormalization; gradient, preconditioner,
-line search), subspace diagonalization, fillings, output density, energy,
-Pulay mixing.
+terms; overlaps and the inverse overlap; gradient, preconditioner, line
+search), orthonormalization and subspace diagonalization, fillings, output
+density, energy, Pulay mixing.
 
 `value` is the H.C throughput of the step: (band, k-point) H applications
 performed inside the timed SCF iterations divided by their wall time.  The
-isolated H.C rate of the whole block and the seconds per SCF iteration are
-reported beside it.  Usage: python bench.py [--steps K] [--warmup W].
+isolated H.C rate of the whole block, the seconds per SCF iteration of the
+FP64 and mixed-precision systems, the iterations to 1e-6 Ha/atom of an FP64
+reference converged to 1e-10 Ha/atom, the roofline fractions of the dominant
+HBM-bound kernel and of the MFMA contractions, and the same timings for the
+8-atom cell with 8 k-points and for the 48-cell batch are reported beside it.
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload config3|config2|config4]
+       python bench.py --pmc-probe {apply_H,copy} [--workload ...]   (a short
+       loop for rocprofv3 counter collection: the system's H application, or
+       a 256 MiB device copy that calibrates FETCH_SIZE / WRITE_SIZE)
 """
 from __future__ import annotations
 
@@ -27,7 +36,12 @@ import os
 import sys
 import time
 
-import numpy as np
+# the CPU oracle sample runs on one thread per process (set before NumPy loads
+# its BLAS); the GPU path does not use these libraries
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
+
+import numpy as np  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -35,17 +49,21 @@ sys.path.insert(0, ROOT)
 METRIC = "H·C bands·k/s and s per SCF iter, mixed vs FP64 GPU at 1e-6 Ha/atom"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-
+MAX_WORKERS = 16  # the GPU machine's CPU share for one GPU
 
 WORKLOADS = {
     "config2": "diamond 8-atom cubic cell a=10.26 bohr, Ecut 12 Ha, FFT 40^3, 16 bands, Gamma-centred 2x2x2 k "
-               "(8 k-points), one SCF iteration per step (3 band-CG steps/k)",
-    "config3": "64-atom diamond supercell L=20.52 bohr displaced N(0,0.1^2), Ecut 15 Ha, FFT 90^3, 128 bands, "
-               "Gamma only, one SCF iteration per step (3 band-CG steps)",
+               "(8 k-points, 2103-2176 plane waves), one SCF iteration per step (3 band-CG steps/k)",
+    "config3": "64-atom diamond supercell L=20.52 bohr displaced N(0,0.1^2), Ecut 15 Ha (23847 plane waves), "
+               "FFT 90^3, 128 bands, Gamma only, one SCF iteration per step (3 band-CG steps)",
     "config4": "48 independent cubic cells (edges 8-14 bohr, 2-16 atoms Z in {1,4}, Ecut 10 Ha, FFT 24^3-40^3, "
                "4-32 bands, 1-8 k-points; 171 cell/k items) batched into single launches, one SCF iteration of "
                "every cell per step (3 band-CG steps/k)",
 }
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash(files):
@@ -77,58 +95,249 @@ def cells_for(name):
     return {"config2": lambda: [W.config2()], "config3": lambda: [W.config3()], "config4": W.config4}[name]()
 
 
-def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
 
-def cpu_baseline(budget_s: float = 20.0):
-    """The FP64 oracle (NumPy, 1 thread) on a bounded sample of the same workload:
-    SCF iterations of config 2, counting (band, k) H applications."""
+# ----------------------------------------------------------- CPU oracle ------
+_ORACLE = {}
+
+
+def _oracle_setup(workload):
+    """The oracle system of the workload's first cell and its start potential."""
+    import workloads as W
+    from oracle import energy as oe
+    cell = cells_for(workload)[0]
+    s = oe.build_system(cell)
+    n0 = oe.start_density(cell, W.START_SIGMA)
+    Veff, _ = oe.potentials(n0, s)
+    b = s.bases[0]
+    rng = np.random.default_rng(7)
+    C = rng.standard_normal((b.npw, 4)) + 1j * rng.standard_normal((b.npw, 4))
+    _ORACLE.update(s=s, Veff=Veff, C=C, cell=cell)
+
+
+def _oracle_bands(budget_s):
+    """H applied by the oracle to 4-band blocks for about budget_s seconds
+    (one thread); returns (bands, seconds)."""
+    from oracle import operators as oo
+    s, Veff, C = _ORACLE["s"], _ORACLE["Veff"], _ORACLE["C"]
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oo.apply_H(C, s.bases[0], Veff, s.P[0], s.D)
+        n += C.shape[1]
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            return n, dt
+
+
+def cpu_baseline(workload, budget_s=10.0):
+    """The FP64 oracle on the host: H applied to the workload's band blocks at
+    its own start potential, for a bounded time on one core, then in one
+    process per core (the oracle's FFT is single-threaded)."""
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
-    except Exception:  # threadpoolctl missing: NumPy FFT is single-threaded anyway
-        limiter = None
-    import workloads as W
-    from oracle import energy as oe, operators as oo, scf as oscf
+        threadpool_limits(1)
+    except Exception:
+        pass
+    import multiprocessing as mp
+    _oracle_setup(workload)
+    bands1, dt1 = _oracle_bands(budget_s)
+    rate1 = bands1 / dt1
+    ncpu = min(os.cpu_count() or 1, MAX_WORKERS)
+    rate_all, used = rate1, 1
+    if ncpu > 1:
+        ctx = mp.get_context("fork")  # before the GPU is touched
+        with ctx.Pool(ncpu) as pool:
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_bands, [budget_s / 2] * ncpu)
+            dt = time.perf_counter() - t0
+        rate_all = sum(n for n, _ in res) / dt
+        used = ncpu
+    model, nproc = host_cpu()
+    cell = _ORACLE["cell"]
+    return {"value": rate1, "unit": "bands·k/s", "cores": 1, "kind": "oracle",
+            "sample": f"{workload} ({cell.nat} atoms, {cell.S[0]}^3, {_ORACLE['s'].bases[0].npw} plane waves): "
+                      f"NumPy FP64 oracle applying H to 4-band blocks at the start potential for {dt1:.1f} s on one "
+                      f"core ({bands1} bands)",
+            "all_cores": {"value": rate_all, "cores": used, "processes": used,
+                          "sample": f"the same, {used} processes of one thread each for {budget_s / 2:.1f} s"},
+            "host_cpu": model, "nproc": nproc}
 
-    cell = W.config2()
-    s = oe.build_system(cell)
-    shapes = [(cell.nb, b.npw) for b in s.bases]
-    Y = [y.T.copy() for y in W.initial_wavefunctions(cell.y0_seed, shapes)]
-    n0 = oe.start_density(cell, W.START_SIGMA)
-    count = {"bk": 0}
-    orig = oo.apply_H
 
-    def counting(C, b, Veff, P, D):
-        count["bk"] += C.shape[1] if C.ndim == 2 else 1
-        return orig(C, b, Veff, P, D)
+# ------------------------------------------------------------- GPU runs ------
+def make_system(D, W, ctx, cells, prec, graph, dev):
+    import torch
+    descs = [dict(R=c.R, S=c.S, ecut=c.ecut, kpts=c.kpts, wk=c.wk, nb=c.nb, n_electrons=c.n_electrons, tau=c.tau,
+                  Z=c.Z.astype(float), rc=c.rc, has_proj=c.has_proj.astype(int), rp=W.PROJ_RP, D=W.PROJ_D)
+             for c in cells]
+    sys_ = D.dpp_batch_create(ctx, descs, prec)
+    # mixed: FP32 bulk, FP64 refinement once the band residual < 1e-4 Ha
+    D.dpp_set_precision_policy(sys_, prec, 1e-4 if prec == D.DPP_F32 else 0.0)
+    D.dpp_set_graph_mode(sys_, graph)
+    off, npw = D.dpp_system_layout(sys_)
+    item0, _, _ = D.dpp_system_cells(sys_)
+    blocks = []
+    for ci, c in enumerate(cells):
+        blocks += W.initial_wavefunctions(c.y0_seed, [(c.nb, npw[k]) for k in range(item0[ci], item0[ci + 1])])
+    Y = torch.from_numpy(np.concatenate([b.reshape(-1) for b in blocks])).to(dev)
+    return sys_, Y
 
-    oo.apply_H = counting
-    import oracle.energy as oen
-    import oracle.scf as osc
-    oen.ops.apply_H = counting
-    osc.ops.apply_H = counting
+
+def energies(D, sys_, Y):
+    E, _ = D.dpp_scf_iteration(sys_, Y)
+    return np.array([e["E_el"] for e in E])
+
+
+def run_arm(D, W, ctx, cells, prec, args, dev, stream, tune=True, detail=True):
+    """Timed SCF iterations of one system (graph replay), then the same steps
+    eagerly with the kernel timer, then the isolated H.C rate."""
+    import torch
+    sys_, Y = make_system(D, W, ctx, cells, prec, not args.eager, dev)
+    scf_cells = [dict(tau=c.tau, Z=c.Z.astype(float), sigma=W.START_SIGMA) for c in cells]
+    tuning = None
+    if tune and not args.no_tune:
+        # launch autotuner (untimed): x-pass variant per box length and
+        # precision, rotate point tiles, overlap block shape
+        scratch = torch.empty_like(Y)
+        D.dpp_system_tune(sys_, Y, scratch, 5)
+        del scratch
+        tuning = D.dpp_system_tune_report(sys_)
+    D.dpp_scf_init(sys_, cells=scf_cells)
+    for _ in range(args.warmup):
+        energies(D, sys_, Y)
+    torch.cuda.synchronize()
+    c0 = D.dpp_system_counters(sys_)
     t0 = time.perf_counter()
-    it = 0
-    try:
-        # one SCF iteration at a time until the time budget is used
-        n_in = n0
-        while time.perf_counter() - t0 < budget_s and it < 8:
-            res = oscf.scf(s, Y, n_in, 1)
-            Y, n_in = res["Y"], res["n_in"]
-            it += 1
-    finally:
-        oo.apply_H = orig
-        oen.ops.apply_H = orig
-        osc.ops.apply_H = orig
-        if limiter is not None:
-            limiter.unregister() if hasattr(limiter, "unregister") else None
-    dt = time.perf_counter() - t0
-    return {"value": count["bk"] / dt, "unit": "bands·k/s", "cores": 1, "kind": "oracle",
-            "sample": f"{it} SCF iteration(s) of config 2 (8 k x 16 bands, 40^3) with the NumPy FP64 oracle, "
-                      f"{count['bk']} band-k H applications in {dt:.1f} s",
-            "s_per_scf_iter": dt / max(it, 1)}
+    for _ in range(args.steps):
+        energies(D, sys_, Y)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = D.dpp_system_counters(sys_)
+    res_end, prec_end, _ = D.dpp_scf_status(sys_)
+    out = dict(ms_per_step=(t1 - t0) * 1e3 / args.steps, hc_rate=(c1 - c0) / (t1 - t0),
+               timed_prec_end=("f32" if prec_end == 1 else "f64"), residual_after_timed=res_end, tuning=tuning)
+    if detail:
+        D.dpp_set_graph_mode(sys_, False)
+        D.dpp_timer_reset(ctx)
+        D.dpp_timer_enable(ctx, True)
+        te0 = time.perf_counter()
+        for _ in range(args.steps):
+            energies(D, sys_, Y)
+        torch.cuda.synchronize()
+        out["ms_per_step_eager_timer"] = (time.perf_counter() - te0) * 1e3 / args.steps
+        kern = {}
+        for kname in D.TIMER_KINDS:
+            ms, n, by, fl = D.dpp_timer_read(ctx, kname)
+            if n:
+                kern[kname] = {"ms_total": ms, "launches": n, "avg_us": 1e3 * ms / n, "alg_bytes": by,
+                               "alg_flops": fl}
+        D.dpp_timer_enable(ctx, False)
+        D.dpp_set_graph_mode(sys_, not args.eager)
+        out["kernels"] = kern
+        # isolated H.C on the whole block (every band of every item), at the current V_eff
+        HY = torch.empty_like(Y)
+        for _ in range(3):
+            D.dpp_system_apply_H(sys_, Y, HY)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 10
+        nbk = sum(c.nb * len(c.kpts) for c in cells)
+        e0.record(stream)
+        for _ in range(reps):
+            D.dpp_system_apply_H(sys_, Y, HY)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["hc_only"] = reps * nbk / (e0.elapsed_time(e1) * 1e-3)
+    return sys_, Y, out
+
+
+def converge(D, W, sys_, Y, cells, max_it, tol):
+    """SCF from the seeded start until the energy of every cell changed by
+    less than tol Ha/atom in two successive iterations (at most max_it)."""
+    nat = np.array([c.nat for c in cells])
+    D.dpp_scf_init(sys_, cells=[dict(tau=c.tau, Z=c.Z.astype(float), sigma=W.START_SIGMA) for c in cells])
+    hist = []
+    quiet = 0
+    for _ in range(max_it):
+        hist.append(energies(D, sys_, Y))
+        if len(hist) > 1 and np.all(np.abs(hist[-1] - hist[-2]) / nat < tol):
+            quiet += 1
+            if quiet >= 2:
+                break
+        else:
+            quiet = 0
+    return np.array(hist)
+
+
+def iters_to(hist, ref, nat, tol=1e-6):
+    ok = np.all(np.abs(hist - ref[None, :]) / nat[None, :] < tol, axis=1)
+    for i in range(len(ok)):
+        if ok[i:].all():
+            return i + 1
+    return None
+
+
+def roofline_of(kern, workload):
+    # dominant single HBM-bound kernel class with an algorithmic byte count
+    single = [k for k in ("planes_in", "xz_h", "planes_out", "xz_density") if k in kern]
+    dom = max(single, key=lambda k: kern[k]["ms_total"])
+    dk = kern[dom]
+    ach = dk["alg_bytes"] / (dk["ms_total"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic(dom, workload), "kernel": dom, "avg_launch_us": dk["avg_us"],
+            "alg_bytes_per_launch": dk["alg_bytes"] / dk["launches"],
+            "timing": "HIP events around each launch on the library stream (eager pass)",
+            "traffic_source": f"profiles/{dom}_{workload}_traffic.md (rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                              "copy-calibrated); null when the kernel source changed since"}
+    contr = {}
+    for k in ("overlap", "rotate"):
+        if k in kern and kern[k]["alg_flops"]:
+            tf = kern[k]["alg_flops"] / (kern[k]["ms_total"] * 1e-3) / 1e12
+            contr[k] = {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / FP64_PEAK_TFLOPS, "avg_launch_us": kern[k]["avg_us"],
+                        "dtype": "f64 (16x16x4 MFMA)"}
+    return roof, contr
+
+
+def pmc_probe(kind, workload):
+    """A short loop for counter collection under rocprofv3 --pmc."""
+    import torch
+    if kind == "copy":
+        n = 256 << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": "copy", "bytes_per_copy": n}))
+        return
+    import workloads as W
+    from paper_1708_03621_amd import dftpp as D
+    dev = torch.device("cuda:0")
+    ctx = D.dpp_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+    cells = cells_for(workload)
+
+    sys_, Y = make_system(D, W, ctx, cells, D.DPP_F64, False, dev)
+    scratch = torch.empty_like(Y)
+    D.dpp_system_tune(sys_, Y, scratch, 2)
+    D.dpp_scf_init(sys_, cells=[dict(tau=c.tau, Z=c.Z.astype(float), sigma=W.START_SIGMA) for c in cells])
+    energies(D, sys_, Y)
+    for _ in range(3):
+        D.dpp_system_apply_H(sys_, Y, scratch)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": "apply_H", "workload": workload, "tuning": D.dpp_system_tune_report(sys_)}))
+    D.dpp_system_destroy(sys_)
 
 
 def main():
@@ -137,18 +346,29 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--converge", type=int, default=200, help="SCF iterations for the convergence report")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4"],
-                    help="config2 (the metric's workload), config3 (64 atoms, 90^3, 128 bands) or config4 "
-                         "(48 cells batched)")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work per CPU sample")
+    ap.add_argument("--converge", type=int, default=600,
+                    help="at most this many SCF iterations for the convergence report (0: skip)")
+    ap.add_argument("--workload", default="config3", choices=["config2", "config3", "config4"])
+    ap.add_argument("--no-others", action="store_true", help="skip the extra timings of the other two workloads")
     ap.add_argument("--eager", action="store_true", help="launch every kernel from the host (no graph replay)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (default launch rules)")
+    ap.add_argument("--pmc-probe", choices=["apply_H", "copy"], help="run a short loop for counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built: "
-              "k-point shards would need an all-reduce of the density, described in DESIGN.md", file=sys.stderr)
+              "k-point or band shards would need an all-reduce of the density, described in DESIGN.md",
+              file=sys.stderr)
         sys.exit(2)
+    if args.pmc_probe:
+        pmc_probe(args.pmc_probe, args.workload)
+        return
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle runs first, in forked processes, before the GPU is touched
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(args.workload, args.cpu_budget)
 
     import torch
     import workloads as W
@@ -159,120 +379,59 @@ def main():
     ctx = D.dpp_ctx_create(0, stream.cuda_stream)
     cells = cells_for(args.workload)
     nat = np.array([c.nat for c in cells])
-    scf_cells = [dict(tau=c.tau, Z=c.Z.astype(float), sigma=W.START_SIGMA) for c in cells]
 
-    def make(prec):
-        descs = [dict(R=c.R, S=c.S, ecut=c.ecut, kpts=c.kpts, wk=c.wk, nb=c.nb, n_electrons=c.n_electrons, tau=c.tau,
-                      Z=c.Z.astype(float), rc=c.rc, has_proj=c.has_proj.astype(int), rp=W.PROJ_RP, D=W.PROJ_D)
-                 for c in cells]
-        sys_ = D.dpp_batch_create(ctx, descs, prec)
-        # mixed: FP32 bulk, FP64 refinement once the band residual < 1e-4 Ha
-        D.dpp_set_precision_policy(sys_, prec, 1e-4 if prec == D.DPP_F32 else 0.0)
-        D.dpp_set_graph_mode(sys_, not args.eager)
-        off, npw = D.dpp_system_layout(sys_)
-        item0, _, _ = D.dpp_system_cells(sys_)
-        blocks = []
-        for ci, c in enumerate(cells):
-            blocks += W.initial_wavefunctions(c.y0_seed, [(c.nb, npw[k]) for k in range(item0[ci], item0[ci + 1])])
-        Y = torch.from_numpy(np.concatenate([b.reshape(-1) for b in blocks])).to(dev)
-        return sys_, Y
-
-    def energies(sys_, Y):
-        E, _ = D.dpp_scf_iteration(sys_, Y)
-        return np.array([e["E_el"] for e in E])
-
-    results = {}
-    tuning = {}
+    results, systems = {}, {}
     for prec, name in [(D.DPP_F64, "f64"), (D.DPP_F32, "mixed")]:
-        sys_, Y = make(prec)
-        if not args.no_tune:
-            # launch autotuner (untimed): x-pass variant per box length and
-            # precision, rotate point tiles, overlap block shape
-            scratch = torch.empty_like(Y)
-            D.dpp_system_tune(sys_, Y, scratch, 5)
-            del scratch
-            tuning[name] = D.dpp_system_tune_report(sys_)
-            log(f"[{name}] tuning: {tuning[name]}")
-        D.dpp_scf_init(sys_, cells=scf_cells)
-        log(f"[{name}] warmup {args.warmup}")
-        for _ in range(args.warmup):
-            energies(sys_, Y)
-        torch.cuda.synchronize()
-        c0 = D.dpp_system_counters(sys_)
-        log(f"[{name}] timed {args.steps} SCF iterations")
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            E = energies(sys_, Y)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        c1 = D.dpp_system_counters(sys_)
-        res_end, prec_end, _ = D.dpp_scf_status(sys_)
-        ms_step = (t1 - t0) * 1e3 / args.steps
-        hc_rate = (c1 - c0) / (t1 - t0)
-        # same steps again, eager, with the kernel timer on (HIP events on the library stream)
-        D.dpp_set_graph_mode(sys_, False)
-        D.dpp_timer_reset(ctx)
-        D.dpp_timer_enable(ctx, True)
-        te0 = time.perf_counter()
-        for _ in range(args.steps):
-            energies(sys_, Y)
-        torch.cuda.synchronize()
-        ms_eager_timed = (time.perf_counter() - te0) * 1e3 / args.steps
-        kern = {}
-        for kname in D.TIMER_KINDS:
-            ms, n, by, fl = D.dpp_timer_read(ctx, kname)
-            if n:
-                kern[kname] = {"ms_total": ms, "launches": n, "avg_us": 1e3 * ms / n, "alg_bytes": by,
-                               "alg_flops": fl}
-        D.dpp_timer_enable(ctx, False)
-        D.dpp_set_graph_mode(sys_, not args.eager)
-        # isolated H.C on the whole block (every band of every item), at the current V_eff
-        HY = torch.empty_like(Y)
-        for _ in range(3):
-            D.dpp_system_apply_H(sys_, Y, HY)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        reps = 50 if args.workload != "config3" else 10
-        nbk = sum(c.nb * len(c.kpts) for c in cells)
-        e0.record(stream)
-        for _ in range(reps):
-            D.dpp_system_apply_H(sys_, Y, HY)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        hc_only = reps * nbk / (e0.elapsed_time(e1) * 1e-3)
-        # convergence report (untimed): iterations until |E_i - E_final| < 1e-6 Ha/atom for every cell
-        it_conv, Ef, prec_conv = None, None, prec_end
-        if args.converge > 0:
-            D.dpp_scf_init(sys_, cells=scf_cells)
-            hist = [energies(sys_, Y) for _ in range(args.converge)]
-            Ef = hist[-1]
-            it_conv = next((i + 1 for i in range(len(hist))
-                            if all(np.all(np.abs(h - Ef) / nat < 1e-6) for h in hist[i:])), None)
-            _, prec_conv, _ = D.dpp_scf_status(sys_)
-        results[name] = dict(ms_per_step=ms_step, hc_rate=hc_rate, hc_only=hc_only, kernels=kern,
-                             ms_per_step_eager_timer=ms_eager_timed,
-                             timed_prec_end=("f32" if prec_end == 1 else "f64"), residual_after_timed=res_end,
-                             converged_prec=("f32" if prec_conv == 1 else "f64"),
-                             E_final=(float(Ef[0]) if Ef is not None and len(Ef) == 1 else
-                                      (None if Ef is None else float(np.sum(Ef)))),
-                             iters_to_1e6=it_conv, E_last_step=float(E[0]) if len(E) == 1 else float(np.sum(E)))
+        log(f"[{name}] {args.workload}: tune, warm up {args.warmup}, time {args.steps} SCF iterations")
+        sys_, Y, r = run_arm(D, W, ctx, cells, prec, args, dev, stream)
+        log(f"[{name}] {r['ms_per_step']:.3f} ms per SCF iteration; tuning: {r['tuning']}")
+        results[name] = r
+        systems[name] = (sys_, Y)
+
+    conv = None
+    if args.converge > 0:
+        # FP64 reference converged to 1e-10 Ha/atom, then iterations of each
+        # arm until it stays within 1e-6 Ha/atom of that reference
+        log("convergence: FP64 reference to 1e-10 Ha/atom")
+        href = converge(D, W, *systems["f64"], cells, args.converge, 1e-10)
+        ref = href[-1]
+        ref_conv = bool(len(href) > 1 and np.all(np.abs(href[-1] - href[-2]) / nat < 1e-10))
+        log("convergence: mixed")
+        hmix = converge(D, W, *systems["mixed"], cells, args.converge, 1e-10)
+        _, prec_mix, _ = D.dpp_scf_status(systems["mixed"][0])
+        conv = {"reference": {"E_el": [float(x) for x in ref], "iterations": len(href),
+                              "converged_to_1e-10_Ha_per_atom": ref_conv},
+                "f64": {"iters_to_1e-6_Ha_per_atom": iters_to(href, ref, nat), "window": len(href)},
+                "mixed": {"iters_to_1e-6_Ha_per_atom": iters_to(hmix, ref, nat), "window": len(hmix),
+                          "precision_at_end": "f32" if prec_mix == 1 else "f64",
+                          "max_dE_per_atom_at_end": float(np.max(np.abs(hmix[-1] - ref) / nat))},
+                "definition": "first SCF iteration from which every later energy of the run stays within "
+                              "1e-6 Ha/atom of the FP64 energy converged until two successive changes were "
+                              "below 1e-10 Ha/atom"}
+    for sys_, _ in systems.values():
         D.dpp_system_destroy(sys_)
+
+    others = {}
+    if not args.no_others:
+        for wl in [w for w in ("config2", "config3", "config4") if w != args.workload]:
+            oc = cells_for(wl)
+            o = {}
+            for prec, name in [(D.DPP_F64, "f64"), (D.DPP_F32, "mixed")]:
+                log(f"[{wl} {name}] tune, warm up, time {args.steps} SCF iterations")
+                s2, _, r2 = run_arm(D, W, ctx, oc, prec, args, dev, stream, detail=(name == "f64"))
+                D.dpp_system_destroy(s2)
+                o[name] = r2
+            roof2 = roofline_of(o["f64"]["kernels"], wl)[0]
+            others[wl] = {"workload": WORKLOADS[wl],
+                          "s_per_scf_iter": {k: v["ms_per_step"] * 1e-3 for k, v in o.items()},
+                          "hc_in_scf_bands_k_per_s": {k: v["hc_rate"] for k, v in o.items()},
+                          "hc_only_bands_k_per_s_f64": o["f64"]["hc_only"],
+                          "speedup_mixed_vs_f64": o["f64"]["ms_per_step"] / o["mixed"]["ms_per_step"],
+                          "roofline_f64": {k: roof2[k] for k in ("kernel", "achieved", "frac", "avg_launch_us")}}
 
     r = results["f64"]
     kern = r["kernels"]
-    # dominant single kernel among the HBM-bound passes with an algorithmic
-    # byte count (aggregate classes of small kernels are reported beside it)
-    single = [k for k in ("planes_in", "xz_h", "planes_out", "xz_density", "overlap", "rotate") if k in kern]
-    dom = max(single, key=lambda k: kern[k]["ms_total"])
-    dk = kern[dom]
-    ach = dk["alg_bytes"] / (dk["ms_total"] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom, args.workload), "kernel": dom, "avg_launch_us": dk["avg_us"],
-            "alg_bytes_per_launch": dk["alg_bytes"] / dk["launches"],
-            "timing": "HIP events around each launch on the library stream (eager pass)",
-            "traffic_source": "profiles/xz_h_config2_f64_traffic.md (rocprofv3 FETCH_SIZE/WRITE_SIZE, "
-                              "copy-calibrated); null when the kernel source changed since"}
+    roof, contr = roofline_of(kern, args.workload)
     out = {
         "metric": METRIC,
         "value": r["hc_rate"],
@@ -293,24 +452,25 @@ def main():
         "hc_in_scf_bands_k_per_s": {k: v["hc_rate"] for k, v in results.items()},
         "hc_only_bands_k_per_s": {k: v["hc_only"] for k, v in results.items()},
         "speedup_mixed_vs_f64": results["f64"]["ms_per_step"] / results["mixed"]["ms_per_step"],
-        "scf_convergence": {k: {"iters_to_1e-6_Ha_per_atom": v["iters_to_1e6"], "E_el": v["E_final"],
-                                "precision_at_end": v["converged_prec"], "window": args.converge,
-                                "definition": "first iteration from which every later energy of the window "
-                                              "is within 1e-6 Ha/atom of the window's last"}
-                            for k, v in results.items()},
+        "scf_convergence": conv,
         "timed_region_precision": {k: {"after_last_step": v["timed_prec_end"],
                                        "band_residual": v["residual_after_timed"]} for k, v in results.items()},
         "mixed_note": "mixed = FFT passes, potential multiply and density in FP32 until the band residual "
                       "falls below 1e-4 Ha, FP64 after; contractions, Cholesky, eigensolver and reductions in FP64",
-        "tuning": tuning if tuning else None,
+        "tuning": {k: v["tuning"] for k, v in results.items()},
         "roofline": roof,
+        "roofline_contractions": contr,
         "kernels": {k: {"avg_us": v["avg_us"], "launches": v["launches"], "ms_total": v["ms_total"],
                         "GBps": (v["alg_bytes"] / (v["ms_total"] * 1e-3) / 1e9) if v["alg_bytes"] else None}
                     for k, v in kern.items()},
+        "other_workloads": others or None,
     }
-    if not args.no_cpu_baseline and args.workload == "config2":
-        log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        out["cpu_oracle_s_per_scf_iter_estimate"] = {
+            "value": (r["hc_rate"] * r["ms_per_step"] * 1e-3) / cpu["value"],
+            "note": "H applications of one GPU SCF iteration divided by the oracle's one-core H.C rate "
+                    "(H only: the oracle's other steps are not counted)"}
     print(json.dumps(out), flush=True)
 
 
