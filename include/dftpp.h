@@ -213,6 +213,18 @@ dpp_status dpp_cholesky_orthonormalize(dpp_basis basis, int nb, dpp_c64 *Y, int6
 dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dpp_c64 *H, double *eig,
                              dpp_c64 *vecs, void *ws);
 dpp_status dpp_eigh_workspace_size(int nb, int batch, size_t *bytes);
+/* dpp_subspace_eigh for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the workspace in a static device array
+ * of 8 MiB per GPU held until the process ends (address taken once per device
+ * by dpp_ctx_create).  Sizes needing more workspace than that (for example
+ * more than three 128 x 128 matrices per call) return DPP_EINVAL with a
+ * message and launch nothing.  No allocation of any kind.  Calls that overlap
+ * on one GPU (other streams or threads) share the array and race; calls on
+ * one stream are ordered.  The array keeps the last call's contents; no call
+ * reads what an earlier call left. */
+dpp_status dpp_subspace_eigh_noalloc(dpp_ctx ctx, int nb, int batch, const dpp_c64 *H, double *eig,
+                                     dpp_c64 *vecs);
 
 /* ------------------------------------------------ densities, potentials -- */
 

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <cmath>
 #include <vector>
 
@@ -1289,6 +1291,34 @@ extern "C" dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const
     return DPP_OK;
 }
 
+// ------------------------------------- eigensolver without allocation ------
+// Workspace of dpp_subspace_eigh_noalloc: a file-scope device array (each GPU
+// the library runs on holds its own copy until the process ends).  Host code
+// never uses the array's name as an address: dpp_ctx_create records, with the
+// context's device current, the address hipGetSymbolAddress returns, and the
+// entry point passes that address to the kernels.
+constexpr size_t EIGH_STATIC_BYTES = (size_t)8 << 20;
+static __device__ __align__(256) char scratch[EIGH_STATIC_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES];
+}  // namespace
+
+dpp_status dpp::eigh_scratch_setup(int device) {
+    DPP_REQUIRE(device >= 0 && device < SCRATCH_MAX_DEVICES, "eigh_scratch_setup: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return DPP_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return set_error(DPP_EDEVICE, std::string("eigh_scratch_setup: hipGetSymbolAddress failed: ") +
+                                          hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+    return DPP_OK;
+}
+
 static size_t eigh_ws_split(int nb, int batch) {
     return ((eigh_tiles_ws_bytes((int64_t)batch * nb * nb) + 255) / 256) * 256;
 }
@@ -1325,6 +1355,23 @@ extern "C" dpp_status dpp_subspace_eigh(dpp_ctx ctx, int nb, int batch, const dp
     return DPP_OK;
 }
 
+
+extern "C" dpp_status dpp_subspace_eigh_noalloc(dpp_ctx ctx, int nb, int batch, const dpp_c64* H, double* eig,
+                                                dpp_c64* vecs) {
+    clear_error();
+    DPP_REQUIRE(ctx && nb >= 1 && batch >= 0, "dpp_subspace_eigh_noalloc: bad arguments");
+    DPP_REQUIRE(nb <= EIG_MAXN, "dpp_subspace_eigh_noalloc: nb > 128");
+    if (batch == 0) return DPP_OK;
+    const size_t need = nb <= EIGW_MAXN ? 0 : eigh_ws_split(nb, batch) + eigh_perm_bytes(batch);
+    if (need > EIGH_STATIC_BYTES)
+        return set_error(DPP_EINVAL, "dpp_subspace_eigh_noalloc: " + std::to_string(batch) + " matrices of order " +
+                                         std::to_string(nb) + " need " + std::to_string(need) +
+                                         " bytes of workspace, more than the " + std::to_string(EIGH_STATIC_BYTES) +
+                                         "-byte static array; use dpp_subspace_eigh with a workspace");
+    void* ws = (ctx->device >= 0 && ctx->device < SCRATCH_MAX_DEVICES) ? g_scratch_ptr[ctx->device] : nullptr;
+    DPP_REQUIRE(ws, "dpp_subspace_eigh_noalloc: static workspace not set up for this device");
+    return dpp_subspace_eigh(ctx, nb, batch, H, eig, vecs, ws);
+}
 
 size_t dpp::proj_ws_bytes(const dpp_basis_s* b, int nb) {
     // Pi (64 projectors max per call chunk is not assumed: use the actual count later)

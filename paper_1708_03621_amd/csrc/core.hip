@@ -36,6 +36,7 @@ extern "C" dpp_status dpp_ctx_create(int device, void* hip_stream, dpp_ctx* out)
     DPP_HIP(hipGetDeviceCount(&ndev));
     DPP_REQUIRE(device >= 0 && device < ndev, "dpp_ctx_create: no such device");
     DPP_HIP(hipSetDevice(device));
+    DPP_TRY(eigh_scratch_setup(device));
     dpp_ctx c = new dpp_ctx_s();
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);

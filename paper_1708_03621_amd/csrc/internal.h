@@ -315,4 +315,8 @@ size_t proj_ws_bytes(const dpp_basis_s* b, int nb);
 dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
                       const double2* M, double beta, double2* out, int64_t ldout);
 
+// Records, for the current device, the address of the eigensolver's static
+// workspace (dpp_subspace_eigh_noalloc); called by dpp_ctx_create.
+dpp_status eigh_scratch_setup(int device);
+
 }  // namespace dpp

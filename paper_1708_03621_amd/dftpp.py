@@ -96,6 +96,7 @@ SIGNATURES = {
     "dpp_ortho_workspace_size": [_vp, _i, _szp],
     "dpp_subspace_eigh": [_vp, _i, _i, _vp, _vp, _vp, _vp],
     "dpp_eigh_workspace_size": [_i, _i, _szp],
+    "dpp_subspace_eigh_noalloc": [_vp, _i, _i, _vp, _vp, _vp],
     "dpp_density_accumulate": [_vp, _i, _vp, _i64, _vp, _d, _vp, _i, _vp],
     "dpp_hartree": [_vp, _vp, _vp, _vp, _vp],
     "dpp_lda_pz81": [_vp, _vp, _vp, _vp, _vp],
@@ -342,6 +343,10 @@ def dpp_cholesky_orthonormalize(basis, nb, Y, ldY, Rinv, ws):
 
 def dpp_subspace_eigh(ctx, nb, batch, H, eig, vecs, ws):
     _call("dpp_subspace_eigh", ctx, nb, batch, _ptr(H), _ptr(eig), _ptr(vecs), _ptr(ws))
+
+
+def dpp_subspace_eigh_noalloc(ctx, nb, batch, H, eig, vecs):
+    _call("dpp_subspace_eigh_noalloc", ctx, nb, batch, _ptr(H), _ptr(eig), _ptr(vecs))
 
 
 # ------------------------------------------------- densities, potentials ----
