@@ -220,7 +220,7 @@ __device__ __forceinline__ void fft_stage(typename cx<T>::t* lds, int n, int nff
 // All stages of one axis.  sign = +1: exp(+i ...) (inverse, unnormalized);
 // sign = -1: exp(-i ...) (forward).
 template <typename T, bool FMAJOR, int NT, typename Addr>
-__device__ void fft_axis(typename cx<T>::t* lds, const FftAxis& ax, int nfft, const Addr& addr,
+__device__ __forceinline__ void fft_axis(typename cx<T>::t* lds, const FftAxis& ax, int nfft, const Addr& addr,
                          const double2* tw64, const float2* tw32, int sign) {
     int Ns = 1;
     for (int s = 0; s < ax.nrad; ++s) {
