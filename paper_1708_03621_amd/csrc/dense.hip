@@ -699,6 +699,7 @@ struct EighWs {
     z2* tau;      // n
     z2* ph;       // 1
     int *bs, *be;  // block [bs, be) of each index after splitting
+    double* lu;    // 3 n x n: LU rows of the inverse iteration, 3n per eigenvalue index
 };
 
 __host__ __device__ inline EighWs eigh_ws(z2* base, int n) {
@@ -719,6 +720,7 @@ __host__ __device__ inline EighWs eigh_ws(z2* base, int n) {
     int* q = reinterpret_cast<int*>(w.ph + 1);
     w.bs = q;
     w.be = q + n;
+    w.lu = reinterpret_cast<double*>(q + 2 * n);
     return w;
 }
 
@@ -995,11 +997,173 @@ __device__ __forceinline__ double start_value(int r, int m) {
     return (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
 }
 
+// (T - lm) x = rhs in place on one block of m rows, by elimination with
+// partial pivoting (one thread): row j of the upper factor is (u0, u1, u2) at
+// columns j, j+1, j+2.  A zero pivot is replaced by pivmin.
+__device__ void tri_solve(int m, const double* __restrict__ d, const double* __restrict__ e, double lm,
+                          double pivmin, double* __restrict__ x, double* __restrict__ u0, double* __restrict__ u1,
+                          double* __restrict__ u2) {
+    double p0 = d[0] - lm, p1 = m > 1 ? e[0] : 0.0, p2 = 0.0;
+    double ri = x[0];
+    for (int j = 0; j + 1 < m; ++j) {
+        double q0 = e[j], q1 = d[j + 1] - lm, q2 = j + 2 < m ? e[j + 1] : 0.0;
+        double rn = x[j + 1];
+        if (fabs(q0) > fabs(p0)) {
+            double tq = p0;
+            p0 = q0;
+            q0 = tq;
+            tq = p1;
+            p1 = q1;
+            q1 = tq;
+            tq = p2;
+            p2 = q2;
+            q2 = tq;
+            tq = ri;
+            ri = rn;
+            rn = tq;
+        }
+        if (p0 == 0.0) p0 = pivmin;
+        const double mu = q0 / p0;
+        u0[j] = p0;
+        u1[j] = p1;
+        u2[j] = p2;
+        x[j] = ri;
+        ri = rn - mu * ri;
+        p0 = q1 - mu * p1;
+        p1 = q2 - mu * p2;
+        p2 = 0.0;
+    }
+    if (fabs(p0) < pivmin) p0 = p0 < 0.0 ? -pivmin : pivmin;
+    u0[m - 1] = p0;
+    x[m - 1] = ri;
+    for (int j = m - 1; j >= 0; --j) {
+        double tt = x[j];
+        if (j + 1 < m) tt -= u1[j] * x[j + 1];
+        if (j + 2 < m) tt -= u2[j] * x[j + 2];
+        x[j] = tt / u0[j];
+    }
+}
+
+// x <- x / |x| over m entries (scaled by the largest entry first), one wave.
+__device__ __forceinline__ void wave_normalize(int m, double* __restrict__ x) {
+    const int lane = threadIdx.x;
+    double xm = 0.0;
+    for (int j = lane; j < m; j += 64) xm = fmax(xm, fabs(x[j]));
+    xm = wmax(xm);
+    const double isc = xm > 0.0 ? 1.0 / xm : 1.0;
+    double nr = 0.0;
+    for (int j = lane; j < m; j += 64) {
+        x[j] *= isc;
+        nr += x[j] * x[j];
+    }
+    nr = wsum(nr);
+    const double inr = 1.0 / sqrt(nr);
+    for (int j = lane; j < m; j += 64) x[j] *= inr;
+}
+
+// Clusters of up to CL_MAX eigenvalues run as a block: every member's inverse
+// iteration in its own lane, the block orthonormalized (modified Gram-Schmidt)
+// after each iteration, then a Rayleigh-Ritz step: K = X^T T X, K = V diag V^T
+// by parallel-order Jacobi, eigenvectors X V in ascending order.
+constexpr int CL_MAX = 48;
+constexpr int KLD = CL_MAX + 1;
+constexpr int XLD = EIG_TILE_MAXN + 1;  // odd row stride: lanes walking their own rows hit different banks
+
+// Real symmetric eigen-decomposition of K (mc x mc, row stride KLD, LDS) in
+// one wave: parallel-order cyclic Jacobi (round-robin pairs), V accumulated.
+__device__ void jacobi_small(int mc, double* __restrict__ K, double* __restrict__ V, int* __restrict__ rp,
+                             double* __restrict__ rc) {
+    const int lane = threadIdx.x;
+    const int m2 = mc + (mc & 1);
+    for (int i = lane; i < mc * KLD; i += 64) V[i] = 0.0;
+    __syncthreads();
+    for (int i = lane; i < mc; i += 64) V[i * KLD + i] = 1.0;
+    __syncthreads();
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, all = 0.0;
+        for (int i = lane; i < mc * mc; i += 64) {
+            const int r = i / mc, c = i - r * mc;
+            const double v = K[r * KLD + c];
+            all += v * v;
+            if (r != c) off += v * v;
+        }
+        off = wsum(off);
+        all = wsum(all);
+        if (!(off > fmax(1e-28, 4e-32 * (double)mc * (double)mc) * all)) break;
+        for (int round = 0; round < m2 - 1; ++round) {
+            if (lane < m2 / 2) {
+                int p, q;
+                if (lane == 0) {
+                    p = m2 - 1;
+                    q = round;
+                } else {
+                    p = (round + lane) % (m2 - 1);
+                    q = (round - lane + (m2 - 1)) % (m2 - 1);
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, sn = 0.0;
+                if (q < mc) {
+                    const double apq = K[p * KLD + q];
+                    if (apq != 0.0) {
+                        const double tau = (K[q * KLD + q] - K[p * KLD + p]) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        sn = t * c;
+                    }
+                } else {
+                    q = p;  // paired with the dummy: identity
+                }
+                rp[2 * lane] = p;
+                rp[2 * lane + 1] = q;
+                rc[2 * lane] = c;
+                rc[2 * lane + 1] = sn;
+            }
+            __syncthreads();
+            // columns: K <- K J and V <- V J (lanes over rows)
+            for (int i = lane; i < mc; i += 64) {
+                for (int s2 = 0; s2 < m2 / 2; ++s2) {
+                    const int p = rp[2 * s2], q = rp[2 * s2 + 1];
+                    if (p == q) continue;
+                    const double c = rc[2 * s2], sn = rc[2 * s2 + 1];
+                    const double kp = K[i * KLD + p], kq = K[i * KLD + q];
+                    K[i * KLD + p] = c * kp - sn * kq;
+                    K[i * KLD + q] = sn * kp + c * kq;
+                    const double vp = V[i * KLD + p], vq = V[i * KLD + q];
+                    V[i * KLD + p] = c * vp - sn * vq;
+                    V[i * KLD + q] = sn * vp + c * vq;
+                }
+            }
+            __syncthreads();
+            // rows: K <- J^T K (lanes over columns)
+            for (int i = lane; i < mc; i += 64) {
+                for (int s2 = 0; s2 < m2 / 2; ++s2) {
+                    const int p = rp[2 * s2], q = rp[2 * s2 + 1];
+                    if (p == q) continue;
+                    const double c = rc[2 * s2], sn = rc[2 * s2 + 1];
+                    const double kp = K[p * KLD + i], kq = K[q * KLD + i];
+                    K[p * KLD + i] = c * kp - sn * kq;
+                    K[q * KLD + i] = sn * kp + c * kq;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 __global__ void __launch_bounds__(64)
 k_eigh_invit(const Seg* __restrict__ seg, int n0, z2* __restrict__ ws, double* __restrict__ eig,
              int* __restrict__ perm_out) {
     __shared__ double lam[EIG_TILE_MAXN], d[EIG_TILE_MAXN], e[EIG_TILE_MAXN];
-    __shared__ double x[EIG_TILE_MAXN], u0[EIG_TILE_MAXN], u1[EIG_TILE_MAXN], u2[EIG_TILE_MAXN];
+    __shared__ double Xs[CL_MAX * XLD];  // cluster vectors, member-major
+    __shared__ double Ws[CL_MAX * XLD];  // T X; single-vector LU rows
+    __shared__ double KV[2 * CL_MAX * KLD];        // Ritz matrix K and its eigenvectors V
+    __shared__ int rp[64];
+    __shared__ double rc[64];
+    __shared__ int ord[CL_MAX];
     const Mat M = mat_of(seg, 0, n0, blockIdx.y);
     const int n = M.n, g = blockIdx.x, lane = threadIdx.x;
     if (g >= n) return;
@@ -1019,6 +1183,9 @@ k_eigh_invit(const Seg* __restrict__ seg, int n0, z2* __restrict__ ws, double* _
     const int s = W.bs[g], be = W.be[g];
     const double ortol = W.ortol[g];
     if (!(g == s || lam[g] - lam[g - 1] > ortol)) return;
+    // the cluster: g and the following eigenvalues of the block closer than ortol to their predecessor
+    int mc = 1;
+    while (g + mc < be && lam[g + mc] - lam[g + mc - 1] <= ortol) ++mc;
     const int m = be - s;
     for (int j = lane; j < m; j += 64) {
         d[j] = W.d[s + j];
@@ -1028,56 +1195,103 @@ k_eigh_invit(const Seg* __restrict__ seg, int n0, z2* __restrict__ ws, double* _
     for (int j = lane; j < m; j += 64) tn = fmax(tn, fabs(d[j]) + (j > 0 ? fabs(e[j - 1]) : 0.0) + fabs(e[j]));
     const double pivmin = DBL_EPSILON * fmax(wmax(tn), DBL_MIN);
     __syncthreads();
-    for (int g2 = g;; ++g2) {
+    if (mc >= 2 && mc <= CL_MAX) {
+        for (int k = 0; k < mc; ++k)
+            for (int j = lane; j < m; j += 64) Xs[k * XLD + j] = start_value(j, g + k);
+        __syncthreads();
+        for (int it = 0; it < 3; ++it) {
+            if (lane < mc) {
+                // one slice per eigenvalue index: clusters run in separate workgroups at once
+                double* lu = W.lu + (int64_t)(g + lane) * 3 * n;
+                tri_solve(m, d, e, lam[g + lane], pivmin, Xs + lane * XLD, lu, lu + n, lu + 2 * n);
+            }
+            __syncthreads();
+            for (int pass = 0; pass < (it == 2 ? 2 : 1); ++pass) {
+                for (int j = 0; j < mc; ++j) {
+                    double* xj = Xs + j * XLD;
+                    wave_normalize(m, xj);
+                    __syncthreads();
+                    if (lane > j && lane < mc) {
+                        double* xk = Xs + lane * XLD;
+                        double dt = 0.0;
+                        for (int r = 0; r < m; ++r) dt += xj[r] * xk[r];
+                        for (int r = 0; r < m; ++r) xk[r] -= dt * xj[r];
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        // Rayleigh-Ritz: Y = T X, then K = X^T Y (symmetrized)
+        if (lane < mc) {
+            const double* x = Xs + lane * XLD;
+            double* y = Ws + lane * XLD;
+            for (int r = 0; r < m; ++r) {
+                double v = d[r] * x[r];
+                if (r > 0) v += e[r - 1] * x[r - 1];
+                if (r + 1 < m) v += e[r] * x[r + 1];
+                y[r] = v;
+            }
+        }
+        __syncthreads();
+        double* K = KV;
+        double* V = KV + CL_MAX * KLD;
+        if (lane < mc) {
+            const double* y = Ws + lane * XLD;
+            for (int j = 0; j < mc; ++j) {
+                const double* xj = Xs + j * XLD;
+                double v = 0.0;
+                for (int r = 0; r < m; ++r) v += xj[r] * y[r];
+                K[j * KLD + lane] = v;
+            }
+        }
+        __syncthreads();
+        for (int i = lane; i < mc * mc; i += 64) {
+            const int r = i / mc, c = i - r * mc;
+            if (r < c) {
+                const double v = 0.5 * (K[r * KLD + c] + K[c * KLD + r]);
+                K[r * KLD + c] = v;
+                K[c * KLD + r] = v;
+            }
+        }
+        __syncthreads();
+        jacobi_small(mc, K, V, rp, rc);
+        // ascending order of the Ritz values (ties by index)
+        if (lane < mc) {
+            const double kv = K[lane * KLD + lane];
+            int r = 0;
+            for (int j = 0; j < mc; ++j) {
+                const double kj = K[j * KLD + j];
+                r += (kj < kv || (kj == kv && j < lane)) ? 1 : 0;
+            }
+            ord[r] = lane;
+        }
+        __syncthreads();
+        // Z[:, g + k] = X V[:, ord[k]] on the block, zero elsewhere
+        for (int k = 0; k < mc; ++k) {
+            const int c = ord[k];
+            double* zc = W.Z + (int64_t)(g + k) * n;
+            for (int j = lane; j < n; j += 64) {
+                double v = 0.0;
+                if (j >= s && j < be)
+                    for (int q = 0; q < mc; ++q) v += Xs[q * XLD + (j - s)] * V[q * KLD + c];
+                zc[j] = v;
+            }
+        }
+        return;
+    }
+    // one eigenvalue, or a cluster too large for the block: members in turn,
+    // each orthogonalized against the earlier ones inside its iteration
+    double* x = Ws;
+    double* u0 = Ws + XLD;
+    double* u1 = Ws + 2 * XLD;
+    double* u2 = Ws + 3 * XLD;
+    for (int g2 = g; g2 < g + mc; ++g2) {
         const double lm = lam[g2];
         for (int j = lane; j < m; j += 64) x[j] = start_value(j, g2);
         __syncthreads();
         for (int it = 0; it < 3; ++it) {
-            if (lane == 0) {
-                // (T - lm) x = rhs by elimination with partial pivoting: row j of
-                // the upper factor is (u0, u1, u2) at columns j, j+1, j+2
-                double p0 = d[0] - lm, p1 = m > 1 ? e[0] : 0.0, p2 = 0.0;
-                double ri = x[0];
-                for (int j = 0; j + 1 < m; ++j) {
-                    double q0 = e[j], q1 = d[j + 1] - lm, q2 = j + 2 < m ? e[j + 1] : 0.0;
-                    double rn = x[j + 1];
-                    if (fabs(q0) > fabs(p0)) {
-                        double tq = p0;
-                        p0 = q0;
-                        q0 = tq;
-                        tq = p1;
-                        p1 = q1;
-                        q1 = tq;
-                        tq = p2;
-                        p2 = q2;
-                        q2 = tq;
-                        tq = ri;
-                        ri = rn;
-                        rn = tq;
-                    }
-                    if (p0 == 0.0) p0 = pivmin;
-                    const double mu = q0 / p0;
-                    u0[j] = p0;
-                    u1[j] = p1;
-                    u2[j] = p2;
-                    x[j] = ri;
-                    ri = rn - mu * ri;
-                    p0 = q1 - mu * p1;
-                    p1 = q2 - mu * p2;
-                    p2 = 0.0;
-                }
-                if (fabs(p0) < pivmin) p0 = p0 < 0.0 ? -pivmin : pivmin;
-                u0[m - 1] = p0;
-                x[m - 1] = ri;
-                for (int j = m - 1; j >= 0; --j) {
-                    double tt = x[j];
-                    if (j + 1 < m) tt -= u1[j] * x[j + 1];
-                    if (j + 2 < m) tt -= u2[j] * x[j + 2];
-                    x[j] = tt / u0[j];
-                }
-            }
+            if (lane == 0) tri_solve(m, d, e, lm, pivmin, x, u0, u1, u2);
             __syncthreads();
-            // orthogonalize against the earlier vectors of the cluster
             for (int p = g; p < g2; ++p) {
                 const double* zp = W.Z + (int64_t)p * n + s;
                 double dt = 0.0;
@@ -1086,24 +1300,12 @@ k_eigh_invit(const Seg* __restrict__ seg, int n0, z2* __restrict__ ws, double* _
                 for (int j = lane; j < m; j += 64) x[j] -= dt * zp[j];
                 __syncthreads();
             }
-            double xm = 0.0;
-            for (int j = lane; j < m; j += 64) xm = fmax(xm, fabs(x[j]));
-            xm = wmax(xm);
-            const double isc = xm > 0.0 ? 1.0 / xm : 1.0;
-            double nr = 0.0;
-            for (int j = lane; j < m; j += 64) {
-                x[j] *= isc;
-                nr += x[j] * x[j];
-            }
-            nr = wsum(nr);
-            const double inr = 1.0 / sqrt(nr);
-            for (int j = lane; j < m; j += 64) x[j] *= inr;
+            wave_normalize(m, x);
             __syncthreads();
         }
         double* zc = W.Z + (int64_t)g2 * n;
         for (int j = lane; j < n; j += 64) zc[j] = (j >= s && j < be) ? x[j - s] : 0.0;
         __syncthreads();
-        if (!(g2 + 1 < be && lam[g2 + 1] - lam[g2] <= ortol)) break;
     }
 }
 

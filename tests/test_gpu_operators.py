@@ -233,7 +233,7 @@ def test_cholesky_flags_rank_deficient(dev, nb):
 def test_subspace_eigh(dev, nb):
     log(f"eigh nb={nb}")
     rng = np.random.default_rng(nb)
-    batch = 6 if nb >= 33 else 3
+    batch = 7 if nb >= 33 else 3
     H = rng.standard_normal((batch, nb, nb)) + 1j * rng.standard_normal((batch, nb, nb))
     H = H + np.conj(np.transpose(H, (0, 2, 1)))
     if nb >= 5:
@@ -249,6 +249,8 @@ def test_subspace_eigh(dev, nb):
         ev[5:13] = ev[5] + 1e-9 * np.arange(8)
         H[4] = 1e3 * ((Q * ev) @ Q.conj().T)
         H[5] = np.eye(nb) + 0j                               # every eigenvalue equal
+        # one cluster of nb eigenvalues 1e-7 apart (larger than a block cluster)
+        H[6] = (Q * (1.0 + 1e-7 * np.arange(nb))) @ Q.conj().T
     eig = dev.empty((batch, nb), dev.torch.float64)
     vec = dev.empty((batch, nb, nb), dev.torch.complex128)
     ws = dev.ws(dev.D.dpp_eigh_workspace_size(nb, batch))
