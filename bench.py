@@ -49,6 +49,8 @@ sys.path.insert(0, ROOT)
 METRIC = "H·C bands·k/s and s per SCF iter, mixed vs FP64 GPU at 1e-6 Ha/atom"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
 MAX_WORKERS = 16  # the GPU machine's CPU share for one GPU
 
 WORKLOADS = {
@@ -310,6 +312,32 @@ def roofline_of(kern, workload):
     return roof, contr
 
 
+def roofline_mixed_contractions(kern):
+    """The mixed-precision bulk's contractions.  A^dag B on split-BF16 MFMA
+    executes 4 BF16 MFMA flops per algorithmic flop (four split products), so
+    its MFMA bound is BF16 peak / 4 = 625 TF/s of algorithmic flops, above the
+    HBM bound at its 32 flop/B (128 bands): it is reported against HBM, with
+    the BF16 MFMA busy fraction beside it.  X M on FP32 MFMA is bound by the
+    FP32 MFMA peak (157.3 TF/s < 8 TB/s x 32 flop/B)."""
+    out = {}
+    if "overlap" in kern and kern["overlap"]["alg_flops"]:
+        k = kern["overlap"]
+        t = k["ms_total"] * 1e-3
+        gbs = k["alg_bytes"] / t / 1e9
+        out["overlap"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": gbs / HBM_PEAK_GBS, "avg_launch_us": k["avg_us"],
+                          "alg_TFLOPs": k["alg_flops"] / t / 1e12,
+                          "bf16_mfma_busy_frac": 4 * k["alg_flops"] / t / (BF16_PEAK_TFLOPS * 1e12),
+                          "dtype": "split-BF16 (16x16x32 MFMA, 4 products, FP32 accumulation, FP64 chunk sums)"}
+    if "rotate" in kern and kern["rotate"]["alg_flops"]:
+        k = kern["rotate"]
+        tf = k["alg_flops"] / (k["ms_total"] * 1e-3) / 1e12
+        out["rotate"] = {"bound": "mfma", "achieved": tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / FP32_PEAK_TFLOPS, "avg_launch_us": k["avg_us"],
+                         "dtype": "f32 (16x16x4 MFMA, FP32 accumulation)"}
+    return out
+
+
 def pmc_probe(kind, workload):
     """A short loop for counter collection under rocprofv3 --pmc."""
     import torch
@@ -455,8 +483,10 @@ def main():
         "scf_convergence": conv,
         "timed_region_precision": {k: {"after_last_step": v["timed_prec_end"],
                                        "band_residual": v["residual_after_timed"]} for k, v in results.items()},
-        "mixed_note": "mixed = FFT passes, potential multiply and density in FP32 until the band residual "
-                      "falls below 1e-4 Ha, FP64 after; contractions, Cholesky, eigensolver and reductions in FP64",
+        "mixed_note": "mixed = FFT passes, potential multiply and density in FP32, overlaps on split-BF16 MFMA "
+                      "and X.M contractions on FP32 MFMA (FP32 accumulation), until the band residual falls below "
+                      "1e-4 Ha, FP64 after; Cholesky, eigensolver, energies and reductions in FP64",
+        "roofline_contractions_mixed": roofline_mixed_contractions(results["mixed"]["kernels"]),
         "tuning": {k: v["tuning"] for k, v in results.items()},
         "roofline": roof,
         "roofline_contractions": contr,

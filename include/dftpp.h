@@ -57,8 +57,14 @@ typedef enum {
 
 typedef enum {
     DPP_F64 = 0,   /* everything in FP64                                    */
-    DPP_F32 = 1    /* FFT passes and the potential multiply in FP32;
-                      contractions and reductions keep FP64 accumulation   */
+    DPP_F32 = 1    /* the mixed-precision bulk: FFT passes, the potential
+                      multiply and the density transforms in FP32; A^dag B
+                      contractions on split-BF16 MFMA (inputs rounded to
+                      FP32 and split into two BF16 parts, all four products,
+                      FP32 accumulation over 1024-point chunks, FP64 sums of
+                      the chunks); X M contractions on FP32 MFMA with FP32
+                      accumulation; Cholesky, eigensolver, energies and
+                      other reductions in FP64                             */
 } dpp_precision;
 
 /* Device status word bits (dpp_ctx_status). */
@@ -185,14 +191,21 @@ dpp_status dpp_apply_H(dpp_ham ham, int nb, const dpp_c64 *C, int64_t ldC, dpp_c
 /* --------------------------------------------------------- contractions -- */
 
 /* U = scale * A^dag B (nbA x nbB, row-major dpp_c64, device) over the npw
- * coefficients of `basis`; scale = Omega gives the overlap A^dag O B.
+ * coefficients of `basis`; scale = Omega gives the overlap A^dag O B (the
+ * overlap and subspace matrices of Sec. 2.1).  prec: DPP_F64 (FP64 MFMA) or
+ * DPP_F32 (split-BF16 MFMA with FP32 accumulation per 1024 points and FP64
+ * sums of those partials; relative error ~1e-7 of the row norms).  U is
+ * FP64 either way.  ws: overlap_ws bytes (dpp_workspace_size covers it).
  * Deterministic (fixed reduction order). */
 dpp_status dpp_overlap(dpp_basis basis, int nbA, const dpp_c64 *A, int64_t ldA, int nbB,
-                       const dpp_c64 *B, int64_t ldB, double scale, dpp_c64 *U, void *ws);
+                       const dpp_c64 *B, int64_t ldB, double scale, dpp_c64 *U, dpp_precision prec,
+                       void *ws);
 /* out = beta * out + X M: X is nbX bands, M is nbX x nbO (row-major, device),
- * out is nbO bands.  out must not alias X. */
+ * out is nbO bands.  out must not alias X.  prec: DPP_F64 (FP64 MFMA) or
+ * DPP_F32 (X and M rounded to FP32, FP32 MFMA and accumulation; out and the
+ * beta term in FP64). */
 dpp_status dpp_rotate(dpp_basis basis, int nbX, const dpp_c64 *X, int64_t ldX, int nbO,
-                      const dpp_c64 *M, double beta, dpp_c64 *out, int64_t ldout);
+                      const dpp_c64 *M, double beta, dpp_c64 *out, int64_t ldout, dpp_precision prec);
 /* U = R^dag R (Cholesky, R upper triangular with positive real diagonal) of
  * the Hermitian positive-definite nb x nb matrix U (device, row-major), then
  * Rinv = R^{-1}.  A pivot R_jj^2 <= 1e-14 max_i U_ii latches

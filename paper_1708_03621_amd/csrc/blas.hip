@@ -1,5 +1,6 @@
-// Contractions on wavefunction blocks (FP64 MFMA), Cholesky factorization and
-// triangular inverse, Hermitian Jacobi eigensolver, and the full H apply.
+// Contractions on wavefunction blocks (FP64 MFMA; split-BF16 and FP32 MFMA
+// for the mixed-precision bulk), Cholesky factorization and triangular
+// inverse, Hermitian Jacobi eigensolver, and the full H apply.
 //
 // Complex products are built from real 16x16x4 FP64 MFMAs (v_mfma_f64_16x16x4f64):
 //   A^dag B :  Re = Ar.Br + Ai.Bi,  Im = Ar.Bi - Ai.Br
@@ -13,6 +14,7 @@
 #include <mutex>
 #include <string>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "blockops.h"
@@ -21,9 +23,22 @@
 namespace dpp {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// FP32 16x16x4: operands as for FP64; result element v of lane l is
+// D[4 (l / 16) + v][l % 16] (measured on gfx950).
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// BF16 16x16x32: A[i][k] in lane i + 16 (k / 8), element k % 8; B[k][j] in
+// lane j + 16 (k / 8), element k % 8; result element v of lane l is
+// D[4 (l / 16) + v][l % 16] (measured on gfx950).
+__device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // Load through the global address space (table pointers are otherwise
@@ -234,6 +249,348 @@ void overlap_worklist(const std::vector<OvTask>& h, int ov_mode, std::vector<int
     }
 }
 
+// ------------------------------------------- A^dag B, split-BF16 MFMA ------
+// The mixed-precision bulk: every FP64 input is rounded to FP32 and split
+// into x = hi + lo, two BF16 values (|x - hi - lo| <= 2^-16 |x|).  The four
+// products hi hi' + hi lo' + lo hi' + lo lo' accumulate in FP32 (all four:
+// without lo lo' the diagonal of A^dag A would be biased low by ~1e-6
+// relative, since every dropped term there is positive).  A complex point
+// is two consecutive K entries (re, im): Re = <(Ar, Ai), (Br, Bi)> and
+// Im = <(Ar, Ai), (Bi, -Br)>, so a 16x16x32 MFMA covers 16 points.  FP32
+// sums run over at most 128 points; their partials are summed in FP64 in
+// fixed order.
+//
+// Two launch forms:
+//  - up to 15 output tiles per task (<= 48 bands): the FP64 kernel's shape, a
+//    wave per 2x2 tile block over 64 points, four waves per 256-point chunk,
+//    FP64 partials per chunk (k_overlap_reduce);
+//  - larger tasks: one workgroup per (task, 128-point slice) computes every
+//    output tile.  Each 16-point step of the slice is read from HBM once,
+//    split into BF16 hi/lo by the whole workgroup and staged in LDS (double
+//    buffered, one barrier per step); eight waves then take 4 x 2 tile
+//    blocks from LDS.  FP32 partials per slice (k_overlap_reduce_slices).
+constexpr int OVB_WAVES = 4;
+constexpr int OVW_WAVES = 8;
+constexpr int OVW_SLICE = 128;  // points per workgroup
+constexpr int OVW_ROW = 72;     // LDS row: hi (32 BF16), lo (32 BF16), pad (8); 144 bytes
+constexpr int OVW_MIN_TILES = 16;
+
+__device__ __forceinline__ void bsplit(double x, __bf16& hi, __bf16& lo) {
+    const float f = (float)x;
+    hi = (__bf16)f;
+    lo = (__bf16)(f - (float)hi);
+}
+
+// (re, im) pairs -> (im, -re) pairs on an 8-element operand.
+__device__ __forceinline__ bf8 swap_neg(bf8 v) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4 u = __builtin_bit_cast(u4, v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = ((u[i] >> 16) | (u[i] << 16)) ^ 0x80000000u;
+    return __builtin_bit_cast(bf8, u);
+}
+
+template <int TA, int TB>
+__device__ __forceinline__ void ovb_block(const OvTask& T, double2* __restrict__ part,
+                                          double (*red)[2][4][64], int chunk, int blk) {
+    const int tilesA = (T.nbA + 15) / 16;
+    const int sB = (T.tilesB + TB - 1) / TB, sA = (tilesA + TA - 1) / TA;
+    if (blk >= sA * sB) return;
+    const int ti0 = (blk / sB) * TA, tj0 = (blk % sB) * TB;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, ks = lane >> 4;
+    const double2* Ap[TA];
+    const double2* Bp[TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a) Ap[a] = T.A + (int64_t)min((ti0 + a) * 16 + r, T.nbA - 1) * T.ldA;
+#pragma unroll
+    for (int b = 0; b < TB; ++b) Bp[b] = T.B + (int64_t)min((tj0 + b) * 16 + r, T.nbB - 1) * T.ldB;
+    f4 cre[TA][TB], cim[TA][TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+            cre[a][b] = f4{0, 0, 0, 0};
+            cim[a][b] = f4{0, 0, 0, 0};
+        }
+    constexpr int sub = OV_CHUNK / OVB_WAVES;
+    const int ga = chunk * OV_CHUNK + w * sub, ge = min(T.npw, ga + sub);
+    const int nst = ge > ga ? (ge - ga + 15) / 16 : 0;
+    // lane covers points g + 4 ks + s, s = 0..3, of the step at g (K entries
+    // 8 ks + 2 s and 8 ks + 2 s + 1); clamped, unconditional loads
+    double2 an[TA][4], bn[TB][4];
+    auto load = [&](int g) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int q = min(g + 4 * ks + s, T.npw - 1);
+#pragma unroll
+            for (int a = 0; a < TA; ++a) an[a][s] = gld(Ap[a] + q);
+#pragma unroll
+            for (int b = 0; b < TB; ++b) bn[b][s] = gld(Bp[b] + q);
+        }
+    };
+    if (nst > 0) load(ga);
+    for (int st = 0; st < nst; ++st) {
+        const int g = ga + 16 * st;
+        bf8 ah[TA], al[TA], bh[TB], bl[TB];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bool in = g + 4 * ks + s < ge;
+#pragma unroll
+            for (int a = 0; a < TA; ++a) {
+                __bf16 h, l;
+                bsplit(in ? an[a][s].x : 0.0, h, l);
+                ah[a][2 * s] = h;
+                al[a][2 * s] = l;
+                bsplit(in ? an[a][s].y : 0.0, h, l);
+                ah[a][2 * s + 1] = h;
+                al[a][2 * s + 1] = l;
+            }
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+                __bf16 h, l;
+                bsplit(bn[b][s].x, h, l);
+                bh[b][2 * s] = h;
+                bl[b][2 * s] = l;
+                bsplit(bn[b][s].y, h, l);
+                bh[b][2 * s + 1] = h;
+                bl[b][2 * s + 1] = l;
+            }
+        }
+        if (st + 1 < nst) load(g + 16);
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+            const bf8 ch = swap_neg(bh[b]), cl = swap_neg(bl[b]);
+#pragma unroll
+            for (int a = 0; a < TA; ++a) {
+                cre[a][b] = mfma(al[a], bl[b], cre[a][b]);
+                cre[a][b] = mfma(al[a], bh[b], cre[a][b]);
+                cre[a][b] = mfma(ah[a], bl[b], cre[a][b]);
+                cre[a][b] = mfma(ah[a], bh[b], cre[a][b]);
+                cim[a][b] = mfma(al[a], cl, cim[a][b]);
+                cim[a][b] = mfma(al[a], ch, cim[a][b]);
+                cim[a][b] = mfma(ah[a], cl, cim[a][b]);
+                cim[a][b] = mfma(ah[a], ch, cim[a][b]);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+            if (ti0 + a >= tilesA || tj0 + b >= T.tilesB) continue;  // uniform over the workgroup
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                red[w][0][v][lane] = (double)cre[a][b][v];
+                red[w][1][v][lane] = (double)cim[a][b][v];
+            }
+            __syncthreads();
+            if (w == 0) {
+                const int tile = (ti0 + a) * T.tilesB + tj0 + b;
+                double2* dst = part + T.part_off + ((int64_t)chunk * T.ntiles + tile) * 256;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double sr = 0, si = 0;
+                    for (int u = 0; u < OVB_WAVES; ++u) {
+                        sr += red[u][0][v][lane];
+                        si += red[u][1][v][lane];
+                    }
+                    dst[(4 * (lane >> 4) + v) * 16 + (lane & 15)] = double2{sr, si};
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// Small tasks: work list entries (task, chunk, block) as overlap_worklist's.
+__global__ void __launch_bounds__(64 * OVB_WAVES)
+k_overlap_bf16(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part,
+               const int* __restrict__ act, const int4* __restrict__ work) {
+    __shared__ double red[OVB_WAVES][2][4][64];
+    int ti, chunk, blk;
+    if (work) {
+        const int4 w = work[blockIdx.x];
+        ti = w.x, chunk = w.y, blk = w.z;
+    } else {
+        ti = (int)blockIdx.z, chunk = (int)blockIdx.x, blk = (int)blockIdx.y;
+    }
+    const OvTask T = tasks ? tasks[ti] : single;
+    if (act && !act[T.item]) return;
+    if (chunk >= T.nchunk) return;
+    const int tA = (T.nbA + 15) / 16, tB = T.tilesB;
+    if (tA >= 2 && tB >= 2)
+        ovb_block<2, 2>(T, part, red, chunk, blk);
+    else if (tB >= 2)
+        ovb_block<1, 2>(T, part, red, chunk, blk);
+    else if (tA >= 2)
+        ovb_block<2, 1>(T, part, red, chunk, blk);
+    else
+        ovb_block<1, 1>(T, part, red, chunk, blk);
+}
+
+__host__ __device__ inline int ovw_slices(int npw) { return (npw + OVW_SLICE - 1) / OVW_SLICE; }
+
+// Large tasks: one workgroup per (task, slice) (work list entries, or the
+// grid (slice, task)).  LDS rows: A rows 0 .. 16 tilesA - 1, then B rows
+// (rows past a band count are zero).  FP32 partials, as float2, at the
+// task's partial offset: slice s, tile t at (s ntiles + t) 256.
+__global__ void __launch_bounds__(64 * OVW_WAVES)
+k_overlap_bf16_wg(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part,
+                  const int* __restrict__ act, const int4* __restrict__ work) {
+    __shared__ __attribute__((aligned(16))) __bf16 st[2][2 * EIG_TILE_MAXN * OVW_ROW];
+    int ti, slice;
+    if (work) {
+        const int4 w = work[blockIdx.x];
+        ti = w.x, slice = w.y;
+    } else {
+        ti = (int)blockIdx.y, slice = (int)blockIdx.x;
+    }
+    const OvTask T = tasks ? tasks[ti] : single;
+    if (act && !act[T.item]) return;
+    if (slice >= ovw_slices(T.npw)) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r = lane & 15, ks = lane >> 4;
+    const int tilesA = (T.nbA + 15) / 16, tilesB = T.tilesB;
+    const int rowsA = 16 * tilesA, nrows = rowsA + 16 * tilesB;
+    // staging: thread -> LDS row tid / 2, points 8 (tid % 2) .. + 7 of a step
+    const int srow = tid >> 1, sp = (tid & 1) * 8;
+    const bool isA = srow < rowsA;
+    const int brow = isA ? srow : srow - rowsA;
+    const bool valid = srow < nrows && brow < (isA ? T.nbA : T.nbB);
+    const double2* src = isA ? T.A + (int64_t)brow * T.ldA : T.B + (int64_t)brow * T.ldB;
+    const int g0 = slice * OVW_SLICE, g1 = min(T.npw, g0 + OVW_SLICE);
+    const int nst = (g1 - g0 + 15) / 16;
+    double2 raw[8];
+    // rows past the band counts load nothing; points past the slice are
+    // clamped to the last point (and zeroed when staged)
+    auto load = [&](int g) {
+        if (valid) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) raw[e] = gld(src + min(g + sp + e, T.npw - 1));
+        }
+    };
+    auto stage = [&](int buf, int g) {
+        if (srow >= nrows) return;
+        bf8 h0, h1, l0, l1;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const bool in = valid && g + sp + e < g1;
+            __bf16 hr, lr, hi, li;
+            bsplit(in ? raw[e].x : 0.0, hr, lr);
+            bsplit(in ? raw[e].y : 0.0, hi, li);
+            if (e < 4) {
+                h0[2 * e] = hr, h0[2 * e + 1] = hi, l0[2 * e] = lr, l0[2 * e + 1] = li;
+            } else {
+                h1[2 * e - 8] = hr, h1[2 * e - 7] = hi, l1[2 * e - 8] = lr, l1[2 * e - 7] = li;
+            }
+        }
+        __bf16* row = st[buf] + srow * OVW_ROW;
+        *(bf8*)(row + 2 * sp) = h0;
+        *(bf8*)(row + 2 * sp + 8) = h1;
+        *(bf8*)(row + 32 + 2 * sp) = l0;
+        *(bf8*)(row + 32 + 2 * sp + 8) = l1;
+    };
+    // this wave's tiles: A tiles 4 ga .. 4 ga + 3, B tiles 2 gb, 2 gb + 1
+    const int ga = w >> 2, gb = w & 3;
+    f4 cre[4][2], cim[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cre[a][b] = f4{0, 0, 0, 0};
+            cim[a][b] = f4{0, 0, 0, 0};
+        }
+    if (nst > 0) load(g0);
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        stage(buf, g0 + 16 * s);
+        if (s + 1 < nst) load(g0 + 16 * (s + 1));
+        __syncthreads();
+        const __bf16* S = st[buf];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int tb = 2 * gb + b;
+            if (tb >= tilesB) continue;  // uniform over the wave
+            const __bf16* rb = S + (rowsA + 16 * tb + r) * OVW_ROW + 8 * ks;
+            const bf8 bh = *(const bf8*)rb, bl = *(const bf8*)(rb + 32);
+            const bf8 ch = swap_neg(bh), cl = swap_neg(bl);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int ta = 4 * ga + a;
+                if (ta >= tilesA) continue;
+                const __bf16* ra = S + (16 * ta + r) * OVW_ROW + 8 * ks;
+                const bf8 ah = *(const bf8*)ra, al = *(const bf8*)(ra + 32);
+                cre[a][b] = mfma(al, bl, cre[a][b]);
+                cre[a][b] = mfma(al, bh, cre[a][b]);
+                cre[a][b] = mfma(ah, bl, cre[a][b]);
+                cre[a][b] = mfma(ah, bh, cre[a][b]);
+                cim[a][b] = mfma(al, cl, cim[a][b]);
+                cim[a][b] = mfma(al, ch, cim[a][b]);
+                cim[a][b] = mfma(ah, cl, cim[a][b]);
+                cim[a][b] = mfma(ah, ch, cim[a][b]);
+            }
+        }
+    }
+    float2* out = reinterpret_cast<float2*>(part + T.part_off) + (int64_t)slice * T.ntiles * 256;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int ta = 4 * ga + a, tb = 2 * gb + b;
+            if (ta >= tilesA || tb >= tilesB) continue;
+            float2* dst = out + (ta * tilesB + tb) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[(4 * ks + v) * 16 + r] = float2{cre[a][b][v], cim[a][b][v]};
+        }
+}
+
+// Sums the FP32 slice partials of every task in FP64, in fixed order.
+__global__ void k_overlap_reduce_slices(const OvTask* __restrict__ tasks, OvTask single,
+                                        const double2* __restrict__ part, const int* __restrict__ act) {
+    const OvTask& T = tasks ? tasks[blockIdx.y] : single;
+    if (act && !act[T.item]) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= T.ntiles * 256) return;
+    const int tile = e >> 8, ij = e & 255;
+    const int ti = tile / T.tilesB, tj = tile - ti * T.tilesB;
+    const int i = ti * 16 + (ij >> 4), j = tj * 16 + (ij & 15);
+    if (i >= T.nbA || j >= T.nbB) return;
+    const float2* p = reinterpret_cast<const float2*>(part + T.part_off) + e;
+    double sr = 0, si = 0;
+    const int ns = ovw_slices(T.npw);
+    for (int c = 0; c < ns; ++c) {
+        const float2 v = p[(int64_t)c * T.ntiles * 256];
+        sr += v.x;
+        si += v.y;
+    }
+    T.out[(int64_t)i * T.out_ld + j] = double2{T.scale * sr, T.scale * si};
+}
+
+// Which split-BF16 form a task table takes: the workgroup form when some
+// task has at least OVW_MIN_TILES output tiles and every task fits its LDS
+// rows and wave blocks (at most 128 bands on either side).
+bool overlap_bf16_wide(const std::vector<OvTask>& h) {
+    int mt = 0;
+    for (const OvTask& t : h) {
+        if (t.nbA > EIG_TILE_MAXN || t.nbB > EIG_TILE_MAXN) return false;
+        mt = std::max(mt, t.ntiles);
+    }
+    return mt >= OVW_MIN_TILES;
+}
+
+// Work list of the split-BF16 overlap: (task, slice) entries for the
+// workgroup form (as int4 {task, slice, 0, 0}), else overlap_worklist's.
+void overlap_worklist_bf16(const std::vector<OvTask>& h, std::vector<int4>& w) {
+    if (!overlap_bf16_wide(h)) {
+        overlap_worklist(h, 0, w);
+        return;
+    }
+    w.clear();
+    for (size_t i = 0; i < h.size(); ++i)
+        for (int c = 0; c < std::max(1, ovw_slices(h[i].npw)); ++c) w.push_back(int4{(int)i, c, 0, 0});
+}
+
+// Sums the chunk partials of every task in fixed order.
 __global__ void k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part,
                                  const int* __restrict__ act) {
     const OvTask& T = tasks ? tasks[blockIdx.y] : single;
@@ -280,23 +637,36 @@ OvTask make_ov_task(int npw, int nbA, const double2* A, int64_t ldA, int nbB, co
     return t;
 }
 
-dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
-                       const double2* B, int64_t ldB, double scale, double2* U, void* ws,
-                       size_t ws_bytes) {
+dpp_status overlap_single(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
+                          const double2* B, int64_t ldB, double scale, double2* U, void* ws, size_t ws_bytes,
+                          dpp_precision prec) {
     OvTask t = make_ov_task(npw, nbA, A, ldA, nbB, B, ldB, scale, U, nbB);
     if (overlap_ws_bytes(npw, nbA, nbB) > ws_bytes)
         return set_error(DPP_EINVAL, "overlap: workspace too small");
     if (t.ntiles > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: too many bands");
     double2* part = reinterpret_cast<double2*>(ws);
+    const int nblk = ov_task_blocks((nbA + 15) / 16, t.tilesB);
+    const bool wide = prec == DPP_F32 && overlap_bf16_wide(std::vector<OvTask>{t});
     {
         TimerScope ts_(ctx, DPP_TK_OVERLAP, 16.0 * npw * (nbA + nbB), 8.0 * npw * nbA * (double)nbB);
-        overlap_launch(ctx, nullptr, t, 1, t.nchunk, ov_task_blocks((nbA + 15) / 16, t.tilesB), t.ntiles > 1, part,
-                       nullptr);
+        if (wide)
+            hipLaunchKernelGGL(k_overlap_bf16_wg, dim3(std::max(1, ovw_slices(npw)), 1), dim3(64 * OVW_WAVES), 0,
+                               ctx->stream, (const OvTask*)nullptr, t, part, (const int*)nullptr,
+                               (const int4*)nullptr);
+        else if (prec == DPP_F32)
+            hipLaunchKernelGGL(k_overlap_bf16, dim3(t.nchunk, nblk, 1), dim3(64 * OVB_WAVES), 0, ctx->stream,
+                               (const OvTask*)nullptr, t, part, (const int*)nullptr, (const int4*)nullptr);
+        else
+            overlap_launch(ctx, nullptr, t, 1, t.nchunk, nblk, t.ntiles > 1, part, nullptr);
         DPP_LAUNCHED();
     }
     TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
-    hipLaunchKernelGGL(k_overlap_reduce, dim3((t.ntiles * 256 + 255) / 256, 1), dim3(256), 0, ctx->stream,
-                       (const OvTask*)nullptr, t, part, (const int*)nullptr);
+    if (wide)
+        hipLaunchKernelGGL(k_overlap_reduce_slices, dim3((t.ntiles * 256 + 255) / 256, 1), dim3(256), 0,
+                           ctx->stream, (const OvTask*)nullptr, t, part, (const int*)nullptr);
+    else
+        hipLaunchKernelGGL(k_overlap_reduce, dim3((t.ntiles * 256 + 255) / 256, 1), dim3(256), 0, ctx->stream,
+                           (const OvTask*)nullptr, t, part, (const int*)nullptr);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -304,9 +674,11 @@ dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t 
 // Batched: the caller has set part_off of every task (disjoint partial areas)
 // and copied the table to d_tasks.
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
-                         const int* act, int ov_mode, const int4* d_work, int nwork) {
-    const int ov_narrow = ov_mode == 1;
-    const bool full = ov_mode == 2;
+                         const int* act, int ov_mode, const int4* d_work, int nwork, dpp_precision prec) {
+    const bool bf = prec == DPP_F32;
+    const bool wide = bf && overlap_bf16_wide(h);  // the work list is overlap_worklist_bf16's
+    const int ov_narrow = !bf && ov_mode == 1;
+    const bool full = !bf && ov_mode == 2;
     if (h.empty()) return DPP_OK;
     int mc = 1, mt = 1, mblk = 1;
     double by = 0, fl = 0;
@@ -320,14 +692,30 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
     if (mt > 65535 || h.size() > 65535) return set_error(DPP_EUNSUPPORTED, "overlap: batch too large");
     {
         TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_OVERLAP, act ? 0.0 : by, act ? 0.0 : fl);
-        overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act, full,
-                       d_work, nwork);
+        if (wide) {
+            int ms = 1;
+            for (const OvTask& t : h) ms = std::max(ms, ovw_slices(t.npw));
+            const dim3 grid = d_work ? dim3((unsigned)nwork) : dim3(ms, h.size());
+            hipLaunchKernelGGL(k_overlap_bf16_wg, grid, dim3(64 * OVW_WAVES), 0, ctx->stream, d_tasks, OvTask{},
+                               part, act, d_work);
+        } else if (bf) {
+            const dim3 grid = d_work ? dim3((unsigned)nwork) : dim3(mc, mblk, h.size());
+            hipLaunchKernelGGL(k_overlap_bf16, grid, dim3(64 * OVB_WAVES), 0, ctx->stream, d_tasks, OvTask{}, part,
+                               act, d_work);
+        } else {
+            overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act,
+                           full, d_work, nwork);
+        }
         DPP_LAUNCHED();
     }
     if (full) return DPP_OK;
     TimerScope ts2_(ctx, act ? DPP_TK_MASKED : DPP_TK_BLOCKOPS);
-    hipLaunchKernelGGL(k_overlap_reduce, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
-                       ctx->stream, d_tasks, OvTask{}, (const double2*)part, act);
+    if (wide)
+        hipLaunchKernelGGL(k_overlap_reduce_slices, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
+                           ctx->stream, d_tasks, OvTask{}, (const double2*)part, act);
+    else
+        hipLaunchKernelGGL(k_overlap_reduce, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
+                           ctx->stream, d_tasks, OvTask{}, (const double2*)part, act);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -338,10 +726,14 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
 // and K step for all PT point tiles.  The loads of the next K step are issued
 // before the MFMAs of the current one.  Wide outputs take (1, 8); narrow ones
 // take PT > 1 when the batch still gives every CU many waves.
-template <int PT, int JT>
+// F32 (the mixed-precision bulk): X and M rounded to FP32, FP32 MFMA and
+// accumulation over the bands, the result (and beta out) in FP64.
+template <int PT, int JT, bool F32>
 __global__ void __launch_bounds__(64 * RT_WAVES)
 k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const int* __restrict__ act,
               const int2* __restrict__ work) {
+    using acc_t = typename std::conditional<F32, f4, d4>::type;
+    using real_t = typename std::conditional<F32, float, double>::type;
     // a work list (task, block) covers only the workgroups with points
     const int2 wk = work ? work[blockIdx.x] : int2{(int)blockIdx.y, (int)blockIdx.x};
     const RotTask T = tasks ? tasks[wk.x] : single;
@@ -352,13 +744,13 @@ k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const 
     const int njt = min(JT, (T.nbO + 15) / 16 - jt0);
     if (njt <= 0) return;
     const int c = lane & 15, ks = lane >> 4;
-    d4 dre[PT][JT], dim[PT][JT];
+    acc_t dre[PT][JT], dim[PT][JT];
 #pragma unroll
     for (int u = 0; u < PT; ++u)
 #pragma unroll
         for (int t = 0; t < JT; ++t) {
-            dre[u][t] = d4{0, 0, 0, 0};
-            dim[u][t] = d4{0, 0, 0, 0};
+            dre[u][t] = acc_t{0, 0, 0, 0};
+            dim[u][t] = acc_t{0, 0, 0, 0};
         }
     const int nterm = T.nbX2 > 0 ? 2 : 1;
     // K steps run over the rows of X then those of X2
@@ -393,12 +785,14 @@ k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const 
 #pragma unroll
         for (int t = 0; t < JT; ++t) {
             if (t < njt) {
+                const real_t mr = (real_t)m[t].x, mi = (real_t)m[t].y;
 #pragma unroll
                 for (int u = 0; u < PT; ++u) {
-                    dre[u][t] = mfma(m[t].x, x[u].x, dre[u][t]);
-                    dre[u][t] = mfma(-m[t].y, x[u].y, dre[u][t]);
-                    dim[u][t] = mfma(m[t].y, x[u].x, dim[u][t]);
-                    dim[u][t] = mfma(m[t].x, x[u].y, dim[u][t]);
+                    const real_t xr = (real_t)x[u].x, xi = (real_t)x[u].y;
+                    dre[u][t] = mfma(mr, xr, dre[u][t]);
+                    dre[u][t] = mfma(-mi, xi, dre[u][t]);
+                    dim[u][t] = mfma(mi, xr, dim[u][t]);
+                    dim[u][t] = mfma(mr, xi, dim[u][t]);
                 }
             }
         }
@@ -412,10 +806,11 @@ k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const 
             if (t < njt) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int j = (jt0 + t) * 16 + 4 * v + ks;
+                    // result row of element v: 4 v + l / 16 (FP64), 4 (l / 16) + v (FP32)
+                    const int j = (jt0 + t) * 16 + (F32 ? 4 * ks + v : 4 * v + ks);
                     if (j < T.nbO) {
                         double2* o = T.out + (int64_t)j * T.ldout + q;
-                        double2 r = double2{dre[u][t][v], dim[u][t][v]};
+                        double2 r = double2{(double)dre[u][t][v], (double)dim[u][t][v]};
                         if (T.beta != 0.0) {
                             const double2 p = *o;
                             r.x += T.beta * p.x;
@@ -455,11 +850,15 @@ static double rot_bytes(const RotTask& t) {
 
 template <int PT, int JT>
 static void rotate_go(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single, unsigned ntasks, int ntile,
-                      int jt0, const int* act, const int2* work, int nwork) {
+                      int jt0, const int* act, const int2* work, int nwork, bool f32) {
     const int nblk = (ntile + RT_WAVES * PT - 1) / (RT_WAVES * PT);
     const dim3 grid = work ? dim3((unsigned)nwork) : dim3(nblk, ntasks);
-    hipLaunchKernelGGL((k_rotate_mfma<PT, JT>), grid, dim3(64 * RT_WAVES), 0, ctx->stream, d_tasks, single, jt0, act,
-                       work);
+    if (f32)
+        hipLaunchKernelGGL((k_rotate_mfma<PT, JT, true>), grid, dim3(64 * RT_WAVES), 0, ctx->stream, d_tasks, single,
+                           jt0, act, work);
+    else
+        hipLaunchKernelGGL((k_rotate_mfma<PT, JT, false>), grid, dim3(64 * RT_WAVES), 0, ctx->stream, d_tasks,
+                           single, jt0, act, work);
 }
 
 // Launch the rotate kernel shape for the widest output of a batch; tiles =
@@ -475,26 +874,26 @@ static int rotate_pt_rule(int jtiles, int64_t tiles, int rot_pt) {
 }
 
 static dpp_status rotate_launch(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single, unsigned ntasks,
-                                int maxnpw, int maxnbO, int64_t tiles, const int* act, int rot_pt = 0,
-                                const int2* work = nullptr, int nwork = 0) {
+                                int maxnpw, int maxnbO, int64_t tiles, const int* act, int rot_pt,
+                                const int2* work, int nwork, bool f32) {
     const int ntile = (maxnpw + 15) / 16;
     const int jtiles = (maxnbO + 15) / 16;
     const int pt = rotate_pt_rule(jtiles, tiles, rot_pt);
     if (jtiles == 1) {
         if (pt == 4)
-            rotate_go<4, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
+            rotate_go<4, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
         else if (pt == 2)
-            rotate_go<2, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
+            rotate_go<2, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
         else
-            rotate_go<1, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
+            rotate_go<1, 1>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
     } else if (jtiles == 2) {
         if (pt == 2)
-            rotate_go<2, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
+            rotate_go<2, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
         else
-            rotate_go<1, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork);
+            rotate_go<1, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
     } else {
         for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT)
-            rotate_go<1, RT_JT>(ctx, d_tasks, single, ntasks, ntile, jt0, act, work, nwork);
+            rotate_go<1, RT_JT>(ctx, d_tasks, single, ntasks, ntile, jt0, act, work, nwork, f32);
     }
     DPP_LAUNCHED();
     return DPP_OK;
@@ -521,15 +920,15 @@ void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2
     }
 }
 
-dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
-                      const double2* M, double beta, double2* out, int64_t ldout) {
+dpp_status rotate_single(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
+                         const double2* M, double beta, double2* out, int64_t ldout, dpp_precision prec) {
     RotTask t = make_rot_task(npw, nbX, X, ldX, nbO, M, nbO, beta, out, ldout);
     TimerScope ts_(ctx, DPP_TK_ROTATE, rot_bytes(t), 8.0 * npw * nbX * (double)nbO);
-    return rotate_launch(ctx, nullptr, t, 1, npw, nbO, (npw + 15) / 16, nullptr);
+    return rotate_launch(ctx, nullptr, t, 1, npw, nbO, (npw + 15) / 16, nullptr, 0, nullptr, 0, prec == DPP_F32);
 }
 
 dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks, const int* act,
-                        int rot_pt, const int2* d_work, int nwork) {
+                        int rot_pt, const int2* d_work, int nwork, dpp_precision prec) {
     if (h.empty()) return DPP_OK;
     int mp = 1, mj = 1;
     int64_t tiles = 0;
@@ -542,7 +941,8 @@ dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTas
         fl += 8.0 * t.npw * (t.nbX + t.nbX2) * (double)t.nbO;
     }
     TimerScope ts_(ctx, act ? DPP_TK_MASKED : DPP_TK_ROTATE, act ? 0.0 : by, act ? 0.0 : fl);
-    return rotate_launch(ctx, d_tasks, RotTask{}, (unsigned)h.size(), mp, mj * 16, tiles, act, rot_pt, d_work, nwork);
+    return rotate_launch(ctx, d_tasks, RotTask{}, (unsigned)h.size(), mp, mj * 16, tiles, act, rot_pt, d_work, nwork,
+                         prec == DPP_F32);
 }
 
 // ------------------------------------------------- small-matrix products ---
@@ -1254,27 +1654,30 @@ using namespace dpp;
 // ------------------------------------------------------------- C ABI -------
 
 extern "C" dpp_status dpp_overlap(dpp_basis basis, int nbA, const dpp_c64* A, int64_t ldA, int nbB,
-                                  const dpp_c64* B, int64_t ldB, double scale, dpp_c64* U, void* ws) {
+                                  const dpp_c64* B, int64_t ldB, double scale, dpp_c64* U, dpp_precision prec,
+                                  void* ws) {
     clear_error();
     DPP_REQUIRE(basis && nbA >= 0 && nbB >= 0, "dpp_overlap: bad arguments");
+    DPP_REQUIRE(prec == DPP_F64 || prec == DPP_F32, "dpp_overlap: bad precision");
     DPP_REQUIRE((nbA == 0 || A) && (nbB == 0 || B), "dpp_overlap: null block");
     DPP_REQUIRE(ldA >= basis->npw && ldB >= basis->npw, "dpp_overlap: leading dimension < npw");
     if (nbA == 0 || nbB == 0) return DPP_OK;
     DPP_REQUIRE(U && ws, "dpp_overlap: null output or workspace");
-    return overlap_f64(basis->grid->ctx, (int)basis->npw, nbA, (const double2*)A, ldA, nbB, (const double2*)B,
-                       ldB, scale, (double2*)U, ws, overlap_ws_bytes((int)basis->npw, nbA, nbB));
+    return overlap_single(basis->grid->ctx, (int)basis->npw, nbA, (const double2*)A, ldA, nbB, (const double2*)B,
+                          ldB, scale, (double2*)U, ws, overlap_ws_bytes((int)basis->npw, nbA, nbB), prec);
 }
 
 extern "C" dpp_status dpp_rotate(dpp_basis basis, int nbX, const dpp_c64* X, int64_t ldX, int nbO,
-                                 const dpp_c64* M, double beta, dpp_c64* out, int64_t ldout) {
+                                 const dpp_c64* M, double beta, dpp_c64* out, int64_t ldout, dpp_precision prec) {
     clear_error();
     DPP_REQUIRE(basis && nbX >= 0 && nbO >= 0, "dpp_rotate: bad arguments");
+    DPP_REQUIRE(prec == DPP_F64 || prec == DPP_F32, "dpp_rotate: bad precision");
     DPP_REQUIRE(ldX >= basis->npw && ldout >= basis->npw, "dpp_rotate: leading dimension < npw");
     if (nbO == 0) return DPP_OK;
     DPP_REQUIRE(out && (nbX == 0 || (X && M)), "dpp_rotate: null pointer");
     DPP_REQUIRE((const void*)X != (const void*)out, "dpp_rotate: out must not alias X");
-    return rotate_f64(basis->grid->ctx, (int)basis->npw, nbX, (const double2*)X, ldX, nbO, (const double2*)M,
-                      beta, (double2*)out, ldout);
+    return rotate_single(basis->grid->ctx, (int)basis->npw, nbX, (const double2*)X, ldX, nbO, (const double2*)M,
+                         beta, (double2*)out, ldout, prec);
 }
 
 extern "C" dpp_status dpp_cholesky_inverse(dpp_ctx ctx, int nb, int batch, const dpp_c64* U, dpp_c64* Rinv) {
@@ -1401,10 +1804,10 @@ extern "C" dpp_status dpp_apply_H(dpp_ham ham, int nb, const dpp_c64* C, int64_t
         double2* Pi = reinterpret_cast<double2*>(base);
         char* ovws = base + (((size_t)ham->nproj * nb * sizeof(double2) + 255) / 256) * 256;
         // Pi' = D P^dag C, then HC += P Pi'
-        DPP_TRY(overlap_f64(b->grid->ctx, (int)b->npw, ham->nproj, ham->d_P, b->npw, nb, (const double2*)C, ldC,
-                            ham->D, Pi, ovws, overlap_ws_bytes((int)b->npw, ham->nproj, nb)));
-        DPP_TRY(rotate_f64(b->grid->ctx, (int)b->npw, ham->nproj, ham->d_P, b->npw, nb, Pi, 1.0, (double2*)HC,
-                           ldHC));
+        DPP_TRY(overlap_single(b->grid->ctx, (int)b->npw, ham->nproj, ham->d_P, b->npw, nb, (const double2*)C,
+                               ldC, ham->D, Pi, ovws, overlap_ws_bytes((int)b->npw, ham->nproj, nb), prec));
+        DPP_TRY(rotate_single(b->grid->ctx, (int)b->npw, ham->nproj, ham->d_P, b->npw, nb, Pi, 1.0, (double2*)HC,
+                              ldHC, prec));
     }
     return DPP_OK;
 }
@@ -1437,11 +1840,11 @@ extern "C" dpp_status dpp_cholesky_orthonormalize(dpp_basis basis, int nb, dpp_c
     double2* Yc = reinterpret_cast<double2*>(take((size_t)nb * basis->npw * 16));
     void* ovws = take(overlap_ws_bytes((int)basis->npw, nb, nb));
     dpp_ctx ctx = basis->grid->ctx;
-    DPP_TRY(overlap_f64(ctx, (int)basis->npw, nb, (const double2*)Y, ldY, nb, (const double2*)Y, ldY,
+    DPP_TRY(overlap_single(ctx, (int)basis->npw, nb, (const double2*)Y, ldY, nb, (const double2*)Y, ldY,
                         basis->grid->omega, U, ovws, overlap_ws_bytes((int)basis->npw, nb, nb)));
     DPP_TRY(dpp_cholesky_inverse(ctx, nb, 1, (const dpp_c64*)U, (dpp_c64*)Ri));
     DPP_HIP(hipMemcpy2DAsync(Yc, basis->npw * 16, Y, ldY * 16, basis->npw * 16, nb, hipMemcpyDeviceToDevice,
                              ctx->stream));
-    DPP_TRY(rotate_f64(ctx, (int)basis->npw, nb, Yc, basis->npw, nb, Ri, 0.0, (double2*)Y, ldY));
+    DPP_TRY(rotate_single(ctx, (int)basis->npw, nb, Yc, basis->npw, nb, Ri, 0.0, (double2*)Y, ldY));
     return DPP_OK;
 }

@@ -296,12 +296,17 @@ struct OvJob {
 
 // Overlap launch over a task table with its work list (only the workgroups
 // that have work are launched).
+// The contractions follow the system's current precision: split-BF16 (A^dag B)
+// and FP32 (X M) MFMA in the mixed-precision bulk, FP64 otherwise.
 dpp_status overlap_run(dpp_system_s* s, const std::vector<OvTask>& t, const OvTask* d, const int* act) {
     std::vector<int4> w;
-    overlap_worklist(t, s->ov_mode, w);
+    if (s->prec == DPP_F32)
+        overlap_worklist_bf16(t, w);
+    else
+        overlap_worklist(t, s->ov_mode, w);
     const int4* dw = nullptr;
     DPP_TRY(table_t(s, w, &dw));
-    return overlap_tasks(s->ctx, t, d, s->ov_part, act, s->ov_mode, dw, (int)w.size());
+    return overlap_tasks(s->ctx, t, d, s->ov_part, act, s->ov_mode, dw, (int)w.size(), s->prec);
 }
 
 dpp_status rotate_run(dpp_system_s* s, const std::vector<RotTask>& t, const RotTask* d, const int* act) {
@@ -309,7 +314,7 @@ dpp_status rotate_run(dpp_system_s* s, const std::vector<RotTask>& t, const RotT
     rotate_worklist(t, s->rot_pt, w);
     const int2* dw = nullptr;
     DPP_TRY(table_t(s, w, &dw));
-    return rotate_tasks(s->ctx, t, d, act, s->rot_pt, dw, (int)w.size());
+    return rotate_tasks(s->ctx, t, d, act, s->rot_pt, dw, (int)w.size(), s->prec);
 }
 
 // Several A^dag B contractions over every item in one launch (nbo bands).
@@ -1186,7 +1191,8 @@ extern "C" dpp_status dpp_system_create(dpp_ctx ctx, const dpp_system_desc* d, d
 extern "C" dpp_status dpp_system_destroy(dpp_system s) {
     if (!s) return DPP_OK;
     if (s->ctx) (void)hipStreamSynchronize(s->ctx->stream);
-    for (ScfGraph& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (ScfGraph& g : s->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     for (void* p : s->allocs) (void)hipFree(p);
     if (s->h_ring) (void)hipHostFree(s->h_ring);
@@ -1348,16 +1354,20 @@ extern "C" dpp_status dpp_scf_iteration(dpp_system s, dpp_c64* Yc, dpp_energy* E
     DPP_REQUIRE(s && Yc, "dpp_scf_iteration: null argument");
     double2* Y = (double2*)Yc;
     const int steps = s->scf_iter == 0 ? s->n_inner_first : s->n_inner_steps;
+    ScfGraph* g = nullptr;
     if (s->graph_on && s->scf_iter > 0) {
-        ScfGraph* g = nullptr;
         for (ScfGraph& x : s->graphs)
             if (x.Y == Y && x.steps == steps && x.prec == s->prec) g = &x;
         if (!g) {
-            ScfGraph ng{nullptr, Y, steps, s->prec};
-            DPP_TRY(capture_scf(s, Y, steps, &ng.exec));
-            s->graphs.push_back(ng);
-            g = &s->graphs.back();
+            // the first iteration with a new (block, steps, precision) runs
+            // eagerly: it builds the device tables of that precision's
+            // launches, which cannot be created while capturing
+            s->graphs.push_back(ScfGraph{nullptr, Y, steps, s->prec});
+        } else if (!g->exec) {
+            DPP_TRY(capture_scf(s, Y, steps, &g->exec));
         }
+    }
+    if (g && g->exec) {
         DPP_HIP(hipGraphLaunch(g->exec, stream(s)));
         for (int k = 0; k < s->nit; ++k) s->hc_bandk += (int64_t)s->inb[k] * (1 + steps);
     } else {
@@ -1517,10 +1527,12 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
         rep += buf;
     }
     {
+        // the launch shapes of the FP64 overlap (the split-BF16 one has a single shape)
+        s->prec = DPP_F64;
         static const char* oname[] = {"wide", "single-tile", "single-pass"};
         double best = 1e300;
         int bn = 0;
-        rep += "overlap blocks:";
+        rep += "overlap blocks (f64):";
         for (int mode : {0, 1, 2}) {
             s->ov_mode = mode;
             const double t = timeit([&] {
@@ -1533,13 +1545,15 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
         s->ov_mode = bn;
         snprintf(buf, sizeof buf, " us -> %s", oname[bn]);
         rep += buf;
+        s->prec = keep;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     s->hc_bandk = bandk;
     s->cgB_ready = false;  // the tuning runs overwrote the band-CG work blocks
     // captured graphs hold the old launch shapes
-    for (ScfGraph& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (ScfGraph& g : s->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     s->graphs.clear();
     s->tune_report = rep;
     return err;
@@ -1573,7 +1587,8 @@ extern "C" dpp_status dpp_system_set_launch_choice(dpp_system s, int which, int 
         default:
             return set_error(DPP_EINVAL, "dpp_system_set_launch_choice: unknown choice");
     }
-    for (ScfGraph& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (ScfGraph& g : s->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     s->graphs.clear();
     return DPP_OK;
 }

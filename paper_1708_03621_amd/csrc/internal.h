@@ -297,23 +297,32 @@ RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, 
 // tile block) over all points, writing the result directly (one launch).
 // rot_pt = 1, 2 or 4 fixes the point tiles per rotate wave for outputs of up
 // to 32 bands (0: by the launch size).
+// prec = DPP_F32 (the mixed-precision bulk): the overlap runs on split-BF16
+// MFMA with FP32 accumulation over 1024-point chunks and FP64 chunk sums (its
+// work list from overlap_worklist_bf16; ov_mode does not apply), the rotate on
+// FP32 MFMA with FP32 accumulation.
 dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask* d_tasks, double2* part,
-                         const int* act = nullptr, int ov_mode = 0, const int4* d_work = nullptr, int nwork = 0);
+                         const int* act = nullptr, int ov_mode = 0, const int4* d_work = nullptr, int nwork = 0,
+                         dpp_precision prec = DPP_F64);
 // The (task, chunk, block) workgroups with work of a task table in launch
 // mode ov_mode, for the work-list form of the overlap launch.
 void overlap_worklist(const std::vector<OvTask>& h, int ov_mode, std::vector<int4>& w);
+// The same for the split-BF16 overlap, ordered so that the workgroups of one
+// (task, chunk) run on one XCD (padding entries have x < 0).
+void overlap_worklist_bf16(const std::vector<OvTask>& h, std::vector<int4>& w);
 dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTask* d_tasks,
-                        const int* act = nullptr, int rot_pt = 0, const int2* d_work = nullptr, int nwork = 0);
+                        const int* act = nullptr, int rot_pt = 0, const int2* d_work = nullptr, int nwork = 0,
+                        dpp_precision prec = DPP_F64);
 // The (task, block) workgroups with points of a rotate task table for the
 // launch shape rot_pt picks, for the work-list form of the launch.
 void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2>& w);
-dpp_status overlap_f64(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
-                       const double2* B, int64_t ldB, double scale, double2* U, void* ws,
-                       size_t ws_bytes);
+dpp_status overlap_single(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
+                          const double2* B, int64_t ldB, double scale, double2* U, void* ws, size_t ws_bytes,
+                          dpp_precision prec = DPP_F64);
 size_t overlap_ws_bytes(int npw, int nbA, int nbB);
 size_t proj_ws_bytes(const dpp_basis_s* b, int nb);
-dpp_status rotate_f64(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
-                      const double2* M, double beta, double2* out, int64_t ldout);
+dpp_status rotate_single(dpp_ctx ctx, int npw, int nbX, const double2* X, int64_t ldX, int nbO,
+                         const double2* M, double beta, double2* out, int64_t ldout, dpp_precision prec = DPP_F64);
 
 // Records, for the current device, the address of the eigensolver's static
 // workspace (dpp_subspace_eigh_noalloc); called by dpp_ctx_create.

@@ -89,8 +89,8 @@ SIGNATURES = {
     "dpp_ham_destroy": [_vp],
     "dpp_ham_set_potential": [_vp, _vp],
     "dpp_apply_H": [_vp, _i, _vp, _i64, _vp, _i64, _i, _vp],
-    "dpp_overlap": [_vp, _i, _vp, _i64, _i, _vp, _i64, _d, _vp, _vp],
-    "dpp_rotate": [_vp, _i, _vp, _i64, _i, _vp, _d, _vp, _i64],
+    "dpp_overlap": [_vp, _i, _vp, _i64, _i, _vp, _i64, _d, _vp, _i, _vp],
+    "dpp_rotate": [_vp, _i, _vp, _i64, _i, _vp, _d, _vp, _i64, _i],
     "dpp_cholesky_inverse": [_vp, _i, _i, _vp, _vp],
     "dpp_cholesky_orthonormalize": [_vp, _i, _vp, _i64, _vp, _vp],
     "dpp_ortho_workspace_size": [_vp, _i, _szp],
@@ -325,12 +325,12 @@ def dpp_apply_H(ham, nb, C_, ldC, HC, ldHC, prec, ws):
 
 # --------------------------------------------------------- contractions ----
 
-def dpp_overlap(basis, nbA, A, ldA, nbB, B, ldB, scale, U, ws):
-    _call("dpp_overlap", basis, nbA, _ptr(A), ldA, nbB, _ptr(B), ldB, float(scale), _ptr(U), _ptr(ws))
+def dpp_overlap(basis, nbA, A, ldA, nbB, B, ldB, scale, U, ws, prec=DPP_F64):
+    _call("dpp_overlap", basis, nbA, _ptr(A), ldA, nbB, _ptr(B), ldB, float(scale), _ptr(U), prec, _ptr(ws))
 
 
-def dpp_rotate(basis, nbX, X, ldX, nbO, M, beta, out, ldout):
-    _call("dpp_rotate", basis, nbX, _ptr(X), ldX, nbO, _ptr(M), float(beta), _ptr(out), ldout)
+def dpp_rotate(basis, nbX, X, ldX, nbO, M, beta, out, ldout, prec=DPP_F64):
+    _call("dpp_rotate", basis, nbX, _ptr(X), ldX, nbO, _ptr(M), float(beta), _ptr(out), ldout, prec)
 
 
 def dpp_cholesky_inverse(ctx, nb, batch, U, Rinv):

@@ -1,6 +1,7 @@
 """Write config3_scf2.txt: two FP64 SCF iterations (protocol S) of config 3
 (64-atom displaced diamond supercell, 90^3 box, 128 bands, Gamma) computed by
-the oracle alone, for the GPU parity test of the 128-band path.
+the oracle alone, for the GPU parity tests of the 128-band path: energies,
+eigenvalues, and the output density at 2048 seeded grid points.
 
 Usage (from the repository root): python tests/golden/make_config3_scf.py
 Takes a few minutes on one core.
@@ -18,6 +19,12 @@ import workloads as W  # noqa: E402
 from oracle import energy as oe, scf as oscf  # noqa: E402
 
 NIT = 2
+NSAMPLE = 2048
+SAMPLE_SEED = 3031
+
+
+def sample_indices(size):
+    return np.sort(np.random.default_rng(SAMPLE_SEED).choice(size, NSAMPLE, replace=False))
 
 
 def main():
@@ -38,6 +45,10 @@ def main():
         for i, e in enumerate(res["eigs"][0]):
             f.write(f"eig {i} {e:.15e}\n")
         f.write(f"n_out_abs_sum {float(np.sum(np.abs(res['n_out']))):.15e}\n")
+        # the output density at NSAMPLE seeded grid points (flat row-major index)
+        n = np.asarray(res["n_out"]).reshape(-1)
+        for j in sample_indices(n.size):
+            f.write(f"n_out {j} {n[j]:.15e}\n")
     print("wrote", out, f"{dt:.0f} s")
 
 

@@ -10,8 +10,10 @@ These tests run band CG (protocol B) and SCF (protocol S) through them:
   * a batch that mixes a 16-band cell with a 40-band one (every item then
     takes the register-tile path);
   * two SCF iterations of config 3 itself (64 atoms, 90^3, 128 bands) against
-    oracle values stored by tests/golden/make_config3_scf.py.
-Bars: 1e-8 Ha per atom on energies (FP64), 1e-7 Ha on eigenvalues.
+    oracle values stored by tests/golden/make_config3_scf.py, in FP64 and with
+    the mixed-precision bulk.
+Bars: 1e-8 Ha per atom on energies (FP64), 1e-7 Ha on eigenvalues; mixed:
+1e-6 Ha per atom, 1e-5 Ha, 1e-5 relative L1 on the density.
 """
 import os
 
@@ -123,7 +125,7 @@ def test_batch_mixing_16_and_40_bands(dev):
 
 
 def _golden():
-    E, eig, nsum = {}, {}, None
+    E, eig, nsum, ns = {}, {}, None, {}
     for line in open(GOLDEN):
         if line.startswith("#") or not line.strip():
             continue
@@ -134,25 +136,59 @@ def _golden():
             eig[int(v[0])] = float(v[1])
         elif k == "n_out_abs_sum":
             nsum = float(v[0])
-    return [E[i] for i in sorted(E)], np.array([eig[i] for i in sorted(eig)]), nsum
+        elif k == "n_out":
+            ns[int(v[0])] = float(v[1])
+    idx = np.array(sorted(ns))
+    return ([E[i] for i in sorted(E)], np.array([eig[i] for i in sorted(eig)]), nsum, idx,
+            np.array([ns[i] for i in idx]))
+
+
+def _config3_run(dev, prec):
+    cell = W.config3()
+    sysg, off, npw = make_gpu_system(dev, cell, prec=prec)
+    Y, _ = packed_Y(dev, cell, npw)
+    dev.D.dpp_scf_init(sysg, cell.tau, cell.Z, W.START_SIGMA)
+    Eg = []
+    for _ in range(2):
+        E, e = dev.D.dpp_scf_iteration(sysg, Y, 1, cell.nb)
+        Eg.append(E["E_el"])
+    nout = dev.field(sysg, dev.D.DPP_FIELD_NOUT, cell.S)
+    dev.D.dpp_system_destroy(sysg)
+    return cell, np.array(Eg), e[0], nout
 
 
 def test_config3_scf_two_iterations(dev):
     """Config 3 (64 atoms, 23847 plane waves, 90^3, 128 bands): two FP64 SCF
-    iterations from the seeded start against the oracle's."""
+    iterations from the seeded start against the oracle's: energies,
+    eigenvalues, and the output density at 2048 seeded grid points."""
     log("config 3 SCF x2")
-    Eo, eo, nsum = _golden()
-    cell = W.config3()
-    sysg, off, npw = make_gpu_system(dev, cell)
-    Y, _ = packed_Y(dev, cell, npw)
-    dev.D.dpp_scf_init(sysg, cell.tau, cell.Z, W.START_SIGMA)
-    Eg = []
-    for _ in range(len(Eo)):
-        E, e = dev.D.dpp_scf_iteration(sysg, Y, 1, cell.nb)
-        Eg.append(E["E_el"])
-    nout = dev.field(sysg, dev.D.DPP_FIELD_NOUT, cell.S)
-    log(f"gpu {Eg} oracle {Eo}")
-    assert np.max(np.abs(np.array(Eg) - np.array(Eo))) / cell.nat < TOL_ATOM
-    assert np.max(np.abs(e[0] - eo)) < TOL_EIG
+    Eo, eo, nsum, idx, no = _golden()
+    cell, Eg, e, nout = _config3_run(dev, dev.D.DPP_F64)
+    log(f"gpu {list(Eg)} oracle {Eo}")
+    assert np.max(np.abs(Eg - np.array(Eo))) / cell.nat < TOL_ATOM
+    assert np.max(np.abs(e - eo)) < TOL_EIG
     assert abs(np.sum(np.abs(nout)) - nsum) / nsum < 1e-10
-    dev.D.dpp_system_destroy(sysg)
+    ns = nout.reshape(-1)[idx]
+    log(f"sampled density max rel err {np.max(np.abs(ns - no)) / np.max(np.abs(no)):.2e}")
+    assert np.max(np.abs(ns - no)) < 1e-9 * np.max(np.abs(no))
+
+
+def test_config3_scf_mixed_two_iterations(dev):
+    """The same two iterations with the mixed-precision bulk (FP32 FFT passes,
+    potential multiply and density transforms; split-BF16 overlaps and FP32
+    X M contractions on MFMA; FP64 Cholesky, eigensolver and energies) against
+    the FP64 oracle at the mixed-precision bars: 1e-6 Ha/atom on energies,
+    1e-5 Ha on eigenvalues, 1e-5 relative L1 on the output density (over the
+    2048 sampled points).  The band residual stays far above 1e-4 in two
+    iterations, so no FP64 refinement takes part."""
+    log("config 3 mixed SCF x2")
+    Eo, eo, nsum, idx, no = _golden()
+    cell, Eg, e, nout = _config3_run(dev, dev.D.DPP_F32)
+    dE = np.max(np.abs(Eg - np.array(Eo))) / cell.nat
+    de = np.max(np.abs(e - eo))
+    ns = nout.reshape(-1)[idx]
+    l1 = np.sum(np.abs(ns - no)) / np.sum(np.abs(no))
+    log(f"mixed: dE/atom {dE:.2e}, eig {de:.2e}, density rel L1 {l1:.2e}")
+    assert dE < 1e-6
+    assert de < 1e-5
+    assert l1 < 1e-5

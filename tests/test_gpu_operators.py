@@ -190,6 +190,75 @@ def test_rotate(dev, nbX, nbO, beta):
     assert rel_err(dev.host(out), ref) < 1e-12
 
 
+# Mixed-precision contractions (DPP_F32).  A^dag B on split-BF16 MFMA: every
+# real input x is rounded to FP32 and split into hi + lo (BF16 each), with
+# hi + lo = x (1 + d), |d| <= 2^-16 + 2^-24, d uniform in sign at about half
+# that size; all four split products are exact in FP32, so one real product
+# carries d_a + d_b, about 2^-17 rms.  The per-element statistical scale is
+# therefore sigma_ij = 2^-17 sqrt(sum_g |a_g|^2 |b_g|^2); a correct kernel stays
+# well inside 8 sigma over a whole matrix, while plain BF16 (no lo parts) is
+# ~2^8 times larger and dropping the lo lo' product biases the Gram diagonal by
+# ~2^-18/3 of sum |a|^2 (> 8 sigma at these sizes).
+def _split_sigma(A, B):
+    return 2.0 ** -17 * np.sqrt((np.abs(A) ** 2) @ (np.abs(B) ** 2).T)
+
+
+@pytest.mark.parametrize("which,nbA,nbB", [("cfg1", 5, 3), ("cfg2", 16, 16), ("cfg2", 33, 20),
+                                           ("cfg3", 128, 128), ("cfg3", 64, 128), ("cfg3", 1, 1)])
+@pytest.mark.parametrize("gram", [False, True])
+def test_overlap_split_bf16(dev, which, nbA, nbB, gram):
+    log(f"overlap f32 {which} {nbA}x{nbB} gram={gram}")
+    cell = {"cfg1": W.config1, "cfg2": W.config2, "cfg3": W.config3}[which]()
+    g = dev.grid(cell.R, cell.S)
+    b = dev.basis(g, cell.kpts[-1], cell.ecut)
+    npw, _ = dev.D.dpp_basis_info(b)
+    rng = np.random.default_rng(nbA * 131 + nbB + (7 if gram else 0))
+    ld = npw + 3  # ragged leading dimension
+    A = rng.standard_normal((nbA, ld)) + 1j * rng.standard_normal((nbA, ld))
+    B = A[:nbB] if gram else rng.standard_normal((nbB, ld)) + 1j * rng.standard_normal((nbB, ld))
+    if gram:
+        nbB = min(nbA, nbB)
+    U = dev.empty((nbA, nbB), dev.torch.complex128)
+    ws = dev.ws(2 ** 26)
+    dev.D.dpp_overlap(b, nbA, dev.tensor(A), ld, nbB, dev.tensor(B[:nbB]), ld, 2.5, U, ws, dev.D.DPP_F32)
+    a, bb = A[:, :npw], B[:nbB, :npw]
+    ref = 2.5 * a.conj() @ bb.T
+    err = np.abs(dev.host(U) - ref) / (2.5 * _split_sigma(a, bb))
+    log(f"max |err|/sigma = {err.max():.2f}")
+    assert err.max() < 8.0
+
+
+def _f32_bound(X, M, K):
+    """Worst-case error of X M with X and M rounded to FP32 and an FP32 sum of
+    K complex terms (2K real products per component): (2K + 4) 2^-24 times
+    sum_k (|Re M|+|Im M|)(|Re X|+|Im X|)."""
+    m1 = np.abs(M.real) + np.abs(M.imag)
+    x1 = np.abs(X.real) + np.abs(X.imag)
+    return (2 * K + 4) * 2.0 ** -24 * (x1.T @ m1).T
+
+
+@pytest.mark.parametrize("nbX,nbO", [(1, 1), (5, 3), (16, 16), (64, 128), (128, 128), (128, 130)])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_rotate_f32(dev, nbX, nbO, beta):
+    log(f"rotate f32 {nbX}->{nbO} beta={beta}")
+    g = dev.grid(np.eye(3) * 10.26, (40, 40, 40))
+    b = dev.basis(g, np.array([0.5, 0.5, 0.5]), 12.0)
+    npw, _ = dev.D.dpp_basis_info(b)
+    rng = np.random.default_rng(3 * nbX + 11 * nbO)
+    X = rng.standard_normal((nbX, npw)) + 1j * rng.standard_normal((nbX, npw))
+    M = rng.standard_normal((nbX, nbO)) + 1j * rng.standard_normal((nbX, nbO))
+    O0 = rng.standard_normal((nbO, npw)) + 1j * rng.standard_normal((nbO, npw))
+    out = dev.tensor(O0)
+    dev.D.dpp_rotate(b, nbX, dev.tensor(X), npw, nbO, dev.tensor(M), beta, out, npw, dev.D.DPP_F32)
+    ref = (X.T @ M).T + beta * O0
+    bound = _f32_bound(X, M, nbX) + 1e-15 * np.abs(ref)
+    err = np.abs(dev.host(out) - ref)
+    log(f"max err/bound = {(err / bound).max():.3e}")
+    assert np.all(err <= bound)
+    # and well above BF16-level accuracy: the typical error is at FP32 rounding
+    assert np.sqrt(np.mean(err ** 2)) < 1e-5 * np.sqrt(np.mean(np.abs(ref) ** 2))
+
+
 @pytest.mark.parametrize("nb", [1, 4, 16, 33, 64, 65, 100, 128])
 def test_cholesky_orthonormalize(dev, nb):
     log(f"cholesky nb={nb}")
