@@ -24,7 +24,7 @@ HBM-bound kernel and of the MFMA contractions, and the same timings for the
 8-atom cell with 8 k-points and for the 48-cell batch are reported beside it.
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload config3|config2|config4]
-       python bench.py --pmc-probe {apply_H,copy} [--workload ...]   (a short
+       python bench.py --pmc-probe {apply_H,copy} [--workload ...] [--pmc-prec f64|mixed]   (a short
        loop for rocprofv3 counter collection: the system's H application, or
        a 256 MiB device copy that calibrates FETCH_SIZE / WRITE_SIZE)
 """
@@ -338,8 +338,9 @@ def roofline_mixed_contractions(kern):
     return out
 
 
-def pmc_probe(kind, workload):
-    """A short loop for counter collection under rocprofv3 --pmc."""
+def pmc_probe(kind, workload, prec="f64"):
+    """A short loop for counter collection under rocprofv3 --pmc: one SCF
+    iteration and three H applications of the FP64 or the mixed system."""
     import torch
     if kind == "copy":
         n = 256 << 20
@@ -356,7 +357,7 @@ def pmc_probe(kind, workload):
     ctx = D.dpp_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     cells = cells_for(workload)
 
-    sys_, Y = make_system(D, W, ctx, cells, D.DPP_F64, False, dev)
+    sys_, Y = make_system(D, W, ctx, cells, D.DPP_F64 if prec == "f64" else D.DPP_F32, False, dev)
     scratch = torch.empty_like(Y)
     D.dpp_system_tune(sys_, Y, scratch, 2)
     D.dpp_scf_init(sys_, cells=[dict(tau=c.tau, Z=c.Z.astype(float), sigma=W.START_SIGMA) for c in cells])
@@ -364,7 +365,8 @@ def pmc_probe(kind, workload):
     for _ in range(3):
         D.dpp_system_apply_H(sys_, Y, scratch)
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_probe": "apply_H", "workload": workload, "tuning": D.dpp_system_tune_report(sys_)}))
+    print(json.dumps({"pmc_probe": "apply_H", "workload": workload, "prec": prec,
+                      "tuning": D.dpp_system_tune_report(sys_)}))
     D.dpp_system_destroy(sys_)
 
 
@@ -382,6 +384,7 @@ def main():
     ap.add_argument("--eager", action="store_true", help="launch every kernel from the host (no graph replay)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (default launch rules)")
     ap.add_argument("--pmc-probe", choices=["apply_H", "copy"], help="run a short loop for counter collection")
+    ap.add_argument("--pmc-prec", choices=["f64", "mixed"], default="f64", help="system precision of the probe")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built: "
@@ -389,7 +392,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.pmc_probe:
-        pmc_probe(args.pmc_probe, args.workload)
+        pmc_probe(args.pmc_probe, args.workload, args.pmc_prec)
         return
 
     cpu = None

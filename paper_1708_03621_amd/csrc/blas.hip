@@ -730,16 +730,18 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
 // accumulation over the bands, the result (and beta out) in FP64.
 template <int PT, int JT, bool F32>
 __global__ void __launch_bounds__(64 * RT_WAVES)
-k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0, const int* __restrict__ act,
+k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0_in, int ngrp, const int* __restrict__ act,
               const int2* __restrict__ work) {
     using acc_t = typename std::conditional<F32, f4, d4>::type;
     using real_t = typename std::conditional<F32, float, double>::type;
-    // a work list (task, block) covers only the workgroups with points
+    // a work list (task, block) covers only the workgroups with points; a
+    // block is (point block, group of JT output tiles) when ngrp > 1
     const int2 wk = work ? work[blockIdx.x] : int2{(int)blockIdx.y, (int)blockIdx.x};
     const RotTask T = tasks ? tasks[wk.x] : single;
     if (act && !act[T.item]) return;
+    const int jt0 = jt0_in + (wk.y % ngrp) * JT;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int gt = (wk.y * RT_WAVES + w) * PT;
+    const int gt = ((wk.y / ngrp) * RT_WAVES + w) * PT;
     if (gt * 16 >= T.npw) return;
     const int njt = min(JT, (T.nbO + 15) / 16 - jt0);
     if (njt <= 0) return;
@@ -850,15 +852,23 @@ static double rot_bytes(const RotTask& t) {
 
 template <int PT, int JT>
 static void rotate_go(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single, unsigned ntasks, int ntile,
-                      int jt0, const int* act, const int2* work, int nwork, bool f32) {
+                      int jt0, const int* act, const int2* work, int nwork, bool f32, int ngrp = 1) {
     const int nblk = (ntile + RT_WAVES * PT - 1) / (RT_WAVES * PT);
-    const dim3 grid = work ? dim3((unsigned)nwork) : dim3(nblk, ntasks);
+    const dim3 grid = work ? dim3((unsigned)nwork) : dim3(nblk * ngrp, ntasks);
     if (f32)
         hipLaunchKernelGGL((k_rotate_mfma<PT, JT, true>), grid, dim3(64 * RT_WAVES), 0, ctx->stream, d_tasks, single,
-                           jt0, act, work);
+                           jt0, ngrp, act, work);
     else
         hipLaunchKernelGGL((k_rotate_mfma<PT, JT, false>), grid, dim3(64 * RT_WAVES), 0, ctx->stream, d_tasks,
-                           single, jt0, act, work);
+                           single, jt0, ngrp, act, work);
+}
+
+// FP32 outputs of more than two 16-band tiles: groups of RT_JT32 tiles per
+// wave, all groups in one launch (twice the waves of the FP64 shape, so the
+// loads of more waves are in flight).
+constexpr int RT_JT32 = 4;
+static int rotate_groups(int jtiles, bool f32) {
+    return (f32 && jtiles > 2) ? (jtiles + RT_JT32 - 1) / RT_JT32 : 1;
 }
 
 // Launch the rotate kernel shape for the widest output of a batch; tiles =
@@ -891,9 +901,12 @@ static dpp_status rotate_launch(dpp_ctx ctx, const RotTask* d_tasks, const RotTa
             rotate_go<2, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
         else
             rotate_go<1, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
+    } else if (f32) {
+        rotate_go<1, RT_JT32>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, true,
+                              rotate_groups(jtiles, true));
     } else {
         for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT)
-            rotate_go<1, RT_JT>(ctx, d_tasks, single, ntasks, ntile, jt0, act, work, nwork, f32);
+            rotate_go<1, RT_JT>(ctx, d_tasks, single, ntasks, ntile, jt0, act, work, nwork, false);
     }
     DPP_LAUNCHED();
     return DPP_OK;
@@ -908,15 +921,16 @@ static void rotate_shape(const std::vector<RotTask>& h, int& mp, int& mj, int64_
     }
 }
 
-void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2>& w) {
+void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2>& w, bool f32) {
     int mp, mj;
     int64_t tiles;
     rotate_shape(h, mp, mj, tiles);
     const int pt = rotate_pt_rule(mj, tiles, rot_pt);
+    const int ng = rotate_groups(mj, f32);
     w.clear();
     for (size_t i = 0; i < h.size(); ++i) {
         const int nblk = ((h[i].npw + 15) / 16 + RT_WAVES * pt - 1) / (RT_WAVES * pt);
-        for (int b = 0; b < nblk; ++b) w.push_back(int2{(int)i, b});
+        for (int b = 0; b < nblk * ng; ++b) w.push_back(int2{(int)i, b});
     }
 }
 

@@ -311,7 +311,7 @@ dpp_status overlap_run(dpp_system_s* s, const std::vector<OvTask>& t, const OvTa
 
 dpp_status rotate_run(dpp_system_s* s, const std::vector<RotTask>& t, const RotTask* d, const int* act) {
     std::vector<int2> w;
-    rotate_worklist(t, s->rot_pt, w);
+    rotate_worklist(t, s->rot_pt, w, s->prec == DPP_F32);
     const int2* dw = nullptr;
     DPP_TRY(table_t(s, w, &dw));
     return rotate_tasks(s->ctx, t, d, act, s->rot_pt, dw, (int)w.size(), s->prec);

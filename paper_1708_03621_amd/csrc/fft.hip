@@ -462,6 +462,53 @@ k_xz_reg(const FftItem* __restrict__ items, const int* __restrict__ idx, typenam
     }
 }
 
+// v, hidden from the optimizer (addresses derived from it are computed where
+// they are used instead of being kept live from earlier uses).
+__device__ __forceinline__ int xz_opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Half-lengths whose register transforms run one butterfly at a time.
+constexpr bool XZ2_SER(int m) { return m > 32; }
+// Points per group of potential loads.
+constexpr int XZ2_VG = 9;
+
+// Buffer resources (raw, stride 0): word 3 of the descriptor for gfx9-family
+// devices, and an offset beyond any buffer here (loads there return 0,
+// stores there are dropped).
+constexpr int XZ2_RSRC_WORD3 = 0x00020000;
+constexpr unsigned XZ2_OUT_OF_RANGE = 0x80000000u;
+
+template <typename C>
+__device__ __forceinline__ C xz_buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double2 xz_buf_load<double2>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const dv2 v = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return double2{v.x, v.y};
+}
+template <>
+__device__ __forceinline__ float2 xz_buf_load<float2>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef float fv2 __attribute__((ext_vector_type(2)));
+    const fv2 v = __builtin_bit_cast(fv2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return float2{v.x, v.y};
+}
+template <typename C>
+__device__ __forceinline__ void xz_buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, C v);
+template <>
+__device__ __forceinline__ void xz_buf_store<double2>(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, dv2{v.x, v.y}), r, off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void xz_buf_store<float2>(__amdgpu_buffer_rsrc_t r, unsigned off, float2 v) {
+    typedef float fv2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, fv2{v.x, v.y}), r, off, 0, 0);
+}
+
 // Value of the other lane of an adjacent pair (lane ^ 1) by a DPP quad
 // permutation [1, 0, 3, 2].
 __device__ __forceinline__ float pair_swap(float v) {
@@ -482,7 +529,11 @@ __device__ __forceinline__ double pair_swap(double v) {
 // inverse ends with the matching step, out[j + h M] = z_0[j] + (-1)^h
 // w^{-j} z_1[j].  Everything between stays in the thread's registers.
 template <typename T, int S0>
-__global__ void __launch_bounds__(256)
+// Two waves per SIMD: the FP64 90-point form needs 266 registers without the
+// hint (one wave per SIMD) and 256 plus a 24-byte spill with it, which runs
+// faster (386 vs 517 us per config-3 H); every other length fits two waves
+// without it.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_xz_reg2(const FftItem* __restrict__ items, const int* __restrict__ idx, typename cx<T>::t* __restrict__ Tb,
           const double* __restrict__ V, const int* __restrict__ act) {
     using Cx = typename cx<T>::t;
@@ -497,14 +548,22 @@ k_xz_reg2(const FftItem* __restrict__ items, const int* __restrict__ idx, typena
     const int h = threadIdx.x & 1;
     if (col >= np) return;  // both lanes of a pair leave together
     const int nP = it.nplanes;
-    Cx* base = Tb + it.t_off + (int64_t)b * nP * np + col;
+    // this band's planes as a buffer: points on planes the sphere does not
+    // touch get an offset past the end, where the hardware range check makes
+    // loads return 0 and drops stores (no branch per point)
+    const auto planes = __builtin_amdgcn_make_buffer_rsrc(Tb + it.t_off + (int64_t)b * nP * np, (short)0,
+                                                          (int)(nP * np * (int)sizeof(Cx)), XZ2_RSRC_WORD3);
+    // plane of point j + h M: d = (j + h M - n0min) mod S0, stepped from d0
+    int d0 = (h * M - it.n0min) % S0;
+    d0 += d0 < 0 ? S0 : 0;
+    auto plane_off = [&](int j, int dstart, int c) -> unsigned {
+        int d = dstart + j;
+        d -= d >= S0 ? S0 : 0;
+        return d < nP ? (unsigned)((c + d * np) * (int)sizeof(Cx)) : XZ2_OUT_OF_RANGE;
+    };
     Cx x[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        int d = (j + h * M - it.n0min) % S0;
-        d += d < 0 ? S0 : 0;
-        x[j] = d < nP ? base[(int64_t)d * np] : Cx{0, 0};
-    }
+    for (int j = 0; j < M; ++j) x[j] = xz_buf_load<Cx>(planes, plane_off(j, d0, col));
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const Cx o = Cx{pair_swap(x[j].x), pair_swap(x[j].y)};
@@ -515,33 +574,41 @@ k_xz_reg2(const FftItem* __restrict__ items, const int* __restrict__ idx, typena
             x[j] = j == 0 ? dlt : cmul(dlt, reg_twiddle<T, S0>(j, +1));
         }
     }
-    reg_dif<T, M, +1, 0>(x, nullptr, nullptr);
+    reg_dif<T, M, +1, 0, XZ2_SER(M)>(x, nullptr, nullptr);
     int vcol = col;
     if (it.vperm && it.perm) {
         const int p1 = col / it.S2, p2 = col - p1 * it.S2;
         vcol = digit_rev_axis(it.ax[1], p1) * it.S2 + digit_rev_axis(it.ax[2], p2);
     }
-    const double* Vp = V + it.v_off + vcol + (int64_t)h * np;
+    // V of the item's box as a buffer (32-bit offsets from a uniform base)
+    const auto vbuf = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(V + it.v_off), (short)0,
+                                                        (int)(S0 * np * (int)sizeof(double)), XZ2_RSRC_WORD3);
+    const int vbase = vcol + h * np;
     const T sc = (T)(it.vperm ? it.vscale : 1.0);
+    // in groups of XZ2_VG points, so that not every load is in flight at once
 #pragma unroll
-    for (int p = 0; p < M; ++p) {
-        const int k = 2 * reg_digit_rev(M, p);
-        const T v = (T)Vp[(int64_t)k * np] * sc;
-        x[p] = Cx{x[p].x * v, x[p].y * v};
+    for (int p0 = 0; p0 < M; p0 += XZ2_VG) {
+#pragma unroll
+        for (int p = p0; p < (p0 + XZ2_VG < M ? p0 + XZ2_VG : M); ++p) {
+            const int k = 2 * reg_digit_rev(M, p);
+            const T v = (T)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                          vbuf, (unsigned)((vbase + k * np) * 8), 0, 0)) *
+                        sc;
+            x[p] = Cx{x[p].x * v, x[p].y * v};
+        }
+        if constexpr (M > XZ2_VG) __builtin_amdgcn_sched_barrier(0);
     }
-    reg_dit<T, M, -1, 0>(x, nullptr, nullptr);
+    reg_dit<T, M, -1, 0, XZ2_SER(M)>(x, nullptr, nullptr);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const Cx t = (h == 0 || j == 0) ? x[j] : cmul(x[j], reg_twiddle<T, S0>(j, -1));
         const Cx o = Cx{pair_swap(t.x), pair_swap(t.y)};
         x[j] = h == 0 ? Cx{t.x + o.x, t.y + o.y} : Cx{o.x - t.x, o.y - t.y};
     }
+    // offsets recomputed here (from opaque values), not kept live since the loads
+    const int d0s = xz_opaque(d0), cols = xz_opaque(col);
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        int d = (j + h * M - it.n0min) % S0;
-        d += d < 0 ? S0 : 0;
-        if (d < nP) base[(int64_t)d * np] = x[j];
-    }
+    for (int j = 0; j < M; ++j) xz_buf_store<Cx>(planes, plane_off(j, d0s, cols), x[j]);
 }
 
 template <typename T, int N>
@@ -551,11 +618,10 @@ static void xz_reg2_one(dim3 grid, hipStream_t st, const FftItem* items, const i
     hipLaunchKernelGGL((k_xz_reg2<T, N>), grid, dim3(256), 0, st, items, idx, Tb, V, act);
 }
 
-// Register x pass lengths: FP64 up to 45 and FP32 up to 64 points keep every
-// column in registers without scratch spills on gfx950.
-// One thread per column needs FP64 lengths up to 45 (FP32: 64); the lane-pair
-// split takes even lengths.  XZ_AUTO: the split from 24 (FP64, up to 45) or
-// 36 (FP32) points, where one thread per column runs at low occupancy.
+// Register x pass lengths: one thread per column needs FP64 lengths up to 45
+// (FP32: 64); the lane-pair split takes even lengths (up to 90).  XZ_AUTO:
+// the split from 24 (FP64) or 36 (FP32) points, where one thread per column
+// runs at low occupancy.
 template <typename T, int N>
 constexpr bool xz_has(int v) {
     const bool reg1 = !(sizeof(T) == 8 && N > 45);
@@ -564,7 +630,7 @@ constexpr bool xz_has(int v) {
 }
 template <typename T, int N>
 constexpr int xz_auto() {
-    if (N % 2 == 0 && N >= (sizeof(T) == 8 ? 24 : 36) && !(sizeof(T) == 8 && N > 45)) return XZ_REG2;
+    if (N % 2 == 0 && N >= (sizeof(T) == 8 ? 24 : 36)) return XZ_REG2;
     return xz_has<T, N>(XZ_REG1) ? XZ_REG1 : XZ_LDS;
 }
 

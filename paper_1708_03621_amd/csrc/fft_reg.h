@@ -141,7 +141,17 @@ __device__ __forceinline__ typename cx<T>::t reg_twiddle(int m, int sign) {
     return C{(T)re, (T)(sign > 0 ? -im : im)};
 }
 
-template <typename T, int N, int SIGN, int STAGE>
+// SER: the butterflies run one after another: each one's inputs and outputs
+// pass through an empty volatile asm (a data dependency the compiler keeps in
+// order), so the butterflies of a stage are not interleaved (for long
+// transforms, whose interleaved temporaries would not fit the register file
+// next to the column).
+template <typename C>
+__device__ __forceinline__ void reg_pin(C& v) {
+    asm volatile("" : "+v"(v.x), "+v"(v.y));
+}
+
+template <typename T, int N, int SIGN, int STAGE, bool SER = false>
 __device__ __forceinline__ void reg_dif(typename cx<T>::t* x, const double2* tw64, const float2* tw32) {
     using C = typename cx<T>::t;
     if constexpr (STAGE < reg_num_radices(N)) {
@@ -154,24 +164,28 @@ __device__ __forceinline__ void reg_dif(typename cx<T>::t* x, const double2* tw6
             for (int j = 0; j < S; ++j) {
                 C v[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[r] = x[base + j + r * S];
+                for (int r = 0; r < R; ++r) {
+                    v[r] = x[base + j + r * S];
+                    if constexpr (SER) reg_pin(v[r]);
+                }
                 Dft<T, R>::run(v, SIGN);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int m = ((N / n) * r * j) % N;
                     x[base + j + r * S] = m == 0 ? v[r] : cmul(v[r], reg_twiddle<T, N>(m, SIGN));
+                    if constexpr (SER) reg_pin(x[base + j + r * S]);
                 }
             }
         }
-        reg_dif<T, N, SIGN, STAGE + 1>(x, tw64, tw32);
+        reg_dif<T, N, SIGN, STAGE + 1, SER>(x, tw64, tw32);
     }
 }
 
-template <typename T, int N, int SIGN, int STAGE>
+template <typename T, int N, int SIGN, int STAGE, bool SER = false>
 __device__ __forceinline__ void reg_dit(typename cx<T>::t* x, const double2* tw64, const float2* tw32) {
     using C = typename cx<T>::t;
     if constexpr (STAGE < reg_num_radices(N)) {
-        reg_dit<T, N, SIGN, STAGE + 1>(x, tw64, tw32);
+        reg_dit<T, N, SIGN, STAGE + 1, SER>(x, tw64, tw32);
         constexpr int R = reg_radix(N, STAGE);
         constexpr int n = reg_block(N, STAGE);
         constexpr int S = n / R;
@@ -183,12 +197,16 @@ __device__ __forceinline__ void reg_dit(typename cx<T>::t* x, const double2* tw6
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int m = ((N / n) * r * j) % N;
-                    const C a = x[base + j + r * S];
+                    C a = x[base + j + r * S];
+                    if constexpr (SER) reg_pin(a);
                     v[r] = m == 0 ? a : cmul(a, reg_twiddle<T, N>(m, SIGN));
                 }
                 Dft<T, R>::run(v, SIGN);
 #pragma unroll
-                for (int r = 0; r < R; ++r) x[base + j + r * S] = v[r];
+                for (int r = 0; r < R; ++r) {
+                    x[base + j + r * S] = v[r];
+                    if constexpr (SER) reg_pin(x[base + j + r * S]);
+                }
             }
         }
     }

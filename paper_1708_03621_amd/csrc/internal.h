@@ -315,7 +315,7 @@ dpp_status rotate_tasks(dpp_ctx ctx, const std::vector<RotTask>& h, const RotTas
                         dpp_precision prec = DPP_F64);
 // The (task, block) workgroups with points of a rotate task table for the
 // launch shape rot_pt picks, for the work-list form of the launch.
-void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2>& w);
+void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2>& w, bool f32 = false);
 dpp_status overlap_single(dpp_ctx ctx, int npw, int nbA, const double2* A, int64_t ldA, int nbB,
                           const double2* B, int64_t ldB, double scale, double2* U, void* ws, size_t ws_bytes,
                           dpp_precision prec = DPP_F64);
