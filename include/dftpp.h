@@ -416,6 +416,24 @@ dpp_status dpp_scf_cell_residuals(dpp_system sys, double *res);
 /* Fillings of the last SCF iteration (host, nstates). */
 dpp_status dpp_system_fillings(dpp_system sys, double *f);
 
+/* Forces on the ions of every cell (Table 1: ionic optimization; Sec. 3:
+ * the ionic minimization of the example), in hartree/bohr, at the state the
+ * last dpp_scf_iteration left: Y its orthonormal wavefunctions (the packed
+ * block it updated), its fillings and its output density n_out.
+ *   F_loc  -dE_loc/dtau at fixed n_out (local pseudopotential),
+ *   F_nl   -dE_nl/dtau at fixed psi and fillings (projectors),
+ *   F_ion  -dE_ion/dtau of the point ions in a compensating background
+ *          (Ewald sums),
+ * each a device array of 3 doubles per atom (cell-major, then atom, then
+ * x, y, z), any may be NULL; at a self-consistent state their sum is the
+ * force -dE/dtau of E = E_el + E_ion.  E_ion (host, one per cell, may be
+ * NULL) receives the ionic energy.  FP64 throughout.  Stream-ordered; with
+ * E_ion it synchronizes the stream.  Not capturable (first call allocates
+ * the derivative projectors: 3 nproj npw complex per item).  Errors:
+ * DPP_EINVAL before the first SCF iteration or while capturing. */
+dpp_status dpp_system_forces(dpp_system sys, const dpp_c64 *Y, double *F_loc, double *F_nl, double *F_ion,
+                             double *E_ion);
+
 /* ------------------------------------------------ learned start density -- */
 
 /* A periodic 3D convolutional network that corrects the superposition start

@@ -52,6 +52,23 @@ struct CellHost {
     double ne, D;
     int item0;
     int64_t foff, N;
+    std::vector<double> tau, Z, rc;  // atoms (tau Cartesian, 3 per atom)
+    std::vector<int> has_proj;
+};
+
+// Buffers of dpp_system_forces, allocated on its first call.
+struct ForceBufs {
+    bool ready = false;
+    double *tau = nullptr, *sfrac = nullptr, *Z = nullptr, *rc = nullptr;  // every atom, cell-major
+    double2* Q = nullptr;      // derivative projectors: per item 3 x nproj x npw
+    double2* Pid = nullptr;    // their overlaps with psi: per item 3 x nproj x nb
+    double* part = nullptr;    // local-force chunk partials / Ewald partials
+    double* nlpart = nullptr;  // per item nproj x 3
+    double* E = nullptr;       // Ewald lattice sums per cell
+    std::vector<int64_t> qoff, nloff, aoff;
+    std::vector<int> proj_atom;  // per cell-major projector: the atom it sits on (within its cell)
+    std::vector<int> proj0;      // per cell: first projector index
+    int64_t natall = 0;
 };
 
 // Item table for a band count override (0: every item's own count) with the
@@ -143,6 +160,7 @@ struct dpp_system_s {
     int ring_slot = 0, ring_slots = 64;
     size_t ring_len = 256;
     std::vector<void*> allocs;
+    ForceBufs fb;
 };
 
 namespace {
@@ -994,6 +1012,10 @@ extern "C" dpp_status dpp_batch_create(dpp_ctx ctx, int ncells, const dpp_system
         ch.nat = d->nat;
         ch.ne = d->n_electrons;
         ch.D = d->D;
+        ch.tau.assign(d->tau, d->tau + 3 * d->nat);
+        ch.Z.assign(d->Z, d->Z + d->nat);
+        ch.rc.assign(d->rc, d->rc + d->nat);
+        ch.has_proj.assign(d->has_proj, d->has_proj + d->nat);
         ch.item0 = (int)s->bases.size();
         ch.foff = s->Ntot;
         ch.N = ch.grid->N;
@@ -1604,6 +1626,196 @@ extern "C" dpp_status dpp_system_apply_H(dpp_system s, const dpp_c64* Y, dpp_c64
     clear_error();
     DPP_REQUIRE(s && Y && HY && (const void*)Y != (const void*)HY, "dpp_system_apply_H: bad arguments");
     DPP_TRY(apply_H_all(s, 0, (const double2*)Y, (double2*)HY));
+    return DPP_OK;
+}
+
+namespace {
+
+// Device tables of dpp_system_forces (first call).
+dpp_status forces_setup(dpp_system_s* s) {
+    ForceBufs& fb = s->fb;
+    if (fb.ready) return DPP_OK;
+    std::vector<double> tau, sfrac, Z, rc;
+    size_t maxpart = 0;
+    for (int c = 0; c < s->ncells; ++c) {
+        const CellHost& ch = s->cells[c];
+        fb.aoff.push_back(fb.natall);
+        fb.proj0.push_back((int)fb.proj_atom.size());
+        fb.natall += ch.nat;
+        // s = R^{-1} tau with R's columns the lattice vectors: s_i = b_i . tau / (2 pi)
+        const double* B = ch.grid->B;
+        for (int a = 0; a < ch.nat; ++a) {
+            const double* t = &ch.tau[3 * a];
+            for (int i = 0; i < 3; ++i) {
+                tau.push_back(t[i]);
+                sfrac.push_back((B[i] * t[0] + B[3 + i] * t[1] + B[6 + i] * t[2]) / (2.0 * M_PI));
+            }
+            Z.push_back(ch.Z[a]);
+            rc.push_back(ch.rc[a]);
+            if (ch.has_proj[a]) fb.proj_atom.push_back(a);
+        }
+        const int64_t N = ch.N;
+        const int64_t chunk = std::max<int64_t>(4096, (N + LF_CHUNKS_MAX - 1) / LF_CHUNKS_MAX);
+        maxpart = std::max(maxpart, (size_t)ch.nat * 3 * (size_t)((N + chunk - 1) / chunk));
+        maxpart = std::max(maxpart, (size_t)ch.nat * 11);  // Ewald partials (8 per atom) and scratch forces
+    }
+    const int64_t na = std::max<int64_t>(fb.natall, 1);
+    DPP_TRY(dalloc_t(s, &fb.tau, 3 * na));
+    DPP_TRY(dalloc_t(s, &fb.sfrac, 3 * na));
+    DPP_TRY(dalloc_t(s, &fb.Z, na));
+    DPP_TRY(dalloc_t(s, &fb.rc, na));
+    DPP_TRY(dalloc_t(s, &fb.part, std::max<size_t>(maxpart, 1)));
+    DPP_TRY(dalloc_t(s, &fb.E, std::max(s->ncells, 1)));
+    if (fb.natall > 0) {
+        DPP_HIP(hipMemcpy(fb.tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice));
+        DPP_HIP(hipMemcpy(fb.sfrac, sfrac.data(), sfrac.size() * sizeof(double), hipMemcpyHostToDevice));
+        DPP_HIP(hipMemcpy(fb.Z, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice));
+        DPP_HIP(hipMemcpy(fb.rc, rc.data(), rc.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    int64_t q = 0, nl = 0;
+    for (int k = 0; k < s->nit; ++k) {
+        fb.qoff.push_back(q);
+        fb.nloff.push_back(nl);
+        q += 3 * (int64_t)s->hams[k]->nproj * s->npw[k];
+        nl += 3 * (int64_t)s->hams[k]->nproj;
+    }
+    DPP_TRY(dalloc_t(s, &fb.Q, std::max<int64_t>(q, 1)));
+    DPP_TRY(dalloc_t(s, &fb.Pid, std::max<int64_t>(3 * s->pisum, 1)));
+    DPP_TRY(dalloc_t(s, &fb.nlpart, std::max<int64_t>(nl, 1)));
+    for (int k = 0; k < s->nit; ++k)
+        DPP_TRY(projector_derivatives(s->ctx, s->bases[k], s->hams[k]->nproj, s->hams[k]->d_P, fb.Q + fb.qoff[k]));
+    fb.ready = true;
+    return DPP_OK;
+}
+
+// Projector forces of one cell: the sum over the cell's items (k-points) of
+// the per-projector terms, onto the atoms that carry the projectors (fixed
+// order: items in k order).
+__global__ void k_nl_gather(int nat, int item0, int nitems, const int* __restrict__ nproj_of,
+                            const int64_t* __restrict__ nloff, const int* __restrict__ proj_atom,
+                            const double* __restrict__ nlpart, double* __restrict__ F) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nat * 3) return;
+    const int a = e / 3, d = e - 3 * a;
+    double s = 0.0;
+    for (int k = 0; k < nitems; ++k) {
+        const int np = nproj_of[item0 + k];
+        for (int p = 0; p < np; ++p)
+            if (proj_atom[p] == a) s += nlpart[nloff[item0 + k] + 3 * p + d];
+    }
+    F[e] = s;
+}
+
+}  // namespace
+
+extern "C" dpp_status dpp_system_forces(dpp_system s, const dpp_c64* Yc, double* F_loc, double* F_nl, double* F_ion,
+                                        double* E_ion) {
+    clear_error();
+    DPP_REQUIRE(s && Yc, "dpp_system_forces: null argument");
+    DPP_REQUIRE(s->scf_iter > 0, "dpp_system_forces: no SCF iteration yet (fillings and density)");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DPP_HIP(hipStreamIsCapturing(stream(s), &cs));
+    DPP_REQUIRE(cs == hipStreamCaptureStatusNone, "dpp_system_forces: stream is capturing");
+    DPP_TRY(forces_setup(s));
+    ForceBufs& fb = s->fb;
+    const double2* Y = (const double2*)Yc;
+    // local and ionic terms, cell by cell
+    for (int c = 0; c < s->ncells; ++c) {
+        const CellHost& ch = s->cells[c];
+        const int64_t a0 = fb.aoff[c];
+        if (F_loc) {
+            double2* nt = reinterpret_cast<double2*>(reinterpret_cast<char*>(s->gws) + grid_coef_offset(ch.grid));
+            DPP_TRY(full_forward_real(ch.grid, s->nout + ch.foff, nt, s->gws));
+            DPP_TRY(forces_local(s->ctx, ch.grid, nt, ch.nat, fb.sfrac + 3 * a0, fb.Z + a0, fb.rc + a0, fb.part,
+                                 F_loc + 3 * a0));
+        }
+        if (F_ion || E_ion) {
+            EwaldSetup e{};
+            for (int i = 0; i < 9; ++i) e.R[i] = ch.grid->R[i], e.B[i] = ch.grid->B[i];
+            e.omega = ch.grid->omega;
+            // splitting parameter balancing the two sums; both are cut where
+            // their terms fall below exp(-36)
+            e.eta = std::sqrt(M_PI) * std::pow((double)std::max(ch.nat, 1) / (e.omega * e.omega), 1.0 / 6.0);
+            e.rcut = 6.0 / e.eta;
+            e.gcut = 12.0 * e.eta;
+            for (int i = 0; i < 3; ++i) {
+                const double bi = std::sqrt(e.B[i] * e.B[i] + e.B[3 + i] * e.B[3 + i] + e.B[6 + i] * e.B[6 + i]);
+                const double ai = std::sqrt(e.R[i] * e.R[i] + e.R[3 + i] * e.R[3 + i] + e.R[6 + i] * e.R[6 + i]);
+                e.nr[i] = (int)std::ceil(e.rcut * bi / (2.0 * M_PI)) + 1;  // planes along a_i are 2 pi / |b_i| apart
+                e.ng[i] = (int)std::ceil(e.gcut * ai / (2.0 * M_PI)) + 1;  // |m_i| = |G . a_i| / (2 pi)
+            }
+            double* Fi = F_ion ? F_ion + 3 * a0 : fb.part + 8 * ch.nat;  // energy only: forces to scratch
+            DPP_TRY(ewald_sums(s->ctx, e, ch.nat, fb.tau + 3 * a0, fb.sfrac + 3 * a0, fb.Z + a0, fb.part, Fi,
+                               fb.E + c));
+        }
+    }
+    // nonlocal terms: Pi = P^dag psi and Pid_d = Q_d^dag psi in one FP64 launch
+    if (F_nl) {
+        std::vector<OvTask> t;
+        int64_t poff = 0;
+        for (int k = 0; k < s->nit; ++k) {
+            const dpp_ham h = s->hams[k];
+            if (h->nproj == 0) continue;
+            const int nb = s->inb[k];
+            for (int d = -1; d < 3; ++d) {
+                const double2* A = d < 0 ? h->d_P : fb.Q + fb.qoff[k] + (int64_t)d * h->nproj * s->npw[k];
+                double2* out = d < 0 ? s->Pi + s->pioff[k] : fb.Pid + 3 * s->pioff[k] + (int64_t)d * h->nproj * nb;
+                OvTask x = make_ov_task((int)s->npw[k], h->nproj, A, s->npw[k], nb, Y + s->off[k], s->npw[k], 1.0,
+                                        out, nb);
+                x.part_off = poff;
+                x.item = k;
+                poff += (int64_t)x.nchunk * x.ntiles * 256;
+                t.push_back(x);
+            }
+        }
+        if ((size_t)poff > s->ov_part_elems) return set_error(DPP_EUNSUPPORTED, "overlap partial buffer too small");
+        if (!t.empty()) {
+            const OvTask* dt = nullptr;
+            DPP_TRY(table_t(s, t, &dt));
+            std::vector<int4> w;
+            overlap_worklist(t, 0, w);
+            const int4* dw = nullptr;
+            DPP_TRY(table_t(s, w, &dw));
+            DPP_TRY(overlap_tasks(s->ctx, t, dt, s->ov_part, nullptr, 0, dw, (int)w.size(), DPP_F64));
+        }
+        for (int k = 0; k < s->nit; ++k) {
+            const dpp_ham h = s->hams[k];
+            DPP_TRY(forces_nonlocal_item(s->ctx, h->nproj, s->inb[k], s->wk[k], h->D, s->d_f + s->f_off[k],
+                                         s->Pi + s->pioff[k], fb.Pid + 3 * s->pioff[k], fb.nlpart + fb.nloff[k]));
+        }
+        std::vector<int> np(s->nit);
+        for (int k = 0; k < s->nit; ++k) np[k] = s->hams[k]->nproj;
+        const int* d_np = nullptr;
+        const int64_t* d_nloff = nullptr;
+        const int* d_pa = nullptr;
+        DPP_TRY(table_t(s, np, &d_np));
+        DPP_TRY(table_t(s, fb.nloff, &d_nloff));
+        std::vector<int> pa = fb.proj_atom;
+        if (pa.empty()) pa.push_back(-1);
+        DPP_TRY(table_t(s, pa, &d_pa));
+        for (int c = 0; c < s->ncells; ++c) {
+            const CellHost& ch = s->cells[c];
+            if (ch.nat == 0) continue;
+            hipLaunchKernelGGL(k_nl_gather, dim3((ch.nat * 3 + 255) / 256), dim3(256), 0, stream(s), ch.nat,
+                               ch.item0, ch.nk, d_np, d_nloff, d_pa + fb.proj0[c], (const double*)fb.nlpart,
+                               F_nl + 3 * fb.aoff[c]);
+            DPP_LAUNCHED();
+        }
+    }
+    if (E_ion) {
+        std::vector<double> e(s->ncells);
+        DPP_HIP(hipMemcpyAsync(e.data(), fb.E, s->ncells * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
+        DPP_HIP(hipStreamSynchronize(stream(s)));
+        for (int c = 0; c < s->ncells; ++c) {
+            const CellHost& ch = s->cells[c];
+            const double omega = ch.grid->omega;
+            const double eta = std::sqrt(M_PI) * std::pow((double)std::max(ch.nat, 1) / (omega * omega), 1.0 / 6.0);
+            double z2 = 0.0, zs = 0.0;
+            for (double z : ch.Z) z2 += z * z, zs += z;
+            // self and compensating-background terms
+            E_ion[c] = e[c] - eta / std::sqrt(M_PI) * z2 - M_PI * zs * zs / (2.0 * omega * eta * eta);
+        }
+    }
     return DPP_OK;
 }
 

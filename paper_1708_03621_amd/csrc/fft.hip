@@ -1616,6 +1616,26 @@ static dpp_status full_transform(dpp_grid g, int nf, const double2* x, double2* 
     return DPP_OK;
 }
 
+// y = J n for a real field n on the grid's box (FP64, natural order); ws
+// holds the N-point plane buffer.
+dpp_status dpp::full_forward_real(dpp_grid_s* g, const double* n, double2* y, void* ws) {
+    hipStream_t st = g->ctx->stream;
+    TimerScope ts_(g->ctx, DPP_TK_FULLBOX);
+    const FftItem& it = g->h_item;
+    double2* Tb = reinterpret_cast<double2*>(ws);
+    Launch Lp = plane_launch(it.S1, it.S2, true);
+    Launch Lx = xz_launch(it.S0, it.S2, true);
+    DPP_NT_DISPATCH(Lp.threads, auto kp = k_planes_from_box<double, true, NT_>; DPP_TRY(set_lds(kp, Lp.lds));
+                    hipLaunchKernelGGL(kp, dim3(it.S0, 1, 1), dim3(NT_), Lp.lds, st, nullptr, it, (const void*)n,
+                                       (int64_t)0, -1, Tb));
+    DPP_LAUNCHED();
+    DPP_NT_DISPATCH(Lx.threads, auto kx = k_xz_full<double, NT_>; DPP_TRY(set_lds(kx, Lx.lds));
+                    hipLaunchKernelGGL(kx, dim3(it.S1, 1, 1), dim3(NT_), Lx.lds, st, it, Tb, -1,
+                                       1.0 / (double)g->N, y, (int64_t)0));
+    DPP_LAUNCHED();
+    return DPP_OK;
+}
+
 extern "C" dpp_status dpp_J(dpp_grid grid, int nf, const dpp_c64* x, dpp_c64* y, void* ws) {
     clear_error();
     DPP_REQUIRE(grid && nf >= 0, "dpp_J: bad arguments");

@@ -182,6 +182,34 @@ size_t plane_buffer_elems(const dpp_basis_s* b, int nb);   // complex elements o
 // e^{+iG.r}) keeping the real part; coef may live in the grid workspace at
 // grid_coef_offset (fft.hip).
 dpp_status full_inverse_real(dpp_grid_s* g, const double2* coef, double* out, void* ws);
+// y = J n (natural order) of a real field on the grid's box; ws: N complex.
+dpp_status full_forward_real(dpp_grid_s* g, const double* n, double2* y, void* ws);
+
+// Forces on the ions (forces.hip).  Positions enter as fractional
+// coordinates s = R^{-1} tau (3 per atom).
+// Local: F_a = -Omega sum_G G v_a(G) Im[conj(nt(G)) exp(-i G.tau_a)] over the
+// full box of one cell (nt = J n), per atom into F (nat x 3, device); part
+// holds nat * LF_CHUNKS_MAX * 3 doubles.
+dpp_status forces_local(dpp_ctx_s* ctx, const dpp_grid_s* g, const double2* nt, int nat, const double* d_sfrac,
+                        const double* d_Z, const double* d_rc, double* part, double* F);
+// Derivative projectors Q_d[a][g] = -i G_d P[a][g] (d = x, y, z; each nproj x npw, band-major).
+dpp_status projector_derivatives(dpp_ctx_s* ctx, const dpp_basis_s* b, int nproj, const double2* P, double2* Q);
+// Nonlocal force terms of one item: out[p * 3 + d] = -w D sum_i f_i 2 Re[conj(Pi_pi) Pid_d,pi],
+// Pi (nproj x nb) and Pid (3 blocks of nproj x nb), row length nb.
+dpp_status forces_nonlocal_item(dpp_ctx_s* ctx, int nproj, int nb, double w, double D, const double* f,
+                                const double2* Pi, const double2* Pid, double* out);
+// Ewald energy and forces of point charges in a compensating background;
+// E (device, 1) gets the two lattice sums; the position-independent self and
+// background terms are the caller's.
+struct EwaldSetup {
+    double R[9], B[9];  // row-major, columns a_i / b_i
+    double eta, rcut, gcut, omega;
+    int nr[3], ng[3];
+};
+// part: 8 nat doubles; F: nat x 3 (device).
+dpp_status ewald_sums(dpp_ctx_s* ctx, const EwaldSetup& e, int nat, const double* d_tau, const double* d_sfrac,
+                      const double* d_Z, double* part, double* F, double* E);
+constexpr int LF_CHUNKS_MAX = 1024;
 size_t grid_coef_offset(const dpp_grid_s* g);
 
 // Batched passes over a table of items (one per k-point or cell/k pair);

@@ -121,6 +121,7 @@ SIGNATURES = {
     "dpp_scf_init": [_vp, C.POINTER(dpp_scf_desc)],
     "dpp_scf_iteration": [_vp, _vp, C.POINTER(dpp_energy), _dp],
     "dpp_system_fillings": [_vp, _dp],
+    "dpp_system_forces": [_vp, _vp, _vp, _vp, _vp, _dp],
     "dpp_system_counters": [_vp, _i64p],
     "dpp_set_precision_policy": [_vp, _i, _d],
     "dpp_scf_status": [_vp, _dp, _ip, _ip],
@@ -564,6 +565,14 @@ def dpp_system_fillings(sys_, nk, nb):
     f = np.zeros((nk, nb))
     _call("dpp_system_fillings", sys_, f.ctypes.data_as(_dp))
     return f
+
+
+def dpp_system_forces(sys_, Y, F_loc, F_nl, F_ion, ncells):
+    """Forces into caller-owned device tensors (3 per atom, or None); returns
+    the ionic energy of every cell."""
+    e = np.zeros(ncells)
+    _call("dpp_system_forces", sys_, _ptr(Y), _ptr(F_loc), _ptr(F_nl), _ptr(F_ion), e.ctypes.data_as(_dp))
+    return e
 
 
 def dpp_set_precision_policy(sys_, bulk, refine_residual):
