@@ -433,6 +433,13 @@ dpp_status dpp_system_fillings(dpp_system sys, double *f);
  * DPP_EINVAL before the first SCF iteration or while capturing. */
 dpp_status dpp_system_forces(dpp_system sys, const dpp_c64 *Y, double *F_loc, double *F_nl, double *F_ion,
                              double *E_ion);
+/* Move the ions (ionic minimization, Table 1 and Sec. 3): tau (host, 3 per
+ * atom, cell-major, Cartesian bohr) replaces every cell's positions; the
+ * local potential, the projectors (and the force tables) are rebuilt in place,
+ * so captured SCF graphs stay valid.  The next dpp_scf_iteration works at the
+ * new positions (a fresh start density needs dpp_scf_init).  Synchronizes the
+ * stream.  DPP_EINVAL: non-finite positions, or while capturing. */
+dpp_status dpp_system_set_positions(dpp_system sys, const double *tau);
 
 /* ------------------------------------------------ learned start density -- */
 

@@ -602,27 +602,48 @@ extern "C" dpp_status dpp_ham_create(dpp_basis basis, int nat, const double* tau
     h->basis = basis;
     h->nproj = nproj;
     h->D = D;
+    h->rp = rp;
     h->d_P = nullptr;
     h->d_Veff = nullptr;
     if (nproj > 0) {
-        double* d_tau = nullptr;
-        if (hipMalloc(&d_tau, tp.size() * sizeof(double)) != hipSuccess ||
-            hipMalloc(&h->d_P, (size_t)nproj * basis->npw * sizeof(double2)) != hipSuccess) {
-            if (d_tau) hipFree(d_tau);
+        if (hipMalloc(&h->d_P, (size_t)nproj * basis->npw * sizeof(double2)) != hipSuccess) {
             delete h;
             return set_error(DPP_ENOMEM, "dpp_ham_create: allocation failed");
         }
-        hipStream_t st = basis->grid->ctx->stream;
-        DPP_HIP(hipMemcpyAsync(d_tau, tp.data(), tp.size() * sizeof(double), hipMemcpyHostToDevice, st));
-        const double* B = basis->grid->B;
-        hipLaunchKernelGGL(k_projectors, dim3((unsigned)((basis->npw + 255) / 256), nproj), dim3(256), 0, st,
-                           (int)basis->npw, nproj, basis->d_miller, basis->d_kG2, d_tau, B[0], B[1], B[2],
-                           B[3], B[4], B[5], B[6], B[7], B[8], rp, h->d_P);
-        DPP_LAUNCHED();
-        DPP_HIP(hipStreamSynchronize(st));
-        hipFree(d_tau);
+        const dpp_status st = ham_set_positions(h, nat, tau, has_proj);
+        if (st != DPP_OK) {
+            hipFree(h->d_P);
+            delete h;
+            return st;
+        }
     }
     *out = h;
+    return DPP_OK;
+}
+
+dpp_status dpp::ham_set_positions(dpp_ham_s* h, int nat, const double* tau, const int* has_proj) {
+    std::vector<double> tp;
+    for (int a = 0; a < nat; ++a)
+        if (has_proj[a])
+            for (int d = 0; d < 3; ++d) tp.push_back(tau[3 * a + d]);
+    if ((int)tp.size() != 3 * h->nproj) return set_error(DPP_EINVAL, "projector atoms changed");
+    if (h->nproj == 0) return DPP_OK;
+    const dpp_basis basis = h->basis;
+    double* d_tau = nullptr;
+    if (hipMalloc(&d_tau, tp.size() * sizeof(double)) != hipSuccess)
+        return set_error(DPP_ENOMEM, "projector positions: allocation failed");
+    hipStream_t st = basis->grid->ctx->stream;
+    hipError_t e = hipMemcpyAsync(d_tau, tp.data(), tp.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        const double* B = basis->grid->B;
+        hipLaunchKernelGGL(k_projectors, dim3((unsigned)((basis->npw + 255) / 256), h->nproj), dim3(256), 0, st,
+                           (int)basis->npw, h->nproj, basis->d_miller, basis->d_kG2, d_tau, B[0], B[1], B[2], B[3],
+                           B[4], B[5], B[6], B[7], B[8], h->rp, h->d_P);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(d_tau);
+    if (e != hipSuccess) return set_error(DPP_EDEVICE, "projector positions: HIP error");
     return DPP_OK;
 }
 

@@ -1631,17 +1631,13 @@ extern "C" dpp_status dpp_system_apply_H(dpp_system s, const dpp_c64* Y, dpp_c64
 
 namespace {
 
-// Device tables of dpp_system_forces (first call).
-dpp_status forces_setup(dpp_system_s* s) {
+// Position tables of dpp_system_forces: Cartesian and fractional positions,
+// derivative projectors.
+dpp_status forces_positions(dpp_system_s* s) {
     ForceBufs& fb = s->fb;
-    if (fb.ready) return DPP_OK;
-    std::vector<double> tau, sfrac, Z, rc;
-    size_t maxpart = 0;
+    std::vector<double> tau, sfrac;
     for (int c = 0; c < s->ncells; ++c) {
         const CellHost& ch = s->cells[c];
-        fb.aoff.push_back(fb.natall);
-        fb.proj0.push_back((int)fb.proj_atom.size());
-        fb.natall += ch.nat;
         // s = R^{-1} tau with R's columns the lattice vectors: s_i = b_i . tau / (2 pi)
         const double* B = ch.grid->B;
         for (int a = 0; a < ch.nat; ++a) {
@@ -1650,6 +1646,29 @@ dpp_status forces_setup(dpp_system_s* s) {
                 tau.push_back(t[i]);
                 sfrac.push_back((B[i] * t[0] + B[3 + i] * t[1] + B[6 + i] * t[2]) / (2.0 * M_PI));
             }
+        }
+    }
+    if (fb.natall > 0) {
+        DPP_HIP(hipMemcpy(fb.tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice));
+        DPP_HIP(hipMemcpy(fb.sfrac, sfrac.data(), sfrac.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    for (int k = 0; k < s->nit; ++k)
+        DPP_TRY(projector_derivatives(s->ctx, s->bases[k], s->hams[k]->nproj, s->hams[k]->d_P, fb.Q + fb.qoff[k]));
+    return DPP_OK;
+}
+
+// Device tables of dpp_system_forces (first call).
+dpp_status forces_setup(dpp_system_s* s) {
+    ForceBufs& fb = s->fb;
+    if (fb.ready) return DPP_OK;
+    std::vector<double> Z, rc;
+    size_t maxpart = 0;
+    for (int c = 0; c < s->ncells; ++c) {
+        const CellHost& ch = s->cells[c];
+        fb.aoff.push_back(fb.natall);
+        fb.proj0.push_back((int)fb.proj_atom.size());
+        fb.natall += ch.nat;
+        for (int a = 0; a < ch.nat; ++a) {
             Z.push_back(ch.Z[a]);
             rc.push_back(ch.rc[a]);
             if (ch.has_proj[a]) fb.proj_atom.push_back(a);
@@ -1667,8 +1686,6 @@ dpp_status forces_setup(dpp_system_s* s) {
     DPP_TRY(dalloc_t(s, &fb.part, std::max<size_t>(maxpart, 1)));
     DPP_TRY(dalloc_t(s, &fb.E, std::max(s->ncells, 1)));
     if (fb.natall > 0) {
-        DPP_HIP(hipMemcpy(fb.tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice));
-        DPP_HIP(hipMemcpy(fb.sfrac, sfrac.data(), sfrac.size() * sizeof(double), hipMemcpyHostToDevice));
         DPP_HIP(hipMemcpy(fb.Z, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice));
         DPP_HIP(hipMemcpy(fb.rc, rc.data(), rc.size() * sizeof(double), hipMemcpyHostToDevice));
     }
@@ -1682,8 +1699,7 @@ dpp_status forces_setup(dpp_system_s* s) {
     DPP_TRY(dalloc_t(s, &fb.Q, std::max<int64_t>(q, 1)));
     DPP_TRY(dalloc_t(s, &fb.Pid, std::max<int64_t>(3 * s->pisum, 1)));
     DPP_TRY(dalloc_t(s, &fb.nlpart, std::max<int64_t>(nl, 1)));
-    for (int k = 0; k < s->nit; ++k)
-        DPP_TRY(projector_derivatives(s->ctx, s->bases[k], s->hams[k]->nproj, s->hams[k]->d_P, fb.Q + fb.qoff[k]));
+    DPP_TRY(forces_positions(s));
     fb.ready = true;
     return DPP_OK;
 }
@@ -1707,6 +1723,35 @@ __global__ void k_nl_gather(int nat, int item0, int nitems, const int* __restric
 }
 
 }  // namespace
+
+extern "C" dpp_status dpp_system_set_positions(dpp_system s, const double* tau) {
+    clear_error();
+    DPP_REQUIRE(s && tau, "dpp_system_set_positions: null argument");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DPP_HIP(hipStreamIsCapturing(stream(s), &cs));
+    DPP_REQUIRE(cs == hipStreamCaptureStatusNone, "dpp_system_set_positions: stream is capturing");
+    int64_t a0 = 0;
+    for (int c = 0; c < s->ncells; ++c) {
+        const int nat = s->cells[c].nat;
+        for (int64_t q = 0; q < 3 * (int64_t)nat; ++q)
+            DPP_REQUIRE(std::isfinite(tau[3 * a0 + q]), "dpp_system_set_positions: non-finite position");
+        a0 += nat;
+    }
+    a0 = 0;
+    for (int c = 0; c < s->ncells; ++c) {
+        CellHost& ch = s->cells[c];
+        ch.tau.assign(tau + 3 * a0, tau + 3 * (a0 + ch.nat));
+        a0 += ch.nat;
+        DPP_TRY(dpp_local_potential(ch.grid, ch.nat, ch.tau.data(), ch.Z.data(), ch.rc.data(), s->Vloc + ch.foff,
+                                    s->gws));
+        for (int k = ch.item0; k < ch.item0 + ch.nk; ++k)
+            DPP_TRY(ham_set_positions(s->hams[k], ch.nat, ch.tau.data(), ch.has_proj.data()));
+    }
+    if (s->fb.ready) DPP_TRY(forces_positions(s));
+    s->vx_dirty = true;
+    DPP_HIP(hipStreamSynchronize(stream(s)));
+    return DPP_OK;
+}
 
 extern "C" dpp_status dpp_system_forces(dpp_system s, const dpp_c64* Yc, double* F_loc, double* F_nl, double* F_ion,
                                         double* E_ion) {

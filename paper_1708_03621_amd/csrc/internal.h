@@ -164,7 +164,7 @@ struct dpp_basis_s {
 struct dpp_ham_s {
     dpp_basis basis;
     int nproj;
-    double D;
+    double D, rp;
     double2* d_P;          // nproj x npw, band-major (projector a at d_P + a*npw)
     const double* d_Veff;
 };
@@ -182,6 +182,9 @@ size_t plane_buffer_elems(const dpp_basis_s* b, int nb);   // complex elements o
 // e^{+iG.r}) keeping the real part; coef may live in the grid workspace at
 // grid_coef_offset (fft.hip).
 dpp_status full_inverse_real(dpp_grid_s* g, const double2* coef, double* out, void* ws);
+// Projectors of ham recomputed in place for new atom positions (tau: 3 per
+// atom, host; the atoms carrying projectors must be those of dpp_ham_create).
+dpp_status ham_set_positions(dpp_ham_s* h, int nat, const double* tau, const int* has_proj);
 // y = J n (natural order) of a real field on the grid's box; ws: N complex.
 dpp_status full_forward_real(dpp_grid_s* g, const double* n, double2* y, void* ws);
 

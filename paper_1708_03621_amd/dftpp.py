@@ -122,6 +122,7 @@ SIGNATURES = {
     "dpp_scf_iteration": [_vp, _vp, C.POINTER(dpp_energy), _dp],
     "dpp_system_fillings": [_vp, _dp],
     "dpp_system_forces": [_vp, _vp, _vp, _vp, _vp, _dp],
+    "dpp_system_set_positions": [_vp, _dp],
     "dpp_system_counters": [_vp, _i64p],
     "dpp_set_precision_policy": [_vp, _i, _d],
     "dpp_scf_status": [_vp, _dp, _ip, _ip],
@@ -573,6 +574,11 @@ def dpp_system_forces(sys_, Y, F_loc, F_nl, F_ion, ncells):
     e = np.zeros(ncells)
     _call("dpp_system_forces", sys_, _ptr(Y), _ptr(F_loc), _ptr(F_nl), _ptr(F_ion), e.ctypes.data_as(_dp))
     return e
+
+
+def dpp_system_set_positions(sys_, tau):
+    t = np.ascontiguousarray(tau, dtype=np.float64).reshape(-1)
+    _call("dpp_system_set_positions", sys_, t.ctypes.data_as(_dp))
 
 
 def dpp_set_precision_policy(sys_, bulk, refine_residual):

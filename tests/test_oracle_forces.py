@@ -8,7 +8,9 @@
     and of E_nl at fixed wavefunctions, the energies computed by the
     operators module (independent of the force formulas);
   * Hellmann-Feynman: at a converged SCF state, the central difference of the
-    converged energy E_el + E_ion equals the sum of the three forces.
+    converged energy E_el + E_ion equals the sum of the three forces;
+  * ionic minimization (oracle/relax.py): it lowers the energy and ends below
+    its force tolerance.
 """
 import numpy as np
 import pytest
@@ -149,3 +151,25 @@ def test_hellmann_feynman_at_convergence():
     for a, d in [(0, 0), (1, 2)]:
         # O(h^2) truncation of the central difference is ~1e-6 here
         assert abs(_fd(E, HF_TAU, a, d, h) - F[a, d]) < 2e-6
+
+
+# a stretched bond (4.0 bohr) that contracts to the minimum near 3.64 bohr;
+# along this path the highest filled and lowest empty levels stay apart, so
+# every aufbau SCF converges (between 3.2 and 3.5 bohr they cross, and SCF
+# without smearing does not converge)
+RELAX_TAU = np.array([[1.748, 4.171, 3.9308], [5.042, 2.519, 2.5392]])
+
+
+def test_relaxation_reaches_force_tolerance():
+    """The oracle's ionic minimization lowers the energy and ends below the
+    force tolerance (the trajectory the GPU relaxation is compared with)."""
+    from oracle import relax as orx
+    cell = _hf_cell(RELAX_TAU)
+    r = orx.relax(orx.energy_forces(cell), RELAX_TAU, ftol=1e-3, max_steps=30)
+    E = [h[0] for h in r["history"]]
+    assert E[-1] < E[0] - 0.02
+    # at the end every force component is below the tolerance, the energy is
+    # the lowest of the trajectory, and the bond is at the minimum
+    assert np.max(np.abs(r["F"])) < 1e-3
+    assert E[-1] <= min(E) + 1e-9
+    assert abs(np.linalg.norm(r["tau"][0] - r["tau"][1]) - 3.643) < 0.01
