@@ -67,28 +67,30 @@ class Runner:
 
     def scf(self, cells, n_start, max_iter=200, tol_atom=1e-10):
         """SCF of all cells from device start densities (ncells, S...);
-        returns energies (iterations, ncells) and the last n_out per cell.
-        Stops once every cell changed by less than tol_atom per atom in two
-        consecutive iterations."""
+        returns energies (iterations, ncells), the last n_out per cell and
+        per cell whether it converged.  Stops once every cell changed by less
+        than tol_atom per atom in two consecutive iterations."""
         D = self.D
         s, Y, _ = self.system(cells)
         D.dpp_scf_init(s, cells=[dict(d_n_start=n_start[i]) for i in range(len(cells))],
                        n_inner=self.n_inner, n_inner_first=self.n_inner_first)
         nat = np.array([c.nat for c in cells])
         E = []
+        conv = np.zeros(len(cells), bool)
         for it in range(max_iter):
             e, _ = D.dpp_scf_iteration(s, Y)
             E.append([x["E_el"] for x in e])
             if it >= 2:
                 a = np.abs(np.array(E[-1]) - np.array(E[-2])) / nat
                 b = np.abs(np.array(E[-2]) - np.array(E[-3])) / nat
-                if np.all(a < tol_atom) and np.all(b < tol_atom):
+                conv = (a < tol_atom) & (b < tol_atom)
+                if np.all(conv):
                     break
         nout = self.torch.empty(n_start.shape, dtype=self.torch.float64, device=self.dev)
         D.dpp_system_copy_field(s, D.DPP_FIELD_NOUT, nout)
         self.torch.cuda.synchronize()
         D.dpp_system_destroy(s)
-        return np.array(E), nout
+        return np.array(E), nout, conv
 
 
 def iterations_to(E, E_ref, nat, tol=1e-6):
@@ -100,14 +102,14 @@ def iterations_to(E, E_ref, nat, tol=1e-6):
 
 
 def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, seed=502, max_iter=200,
-        scf_batch=64, log=_log):
+        scf_batch=64, n_inner=3, log=_log):
     import torch
 
     import workloads as W
     from paper_1708_03621_amd import dftpp as D
 
     ctx = D.dpp_ctx_create(0, torch.cuda.current_stream().cuda_stream)
-    R = Runner(D, torch, ctx, n_inner=3, n_inner_first=n_inner_first)
+    R = Runner(D, torch, ctx, n_inner=n_inner, n_inner_first=n_inner_first)
     train = W.config5("train", n_train)
     evals = W.config5("eval", n_eval)
     S = train[0].S
@@ -119,7 +121,7 @@ def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, se
     for i in range(0, len(train), scf_batch):
         cells = train[i:i + scf_batch]
         n0 = R.start_densities(cells)
-        E, nc = R.scf(cells, n0, max_iter=max_iter)
+        E, nc, _ = R.scf(cells, n0, max_iter=max_iter)
         n0s.append(n0)
         ncs.append(nc)
         scf_iters.append(len(E))
@@ -148,13 +150,14 @@ def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, se
         nl = torch.empty_like(n0)
         for j in range(len(cells)):
             D.dpp_net_predict_density(net, n0[j], ne, omega, nl[j])
-        Ep, nconv = R.scf(cells, n0, max_iter=max_iter)
-        El, _ = R.scf(cells, nl, max_iter=max_iter)
+        Ep, nconv, cp = R.scf(cells, n0, max_iter=max_iter)
+        El, _, cl = R.scf(cells, nl, max_iter=max_iter)
         for j, c in enumerate(cells):
             E_ref = Ep[-1, j]
             l1 = float(torch.sum(torch.abs(nconv[j])))
             rows.append(dict(plain=iterations_to(Ep[:, j], E_ref, c.nat),
                              learned=iterations_to(El[:, j], E_ref, c.nat),
+                             converged_plain=bool(cp[j]), converged_learned=bool(cl[j]),
                              dE_per_atom=abs(El[-1, j] - Ep[-1, j]) / c.nat, E=E_ref,
                              start_err_plain=float(torch.sum(torch.abs(n0[j] - nconv[j]))) / l1,
                              start_err_learned=float(torch.sum(torch.abs(nl[j] - nconv[j]))) / l1))
@@ -162,8 +165,13 @@ def run(n_train=512, n_eval=64, epochs=40, batch=8, lr=1e-3, n_inner_first=3, se
     D.dpp_net_destroy(net)
     ip = [r["plain"] for r in rows if r["plain"]]
     il = [r["learned"] for r in rows if r["learned"]]
+    both = [r for r in rows if r["converged_plain"] and r["converged_learned"]]
     return dict(n_train=len(train), n_eval=len(evals), nb=train[0].nb, epochs=epochs, batch=batch, lr=lr,
-                n_inner=3, n_inner_first=n_inner_first, max_iter=max_iter,
+                n_inner=n_inner, n_inner_first=n_inner_first, max_iter=max_iter,
+                cells_converged_both=len(both),
+                iters_plain_mean_converged=float(np.mean([r["plain"] for r in both])) if both else None,
+                iters_learned_mean_converged=float(np.mean([r["learned"] for r in both])) if both else None,
+                iters_saved_per_cell=[r["plain"] - r["learned"] for r in both],
                 loss_first=losses[0], loss_last=losses[-1], train_data_s=t_data, train_s=t_train, eval_s=t_eval,
                 scf_iters_train_batches=scf_iters,
                 iters_plain_mean=float(np.mean(ip)) if ip else None,
@@ -179,12 +187,13 @@ def main():
     ap.add_argument("--eval", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--first", type=int, default=3, help="band-CG steps of the first SCF iteration")
+    ap.add_argument("--inner", type=int, default=3, help="band-CG steps of every later SCF iteration")
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--scf-batch", type=int, default=64, help="cells per batched SCF system")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     res = run(args.train, args.eval, args.epochs, n_inner_first=args.first, max_iter=args.max_iter,
-              scf_batch=args.scf_batch)
+              scf_batch=args.scf_batch, n_inner=args.inner)
     js = json.dumps(res)
     if args.out:
         with open(args.out, "w") as fh:

@@ -115,15 +115,19 @@ def test_predict_density(dev):
 
 def test_learned_start_small(dev):
     """Small end-to-end run of the learned start: training data from the
-    library's SCF, training on the GPU, held-out evaluation.  The trained
-    network must reduce the start-density error, and SCF from the learned
-    density must converge to the plain start's energy within 1e-6 Ha/atom."""
-    log("learned start: 24 train, 3 eval")
+    library's SCF, training on the GPU, held-out evaluation with the bands
+    converged in every SCF iteration (8 band-CG steps, 30 in the first).  The
+    trained network must reduce the start-density error, both starts must
+    converge (two energy changes below 1e-10 Ha/atom), and their converged
+    energies must agree within 1e-6 Ha/atom."""
+    log("learned start: 24 train, 4 eval")
     from paper_1708_03621_amd import learned
-    res = learned.run(n_train=24, n_eval=3, epochs=30, batch=8, lr=2e-3, n_inner_first=20, log=log)
+    res = learned.run(n_train=24, n_eval=4, epochs=30, batch=8, lr=2e-3, n_inner=8, n_inner_first=30, max_iter=400,
+                      log=log)
     log(f"loss {res['loss_first']:.3e} -> {res['loss_last']:.3e}; start error plain "
         f"{res['start_err_plain_mean']:.3e} learned {res['start_err_learned_mean']:.3e}; iters "
         f"{res['iters_plain_mean']} -> {res['iters_learned_mean']}")
     assert res["loss_last"] < 0.5 * res["loss_first"]
     assert res["start_err_learned_mean"] < res["start_err_plain_mean"]
+    assert res["cells_converged_both"] == res["n_eval"]
     assert res["max_dE_per_atom"] < 1e-6
