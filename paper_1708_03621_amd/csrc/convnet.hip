@@ -10,8 +10,8 @@
 //
 // Kernels: forward (one thread per voxel computes every output channel, the
 // layer's weights staged in LDS), backward-data (transposed correlation),
-// backward-weights (one thread per weight over a voxel chunk, chunk partials
-// reduced in fixed order), SiLU backward, loss, Adam.
+// backward-weights (split-BF16 MFMA implicit GEMM over voxels, workgroup
+// partials reduced in fixed order), SiLU backward, loss, Adam.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,7 +24,6 @@ namespace dpp {
 
 constexpr int NL = 4;
 constexpr int CH[NL + 1] = {1, 16, 16, 16, 1};
-constexpr int WG_CHUNKS = 128;  // voxel chunks of the weight-gradient reduction
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
     return __uint_as_float(((uint32_t)h) << 16);
@@ -123,50 +122,474 @@ k_conv_bwd_data(Box bx, int64_t N, const float* __restrict__ g, const uint16_t* 
     for (int ci = 0; ci < CI; ++ci) dx[((int64_t)b * CI + ci) * N + s] = acc[ci];
 }
 
-// Weight-gradient partials: part[chunk][widx] = sum over the chunk's voxels
-// (all batch samples) of g[b][co][r] x[b][ci][r + d]; bias partials after the
-// weights (widx = CO*CI*27 + co).  One thread per gradient entry.
-template <int CI, int CO>
-__global__ void __launch_bounds__(256)
-k_conv_bwd_weight(Box bx, int64_t N, int batch, const float* __restrict__ g, const float* __restrict__ x,
-                  float* __restrict__ part) {
-    const int nw = CO * CI * 27 + CO;
-    const int widx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int chunk = blockIdx.y;
-    if (widx >= nw) return;
-    const int64_t per = (N + WG_CHUNKS - 1) / WG_CHUNKS;
-    const int64_t r_a = chunk * per, r_e = min(N, r_a + per);
-    float acc = 0.0f;
-    if (widx < CO * CI * 27) {
-        const int co = widx / (CI * 27), rem = widx - co * CI * 27;
-        const int ci = rem / 27, d = rem - ci * 27;
-        const int d0 = d / 9 - 1, d1 = (d / 3) % 3 - 1, d2 = d % 3 - 1;
-        for (int b = 0; b < batch; ++b) {
-            const float* gb = g + ((int64_t)b * CO + co) * N;
-            const float* xb = x + ((int64_t)b * CI + ci) * N;
-            for (int64_t r = r_a; r < r_e; ++r) {
-                const int r2 = (int)(r % bx.S2);
-                const int64_t q = r / bx.S2;
-                const int r1 = (int)(q % bx.S1), r0 = (int)(q / bx.S1);
-                acc += gb[r] * xb[shifted(bx, r0, r1, r2, d0, d1, d2)];
-            }
-        }
-    } else {
-        const int co = widx - CO * CI * 27;
-        for (int b = 0; b < batch; ++b) {
-            const float* gb = g + ((int64_t)b * CO + co) * N;
-            for (int64_t r = r_a; r < r_e; ++r) acc += gb[r];
-        }
-    }
-    part[(int64_t)chunk * nw + widx] = acc;
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 hi + BF16 lo (x = hi + lo to about 2^-16 relative)
+__device__ __forceinline__ void bsplit(float f, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)f;
+    lo = (__bf16)(f - (float)hi);
 }
 
-__global__ void k_sum_chunks(const float* __restrict__ part, int nw, float* __restrict__ grad) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw) return;
-    float s = 0.0f;
-    for (int c = 0; c < WG_CHUNKS; ++c) s += part[(int64_t)c * nw + i];
-    grad[i] = s;
+// v in [-n, 2n) -> v mod n
+__device__ __forceinline__ int wrap(int v, int n) {
+    v += v < 0 ? n : 0;
+    return v - (v >= n ? n : 0);
+}
+
+// ------------------------------------- 16 -> 16 layers on MFMA (forward,
+// backward-data) --------------------------------------------------------------
+// out[m][r] = bias[m] + sum_{k, d} A[m][k][d] src[k][r + s d], an implicit GEMM
+// on BF16 MFMA (16x16x32, FP32 accumulation): M = 16 output channels, N = 16
+// voxels along z, K = 27 taps x 16 input channels = 432 (14 K steps of 32, the
+// last half empty).  Forward: A = W[m][k][d], s = +1 (cross-correlation).
+// Backward-data: A = W[k][m][d], s = -1 (dx[ci][s] = sum W[co][ci][d] g[co][s - d]).
+// The BF16 weights are the A operand exactly; src (FP32) is split into BF16
+// hi + lo, two products per K step.  Workgroup = (sample, plane r0, block of
+// RT z-rows): the 3 x (RT + 2) src rows around the block are staged once, one
+// barrier, channel-last in LDS (row, channel half, position -1..S2 with the
+// periodic halo, 8 channels = one 16-byte operand per lane); each wave then
+// runs up to three 16-voxel tiles with independent accumulators.
+constexpr int C16_THREADS = 256;
+constexpr int C16_TPW = 3;      // tiles per wave
+constexpr int C16_KSTEPS = 14;  // K steps of 32 over 27 taps x 16 channels
+constexpr int C16_SPT = 3;      // staging tasks per thread per batch of loads
+
+__host__ __device__ inline int c16_tiles(int S2) { return (S2 + 15) / 16; }
+// z-rows per workgroup: 4 waves x 3 tiles
+__host__ __device__ inline int c16_rows(int S2) { return 12 / c16_tiles(S2) < 1 ? 1 : 12 / c16_tiles(S2); }
+// staged positions per row: the tiles plus one halo voxel each side
+__host__ __device__ inline int c16_pos(int S2) { return 16 * c16_tiles(S2) + 2; }
+inline size_t c16_lds_bytes(int S2) { return (size_t)3 * (c16_rows(S2) + 2) * 2 * c16_pos(S2) * 8 * 2 * 2; }
+
+// A operands in MFMA lane order, apack[kk * 64 + lane]: lane (m = lane & 15,
+// ks = lane >> 4) holds A[m][8 ks + e] of K step kk, i.e. tap 2 kk + (ks >> 1)
+// and channel 8 (ks & 1) + e; zero past tap 26.
+template <bool TRANS>
+__global__ void __launch_bounds__(C16_KSTEPS * 64) k_pack_a16(const uint16_t* __restrict__ W, bf8* __restrict__ apack) {
+    const int i = threadIdx.x, kk = i / 64, lane = i % 64;
+    const int m = lane & 15, ks = lane >> 4, tap = 2 * kk + (ks >> 1);
+    bf8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int ch = 8 * (ks & 1) + e;
+        const int idx = (TRANS ? ch * 16 + m : m * 16 + ch) * 27 + (tap < 27 ? tap : 0);
+        v[e] = __builtin_bit_cast(__bf16, tap < 27 ? W[idx] : (uint16_t)0);
+    }
+    apack[i] = v;
+}
+
+template <bool TRANS, bool ACT>
+__global__ void __launch_bounds__(C16_THREADS)
+k_conv16_mfma(Box bx, int64_t N, int nblk, const float* __restrict__ src, const bf8* __restrict__ apack,
+              const float* __restrict__ bias, float* __restrict__ out, float* __restrict__ act) {
+    extern __shared__ __attribute__((aligned(16))) char c16_smem[];
+    const int nt = c16_tiles(bx.S2), RT = c16_rows(bx.S2), P = c16_pos(bx.S2);
+    const int nrow = 3 * (RT + 2);
+    __bf16* sh = reinterpret_cast<__bf16*>(c16_smem);
+    __bf16* sl = sh + nrow * 2 * P * 8;
+    // XCD-aware order (workgroups dealt round robin to 8 XCDs): each XCD takes a
+    // contiguous run of (sample, plane, row block), row block fastest
+    const int total = gridDim.x, L = blockIdx.x, xcd = L % 8, q8 = total / 8, rem = total % 8;
+    const int id = xcd * q8 + min(xcd, rem) + L / 8;
+    const int blk = id % nblk, r0 = (id / nblk) % bx.S0, b = id / (nblk * bx.S0);
+    const int r1a = blk * RT;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = lane & 15, ks = lane >> 4;
+    bf8 a[C16_KSTEPS];
+#pragma unroll
+    for (int kk = 0; kk < C16_KSTEPS; ++kk) a[kk] = apack[kk * 64 + lane];
+    // stage src rows (r0 + dl0, r1a - 1 + jj), dl0 = -1..1, jj = 0..RT+1: row
+    // q = (dl0 + 1) (RT + 2) + jj, position p = z + 1 (periodic halo)
+    const float* sb = src + (int64_t)b * 16 * N;
+    const int np = bx.S2 + 2, ntask = nrow * np;
+    for (int t0 = 0; t0 < ntask; t0 += C16_THREADS * C16_SPT) {
+        float v[C16_SPT][16];
+#pragma unroll
+        for (int k = 0; k < C16_SPT; ++k) {
+            int t = t0 + threadIdx.x + C16_THREADS * k;
+            t = t < ntask ? t : 0;
+            const int q = t / np, pz = t % np;
+            const int a0 = ((r0 + q / (RT + 2) - 1) % bx.S0 + bx.S0) % bx.S0;
+            const int a1 = ((r1a - 1 + q % (RT + 2)) % bx.S1 + bx.S1) % bx.S1;
+            const int z = wrap(pz - 1, bx.S2);
+            const float* sp = sb + ((int64_t)a0 * bx.S1 + a1) * bx.S2 + z;
+#pragma unroll
+            for (int ch = 0; ch < 16; ++ch) v[k][ch] = sp[(int64_t)ch * N];
+        }
+#pragma unroll
+        for (int k = 0; k < C16_SPT; ++k) {
+            const int t = t0 + threadIdx.x + C16_THREADS * k;
+            if (t < ntask) {
+                const int q = t / np, pz = t % np;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    bf8 hi, lo;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        __bf16 x0, x1;
+                        bsplit(v[k][8 * h + e], x0, x1);
+                        hi[e] = x0;
+                        lo[e] = x1;
+                    }
+                    const int o = ((q * 2 + h) * P + pz) * 8;
+                    *reinterpret_cast<bf8*>(sh + o) = hi;
+                    *reinterpret_cast<bf8*>(sl + o) = lo;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // per K step: lane (voxel c, ks) reads 8 channels of tap 2 kk + (ks >> 1)
+    constexpr int sg = TRANS ? -1 : 1;
+    int off[C16_KSTEPS];
+#pragma unroll
+    for (int kk = 0; kk < C16_KSTEPS; ++kk) {
+        int tap = 2 * kk + (ks >> 1);
+        tap = tap < 27 ? tap : 26;  // A is zero there
+        const int d0 = tap / 9 - 1, d1 = (tap / 3) % 3 - 1, d2 = tap % 3 - 1;
+        const int q = (sg * d0 + 1) * (RT + 2) + sg * d1 + 1;
+        off[kk] = ((q * 2 + (ks & 1)) * P + c + sg * d2 + 1) * 8;
+    }
+    int toff[C16_TPW];
+    bool tvalid[C16_TPW];
+#pragma unroll
+    for (int i = 0; i < C16_TPW; ++i) {
+        const int T = w + 4 * i;
+        tvalid[i] = T < RT * nt;
+        const int j = tvalid[i] ? T / nt : 0, tz = tvalid[i] ? T % nt : 0;
+        toff[i] = (j * 2 * P + 16 * tz) * 8;
+    }
+    f4 ah[C16_TPW], al[C16_TPW];
+#pragma unroll
+    for (int i = 0; i < C16_TPW; ++i) ah[i] = al[i] = f4{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < C16_KSTEPS; ++kk) {
+#pragma unroll
+        for (int i = 0; i < C16_TPW; ++i) {
+            if (tvalid[i]) {  // uniform over the wave
+                const bf8 bh = *reinterpret_cast<const bf8*>(sh + off[kk] + toff[i]);
+                const bf8 bl = *reinterpret_cast<const bf8*>(sl + off[kk] + toff[i]);
+                ah[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kk], bh, ah[i], 0, 0, 0);
+                al[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kk], bl, al[i], 0, 0, 0);
+            }
+        }
+    }
+    // D[4 (l / 16) + v][l % 16] = (output channel m, voxel c of the tile)
+#pragma unroll
+    for (int i = 0; i < C16_TPW; ++i) {
+        const int T = w + 4 * i;
+        if (!tvalid[i]) continue;
+        const int r1 = r1a + T / nt, z = 16 * (T % nt) + c;
+        if (r1 >= bx.S1 || z >= bx.S2) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = 4 * ks + v;
+            float val = ah[i][v] + al[i][v];
+            if (!TRANS) val += bias[m];
+            const int64_t o = ((int64_t)b * 16 + m) * N + ((int64_t)r0 * bx.S1 + r1) * bx.S2 + z;
+            out[o] = val;
+            if (ACT) act[o] = val * sigm(val);
+        }
+    }
+}
+
+// ------------------------------------------- weight gradient on MFMA ------
+// The weight gradient as an implicit GEMM on split-BF16 MFMA (16x16x32,
+// FP32 accumulation): for each tap d = (d0, d1, d2),
+//   dW_d[co][ci] = sum_r g[co][r] x[ci][r + d] = sum_s g[co][s - d] x[ci][s],
+// K running over the voxels s of x rows.  Inputs are FP32 values split into
+// BF16 hi + lo (hi hi + hi lo + lo hi products).
+// Workgroup = (g plane r0, sample b, part of the z-rows r1), three waves; wave
+// w takes the nine taps with d0 = w - 1.  For the g row (r0, r1) the x rows
+// (r0 + d0, r1 + d1) are needed: they live in LDS as BF16 hi/lo in a ring of 4
+// row slots (slot R mod 4 holds x rows (r0 + d0, R) for d0 = -1, 0, 1 and
+// every input channel), so each z-row stages one new row triple.  The g row is
+// staged in 2 slots as three copies shifted by d2 (copy i at position p holds
+// g[s - d2], s = zs + p, d2 = i - 1), so the B operand of x row (d0, d1) serves
+// the three taps d2 = -1, 0, 1 and every operand read is an aligned 16-byte
+// LDS load.  Next rows are prefetched into registers during the current one
+// (branch-free buffer loads); one barrier per row.  K steps take 32
+// consecutive positions (8 per lane group); g copies are zero past the row
+// and past the segment (rows longer than 64 voxels run as 64-voxel segments).
+// Channels past CI or CO are zero.  FP32 partials per workgroup: weights
+// (co, ci, d) then biases, summed in FP64 in fixed order by
+// k_sum_weight_partials.
+constexpr int WGM_THREADS = 192;  // three waves
+constexpr int WGM_SPLIT = 2;      // workgroups per g plane and sample (parts of the z-rows)
+constexpr int WGM_XPF = 2;        // x staging tasks per thread (3 rows * 16 channels * 8 groups / 192)
+constexpr int WGM_RSRC_WORD3 = 0x00020000;
+constexpr unsigned WGM_OUT_OF_RANGE = 0x80000000u;  // buffer loads there return 0
+
+// x row segment staged at once: the row rounded up to 8 voxels, at most 64
+__host__ __device__ inline int wgm_row(int S2) { return S2 > 64 ? 64 : (S2 + 7) / 8 * 8; }
+// g row length: whole K steps of 32
+__host__ __device__ inline int wgm_arow(int S2) { return (wgm_row(S2) + 31) / 32 * 32; }
+// LDS row strides: an odd number of 16-byte units, so the 16 channel rows
+// that one 16-byte read spans fall in distinct banks
+__host__ __device__ inline int wgm_pad(int len) { return (len / 8) % 2 ? len : len + 8; }
+// LDS elements (hi or lo) of the x ring (4 slots x 3 rows x 16 channels, plus
+// room for the last K step's reads past the final row, where g is zero) and
+// of the g slots (2 slots x 3 shifts x 16 channels)
+__host__ __device__ inline int wgm_x_elems(int S2) { return 4 * 3 * 16 * wgm_pad(wgm_row(S2)) + 32; }
+__host__ __device__ inline int wgm_g_elems(int S2) { return 2 * 3 * 16 * wgm_pad(wgm_arow(S2)); }
+inline size_t wgm_lds_bytes(int S2) { return 2 * (size_t)(wgm_x_elems(S2) + wgm_g_elems(S2)) * 2; }
+
+__device__ __forceinline__ float wgm_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+template <int CI, int CO>
+struct WgmPipe {
+    float xv[WGM_XPF][8];  // x rows (r0 + d0, R): task t = (d0 + 1, ci, 8-voxel group)
+    float gv[10];          // g row window: task t = (co, group), gv[j] = g[zs + 8 group - 1 + j]
+                           // (row-periodic for every counted position; the others may read
+                           // another row, or 0 past the array, and are masked)
+
+    __device__ __forceinline__ void load_x(const Box& bx, int64_t N, __amdgpu_buffer_rsrc_t xr, int r0, int R, int zs,
+                                           int ngroups) {
+        const int cc = wrap(R, bx.S1);
+#pragma unroll
+        for (int k = 0; k < WGM_XPF; ++k) {
+            int t = threadIdx.x + WGM_THREADS * k;
+            t = t < 3 * CI * ngroups ? t : 0;
+            const int gq = t % ngroups, q = t / ngroups;
+            const int ci = q % CI, d0i = q / CI;
+            const int a = wrap(r0 + d0i - 1, bx.S0);
+            const int base = ci * (int)N + (a * bx.S1 + cc) * bx.S2;
+            if (bx.S2 % 4 == 0) {  // 16-byte aligned halves, each wholly inside or past the row
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int z = zs + 8 * gq + 4 * h;
+                    const f4 q = __builtin_bit_cast(
+                        f4, __builtin_amdgcn_raw_buffer_load_b128(
+                                xr, z < bx.S2 ? (unsigned)(base + z) * 4u : WGM_OUT_OF_RANGE, 0, 0));
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) xv[k][4 * h + e] = q[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int z = zs + 8 * gq + e;
+                    xv[k][e] = wgm_load(xr, z < bx.S2 ? (unsigned)(base + z) * 4u : WGM_OUT_OF_RANGE);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void store_x(__bf16* xh, __bf16* xl, int xst, int slot, int ngroups) const {
+#pragma unroll
+        for (int k = 0; k < WGM_XPF; ++k) {
+            const int t = threadIdx.x + WGM_THREADS * k;
+            if (t < 3 * CI * ngroups) {
+                const int gq = t % ngroups, q = t / ngroups;
+                const int ci = q % CI, d0i = q / CI;
+                bf8 hi, lo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    __bf16 h, l;
+                    bsplit(xv[k][e], h, l);
+                    hi[e] = h;
+                    lo[e] = l;
+                }
+                const int o = ((slot * 3 + d0i) * 16 + ci) * xst + 8 * gq;
+                *reinterpret_cast<bf8*>(xh + o) = hi;
+                *reinterpret_cast<bf8*>(xl + o) = lo;
+            }
+        }
+    }
+    __device__ __forceinline__ void load_g(const Box& bx, int64_t N, __amdgpu_buffer_rsrc_t gr, int r0, int r1, int zs,
+                                           int nga) {
+        int t = threadIdx.x;
+        t = t < CO * nga ? t : 0;
+        const int gq = t % nga, co = t / nga;
+        const int base = co * (int)N + (r0 * bx.S1 + r1) * bx.S2;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) gv[j] = wgm_load(gr, (unsigned)(base + wrap(zs + 8 * gq - 1 + j, bx.S2)) * 4u);
+    }
+    // copy i (d2 = i - 1) at position p = 8 group + e: g[zs + p - d2] = gv[e + 2 - i],
+    // zero unless p < zl and zs + p < S2; bsum gathers the unshifted counted values
+    __device__ __forceinline__ void store_g(__bf16* gh, __bf16* gl, int zl, int gst, int slot, int zs, int S2,
+                                            int nga, float& bsum) const {
+        const int t = threadIdx.x;
+        if (t < CO * nga) {
+            const int gq = t % nga, co = t / nga;
+            bf8 hi[3], lo[3];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int p = 8 * gq + e;
+                const bool ok = p < zl && zs + p < S2;
+                bsum += ok ? gv[e + 1] : 0.0f;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    __bf16 h, l;
+                    bsplit(ok ? gv[e + 2 - i] : 0.0f, h, l);
+                    hi[i][e] = h;
+                    lo[i][e] = l;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int o = ((slot * 3 + i) * 16 + co) * gst + 8 * gq;
+                *reinterpret_cast<bf8*>(gh + o) = hi[i];
+                *reinterpret_cast<bf8*>(gl + o) = lo[i];
+            }
+        }
+    }
+};
+
+// One wave's share: the nine taps with d0 = W - 1 (compile-time, so every
+// operand offset is static); every wave passes the same barriers.
+template <int CI, int CO, int W>
+__device__ __forceinline__ void wgm_body(const Box& bx, int64_t N, const float* __restrict__ g,
+                                         const float* __restrict__ x, float* __restrict__ part, __bf16* xh,
+                                         __bf16* xl, __bf16* gh, __bf16* gl, int r0, int b, int part_i) {
+    const int zl = wgm_row(bx.S2), zla = wgm_arow(bx.S2);
+    const int xst = wgm_pad(zl), gst = wgm_pad(zla);  // LDS row strides
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 15, ks = lane >> 4;
+    f4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f4{0, 0, 0, 0};
+    float bsum = 0.0f;
+    const auto gr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(g + (int64_t)b * CO * N), (short)0,
+                                                      (int)(CO * N * 4), WGM_RSRC_WORD3);
+    const auto xr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(x + (int64_t)b * CI * N), (short)0,
+                                                      (int)(CI * N * 4), WGM_RSRC_WORD3);
+    const int rows = (bx.S1 + WGM_SPLIT - 1) / WGM_SPLIT;
+    const int r1a = part_i * rows, r1e = min(bx.S1, r1a + rows);
+    const int ngroups = zl / 8, nga = zla / 8, nks = zla / 32;
+    const int nseg = (bx.S2 + zl - 1) / zl;
+    // two register sets: at row r1 one holds x row r1 + 1 and g row r1 (stored
+    // now), the other x row r1 + 2 and g row r1 + 1 (in flight since the
+    // previous row); loads run two rows ahead of their use
+    WgmPipe<CI, CO> pa, pb;
+    for (int seg = 0; seg < nseg && r1a < r1e; ++seg) {
+        const int zs = seg * zl;
+        auto row = [&](int r1, WgmPipe<CI, CO>& cur) {
+            // x slot (r1 + 1) mod 4 and g slot r1 mod 2 were last read for row
+            // r1 - 2, before the previous barrier
+            cur.store_x(xh, xl, xst, (r1 + 1) & 3, ngroups);
+            cur.store_g(gh, gl, zl, gst, r1 & 1, zs, bx.S2, nga, bsum);
+            if (r1 + 2 < r1e) {
+                cur.load_x(bx, N, xr, r0, r1 + 3, zs, ngroups);
+                cur.load_g(bx, N, gr, r0, r1 + 2, zs, nga);
+            }
+            __syncthreads();
+            const int go = ((r1 & 1) * 3 * 16 + c) * gst;  // g slot, copy 0, channel c
+            int xo[3];                                      // x slots of rows r1 + d1, d0 = W - 1, channel c
+#pragma unroll
+            for (int i = 0; i < 3; ++i) xo[i] = ((((r1 + i + 3) & 3) * 3 + W) * 16 + c) * xst;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                if (kk >= nks) break;
+                const int z0 = 8 * (4 * kk + ks);
+                bf8 ah[3], al[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    ah[i] = *reinterpret_cast<const bf8*>(gh + go + i * 16 * gst + z0);
+                    al[i] = *reinterpret_cast<const bf8*>(gl + go + i * 16 * gst + z0);
+                }
+#pragma unroll
+                for (int d1i = 0; d1i < 3; ++d1i) {
+                    const bf8 bh = *reinterpret_cast<const bf8*>(xh + xo[d1i] + z0);
+                    const bf8 bl = *reinterpret_cast<const bf8*>(xl + xo[d1i] + z0);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        acc[3 * d1i + i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[3 * d1i + i], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        acc[3 * d1i + i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[3 * d1i + i], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        acc[3 * d1i + i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[3 * d1i + i], 0, 0, 0);
+                }
+            }
+        };
+        // prologue: x rows r1a - 1 and r1a into their slots; x rows r1a + 1,
+        // r1a + 2 and g rows r1a, r1a + 1 in registers
+        pa.load_x(bx, N, xr, r0, r1a - 1, zs, ngroups);
+        pa.store_x(xh, xl, xst, (r1a + 3) & 3, ngroups);
+        pa.load_x(bx, N, xr, r0, r1a, zs, ngroups);
+        pa.store_x(xh, xl, xst, r1a & 3, ngroups);
+        pa.load_x(bx, N, xr, r0, r1a + 1, zs, ngroups);
+        pa.load_g(bx, N, gr, r0, r1a, zs, nga);
+        if (r1a + 1 < r1e) {
+            pb.load_x(bx, N, xr, r0, r1a + 2, zs, ngroups);
+            pb.load_g(bx, N, gr, r0, r1a + 1, zs, nga);
+        }
+        for (int r1 = r1a; r1 < r1e; r1 += 2) {
+            row(r1, pa);
+            if (r1 + 1 < r1e) row(r1 + 1, pb);
+        }
+        __syncthreads();  // the segment's reads are done before the next prologue
+    }
+    const int nw = CO * CI * 27 + CO;
+    float* dst = part + ((int64_t)(b * bx.S0 + r0) * WGM_SPLIT + part_i) * nw;
+    // result element v of lane l: D[4 (l / 16) + v][l % 16] = (co, ci); tap 9 W + 3 d1i + i
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int d = 9 * W + t;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int co = 4 * ks + v;
+            if (co < CO && c < CI) dst[(co * CI + c) * 27 + d] = acc[t][v];
+        }
+    }
+    // biases: the g-staging threads' sums (thread t = co * nga + group), per
+    // channel in group order; the x ring is free after the last barrier
+    float* red = reinterpret_cast<float*>(xh);
+    if (threadIdx.x < CO * nga) red[threadIdx.x] = bsum;
+    __syncthreads();
+    if (threadIdx.x < CO) {
+        float sacc = 0.0f;
+        for (int q = 0; q < nga; ++q) sacc += red[threadIdx.x * nga + q];
+        dst[CO * CI * 27 + threadIdx.x] = sacc;
+    }
+}
+
+template <int CI, int CO>
+__global__ void __launch_bounds__(WGM_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_conv_bwd_weight_mfma(Box bx, int64_t N, const float* __restrict__ g, const float* __restrict__ x,
+                       float* __restrict__ part) {
+    extern __shared__ __attribute__((aligned(16))) char wgm_smem[];
+    const int nx = wgm_x_elems(bx.S2), ng = wgm_g_elems(bx.S2);
+    __bf16* xh = reinterpret_cast<__bf16*>(wgm_smem);
+    __bf16* xl = xh + nx;
+    __bf16* gh = xl + nx;
+    __bf16* gl = gh + ng;
+    // zero once: channels past CI or CO and the tail are never staged
+    for (int i = threadIdx.x; i < nx + ng; i += WGM_THREADS) reinterpret_cast<uint32_t*>(wgm_smem)[i] = 0u;
+    __syncthreads();
+    // XCD-aware order: workgroups are dealt to the 8 XCDs round robin, so the
+    // ones on one XCD take a contiguous run of (part, sample, plane) with the
+    // plane fastest; neighbouring planes read the same x rows from one L2
+    const int total = gridDim.x, L = blockIdx.x, xcd = L % 8, q = total / 8, rem = total % 8;
+    const int id = xcd * q + min(xcd, rem) + L / 8;
+    const int r0 = id % bx.S0, b = (id / bx.S0) % (total / (bx.S0 * WGM_SPLIT)), part_i = id / (total / WGM_SPLIT);
+    // the wave index as a scalar, so each wave branches to its own body only
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+        case 0: wgm_body<CI, CO, 0>(bx, N, g, x, part, xh, xl, gh, gl, r0, b, part_i); break;
+        case 1: wgm_body<CI, CO, 1>(bx, N, g, x, part, xh, xl, gh, gl, r0, b, part_i); break;
+        default: wgm_body<CI, CO, 2>(bx, N, g, x, part, xh, xl, gh, gl, r0, b, part_i); break;
+    }
+}
+
+// grad[i] = sum over the npart workgroup partials, FP64 in fixed order: 16
+// strided partial sums per entry (one wave each), then their sum in order.
+__global__ void __launch_bounds__(1024)
+k_sum_weight_partials(const float* __restrict__ part, int npart, int nw, float* __restrict__ grad) {
+    __shared__ double red[16][64];
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+    double s = 0.0;
+    if (i < nw)
+        for (int c = grp; c < npart; c += 16) s += (double)part[(int64_t)c * nw + i];
+    red[grp][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (grp == 0 && i < nw) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
+        grad[i] = (float)t;
+    }
 }
 
 // g *= silu'(a)
@@ -330,6 +753,7 @@ struct dpp_net_s {
     float* pre[NL];             // pre-activations
     float* gbuf[2];             // gradient ping-pong (max_batch * 16 * N)
     float* wpart;               // weight-gradient partials
+    bf8* apack;                 // MFMA A operands of the 16 -> 16 layers: [layer 1, 2][forward, transposed]
     double *dpart, *dsum, *tsum, *loss;
     double *stage_n0, *stage_nc;  // batch staging (gathered samples)
     int adam_t;
@@ -346,21 +770,42 @@ dpp_status nalloc(dpp_net_s* n, void** p, size_t bytes) {
     return DPP_OK;
 }
 
-template <int CI, int CO, bool ACT>
-dpp_status launch_fwd(dpp_net_s* n, int batch, const float* x, const uint16_t* W, const float* b, float* pre, float* act) {
-    const unsigned nb = (unsigned)((n->N + 255) / 256);
-    hipLaunchKernelGGL((k_conv_fwd<CI, CO, ACT>), dim3(nb, batch), dim3(256), 0, n->ctx->stream, n->bx, n->N, x, W, b,
-                       pre, act);
+// A operands of layer l (1 or 2) for the forward or transposed product
+bf8* apack_of(dpp_net_s* n, int l, bool trans) { return n->apack + ((l - 1) * 2 + (trans ? 1 : 0)) * C16_KSTEPS * 64; }
+
+// 16 -> 16 layer on MFMA: forward (bias, SiLU into act) or backward-data
+template <bool TRANS, bool ACT>
+dpp_status launch_c16(dpp_net_s* n, int l, int batch, const float* src, const float* b, float* out, float* act) {
+    bf8* ap = apack_of(n, l, TRANS);
+    hipLaunchKernelGGL((k_pack_a16<TRANS>), dim3(1), dim3(C16_KSTEPS * 64), 0, n->ctx->stream,
+                       (const uint16_t*)(n->wbf + n->woff_bf[l]), ap);
+    DPP_LAUNCHED();
+    const int nblk = (n->bx.S1 + c16_rows(n->bx.S2) - 1) / c16_rows(n->bx.S2);
+    hipLaunchKernelGGL((k_conv16_mfma<TRANS, ACT>), dim3(n->bx.S0 * nblk * batch), dim3(C16_THREADS),
+                       c16_lds_bytes(n->bx.S2), n->ctx->stream, n->bx, n->N, nblk, src, (const bf8*)ap, b, out, act);
     DPP_LAUNCHED();
     return DPP_OK;
 }
 
+template <int CI, int CO, bool ACT>
+dpp_status launch_fwd(dpp_net_s* n, int l, int batch, const float* x, const float* b, float* pre, float* act) {
+    if constexpr (CI == 16 && CO == 16) {
+        return launch_c16<false, ACT>(n, l, batch, x, b, pre, act);
+    } else {
+        const unsigned nb = (unsigned)((n->N + 255) / 256);
+        hipLaunchKernelGGL((k_conv_fwd<CI, CO, ACT>), dim3(nb, batch), dim3(256), 0, n->ctx->stream, n->bx, n->N, x,
+                           (const uint16_t*)(n->wbf + n->woff_bf[l]), b, pre, act);
+        DPP_LAUNCHED();
+        return DPP_OK;
+    }
+}
+
 dpp_status net_forward(dpp_net_s* n, int batch) {
     TimerScope ts_(n->ctx, DPP_TK_NET, 0.0, 2.0 * batch * (double)n->N * (16 * 27 + 2 * 16 * 16 * 27 + 16 * 27));
-    DPP_TRY((launch_fwd<1, 16, true>(n, batch, n->act[0], n->wbf + n->woff_bf[0], n->p + n->off_b[0], n->pre[0], n->act[1])));
-    DPP_TRY((launch_fwd<16, 16, true>(n, batch, n->act[1], n->wbf + n->woff_bf[1], n->p + n->off_b[1], n->pre[1], n->act[2])));
-    DPP_TRY((launch_fwd<16, 16, true>(n, batch, n->act[2], n->wbf + n->woff_bf[2], n->p + n->off_b[2], n->pre[2], n->act[3])));
-    DPP_TRY((launch_fwd<16, 1, false>(n, batch, n->act[3], n->wbf + n->woff_bf[3], n->p + n->off_b[3], n->pre[3], nullptr)));
+    DPP_TRY((launch_fwd<1, 16, true>(n, 0, batch, n->act[0], n->p + n->off_b[0], n->pre[0], n->act[1])));
+    DPP_TRY((launch_fwd<16, 16, true>(n, 1, batch, n->act[1], n->p + n->off_b[1], n->pre[1], n->act[2])));
+    DPP_TRY((launch_fwd<16, 16, true>(n, 2, batch, n->act[2], n->p + n->off_b[2], n->pre[2], n->act[3])));
+    DPP_TRY((launch_fwd<16, 1, false>(n, 3, batch, n->act[3], n->p + n->off_b[3], n->pre[3], nullptr)));
     return DPP_OK;
 }
 
@@ -368,17 +813,21 @@ template <int CI, int CO>
 dpp_status layer_backward(dpp_net_s* n, int l, int batch, const float* gin, float* gout, bool need_dx) {
     const unsigned nb = (unsigned)((n->N + 255) / 256);
     const int nw = CO * CI * 27 + CO;
-    hipLaunchKernelGGL((k_conv_bwd_weight<CI, CO>), dim3((nw + 255) / 256, WG_CHUNKS), dim3(256), 0, n->ctx->stream,
-                       n->bx, n->N, batch, gin, (const float*)n->act[l], n->wpart);
+    hipLaunchKernelGGL((k_conv_bwd_weight_mfma<CI, CO>), dim3(n->bx.S0 * batch * WGM_SPLIT), dim3(WGM_THREADS),
+                       wgm_lds_bytes(n->bx.S2), n->ctx->stream, n->bx, n->N, gin, (const float*)n->act[l], n->wpart);
     DPP_LAUNCHED();
     // weights then biases are contiguous in the flat vector (off_b = off_w + CO*CI*27)
-    hipLaunchKernelGGL(k_sum_chunks, dim3((nw + 255) / 256), dim3(256), 0, n->ctx->stream, (const float*)n->wpart, nw,
-                       n->g + n->off_w[l]);
+    hipLaunchKernelGGL(k_sum_weight_partials, dim3((nw + 63) / 64), dim3(1024), 0, n->ctx->stream,
+                       (const float*)n->wpart, batch * n->bx.S0 * WGM_SPLIT, nw, n->g + n->off_w[l]);
     DPP_LAUNCHED();
     if (need_dx) {
-        hipLaunchKernelGGL((k_conv_bwd_data<CI, CO>), dim3(nb, batch), dim3(256), 0, n->ctx->stream, n->bx, n->N, gin,
-                           (const uint16_t*)(n->wbf + n->woff_bf[l]), gout);
-        DPP_LAUNCHED();
+        if constexpr (CI == 16 && CO == 16) {
+            DPP_TRY((launch_c16<true, false>(n, l, batch, gin, nullptr, gout, nullptr)));
+        } else {
+            hipLaunchKernelGGL((k_conv_bwd_data<CI, CO>), dim3(nb, batch), dim3(256), 0, n->ctx->stream, n->bx, n->N,
+                               gin, (const uint16_t*)(n->wbf + n->woff_bf[l]), gout);
+            DPP_LAUNCHED();
+        }
     }
     return DPP_OK;
 }
@@ -421,6 +870,10 @@ extern "C" dpp_status dpp_net_create(dpp_ctx ctx, const int* S, int max_batch, d
     clear_error();
     DPP_REQUIRE(ctx && S && out && max_batch >= 1, "dpp_net_create: bad arguments");
     DPP_REQUIRE(S[0] >= 3 && S[1] >= 3 && S[2] >= 3, "dpp_net_create: box too small");
+    // the weight-gradient kernel addresses one sample's 16 channels with 32-bit byte offsets below 2^31
+    DPP_REQUIRE((int64_t)S[0] * S[1] * S[2] * 16 * 4 < ((int64_t)1 << 31), "dpp_net_create: box too large");
+    // the 16 -> 16 MFMA layers hold 12 z tiles of 16 voxels per workgroup
+    DPP_REQUIRE(S[2] <= 192, "dpp_net_create: rows longer than 192 voxels are not supported");
     dpp_net_s* n = new dpp_net_s();
     n->ctx = ctx;
     n->bx = Box{S[0], S[1], S[2]};
@@ -462,13 +915,30 @@ extern "C" dpp_status dpp_net_create(dpp_ctx ctx, const int* S, int max_batch, d
     }
     n->act[4] = n->pre[3];
     if ((st = nalloc(n, (void**)&n->gbuf[0], a16)) || (st = nalloc(n, (void**)&n->gbuf[1], a16)) ||
-        (st = nalloc(n, (void**)&n->wpart, (size_t)WG_CHUNKS * (16 * 16 * 27 + 16) * 4)) ||
+        (st = nalloc(n, (void**)&n->wpart, (size_t)max_batch * S[0] * WGM_SPLIT * (16 * 16 * 27 + 16) * 4)) ||
+        (st = nalloc(n, (void**)&n->apack, (size_t)4 * C16_KSTEPS * 64 * sizeof(bf8))) ||
         (st = nalloc(n, (void**)&n->dpart, (size_t)max_batch * RB * 8 * 2)) ||
         (st = nalloc(n, (void**)&n->dsum, (size_t)max_batch * 8)) ||
         (st = nalloc(n, (void**)&n->tsum, (size_t)max_batch * 8)) || (st = nalloc(n, (void**)&n->loss, 64)) ||
         (st = nalloc(n, (void**)&n->stage_n0, (size_t)max_batch * n->N * 8)) ||
         (st = nalloc(n, (void**)&n->stage_nc, (size_t)max_batch * n->N * 8)))
         return fail(st);
+    // dynamic LDS: weight gradient 58 KB for a 40-voxel row (83 KB from 57 voxels up);
+    // 16 -> 16 layers 58 KB at 40 voxels, at most 112 KB
+    const int lds = (int)wgm_lds_bytes(S[2]);
+    if (hipFuncSetAttribute((const void*)k_conv_bwd_weight_mfma<1, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_conv_bwd_weight_mfma<16, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_conv_bwd_weight_mfma<16, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_conv16_mfma<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)c16_lds_bytes(S[2])) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_conv16_mfma<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)c16_lds_bytes(S[2])) != hipSuccess) {
+        set_error(DPP_EDEVICE, "dpp_net_create: weight-gradient LDS size not accepted");
+        return fail(DPP_EDEVICE);
+    }
     hipMemcpy(n->is_weight, isw.data(), np * 4, hipMemcpyHostToDevice);
     hipMemset(n->m, 0, np * 4);
     hipMemset(n->v, 0, np * 4);
