@@ -91,11 +91,18 @@ k_conv_fwd(Box bx, int64_t N, const float* __restrict__ x, const uint16_t* __res
     }
 }
 
-// dx[b][ci][s] = sum_co sum_d W[co][ci][d] g[b][co][s - d]
+// silu'(a) = s (1 + a (1 - s)), s = sigmoid(a)
+__device__ __forceinline__ float dsilu(float a) {
+    const float sg = sigm(a);
+    return sg * (1.0f + a * (1.0f - sg));
+}
+
+// dx[b][ci][s] = silu'(apre[b][ci][s]) sum_co sum_d W[co][ci][d] g[b][co][s - d]
+// (the gradient with respect to the pre-activation of the layer below)
 template <int CI, int CO>
 __global__ void __launch_bounds__(256)
 k_conv_bwd_data(Box bx, int64_t N, const float* __restrict__ g, const uint16_t* __restrict__ W,
-                float* __restrict__ dx) {
+                const float* __restrict__ apre, float* __restrict__ dx) {
     __shared__ float w[CO * CI * 27];
     for (int i = threadIdx.x; i < CO * CI * 27; i += blockDim.x) w[i] = bf16_to_f32(W[i]);
     __syncthreads();
@@ -119,7 +126,10 @@ k_conv_bwd_data(Box bx, int64_t N, const float* __restrict__ g, const uint16_t* 
         }
     }
 #pragma unroll
-    for (int ci = 0; ci < CI; ++ci) dx[((int64_t)b * CI + ci) * N + s] = acc[ci];
+    for (int ci = 0; ci < CI; ++ci) {
+        const int64_t o = ((int64_t)b * CI + ci) * N + s;
+        dx[o] = acc[ci] * dsilu(apre[o]);
+    }
 }
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -179,10 +189,13 @@ __global__ void __launch_bounds__(C16_KSTEPS * 64) k_pack_a16(const uint16_t* __
     apack[i] = v;
 }
 
+// Forward: out = pre-activation (+ bias), act = silu(out) if ACT.  Backward-
+// data: out = the product times silu'(aux), aux the pre-activation of the
+// layer below (the gradient with respect to it).
 template <bool TRANS, bool ACT>
 __global__ void __launch_bounds__(C16_THREADS)
 k_conv16_mfma(Box bx, int64_t N, int nblk, const float* __restrict__ src, const bf8* __restrict__ apack,
-              const float* __restrict__ bias, float* __restrict__ out, float* __restrict__ act) {
+              const float* __restrict__ aux, float* __restrict__ out, float* __restrict__ act) {
     extern __shared__ __attribute__((aligned(16))) char c16_smem[];
     const int nt = c16_tiles(bx.S2), RT = c16_rows(bx.S2), P = c16_pos(bx.S2);
     const int nrow = 3 * (RT + 2);
@@ -286,8 +299,11 @@ k_conv16_mfma(Box bx, int64_t N, int nblk, const float* __restrict__ src, const 
         for (int v = 0; v < 4; ++v) {
             const int m = 4 * ks + v;
             float val = ah[i][v] + al[i][v];
-            if (!TRANS) val += bias[m];
             const int64_t o = ((int64_t)b * 16 + m) * N + ((int64_t)r0 * bx.S1 + r1) * bx.S2 + z;
+            if (TRANS)
+                val *= dsilu(aux[o]);
+            else
+                val += aux[m];  // bias
             out[o] = val;
             if (ACT) act[o] = val * sigm(val);
         }
@@ -592,14 +608,6 @@ k_sum_weight_partials(const float* __restrict__ part, int npart, int nw, float* 
     }
 }
 
-// g *= silu'(a)
-__global__ void k_silu_bwd(int64_t n, const float* __restrict__ a, float* __restrict__ g) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float s = sigm(a[i]);
-    g[i] *= s * (1.0f + a[i] * (1.0f - s));
-}
-
 // x = n0 / nbar (FP64 in, FP32 out)
 __global__ void k_net_input(int64_t n, const double* __restrict__ n0, double inv_nbar, float* __restrict__ x) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -671,14 +679,39 @@ k_target_sum(int64_t N, const double* __restrict__ n0, const double* __restrict_
     if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = red[0];
 }
 
-// Fixed-order sums of per-sample partials: out[b] = sum_j part[b * nblk + j] * scale.
-__global__ void k_sample_reduce(const double* __restrict__ part, int nblk, int batch, double scale,
-                                double* __restrict__ out) {
-    const int b = threadIdx.x;
-    if (b >= batch) return;
+// Fixed-order sums of per-sample partials: out[b] = sum_j part[b * nblk + j] * scale
+// (block b; strided thread sums, then a fixed pairwise tree).
+__global__ void __launch_bounds__(256)
+k_sample_reduce(const double* __restrict__ part, int nblk, double scale, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int b = blockIdx.x;
     double s = 0;
-    for (int j = 0; j < nblk; ++j) s += part[b * nblk + j];
-    out[b] = s * scale;
+    for (int j = threadIdx.x; j < nblk; j += 256) s += part[(int64_t)b * nblk + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = red[0] * scale;
+}
+
+// acc[0] += sum_b v[b] (one thread, fixed order): the epoch's loss stays on the device
+__global__ void k_accumulate(const double* __restrict__ v, int nb, double* __restrict__ acc) {
+    double s = 0;
+    for (int b = 0; b < nb; ++b) s += v[b];
+    acc[0] += s;
+}
+
+// dst[j] = src[order[j]] for the batch's samples (n0 and the target), N values each
+__global__ void k_gather_samples(const int* __restrict__ order, int64_t N, const double* __restrict__ n0,
+                                 const double* __restrict__ nc, double* __restrict__ d0, double* __restrict__ dc) {
+    const int j = blockIdx.y;
+    const int64_t srcoff = (int64_t)order[j] * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        d0[(int64_t)j * N + i] = n0[srcoff + i];
+        dc[(int64_t)j * N + i] = nc[srcoff + i];
+    }
 }
 
 // Adam on FP32 master parameters; refreshes the BF16 weight copies.
@@ -756,6 +789,8 @@ struct dpp_net_s {
     bf8* apack;                 // MFMA A operands of the 16 -> 16 layers: [layer 1, 2][forward, transposed]
     double *dpart, *dsum, *tsum, *loss;
     double *stage_n0, *stage_nc;  // batch staging (gathered samples)
+    int* d_order = nullptr;       // an epoch's sample order on the device
+    int order_cap = 0;
     int adam_t;
     std::vector<void*> allocs;
 };
@@ -822,10 +857,10 @@ dpp_status layer_backward(dpp_net_s* n, int l, int batch, const float* gin, floa
     DPP_LAUNCHED();
     if (need_dx) {
         if constexpr (CI == 16 && CO == 16) {
-            DPP_TRY((launch_c16<true, false>(n, l, batch, gin, nullptr, gout, nullptr)));
+            DPP_TRY((launch_c16<true, false>(n, l, batch, gin, n->pre[l - 1], gout, nullptr)));
         } else {
             hipLaunchKernelGGL((k_conv_bwd_data<CI, CO>), dim3(nb, batch), dim3(256), 0, n->ctx->stream, n->bx, n->N,
-                               gin, (const uint16_t*)(n->wbf + n->woff_bf[l]), gout);
+                               gin, (const uint16_t*)(n->wbf + n->woff_bf[l]), (const float*)n->pre[l - 1], gout);
             DPP_LAUNCHED();
         }
     }
@@ -835,17 +870,10 @@ dpp_status layer_backward(dpp_net_s* n, int l, int batch, const float* gin, floa
 dpp_status net_backward(dpp_net_s* n, int batch) {
     // gbuf[0] holds dL/dy (1 channel); walk the layers down
     TimerScope ts_(n->ctx, DPP_TK_NET, 0.0, 4.0 * batch * (double)n->N * (16 * 27 + 2 * 16 * 16 * 27 + 16 * 27));
-    const int64_t nb16 = (int64_t)batch * 16 * n->N;
-    const unsigned eb = (unsigned)((nb16 + 255) / 256);
+    // each backward-data pass applies silu' of the layer below in its epilogue
     DPP_TRY((layer_backward<16, 1>(n, 3, batch, n->gbuf[0], n->gbuf[1], true)));
-    hipLaunchKernelGGL(k_silu_bwd, dim3(eb), dim3(256), 0, n->ctx->stream, nb16, (const float*)n->pre[2], n->gbuf[1]);
-    DPP_LAUNCHED();
     DPP_TRY((layer_backward<16, 16>(n, 2, batch, n->gbuf[1], n->gbuf[0], true)));
-    hipLaunchKernelGGL(k_silu_bwd, dim3(eb), dim3(256), 0, n->ctx->stream, nb16, (const float*)n->pre[1], n->gbuf[0]);
-    DPP_LAUNCHED();
     DPP_TRY((layer_backward<16, 16>(n, 1, batch, n->gbuf[0], n->gbuf[1], true)));
-    hipLaunchKernelGGL(k_silu_bwd, dim3(eb), dim3(256), 0, n->ctx->stream, nb16, (const float*)n->pre[0], n->gbuf[1]);
-    DPP_LAUNCHED();
     DPP_TRY((layer_backward<1, 16>(n, 0, batch, n->gbuf[1], nullptr, false)));
     return DPP_OK;
 }
@@ -858,11 +886,12 @@ dpp_status set_input(dpp_net_s* n, int batch, const double* d_n0, double nbar) {
     return DPP_OK;
 }
 
-void refresh_bf16(dpp_net_s* n, std::vector<float>& host) {
+dpp_status refresh_bf16(dpp_net_s* n, std::vector<float>& host) {
     std::vector<uint16_t> wb;
     for (int l = 0; l < NL; ++l)
         for (int i = 0; i < CH[l + 1] * CH[l] * 27; ++i) wb.push_back(f32_to_bf16(host[n->off_w[l] + i]));
-    hipMemcpy(n->wbf, wb.data(), wb.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    DPP_HIP(hipMemcpy(n->wbf, wb.data(), wb.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    return DPP_OK;
 }
 }  // namespace
 
@@ -939,18 +968,20 @@ extern "C" dpp_status dpp_net_create(dpp_ctx ctx, const int* S, int max_batch, d
         set_error(DPP_EDEVICE, "dpp_net_create: weight-gradient LDS size not accepted");
         return fail(DPP_EDEVICE);
     }
-    hipMemcpy(n->is_weight, isw.data(), np * 4, hipMemcpyHostToDevice);
-    hipMemset(n->m, 0, np * 4);
-    hipMemset(n->v, 0, np * 4);
-    hipMemset(n->g, 0, np * 4);
+    if (hipMemcpy(n->is_weight, isw.data(), np * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(n->m, 0, np * 4) != hipSuccess || hipMemset(n->v, 0, np * 4) != hipSuccess ||
+        hipMemset(n->g, 0, np * 4) != hipSuccess) {
+        set_error(DPP_EDEVICE, "dpp_net_create: initialisation copy failed");
+        return fail(DPP_EDEVICE);
+    }
     *out = n;
     return DPP_OK;
 }
 
 extern "C" dpp_status dpp_net_destroy(dpp_net n) {
     if (!n) return DPP_OK;
-    hipStreamSynchronize(n->ctx->stream);
-    for (void* p : n->allocs) hipFree(p);
+    (void)hipStreamSynchronize(n->ctx->stream);  // best effort: the net is released regardless
+    for (void* p : n->allocs) (void)hipFree(p);
     delete n;
     return DPP_OK;
 }
@@ -968,7 +999,7 @@ extern "C" dpp_status dpp_net_set_params(dpp_net n, const float* h_params) {
     std::vector<float> host(h_params, h_params + n->nparam);
     DPP_HIP(hipStreamSynchronize(n->ctx->stream));
     DPP_HIP(hipMemcpy(n->p, host.data(), n->nparam * 4, hipMemcpyHostToDevice));
-    refresh_bf16(n, host);
+    DPP_TRY(refresh_bf16(n, host));
     DPP_HIP(hipMemset(n->m, 0, n->nparam * 4));
     DPP_HIP(hipMemset(n->v, 0, n->nparam * 4));
     n->adam_t = 0;
@@ -1000,17 +1031,17 @@ static dpp_status loss_backward(dpp_net_s* n, int batch, const double* d_n0, con
     const double inv = 1.0 / nbar;
     hipLaunchKernelGGL(k_sample_sum, dim3(RB, batch), dim3(256), 0, st, n->N, (const float*)n->pre[3], n->dpart);
     DPP_LAUNCHED();
-    hipLaunchKernelGGL(k_sample_reduce, dim3(1), dim3(64), 0, st, (const double*)n->dpart, RB, batch, 1.0, n->dsum);
+    hipLaunchKernelGGL(k_sample_reduce, dim3(batch), dim3(256), 0, st, (const double*)n->dpart, RB, 1.0, n->dsum);
     DPP_LAUNCHED();
     hipLaunchKernelGGL(k_target_sum, dim3(RB, batch), dim3(256), 0, st, n->N, d_n0, d_nconv, inv, n->dpart);
     DPP_LAUNCHED();
-    hipLaunchKernelGGL(k_sample_reduce, dim3(1), dim3(64), 0, st, (const double*)n->dpart, RB, batch, 1.0, n->tsum);
+    hipLaunchKernelGGL(k_sample_reduce, dim3(batch), dim3(256), 0, st, (const double*)n->dpart, RB, 1.0, n->tsum);
     DPP_LAUNCHED();
     hipLaunchKernelGGL(k_loss_grad, dim3(RB, batch), dim3(256), 0, st, n->N, batch, (const float*)n->pre[3],
                        (const double*)n->dsum, d_n0, d_nconv, inv, (const double*)n->tsum, n->gbuf[0], n->dpart);
     DPP_LAUNCHED();
     // loss = mean over samples of mean over points
-    hipLaunchKernelGGL(k_sample_reduce, dim3(1), dim3(64), 0, st, (const double*)n->dpart, RB, batch,
+    hipLaunchKernelGGL(k_sample_reduce, dim3(batch), dim3(256), 0, st, (const double*)n->dpart, RB,
                        1.0 / ((double)n->N * batch), n->dsum);
     DPP_LAUNCHED();
     DPP_TRY(net_backward(n, batch));
@@ -1057,7 +1088,7 @@ extern "C" dpp_status dpp_net_predict_density(dpp_net n, const double* d_n0, dou
     hipStream_t st = n->ctx->stream;
     hipLaunchKernelGGL(k_sample_sum, dim3(RB, 1), dim3(256), 0, st, n->N, (const float*)n->pre[3], n->dpart);
     DPP_LAUNCHED();
-    hipLaunchKernelGGL(k_sample_reduce, dim3(1), dim3(64), 0, st, (const double*)n->dpart, RB, 1, 1.0, n->dsum);
+    hipLaunchKernelGGL(k_sample_reduce, dim3(1), dim3(256), 0, st, (const double*)n->dpart, RB, 1.0, n->dsum);
     DPP_LAUNCHED();
     hipLaunchKernelGGL(k_predict_density, dim3(RB), dim3(256), 0, st, n->N, d_n0, (const float*)n->pre[3],
                        (const double*)n->dsum, nbar, d_n_out, n->dpart);
@@ -1078,24 +1109,34 @@ extern "C" dpp_status dpp_net_train_epoch(dpp_net n, int nsamples, const double*
     for (int i = 0; i < nsamples; ++i)
         DPP_REQUIRE(order[i] >= 0 && order[i] < nsamples, "dpp_net_train_epoch: order out of range");
     hipStream_t st = n->ctx->stream;
-    const size_t bytes = (size_t)n->N * sizeof(double);
-    double tot = 0;
+    if (n->order_cap < nsamples) {
+        int* d = nullptr;
+        if (hipMalloc((void**)&d, (size_t)nsamples * sizeof(int)) != hipSuccess)
+            return set_error(DPP_ENOMEM, "dpp_net_train_epoch: allocation failed");
+        n->allocs.push_back(d);
+        n->d_order = d;
+        n->order_cap = nsamples;
+    }
+    DPP_HIP(hipMemcpyAsync(n->d_order, order, (size_t)nsamples * sizeof(int), hipMemcpyHostToDevice, st));
+    DPP_HIP(hipMemsetAsync(n->loss, 0, sizeof(double), st));
+    // the batch losses are summed on the device; one readback per epoch
     int nbt = 0;
     for (int s0 = 0; s0 < nsamples; s0 += batch) {
         const int bsz = std::min(batch, nsamples - s0);
-        for (int j = 0; j < bsz; ++j) {
-            const int64_t src = (int64_t)order[s0 + j] * n->N;
-            DPP_HIP(hipMemcpyAsync(n->stage_n0 + (int64_t)j * n->N, d_n0 + src, bytes, hipMemcpyDeviceToDevice, st));
-            DPP_HIP(hipMemcpyAsync(n->stage_nc + (int64_t)j * n->N, d_nconv + src, bytes, hipMemcpyDeviceToDevice, st));
-        }
+        hipLaunchKernelGGL(k_gather_samples, dim3(64, bsz), dim3(256), 0, st, (const int*)(n->d_order + s0), n->N,
+                           d_n0, d_nconv, n->stage_n0, n->stage_nc);
+        DPP_LAUNCHED();
         DPP_TRY(set_input(n, bsz, n->stage_n0, nbar));
         DPP_TRY(net_forward(n, bsz));
-        double l = 0;
-        DPP_TRY(dpp_net_backward(n, bsz, n->stage_n0, n->stage_nc, nbar, &l));
+        DPP_TRY(loss_backward(n, bsz, n->stage_n0, n->stage_nc, nbar));
+        hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(1), 0, st, (const double*)n->dsum, bsz, n->loss);
+        DPP_LAUNCHED();
         DPP_TRY(dpp_net_adam_step(n, lr));
-        tot += l;
         ++nbt;
     }
+    double tot = 0;
+    DPP_HIP(hipMemcpyAsync(&tot, n->loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    DPP_HIP(hipStreamSynchronize(st));
     if (mean_loss) *mean_loss = tot / nbt;
     return DPP_OK;
 }
