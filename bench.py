@@ -370,6 +370,33 @@ def pmc_probe(kind, workload, prec="f64"):
     D.dpp_system_destroy(sys_)
 
 
+def net_training(D, W, ctx, torch, epochs=3):
+    """Training throughput of the learned-start network on the config-5 box
+    (40^3): one warm-up epoch, then `epochs` timed epochs of 64 seeded
+    synthetic samples (gamma-distributed densities and a perturbed target) in
+    batches of 8; every step of an epoch runs in the library."""
+    S = tuple(W.config5("train", 1)[0].S)
+    ns, batch = 64, 8
+    net = D.dpp_net_create(ctx, S, batch)
+    D.dpp_net_set_params(net, W.net_flatten(W.net_init_params(501)))
+    rng = np.random.default_rng(1)
+    n0 = torch.from_numpy(rng.gamma(3.0, 0.01, (ns,) + S)).to("cuda:0")
+    nc = n0 * (1.0 + 0.2 * torch.from_numpy(rng.standard_normal((ns,) + S)).to("cuda:0"))
+    order = np.arange(ns, dtype=np.int32)
+    D.dpp_net_train_epoch(net, ns, n0, nc, 0.03, batch, 1e-3, order)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(epochs):
+        D.dpp_net_train_epoch(net, ns, n0, nc, 0.03, batch, 1e-3, order)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / epochs
+    D.dpp_net_destroy(net)
+    return {"box": list(S), "samples_per_epoch": ns, "batch": batch, "ms_per_epoch": ms,
+            "samples_per_s": ns / (ms * 1e-3),
+            "note": "forward, loss, backward and Adam per batch; 16->16 layers and every weight gradient on "
+                    "split-BF16 MFMA (FP32 accumulation)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,6 +412,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (default launch rules)")
     ap.add_argument("--pmc-probe", choices=["apply_H", "copy"], help="run a short loop for counter collection")
     ap.add_argument("--pmc-prec", choices=["f64", "mixed"], default="f64", help="system precision of the probe")
+    ap.add_argument("--net-only", action="store_true",
+                    help="time only the learned-start network's training (config-5 box) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built: "
@@ -395,6 +424,13 @@ def main():
         pmc_probe(args.pmc_probe, args.workload, args.pmc_prec)
         return
 
+    if args.net_only:
+        import torch
+        import workloads as W
+        from paper_1708_03621_amd import dftpp as D
+        ctx = D.dpp_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+        print(json.dumps({"net_training": net_training(D, W, ctx, torch)}), flush=True)
+        return
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle runs first, in forked processes, before the GPU is touched
@@ -459,6 +495,8 @@ def main():
                            "Ewald; includes the ionic-energy readback"}
     for sys_, _ in systems.values():
         D.dpp_system_destroy(sys_)
+    log("learned-start network: training epochs on the config-5 box")
+    net = net_training(D, W, ctx, torch)
 
     others = {}
     if not args.no_others:
@@ -516,6 +554,7 @@ def main():
                     for k, v in kern.items()},
         "other_workloads": others or None,
         "forces": forces,
+        "net_training": net,
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu

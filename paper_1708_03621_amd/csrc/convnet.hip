@@ -141,6 +141,10 @@ __device__ __forceinline__ void bsplit(float f, __bf16& hi, __bf16& lo) {
     lo = (__bf16)(f - (float)hi);
 }
 
+// buffer resources over one sample's channels (raw, 32-bit byte offsets)
+constexpr int WGM_RSRC_WORD3 = 0x00020000;
+constexpr unsigned WGM_OUT_OF_RANGE = 0x80000000u;  // buffer loads there return 0
+
 // v in [-n, 2n) -> v mod n
 __device__ __forceinline__ int wrap(int v, int n) {
     v += v < 0 ? n : 0;
@@ -166,11 +170,18 @@ constexpr int C16_KSTEPS = 14;  // K steps of 32 over 27 taps x 16 channels
 constexpr int C16_SPT = 3;      // staging tasks per thread per batch of loads
 
 __host__ __device__ inline int c16_tiles(int S2) { return (S2 + 15) / 16; }
-// z-rows per workgroup: 4 waves x 3 tiles
-__host__ __device__ inline int c16_rows(int S2) { return 12 / c16_tiles(S2) < 1 ? 1 : 12 / c16_tiles(S2); }
+// z-rows per workgroup: 4 waves x 3 tiles, at most S1
+__host__ __device__ inline int c16_rows(int S1, int S2) {
+    const int r = 12 / c16_tiles(S2) < 1 ? 1 : 12 / c16_tiles(S2);
+    return r < S1 ? r : S1;
+}
 // staged positions per row: the tiles plus one halo voxel each side
 __host__ __device__ inline int c16_pos(int S2) { return 16 * c16_tiles(S2) + 2; }
-inline size_t c16_lds_bytes(int S2) { return (size_t)3 * (c16_rows(S2) + 2) * 2 * c16_pos(S2) * 8 * 2 * 2; }
+inline size_t c16_lds_bytes(int S1, int S2) { return (size_t)3 * (c16_rows(S1, S2) + 2) * 2 * c16_pos(S2) * 8 * 2 * 2; }
+
+// floor(a / b) for 0 <= a < 2^16 and 1 <= b < 2^10 from a float reciprocal:
+// (a + 1/2) / b is at least 1/(2b) away from an integer, far above the rounding error
+__device__ __forceinline__ int c16_div(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
 
 // A operands in MFMA lane order, apack[kk * 64 + lane]: lane (m = lane & 15,
 // ks = lane >> 4) holds A[m][8 ks + e] of K step kk, i.e. tap 2 kk + (ks >> 1)
@@ -197,7 +208,7 @@ __global__ void __launch_bounds__(C16_THREADS)
 k_conv16_mfma(Box bx, int64_t N, int nblk, const float* __restrict__ src, const bf8* __restrict__ apack,
               const float* __restrict__ aux, float* __restrict__ out, float* __restrict__ act) {
     extern __shared__ __attribute__((aligned(16))) char c16_smem[];
-    const int nt = c16_tiles(bx.S2), RT = c16_rows(bx.S2), P = c16_pos(bx.S2);
+    const int nt = c16_tiles(bx.S2), RT = c16_rows(bx.S1, bx.S2), P = c16_pos(bx.S2);
     const int nrow = 3 * (RT + 2);
     __bf16* sh = reinterpret_cast<__bf16*>(c16_smem);
     __bf16* sl = sh + nrow * 2 * P * 8;
@@ -207,34 +218,39 @@ k_conv16_mfma(Box bx, int64_t N, int nblk, const float* __restrict__ src, const 
     const int id = xcd * q8 + min(xcd, rem) + L / 8;
     const int blk = id % nblk, r0 = (id / nblk) % bx.S0, b = id / (nblk * bx.S0);
     const int r1a = blk * RT;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c = lane & 15, ks = lane >> 4;
     bf8 a[C16_KSTEPS];
 #pragma unroll
     for (int kk = 0; kk < C16_KSTEPS; ++kk) a[kk] = apack[kk * 64 + lane];
     // stage src rows (r0 + dl0, r1a - 1 + jj), dl0 = -1..1, jj = 0..RT+1: row
     // q = (dl0 + 1) (RT + 2) + jj, position p = z + 1 (periodic halo)
-    const float* sb = src + (int64_t)b * 16 * N;
+    const auto sr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(src + (int64_t)b * 16 * N), (short)0,
+                                                      (int)(16 * N * 4), WGM_RSRC_WORD3);
     const int np = bx.S2 + 2, ntask = nrow * np;
+    const float inv_np = 1.0f / (float)np, inv_rt = 1.0f / (float)(RT + 2);
     for (int t0 = 0; t0 < ntask; t0 += C16_THREADS * C16_SPT) {
         float v[C16_SPT][16];
 #pragma unroll
         for (int k = 0; k < C16_SPT; ++k) {
             int t = t0 + threadIdx.x + C16_THREADS * k;
             t = t < ntask ? t : 0;
-            const int q = t / np, pz = t % np;
-            const int a0 = ((r0 + q / (RT + 2) - 1) % bx.S0 + bx.S0) % bx.S0;
-            const int a1 = ((r1a - 1 + q % (RT + 2)) % bx.S1 + bx.S1) % bx.S1;
+            const int q = c16_div(t, inv_np), pz = t - q * np;
+            const int dq = c16_div(q, inv_rt);  // dl0 + 1
+            const int a0 = wrap(r0 + dq - 1, bx.S0);
+            const int a1 = wrap(r1a - 1 + q - dq * (RT + 2), bx.S1);  // within [-1, 2 S1) as RT <= S1
             const int z = wrap(pz - 1, bx.S2);
-            const float* sp = sb + ((int64_t)a0 * bx.S1 + a1) * bx.S2 + z;
+            const unsigned vo = (unsigned)(((a0 * bx.S1 + a1) * bx.S2 + z) * 4);
 #pragma unroll
-            for (int ch = 0; ch < 16; ++ch) v[k][ch] = sp[(int64_t)ch * N];
+            for (int ch = 0; ch < 16; ++ch)  // the channel offset is scalar
+                v[k][ch] = __builtin_bit_cast(float,
+                                              __builtin_amdgcn_raw_buffer_load_b32(sr, vo, (int)(ch * N * 4), 0));
         }
 #pragma unroll
         for (int k = 0; k < C16_SPT; ++k) {
             const int t = t0 + threadIdx.x + C16_THREADS * k;
             if (t < ntask) {
-                const int q = t / np, pz = t % np;
+                const int q = c16_div(t, inv_np), pz = t - q * np;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     bf8 hi, lo;
@@ -276,16 +292,16 @@ k_conv16_mfma(Box bx, int64_t N, int nblk, const float* __restrict__ src, const 
     f4 ah[C16_TPW], al[C16_TPW];
 #pragma unroll
     for (int i = 0; i < C16_TPW; ++i) ah[i] = al[i] = f4{0, 0, 0, 0};
+    // every slot runs (a slot without a tile reads tile 0 and is not stored),
+    // so the MFMA sequence has no branches
 #pragma unroll
     for (int kk = 0; kk < C16_KSTEPS; ++kk) {
 #pragma unroll
         for (int i = 0; i < C16_TPW; ++i) {
-            if (tvalid[i]) {  // uniform over the wave
-                const bf8 bh = *reinterpret_cast<const bf8*>(sh + off[kk] + toff[i]);
-                const bf8 bl = *reinterpret_cast<const bf8*>(sl + off[kk] + toff[i]);
-                ah[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kk], bh, ah[i], 0, 0, 0);
-                al[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kk], bl, al[i], 0, 0, 0);
-            }
+            const bf8 bh = *reinterpret_cast<const bf8*>(sh + off[kk] + toff[i]);
+            const bf8 bl = *reinterpret_cast<const bf8*>(sl + off[kk] + toff[i]);
+            ah[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kk], bh, ah[i], 0, 0, 0);
+            al[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kk], bl, al[i], 0, 0, 0);
         }
     }
     // D[4 (l / 16) + v][l % 16] = (output channel m, voxel c of the tile)
@@ -334,8 +350,6 @@ k_conv16_mfma(Box bx, int64_t N, int nblk, const float* __restrict__ src, const 
 constexpr int WGM_THREADS = 192;  // three waves
 constexpr int WGM_SPLIT = 2;      // workgroups per g plane and sample (parts of the z-rows)
 constexpr int WGM_XPF = 2;        // x staging tasks per thread (3 rows * 16 channels * 8 groups / 192)
-constexpr int WGM_RSRC_WORD3 = 0x00020000;
-constexpr unsigned WGM_OUT_OF_RANGE = 0x80000000u;  // buffer loads there return 0
 
 // x row segment staged at once: the row rounded up to 8 voxels, at most 64
 __host__ __device__ inline int wgm_row(int S2) { return S2 > 64 ? 64 : (S2 + 7) / 8 * 8; }
@@ -815,9 +829,10 @@ dpp_status launch_c16(dpp_net_s* n, int l, int batch, const float* src, const fl
     hipLaunchKernelGGL((k_pack_a16<TRANS>), dim3(1), dim3(C16_KSTEPS * 64), 0, n->ctx->stream,
                        (const uint16_t*)(n->wbf + n->woff_bf[l]), ap);
     DPP_LAUNCHED();
-    const int nblk = (n->bx.S1 + c16_rows(n->bx.S2) - 1) / c16_rows(n->bx.S2);
+    const int rt = c16_rows(n->bx.S1, n->bx.S2), nblk = (n->bx.S1 + rt - 1) / rt;
     hipLaunchKernelGGL((k_conv16_mfma<TRANS, ACT>), dim3(n->bx.S0 * nblk * batch), dim3(C16_THREADS),
-                       c16_lds_bytes(n->bx.S2), n->ctx->stream, n->bx, n->N, nblk, src, (const bf8*)ap, b, out, act);
+                       c16_lds_bytes(n->bx.S1, n->bx.S2), n->ctx->stream, n->bx, n->N, nblk, src, (const bf8*)ap, b,
+                       out, act);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -962,9 +977,9 @@ extern "C" dpp_status dpp_net_create(dpp_ctx ctx, const int* S, int max_batch, d
         hipFuncSetAttribute((const void*)k_conv_bwd_weight_mfma<16, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds) != hipSuccess ||
         hipFuncSetAttribute((const void*)k_conv16_mfma<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)c16_lds_bytes(S[2])) != hipSuccess ||
+                            (int)c16_lds_bytes(S[1], S[2])) != hipSuccess ||
         hipFuncSetAttribute((const void*)k_conv16_mfma<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)c16_lds_bytes(S[2])) != hipSuccess) {
+                            (int)c16_lds_bytes(S[1], S[2])) != hipSuccess) {
         set_error(DPP_EDEVICE, "dpp_net_create: weight-gradient LDS size not accepted");
         return fail(DPP_EDEVICE);
     }
