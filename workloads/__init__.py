@@ -271,3 +271,63 @@ def net_init_params(seed: int = 501):
 def net_flatten(params) -> np.ndarray:
     """Flat float32 vector in the library's order: W1, b1, W2, b2, W3, b3, W4, b4."""
     return np.concatenate([np.concatenate([W.reshape(-1), b.reshape(-1)]) for W, b in params]).astype(np.float32)
+
+
+# ------------------------------------------------------------- LinearPCM inputs
+# The solvation model takes eps(r) and rho(r) as given (the paper leaves the
+# cavity's construction out); these inputs follow the common density-based
+# cavity: eps = 1 + (eps_b - 1) s(n), s(n) = erfc(ln(n / n_c) / (sigma sqrt 2)) / 2,
+# water-like eps_b = 78.4, n_c = 7e-4 bohr^-3, sigma = 0.6.  rho = ions
+# (Gaussians of width 0.6 bohr, charge Z) minus electrons (Gaussians of width
+# 1 bohr, Z electrons per atom): neutral up to sampling.
+PCM_EPS_B, PCM_NC, PCM_SIGMA = 78.4, 7e-4, 0.6
+PCM_ION_WIDTH, PCM_EL_WIDTH = 0.6, 1.0
+
+
+def _gaussians_on_box(R, S, tau, q, width):
+    """sum_a q_a exp(-|r - tau_a|^2 / (2 w^2)) / (2 pi w^2)^(3/2), minimum image."""
+    R = np.asarray(R, float)
+    grids = np.meshgrid(*[np.arange(s) / s for s in S], indexing="ij")
+    frac = np.stack(grids, axis=-1)
+    out = np.zeros(tuple(S))
+    Rinv = np.linalg.inv(R)
+    norm = (2.0 * np.pi * width * width) ** -1.5
+    for a in range(len(tau)):
+        d = frac - Rinv @ np.asarray(tau[a], float)
+        d -= np.round(d)
+        r = d @ R.T
+        out += q[a] * norm * np.exp(-np.sum(r * r, axis=-1) / (2.0 * width * width))
+    return out
+
+
+def pcm_case(kind: str = "small"):
+    """Seeded LinearPCM input: dict(R, S, tau, Z, n, eps, rho).
+    small: cubic 10 bohr, (20, 21, 22), two atoms; skew: a sheared cell,
+    (24, 25, 27), three atoms; config3: config 3's cell and 90^3 grid with the
+    8-atom diamond cube of its first octant centred in the box (a cluster in
+    the dielectric)."""
+    from scipy.special import erfc
+    if kind == "small":
+        R = np.eye(3) * 10.0
+        S = (20, 21, 22)
+        tau = np.array([[4.4, 5.1, 5.0], [5.9, 4.8, 5.3]])
+        Z = np.array([4.0, 1.0])
+    elif kind == "skew":
+        R = np.array([[11.0, 0.8, 0.0], [0.0, 10.4, 0.9], [0.6, 0.0, 11.3]])
+        S = (24, 25, 27)
+        rng = np.random.default_rng(41)
+        tau = R @ np.array([0.5, 0.5, 0.5]) + rng.normal(0.0, 0.9, (3, 3))
+        Z = np.array([4.0, 1.0, 1.0])
+    elif kind == "config3":
+        c3 = config3()
+        R, S = c3.R, c3.S
+        a = R[0, 0] / 2.0
+        tau = DIAMOND_FRAC * a + (np.diag(R) - a) / 2.0
+        Z = np.full(len(tau), 4.0)
+    else:
+        raise ValueError(kind)
+    n = _gaussians_on_box(R, S, tau, Z, PCM_EL_WIDTH)
+    s = 0.5 * erfc(np.log(np.maximum(n, 1e-300) / PCM_NC) / (PCM_SIGMA * np.sqrt(2.0)))
+    eps = 1.0 + (PCM_EPS_B - 1.0) * s
+    rho = _gaussians_on_box(R, S, tau, Z, PCM_ION_WIDTH) - n
+    return dict(R=np.asarray(R, float), S=tuple(S), tau=tau, Z=Z, n=n, eps=eps, rho=rho)
