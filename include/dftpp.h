@@ -248,6 +248,31 @@ dpp_status dpp_density_accumulate(dpp_basis basis, int nb, const dpp_c64 *psi, i
 /* Hartree solve (coulomb operator): V_H = Re I[4 pi (J n)/|G|^2], G = 0
  * dropped; E_H = (Omega/2) sum_{G != 0} 4 pi |J n|^2 / |G|^2 -> *d_EH. */
 dpp_status dpp_hartree(dpp_grid grid, const double *d_n, double *d_VH, double *d_EH, void *ws);
+
+/* ------------------------------------------------------------ LinearPCM -- */
+
+/* Workspace bytes of dpp_pcm_solve on this grid (8 full-box complex fields
+ * plus reduction partials: about 128 N bytes). */
+dpp_status dpp_pcm_workspace_size(dpp_grid grid, size_t *bytes);
+/* LinearPCM solvation (Sec. 2.1, Eqs. (1)-(2), Listing 1): solves
+ * -4 pi rho = div(eps grad phi), posed on reciprocal fields as
+ * (-1/(4 pi)) div(J(eps * I(grad phi~))) = J rho, by conjugate gradients
+ * preconditioned with 4 pi / |G'|^2, from phi~ = 0, until
+ * ||r|| <= tol ||J rho|| (2-norms over the solved modes) or max_iter
+ * iterations; then A_diel = (Omega/2) Re sum_G conj(phi~ - 4 pi rho~/|G|^2) rho~.
+ * grad and div use G' = B m' (m' the signed frequency, the Nyquist index of
+ * an even axis counted as 0); modes with G' = 0 are outside the solve (phi~ = 0,
+ * rho~ dropped there: any net charge meets a neutralizing background).
+ * d_eps, d_rho: device, N doubles each, the box in natural order (eps > 0
+ * expected; not checked).  d_phi: device, N doubles, phi(r) = Re I phi~, or
+ * NULL.  *A_diel (host, hartree), *iterations and *rel_residual (host, may be
+ * NULL) report the result.  ws: dpp_pcm_workspace_size bytes, device,
+ * caller-owned; its contents on return are scratch.  Stream-ordered on the
+ * grid's context; returns after the result is on the host (one host
+ * synchronization per CG iteration for the convergence test).  Errors:
+ * DPP_EINVAL for null pointers, tol < 0 or max_iter < 0. */
+dpp_status dpp_pcm_solve(dpp_grid grid, const double *d_eps, const double *d_rho, double tol, int max_iter,
+                         double *d_phi, double *A_diel, int *iterations, double *rel_residual, void *ws);
 /* LDA (Slater exchange + Perdew-Zunger 1981 correlation): v_xc per point
  * and E_xc = (Omega/N) sum n eps_xc -> *d_Exc.  n < 1e-16 gives 0. */
 dpp_status dpp_lda_pz81(dpp_grid grid, const double *d_n, double *d_vxc, double *d_Exc, void *ws);

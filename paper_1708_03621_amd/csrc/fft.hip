@@ -1616,6 +1616,10 @@ static dpp_status full_transform(dpp_grid g, int nf, const double2* x, double2* 
     return DPP_OK;
 }
 
+dpp_status dpp::full_complex(dpp_grid_s* g, int nf, const double2* x, double2* y, int sign, double scale, void* ws) {
+    return full_transform(g, nf, x, y, sign, scale, ws);
+}
+
 // y = J n for a real field n on the grid's box (FP64, natural order); ws
 // holds the N-point plane buffer.
 dpp_status dpp::full_forward_real(dpp_grid_s* g, const double* n, double2* y, void* ws) {

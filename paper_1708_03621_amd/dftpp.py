@@ -99,6 +99,8 @@ SIGNATURES = {
     "dpp_subspace_eigh_noalloc": [_vp, _i, _i, _vp, _vp, _vp],
     "dpp_density_accumulate": [_vp, _i, _vp, _i64, _vp, _d, _vp, _i, _vp],
     "dpp_hartree": [_vp, _vp, _vp, _vp, _vp],
+    "dpp_pcm_workspace_size": [_vp, C.POINTER(C.c_size_t)],
+    "dpp_pcm_solve": [_vp, _vp, _vp, C.c_double, _i, _vp, _dp, C.POINTER(C.c_int), _dp, _vp],
     "dpp_lda_pz81": [_vp, _vp, _vp, _vp, _vp],
     "dpp_local_potential": [_vp, _i, _dp, _dp, _dp, _vp, _vp],
     "dpp_start_density": [_vp, _i, _dp, _dp, _d, _vp, _vp],
@@ -359,6 +361,20 @@ def dpp_density_accumulate(basis, nb, psi, ldpsi, d_f, wk, d_n, prec, ws):
 
 def dpp_hartree(grid, d_n, d_VH, d_EH, ws):
     _call("dpp_hartree", grid, _ptr(d_n), _ptr(d_VH), _ptr(d_EH), _ptr(ws))
+
+
+def dpp_pcm_workspace_size(grid):
+    v = C.c_size_t()
+    _call("dpp_pcm_workspace_size", grid, C.byref(v))
+    return v.value
+
+
+def dpp_pcm_solve(grid, d_eps, d_rho, tol, max_iter, d_phi, ws):
+    """Returns (A_diel, iterations, relative residual); phi(r) into d_phi (or None)."""
+    A, it, rel = C.c_double(), C.c_int(), C.c_double()
+    _call("dpp_pcm_solve", grid, _ptr(d_eps), _ptr(d_rho), float(tol), int(max_iter), _ptr(d_phi), C.byref(A),
+          C.byref(it), C.byref(rel), _ptr(ws))
+    return A.value, it.value, rel.value
 
 
 def dpp_lda_pz81(grid, d_n, d_vxc, d_Exc, ws):

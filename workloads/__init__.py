@@ -302,14 +302,14 @@ def _gaussians_on_box(R, S, tau, q, width):
 
 def pcm_case(kind: str = "small"):
     """Seeded LinearPCM input: dict(R, S, tau, Z, n, eps, rho).
-    small: cubic 10 bohr, (20, 21, 22), two atoms; skew: a sheared cell,
+    small: cubic 10 bohr, (20, 24, 25), two atoms; skew: a sheared cell,
     (24, 25, 27), three atoms; config3: config 3's cell and 90^3 grid with the
     8-atom diamond cube of its first octant centred in the box (a cluster in
     the dielectric)."""
     from scipy.special import erfc
     if kind == "small":
         R = np.eye(3) * 10.0
-        S = (20, 21, 22)
+        S = (20, 24, 25)
         tau = np.array([[4.4, 5.1, 5.0], [5.9, 4.8, 5.3]])
         Z = np.array([4.0, 1.0])
     elif kind == "skew":
