@@ -251,8 +251,8 @@ dpp_status dpp_hartree(dpp_grid grid, const double *d_n, double *d_VH, double *d
 
 /* ------------------------------------------------------------ LinearPCM -- */
 
-/* Workspace bytes of dpp_pcm_solve on this grid (8 full-box complex fields
- * plus reduction partials: about 128 N bytes). */
+/* Workspace bytes of dpp_pcm_solve on this grid (9 full-box complex fields
+ * plus reduction partials: about 144 N bytes). */
 dpp_status dpp_pcm_workspace_size(dpp_grid grid, size_t *bytes);
 /* LinearPCM solvation (Sec. 2.1, Eqs. (1)-(2), Listing 1): solves
  * -4 pi rho = div(eps grad phi), posed on reciprocal fields as

@@ -1617,7 +1617,21 @@ static dpp_status full_transform(dpp_grid g, int nf, const double2* x, double2* 
 }
 
 dpp_status dpp::full_complex(dpp_grid_s* g, int nf, const double2* x, double2* y, int sign, double scale, void* ws) {
-    return full_transform(g, nf, x, y, sign, scale, ws);
+    // all nf fields in one launch per pass (blockIdx.y = field); ws holds nf plane buffers
+    hipStream_t st = g->ctx->stream;
+    TimerScope ts_(g->ctx, DPP_TK_FULLBOX);
+    const FftItem& it = g->h_item;
+    double2* Tb = reinterpret_cast<double2*>(ws);
+    Launch Lp = plane_launch(it.S1, it.S2, true);
+    Launch Lx = xz_launch(it.S0, it.S2, true);
+    DPP_NT_DISPATCH(Lp.threads, auto kp = k_planes_from_box<double, false, NT_>; DPP_TRY(set_lds(kp, Lp.lds));
+                    hipLaunchKernelGGL(kp, dim3(it.S0, nf, 1), dim3(NT_), Lp.lds, st, nullptr, it, (const void*)x,
+                                       g->N, sign, Tb));
+    DPP_LAUNCHED();
+    DPP_NT_DISPATCH(Lx.threads, auto kx = k_xz_full<double, NT_>; DPP_TRY(set_lds(kx, Lx.lds));
+                    hipLaunchKernelGGL(kx, dim3(it.S1, nf, 1), dim3(NT_), Lx.lds, st, it, Tb, sign, scale, y, g->N));
+    DPP_LAUNCHED();
+    return DPP_OK;
 }
 
 // y = J n for a real field n on the grid's box (FP64, natural order); ws

@@ -188,7 +188,7 @@ dpp_status ham_set_positions(dpp_ham_s* h, int nat, const double* tau, const int
 // y = J n (natural order) of a real field on the grid's box; ws: N complex.
 dpp_status full_forward_real(dpp_grid_s* g, const double* n, double2* y, void* ws);
 // Full-box complex transforms of nf fields (stride N): y = scale * sum_r x e^{sign i G.r}
-// (natural order; x may equal y); ws: N complex.
+// (natural order; x may equal y), one launch per pass for all fields; ws: nf N complex.
 dpp_status full_complex(dpp_grid_s* g, int nf, const double2* x, double2* y, int sign, double scale, void* ws);
 
 // Forces on the ions (forces.hip).  Positions enter as fractional

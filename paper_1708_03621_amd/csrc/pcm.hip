@@ -249,19 +249,19 @@ struct PcmWs {
     double *part, *sc;
 };
 
-size_t pcm_ws_bytes(int64_t N) { return (size_t)N * 16 * 8 + (size_t)PCM_BLOCKS * 2 * 8 + 64 * 8 + 256; }
+size_t pcm_ws_bytes(int64_t N) { return (size_t)N * 16 * 9 + (size_t)PCM_BLOCKS * 2 * 8 + 64 * 8 + 256; }
 
 PcmWs pcm_layout(void* ws, int64_t N) {
     PcmWs w;
     double2* c = reinterpret_cast<double2*>(ws);
-    w.T = c;
-    w.x = c + N;
-    w.r = c + 2 * N;
-    w.p = c + 3 * N;
-    w.q = c + 4 * N;
-    w.U = c + 5 * N;  // two fields
-    w.b = c + 7 * N;
-    w.part = reinterpret_cast<double*>(c + 8 * N);
+    w.T = c;  // two plane buffers
+    w.x = c + 2 * N;
+    w.r = c + 3 * N;
+    w.p = c + 4 * N;
+    w.q = c + 5 * N;
+    w.U = c + 6 * N;  // two fields
+    w.b = c + 8 * N;
+    w.part = reinterpret_cast<double*>(c + 9 * N);
     w.sc = w.part + PCM_BLOCKS * 2;
     return w;
 }
