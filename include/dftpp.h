@@ -276,6 +276,21 @@ dpp_status dpp_pcm_solve(dpp_grid grid, const double *d_eps, const double *d_rho
 /* LDA (Slater exchange + Perdew-Zunger 1981 correlation): v_xc per point
  * and E_xc = (Omega/N) sum n eps_xc -> *d_Exc.  n < 1e-16 gives 0. */
 dpp_status dpp_lda_pz81(dpp_grid grid, const double *d_n, double *d_vxc, double *d_Exc, void *ws);
+/* Workspace bytes of dpp_gga_pbe on this grid (6 full-box complex fields
+ * plus reduction partials: about 96 N bytes). */
+dpp_status dpp_gga_workspace_size(dpp_grid grid, size_t *bytes);
+/* PBE exchange-correlation, spin-unpolarized (Table 1 and Sec. 2.2:
+ * semilocal GGA functionals): per point e(n, sigma) = n eps_x^LDA F_x(s)
+ * + n (eps_c^PW92(r_s) + H(r_s, t)), sigma = |grad n|^2; potential
+ * v_xc = de/dn - div(2 de/dsigma grad n); *d_Exc = (Omega/N) sum_r e.
+ * grad and div are spectral (J, i G', I) with G' = B m', the Nyquist index of
+ * an even axis counted as 0.  Densities below 1e-16 (negative ones
+ * included) contribute e = 0 and no derivatives.  d_n: device, N doubles,
+ * natural box order; d_vxc: device, N doubles (output); d_Exc: device, one
+ * double (output); ws: dpp_gga_workspace_size bytes, device, caller-owned.
+ * Stream-ordered on the grid's context, no host synchronization.  Errors:
+ * DPP_EINVAL for null pointers. */
+dpp_status dpp_gga_pbe(dpp_grid grid, const double *d_n, double *d_vxc, double *d_Exc, void *ws);
 /* V_loc(r) = Re I[sum_a v_a(|G|) exp(-i G.tau_a)], v_a(G) = -4 pi Z_a
  * exp(-G^2 rc_a^2/4) / (Omega G^2), v_a(0) = 0.  Host tau (nat x 3), Z, rc. */
 dpp_status dpp_local_potential(dpp_grid grid, int nat, const double *tau, const double *Z,

@@ -100,6 +100,8 @@ SIGNATURES = {
     "dpp_density_accumulate": [_vp, _i, _vp, _i64, _vp, _d, _vp, _i, _vp],
     "dpp_hartree": [_vp, _vp, _vp, _vp, _vp],
     "dpp_pcm_workspace_size": [_vp, C.POINTER(C.c_size_t)],
+    "dpp_gga_workspace_size": [_vp, C.POINTER(C.c_size_t)],
+    "dpp_gga_pbe": [_vp, _vp, _vp, _vp, _vp],
     "dpp_pcm_solve": [_vp, _vp, _vp, C.c_double, _i, _vp, _dp, C.POINTER(C.c_int), _dp, _vp],
     "dpp_lda_pz81": [_vp, _vp, _vp, _vp, _vp],
     "dpp_local_potential": [_vp, _i, _dp, _dp, _dp, _vp, _vp],
@@ -375,6 +377,16 @@ def dpp_pcm_solve(grid, d_eps, d_rho, tol, max_iter, d_phi, ws):
     _call("dpp_pcm_solve", grid, _ptr(d_eps), _ptr(d_rho), float(tol), int(max_iter), _ptr(d_phi), C.byref(A),
           C.byref(it), C.byref(rel), _ptr(ws))
     return A.value, it.value, rel.value
+
+
+def dpp_gga_workspace_size(grid):
+    v = C.c_size_t()
+    _call("dpp_gga_workspace_size", grid, C.byref(v))
+    return v.value
+
+
+def dpp_gga_pbe(grid, d_n, d_vxc, d_Exc, ws):
+    _call("dpp_gga_pbe", grid, _ptr(d_n), _ptr(d_vxc), _ptr(d_Exc), _ptr(ws))
 
 
 def dpp_lda_pz81(grid, d_n, d_vxc, d_Exc, ws):

@@ -1,0 +1,71 @@
+"""GPU parity of the PBE exchange-correlation (dpp_gga_pbe) with the oracle
+(oracle/gga.py) on the same densities.
+
+Both evaluate the same FP64 formula; the GPU's derivatives come from dual
+numbers, the oracle's from complex steps, both exact to rounding, and the
+gradient and divergence from full-box transforms on both sides (rounding
+~1e-15 of the largest coefficient).  Bars: E_xc to 1e-12 relative, v_xc to
+1e-9 of max |v_xc| (the gradient terms amplify rounding where the density
+is small).  Cases: a smooth two-centre density on a sheared 16 x 15 x 18 box,
+config 3's superposition start density at 90^3, and a density with zeros
+and negative values (the floor: those points contribute nothing).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import energy as oe, gga
+from tests._gpu import Device, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return Device()
+
+
+def _gpu(dev, R, n):
+    D = dev.D
+    g = dev.grid(R, n.shape)
+    ws = dev.ws(D.dpp_gga_workspace_size(g))
+    v = dev.empty(n.shape, dev.torch.float64)
+    E = dev.zeros((1,), dev.torch.float64)
+    D.dpp_gga_pbe(g, dev.tensor(n), v, E, ws)
+    out = dev.host(v), float(dev.host(E)[0])
+    D.dpp_grid_destroy(g)
+    return out
+
+
+def _two_centre(R, S):
+    fr = np.stack(np.meshgrid(*[np.arange(s) / s for s in S], indexing="ij"), axis=-1)
+
+    def blob(c, w):
+        d = fr - np.asarray(c)
+        d -= np.round(d)
+        x = d @ np.asarray(R).T
+        return np.exp(-np.sum(x * x, axis=-1) / (2 * w * w))
+
+    return 0.3 * blob([0.4, 0.5, 0.45], 1.1) + 0.2 * blob([0.7, 0.3, 0.6], 0.9) + 1e-3
+
+
+@pytest.mark.parametrize("case", ["sheared", "config3", "floor"])
+def test_pbe_matches_oracle(dev, case):
+    if case == "sheared":
+        R = np.array([[7.0, 0.3, 0.0], [0.0, 6.6, 0.4], [0.2, 0.0, 7.2]])
+        n = _two_centre(R, (16, 15, 18))
+    elif case == "config3":
+        cell = W.config3()
+        R = cell.R
+        n = oe.start_density(cell, W.START_SIGMA)
+    else:
+        R = np.eye(3) * 6.0
+        n = W.random_density(12, (12, 15, 16), mean=0.05) - 0.02  # some points below zero
+        n[0, 0, :4] = 0.0
+    log(f"pbe {case} S={n.shape} min n {n.min():.2e}")
+    v, E = _gpu(dev, R, n)
+    vo, Eo = gga.pbe_on_grid(n, R)
+    dv = np.max(np.abs(v - vo))
+    log(f"E gpu {E:.15e} oracle {Eo:.15e}; max |dv| {dv:.2e} of {np.max(np.abs(vo)):.3e}")
+    assert abs(E - Eo) < 1e-12 * abs(Eo)
+    assert dv < 1e-9 * np.max(np.abs(vo))
