@@ -291,6 +291,14 @@ dpp_status dpp_gga_workspace_size(dpp_grid grid, size_t *bytes);
  * Stream-ordered on the grid's context, no host synchronization.  Errors:
  * DPP_EINVAL for null pointers. */
 dpp_status dpp_gga_pbe(dpp_grid grid, const double *d_n, double *d_vxc, double *d_Exc, void *ws);
+/* Exchange-correlation functional of a system's SCF (V_eff and E_xc):
+ * DPP_XC_LDA_PZ81 (default, every cell in one launch) or DPP_XC_PBE
+ * (dpp_gga_pbe per cell on its full box).  Allocates the PBE workspace on
+ * first use (the system owns it); drops captured SCF graphs, which are
+ * captured again on the next iterations.  Errors: DPP_EINVAL for a null
+ * system or an unknown value, DPP_ENOMEM. */
+enum { DPP_XC_LDA_PZ81 = 0, DPP_XC_PBE = 1 };
+dpp_status dpp_system_set_xc(dpp_system sys, int functional);
 /* V_loc(r) = Re I[sum_a v_a(|G|) exp(-i G.tau_a)], v_a(G) = -4 pi Z_a
  * exp(-G^2 rc_a^2/4) / (Omega G^2), v_a(0) = 0.  Host tau (nat x 3), Z, rc. */
 dpp_status dpp_local_potential(dpp_grid grid, int nat, const double *tau, const double *Z,

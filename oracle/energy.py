@@ -41,6 +41,7 @@ class System:
     D: float
     n_electrons: int
     nat: int
+    xc: str = "lda"             # "lda" (PZ81, oracle/xc.py) or "pbe" (oracle/gga.py)
 
     @property
     def omega(self) -> float:
@@ -51,8 +52,8 @@ class System:
         return int(np.prod(self.S))
 
 
-def build_system(cell, with_local=True, with_projectors=True) -> System:
-    """Set up bases, V_loc and projectors for a workloads.Cell."""
+def build_system(cell, with_local=True, with_projectors=True, xc="lda") -> System:
+    """Set up bases, V_loc and projectors for a workloads.Cell (xc: "lda" or "pbe")."""
     from workloads import PROJ_D, PROJ_RP
     bases = [gsphere(cell.R, cell.S, k, cell.ecut) for k in cell.kpts]
     if with_local:
@@ -62,7 +63,7 @@ def build_system(cell, with_local=True, with_projectors=True) -> System:
     hp = cell.has_proj if with_projectors else np.zeros(cell.nat, bool)
     P = [ops.projectors(b, cell.tau, hp, PROJ_RP) for b in bases]
     return System(np.asarray(cell.R, float), tuple(cell.S), bases, np.asarray(cell.wk, float),
-                  Vloc, P, PROJ_D, cell.n_electrons, cell.nat)
+                  Vloc, P, PROJ_D, cell.n_electrons, cell.nat, xc)
 
 
 def density(psis, fills, sys: System) -> np.ndarray:
@@ -90,9 +91,13 @@ def hartree(n: np.ndarray, R) -> tuple:
 def potentials(n: np.ndarray, sys: System):
     """V_eff and the density-dependent energy terms for density n."""
     VH, EH = hartree(n, sys.R)
-    eps, vxc = lda_pz81(n)
     dV = sys.omega / sys.N
-    Exc = float(dV * np.sum(n * eps))
+    if sys.xc == "pbe":
+        from .gga import pbe_on_grid
+        vxc, Exc = pbe_on_grid(n, sys.R)
+    else:
+        eps, vxc = lda_pz81(n)
+        Exc = float(dV * np.sum(n * eps))
     Eloc = float(dV * np.sum(sys.Vloc * n))
     return sys.Vloc + VH + vxc, dict(E_H=EH, E_xc=Exc, E_loc=Eloc)
 

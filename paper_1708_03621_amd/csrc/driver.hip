@@ -147,6 +147,9 @@ struct dpp_system_s {
     // launch choices: fixed layout choices, and the ones dpp_system_tune times
     bool reg_xpass = true;  // register-resident x pass of H where S0 is compiled in
     bool reg_planes = true; // register plane passes (digit-reversed planes) for square y-z faces
+    int xc = DPP_XC_LDA_PZ81;      // exchange-correlation functional of the SCF
+    void* gga_ws = nullptr;        // PBE workspace (largest cell) and a scratch energy
+    double* d_gga_scratch = nullptr;
     int rot_pt = 0;         // rotate point tiles per wave (0: by launch size)
     int ov_mode = 0;        // overlap launch shape (0 chunked 2x2 blocks, 1 chunked single tiles, 2 single pass)
     std::string tune_report;
@@ -546,12 +549,24 @@ dpp_status fill(dpp_system_s* s, double* p, int64_t n, double v) {
 }
 
 // ----------------------------------------------------- fields and energies --
+// v_xc[n] of every cell (and E_xc into E[c * E_STRIDE] when E is given):
+// LDA for all cells in one launch, PBE per cell on the cell's full box.
+dpp_status xc_cells(dpp_system_s* s, const double* n, double* E) {
+    if (s->xc == DPP_XC_LDA_PZ81) return lda_cells(s->ctx, s->d_cells, s->ncells, n, s->vxc, s->d_cred, E, E_STRIDE);
+    for (int c = 0; c < s->ncells; ++c) {
+        const CellHost& ch = s->cells[c];
+        double* Ec = E ? E + (int64_t)c * E_STRIDE : s->d_gga_scratch;
+        DPP_TRY(gga_pbe(ch.grid, n + ch.foff, s->vxc + ch.foff, Ec, s->gga_ws));
+    }
+    return DPP_OK;
+}
+
 // V_eff = V_loc + V_H[n] + v_xc[n] for every cell.
 dpp_status potentials(dpp_system_s* s, const double* n) {
     // the potentials only: the energies are those of the output density
     DPP_TRY(hartree_batched(s->ctx, s->d_box, s->h_box, n, s->VH, s->Tplanes, s->d_epart, s->d_cells, nullptr,
                             E_STRIDE));
-    DPP_TRY(lda_cells(s->ctx, s->d_cells, s->ncells, n, s->vxc, s->d_cred, nullptr, E_STRIDE));
+    DPP_TRY(xc_cells(s, n, nullptr));
     TimerScope ts_(s->ctx, DPP_TK_FIELDS);
     hipLaunchKernelGGL(k_grid_lin3, dim3((unsigned)((s->Ntot + 255) / 256)), dim3(256), 0, stream(s), s->Ntot, 1.0,
                        s->Vloc, 1.0, s->VH, 1.0, s->vxc, s->Veff);
@@ -566,7 +581,7 @@ dpp_status potentials(dpp_system_s* s, const double* n) {
 dpp_status energies(dpp_system_s* s, int nbo, const double2* psi, const double* n, bool with_vh = true) {
     DPP_TRY(hartree_batched(s->ctx, s->d_box, s->h_box, n, with_vh ? s->VH : nullptr, s->Tplanes, s->d_epart,
                             s->d_cells, s->d_E + EH, E_STRIDE));
-    DPP_TRY(lda_cells(s->ctx, s->d_cells, s->ncells, n, s->vxc, s->d_cred, s->d_E + EXC, E_STRIDE));
+    DPP_TRY(xc_cells(s, n, s->d_E + EXC));
     DPP_TRY(dot_cells(s->ctx, s->d_cells, s->ncells, s->Vloc, n, s->d_cred, s->d_E + ELOC, E_STRIDE));
     {
         TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
@@ -1609,6 +1624,32 @@ extern "C" dpp_status dpp_system_set_launch_choice(dpp_system s, int which, int 
         default:
             return set_error(DPP_EINVAL, "dpp_system_set_launch_choice: unknown choice");
     }
+    for (ScfGraph& g : s->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_system_set_xc(dpp_system s, int functional) {
+    clear_error();
+    DPP_REQUIRE(s, "dpp_system_set_xc: null system");
+    DPP_REQUIRE(functional == DPP_XC_LDA_PZ81 || functional == DPP_XC_PBE, "dpp_system_set_xc: unknown functional");
+    if (functional == DPP_XC_PBE && !s->gga_ws) {
+        size_t bytes = 0;
+        for (const CellHost& ch : s->cells) {
+            size_t b = 0;
+            DPP_TRY(dpp_gga_workspace_size(ch.grid, &b));
+            bytes = std::max(bytes, b);
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes + 256) != hipSuccess) return set_error(DPP_ENOMEM, "dpp_system_set_xc: allocation failed");
+        s->allocs.push_back(p);
+        s->gga_ws = p;
+        s->d_gga_scratch = reinterpret_cast<double*>(reinterpret_cast<char*>(p) + ((bytes + 255) / 256) * 256);
+    }
+    s->xc = functional;
+    s->vx_dirty = true;
+    // captured SCF graphs hold the previous functional's launches
     for (ScfGraph& g : s->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     s->graphs.clear();

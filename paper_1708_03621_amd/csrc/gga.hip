@@ -208,6 +208,10 @@ extern "C" dpp_status dpp_gga_workspace_size(dpp_grid grid, size_t* bytes) {
 extern "C" dpp_status dpp_gga_pbe(dpp_grid grid, const double* d_n, double* d_vxc, double* d_Exc, void* ws) {
     clear_error();
     DPP_REQUIRE(grid && d_n && d_vxc && d_Exc && ws, "dpp_gga_pbe: null argument");
+    return gga_pbe(grid, d_n, d_vxc, d_Exc, ws);
+}
+
+dpp_status dpp::gga_pbe(dpp_grid_s* grid, const double* d_n, double* d_vxc, double* d_Exc, void* ws) {
     hipStream_t st = grid->ctx->stream;
     TimerScope ts_(grid->ctx, DPP_TK_FIELDS);
     const int64_t N = grid->N;

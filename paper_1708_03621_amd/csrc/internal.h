@@ -187,6 +187,9 @@ dpp_status full_inverse_real(dpp_grid_s* g, const double2* coef, double* out, vo
 dpp_status ham_set_positions(dpp_ham_s* h, int nat, const double* tau, const int* has_proj);
 // y = J n (natural order) of a real field on the grid's box; ws: N complex.
 dpp_status full_forward_real(dpp_grid_s* g, const double* n, double2* y, void* ws);
+// PBE v_xc and E_xc of a real density on the grid's box (gga.hip); ws:
+// dpp_gga_workspace_size bytes.
+dpp_status gga_pbe(dpp_grid_s* g, const double* n, double* vxc, double* Exc, void* ws);
 // Full-box complex transforms of nf fields (stride N): y = scale * sum_r x e^{sign i G.r}
 // (natural order; x may equal y), one launch per pass for all fields; ws: nf N complex.
 dpp_status full_complex(dpp_grid_s* g, int nf, const double2* x, double2* y, int sign, double scale, void* ws);

@@ -102,6 +102,7 @@ SIGNATURES = {
     "dpp_pcm_workspace_size": [_vp, C.POINTER(C.c_size_t)],
     "dpp_gga_workspace_size": [_vp, C.POINTER(C.c_size_t)],
     "dpp_gga_pbe": [_vp, _vp, _vp, _vp, _vp],
+    "dpp_system_set_xc": [_vp, _i],
     "dpp_pcm_solve": [_vp, _vp, _vp, C.c_double, _i, _vp, _dp, C.POINTER(C.c_int), _dp, _vp],
     "dpp_lda_pz81": [_vp, _vp, _vp, _vp, _vp],
     "dpp_local_potential": [_vp, _i, _dp, _dp, _dp, _vp, _vp],
@@ -387,6 +388,13 @@ def dpp_gga_workspace_size(grid):
 
 def dpp_gga_pbe(grid, d_n, d_vxc, d_Exc, ws):
     _call("dpp_gga_pbe", grid, _ptr(d_n), _ptr(d_vxc), _ptr(d_Exc), _ptr(ws))
+
+
+DPP_XC_LDA_PZ81, DPP_XC_PBE = 0, 1
+
+
+def dpp_system_set_xc(sys_, functional):
+    _call("dpp_system_set_xc", sys_, int(functional))
 
 
 def dpp_lda_pz81(grid, d_n, d_vxc, d_Exc, ws):
