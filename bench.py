@@ -420,6 +420,29 @@ def pcm_timing(D, W, ctx, torch, reps=3):
             "note": "4 full-box FP64 transforms per CG iteration; one host readback per iteration"}
 
 
+def gga_timing(D, W, ctx, torch, reps=10):
+    """PBE exchange-correlation (v_xc and E_xc) of a superposition of atomic
+    Gaussians (width 1 bohr) on config 3's 90^3 box: one warm-up call, then
+    `reps` timed calls."""
+    cell = W.config3()
+    g = D.dpp_grid_create(ctx, cell.R, cell.S)
+    ws = torch.empty(D.dpp_gga_workspace_size(g), dtype=torch.uint8, device="cuda:0")
+    n = torch.from_numpy(W.gaussians_on_box(cell.R, cell.S, cell.tau, cell.Z.astype(float), W.START_SIGMA)).to("cuda:0")
+    v = torch.empty_like(n)
+    E = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    D.dpp_gga_pbe(g, n, v, E, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        D.dpp_gga_pbe(g, n, v, E, ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    D.dpp_grid_destroy(g)
+    return {"case": "config 3's atoms as Gaussian densities, 90^3", "ms_per_call": ms, "E_xc_Ha": float(E.cpu()[0]),
+            "note": "gradient, pointwise PBE with dual-number derivatives, divergence: 6 full-box FP64 transform "
+                    "launches (two-field batches)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -435,7 +458,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (default launch rules)")
     ap.add_argument("--pmc-probe", choices=["apply_H", "copy"], help="run a short loop for counter collection")
     ap.add_argument("--pmc-prec", choices=["f64", "mixed"], default="f64", help="system precision of the probe")
-    ap.add_argument("--pcm-only", action="store_true", help="time only the LinearPCM solve (90^3) and print it")
+    ap.add_argument("--pcm-only", action="store_true",
+                    help="time only the LinearPCM solve and the PBE functional (90^3) and print them")
     ap.add_argument("--net-only", action="store_true",
                     help="time only the learned-start network's training (config-5 box) and print it")
     args = ap.parse_args()
@@ -453,7 +477,8 @@ def main():
         import workloads as W
         from paper_1708_03621_amd import dftpp as D
         ctx = D.dpp_ctx_create(0, torch.cuda.current_stream().cuda_stream)
-        print(json.dumps({"pcm": pcm_timing(D, W, ctx, torch)}), flush=True)
+        print(json.dumps({"pcm": pcm_timing(D, W, ctx, torch), "gga_pbe": gga_timing(D, W, ctx, torch)}),
+              flush=True)
         return
     if args.net_only:
         import torch
@@ -530,6 +555,8 @@ def main():
     net = net_training(D, W, ctx, torch)
     log("LinearPCM solve on the 90^3 cluster case")
     pcm = pcm_timing(D, W, ctx, torch)
+    log("PBE exchange-correlation on config 3's box")
+    gga_t = gga_timing(D, W, ctx, torch)
 
     others = {}
     if not args.no_others:
@@ -589,6 +616,7 @@ def main():
         "forces": forces,
         "net_training": net,
         "pcm": pcm,
+        "gga_pbe": gga_t,
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu

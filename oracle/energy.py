@@ -11,6 +11,8 @@ of U_k = Y_k^dag O Y_k (Sec. 2.1, integrals as dot products with O).
   energies  E_kin = sum_k w_k sum_i f_ki (Omega/2) sum_G |k+G|^2 |psi_Gi|^2
             E_nl  = sum_k w_k sum_i f_ki D sum_a |(P_k^dag psi_ki)_a|^2
             E_loc = (Omega/N) sum_j V_loc,j n_j;  E_xc = (Omega/N) sum_j n_j eps_xc
+            (LDA PZ81, oracle/xc.py; with System.xc = "pbe" E_xc and v_xc
+            come from oracle/gga.py)
             E_el  = E_kin + E_nl + E_loc + E_H + E_xc   (ion-ion excluded)
   gradient  with equal fillings f on the minimized block (energy invariant
             under Y -> Y M), dE/dY_k^dag = w_k f (H_k Y - O Y U^{-1} Y^dag H_k Y) U^{-1},

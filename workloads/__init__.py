@@ -284,7 +284,7 @@ PCM_EPS_B, PCM_NC, PCM_SIGMA = 78.4, 7e-4, 0.6
 PCM_ION_WIDTH, PCM_EL_WIDTH = 0.6, 1.0
 
 
-def _gaussians_on_box(R, S, tau, q, width):
+def gaussians_on_box(R, S, tau, q, width):
     """sum_a q_a exp(-|r - tau_a|^2 / (2 w^2)) / (2 pi w^2)^(3/2), minimum image."""
     R = np.asarray(R, float)
     grids = np.meshgrid(*[np.arange(s) / s for s in S], indexing="ij")
@@ -326,8 +326,8 @@ def pcm_case(kind: str = "small"):
         Z = np.full(len(tau), 4.0)
     else:
         raise ValueError(kind)
-    n = _gaussians_on_box(R, S, tau, Z, PCM_EL_WIDTH)
+    n = gaussians_on_box(R, S, tau, Z, PCM_EL_WIDTH)
     s = 0.5 * erfc(np.log(np.maximum(n, 1e-300) / PCM_NC) / (PCM_SIGMA * np.sqrt(2.0)))
     eps = 1.0 + (PCM_EPS_B - 1.0) * s
-    rho = _gaussians_on_box(R, S, tau, Z, PCM_ION_WIDTH) - n
+    rho = gaussians_on_box(R, S, tau, Z, PCM_ION_WIDTH) - n
     return dict(R=np.asarray(R, float), S=tuple(S), tau=tau, Z=Z, n=n, eps=eps, rho=rho)
