@@ -9,7 +9,10 @@ with variational minimization.  One iteration, for input density n_in:
      H~ V = V diag(eps), Y <- psi V
   4. aufbau fillings over all (k, band) states, each holding 2 w_k
      electrons; a degenerate set (|d eps| < 1e-6 Ha) straddling the Fermi
-     level shares the remaining electrons equally
+     level shares the remaining electrons equally.  With a smearing width
+     sigma instead Fermi-Dirac fillings 2 / (1 + exp((eps - mu) / sigma)),
+     mu by bisection on the electron count, and the reported energy is the
+     free energy E - sigma S (Table 1: smearing for metals)
   5. n_out from psi and the fillings; E_el evaluated with n_out
   6. Pulay (DIIS) mixing of n_in: history 8, alpha 0.5, first iteration
      linear n_in + alpha (n_out - n_in); later the residual combination
@@ -56,6 +59,47 @@ def aufbau_fillings(eigs, wk, n_electrons: float, tol: float = DEGEN_TOL):
     return fills
 
 
+SMEAR_BRACKET = 40.0   # bisection bracket: [min eps - 40 sigma, max eps + 40 sigma]
+SMEAR_ITERS = 200      # bisection halvings (the bracket stops shrinking in FP64 well before)
+
+
+def fermi_fillings(eigs, wk, n_electrons: float, sigma: float):
+    """Fermi-Dirac fillings of width sigma (hartree), spin-unpolarized:
+    f = 2 / (1 + exp((eps - mu) / sigma)) with mu by bisection so that
+    sum_k w_k sum_i f_ki = N_e.  Returns (fills per k, mu, S) with the entropy
+    S = -2 sum_k w_k sum_i [g ln g + (1 - g) ln(1 - g)], g = f / 2; the SCF
+    reports the free energy E - sigma S."""
+    e = [np.asarray(ek, float) for ek in eigs]
+    lo = min(float(ek.min()) for ek in e) - SMEAR_BRACKET * sigma
+    hi = max(float(ek.max()) for ek in e) + SMEAR_BRACKET * sigma
+    cap = sum(2.0 * wk[k] * len(ek) for k, ek in enumerate(e))
+    if cap < n_electrons - 1e-9:
+        raise ValueError("not enough bands for the electron count")
+
+    def count(mu):  # exp overflows to inf far above mu: those states hold 0
+        with np.errstate(over="ignore"):
+            return sum(float(np.sum(2.0 * wk[k] / (1.0 + np.exp((ek - mu) / sigma)))) for k, ek in enumerate(e))
+
+    for _ in range(SMEAR_ITERS):
+        mid = 0.5 * (lo + hi)
+        if count(mid) < n_electrons:
+            lo = mid
+        else:
+            hi = mid
+    mu = 0.5 * (lo + hi)
+    fills, S = [], 0.0
+    for k, ek in enumerate(e):
+        x = (ek - mu) / sigma
+        with np.errstate(over="ignore"):
+            g = 1.0 / (1.0 + np.exp(x))       # occupation per spin
+            gc = 1.0 / (1.0 + np.exp(-x))     # 1 - g without cancellation
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = np.where(g > 0, g * np.log(g), 0.0) + np.where(gc > 0, gc * np.log(gc), 0.0)
+        S -= 2.0 * wk[k] * float(np.sum(t))
+        fills.append(2.0 * g)
+    return fills, mu, S
+
+
 class Pulay:
     def __init__(self, omega: float, N: int, alpha: float = 0.5, history: int = 8):
         self.alpha = alpha
@@ -95,11 +139,15 @@ def subspace_rotate(Y, b, Veff, P, D):
     return psi @ V, eps
 
 
-def scf(sys, Ys, n_in, n_iter: int, n_inner: int = 3, callback=None, etol_per_atom=None, n_inner_first=None):
+def scf(sys, Ys, n_in, n_iter: int, n_inner: int = 3, callback=None, etol_per_atom=None, n_inner_first=None,
+        smearing=None):
     """Run protocol S; returns dict with energies per iteration, final Y, eigs, n.
 
     n_inner_first (default n_inner): band-CG steps of the first iteration, so
-    that the bands can be converged in the start potential before mixing."""
+    that the bands can be converged in the start potential before mixing.
+    smearing (hartree, default none): Fermi-Dirac fillings of that width
+    instead of aufbau; the energies are then the free energies E - sigma S,
+    and the result carries mu, the entropy term sigma S and the fillings."""
     Ys = [y.copy() for y in Ys]
     pulay = Pulay(sys.omega, sys.N)
     energies = []
@@ -116,11 +164,16 @@ def scf(sys, Ys, n_in, n_iter: int, n_inner: int = 3, callback=None, etol_per_at
             new_Y.append(Yk)
             eigs.append(ek)
         Ys = new_Y
-        fills = aufbau_fillings(eigs, sys.wk, sys.n_electrons)
+        TS, mu = 0.0, None
+        if smearing:
+            fills, mu, S = fermi_fillings(eigs, sys.wk, sys.n_electrons, smearing)
+            TS = smearing * S
+        else:
+            fills = aufbau_fillings(eigs, sys.wk, sys.n_electrons)
         n_out = density(Ys, fills, sys)
         _, parts = potentials(n_out, sys)
         Ekin, Enl = band_energies(Ys, fills, sys)
-        E = Ekin + Enl + parts["E_loc"] + parts["E_H"] + parts["E_xc"]
+        E = Ekin + Enl + parts["E_loc"] + parts["E_H"] + parts["E_xc"] - TS
         energies.append(E)
         if callback is not None:
             callback(it, E, eigs, n_out)
@@ -128,4 +181,5 @@ def scf(sys, Ys, n_in, n_iter: int, n_inner: int = 3, callback=None, etol_per_at
         n_in = pulay.mix(n_in, n_out)
         if etol_per_atom is not None and it > 0 and abs(energies[-1] - energies[-2]) < etol_per_atom * sys.nat:
             break
-    return dict(energies=energies, Y=Ys, eigs=eigs, n_out=n_out, n_in=n_in, Veff=Veff_last)
+    return dict(energies=energies, Y=Ys, eigs=eigs, n_out=n_out, n_in=n_in, Veff=Veff_last, fills=fills, mu=mu,
+                TS=TS)
