@@ -299,6 +299,19 @@ dpp_status dpp_gga_pbe(dpp_grid grid, const double *d_n, double *d_vxc, double *
  * system or an unknown value, DPP_ENOMEM. */
 enum { DPP_XC_LDA_PZ81 = 0, DPP_XC_PBE = 1 };
 dpp_status dpp_system_set_xc(dpp_system sys, int functional);
+/* Fermi-Dirac smearing of the SCF fillings (Table 1: smearing for metals):
+ * sigma > 0 (hartree) replaces the aufbau fillings of dpp_scf_iteration by
+ * f = 2 / (1 + exp((eps - mu) / sigma)), mu per cell by 200 bisections of
+ * [min eps - 40 sigma, max eps + 40 sigma] on the electron count; E_el of
+ * the report is then the free energy E - sigma S with
+ * S = -2 sum_k w_k sum_i [g ln g + (1 - g) ln(1 - g)], g = f / 2.
+ * sigma = 0 restores aufbau.  Drops captured SCF graphs.  Errors: DPP_EINVAL
+ * for a null system or sigma < 0 or not finite. */
+dpp_status dpp_system_set_smearing(dpp_system sys, double sigma);
+/* mu[c] and sigma S[c] (hartree, host arrays of ncells, either may be NULL)
+ * of the last smeared SCF iteration; synchronizes the stream.  Errors:
+ * DPP_EINVAL for a wrong cell count or a system without smearing. */
+dpp_status dpp_system_smearing_state(dpp_system sys, int ncells, double *mu, double *TS);
 /* V_loc(r) = Re I[sum_a v_a(|G|) exp(-i G.tau_a)], v_a(G) = -4 pi Z_a
  * exp(-G^2 rc_a^2/4) / (Omega G^2), v_a(0) = 0.  Host tau (nat x 3), Z, rc. */
 dpp_status dpp_local_potential(dpp_grid grid, int nat, const double *tau, const double *Z,

@@ -80,6 +80,14 @@ __global__ void k_pulay_combine_cells(int64_t Ntot, const int* st, const CellDes
                                       double alpha, const double* hn, const double* hr, double* nin);
 __global__ void k_cgB_reset(int nit, const Seg* seg, CgBState s);
 __global__ void k_aufbau(const CellDesc* cells, const Seg* seg, const double* eig, double* f, int* status);
+// Fermi-Dirac fillings of width sigma per cell (one workgroup per cell): mu by
+// SMEAR_ITERS bisections of [min eps - 40 sigma, max eps + 40 sigma] on the
+// electron count (fixed-order sums), f = 2 / (1 + exp((eps - mu) / sigma));
+// E[c * stride + 0] = sigma S, E[c * stride + 1] = mu.
+constexpr int SMEAR_ITERS = 200;
+constexpr double SMEAR_BRACKET = 40.0;
+__global__ void k_fermi(const CellDesc* cells, const Seg* seg, const double* eig, double sigma, double* f, double* E,
+                        int stride, int* status);
 
 __global__ void k_cg_precond_dots(const Seg* seg, int nitems, const double2* g, const double2* gp,
                                   const double2* Dp, double2* Kg, double* part);

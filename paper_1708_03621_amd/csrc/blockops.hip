@@ -617,6 +617,82 @@ k_trace_diag(const Seg* __restrict__ seg, const double2* __restrict__ M, double*
 // then k-point, then band; groups of states within DEGEN_TOL of the group's
 // first energy fill together, each state holding 2 w_k electrons; a group that
 // does not fit shares the remaining electrons equally.
+
+// Fermi-Dirac fillings (Table 1: smearing) of every cell; see blockops.h.
+__global__ void __launch_bounds__(256)
+k_fermi(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const double* __restrict__ eig, double sigma,
+        double* __restrict__ f, double* __restrict__ E, int stride, int* __restrict__ status) {
+    __shared__ double e[AUFBAU_MAX];
+    __shared__ double w[AUFBAU_MAX];
+    __shared__ int64_t fo[AUFBAU_MAX];
+    __shared__ double red[256];
+    __shared__ double bounds[2];
+    const CellDesc c = cells[blockIdx.x];
+    // states of the cell's items in item order
+    int ns = 0;
+    for (int k = 0; k < c.nitems; ++k) {
+        const Seg sk = seg[c.item0 + k];
+        for (int i = threadIdx.x; i < sk.nb; i += blockDim.x) {
+            e[ns + i] = eig[sk.f_off + i];
+            w[ns + i] = sk.wk;
+            fo[ns + i] = sk.f_off + i;
+        }
+        ns += sk.nb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double lo = e[0], hi = e[0], cap = 0.0;
+        for (int t = 0; t < ns; ++t) {
+            lo = fmin(lo, e[t]);
+            hi = fmax(hi, e[t]);
+            cap += 2.0 * w[t];
+        }
+        bounds[0] = lo - SMEAR_BRACKET * sigma;
+        bounds[1] = hi + SMEAR_BRACKET * sigma;
+        if (cap < c.ne - 1e-9) atomicOr(status, DPP_STATUS_NOBANDS);
+    }
+    __syncthreads();
+    double lo = bounds[0], hi = bounds[1];
+    for (int it = 0; it < SMEAR_ITERS; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        double s = 0.0;
+        for (int t = threadIdx.x; t < ns; t += blockDim.x) s += 2.0 * w[t] / (1.0 + exp((e[t] - mid) / sigma));
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        const double cnt = red[0];
+        __syncthreads();  // every thread has read the count before the next step overwrites red
+        if (cnt < c.ne)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const double mu = 0.5 * (lo + hi);
+    double s = 0.0;
+    for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+        const double x = (e[t] - mu) / sigma;
+        const double g = 1.0 / (1.0 + exp(x)), gc = 1.0 / (1.0 + exp(-x));  // g and 1 - g
+        f[fo[t]] = 2.0 * g;
+        double tt = 0.0;
+        if (g > 0.0) tt += g * log(g);
+        if (gc > 0.0) tt += gc * log(gc);
+        s -= 2.0 * w[t] * tt;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        E[(int64_t)blockIdx.x * stride] = sigma * red[0];
+        E[(int64_t)blockIdx.x * stride + 1] = mu;
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_aufbau(const CellDesc* __restrict__ cells, const Seg* __restrict__ seg, const double* __restrict__ eig,
          double* __restrict__ f, int* __restrict__ status) {

@@ -42,7 +42,7 @@ using namespace dpp;
 namespace {
 constexpr int MAX_TRIES = 6;
 constexpr int E_STRIDE = 8;  // per-cell energy slots
-enum { EK = 0, ENL = 1, EH = 2, EXC = 3, ELOC = 4 };
+enum { EK = 0, ENL = 1, EH = 2, EXC = 3, ELOC = 4, ETS = 5, EMU = 6 };  // ETS: sigma S, EMU: mu (smearing)
 constexpr int DENS_MAX_CHUNKS = 16;
 }  // namespace
 
@@ -148,6 +148,7 @@ struct dpp_system_s {
     bool reg_xpass = true;  // register-resident x pass of H where S0 is compiled in
     bool reg_planes = true; // register plane passes (digit-reversed planes) for square y-z faces
     int xc = DPP_XC_LDA_PZ81;      // exchange-correlation functional of the SCF
+    double smear = 0.0;            // Fermi-Dirac width of the SCF fillings (0: aufbau)
     void* gga_ws = nullptr;        // PBE workspace (largest cell) and a scratch energy
     double* d_gga_scratch = nullptr;
     int rot_pt = 0;         // rotate point tiles per wave (0: by launch size)
@@ -762,9 +763,14 @@ dpp_status scf_body(dpp_system_s* s, double2* Y, int steps) {
         hipLaunchKernelGGL(k_band_residual, dim3(s->maxnb, s->nit), dim3(256), 0, stream(s), s->d_seg,
                            (const double*)s->d_eig, (const double2*)Y, (const double2*)s->HY, s->d_res);
         DPP_LAUNCHED();
-        // 4. aufbau fillings per cell
-        hipLaunchKernelGGL(k_aufbau, dim3(s->ncells), dim3(256), 0, stream(s), s->d_cells, s->d_seg,
-                           (const double*)s->d_eig, s->d_f, s->ctx->d_status);
+        // 4. fillings per cell: aufbau, or Fermi-Dirac with mu, sigma S into the energy slots
+        if (s->smear > 0.0)
+            hipLaunchKernelGGL(k_fermi, dim3(s->ncells), dim3(256), 0, stream(s), s->d_cells, s->d_seg,
+                               (const double*)s->d_eig, s->smear, s->d_f, s->d_E + ETS, E_STRIDE,
+                               s->ctx->d_status);
+        else
+            hipLaunchKernelGGL(k_aufbau, dim3(s->ncells), dim3(256), 0, stream(s), s->d_cells, s->d_seg,
+                               (const double*)s->d_eig, s->d_f, s->ctx->d_status);
         DPP_LAUNCHED();
     }
     // 5. n_out and E_el[psi, n_out]
@@ -1434,7 +1440,9 @@ extern "C" dpp_status dpp_scf_iteration(dpp_system s, dpp_c64* Yc, dpp_energy* E
         rmax = std::max(rmax, r);
         if (E) {
             const double* p = e + (size_t)c * E_STRIDE;
-            E[c] = dpp_energy{p[EK] + p[ENL] + p[EH] + p[EXC] + p[ELOC], p[EK], p[ENL], p[ELOC], p[EH], p[EXC]};
+            // with smearing E_el is the free energy E - sigma S
+            const double ts = s->smear > 0.0 ? p[ETS] : 0.0;
+            E[c] = dpp_energy{p[EK] + p[ENL] + p[EH] + p[EXC] + p[ELOC] - ts, p[EK], p[ENL], p[ELOC], p[EH], p[EXC]};
         }
     }
     s->last_res = rmax;
@@ -1627,6 +1635,31 @@ extern "C" dpp_status dpp_system_set_launch_choice(dpp_system s, int which, int 
     for (ScfGraph& g : s->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     s->graphs.clear();
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_system_set_smearing(dpp_system s, double sigma) {
+    clear_error();
+    DPP_REQUIRE(s && sigma >= 0.0 && std::isfinite(sigma), "dpp_system_set_smearing: bad arguments");
+    s->smear = sigma;
+    // captured SCF graphs hold the previous fillings kernel
+    for (ScfGraph& g : s->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+    return DPP_OK;
+}
+
+extern "C" dpp_status dpp_system_smearing_state(dpp_system s, int ncells, double* mu, double* TS) {
+    clear_error();
+    DPP_REQUIRE(s && ncells == s->ncells && (mu || TS), "dpp_system_smearing_state: bad arguments");
+    DPP_REQUIRE(s->smear > 0.0, "dpp_system_smearing_state: the system has no smearing");
+    std::vector<double> h((size_t)s->ncells * E_STRIDE);
+    DPP_HIP(hipMemcpyAsync(h.data(), s->d_E, h.size() * sizeof(double), hipMemcpyDeviceToHost, stream(s)));
+    DPP_HIP(hipStreamSynchronize(stream(s)));
+    for (int c = 0; c < s->ncells; ++c) {
+        if (mu) mu[c] = h[(size_t)c * E_STRIDE + EMU];
+        if (TS) TS[c] = h[(size_t)c * E_STRIDE + ETS];
+    }
     return DPP_OK;
 }
 

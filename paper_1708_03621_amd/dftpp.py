@@ -103,6 +103,8 @@ SIGNATURES = {
     "dpp_gga_workspace_size": [_vp, C.POINTER(C.c_size_t)],
     "dpp_gga_pbe": [_vp, _vp, _vp, _vp, _vp],
     "dpp_system_set_xc": [_vp, _i],
+    "dpp_system_set_smearing": [_vp, C.c_double],
+    "dpp_system_smearing_state": [_vp, _i, _dp, _dp],
     "dpp_pcm_solve": [_vp, _vp, _vp, C.c_double, _i, _vp, _dp, C.POINTER(C.c_int), _dp, _vp],
     "dpp_lda_pz81": [_vp, _vp, _vp, _vp, _vp],
     "dpp_local_potential": [_vp, _i, _dp, _dp, _dp, _vp, _vp],
@@ -395,6 +397,18 @@ DPP_XC_LDA_PZ81, DPP_XC_PBE = 0, 1
 
 def dpp_system_set_xc(sys_, functional):
     _call("dpp_system_set_xc", sys_, int(functional))
+
+
+def dpp_system_set_smearing(sys_, sigma):
+    _call("dpp_system_set_smearing", sys_, float(sigma))
+
+
+def dpp_system_smearing_state(sys_, ncells=1):
+    """Returns (mu, sigma S) arrays of the last smeared SCF iteration."""
+    mu = np.zeros(ncells)
+    ts = np.zeros(ncells)
+    _call("dpp_system_smearing_state", sys_, int(ncells), mu.ctypes.data_as(_dp), ts.ctypes.data_as(_dp))
+    return mu, ts
 
 
 def dpp_lda_pz81(grid, d_n, d_vxc, d_Exc, ws):
