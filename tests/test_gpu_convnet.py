@@ -119,7 +119,13 @@ def test_learned_start_small(dev):
     converged in every SCF iteration (8 band-CG steps, 30 in the first).  The
     trained network must reduce the start-density error, both starts must
     converge (two energy changes below 1e-10 Ha/atom), and their converged
-    energies must agree within 1e-6 Ha/atom."""
+    energies must agree within 1e-6 Ha/atom.
+
+    The saving in SCF iterations is not asserted here: single displaced cells
+    range from 76 iterations slower to 65 faster, so four held-out cells
+    cannot resolve the mean gain (this run: 20.75 plain, 23.0 learned).  The
+    gain is measured over 64 held-out cells by learned.py (mean 27.1 -> 23.1,
+    median 22.5 -> 16.0, 45 of 64 faster, one-sided sign test p = 2.5e-4)."""
     log("learned start: 24 train, 4 eval")
     from paper_1708_03621_amd import learned
     res = learned.run(n_train=24, n_eval=4, epochs=30, batch=8, lr=2e-3, n_inner=8, n_inner_first=30, max_iter=400,
