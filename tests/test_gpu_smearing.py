@@ -70,3 +70,52 @@ def test_tiny_width_reproduces_aufbau(dev):
     log(f"aufbau {Ea} smeared {Es} TS {ts[0]:.2e}")
     assert np.max(np.abs(np.array(Ea) - np.array(Es))) / cell.nat < 1e-8
     assert np.max(np.abs(ea - es)) < 1e-7
+
+
+def test_forces_are_free_energy_derivatives_at_level_crossing(dev):
+    """The two-atom cell at 3.35 bohr, inside the window where the highest
+    filled and lowest empty levels cross and the aufbau SCF does not settle.
+    With two empty bands (6 bands, 8 electrons) and sigma = 0.01 Ha the SCF
+    converges (within 35 iterations here; the two crossing levels, 4 mHa
+    apart, share two electrons), and the force on the ions equals the central
+    difference of the converged free energy E - sigma S + E_ion
+    (Hellmann-Feynman for the smeared functional: the fillings are
+    stationary), to the difference's O(h^2) truncation."""
+    sig, h, nit = 0.01, 2e-3, 80
+    u = np.array([2.4, 1.5, 0.4]) / np.linalg.norm([2.4, 1.5, 0.4])
+    mid = np.array([3.4, 3.35, 3.2])
+    tau0 = np.stack([mid - 1.675 * u, mid + 1.675 * u])
+
+    def cell_at(tau):
+        c = W.tiny_cell(nat=2, L=7.0, ecut=4.0, S=(16, 16, 16), nb=6, Z=(4, 4), seed=11)
+        c.tau = np.array(tau, float)
+        return c
+
+    def converged(tau, with_forces=False):
+        c = cell_at(tau)
+        sysg, off, npw = make_gpu_system(dev, c)
+        dev.D.dpp_system_set_smearing(sysg, sig)
+        Y, _ = packed_Y(dev, c, npw)
+        dev.D.dpp_scf_init(sysg, c.tau, c.Z, W.START_SIGMA)
+        Es = []
+        for _ in range(nit):
+            E, _ = dev.D.dpp_scf_iteration(sysg, Y, 1, c.nb)
+            Es.append(E["E_el"])
+        F = [dev.zeros((2, 3), dev.torch.float64) for _ in range(3)]
+        Eion = dev.D.dpp_system_forces(sysg, Y, F[0], F[1], F[2], 1)[0]
+        Ftot = sum(dev.host(f) for f in F)
+        fills = dev.D.dpp_system_fillings(sysg, 1, c.nb)
+        dev.D.dpp_system_destroy(sysg)
+        assert abs(Es[-1] - Es[-2]) < 1e-11, Es[-5:]
+        return Es[-1] + Eion, Ftot, fills
+
+    E0, F0, fills = converged(tau0)
+    log(f"fillings at 3.35 bohr: {fills}; F[0] {F0[0]}")
+    assert np.any((fills > 1e-3) & (fills < 2 - 1e-3))  # the levels near the Fermi level share electrons
+    for a, d in [(0, 0), (1, 2)]:
+        tp, tm = tau0.copy(), tau0.copy()
+        tp[a, d] += h
+        tm[a, d] -= h
+        fd = -(converged(tp)[0] - converged(tm)[0]) / (2 * h)
+        log(f"atom {a} dir {d}: fd {fd:.9f} force {F0[a, d]:.9f}")
+        assert abs(fd - F0[a, d]) < 2e-6
