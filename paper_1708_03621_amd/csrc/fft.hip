@@ -930,6 +930,269 @@ k_planes_to_box(const FftItem* items, FftItem single, const typename cx<T>::t* _
     }
 }
 
+// ------------------------------------------------ 90 x 90 plane passes ------
+// Square faces of 90 points (the 90^3 box) have dedicated LDS kernels.  Each
+// 90-point transform is split as 9 x 10 (n = n1 + 10 n2, k = 9 k1 + k2, so
+// w^(nk) = w10^(n1 k1) w^(n1 k2) w9^(n2 k2)):
+//   step A, per (transform, n1): 9-point DFT over n2 in registers, times
+//           w^(n1 k2), stored back to the slots n1 + 10 k2 it read;
+//   step B, per (transform, k2): 10-point DFT over n1 of those slots, giving
+//           X[9 k1 + k2], stored to slot k1 + 10 k2 (the slots it read).
+// Both steps touch only their own slots, so an axis costs two LDS round trips
+// and one barrier between them, against one round trip and two barriers per
+// radix stage in the generic kernel.  Step B leaves the axis permuted: natural
+// index i sits at slot p90_slot(i) = i / 9 + 10 (i mod 9).  The plane's first
+// step of the inverse direction reads the plane buffer directly, and the last
+// step of the forward direction writes it directly, in natural order.
+namespace p90 {
+constexpr int N = 90;
+constexpr int NT = 1024;
+
+__device__ __forceinline__ int slot(int i) { return i / 9 + 10 * (i - 9 * (i / 9)); }
+
+// 9-point DFT as 3 x 3: v[3p + q] -> rows q, 3-point DFTs over p, twiddles
+// w9^(q c), 3-point DFTs over q, X[c + 3d].
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft9(typename cx<T>::t* v) {
+    using C = typename cx<T>::t;
+    const T c1 = T(0.766044443118978), s1 = T(SIGN) * T(0.6427876096865393);
+    const T c2 = T(0.17364817766693041), s2 = T(SIGN) * T(0.984807753012208);
+    const T c4 = T(-0.9396926207859083), s4 = T(SIGN) * T(0.3420201433256689);
+    C a[3][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        a[q][0] = v[q];
+        a[q][1] = v[q + 3];
+        a[q][2] = v[q + 6];
+        Dft<T, 3>::run(a[q], SIGN);
+    }
+    a[1][1] = cmul(a[1][1], C{c1, s1});
+    a[1][2] = cmul(a[1][2], C{c2, s2});
+    a[2][1] = cmul(a[2][1], C{c2, s2});
+    a[2][2] = cmul(a[2][2], C{c4, s4});
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        C b[3] = {a[0][c], a[1][c], a[2][c]};
+        Dft<T, 3>::run(b, SIGN);
+        v[c] = b[0];
+        v[c + 3] = b[1];
+        v[c + 6] = b[2];
+    }
+}
+
+// 10-point DFT as 5 x 2: 5-point DFTs of the even and odd points, twiddles
+// w10^c on the odd ones, X[c] = e + o, X[c + 5] = e - o.
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft10(typename cx<T>::t* v) {
+    using C = typename cx<T>::t;
+    const T c1 = T(0.8090169943749475), s1 = T(SIGN) * T(0.5877852522924731);
+    const T c2 = T(0.30901699437494745), s2 = T(SIGN) * T(0.9510565162951535);
+    C e[5], o[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        e[p] = v[2 * p];
+        o[p] = v[2 * p + 1];
+    }
+    Dft<T, 5>::run(e, SIGN);
+    Dft<T, 5>::run(o, SIGN);
+    o[1] = cmul(o[1], C{c1, s1});
+    o[2] = cmul(o[2], C{c2, s2});
+    o[3] = cmul(o[3], C{-c2, s2});
+    o[4] = cmul(o[4], C{-c1, s1});
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        v[c] = cadd(e[c], o[c]);
+        v[c + 5] = csub(e[c], o[c]);
+    }
+}
+
+// Step A on the 9 values of one (transform, n1) task: DFT and twiddles.
+template <typename T, int SIGN>
+__device__ __forceinline__ void step_a(typename cx<T>::t* v, int n1, const double2* tw64, const float2* tw32) {
+    dft9<T, SIGN>(v);
+#pragma unroll
+    for (int k2 = 1; k2 < 9; ++k2) v[k2] = cmul(v[k2], twiddle<T>(tw64, tw32, n1 * k2, SIGN));
+}
+
+// Natural row i of the face lies in the plane's data rows [n1lo, n1lo + nrows) (mod 90).
+__device__ __forceinline__ bool row_in(int i, int n1lo, int nrows) {
+    int d = i - n1lo;
+    d += d < 0 ? N : 0;
+    d -= d >= N ? N : 0;
+    return d < nrows;
+}
+__device__ __forceinline__ int row_at(int f, int n1lo) {
+    int r = n1lo + f;
+    r += r < 0 ? N : 0;
+    r -= r >= N ? N : 0;
+    return r;
+}
+}  // namespace p90
+
+// Sphere -> 90 x 90 planes (sign +1): scatter, z along the data rows, y along
+// every column (rows without data read as zero), natural order out.
+template <typename T, typename TIO, bool BATCH = false>
+__global__ void __launch_bounds__(p90::NT)
+k_planes90_from_sphere(const FftItem* items, FftItem single, const TIO* __restrict__ C,
+                       typename cx<T>::t* __restrict__ Tb, const int* __restrict__ act,
+                       const int* __restrict__ idx) {
+    using Cx = typename cx<T>::t;
+    using namespace p90;
+    const int item = (BATCH && idx) ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (BATCH && act && !act[item]) return;
+    const FftItem& it = BATCH ? items[item] : single;
+    const int p = blockIdx.x, b = blockIdx.y;
+    if (p >= it.nplanes || b >= it.nb) return;
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int4 pl = it.planes[p];
+    const int t = threadIdx.x;
+    for (int i = t; i < pl.w * N; i += NT) {
+        const int f = i / N;
+        lds[row_at(f, pl.z) * N + (i - f * N)] = Cx{0, 0};
+    }
+    __syncthreads();
+    const TIO* src = C + it.c_off + (int64_t)b * it.ld + pl.x;
+    const int* poff = it.poff + pl.x;
+    for (int q = t; q < pl.y; q += NT) lds[poff[q]] = Io<T>::from(src[q]);
+    __syncthreads();
+    const double2* tz64 = it.tw64[2];
+    const float2* tz32 = it.tw32[2];
+    if (t < pl.w * 10) {  // z, step A: task (row f, n1)
+        const int f = t / 10, n1 = t - 10 * f;
+        Cx* row = lds + row_at(f, pl.z) * N;
+        Cx v[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = row[n1 + 10 * j];
+        step_a<T, +1>(v, n1, tz64, tz32);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) row[n1 + 10 * j] = v[j];
+    }
+    __syncthreads();
+    if (t < pl.w * 9) {  // z, step B: task (row f, k2); the row ends permuted
+        const int f = t / 9, k2 = t - 9 * f;
+        Cx* row = lds + row_at(f, pl.z) * N + 10 * k2;
+        Cx u[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) u[j] = row[j];
+        dft10<T, +1>(u);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) row[j] = u[j];
+    }
+    __syncthreads();
+    const double2* ty64 = it.tw64[1];
+    const float2* ty32 = it.tw32[1];
+    if (t < 10 * N) {  // y, step A: task (column slot c, n1)
+        const int n1 = t / N, c = t - N * n1;
+        Cx v[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int r = n1 + 10 * j;
+            v[j] = row_in(r, pl.z, pl.w) ? lds[r * N + c] : Cx{0, 0};
+        }
+        step_a<T, +1>(v, n1, ty64, ty32);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) lds[(n1 + 10 * j) * N + c] = v[j];
+    }
+    __syncthreads();
+    if (t < 9 * N) {  // y, step B: task (natural column z, k2), straight to the plane buffer
+        const int k2 = t / N, z = t - N * k2;
+        const int c = slot(z);
+        Cx u[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) u[j] = lds[(j + 10 * k2) * N + c];
+        dft10<T, +1>(u);
+        Cx* dst = Tb + it.t_off + ((int64_t)b * it.nplanes + p) * (N * N) + z;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) dst[(9 * j + k2) * N] = u[j];
+    }
+}
+
+// 90 x 90 planes -> sphere (sign -1): y along every column straight from the
+// plane buffer (rows end permuted), z along the data rows (slots end
+// permuted), then the gather of the sphere points as in k_planes_to_sphere.
+template <typename T, int MODE, typename TIO, bool BATCH = false>
+__global__ void __launch_bounds__(p90::NT)
+k_planes90_to_sphere(const FftItem* items, FftItem single, const typename cx<T>::t* __restrict__ Tb,
+                     const double2* __restrict__ Cin, TIO* __restrict__ out, int64_t ldout_override,
+                     const int* __restrict__ act, const int* __restrict__ idx) {
+    using Cx = typename cx<T>::t;
+    using namespace p90;
+    const int item = (BATCH && idx) ? idx[blockIdx.z] : (int)blockIdx.z;
+    if (BATCH && act && !act[item]) return;
+    const FftItem& it = BATCH ? items[item] : single;
+    const int p = blockIdx.x, b = blockIdx.y;
+    if (p >= it.nplanes || b >= it.nb) return;
+    extern __shared__ char smem_raw[];
+    Cx* lds = reinterpret_cast<Cx*>(smem_raw);
+    const int4 pl = it.planes[p];
+    const int t = threadIdx.x;
+    const double2* ty64 = it.tw64[1];
+    const float2* ty32 = it.tw32[1];
+    if (t < 10 * N) {  // y, step A: task (column c, n1), from the plane buffer
+        const int n1 = t / N, c = t - N * n1;
+        const Cx* src = Tb + it.t_off + ((int64_t)b * it.nplanes + p) * (N * N) + c;
+        Cx v[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = src[(n1 + 10 * j) * N];
+        step_a<T, -1>(v, n1, ty64, ty32);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) lds[(n1 + 10 * j) * N + c] = v[j];
+    }
+    __syncthreads();
+    if (t < 9 * N) {  // y, step B: task (column c, k2); natural row i at LDS row slot(i)
+        const int k2 = t / N, c = t - N * k2;
+        Cx u[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) u[j] = lds[(j + 10 * k2) * N + c];
+        dft10<T, -1>(u);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) lds[(j + 10 * k2) * N + c] = u[j];
+    }
+    __syncthreads();
+    const double2* tz64 = it.tw64[2];
+    const float2* tz32 = it.tw32[2];
+    if (t < pl.w * 10) {  // z, step A: task (data row f, n1)
+        const int f = t / 10, n1 = t - 10 * f;
+        Cx* row = lds + slot(row_at(f, pl.z)) * N;
+        Cx v[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = row[n1 + 10 * j];
+        step_a<T, -1>(v, n1, tz64, tz32);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) row[n1 + 10 * j] = v[j];
+    }
+    __syncthreads();
+    if (t < pl.w * 9) {  // z, step B: task (data row f, k2); natural z at slot(z)
+        const int f = t / 9, k2 = t - 9 * f;
+        Cx* row = lds + slot(row_at(f, pl.z)) * N + 10 * k2;
+        Cx u[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) u[j] = row[j];
+        dft10<T, -1>(u);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) row[j] = u[j];
+    }
+    __syncthreads();
+    const int64_t ld = ldout_override > 0 ? ldout_override : it.ld;
+    TIO* dst = out + it.c_off + (int64_t)b * ld + pl.x;
+    const int* poff = it.poff + pl.x;
+    for (int q = t; q < pl.y; q += NT) {
+        const int o = poff[q], i1 = o / N;
+        const double2 v = Io<T>::to_d(lds[slot(i1) * N + slot(o - N * i1)]);
+        if (MODE == G_H) {
+            const double2 c = Cin[it.c_off + (int64_t)b * it.ld + pl.x + q];
+            const double tk = 0.5 * it.omega * it.kG2[pl.x + q];
+            dst[q] = store_as<TIO>(double2{tk * c.x + v.x, tk * c.y + v.y});
+        } else if (MODE == G_ADD) {
+            const TIO w = dst[q];
+            dst[q] = store_as<TIO>(double2{(double)w.x + v.x, (double)w.y + v.y});
+        } else {
+            dst[q] = store_as<TIO>(v);
+        }
+    }
+}
+
 // ----------------------------------------------------------- launchers -----
 namespace {
 
@@ -977,6 +1240,10 @@ dpp_status set_lds(K kernel, size_t bytes) {
             return set_error(DPP_EUNSUPPORTED, "FFT tile too large for one workgroup"); \
     }
 
+// Faces the 90 x 90 kernels take: square 90-point faces in natural order.
+bool plane90(const FftItem& it) { return it.S1 == p90::N && it.S2 == p90::N && !it.perm && !it.full; }
+size_t plane90_lds(bool fp64) { return (size_t)p90::N * p90::N * (fp64 ? 16 : 8); }
+
 FftItem item_for(const dpp_basis_s* b, int nb, int64_t ld) {
     FftItem it = b->h_item;
     it.nb = nb;
@@ -996,6 +1263,14 @@ static dpp_status pass1(dpp_ctx_s* cx_, const FftItem& it, const TIO* C, typenam
     const double pl_ = (double)it.nplanes * it.S1 * it.S2;
     TimerScope ts_(cx_, DPP_TK_PLANES_IN, (double)it.nb * (sizeof(TIO) * (double)it.npw + sizeof(typename cx<T>::t) * pl_));
     const bool fp64 = sizeof(T) == 8;
+    if (plane90(it)) {
+        auto k = k_planes90_from_sphere<T, TIO>;
+        DPP_TRY(set_lds(k, plane90_lds(fp64)));
+        hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(p90::NT), plane90_lds(fp64), st, nullptr, it, C, Tb,
+                           (const int*)nullptr, (const int*)nullptr);
+        DPP_LAUNCHED();
+        return DPP_OK;
+    }
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_from_sphere<T, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, C, Tb,
@@ -1029,6 +1304,14 @@ static dpp_status pass3(dpp_ctx_s* cx_, const FftItem& it, const typename cx<T>:
     TimerScope ts_(cx_, DPP_TK_PLANES_OUT,
                    (double)it.nb * (sizeof(typename cx<T>::t) * pl_ + sizeof(TIO) * (MODE == G_ADD ? 2.0 : 1.0) * it.npw));
     const bool fp64 = sizeof(T) == 8;
+    if (plane90(it)) {
+        auto k = k_planes90_to_sphere<T, MODE, TIO>;
+        DPP_TRY(set_lds(k, plane90_lds(fp64)));
+        hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(p90::NT), plane90_lds(fp64), st, nullptr, it, Tb, Cin,
+                           out, (int64_t)0, (const int*)nullptr, (const int*)nullptr);
+        DPP_LAUNCHED();
+        return DPP_OK;
+    }
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, MODE, TIO, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(it.nplanes, it.nb, 1), dim3(NT_), L.lds, st, nullptr, it, Tb, Cin,
@@ -1053,6 +1336,14 @@ dpp_status run_apply_H_local(dpp_ham_s* ham, int nb, const double2* C, int64_t l
     FftItem ot = it;
     // gather writes HC with its own leading dimension; kinetic term reads C with ldC
     const bool fp64 = sizeof(T) == 8;
+    if (plane90(ot)) {
+        auto k = k_planes90_to_sphere<T, G_H, double2>;
+        DPP_TRY(set_lds(k, plane90_lds(fp64)));
+        hipLaunchKernelGGL(k, dim3(ot.nplanes, ot.nb, 1), dim3(p90::NT), plane90_lds(fp64), st, nullptr, ot, Tb, C,
+                           HC, ldHC, (const int*)nullptr, (const int*)nullptr);
+        DPP_LAUNCHED();
+        return DPP_OK;
+    }
     Launch L = plane_launch(it.S1, it.S2, fp64);
     DPP_NT_DISPATCH(L.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_>; DPP_TRY(set_lds(k, L.lds));
                     hipLaunchKernelGGL(k, dim3(ot.nplanes, ot.nb, 1), dim3(NT_), L.lds, st, nullptr, ot, Tb, C, HC,
@@ -1117,6 +1408,21 @@ static dpp_status planes_pass(dpp_ctx_s* cx_, bool to_sphere, const BatchShape& 
             DPP_LAUNCHED();
             continue;
         }
+        if (N == kPlane90Group) {
+            const size_t lds = plane90_lds(sizeof(T) == 8);
+            if (to_sphere) {
+                auto k = k_planes90_to_sphere<T, G_H, double2, true>;
+                DPP_TRY(set_lds(k, lds));
+                hipLaunchKernelGGL(k, grid, dim3(p90::NT), lds, st, d_items, i0, (const Cx*)Tb, X, HX, (int64_t)0,
+                                   act, idx);
+            } else {
+                auto k = k_planes90_from_sphere<T, double2, true>;
+                DPP_TRY(set_lds(k, lds));
+                hipLaunchKernelGGL(k, grid, dim3(p90::NT), lds, st, d_items, i0, X, Tb, act, idx);
+            }
+            DPP_LAUNCHED();
+            continue;
+        }
         if (N > 0) return set_error(DPP_EUNSUPPORTED, "plane pass length without a register kernel");
         if (to_sphere) {
             DPP_NT_DISPATCH(bs.plane.threads, auto k = k_planes_to_sphere<T, G_H, double2, NT_, true>;
@@ -1142,7 +1448,7 @@ PlanePlan plane_plan_groups(const std::vector<FftItem>& h, std::vector<std::vect
     members.clear();
     for (size_t k = 0; k < h.size(); ++k) {
         const FftItem& it = h[k];
-        const int key = it.perm ? it.S1 : 0;
+        const int key = it.perm ? it.S1 : plane90(it) ? kPlane90Group : 0;
         size_t g = 0;
         while (g < p.N.size() && p.N[g] != key) ++g;
         if (g == p.N.size()) {

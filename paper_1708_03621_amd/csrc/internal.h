@@ -241,6 +241,10 @@ XzPlan xz_plan_groups(const std::vector<FftItem>& h, std::vector<std::vector<int
 // Items grouped for the plane passes: group g with N[g] > 0 holds items with
 // square y-z faces S1 = S2 = N[g] whose planes are stored digit-reversed
 // (perm = 1, register plane passes); N[g] = 0 is the LDS group.
+// Plane-pass groups: N is the register kernel's face length (digit-reversed
+// items), kPlane90Group for 90 x 90 faces in natural order, 0 for the rest
+// (generic LDS kernel).
+constexpr int kPlane90Group = -90;
 struct PlanePlan {
     std::vector<int> N, count, maxP, nbm;
     std::vector<const int*> idx;
