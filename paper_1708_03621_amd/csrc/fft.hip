@@ -100,6 +100,162 @@ __device__ __forceinline__ TO store_as(C v) {
 // table indexed by blockIdx.z (batched launches); the choice is compile-time.
 #define DPP_ITEM(items, single) (BATCH ? (items)[blockIdx.z] : (single))
 
+// ------------------------------------------------ 90-point transforms ------
+// Square faces of 90 points (the 90^3 box) have dedicated LDS paths.  Each
+// 90-point transform is split as 9 x 10 (n = n1 + 10 n2, k = 9 k1 + k2, so
+// w^(nk) = w10^(n1 k1) w^(n1 k2) w9^(n2 k2)):
+//   step A, per (transform, n1): 9-point DFT over n2 in registers, times
+//           w^(n1 k2), stored back to the slots n1 + 10 k2 it read;
+//   step B, per (transform, k2): 10-point DFT over n1 of those slots, giving
+//           X[9 k1 + k2], stored to slot k1 + 10 k2 (the slots it read).
+// Both steps touch only their own slots, so an axis costs two LDS round trips
+// and one barrier between them, against one round trip and two barriers per
+// radix stage in the generic kernel.  Step B leaves the axis permuted: natural
+// index i sits at slot(i) = i / 9 + 10 (i mod 9).  Where a step can read its
+// input from, or write its output to, device memory directly (the first and
+// last steps of a pass), it does.
+namespace p90 {
+constexpr int N = 90;
+constexpr int NT = 1024;
+
+__device__ __forceinline__ int slot(int i) { return i / 9 + 10 * (i - 9 * (i / 9)); }
+
+// 9-point DFT as 3 x 3: v[3p + q] -> rows q, 3-point DFTs over p, twiddles
+// w9^(q c), 3-point DFTs over q, X[c + 3d].
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft9(typename cx<T>::t* v) {
+    using C = typename cx<T>::t;
+    const T c1 = T(0.766044443118978), s1 = T(SIGN) * T(0.6427876096865393);
+    const T c2 = T(0.17364817766693041), s2 = T(SIGN) * T(0.984807753012208);
+    const T c4 = T(-0.9396926207859083), s4 = T(SIGN) * T(0.3420201433256689);
+    C a[3][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        a[q][0] = v[q];
+        a[q][1] = v[q + 3];
+        a[q][2] = v[q + 6];
+        Dft<T, 3>::run(a[q], SIGN);
+    }
+    a[1][1] = cmul(a[1][1], C{c1, s1});
+    a[1][2] = cmul(a[1][2], C{c2, s2});
+    a[2][1] = cmul(a[2][1], C{c2, s2});
+    a[2][2] = cmul(a[2][2], C{c4, s4});
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        C b[3] = {a[0][c], a[1][c], a[2][c]};
+        Dft<T, 3>::run(b, SIGN);
+        v[c] = b[0];
+        v[c + 3] = b[1];
+        v[c + 6] = b[2];
+    }
+}
+
+// 10-point DFT as 5 x 2: 5-point DFTs of the even and odd points, twiddles
+// w10^c on the odd ones, X[c] = e + o, X[c + 5] = e - o.
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft10(typename cx<T>::t* v) {
+    using C = typename cx<T>::t;
+    const T c1 = T(0.8090169943749475), s1 = T(SIGN) * T(0.5877852522924731);
+    const T c2 = T(0.30901699437494745), s2 = T(SIGN) * T(0.9510565162951535);
+    C e[5], o[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        e[p] = v[2 * p];
+        o[p] = v[2 * p + 1];
+    }
+    Dft<T, 5>::run(e, SIGN);
+    Dft<T, 5>::run(o, SIGN);
+    o[1] = cmul(o[1], C{c1, s1});
+    o[2] = cmul(o[2], C{c2, s2});
+    o[3] = cmul(o[3], C{-c2, s2});
+    o[4] = cmul(o[4], C{-c1, s1});
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        v[c] = cadd(e[c], o[c]);
+        v[c + 5] = csub(e[c], o[c]);
+    }
+}
+
+// Step A on the 9 values of one (transform, n1) task: DFT and twiddles.
+template <typename T, int SIGN>
+__device__ __forceinline__ void step_a(typename cx<T>::t* v, int n1, const double2* tw64, const float2* tw32) {
+    dft9<T, SIGN>(v);
+#pragma unroll
+    for (int k2 = 1; k2 < 9; ++k2) v[k2] = cmul(v[k2], twiddle<T>(tw64, tw32, n1 * k2, SIGN));
+}
+
+// Natural row i of the face lies in the plane's data rows [n1lo, n1lo + nrows) (mod 90).
+__device__ __forceinline__ bool row_in(int i, int n1lo, int nrows) {
+    int d = i - n1lo;
+    d += d < 0 ? N : 0;
+    d -= d >= N ? N : 0;
+    return d < nrows;
+}
+__device__ __forceinline__ int row_at(int f, int n1lo) {
+    int r = n1lo + f;
+    r += r < 0 ? N : 0;
+    r -= r >= N ? N : 0;
+    return r;
+}
+
+// Full 90 x 90 face, y then z, in the 9 x 10 steps: y step A reads natural
+// element i = row * 90 + col through ld(i), the rows end permuted (natural
+// row i at LDS row slot(i)), z runs over every LDS row and leaves the slots
+// permuted, and st(i, v) receives natural element i (a coalesced copy out).
+template <typename T, int SIGN, typename Ld, typename St>
+__device__ __forceinline__ void face(typename cx<T>::t* lds, const double2* ty64, const float2* ty32,
+                                     const double2* tz64, const float2* tz32, Ld ld, St st) {
+    using Cx = typename cx<T>::t;
+    const int t = threadIdx.x;
+    if (t < 10 * N) {
+        const int n1 = t / N, c = t - N * n1;
+        Cx v[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = ld((n1 + 10 * j) * N + c);
+        step_a<T, SIGN>(v, n1, ty64, ty32);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) lds[(n1 + 10 * j) * N + c] = v[j];
+    }
+    __syncthreads();
+    if (t < 9 * N) {
+        const int k2 = t / N, c = t - N * k2;
+        Cx u[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) u[j] = lds[(j + 10 * k2) * N + c];
+        dft10<T, SIGN>(u);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) lds[(j + 10 * k2) * N + c] = u[j];
+    }
+    __syncthreads();
+    if (t < 10 * N) {
+        const int r = t / 10, n1 = t - 10 * r;
+        Cx* row = lds + r * N;
+        Cx v[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = row[n1 + 10 * j];
+        step_a<T, SIGN>(v, n1, tz64, tz32);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) row[n1 + 10 * j] = v[j];
+    }
+    __syncthreads();
+    if (t < 9 * N) {
+        const int r = t / 9, k2 = t - 9 * r;
+        Cx* row = lds + r * N + 10 * k2;
+        Cx u[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) u[j] = row[j];
+        dft10<T, SIGN>(u);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) row[j] = u[j];
+    }
+    __syncthreads();
+    for (int i = t; i < N * N; i += NT) {
+        const int i1 = i / N;
+        st(i, lds[slot(i1) * N + slot(i - N * i1)]);
+    }
+}
+}  // namespace p90
+
 // ------------------------------------------------------------- pass 1 ------
 // Sphere coefficients -> inverse transform along z and y -> plane buffer.
 template <typename T, typename TIO, int NT, bool BATCH = false>
@@ -145,6 +301,21 @@ k_planes_from_box(const FftItem* items, FftItem single, const void* __restrict__
     Cx* lds = reinterpret_cast<Cx*>(smem_raw);
     const int S1 = it.S1, S2 = it.S2, np = S1 * S2;
     const int64_t base = it.v_off + (int64_t)f * field_stride + (int64_t)p * np;
+    if constexpr (NT == p90::NT) {
+        if (S1 == p90::N && S2 == p90::N) {  // 90 x 90 face: the 9 x 10 steps
+            Cx* dst = Tb + it.t_off + (int64_t)f * it.S0 * np + (int64_t)p * np;
+            auto ld = [&](int i) {
+                if (REAL_IN) return Cx{(T)(reinterpret_cast<const double*>(in) + base)[i], (T)0};
+                return Io<T>::from((reinterpret_cast<const double2*>(in) + base)[i]);
+            };
+            auto st = [&](int i, Cx v) { dst[i] = v; };
+            if (sign > 0)
+                p90::face<T, +1>(lds, it.tw64[1], it.tw32[1], it.tw64[2], it.tw32[2], ld, st);
+            else
+                p90::face<T, -1>(lds, it.tw64[1], it.tw32[1], it.tw64[2], it.tw32[2], ld, st);
+            return;
+        }
+    }
     if (REAL_IN) {
         const double* src = reinterpret_cast<const double*>(in) + base;
         for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = Cx{(T)src[i], (T)0};
@@ -687,6 +858,38 @@ static bool xz_available_t(int S0, int v) {
 
 // Full-box x pass: plane buffer (all S0 planes) -> transform along x (sign)
 // -> multiply by `scale` -> complex output box.
+// x transform of one 90 x 90 (x, z) slab of a full box: step A per (column z,
+// n1) straight from the plane buffer, one LDS exchange, step B per (z, k2)
+// straight to the output rows 9 k1 + k2, times `scale`.
+template <typename T, int SIGN>
+__device__ __forceinline__ void xz_full90(const FftItem& it, const typename cx<T>::t* src, double2* dst, double scale,
+                                          typename cx<T>::t* lds) {
+    using Cx = typename cx<T>::t;
+    using namespace p90;
+    const int64_t rs = (int64_t)it.S1 * it.S2;  // x stride of the box
+    const int t = threadIdx.x;
+    if (t < 10 * N) {
+        const int n1 = t / N, z = t - N * n1;
+        Cx v[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = src[(n1 + 10 * j) * rs + z];
+        step_a<T, SIGN>(v, n1, it.tw64[0], it.tw32[0]);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) lds[(n1 + 10 * j) * N + z] = v[j];
+    }
+    __syncthreads();
+    if (t < 9 * N) {
+        const int k2 = t / N, z = t - N * k2;
+        Cx u[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) u[j] = lds[(j + 10 * k2) * N + z];
+        dft10<T, SIGN>(u);
+#pragma unroll
+        for (int j = 0; j < 10; ++j)
+            dst[(9 * j + k2) * rs + z] = double2{(double)u[j].x * scale, (double)u[j].y * scale};
+    }
+}
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
 k_xz_full(FftItem it, const typename cx<T>::t* __restrict__ Tb, int sign, double scale,
@@ -700,13 +903,22 @@ k_xz_full(FftItem it, const typename cx<T>::t* __restrict__ Tb, int sign, double
     const int e = S0 * S2;
     const int64_t N = (int64_t)S0 * S1 * S2;
     const Cx* src = Tb + (int64_t)f * N + (int64_t)i1 * S2;
+    double2* dst = out + (int64_t)f * field_stride + (int64_t)i1 * S2;
+    if constexpr (NT == p90::NT) {
+        if (S0 == p90::N && S2 == p90::N) {  // 90-point x, 90 columns: the 9 x 10 steps, one LDS exchange
+            if (sign > 0)
+                xz_full90<T, +1>(it, src, dst, scale, lds);
+            else
+                xz_full90<T, -1>(it, src, dst, scale, lds);
+            return;
+        }
+    }
     for (int i = threadIdx.x; i < e; i += blockDim.x) {
         const int i0 = i / S2, i2 = i - i0 * S2;
         lds[i] = src[(int64_t)i0 * S1 * S2 + i2];
     }
     __syncthreads();
     fft_axis<T, true, NT>(lds, it.ax[0], S2, AddrLinear{1, S2}, it.tw64[0], it.tw32[0], sign);
-    double2* dst = out + (int64_t)f * field_stride + (int64_t)i1 * S2;
     for (int i = threadIdx.x; i < e; i += blockDim.x) {
         const int i0 = i / S2, i2 = i - i0 * S2;
         dst[(int64_t)i0 * S1 * S2 + i2] = double2{lds[i].x * scale, lds[i].y * scale};
@@ -915,11 +1127,27 @@ k_planes_to_box(const FftItem* items, FftItem single, const typename cx<T>::t* _
     Cx* lds = reinterpret_cast<Cx*>(smem_raw);
     const int S1 = it.S1, S2 = it.S2, np = S1 * S2;
     const Cx* src = Tb + it.t_off + (int64_t)f * it.S0 * np + (int64_t)p * np;
+    const int64_t base = it.v_off + (int64_t)f * field_stride + (int64_t)p * np;
+    if constexpr (NT == p90::NT) {
+        if (S1 == p90::N && S2 == p90::N) {  // 90 x 90 face: the 9 x 10 steps
+            auto ld = [&](int i) { return src[i]; };
+            auto st = [&](int i, Cx v) {
+                if (REAL_OUT)
+                    (reinterpret_cast<double*>(out) + base)[i] = (double)v.x * scale;
+                else
+                    (reinterpret_cast<double2*>(out) + base)[i] = double2{(double)v.x * scale, (double)v.y * scale};
+            };
+            if (sign > 0)
+                p90::face<T, +1>(lds, it.tw64[1], it.tw32[1], it.tw64[2], it.tw32[2], ld, st);
+            else
+                p90::face<T, -1>(lds, it.tw64[1], it.tw32[1], it.tw64[2], it.tw32[2], ld, st);
+            return;
+        }
+    }
     for (int i = threadIdx.x; i < np; i += blockDim.x) lds[i] = src[i];
     __syncthreads();
     fft_axis<T, true, NT>(lds, it.ax[1], S2, AddrLinear{1, S2}, it.tw64[1], it.tw32[1], sign);
     fft_axis<T, false, NT>(lds, it.ax[2], S1, AddrLinear{S2, 1}, it.tw64[2], it.tw32[2], sign);
-    const int64_t base = it.v_off + (int64_t)f * field_stride + (int64_t)p * np;
     if (REAL_OUT) {
         double* dst = reinterpret_cast<double*>(out) + base;
         for (int i = threadIdx.x; i < np; i += blockDim.x) dst[i] = (double)lds[i].x * scale;
@@ -931,104 +1159,6 @@ k_planes_to_box(const FftItem* items, FftItem single, const typename cx<T>::t* _
 }
 
 // ------------------------------------------------ 90 x 90 plane passes ------
-// Square faces of 90 points (the 90^3 box) have dedicated LDS kernels.  Each
-// 90-point transform is split as 9 x 10 (n = n1 + 10 n2, k = 9 k1 + k2, so
-// w^(nk) = w10^(n1 k1) w^(n1 k2) w9^(n2 k2)):
-//   step A, per (transform, n1): 9-point DFT over n2 in registers, times
-//           w^(n1 k2), stored back to the slots n1 + 10 k2 it read;
-//   step B, per (transform, k2): 10-point DFT over n1 of those slots, giving
-//           X[9 k1 + k2], stored to slot k1 + 10 k2 (the slots it read).
-// Both steps touch only their own slots, so an axis costs two LDS round trips
-// and one barrier between them, against one round trip and two barriers per
-// radix stage in the generic kernel.  Step B leaves the axis permuted: natural
-// index i sits at slot p90_slot(i) = i / 9 + 10 (i mod 9).  The plane's first
-// step of the inverse direction reads the plane buffer directly, and the last
-// step of the forward direction writes it directly, in natural order.
-namespace p90 {
-constexpr int N = 90;
-constexpr int NT = 1024;
-
-__device__ __forceinline__ int slot(int i) { return i / 9 + 10 * (i - 9 * (i / 9)); }
-
-// 9-point DFT as 3 x 3: v[3p + q] -> rows q, 3-point DFTs over p, twiddles
-// w9^(q c), 3-point DFTs over q, X[c + 3d].
-template <typename T, int SIGN>
-__device__ __forceinline__ void dft9(typename cx<T>::t* v) {
-    using C = typename cx<T>::t;
-    const T c1 = T(0.766044443118978), s1 = T(SIGN) * T(0.6427876096865393);
-    const T c2 = T(0.17364817766693041), s2 = T(SIGN) * T(0.984807753012208);
-    const T c4 = T(-0.9396926207859083), s4 = T(SIGN) * T(0.3420201433256689);
-    C a[3][3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        a[q][0] = v[q];
-        a[q][1] = v[q + 3];
-        a[q][2] = v[q + 6];
-        Dft<T, 3>::run(a[q], SIGN);
-    }
-    a[1][1] = cmul(a[1][1], C{c1, s1});
-    a[1][2] = cmul(a[1][2], C{c2, s2});
-    a[2][1] = cmul(a[2][1], C{c2, s2});
-    a[2][2] = cmul(a[2][2], C{c4, s4});
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        C b[3] = {a[0][c], a[1][c], a[2][c]};
-        Dft<T, 3>::run(b, SIGN);
-        v[c] = b[0];
-        v[c + 3] = b[1];
-        v[c + 6] = b[2];
-    }
-}
-
-// 10-point DFT as 5 x 2: 5-point DFTs of the even and odd points, twiddles
-// w10^c on the odd ones, X[c] = e + o, X[c + 5] = e - o.
-template <typename T, int SIGN>
-__device__ __forceinline__ void dft10(typename cx<T>::t* v) {
-    using C = typename cx<T>::t;
-    const T c1 = T(0.8090169943749475), s1 = T(SIGN) * T(0.5877852522924731);
-    const T c2 = T(0.30901699437494745), s2 = T(SIGN) * T(0.9510565162951535);
-    C e[5], o[5];
-#pragma unroll
-    for (int p = 0; p < 5; ++p) {
-        e[p] = v[2 * p];
-        o[p] = v[2 * p + 1];
-    }
-    Dft<T, 5>::run(e, SIGN);
-    Dft<T, 5>::run(o, SIGN);
-    o[1] = cmul(o[1], C{c1, s1});
-    o[2] = cmul(o[2], C{c2, s2});
-    o[3] = cmul(o[3], C{-c2, s2});
-    o[4] = cmul(o[4], C{-c1, s1});
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        v[c] = cadd(e[c], o[c]);
-        v[c + 5] = csub(e[c], o[c]);
-    }
-}
-
-// Step A on the 9 values of one (transform, n1) task: DFT and twiddles.
-template <typename T, int SIGN>
-__device__ __forceinline__ void step_a(typename cx<T>::t* v, int n1, const double2* tw64, const float2* tw32) {
-    dft9<T, SIGN>(v);
-#pragma unroll
-    for (int k2 = 1; k2 < 9; ++k2) v[k2] = cmul(v[k2], twiddle<T>(tw64, tw32, n1 * k2, SIGN));
-}
-
-// Natural row i of the face lies in the plane's data rows [n1lo, n1lo + nrows) (mod 90).
-__device__ __forceinline__ bool row_in(int i, int n1lo, int nrows) {
-    int d = i - n1lo;
-    d += d < 0 ? N : 0;
-    d -= d >= N ? N : 0;
-    return d < nrows;
-}
-__device__ __forceinline__ int row_at(int f, int n1lo) {
-    int r = n1lo + f;
-    r += r < 0 ? N : 0;
-    r -= r >= N ? N : 0;
-    return r;
-}
-}  // namespace p90
-
 // Sphere -> 90 x 90 planes (sign +1): scatter, z along the data rows, y along
 // every column (rows without data read as zero), natural order out.
 template <typename T, typename TIO, bool BATCH = false>
