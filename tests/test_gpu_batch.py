@@ -241,20 +241,33 @@ def test_launch_choices_match_default(dev, which, value):
 def test_x_pass_variants(dev, prec, S0):
     """At config 2's 40-point and config 3's 90-point x lengths every x-pass
     variant the tuner can pick (one thread per column where it compiles, lane
-    pair, LDS) gives the LDS pass's H Y to rounding; the box is S0 x 20 x 18."""
+    pair, LDS) gives the LDS pass's H Y to rounding; the box is S0 x 20 x 18.
+    H is applied at the potential of one SCF iteration: the x pass multiplies
+    by V_eff, so with no potential set every variant would transform zeros and
+    agree trivially.  The test checks that the potential's part of H Y is
+    there (at least 1% of max |H Y|; it is about 6%)."""
     D = dev.D
     cell = W.tiny_cell(nat=2, L=10.0, ecut=4.0, S=(S0, 20, 18), nb=4, Z=(4, 4), seed=19)
     s, Y, _ = _batch(dev, [cell], prec=prec)
+    Y0 = Y.clone()
+    HY = dev.torch.empty_like(Y)
+    D.dpp_system_apply_H(s, Y0, HY)  # no potential yet: kinetic and nonlocal terms only
+    no_v = dev.host(HY)
+    D.dpp_scf_init(s, cells=[dict(tau=cell.tau, Z=cell.Z, sigma=W.START_SIGMA)])
+    D.dpp_scf_iteration(s, Y)  # sets V_eff
     out = {}
-    for v in (3, 0, 1, 2):  # LDS first: the reference
+    variants = (0, 1, 2)
+    for v in (3,) + variants:  # LDS first: the reference
         D.dpp_system_set_launch_choice(s, D.DPP_CHOICE_XPASS, v)
-        HY = dev.torch.empty_like(Y)
-        D.dpp_system_apply_H(s, Y, HY)
+        D.dpp_system_apply_H(s, Y0, HY)
         out[v] = dev.host(HY)
     D.dpp_system_destroy(s)
     ref = out[3]
+    share = np.max(np.abs(ref - no_v)) / np.max(np.abs(ref))
+    log(f"x pass S0={S0} prec={prec}: potential part {share:.2f} of max |H Y|")
+    assert share > 0.01
     tol = 1e-12 if prec == 0 else 1e-5
-    for v in (0, 1, 2):
+    for v in variants:
         err = np.max(np.abs(out[v] - ref)) / np.max(np.abs(ref))
         log(f"x pass variant {v} at S0={S0} prec={prec}: max rel difference {err:.2e}")
         assert err < tol
