@@ -712,10 +712,13 @@ k_xz_reg2(const FftItem* __restrict__ items, const int* __restrict__ idx, typena
     const int item = idx ? idx[blockIdx.z] : (int)blockIdx.z;
     if (act && !act[item]) return;
     const FftItem& it = items[item];
-    const int b = blockIdx.y;
+    // workgroups in dispatch order take the bands of one column tile first,
+    // so the tile's V (90 KB at S0 = 90) is reused from L2 across bands
+    const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+    const int b = lin % gridDim.y;
     if (b >= it.nb) return;
     const int np = it.S1 * it.S2;
-    const int col = blockIdx.x * 128 + (threadIdx.x >> 1);
+    const int col = (lin / gridDim.y) * 128 + (threadIdx.x >> 1);
     const int h = threadIdx.x & 1;
     if (col >= np) return;  // both lanes of a pair leave together
     const int nP = it.nplanes;
