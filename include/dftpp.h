@@ -438,8 +438,8 @@ dpp_status dpp_system_apply_H(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY);
  * the default rule unless another candidate is at least 3% faster.  Choices: per x-pass length S0 and precision, the register
  * x pass with one thread per column, with a lane pair per column, or the
  * LDS pass; point tiles per wave of the X M contraction (1, 2 or 4, for up
- * to 32 bands); the A^dag O B block shape (2x2 tiles per wave or single
- * tiles).  Y (device, packed layout) is the block the H applications and
+ * to 32 bands); the A^dag O B launch (2x2 tiles per wave, single tiles,
+ * one pass, or 4x4 tile blocks staged in LDS).  Y (device, packed layout) is the block the H applications and
  * contractions run on; HY (device, same size) is overwritten.  Each
  * candidate runs reps >= 1 times after a warm-up.  Runs eagerly and
  * synchronizes; the system's internal work blocks are overwritten (a band-CG
@@ -450,7 +450,8 @@ dpp_status dpp_system_tune(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY, int re
 /* Sets one launch choice by hand (what dpp_system_tune would choose), for
  * tests and experiments: DPP_CHOICE_OVERLAP (0: 2x2 tile blocks over
  * 256-point chunks plus a reduction launch, 1: single tiles, 2: one
- * workgroup per task over all points), DPP_CHOICE_ROTATE_PT (0 = by launch
+ * workgroup per task over all points, 3: 4x4 tile blocks over 256-point
+ * chunks with the operands staged in LDS), DPP_CHOICE_ROTATE_PT (0 = by launch
  * size, 1, 2 or 4 point tiles per wave), DPP_CHOICE_XPASS (0 auto, 1 one
  * thread per column, 2 lane pair per column, 3 LDS; for every x length,
  * lengths without the variant use the LDS pass).  Drops captured graphs.

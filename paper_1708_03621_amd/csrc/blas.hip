@@ -207,8 +207,113 @@ k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restr
     }
 }
 
-// Blocks of a task in the shape k_overlap_mfma picks for it.
-static int ov_task_blocks(int tA, int tB) {
+// LDS-staged form (launch mode 3): one workgroup of four waves per (task,
+// chunk, 4 x 4 tile block).  Each 16-point step of the block's 64 A rows and
+// 64 B rows is staged once in LDS (double-buffered, rows padded to an odd
+// number of 16-byte units), and each wave accumulates its 2 x 2 tiles from
+// there, so every operand is read from memory once per block instead of once
+// per wave.  Partials use k_overlap_mfma's layout (chunk, tile) and are
+// summed by k_overlap_reduce.
+constexpr int OVS_ROWS = 128;  // 64 A rows, then 64 B rows
+constexpr int OVS_ROW = 17;    // 16 points + 1 unit of padding
+
+__global__ void __launch_bounds__(256)
+k_overlap_staged(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part,
+                 const int* __restrict__ act, const int4* __restrict__ work) {
+    __shared__ double2 st[2][OVS_ROWS * OVS_ROW];
+    int ti, chunk, blk;
+    if (work) {
+        const int4 w = work[blockIdx.x];
+        ti = w.x, chunk = w.y, blk = w.z;
+    } else {
+        ti = (int)blockIdx.z, chunk = (int)blockIdx.x, blk = (int)blockIdx.y;
+    }
+    const OvTask T = tasks ? tasks[ti] : single;
+    if (act && !act[T.item]) return;
+    if (chunk >= T.nchunk) return;
+    const int tilesA = (T.nbA + 15) / 16;
+    const int sB = (T.tilesB + 3) / 4, sA = (tilesA + 3) / 4;
+    if (blk >= sA * sB) return;
+    const int ti0 = (blk / sB) * 4, tj0 = (blk % sB) * 4;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r = lane & 15, ks = lane >> 4;
+    // staging: thread -> LDS row tid / 2, points 8 (tid % 2) .. + 7 of a step
+    const int srow = tid >> 1, sp = (tid & 1) * 8;
+    const bool isA = srow < 64;
+    const int brow = isA ? 16 * ti0 + srow : 16 * tj0 + srow - 64;
+    const bool valid = brow < (isA ? T.nbA : T.nbB);
+    const double2* src = isA ? T.A + (int64_t)brow * T.ldA : T.B + (int64_t)brow * T.ldB;
+    const int g0 = chunk * OV_CHUNK, g1 = min(T.npw, g0 + OV_CHUNK);
+    const int nst = g1 > g0 ? (g1 - g0 + 15) / 16 : 0;
+    double2 raw[8];
+    // rows past the band counts load nothing and stage zeros; points past the
+    // chunk are clamped to the last point when loaded and zeroed when staged
+    auto load = [&](int g) {
+        if (valid) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) raw[e] = gld(src + min(g + sp + e, T.npw - 1));
+        }
+    };
+    auto stage = [&](int buf, int g) {
+        double2* row = st[buf] + srow * OVS_ROW + sp;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) row[e] = (valid && g + sp + e < g1) ? raw[e] : double2{0, 0};
+    };
+    // this wave's tiles: A tiles ti0 + 2 (w / 2) + a, B tiles tj0 + 2 (w % 2) + b
+    const int wa = 2 * (w >> 1), wb = 2 * (w & 1);
+    d4 cre[2][2], cim[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cre[a][b] = d4{0, 0, 0, 0};
+            cim[a][b] = d4{0, 0, 0, 0};
+        }
+    if (nst > 0) load(g0);
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        stage(buf, g0 + 16 * s);
+        if (s + 1 < nst) load(g0 + 16 * (s + 1));
+        __syncthreads();
+        const double2* S = st[buf];
+        // lane (r, ks) takes points 4 ks + q of the step for the q-th MFMA
+        double2 av[2][4], bv[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) av[a][q] = S[(16 * (wa + a) + r) * OVS_ROW + 4 * ks + q];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bv[b][q] = S[(64 + 16 * (wb + b) + r) * OVS_ROW + 4 * ks + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    cre[a][b] = mfma(av[a][q].x, bv[b][q].x, cre[a][b]);
+                    cre[a][b] = mfma(av[a][q].y, bv[b][q].y, cre[a][b]);
+                    cim[a][b] = mfma(av[a][q].x, bv[b][q].y, cim[a][b]);
+                    cim[a][b] = mfma(-av[a][q].y, bv[b][q].x, cim[a][b]);
+                }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int ta = ti0 + wa + a, tb = tj0 + wb + b;
+            if (ta >= tilesA || tb >= T.tilesB) continue;  // uniform over the wave
+            double2* dst = part + T.part_off + ((int64_t)chunk * T.ntiles + ta * T.tilesB + tb) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[(4 * v + (lane >> 4)) * 16 + (lane & 15)] = double2{cre[a][b][v], cim[a][b][v]};
+        }
+}
+
+// Blocks of a task in the shape k_overlap_mfma picks for it (staged: the 4 x 4
+// blocks of k_overlap_staged).
+static int ov_task_blocks(int tA, int tB, bool staged = false) {
+    if (staged) return ov_blocks<4, 4>(tA, tB);
     if (tA >= 2 && tB >= 2) return ov_blocks<2, 2>(tA, tB);
     if (tB >= 2) return ov_blocks<1, 2>(tA, tB);
     if (tA >= 2) return ov_blocks<2, 1>(tA, tB);
@@ -243,7 +348,7 @@ void overlap_worklist(const std::vector<OvTask>& h, int ov_mode, std::vector<int
     for (size_t i = 0; i < h.size(); ++i) {
         const OvTask& t = h[i];
         const int nch = ov_mode == 2 ? 1 : t.nchunk;
-        const int nb = ov_mode == 1 ? t.ntiles : ov_task_blocks((t.nbA + 15) / 16, t.tilesB);
+        const int nb = ov_mode == 1 ? t.ntiles : ov_task_blocks((t.nbA + 15) / 16, t.tilesB, ov_mode == 3);
         for (int c = 0; c < nch; ++c)
             for (int b = 0; b < nb; ++b) w.push_back(int4{(int)i, c, b, 0});
     }
@@ -679,13 +784,14 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
     const bool wide = bf && overlap_bf16_wide(h);  // the work list is overlap_worklist_bf16's
     const int ov_narrow = !bf && ov_mode == 1;
     const bool full = !bf && ov_mode == 2;
+    const bool staged = !bf && ov_mode == 3;
     if (h.empty()) return DPP_OK;
     int mc = 1, mt = 1, mblk = 1;
     double by = 0, fl = 0;
     for (const OvTask& t : h) {
         mc = std::max(mc, t.nchunk);
         mt = std::max(mt, t.ntiles);
-        mblk = std::max(mblk, ov_narrow ? t.ntiles : ov_task_blocks((t.nbA + 15) / 16, t.tilesB));
+        mblk = std::max(mblk, ov_narrow ? t.ntiles : ov_task_blocks((t.nbA + 15) / 16, t.tilesB, staged));
         by += 16.0 * t.npw * (t.nbA + t.nbB);
         fl += 8.0 * t.npw * t.nbA * (double)t.nbB;
     }
@@ -702,6 +808,10 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
             const dim3 grid = d_work ? dim3((unsigned)nwork) : dim3(mc, mblk, h.size());
             hipLaunchKernelGGL(k_overlap_bf16, grid, dim3(64 * OVB_WAVES), 0, ctx->stream, d_tasks, OvTask{}, part,
                                act, d_work);
+        } else if (staged) {
+            const dim3 grid = d_work ? dim3((unsigned)nwork) : dim3(mc, mblk, h.size());
+            hipLaunchKernelGGL(k_overlap_staged, grid, dim3(256), 0, ctx->stream, d_tasks, OvTask{}, part, act,
+                               d_work);
         } else {
             overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act,
                            full, d_work, nwork);

@@ -152,7 +152,8 @@ struct dpp_system_s {
     void* gga_ws = nullptr;        // PBE workspace (largest cell) and a scratch energy
     double* d_gga_scratch = nullptr;
     int rot_pt = 0;         // rotate point tiles per wave (0: by launch size)
-    int ov_mode = 0;        // overlap launch shape (0 chunked 2x2 blocks, 1 chunked single tiles, 2 single pass)
+    int ov_mode = 0;        // overlap launch shape (0 chunked 2x2 blocks, 1 chunked single tiles, 2 single pass,
+                            // 3 chunked 4x4 blocks staged in LDS)
     std::string tune_report;
     // graphs
     bool graph_on = false;
@@ -1574,11 +1575,11 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
     {
         // the launch shapes of the FP64 overlap (the split-BF16 one has a single shape)
         s->prec = DPP_F64;
-        static const char* oname[] = {"wide", "single-tile", "single-pass"};
+        static const char* oname[] = {"wide", "single-tile", "single-pass", "staged"};
         double best = 1e300;
         int bn = 0;
         rep += "overlap blocks (f64):";
-        for (int mode : {0, 1, 2}) {
+        for (int mode : {0, 1, 2, 3}) {
             s->ov_mode = mode;
             const double t = timeit([&] {
                 return overlap_jobs(s, 0, {OvJob{Y, Y, 1.0, true, s->U}, OvJob{Y, HY, 1.0, false, s->H0}});
@@ -1609,7 +1610,7 @@ extern "C" dpp_status dpp_system_set_launch_choice(dpp_system s, int which, int 
     DPP_REQUIRE(s, "dpp_system_set_launch_choice: null system");
     switch (which) {
         case DPP_CHOICE_OVERLAP:
-            DPP_REQUIRE(value >= 0 && value <= 2, "dpp_system_set_launch_choice: overlap mode 0..2");
+            DPP_REQUIRE(value >= 0 && value <= 3, "dpp_system_set_launch_choice: overlap mode 0..3");
             s->ov_mode = value;
             break;
         case DPP_CHOICE_ROTATE_PT:

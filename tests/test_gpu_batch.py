@@ -217,7 +217,7 @@ def test_tuner_keeps_results(dev):
     D.dpp_system_destroy(sb)
 
 
-@pytest.mark.parametrize("which,value", [(0, 1), (0, 2), (1, 2), (1, 4), (2, 1), (2, 2), (2, 3)])
+@pytest.mark.parametrize("which,value", [(0, 1), (0, 2), (0, 3), (1, 2), (1, 4), (2, 1), (2, 2), (2, 3)])
 def test_launch_choices_match_default(dev, which, value):
     """Every launch variant the tuner can pick gives the default SCF energies
     to rounding (mixed cells: several boxes, band counts and k-point sets)."""

@@ -6,7 +6,8 @@ band-gradient preparation, band-energy line search and the subspace
 eigensolver (Householder tridiagonalization, bisection, inverse iteration).
 These tests run band CG (protocol B) and SCF (protocol S) through them:
   * protocol B trajectories at 33, 64, 65 and 128 bands;
-  * SCF trajectories at 40 and 65 bands;
+  * SCF trajectories at 40, 65 and 128 bands (65 and 128 also with the
+    LDS-staged overlap launch);
   * a batch that mixes a 16-band cell with a 40-band one (every item then
     takes the register-tile path);
   * two SCF iterations of config 3 itself (64 atoms, 90^3, 128 bands) against
@@ -69,12 +70,15 @@ def test_band_cg_many_bands(dev, nb):
     dev.D.dpp_system_destroy(sysg)
 
 
-@pytest.mark.parametrize("nb", [40, 65])
-def test_scf_many_bands(dev, nb):
-    log(f"scf nb={nb}")
+@pytest.mark.parametrize("nb,ov", [(40, 0), (65, 0), (65, 3), (128, 3)])
+def test_scf_many_bands(dev, nb, ov):
+    """ov: overlap launch mode (3: the LDS-staged 4 x 4 tile blocks; at 65
+    bands its second block row holds one tile)."""
+    log(f"scf nb={nb} overlap mode {ov}")
     cell = _cell(nb, seed=43)
     s = oe.build_system(cell)
     sysg, off, npw = make_gpu_system(dev, cell)
+    dev.D.dpp_system_set_launch_choice(sysg, dev.D.DPP_CHOICE_OVERLAP, ov)
     Y, blocks = packed_Y(dev, cell, npw)
     dev.D.dpp_scf_init(sysg, cell.tau, cell.Z, W.START_SIGMA)
     nit = 3
