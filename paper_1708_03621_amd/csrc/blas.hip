@@ -936,6 +936,131 @@ k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0_in, int
     }
 }
 
+// FP64 outputs of more than two 16-band tiles: RS_WAVES waves per workgroup,
+// one 16-point tile each, share the rows of M through LDS.  M is staged 16 K
+// rows (four MFMA steps) at a time for the RT_JT output tiles from jt0,
+// double-buffered; X is read by its own wave as in k_rotate_mfma.  The K
+// order (rows of X, then of X2), the padding rules and the output are those
+// of k_rotate_mfma, so both give the same sums.
+constexpr int RS_WAVES = 8;
+constexpr int RS_COLS = RT_JT * 16;
+
+__global__ void __launch_bounds__(64 * RS_WAVES)
+k_rotate_staged(const RotTask* __restrict__ tasks, RotTask single, int jt0, const int* __restrict__ act,
+                const int2* __restrict__ work) {
+    __shared__ double2 ms[2][16 * RS_COLS];
+    const int2 wk = work ? work[blockIdx.x] : int2{(int)blockIdx.y, (int)blockIdx.x};
+    const RotTask T = tasks ? tasks[wk.x] : single;
+    if (act && !act[T.item]) return;
+    const int njt = min(RT_JT, (T.nbO + 15) / 16 - jt0);
+    if (njt <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int gt = wk.y * RS_WAVES + w;
+    if (wk.y * RS_WAVES * 16 >= T.npw) return;  // uniform over the workgroup
+    const bool live = gt * 16 < T.npw;          // waves past the points still stage M
+    const int c = lane & 15, ks = lane >> 4;
+    const int nk1 = (T.nbX + 3) / 4, nk = nk1 + (T.nbX2 > 0 ? (T.nbX2 + 3) / 4 : 0);
+    const int nch = (nk + 3) / 4;
+    // K step k, sub-row r4: the term, its row and whether the row exists
+    auto krow = [&](int k, int r4, bool& second, int& ic) {
+        second = k >= nk1;
+        const int nbx = second ? T.nbX2 : T.nbX;
+        const int row = (second ? k - nk1 : k) * 4 + r4;
+        ic = min(row, nbx - 1);
+        return k < nk && row < nbx;
+    };
+    // staging: element e = tid + 512 i (i < 4) of the chunk is K row e / RS_COLS
+    // (step e / (4 RS_COLS), sub-row (e / RS_COLS) % 4), output band jt0 16 + e % RS_COLS
+    double2 mraw[4];
+    auto mload = [&](int ch) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 64 * RS_WAVES * i, kk = e / RS_COLS, col = e - kk * RS_COLS;
+            bool second;
+            int ic;
+            const bool ok = krow(4 * ch + kk / 4, kk % 4, second, ic);
+            const double2* Ms = second ? T.M2 : T.M;
+            const int j = min(jt0 * 16 + col, T.nbO - 1);
+            mraw[i] = ok ? gld(Ms + (int64_t)ic * T.M_ld + j) : double2{0, 0};
+        }
+    };
+    auto mstage = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ms[buf][tid + 64 * RS_WAVES * i] = mraw[i];
+    };
+    double2 xn[4];
+    auto xload = [&](int ch) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bool second;
+            int ic;
+            // steps past the last one (the chunk's tail) have no row to read
+            const bool ok = 4 * ch + q < nk;
+            krow(4 * ch + q, ks, second, ic);
+            const double2* Xs = second ? T.X2 : T.X;
+            xn[q] = ok ? gld(Xs + (int64_t)ic * T.ldX + min(gt * 16 + c, T.npw - 1)) : double2{0, 0};
+        }
+    };
+    d4 dre[RT_JT], dim[RT_JT];
+#pragma unroll
+    for (int t = 0; t < RT_JT; ++t) {
+        dre[t] = d4{0, 0, 0, 0};
+        dim[t] = d4{0, 0, 0, 0};
+    }
+    if (nch > 0) {
+        mload(0);
+        xload(0);
+    }
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        mstage(buf);
+        double2 x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = xn[q];
+        if (ch + 1 < nch) {
+            mload(ch + 1);
+            xload(ch + 1);
+        }
+        __syncthreads();
+        const double2* M = ms[buf];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double xr = x[q].x, xi = x[q].y;
+#pragma unroll
+            for (int t = 0; t < RT_JT; ++t) {
+                if (t < njt) {
+                    const double2 m = M[(4 * q + ks) * RS_COLS + t * 16 + c];
+                    dre[t] = mfma(m.x, xr, dre[t]);
+                    dre[t] = mfma(-m.y, xi, dre[t]);
+                    dim[t] = mfma(m.y, xr, dim[t]);
+                    dim[t] = mfma(m.x, xi, dim[t]);
+                }
+            }
+        }
+    }
+    const int q = gt * 16 + c;
+    if (!live || q >= T.npw) return;
+#pragma unroll
+    for (int t = 0; t < RT_JT; ++t) {
+        if (t < njt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = (jt0 + t) * 16 + 4 * v + ks;  // FP64 result row of element v
+                if (j < T.nbO) {
+                    double2* o = T.out + (int64_t)j * T.ldout + q;
+                    double2 r = double2{dre[t][v], dim[t][v]};
+                    if (T.beta != 0.0) {
+                        const double2 p = *o;
+                        r.x += T.beta * p.x;
+                        r.y += T.beta * p.y;
+                    }
+                    *o = r;
+                }
+            }
+        }
+    }
+}
+
 RotTask make_rot_task(int npw, int nbX, const double2* X, int64_t ldX, int nbO, const double2* M, int M_ld,
                       double beta, double2* out, int64_t ldout) {
     RotTask t;
@@ -1015,8 +1140,10 @@ static dpp_status rotate_launch(dpp_ctx ctx, const RotTask* d_tasks, const RotTa
         rotate_go<1, RT_JT32>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, true,
                               rotate_groups(jtiles, true));
     } else {
+        const dim3 grid = work ? dim3((unsigned)nwork) : dim3((ntile + RS_WAVES - 1) / RS_WAVES, ntasks);
         for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT)
-            rotate_go<1, RT_JT>(ctx, d_tasks, single, ntasks, ntile, jt0, act, work, nwork, false);
+            hipLaunchKernelGGL(k_rotate_staged, grid, dim3(64 * RS_WAVES), 0, ctx->stream, d_tasks, single, jt0, act,
+                               work);
     }
     DPP_LAUNCHED();
     return DPP_OK;
@@ -1037,9 +1164,10 @@ void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2
     rotate_shape(h, mp, mj, tiles);
     const int pt = rotate_pt_rule(mj, tiles, rot_pt);
     const int ng = rotate_groups(mj, f32);
+    const int per = (!f32 && mj > 2) ? RS_WAVES : RT_WAVES * pt;  // point tiles per block
     w.clear();
     for (size_t i = 0; i < h.size(); ++i) {
-        const int nblk = ((h[i].npw + 15) / 16 + RT_WAVES * pt - 1) / (RT_WAVES * pt);
+        const int nblk = ((h[i].npw + 15) / 16 + per - 1) / per;
         for (int b = 0; b < nblk * ng; ++b) w.push_back(int2{(int)i, b});
     }
 }
