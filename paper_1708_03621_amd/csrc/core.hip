@@ -166,6 +166,7 @@ static void free_grid(dpp_grid g) {
         if (g->d_tw32[a]) hipFree(g->d_tw32[a]);
     }
     if (g->d_fullplanes) hipFree(g->d_fullplanes);
+    if (g->h_pin) hipHostFree(g->h_pin);
     delete g;
 }
 

@@ -142,6 +142,7 @@ struct dpp_grid_s {
     int4* d_fullplanes;      // plane table for full-box transforms
     dpp::FftItem* d_item;    // full-box FFT item (nb = 1)
     dpp::FftItem h_item;
+    double* h_pin = nullptr;  // pinned host scalars for the readbacks of iterative solves (first use)
 };
 
 struct dpp_basis_s {

@@ -299,7 +299,11 @@ extern "C" dpp_status dpp_pcm_solve(dpp_grid grid, const double* d_eps, const do
     DPP_LAUNCHED();
     // sc[4] = |b|^2, sc[5] = r.Mr -> move r.Mr to slot 0
     DPP_HIP(hipMemcpyAsync(sc, sc + 5, sizeof(double), hipMemcpyDeviceToDevice, st));
-    double host[2] = {0.0, 0.0};
+    // the per-iteration readback goes through pinned memory (a pageable
+    // destination is staged by the host runtime on every copy)
+    if (!grid->h_pin) DPP_HIP(hipHostMalloc((void**)&grid->h_pin, 8 * sizeof(double), hipHostMallocDefault));
+    double* host = grid->h_pin;
+    host[0] = 0.0;
     DPP_HIP(hipMemcpyAsync(host, sc + 4, sizeof(double), hipMemcpyDeviceToHost, st));
     DPP_HIP(hipStreamSynchronize(st));
     const double bn = std::sqrt(host[0]);
