@@ -7,7 +7,12 @@
 
 namespace dpp {
 
-constexpr int DOT_BLOCKS = 64;  // fixed partial-sum count per block reduction
+// Partial sums per item of the block reductions over bands x points: 256 for
+// systems of up to three items (one item alone then spreads over every CU),
+// 64 for more (whose items together fill the chip; more blocks only add
+// near-empty workgroups).  Fixed per system, so the summation order is too.
+constexpr int DOT_BLOCKS = 256;  // the most per item (partial buffer size)
+inline int dot_blocks(int nitems) { return nitems <= 3 ? DOT_BLOCKS : 64; }
 constexpr int PULAY_MAX = 8;
 
 // One work item (a k-point of a cell): where its data sits in the packed
@@ -50,16 +55,16 @@ __global__ void k_seg_axpby(const Seg* seg, int nbo, const double* a, const doub
 //   retry:     mark failed CG searches, then D = cK Kg + cD D (D = -Kg for them);
 //   finish:    accept the steps (stepf), then Y += a D, HY += a HD, g_prev = g, D_prev = D.
 __global__ void k_cgB_direction(const Seg* seg, int nitems, const double* part, double* dots, CgBState s,
-                                const double2* Kg, const double2* Dp, double2* Dd);
+                                const double2* Kg, const double2* Dp, double2* Dd, int nblk);
 __global__ void k_cgB_retry_axpby(const Seg* seg, const double* dots, CgBState s, const double2* Kg, double2* Dd);
 __global__ void k_cgB_finish_update(const Seg* seg, const double* dots, CgBState s, double2* Y, const double2* Dd,
                                     double2* HY, const double2* HD, const double2* g, double2* gp, double2* Dp);
 __global__ void k_seg_precond(const Seg* seg, int nbo, double scale, const double2* x, double2* out);
 __global__ void k_seg_dots(const Seg* seg, int nitems, int nbo, int npair, DotPairs pr, double* part);
-__global__ void k_seg_dots_reduce(const double* part, int nitems, int npair, double* out);
+__global__ void k_seg_dots_reduce(const double* part, int nitems, int npair, double* out, int nblk);
 __global__ void k_seg_kinetic(const Seg* seg, int nbo, const double* f, const double2* psi, double* part);
 __global__ void k_cell_weighted_totals(const double* part, const Seg* seg, const CellDesc* cells, int ncells,
-                                       double scale_omega, double* out, int out_stride);
+                                       double scale_omega, double* out, int out_stride, int nblk);
 __global__ void k_nonlocal_energy(const Seg* seg, const CellDesc* cells, int nbo, const double2* pi, const double* f,
                                   double* out, int out_stride);
 __global__ void k_sm_scale(const Seg* seg, int nbo, int op, double scale, int flags, const double2* A,

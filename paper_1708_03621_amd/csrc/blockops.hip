@@ -54,7 +54,8 @@ __global__ void k_seg_precond(const Seg* __restrict__ seg, int nbo, double scale
 }
 
 // Per-item dots 2 Re sum conj(A) B for up to 4 pairs: partial sums per
-// (pair, item, block) -> part[(pair * nitems + k) * DOT_BLOCKS + blockIdx.x].
+// (pair, item, block) -> part[(pair * nitems + k) * gridDim.x + blockIdx.x]
+// (gridDim.x = dot_blocks of the system).
 __global__ void __launch_bounds__(256)
 k_seg_dots(const Seg* __restrict__ seg, int nitems, int nbo, int npair, DotPairs pr, double* __restrict__ part) {
     __shared__ double red[4][256];
@@ -62,7 +63,7 @@ k_seg_dots(const Seg* __restrict__ seg, int nitems, int nbo, int npair, DotPairs
     const Seg s = seg[k];
     const int64_t n = (int64_t)item_nb(s, nbo) * s.npw;
     double acc[4] = {0, 0, 0, 0};
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * 256) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
         const int64_t o = s.off + e;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -81,17 +82,18 @@ k_seg_dots(const Seg* __restrict__ seg, int nitems, int nbo, int npair, DotPairs
         __syncthreads();
     }
     if (threadIdx.x < npair)
-        part[((int64_t)threadIdx.x * nitems + k) * DOT_BLOCKS + blockIdx.x] = 2.0 * red[threadIdx.x][0];
+        part[((int64_t)threadIdx.x * nitems + k) * gridDim.x + blockIdx.x] = 2.0 * red[threadIdx.x][0];
 }
 
 // Fixed-order sums: out[pair * (nitems + 1) + k] per item and the total over
 // items at out[pair * (nitems + 1) + nitems].
-__global__ void k_seg_dots_reduce(const double* __restrict__ part, int nitems, int npair, double* __restrict__ out) {
+__global__ void k_seg_dots_reduce(const double* __restrict__ part, int nitems, int npair, double* __restrict__ out,
+                                  int nblk) {
     const int p = blockIdx.x;
     if (p >= npair) return;
     for (int k = threadIdx.x; k < nitems; k += blockDim.x) {
         double s = 0;
-        for (int b = 0; b < DOT_BLOCKS; ++b) s += part[((int64_t)p * nitems + k) * DOT_BLOCKS + b];
+        for (int b = 0; b < nblk; ++b) s += part[((int64_t)p * nitems + k) * nblk + b];
         out[p * (nitems + 1) + k] = s;
     }
     __syncthreads();
@@ -102,7 +104,7 @@ __global__ void k_seg_dots_reduce(const double* __restrict__ part, int nitems, i
     }
 }
 
-// Band-weighted kinetic sums: part[k * DOT_BLOCKS + block] of
+// Band-weighted kinetic sums: part[k * gridDim.x + block] of
 // sum_i f_ki * sum_G |k+G|^2 |psi_Gi|^2.
 __global__ void __launch_bounds__(256)
 k_seg_kinetic(const Seg* __restrict__ seg, int nbo, const double* __restrict__ f, const double2* __restrict__ psi,
@@ -112,7 +114,7 @@ k_seg_kinetic(const Seg* __restrict__ seg, int nbo, const double* __restrict__ f
     const Seg s = seg[k];
     const int64_t n = (int64_t)item_nb(s, nbo) * s.npw;
     double acc = 0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * 256) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
         const int b = (int)(e / s.npw);
         const int q = (int)(e - (int64_t)b * s.npw);
         const double2 v = psi[s.off + e];
@@ -124,21 +126,21 @@ k_seg_kinetic(const Seg* __restrict__ seg, int nbo, const double* __restrict__ f
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[k * DOT_BLOCKS + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) part[k * gridDim.x + blockIdx.x] = red[0];
 }
 
 // out[c * out_stride] = sum over the cell's items of w_k (scale_omega * Omega)
 // * sum_blocks part[k]  (fixed order; one thread per cell).
 __global__ void k_cell_weighted_totals(const double* __restrict__ part, const Seg* __restrict__ seg,
                                        const CellDesc* __restrict__ cells, int ncells, double scale_omega,
-                                       double* __restrict__ out, int out_stride) {
+                                       double* __restrict__ out, int out_stride, int nblk) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     const CellDesc cr = cells[c];
     double tot = 0;
     for (int k = cr.item0; k < cr.item0 + cr.nitems; ++k) {
         double s = 0;
-        for (int b = 0; b < DOT_BLOCKS; ++b) s += part[k * DOT_BLOCKS + b];
+        for (int b = 0; b < nblk; ++b) s += part[k * nblk + b];
         tot += seg[k].wk * scale_omega * seg[k].omega * s;
     }
     out[c * out_stride] = tot;
@@ -433,7 +435,7 @@ __global__ void k_cgB_reset(int nit, const Seg* __restrict__ seg, CgBState s) {
 
 // Fused start of a band-CG step: Kg = K g and, per item, partial sums of
 // <g, Kg>, <g_prev, Kg>, <g, D_prev> (2 Re sum conj(a) b) in one pass:
-// part[(pair * nitems + k) * DOT_BLOCKS + block].
+// part[(pair * nitems + k) * gridDim.x + block].
 __global__ void __launch_bounds__(256)
 k_cg_precond_dots(const Seg* __restrict__ seg, int nitems, const double2* __restrict__ g,
                   const double2* __restrict__ gp, const double2* __restrict__ Dp, double2* __restrict__ Kg,
@@ -443,7 +445,7 @@ k_cg_precond_dots(const Seg* __restrict__ seg, int nitems, const double2* __rest
     const Seg s = seg[k];
     const int64_t n = (int64_t)s.nb * s.npw;
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * 256) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
         const int q = (int)(e % s.npw);
         const int64_t o = s.off + e;
         const double kk = 1.0 / (1.0 + 0.5 * s.kG2[q]);
@@ -463,7 +465,7 @@ k_cg_precond_dots(const Seg* __restrict__ seg, int nitems, const double2* __rest
             for (int p = 0; p < 3; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < 3) part[((int64_t)threadIdx.x * nitems + k) * DOT_BLOCKS + blockIdx.x] = 2.0 * red[threadIdx.x][0];
+    if (threadIdx.x < 3) part[((int64_t)threadIdx.x * nitems + k) * gridDim.x + blockIdx.x] = 2.0 * red[threadIdx.x][0];
 }
 
 // Per item (one 64-thread workgroup): fixed-order sums of the three dot
@@ -473,14 +475,15 @@ k_cg_precond_dots(const Seg* __restrict__ seg, int nitems, const double2* __rest
 
 __global__ void __launch_bounds__(256)
 k_cgB_direction(const Seg* __restrict__ seg, int nitems, const double* __restrict__ part, double* __restrict__ dots,
-                CgBState s, const double2* __restrict__ Kg, const double2* __restrict__ Dp, double2* __restrict__ Dd) {
+                CgBState s, const double2* __restrict__ Kg, const double2* __restrict__ Dp, double2* __restrict__ Dd,
+                int nblk) {
     __shared__ double red[3][64];
     __shared__ double coef[2];
     const int k = blockIdx.y;
     if (threadIdx.x < 64) {
         for (int p = 0; p < 3; ++p) {
             double v = 0.0;
-            for (int b = threadIdx.x; b < DOT_BLOCKS; b += 64) v += part[((int64_t)p * nitems + k) * DOT_BLOCKS + b];
+            for (int b = threadIdx.x; b < nblk; b += 64) v += part[((int64_t)p * nitems + k) * nblk + b];
             red[p][threadIdx.x] = v;
         }
     }

@@ -496,11 +496,12 @@ dpp_status dots_dev(dpp_system_s* s, int nbo, int npair, const double2* const* a
         pr.a[p] = p < npair ? a[p] : nullptr;
         pr.b[p] = p < npair ? b[p] : nullptr;
     }
-    hipLaunchKernelGGL(k_seg_dots, dim3(DOT_BLOCKS, s->nit), dim3(256), 0, stream(s), s->d_seg, s->nit, nbo, npair, pr,
+    const int nblk = dot_blocks(s->nit);
+    hipLaunchKernelGGL(k_seg_dots, dim3(nblk, s->nit), dim3(256), 0, stream(s), s->d_seg, s->nit, nbo, npair, pr,
                        s->d_part);
     DPP_LAUNCHED();
     hipLaunchKernelGGL(k_seg_dots_reduce, dim3(npair), dim3(64), 0, stream(s), (const double*)s->d_part, s->nit, npair,
-                       s->d_dots);
+                       s->d_dots, nblk);
     DPP_LAUNCHED();
     return DPP_OK;
 }
@@ -587,11 +588,12 @@ dpp_status energies(dpp_system_s* s, int nbo, const double2* psi, const double* 
     DPP_TRY(dot_cells(s->ctx, s->d_cells, s->ncells, s->Vloc, n, s->d_cred, s->d_E + ELOC, E_STRIDE));
     {
         TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
-        hipLaunchKernelGGL(k_seg_kinetic, dim3(DOT_BLOCKS, s->nit), dim3(256), 0, stream(s), s->d_seg, nbo,
+        hipLaunchKernelGGL(k_seg_kinetic, dim3(dot_blocks(s->nit), s->nit), dim3(256), 0, stream(s), s->d_seg, nbo,
                            (const double*)s->d_f, psi, s->d_part);
         DPP_LAUNCHED();
         hipLaunchKernelGGL(k_cell_weighted_totals, dim3((s->ncells + 63) / 64), dim3(64), 0, stream(s),
-                           (const double*)s->d_part, s->d_seg, s->d_cells, s->ncells, 0.5, s->d_E + EK, E_STRIDE);
+                           (const double*)s->d_part, s->d_seg, s->d_cells, s->ncells, 0.5, s->d_E + EK, E_STRIDE,
+                           dot_blocks(s->nit));
         DPP_LAUNCHED();
     }
     DPP_TRY(proj_overlaps(s, nbo, psi));
@@ -702,11 +704,11 @@ dpp_status cgB_step(dpp_system_s* s, double2* Y) {
     {
         // Kg and the direction dots, then beta and D = -Kg + beta D_prev
         TimerScope ts_(s->ctx, DPP_TK_BLOCKOPS);
-        hipLaunchKernelGGL(k_cg_precond_dots, dim3(DOT_BLOCKS, s->nit), dim3(256), 0, stream(s), s->d_seg, s->nit,
+        hipLaunchKernelGGL(k_cg_precond_dots, dim3(dot_blocks(s->nit), s->nit), dim3(256), 0, stream(s), s->d_seg, s->nit,
                            (const double2*)s->g, (const double2*)s->gp, (const double2*)s->Dp, s->Kg, s->d_part);
         DPP_LAUNCHED();
         hipLaunchKernelGGL(k_cgB_direction, eg, dim3(256), 0, stream(s), s->d_seg, s->nit, (const double*)s->d_part,
-                           s->d_dots, s->cg, (const double2*)s->Kg, (const double2*)s->Dp, s->Dd);
+                           s->d_dots, s->cg, (const double2*)s->Kg, (const double2*)s->Dp, s->Dd, dot_blocks(s->nit));
         DPP_LAUNCHED();
     }
     DPP_TRY(line_mats_B(s, Y, nullptr));
