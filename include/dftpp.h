@@ -448,8 +448,9 @@ dpp_status dpp_system_apply_H(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY);
  * DPP_EINVAL for bad arguments or a capturing stream. */
 dpp_status dpp_system_tune(dpp_system sys, const dpp_c64 *Y, dpp_c64 *HY, int reps);
 /* Sets one launch choice by hand (what dpp_system_tune would choose), for
- * tests and experiments: DPP_CHOICE_OVERLAP (0: 2x2 tile blocks over
- * 256-point chunks plus a reduction launch, 1: single tiles, 2: one
+ * tests and experiments: DPP_CHOICE_OVERLAP (0: the default rule, mode 3
+ * when every task has at least 4x4 output tiles, else 2x2 tile blocks over
+ * 256-point chunks plus a reduction launch; 1: single tiles, 2: one
  * workgroup per task over all points, 3: 4x4 tile blocks over 256-point
  * chunks with the operands staged in LDS), DPP_CHOICE_ROTATE_PT (0 = by launch
  * size, 1, 2 or 4 point tiles per wave), DPP_CHOICE_XPASS (0 auto, 1 one

@@ -152,8 +152,8 @@ struct dpp_system_s {
     void* gga_ws = nullptr;        // PBE workspace (largest cell) and a scratch energy
     double* d_gga_scratch = nullptr;
     int rot_pt = 0;         // rotate point tiles per wave (0: by launch size)
-    int ov_mode = 0;        // overlap launch shape (0 chunked 2x2 blocks, 1 chunked single tiles, 2 single pass,
-                            // 3 chunked 4x4 blocks staged in LDS)
+    int ov_mode = 0;        // overlap launch shape (0 auto: staged 4x4 blocks when every task has 4x4 tiles,
+                            // else chunked 2x2 blocks; 1 chunked single tiles, 2 single pass, 3 staged)
     std::string tune_report;
     // graphs
     bool graph_on = false;
@@ -1577,7 +1577,7 @@ extern "C" dpp_status dpp_system_tune(dpp_system s, const dpp_c64* Yc, dpp_c64* 
     {
         // the launch shapes of the FP64 overlap (the split-BF16 one has a single shape)
         s->prec = DPP_F64;
-        static const char* oname[] = {"wide", "single-tile", "single-pass", "staged"};
+        static const char* oname[] = {"auto", "single-tile", "single-pass", "staged"};
         double best = 1e300;
         int bn = 0;
         rep += "overlap blocks (f64):";
