@@ -847,8 +847,9 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
 // One wave owns PT tiles of 16 consecutive sphere points and up to JT x 16
 // output bands in accumulators; X is read once, each M value once per wave
 // and K step for all PT point tiles.  The loads of the next K step are issued
-// before the MFMAs of the current one.  Wide outputs take (1, 8); narrow ones
-// take PT > 1 when the batch still gives every CU many waves.
+// before the MFMAs of the current one.  Outputs of one or two tiles take
+// PT > 1 when the batch still gives every CU many waves; wider outputs run
+// k_rotate_staged (below).
 // F32 (the mixed-precision bulk): X and M rounded to FP32, FP32 MFMA and
 // accumulation over the bands, the result (and beta out) in FP64.
 template <int PT, int JT, bool F32>
@@ -949,23 +950,30 @@ k_rotate_mfma(const RotTask* __restrict__ tasks, RotTask single, int jt0_in, int
     }
 }
 
-// FP64 outputs of more than two 16-band tiles: RS_WAVES waves per workgroup,
-// one 16-point tile each, share the rows of M through LDS.  M is staged 16 K
-// rows (four MFMA steps) at a time for the RT_JT output tiles from jt0,
-// double-buffered; X is read by its own wave as in k_rotate_mfma.  The K
-// order (rows of X, then of X2), the padding rules and the output are those
-// of k_rotate_mfma, so both give the same sums.
+// Outputs of more than two 16-band tiles: RS_WAVES waves per workgroup, one
+// 16-point tile each, share the rows of M through LDS.  M is staged 16 K rows
+// (four MFMA steps) at a time for the RT_JT output tiles from jt0,
+// double-buffered (F32: rounded to FP32 when staged, as k_rotate_mfma rounds
+// it at use); X is read by its own wave as in k_rotate_mfma.  The K order
+// (rows of X, then of X2), the padding rules and the output are those of
+// k_rotate_mfma, so both give the same sums.
 constexpr int RS_WAVES = 8;
 constexpr int RS_COLS = RT_JT * 16;
 
+template <bool F32>
 __global__ void __launch_bounds__(64 * RS_WAVES)
 k_rotate_staged(const RotTask* __restrict__ tasks, RotTask single, int jt0, const int* __restrict__ act,
                 const int2* __restrict__ work) {
-    __shared__ double2 ms[2][16 * RS_COLS];
+    using acc_t = typename std::conditional<F32, f4, d4>::type;
+    using real_t = typename std::conditional<F32, float, double>::type;
+    using mt = typename std::conditional<F32, float2, double2>::type;
+    __shared__ mt ms[2][16 * RS_COLS];
     const int2 wk = work ? work[blockIdx.x] : int2{(int)blockIdx.y, (int)blockIdx.x};
     const RotTask T = tasks ? tasks[wk.x] : single;
     if (act && !act[T.item]) return;
-    const int njt = min(RT_JT, (T.nbO + 15) / 16 - jt0);
+    // uniform over the wave (readfirstlane): the per-tile branches below then
+    // stay scalar, instead of masking the MFMAs and copying their accumulators
+    const int njt = __builtin_amdgcn_readfirstlane(min(RT_JT, (T.nbO + 15) / 16 - jt0));
     if (njt <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int gt = wk.y * RS_WAVES + w;
@@ -999,7 +1007,7 @@ k_rotate_staged(const RotTask* __restrict__ tasks, RotTask single, int jt0, cons
     };
     auto mstage = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ms[buf][tid + 64 * RS_WAVES * i] = mraw[i];
+        for (int i = 0; i < 4; ++i) ms[buf][tid + 64 * RS_WAVES * i] = mt{(real_t)mraw[i].x, (real_t)mraw[i].y};
     };
     double2 xn[4];
     auto xload = [&](int ch) {
@@ -1014,11 +1022,11 @@ k_rotate_staged(const RotTask* __restrict__ tasks, RotTask single, int jt0, cons
             xn[q] = ok ? gld(Xs + (int64_t)ic * T.ldX + min(gt * 16 + c, T.npw - 1)) : double2{0, 0};
         }
     };
-    d4 dre[RT_JT], dim[RT_JT];
+    acc_t dre[RT_JT], dim[RT_JT];
 #pragma unroll
     for (int t = 0; t < RT_JT; ++t) {
-        dre[t] = d4{0, 0, 0, 0};
-        dim[t] = d4{0, 0, 0, 0};
+        dre[t] = acc_t{0, 0, 0, 0};
+        dim[t] = acc_t{0, 0, 0, 0};
     }
     if (nch > 0) {
         mload(0);
@@ -1035,20 +1043,24 @@ k_rotate_staged(const RotTask* __restrict__ tasks, RotTask single, int jt0, cons
             xload(ch + 1);
         }
         __syncthreads();
-        const double2* M = ms[buf];
+        const mt* M = ms[buf];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double xr = x[q].x, xi = x[q].y;
+            const real_t xr = (real_t)x[q].x, xi = (real_t)x[q].y;
 #pragma unroll
             for (int t = 0; t < RT_JT; ++t) {
-                if (t < njt) {
-                    const double2 m = M[(4 * q + ks) * RS_COLS + t * 16 + c];
+                // FP32 runs every tile (padding tiles read clamped, finite
+                // columns and are not stored): with the per-tile condition the
+                // compiler masks the MFMAs and spills their accumulators
+                if (F32 || t < njt) {
+                    const mt m = M[(4 * q + ks) * RS_COLS + t * 16 + c];
                     dre[t] = mfma(m.x, xr, dre[t]);
                     dre[t] = mfma(-m.y, xi, dre[t]);
                     dim[t] = mfma(m.y, xr, dim[t]);
                     dim[t] = mfma(m.x, xi, dim[t]);
                 }
             }
+            if constexpr (F32) __builtin_amdgcn_sched_barrier(0);
         }
     }
     const int q = gt * 16 + c;
@@ -1058,10 +1070,11 @@ k_rotate_staged(const RotTask* __restrict__ tasks, RotTask single, int jt0, cons
         if (t < njt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int j = (jt0 + t) * 16 + 4 * v + ks;  // FP64 result row of element v
+                // result row of element v: 4 v + l / 16 (FP64), 4 (l / 16) + v (FP32)
+                const int j = (jt0 + t) * 16 + (F32 ? 4 * ks + v : 4 * v + ks);
                 if (j < T.nbO) {
                     double2* o = T.out + (int64_t)j * T.ldout + q;
-                    double2 r = double2{dre[t][v], dim[t][v]};
+                    double2 r = double2{(double)dre[t][v], (double)dim[t][v]};
                     if (T.beta != 0.0) {
                         const double2 p = *o;
                         r.x += T.beta * p.x;
@@ -1111,14 +1124,6 @@ static void rotate_go(dpp_ctx ctx, const RotTask* d_tasks, const RotTask& single
                            single, jt0, ngrp, act, work);
 }
 
-// FP32 outputs of more than two 16-band tiles: groups of RT_JT32 tiles per
-// wave, all groups in one launch (twice the waves of the FP64 shape, so the
-// loads of more waves are in flight).
-constexpr int RT_JT32 = 4;
-static int rotate_groups(int jtiles, bool f32) {
-    return (f32 && jtiles > 2) ? (jtiles + RT_JT32 - 1) / RT_JT32 : 1;
-}
-
 // Launch the rotate kernel shape for the widest output of a batch; tiles =
 // point tiles summed over the tasks.  Several point tiles per wave only while
 // the launch keeps at least RT_MIN_WAVES waves.
@@ -1149,14 +1154,16 @@ static dpp_status rotate_launch(dpp_ctx ctx, const RotTask* d_tasks, const RotTa
             rotate_go<2, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
         else
             rotate_go<1, 2>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, f32);
-    } else if (f32) {
-        rotate_go<1, RT_JT32>(ctx, d_tasks, single, ntasks, ntile, 0, act, work, nwork, true,
-                              rotate_groups(jtiles, true));
     } else {
         const dim3 grid = work ? dim3((unsigned)nwork) : dim3((ntile + RS_WAVES - 1) / RS_WAVES, ntasks);
-        for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT)
-            hipLaunchKernelGGL(k_rotate_staged, grid, dim3(64 * RS_WAVES), 0, ctx->stream, d_tasks, single, jt0, act,
-                               work);
+        for (int jt0 = 0; jt0 < jtiles; jt0 += RT_JT) {
+            if (f32)
+                hipLaunchKernelGGL(k_rotate_staged<true>, grid, dim3(64 * RS_WAVES), 0, ctx->stream, d_tasks, single,
+                                   jt0, act, work);
+            else
+                hipLaunchKernelGGL(k_rotate_staged<false>, grid, dim3(64 * RS_WAVES), 0, ctx->stream, d_tasks,
+                                   single, jt0, act, work);
+        }
     }
     DPP_LAUNCHED();
     return DPP_OK;
@@ -1176,12 +1183,13 @@ void rotate_worklist(const std::vector<RotTask>& h, int rot_pt, std::vector<int2
     int64_t tiles;
     rotate_shape(h, mp, mj, tiles);
     const int pt = rotate_pt_rule(mj, tiles, rot_pt);
-    const int ng = rotate_groups(mj, f32);
-    const int per = (!f32 && mj > 2) ? RS_WAVES : RT_WAVES * pt;  // point tiles per block
+    // point tiles per block (k_rotate_staged above two output tiles, in both precisions)
+    const int per = mj > 2 ? RS_WAVES : RT_WAVES * pt;
+    (void)f32;
     w.clear();
     for (size_t i = 0; i < h.size(); ++i) {
         const int nblk = ((h[i].npw + 15) / 16 + per - 1) / per;
-        for (int b = 0; b < nblk * ng; ++b) w.push_back(int2{(int)i, b});
+        for (int b = 0; b < nblk; ++b) w.push_back(int2{(int)i, b});
     }
 }
 
