@@ -662,26 +662,44 @@ k_overlap_bf16_wg(const OvTask* __restrict__ tasks, OvTask single, double2* __re
         }
 }
 
-// Sums the FP32 slice partials of every task in FP64, in fixed order.
-__global__ void k_overlap_reduce_slices(const OvTask* __restrict__ tasks, OvTask single,
-                                        const double2* __restrict__ part, const int* __restrict__ act) {
-    const OvTask& T = tasks ? tasks[blockIdx.y] : single;
-    if (act && !act[T.item]) return;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= T.ntiles * 256) return;
+// Reductions of the overlap partials: OVR_OUT output elements per 256-thread
+// workgroup, four threads each summing a contiguous quarter of the partials
+// in order; the quarters are added in order, so the sum is deterministic.
+constexpr int OVR_OUT = 64;
+
+__device__ __forceinline__ void ovr_store(const OvTask& T, int e, const double2 (*acc)[OVR_OUT], int o) {
     const int tile = e >> 8, ij = e & 255;
     const int ti = tile / T.tilesB, tj = tile - ti * T.tilesB;
     const int i = ti * 16 + (ij >> 4), j = tj * 16 + (ij & 15);
     if (i >= T.nbA || j >= T.nbB) return;
-    const float2* p = reinterpret_cast<const float2*>(part + T.part_off) + e;
-    double sr = 0, si = 0;
-    const int ns = ovw_slices(T.npw);
-    for (int c = 0; c < ns; ++c) {
-        const float2 v = p[(int64_t)c * T.ntiles * 256];
-        sr += v.x;
-        si += v.y;
-    }
+    const double sr = ((acc[0][o].x + acc[1][o].x) + acc[2][o].x) + acc[3][o].x;
+    const double si = ((acc[0][o].y + acc[1][o].y) + acc[2][o].y) + acc[3][o].y;
     T.out[(int64_t)i * T.out_ld + j] = double2{T.scale * sr, T.scale * si};
+}
+
+// Sums the FP32 slice partials of every task in FP64, in fixed order.
+__global__ void __launch_bounds__(256)
+k_overlap_reduce_slices(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part,
+                        const int* __restrict__ act) {
+    const OvTask& T = tasks ? tasks[blockIdx.y] : single;
+    if (act && !act[T.item]) return;  // uniform over the workgroup
+    __shared__ double2 acc[4][OVR_OUT];
+    const int o = threadIdx.x % OVR_OUT, qd = threadIdx.x / OVR_OUT;
+    const int e = blockIdx.x * OVR_OUT + o;
+    const bool ok = e < T.ntiles * 256;
+    double sr = 0, si = 0;
+    if (ok) {
+        const float2* p = reinterpret_cast<const float2*>(part + T.part_off) + e;
+        const int ns = ovw_slices(T.npw), per = (ns + 3) / 4, c1 = min(ns, (qd + 1) * per);
+        for (int c = qd * per; c < c1; ++c) {
+            const float2 v = p[(int64_t)c * T.ntiles * 256];
+            sr += v.x;
+            si += v.y;
+        }
+    }
+    acc[qd][o] = double2{sr, si};
+    __syncthreads();
+    if (qd == 0 && ok) ovr_store(T, e, acc, o);
 }
 
 // Which split-BF16 form a task table takes: the workgroup form when some
@@ -709,23 +727,28 @@ void overlap_worklist_bf16(const std::vector<OvTask>& h, std::vector<int4>& w) {
 }
 
 // Sums the chunk partials of every task in fixed order.
-__global__ void k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part,
-                                 const int* __restrict__ act) {
+__global__ void __launch_bounds__(256)
+k_overlap_reduce(const OvTask* __restrict__ tasks, OvTask single, const double2* __restrict__ part,
+                 const int* __restrict__ act) {
     const OvTask& T = tasks ? tasks[blockIdx.y] : single;
-    if (act && !act[T.item]) return;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= T.ntiles * 256) return;
-    const int tile = e >> 8, ij = e & 255;
-    const int ti = tile / T.tilesB, tj = tile - ti * T.tilesB;
-    const int i = ti * 16 + (ij >> 4), j = tj * 16 + (ij & 15);
-    if (i >= T.nbA || j >= T.nbB) return;
+    if (act && !act[T.item]) return;  // uniform over the workgroup
+    __shared__ double2 acc[4][OVR_OUT];
+    const int o = threadIdx.x % OVR_OUT, qd = threadIdx.x / OVR_OUT;
+    const int e = blockIdx.x * OVR_OUT + o;
+    const bool ok = e < T.ntiles * 256;
     double sr = 0, si = 0;
-    for (int c = 0; c < T.nchunk; ++c) {
-        const double2 v = part[T.part_off + ((int64_t)c * T.ntiles + tile) * 256 + ij];
-        sr += v.x;
-        si += v.y;
+    if (ok) {
+        const int tile = e >> 8, ij = e & 255;
+        const int per = (T.nchunk + 3) / 4, c1 = min(T.nchunk, (qd + 1) * per);
+        for (int c = qd * per; c < c1; ++c) {
+            const double2 v = part[T.part_off + ((int64_t)c * T.ntiles + tile) * 256 + ij];
+            sr += v.x;
+            si += v.y;
+        }
     }
-    T.out[(int64_t)i * T.out_ld + j] = double2{T.scale * sr, T.scale * si};
+    acc[qd][o] = double2{sr, si};
+    __syncthreads();
+    if (qd == 0 && ok) ovr_store(T, e, acc, o);
 }
 
 size_t overlap_ws_bytes(int npw, int nbA, int nbB) {
@@ -780,10 +803,10 @@ dpp_status overlap_single(dpp_ctx ctx, int npw, int nbA, const double2* A, int64
     }
     TimerScope ts2_(ctx, DPP_TK_BLOCKOPS);
     if (wide)
-        hipLaunchKernelGGL(k_overlap_reduce_slices, dim3((t.ntiles * 256 + 255) / 256, 1), dim3(256), 0,
+        hipLaunchKernelGGL(k_overlap_reduce_slices, dim3((t.ntiles * 256 + OVR_OUT - 1) / OVR_OUT, 1), dim3(256), 0,
                            ctx->stream, (const OvTask*)nullptr, t, part, (const int*)nullptr);
     else
-        hipLaunchKernelGGL(k_overlap_reduce, dim3((t.ntiles * 256 + 255) / 256, 1), dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL(k_overlap_reduce, dim3((t.ntiles * 256 + OVR_OUT - 1) / OVR_OUT, 1), dim3(256), 0, ctx->stream,
                            (const OvTask*)nullptr, t, part, (const int*)nullptr);
     DPP_LAUNCHED();
     return DPP_OK;
@@ -834,10 +857,10 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
     if (full) return DPP_OK;
     TimerScope ts2_(ctx, act ? DPP_TK_MASKED : DPP_TK_BLOCKOPS);
     if (wide)
-        hipLaunchKernelGGL(k_overlap_reduce_slices, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
+        hipLaunchKernelGGL(k_overlap_reduce_slices, dim3((mt * 256 + OVR_OUT - 1) / OVR_OUT, (unsigned)h.size()), dim3(256), 0,
                            ctx->stream, d_tasks, OvTask{}, (const double2*)part, act);
     else
-        hipLaunchKernelGGL(k_overlap_reduce, dim3((mt * 256 + 255) / 256, (unsigned)h.size()), dim3(256), 0,
+        hipLaunchKernelGGL(k_overlap_reduce, dim3((mt * 256 + OVR_OUT - 1) / OVR_OUT, (unsigned)h.size()), dim3(256), 0,
                            ctx->stream, d_tasks, OvTask{}, (const double2*)part, act);
     DPP_LAUNCHED();
     return DPP_OK;
