@@ -39,15 +39,37 @@ __global__ void k_seg_axpby(const Seg* __restrict__ seg, int nbo, const double* 
     }
 }
 
+// (band, point) of element e = band * npw + point of a grid-stride loop,
+// stepped with the loop instead of divided per element: the first index takes
+// one 64-bit division per thread, each step an add and at most one carry.
+struct BandPoint {
+    int b, q, db, dq, npw;
+    __device__ BandPoint(int64_t e0, int64_t stride, int npw_) : npw(npw_) {
+        b = (int)(e0 / npw_);
+        q = (int)(e0 - (int64_t)b * npw_);
+        db = (int)(stride / npw_);
+        dq = (int)(stride - (int64_t)db * npw_);
+    }
+    __device__ __forceinline__ void next() {
+        b += db;
+        q += dq;
+        if (q >= npw) {
+            q -= npw;
+            ++b;
+        }
+    }
+};
+
 // out = scale * K x  (K = 1/(1 + |k+G|^2/2)), per item.
 __global__ void k_seg_precond(const Seg* __restrict__ seg, int nbo, double scale, const double2* __restrict__ x,
                               double2* __restrict__ out) {
     const int k = blockIdx.y;
     const Seg s = seg[k];
     const int64_t n = (int64_t)item_nb(s, nbo) * s.npw;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int q = (int)(e % s.npw);
-        const double kk = scale / (1.0 + 0.5 * s.kG2[q]);
+    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, st = (int64_t)gridDim.x * blockDim.x;
+    BandPoint bp(e0, st, s.npw);
+    for (int64_t e = e0; e < n; e += st, bp.next()) {
+        const double kk = scale / (1.0 + 0.5 * s.kG2[bp.q]);
         const double2 v = x[s.off + e];
         out[s.off + e] = double2{kk * v.x, kk * v.y};
     }
@@ -114,11 +136,11 @@ k_seg_kinetic(const Seg* __restrict__ seg, int nbo, const double* __restrict__ f
     const Seg s = seg[k];
     const int64_t n = (int64_t)item_nb(s, nbo) * s.npw;
     double acc = 0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-        const int b = (int)(e / s.npw);
-        const int q = (int)(e - (int64_t)b * s.npw);
+    const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x, st = (int64_t)gridDim.x * 256;
+    BandPoint bp(e0, st, s.npw);
+    for (int64_t e = e0; e < n; e += st, bp.next()) {
         const double2 v = psi[s.off + e];
-        acc += f[s.f_off + b] * s.kG2[q] * (v.x * v.x + v.y * v.y);
+        acc += f[s.f_off + bp.b] * s.kG2[bp.q] * (v.x * v.x + v.y * v.y);
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -445,10 +467,11 @@ k_cg_precond_dots(const Seg* __restrict__ seg, int nitems, const double2* __rest
     const Seg s = seg[k];
     const int64_t n = (int64_t)s.nb * s.npw;
     double a0 = 0, a1 = 0, a2 = 0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-        const int q = (int)(e % s.npw);
+    const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x, st = (int64_t)gridDim.x * 256;
+    BandPoint bp(e0, st, s.npw);
+    for (int64_t e = e0; e < n; e += st, bp.next()) {
         const int64_t o = s.off + e;
-        const double kk = 1.0 / (1.0 + 0.5 * s.kG2[q]);
+        const double kk = 1.0 / (1.0 + 0.5 * s.kG2[bp.q]);
         const double2 gv = g[o], gpv = gp[o], dv = Dp[o];
         const double2 kg = double2{kk * gv.x, kk * gv.y};
         Kg[o] = kg;
