@@ -207,17 +207,23 @@ k_overlap_mfma(const OvTask* __restrict__ tasks, OvTask single, double2* __restr
     }
 }
 
-// LDS-staged form (launch mode 3): one workgroup of four waves per (task,
+// LDS-staged form (launch mode 3): one workgroup of eight waves per (task,
 // chunk, 4 x 4 tile block).  Each 16-point step of the block's 64 A rows and
 // 64 B rows is staged once in LDS (double-buffered, rows padded to an odd
-// number of 16-byte units), and each wave accumulates its 2 x 2 tiles from
-// there, so every operand is read from memory once per block instead of once
-// per wave.  Partials use k_overlap_mfma's layout (chunk, tile) and are
+// number of 16-byte units), and each wave accumulates one A tile against two
+// B tiles from there, so every operand is read from memory once per block
+// instead of once per wave.  Eight waves of two tiles ran faster than four of
+// four (115 against 136 us per 128 x 128 product): the 376 workgroups of a
+// 128-band product fill only part of the chip, and the extra waves hide the
+// LDS and MFMA latencies.  Partials use k_overlap_mfma's layout (chunk, tile) and are
 // summed by k_overlap_reduce.
 constexpr int OVS_ROWS = 128;  // 64 A rows, then 64 B rows
 constexpr int OVS_ROW = 17;    // 16 points + 1 unit of padding
 
-__global__ void __launch_bounds__(256)
+constexpr int OVS_TA = 1;      // A tiles per wave (eight waves: one A tile by two B tiles each)
+constexpr int OVS_THREADS = 512;
+
+__global__ void __launch_bounds__(OVS_THREADS)
 k_overlap_staged(const OvTask* __restrict__ tasks, OvTask single, double2* __restrict__ part,
                  const int* __restrict__ act, const int4* __restrict__ work) {
     __shared__ double2 st[2][OVS_ROWS * OVS_ROW];
@@ -238,32 +244,32 @@ k_overlap_staged(const OvTask* __restrict__ tasks, OvTask single, double2* __res
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int r = lane & 15, ks = lane >> 4;
     // staging: thread -> LDS row tid / 2, points 8 (tid % 2) .. + 7 of a step
-    const int srow = tid >> 1, sp = (tid & 1) * 8;
+    const int srow = tid >> 2, sp = (tid & 3) * 4;
     const bool isA = srow < 64;
     const int brow = isA ? 16 * ti0 + srow : 16 * tj0 + srow - 64;
     const bool valid = brow < (isA ? T.nbA : T.nbB);
     const double2* src = isA ? T.A + (int64_t)brow * T.ldA : T.B + (int64_t)brow * T.ldB;
     const int g0 = chunk * OV_CHUNK, g1 = min(T.npw, g0 + OV_CHUNK);
     const int nst = g1 > g0 ? (g1 - g0 + 15) / 16 : 0;
-    double2 raw[8];
+    double2 raw[4];
     // rows past the band counts load nothing and stage zeros; points past the
     // chunk are clamped to the last point when loaded and zeroed when staged
     auto load = [&](int g) {
         if (valid) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) raw[e] = gld(src + min(g + sp + e, T.npw - 1));
+            for (int e = 0; e < 4; ++e) raw[e] = gld(src + min(g + sp + e, T.npw - 1));
         }
     };
     auto stage = [&](int buf, int g) {
         double2* row = st[buf] + srow * OVS_ROW + sp;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) row[e] = (valid && g + sp + e < g1) ? raw[e] : double2{0, 0};
+        for (int e = 0; e < 4; ++e) row[e] = (valid && g + sp + e < g1) ? raw[e] : double2{0, 0};
     };
     // this wave's tiles: A tiles ti0 + 2 (w / 2) + a, B tiles tj0 + 2 (w % 2) + b
-    const int wa = 2 * (w >> 1), wb = 2 * (w & 1);
-    d4 cre[2][2], cim[2][2];
+    const int wa = OVS_TA * (w >> 1), wb = 2 * (w & 1);
+    d4 cre[OVS_TA][2], cim[OVS_TA][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < OVS_TA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             cre[a][b] = d4{0, 0, 0, 0};
@@ -277,9 +283,9 @@ k_overlap_staged(const OvTask* __restrict__ tasks, OvTask single, double2* __res
         __syncthreads();
         const double2* S = st[buf];
         // lane (r, ks) takes points 4 ks + q of the step for the q-th MFMA
-        double2 av[2][4], bv[2][4];
+        double2 av[OVS_TA][4], bv[2][4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < OVS_TA; ++a)
 #pragma unroll
             for (int q = 0; q < 4; ++q) av[a][q] = S[(16 * (wa + a) + r) * OVS_ROW + 4 * ks + q];
 #pragma unroll
@@ -289,7 +295,7 @@ k_overlap_staged(const OvTask* __restrict__ tasks, OvTask single, double2* __res
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < OVS_TA; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     cre[a][b] = mfma(av[a][q].x, bv[b][q].x, cre[a][b]);
@@ -299,7 +305,7 @@ k_overlap_staged(const OvTask* __restrict__ tasks, OvTask single, double2* __res
                 }
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < OVS_TA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int ta = ti0 + wa + a, tb = tj0 + wb + b;
@@ -846,7 +852,7 @@ dpp_status overlap_tasks(dpp_ctx ctx, const std::vector<OvTask>& h, const OvTask
                                act, d_work);
         } else if (staged) {
             const dim3 grid = d_work ? dim3((unsigned)nwork) : dim3(mc, mblk, h.size());
-            hipLaunchKernelGGL(k_overlap_staged, grid, dim3(256), 0, ctx->stream, d_tasks, OvTask{}, part, act,
+            hipLaunchKernelGGL(k_overlap_staged, grid, dim3(OVS_THREADS), 0, ctx->stream, d_tasks, OvTask{}, part, act,
                                d_work);
         } else {
             overlap_launch(ctx, d_tasks, OvTask{}, (unsigned)h.size(), mc, mblk, mt > 1 && !ov_narrow, part, act,
